@@ -1,0 +1,274 @@
+"""Pins of the oracle's Simulation-step sampler and of its adjoint (CPU only).
+
+Sampler: special cases that reduce to a single key, a single clip, the
+quaternion double cover, the loop wrap, and the closed form of a normalised
+lerp between two rotations about one axis.
+
+Adjoint: central finite differences of the oracle's own FP64 forward,
+the textbook geometric Jacobian of a planar revolute chain, a one-joint
+closed form, and torch float64 autograd through an independent torch
+forward.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2505_06703_amd import workloads as wl
+
+
+def _lib(rng, clips=3, keys=30, J=5, max_angle=0.3):
+    kq = wl.random_quats(rng, clips * keys * J, max_angle).reshape(clips, keys, J, 4)
+    kt = wl.random_offsets(rng, clips * keys * J).reshape(clips, keys, J, 3)
+    return kq, kt
+
+
+def _one_char(J):
+    return np.array([0, J], np.int64)
+
+
+def _normalized(q):
+    q = np.asarray(q, np.float64)
+    return q / np.linalg.norm(q, axis=-1, keepdims=True)
+
+
+def test_time_zero_weight_zero_returns_first_key_of_clip_a():
+    rng = np.random.default_rng(1)
+    kq, kt = _lib(rng)
+    q, t = oracle.pose_sample(_one_char(5), kq, kt, [1], [2], [0.0], [0.0])
+    np.testing.assert_allclose(q, _normalized(kq[1, 0]), atol=1e-15)
+    np.testing.assert_allclose(t, kt[1, 0], atol=0)
+
+
+def test_weight_one_returns_clip_b_sample_and_weight_zero_clip_a():
+    rng = np.random.default_rng(2)
+    kq, kt = _lib(rng)
+    qa, ta = oracle.pose_sample(_one_char(5), kq, kt, [0], [0], [0.37], [0.0])
+    qb, tb = oracle.pose_sample(_one_char(5), kq, kt, [2], [2], [0.37], [0.0])
+    q0, t0 = oracle.pose_sample(_one_char(5), kq, kt, [0], [2], [0.37], [0.0])
+    q1, t1 = oracle.pose_sample(_one_char(5), kq, kt, [0], [2], [0.37], [1.0])
+    np.testing.assert_allclose(q0, qa, atol=1e-15)
+    np.testing.assert_allclose(t0, ta, atol=1e-15)
+    np.testing.assert_allclose(q1, qb, atol=1e-15)
+    np.testing.assert_allclose(t1, tb, atol=1e-15)
+
+
+def test_key_sign_flip_gives_same_rotation():
+    rng = np.random.default_rng(3)
+    kq, kt = _lib(rng)
+    q1, _ = oracle.pose_sample(_one_char(5), kq, kt, [0], [1], [0.5 / 30 + 3 / 30], [0.4])
+    kq2 = kq.copy()
+    kq2[0, 4] *= -1  # key k1 of clip A
+    kq2[1, 3] *= -1  # key k0 of clip B
+    q2, _ = oracle.pose_sample(_one_char(5), kq2, kt, [0], [1], [0.5 / 30 + 3 / 30], [0.4])
+    R1 = Rotation.from_quat(q1).as_matrix()
+    R2 = Rotation.from_quat(q2).as_matrix()
+    np.testing.assert_allclose(R1, R2, atol=1e-12)
+
+
+def test_loop_wrap_just_before_one_second_approaches_key_zero():
+    rng = np.random.default_rng(4)
+    kq, kt = _lib(rng)
+    tau = np.nextafter(np.float32(1.0), np.float32(0.0))
+    q, t = oracle.pose_sample(_one_char(5), kq, kt, [2], [2], [tau], [0.0])
+    d = np.sign(np.sum(q * kq[2, 0], axis=1))[:, None]
+    np.testing.assert_allclose(q * d, _normalized(kq[2, 0]), atol=1e-5)
+    np.testing.assert_allclose(t, kt[2, 0], atol=1e-6)
+    # and a time beyond one period loops (1.25 s behaves as 0.25 s)
+    qa, ta = oracle.pose_sample(_one_char(5), kq, kt, [2], [2], [1.25], [0.0])
+    qb, tb = oracle.pose_sample(_one_char(5), kq, kt, [2], [2], [0.25], [0.0])
+    np.testing.assert_allclose(qa, qb, atol=1e-15)
+    np.testing.assert_allclose(ta, tb, atol=1e-15)
+
+
+def test_same_axis_nlerp_closed_form_and_translation_lerp():
+    """Two keys rotating about one axis by a and b: the normalised lerp keeps the
+    axis and its half angle satisfies tan(phi/2) = ((1-u) sin(a/2) + u sin(b/2)) /
+    ((1-u) cos(a/2) + u cos(b/2))."""
+    a_ang, b_ang = np.float32(0.2), np.float32(1.1)
+    axis = np.array([1.0, 2.0, 2.0]) / 3.0
+    kq = np.zeros((1, 30, 1, 4), np.float32)
+    kt = np.zeros((1, 30, 1, 3), np.float32)
+    for k in range(30):
+        ang = a_ang if k % 2 == 0 else b_ang
+        kq[0, k, 0, :3] = axis * math.sin(ang / 2)
+        kq[0, k, 0, 3] = math.cos(ang / 2)
+        kt[0, k, 0] = [k, 2 * k, -k]
+    tau = np.float32(4.25 / 30.0)  # between keys 4 and 5
+    q, t = oracle.pose_sample(_one_char(1), kq, kt, [0], [0], [tau], [0.0])
+    f = np.float32(np.float32(30.0) * tau)
+    u = float(f) - math.floor(float(f))
+    qa, qb = kq[0, 4, 0].astype(np.float64), kq[0, 5, 0].astype(np.float64)
+    half = math.atan2((1 - u) * np.linalg.norm(qa[:3]) + u * np.linalg.norm(qb[:3]),
+                      (1 - u) * qa[3] + u * qb[3])
+    got_half = math.atan2(np.linalg.norm(q[0, :3]), q[0, 3])
+    assert abs(got_half - half) < 1e-12
+    np.testing.assert_allclose(q[0, :3] / np.linalg.norm(q[0, :3]), axis, atol=1e-7)
+    np.testing.assert_allclose(t[0], (1 - u) * kt[0, 4, 0] + u * kt[0, 5, 0], atol=1e-12)
+
+
+def test_sampler_rejects_bad_clip_ids_and_short_clips():
+    rng = np.random.default_rng(5)
+    kq, kt = _lib(rng)
+    with pytest.raises(oracle.OracleError):
+        oracle.pose_sample(_one_char(5), kq, kt, [3], [0], [0.1], [0.5])
+    with pytest.raises(oracle.OracleError):
+        oracle.pose_sample(_one_char(6), kq, kt, [0], [1], [0.1], [0.5])
+
+
+# --------------------------------------------------------------------------
+# adjoint
+# --------------------------------------------------------------------------
+
+
+def _loss(offsets, parents, q, t, s, W):
+    G = oracle.forward(offsets, parents, q, t, s)
+    return float(np.sum(W * G))
+
+
+def _small_batch(rng, sizes, with_scale):
+    par = []
+    for n in sizes:
+        p = np.empty(n, np.int32)
+        p[0] = -1
+        for i in range(1, n):
+            p[i] = i - 1 if rng.uniform() < 0.6 else rng.integers(0, i)
+        par.append(p)
+    parents = np.concatenate(par)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    N = parents.size
+    q = rng.standard_normal((N, 4))  # raw components, not normalised on purpose
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q *= rng.uniform(0.9, 1.1, (N, 1))
+    t = rng.uniform(-0.5, 0.5, (N, 3))
+    s = rng.uniform(0.7, 1.3, (N, 3)) if with_scale else np.ones((N, 3))
+    return offsets, parents, q, t, s
+
+
+@pytest.mark.parametrize("with_scale", [False, True])
+def test_backward_matches_central_differences(with_scale):
+    rng = np.random.default_rng(20 + with_scale)
+    offsets, parents, q, t, s = _small_batch(rng, [1, 5, 16, 9], with_scale)
+    N = parents.size
+    W = rng.standard_normal((N, 4, 4))
+    gq, gt, gs = oracle.backward(offsets, parents, q, t, s, W)
+    h = 1e-6
+    for arr, grad in ((q, gq), (t, gt), (s, gs)):
+        fd = np.empty_like(arr)
+        for idx in np.ndindex(arr.shape):
+            old = arr[idx]
+            arr[idx] = old + h
+            lp = _loss(offsets, parents, q, t, s, W)
+            arr[idx] = old - h
+            lm = _loss(offsets, parents, q, t, s, W)
+            arr[idx] = old
+            fd[idx] = (lp - lm) / (2 * h)
+        np.testing.assert_allclose(grad, fd, rtol=1e-6, atol=1e-7)
+
+
+def test_backward_ignores_bottom_row_of_incoming_gradient():
+    rng = np.random.default_rng(22)
+    offsets, parents, q, t, s = _small_batch(rng, [12], True)
+    W = rng.standard_normal((12, 4, 4))
+    W2 = W.copy()
+    W2[:, 3, :] = rng.standard_normal((12, 4)) * 100
+    a = oracle.backward(offsets, parents, q, t, s, W)
+    b = oracle.backward(offsets, parents, q, t, s, W2)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, atol=1e-12)
+
+
+def test_planar_revolute_chain_geometric_jacobian():
+    """Joints rotating about z: d b_e / d theta_k = z x (b_e - b_k) for e below k."""
+    rng = np.random.default_rng(23)
+    n = 30
+    th = rng.uniform(-0.4, 0.4, n)
+    ell = rng.uniform(0.1, 0.3, n)
+    q = np.stack([np.zeros(n), np.zeros(n), np.sin(th / 2), np.cos(th / 2)], 1)
+    t = np.stack([ell, np.zeros(n), np.zeros(n)], 1)
+    par = np.arange(-1, n - 1, dtype=np.int32)
+    off = np.array([0, n])
+    G = oracle.forward(off, par, q, t)
+    b = G[:, :3, 3]
+    eff = [9, 20, 29]
+    y = b[eff] + rng.uniform(-0.3, 0.3, (3, 3))
+    W = np.zeros((n, 4, 4))
+    for e, target in zip(eff, y):
+        W[e, :3, 3] = 2 * (b[e] - target)
+    gq, gt, _ = oracle.backward(off, par, q, t, None, W)
+    dq_dth = np.stack([np.zeros(n), np.zeros(n), 0.5 * np.cos(th / 2), -0.5 * np.sin(th / 2)], 1)
+    dl_dth = np.sum(gq * dq_dth, axis=1)
+    z = np.array([0.0, 0.0, 1.0])
+    expect = np.zeros(n)
+    for k in range(n):
+        for e, target in zip(eff, y):
+            if e >= k:
+                expect[k] += 2 * (b[e] - target) @ np.cross(z, b[e] - b[k])
+    np.testing.assert_allclose(dl_dth, expect, atol=1e-12)
+    # translation gradient: d b_e / d t_k = A_parent(k) for e below k
+    expect_t = np.zeros((n, 3))
+    for k in range(n):
+        Ap = np.eye(3) if k == 0 else G[k - 1, :3, :3]
+        for e, target in zip(eff, y):
+            if e >= k:
+                expect_t[k] += Ap.T @ (2 * (b[e] - target))
+    np.testing.assert_allclose(gt, expect_t, atol=1e-12)
+
+
+def test_single_joint_translation_loss():
+    q = np.array([[0.1, -0.2, 0.3, 0.9]])
+    t = np.array([[0.3, -0.1, 0.7]])
+    y = np.array([1.0, 2.0, -0.5])
+    W = np.zeros((1, 4, 4))
+    W[0, :3, 3] = 2 * (t[0] - y)
+    _, gt, _ = oracle.backward(np.array([0, 1]), np.array([-1], np.int32), q, t, None, W)
+    np.testing.assert_allclose(gt[0], 2 * (t[0] - y), atol=0)
+
+
+def _torch_forward(offsets, parents, q, t, s):
+    """Independent float64 torch forward: rotation via the axis-angle route
+    (Rodrigues) of the normalised quaternion, times its squared norm, which
+    equals the raw-component polynomial for any quaternion."""
+    N = parents.size
+    nrm2 = (q * q).sum(1)
+    u = q / nrm2.sqrt()[:, None]
+    v, w = u[:, :3], u[:, 3]
+    K = torch.zeros((N, 3, 3), dtype=torch.float64)
+    K[:, 0, 1], K[:, 0, 2] = -v[:, 2], v[:, 1]
+    K[:, 1, 0], K[:, 1, 2] = v[:, 2], -v[:, 0]
+    K[:, 2, 0], K[:, 2, 1] = -v[:, 1], v[:, 0]
+    eye = torch.eye(3, dtype=torch.float64).expand(N, 3, 3)
+    Runit = eye + 2 * w[:, None, None] * K + 2 * K @ K
+    # the raw polynomial R(q) = |q|^2 Runit + (1 - |q|^2) I
+    R = nrm2[:, None, None] * Runit + (1 - nrm2)[:, None, None] * eye
+    out = []
+    for c in range(offsets.size - 1):
+        Gs = []
+        for j in range(offsets[c + 1] - offsets[c]):
+            g = offsets[c] + j
+            A = R[g] * s[g][None, :]
+            L = torch.cat([torch.cat([A, t[g][:, None]], 1),
+                           torch.tensor([[0.0, 0.0, 0.0, 1.0]], dtype=torch.float64)], 0)
+            p = parents[g]
+            Gs.append(L if p < 0 else Gs[p] @ L)
+        out.extend(Gs)
+    return torch.stack(out)
+
+
+def test_backward_matches_torch_float64_autograd():
+    rng = np.random.default_rng(24)
+    offsets, parents, q, t, s = _small_batch(rng, [7, 20], True)
+    W = rng.standard_normal((parents.size, 4, 4))
+    qt = torch.tensor(q, requires_grad=True)
+    tt = torch.tensor(t, requires_grad=True)
+    st = torch.tensor(s, requires_grad=True)
+    G = _torch_forward(offsets, parents, qt, tt, st)
+    np.testing.assert_allclose(G.detach().numpy(), oracle.forward(offsets, parents, q, t, s), atol=1e-12)
+    (G * torch.tensor(W)).sum().backward()
+    gq, gt, gs = oracle.backward(offsets, parents, q, t, s, W)
+    np.testing.assert_allclose(gq, qt.grad.numpy(), atol=1e-10)
+    np.testing.assert_allclose(gt, tt.grad.numpy(), atol=1e-10)
+    np.testing.assert_allclose(gs, st.grad.numpy(), atol=1e-10)
