@@ -1,0 +1,228 @@
+/*
+ * hs.h -- Hierarchy-Scan on AMD Instinct MI355X (gfx950): C ABI.
+ *
+ * The library computes, for batches of skeletal characters, the three
+ * per-frame steps of GPU skeletal animation (Sec. 1 of the paper):
+ *   1. Simulation     -- sample and blend animation clips into local poses
+ *                        (hs_pose_sample, or fused into hs_scan_forward);
+ *   2. Hierarchy-Scan -- the tree prefix product of Eq. 1 (Sec. 3): every
+ *                        joint's model-space transform is its parent's
+ *                        transform times its own local transform,
+ *                        G_j = G_parent(j) * L_j (hs_scan_forward);
+ *   3. Bind MeshPose  -- skin matrices S_j = G_j * B_j^-1 (hs_skin, or fused
+ *                        into hs_scan_forward);
+ * plus the adjoint of step 2 (hs_scan_backward) for gradient-based use.
+ *
+ * Conventions
+ *   - Matrices act on column vectors.  Outputs are 4x4 row-major fp32; the
+ *     bottom row of every global matrix is written as exactly (0, 0, 0, 1).
+ *   - A joint's local transform is L = T(t) * R(q) * diag(s) with the unit
+ *     quaternion q = (x, y, z, w) turned into a rotation by the textbook
+ *     polynomial (no renormalisation); s may be omitted (unit scale).
+ *   - A batch is CSR: joint_offsets[C+1] (offsets[0] = 0, non-decreasing,
+ *     offsets[C] = N) and parents[N], character-local indices, -1 for a
+ *     root, each parent preceding its child (parents[j] < j), the ordering
+ *     the paper obtains from a tree traversal (Sec. 3.2.1).  Several roots
+ *     per character (a forest) and empty characters are allowed.
+ *
+ * Memory and streams
+ *   - Every array argument of the per-frame calls is a caller-owned device
+ *     pointer.  The library allocates only inside hs_context_create and
+ *     hs_plan_create (and frees in the matching destroy call); the per-frame
+ *     calls neither allocate nor synchronise, run asynchronously on the
+ *     given stream, and may be captured into a HIP graph.
+ *   - Outputs must not overlap inputs or each other.
+ *   - Arrays read or written as 16-byte vectors (quat, global_out, inv_bind,
+ *     skin_out, grad_global, grad_quat, ckpt) must be 16-byte aligned; the
+ *     others 4-byte aligned.
+ *
+ * Errors
+ *   Every call returns an hs_status.  Argument, alignment, aliasing and
+ *   topology errors are detected on the host before anything is launched;
+ *   a failed launch returns HS_ERR_DEVICE.  hs_last_error() returns a
+ *   thread-local description of the last failure on the calling thread.
+ *   NaN and Inf inputs are not errors: they propagate into the outputs.
+ */
+#ifndef HS_H_
+#define HS_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hs_status;
+#define HS_OK 0
+#define HS_ERR_INVALID_ARG 1
+#define HS_ERR_TOPOLOGY 2
+#define HS_ERR_UNSUPPORTED 3
+#define HS_ERR_DEVICE 4
+#define HS_ERR_OOM 5
+
+typedef struct hs_context hs_context;
+typedef struct hs_plan hs_plan;
+typedef struct hs_graph hs_graph;
+
+/* Library version string (static storage). */
+const char *hs_version(void);
+
+/* Description of the last failure on this thread; valid until the next
+ * failing call on the same thread.  Never NULL. */
+const char *hs_last_error(void);
+
+/* Create a context bound to HIP device `device`.  The context owns the
+ * device properties and the in-memory autotuning cache.  *out receives the
+ * context; destroy it with hs_context_destroy after every plan made from it
+ * has been destroyed. */
+hs_status hs_context_create(int device, hs_context **out);
+void hs_context_destroy(hs_context *ctx);
+
+/* ------------------------------------------------------------------------
+ * Plans: topology analysis, done once per skeleton batch.
+ * ------------------------------------------------------------------------ */
+
+/* A batch of characters.  joint_offsets and parents may be host or device
+ * pointers; hs_plan_create copies what it needs (a device pointer costs one
+ * synchronous device-to-host copy) and keeps no reference to them. */
+typedef struct hs_batch {
+    int64_t num_characters;       /* C >= 0 */
+    int64_t num_joints;           /* N = joint_offsets[C], 0 <= N < 2^31 */
+    const int64_t *joint_offsets; /* [C+1] */
+    const int32_t *parents;       /* [N] character-local, -1 = root, parents[j] < j */
+} hs_batch;
+
+/* Scan strategy. */
+#define HS_STRATEGY_AUTO 0      /* tiles where a character fits, multipass beyond */
+#define HS_STRATEGY_TILE 1      /* every character in an LDS tile (error if one does not fit) */
+#define HS_STRATEGY_MULTIPASS 2 /* every character on the global multipass path */
+
+typedef struct hs_plan_opts {
+    int32_t strategy;       /* HS_STRATEGY_* */
+    int32_t tile_joints;    /* tile capacity in joints (multiple of 64), 0 = choose */
+    int32_t waves_per_tile; /* 64-lane waves per workgroup (1..16), 0 = choose */
+    int32_t grid_tiles;     /* workgroups launched: 0 = one per tile; k > 0 = k per CU, each
+                               looping over the cost-sorted tiles */
+    int32_t autotune;       /* non-zero: time candidate launch shapes on the device when the
+                               plan is created (result cached in the context) */
+    int32_t reserved[3];    /* must be zero */
+} hs_plan_opts;
+
+typedef struct hs_plan_info {
+    int64_t num_characters;
+    int64_t num_joints;
+    int64_t tiled_joints;      /* joints scanned in LDS tiles */
+    int64_t multipass_joints;  /* joints on the multipass path */
+    int32_t max_depth;         /* levels on the longest root-to-leaf path (root = 1) */
+    int32_t max_character;     /* largest character, in joints */
+    int32_t num_tiles;
+    int32_t tile_joints;
+    int32_t waves_per_tile;
+    int32_t grid;              /* workgroups per tiled launch */
+    int32_t multipass_rounds;  /* global jump rounds of the multipass path */
+    int32_t max_block_chain;   /* longest chain of 64-joint blocks on any path */
+} hs_plan_info;
+
+/* Analyse a batch: validates the CSR topology (HS_ERR_TOPOLOGY if some
+ * parents[j] is outside [-1, j)), packs whole characters into LDS tiles,
+ * prepares the multipass path for characters larger than a tile, uploads
+ * the device tables and, if asked, autotunes the launch shape.  opts may be
+ * NULL.  Synchronises the device once. */
+hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts,
+                         hs_plan **out);
+void hs_plan_destroy(hs_plan *plan);
+hs_status hs_plan_get_info(const hs_plan *plan, hs_plan_info *out);
+
+/* ------------------------------------------------------------------------
+ * Simulation step (Sec. 1, step 1): looping clips, sampled and blended.
+ * ------------------------------------------------------------------------ */
+
+/* A library of clips, each num_keys keyframes at fps, every keyframe a pose
+ * of joints_per_clip joints.  key_quat [clips][keys][J][4] (16-byte
+ * aligned), key_trans [clips][keys][J][3].  Joint j of a character samples
+ * joint j of the clip, so every character must have <= J joints. */
+typedef struct hs_clip_lib {
+    int32_t num_clips;
+    int32_t num_keys;
+    int32_t joints_per_clip;
+    float fps;
+    const float *key_quat;
+    const float *key_trans;
+} hs_clip_lib;
+
+/* Per-character choices, each [C]: clip ids in [0, num_clips), time in
+ * seconds (clips loop with period num_keys / fps), blend weight of clip b. */
+typedef struct hs_clip_params {
+    const int32_t *clip_a;
+    const int32_t *clip_b;
+    const float *time;
+    const float *weight;
+} hs_clip_params;
+
+/* For each character: frame f = fps * time (one fp32 multiply), keys
+ * k0 = floor(f) mod K and k1 = (k0 + 1) mod K, alpha = f - floor(f).  For
+ * each clip, q = normalise((1 - alpha) q_k0 + alpha * sign * q_k1) where
+ * sign is that of the dot product of the two keys (+1 when it is zero,
+ * decided in fp64 from the exact fp32 products), t = (1 - alpha) t_k0 +
+ * alpha t_k1.  The two clips are then blended the same way with the weight
+ * (the sign decided on the fp32 clip quaternions).  Writes quat_out [N,4]
+ * (16-byte aligned) and trans_out [N,3]; the scale is implicitly 1. */
+hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
+                         float *quat_out, float *trans_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Hierarchy-Scan (Sec. 1 step 2; Eq. 1; Sec. 3) with optional fused skin.
+ * ------------------------------------------------------------------------ */
+
+#define HS_POSE_TRS 0   /* local poses given as quat/trans/scale arrays */
+#define HS_POSE_CLIPS 1 /* local poses sampled on the fly (hs_pose_sample, fused) */
+
+typedef struct hs_pose_src {
+    int32_t kind;                  /* HS_POSE_TRS or HS_POSE_CLIPS */
+    const float *quat;             /* TRS: [N,4] */
+    const float *trans;            /* TRS: [N,3] */
+    const float *scale;            /* TRS: [N,3] or NULL for unit scale */
+    const hs_clip_lib *clips;      /* CLIPS */
+    const hs_clip_params *params;  /* CLIPS */
+} hs_pose_src;
+
+/* Global transforms G_j = G_parent(j) L_j for every joint of the plan.
+ *   global_out [N,4,4]  written if non-NULL;
+ *   inv_bind   [N,4,4]  with skin_out [N,4,4]: if both are non-NULL the skin
+ *                        S_j = G_j * inv_bind_j (full 4x4 product) is written
+ *                        from the same pass (fused Bind MeshPose step);
+ *   ckpt_out   [N,12]   if non-NULL (ckpt_k >= 1): rows 0-2 of G_j are stored
+ *                        for joints whose level (root = 1) is a multiple of
+ *                        ckpt_k, other rows untouched -- the checkpoints
+ *                        hs_scan_backward may read instead of recomputing.
+ * At least one of global_out, skin_out must be non-NULL.  flags must be 0. */
+hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out,
+                          const float *inv_bind, float *skin_out, float *ckpt_out, int32_t ckpt_k,
+                          uint32_t flags, hipStream_t stream);
+
+/* Bind MeshPose step on its own: S_j = G_j * inv_bind_j, full 4x4 products,
+ * for n joints. */
+hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,
+                  hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Adjoint of the Hierarchy-Scan.
+ * ------------------------------------------------------------------------ */
+
+/* Given dLoss/dG (grad_global [N,4,4]; its bottom rows are ignored since G's
+ * bottom row is constant), writes dLoss/dq (grad_quat [N,4], derivative of
+ * the rotation polynomial in the raw quaternion components), dLoss/dt
+ * (grad_trans [N,3]) and, if non-NULL, dLoss/ds (grad_scale [N,3]).  The
+ * global transforms the adjoint needs are recomputed on chip (ckpt NULL) or
+ * rebuilt from the checkpoints hs_scan_forward stored with the same ckpt_k.
+ * src must be HS_POSE_TRS.  flags must be 0. */
+hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const float *grad_global,
+                           const float *ckpt, int32_t ckpt_k, float *grad_quat, float *grad_trans,
+                           float *grad_scale, uint32_t flags, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HS_H_ */

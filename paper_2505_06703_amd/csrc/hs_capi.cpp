@@ -1,0 +1,786 @@
+// hs_capi.cpp -- the C ABI of include/hs.h: argument validation, topology
+// analysis and tiling (plans), launch-shape autotuning, and dispatch of the
+// HIP kernels in hs_kernels.hip.
+#include "hs.h"
+#include "hs_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using hs::MPBlock;
+using hs::TileDesc;
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+hs_status fail(hs_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+hs_status fail_hip(hipError_t err, const char *what)
+{
+    if (err == hipErrorOutOfMemory)
+        return fail(HS_ERR_OOM, "%s: out of device memory", what);
+    return fail(HS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(err));
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+struct Range {
+    const void *p;
+    size_t bytes;
+    const char *name;
+};
+
+bool overlap(const Range &a, const Range &b)
+{
+    if (!a.p || !b.p || a.bytes == 0 || b.bytes == 0) return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a.p), b0 = reinterpret_cast<uintptr_t>(b.p);
+    return a0 < b0 + b.bytes && b0 < a0 + a.bytes;
+}
+
+// Every output must be disjoint from every input and from the other outputs.
+hs_status check_aliasing(const std::vector<Range> &outs, const std::vector<Range> &ins)
+{
+    for (size_t i = 0; i < outs.size(); ++i) {
+        for (const Range &in : ins)
+            if (overlap(outs[i], in))
+                return fail(HS_ERR_INVALID_ARG, "output %s overlaps input %s", outs[i].name, in.name);
+        for (size_t k = i + 1; k < outs.size(); ++k)
+            if (overlap(outs[i], outs[k]))
+                return fail(HS_ERR_INVALID_ARG, "outputs %s and %s overlap", outs[i].name, outs[k].name);
+    }
+    return HS_OK;
+}
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty()) return hipSuccess;
+    hipError_t err = hipMalloc(reinterpret_cast<void **>(dst), src.size() * sizeof(T));
+    if (err != hipSuccess) return err;
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Copy n elements from a host or device pointer into a host vector.
+template <class T>
+hipError_t fetch(std::vector<T> &dst, const T *src, size_t n)
+{
+    dst.resize(n);
+    if (n == 0) return hipSuccess;
+    hipPointerAttribute_t attr;
+    bool device = false;
+    if (hipPointerGetAttributes(&attr, src) == hipSuccess)
+        device = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+    (void)hipGetLastError();  // clear the error left for unregistered host memory
+    if (!device) {
+        std::memcpy(dst.data(), src, n * sizeof(T));
+        return hipSuccess;
+    }
+    return hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost);
+}
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+int ceil_log2(int64_t v)
+{
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+struct Shape {
+    int tile_cap = 0;
+    int waves = 0;
+    int grid_per_cu = 0;  // 0 = one workgroup per tile
+};
+
+} // namespace
+
+struct hs_context {
+    int device = 0;
+    int num_cu = 0;
+    size_t max_lds = 0;
+    std::string arch;
+    std::mutex mu;
+    std::map<std::string, Shape> tuned;  // autotuning cache keyed by arch + size class
+};
+
+struct hs_plan {
+    hs_context *ctx = nullptr;
+    int64_t C = 0, N = 0;
+    std::vector<int64_t> h_offsets;
+    std::vector<int32_t> h_parents;  // character-local
+    hs_plan_info info{};
+    Shape shape;
+    // device tables
+    int64_t *d_offsets = nullptr;
+    int32_t *d_parent = nullptr;  // global parent id or -1
+    int32_t *d_level = nullptr;
+    TileDesc *d_tiles = nullptr;
+    std::vector<TileDesc> h_tiles;
+    // multipass
+    MPBlock *d_mp_blocks = nullptr;
+    int32_t num_mp_blocks = 0;
+    int64_t nmp = 0;
+    int32_t mp_rounds = 0;
+    float4 *d_mp_P[2] = {nullptr, nullptr};
+    int32_t *d_mp_E[2] = {nullptr, nullptr};
+    float4 *d_mp_adj[2] = {nullptr, nullptr};
+};
+
+namespace {
+
+void free_plan(hs_plan *p)
+{
+    if (!p) return;
+    (void)hipFree(p->d_offsets);
+    (void)hipFree(p->d_parent);
+    (void)hipFree(p->d_level);
+    (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_mp_blocks);
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(p->d_mp_P[i]);
+        (void)hipFree(p->d_mp_E[i]);
+        (void)hipFree(p->d_mp_adj[i]);
+    }
+    delete p;
+}
+
+// RAII guard that makes the plan's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// Length of the longest chain of 64-joint blocks along any root-to-joint path
+// of one character (ids relative to `base`, blocks aligned to `align0`).
+int block_chain_length(const int32_t *par, int64_t n, int64_t align0, std::vector<int32_t> &top,
+                       std::vector<int32_t> &chain)
+{
+    top.resize(n);
+    chain.resize(n);
+    int best = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const int32_t p = par[j];
+        const int64_t bj = (j + align0) / 64;
+        if (p >= 0 && (p + align0) / 64 == bj) {
+            top[j] = top[p];
+            chain[j] = chain[p];
+        } else {
+            top[j] = (int32_t)j;
+            chain[j] = p < 0 ? 1 : chain[p] + 1;
+        }
+        best = std::max(best, (int)chain[j]);
+    }
+    return best;
+}
+
+hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
+{
+    const int64_t C = plan->C;
+    const auto &off = plan->h_offsets;
+    const auto &par = plan->h_parents;
+    const int cap = shape.tile_cap;
+
+    std::vector<TileDesc> tiles;
+    std::vector<int64_t> tile_cost;
+    std::vector<MPBlock> mpb;
+    int64_t nmp = 0, tiled = 0;
+    int max_chain_tiles = 0, max_chain_mp = 0;
+    std::vector<int32_t> top, chain;
+
+    TileDesc cur{};
+    bool open = false;
+    int cur_chain = 0;
+    auto flush = [&]() {
+        if (open && cur.count > 0) {
+            tiles.push_back(cur);
+            tile_cost.push_back((int64_t)cur.count + 48 * (int64_t)cur_chain);
+            max_chain_tiles = std::max(max_chain_tiles, cur_chain);
+        }
+        open = false;
+        cur_chain = 0;
+    };
+    for (int64_t c = 0; c < C; ++c) {
+        const int64_t n = off[c + 1] - off[c];
+        const bool to_mp = strategy == HS_STRATEGY_MULTIPASS || n > cap;
+        if (to_mp) {
+            flush();
+            if (n == 0) continue;
+            const int L = block_chain_length(par.data() + off[c], n, 0, top, chain);
+            max_chain_mp = std::max(max_chain_mp, L);
+            for (int64_t k = 0; k < n; k += 64) {
+                MPBlock b{};
+                b.gbegin = off[c] + k;
+                b.cbegin = nmp + k;
+                b.count = (int32_t)std::min<int64_t>(64, n - k);
+                b.chr = (int32_t)c;
+                mpb.push_back(b);
+            }
+            nmp += n;
+            continue;
+        }
+        if (!open) {
+            if (n == 0) continue;
+            cur = TileDesc{};
+            cur.begin = off[c];
+            cur.first_char = (int32_t)c;
+            open = true;
+        } else if (cur.count + n > cap || cur.num_chars + 1 > cap) {
+            // a tile holds at most `cap` joints and `cap` characters (empty
+            // characters inside a tile still take a slot of its LDS table)
+            flush();
+            cur = TileDesc{};
+            cur.begin = off[c];
+            cur.first_char = (int32_t)c;
+            open = true;
+        }
+        if (n > 0) {
+            const int L = block_chain_length(par.data() + off[c], n, cur.count, top, chain);
+            cur_chain = std::max(cur_chain, L);
+        }
+        cur.count += (int32_t)n;
+        cur.num_chars += 1;
+        tiled += n;
+    }
+    flush();
+
+    // heaviest tiles first: the hardware dispatches workgroups in order, so
+    // long serial block chains start early instead of trailing the launch
+    std::vector<size_t> order(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return tile_cost[a] > tile_cost[b]; });
+    std::vector<TileDesc> sorted(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+
+    hipError_t err;
+    (void)hipFree(plan->d_tiles);
+    plan->d_tiles = nullptr;
+    if ((err = upload(&plan->d_tiles, sorted)) != hipSuccess) return fail_hip(err, "hs_plan_create");
+    plan->h_tiles = sorted;
+    (void)hipFree(plan->d_mp_blocks);
+    plan->d_mp_blocks = nullptr;
+    if ((err = upload(&plan->d_mp_blocks, mpb)) != hipSuccess) return fail_hip(err, "hs_plan_create");
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(plan->d_mp_P[i]);
+        (void)hipFree(plan->d_mp_E[i]);
+        (void)hipFree(plan->d_mp_adj[i]);
+        plan->d_mp_P[i] = nullptr;
+        plan->d_mp_E[i] = nullptr;
+        plan->d_mp_adj[i] = nullptr;
+        if (nmp > 0) {
+            if ((err = hipMalloc(&plan->d_mp_P[i], (size_t)nmp * 3 * sizeof(float4))) != hipSuccess ||
+                (err = hipMalloc(&plan->d_mp_E[i], (size_t)nmp * sizeof(int32_t))) != hipSuccess)
+                return fail_hip(err, "hs_plan_create (multipass workspace)");
+        }
+    }
+    plan->num_mp_blocks = (int32_t)mpb.size();
+    plan->nmp = nmp;
+    plan->mp_rounds = ceil_log2(std::max(1, max_chain_mp));
+    plan->shape = shape;
+
+    hs_plan_info &I = plan->info;
+    I.tiled_joints = tiled;
+    I.multipass_joints = nmp;
+    I.num_tiles = (int32_t)sorted.size();
+    I.tile_joints = cap;
+    I.waves_per_tile = shape.waves;
+    I.grid = shape.grid_per_cu > 0
+                 ? (int32_t)std::min<int64_t>(sorted.size(), (int64_t)shape.grid_per_cu * plan->ctx->num_cu)
+                 : (int32_t)sorted.size();
+    I.multipass_rounds = plan->mp_rounds;
+    I.max_block_chain = std::max(max_chain_tiles, max_chain_mp);
+    return HS_OK;
+}
+
+hs::TileLaunch tile_launch(const hs_plan *p)
+{
+    hs::TileLaunch tl{};
+    tl.tiles = p->d_tiles;
+    tl.num_tiles = p->info.num_tiles;
+    tl.tile_cap = p->shape.tile_cap;
+    tl.waves = p->shape.waves;
+    tl.grid = std::max(1, p->info.grid);
+    tl.parent = p->d_parent;
+    return tl;
+}
+
+hs::MPLaunch mp_launch(const hs_plan *p)
+{
+    hs::MPLaunch ml{};
+    ml.blocks = p->d_mp_blocks;
+    ml.num_blocks = p->num_mp_blocks;
+    ml.rounds = p->mp_rounds;
+    ml.nmp = p->nmp;
+    ml.parent = p->d_parent;
+    for (int i = 0; i < 2; ++i) {
+        ml.P[i] = p->d_mp_P[i];
+        ml.E[i] = p->d_mp_E[i];
+    }
+    return ml;
+}
+
+hs_status check_pose_src(const hs_plan *plan, const hs_pose_src *src, hs::PoseArgs &pa,
+                         std::vector<Range> &ins, bool allow_clips)
+{
+    if (!src) return fail(HS_ERR_INVALID_ARG, "pose source is NULL");
+    const size_t N = (size_t)plan->N;
+    pa = hs::PoseArgs{};
+    pa.kind = src->kind;
+    pa.offsets = plan->d_offsets;
+    if (src->kind == HS_POSE_TRS) {
+        if (!src->quat || !src->trans) return fail(HS_ERR_INVALID_ARG, "quat and trans must be non-NULL");
+        if (!aligned(src->quat, 16)) return fail(HS_ERR_INVALID_ARG, "quat must be 16-byte aligned");
+        if (!aligned(src->trans, 4) || (src->scale && !aligned(src->scale, 4)))
+            return fail(HS_ERR_INVALID_ARG, "trans/scale must be 4-byte aligned");
+        pa.quat = src->quat;
+        pa.trans = src->trans;
+        pa.scale = src->scale;
+        ins.push_back({src->quat, N * 16, "quat"});
+        ins.push_back({src->trans, N * 12, "trans"});
+        ins.push_back({src->scale, src->scale ? N * 12 : 0, "scale"});
+        return HS_OK;
+    }
+    if (src->kind != HS_POSE_CLIPS) return fail(HS_ERR_INVALID_ARG, "unknown pose source kind %d", src->kind);
+    if (!allow_clips) return fail(HS_ERR_UNSUPPORTED, "this call needs HS_POSE_TRS poses");
+    const hs_clip_lib *L = src->clips;
+    const hs_clip_params *P = src->params;
+    if (!L || !P) return fail(HS_ERR_INVALID_ARG, "clip library and parameters must be non-NULL");
+    if (L->num_clips <= 0 || L->num_keys <= 0 || L->joints_per_clip <= 0)
+        return fail(HS_ERR_INVALID_ARG, "clip library sizes must be positive");
+    if (!std::isfinite(L->fps)) return fail(HS_ERR_INVALID_ARG, "fps must be finite");
+    if (L->joints_per_clip < plan->info.max_character)
+        return fail(HS_ERR_INVALID_ARG, "clips hold %d joints but a character has %d",
+                    L->joints_per_clip, plan->info.max_character);
+    if (!L->key_quat || !L->key_trans || !P->clip_a || !P->clip_b || !P->time || !P->weight)
+        return fail(HS_ERR_INVALID_ARG, "clip arrays must be non-NULL");
+    if (!aligned(L->key_quat, 16)) return fail(HS_ERR_INVALID_ARG, "key_quat must be 16-byte aligned");
+    pa.num_clips = L->num_clips;
+    pa.num_keys = L->num_keys;
+    pa.joints_per_clip = L->joints_per_clip;
+    pa.fps = L->fps;
+    pa.key_quat = L->key_quat;
+    pa.key_trans = L->key_trans;
+    pa.clip_a = P->clip_a;
+    pa.clip_b = P->clip_b;
+    pa.time = P->time;
+    pa.weight = P->weight;
+    const size_t keys = (size_t)L->num_clips * L->num_keys * L->joints_per_clip;
+    const size_t C = (size_t)plan->C;
+    ins.push_back({L->key_quat, keys * 16, "key_quat"});
+    ins.push_back({L->key_trans, keys * 12, "key_trans"});
+    ins.push_back({P->clip_a, C * 4, "clip_a"});
+    ins.push_back({P->clip_b, C * 4, "clip_b"});
+    ins.push_back({P->time, C * 4, "time"});
+    ins.push_back({P->weight, C * 4, "weight"});
+    return HS_OK;
+}
+
+hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::OutArgs &oa,
+                      hipStream_t stream)
+{
+    hipError_t err = hs::launch_forward_tiles(tile_launch(plan), pa, oa, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (tiles)");
+    err = hs::launch_forward_multipass(mp_launch(plan), pa, oa, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (multipass)");
+    return HS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape autotuning: time the candidates on scratch poses of the
+// plan's own topology and keep the fastest.
+// ---------------------------------------------------------------------------
+std::string tune_key(const hs_plan *p)
+{
+    // size class: number of joints (log2), largest character and deepest
+    // block chain, rounded so that similar batches share an entry
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d", p->ctx->arch.c_str(),
+             ceil_log2(std::max<int64_t>(1, p->N)), round_up(std::max(1, p->info.max_character), 64),
+             ceil_log2(std::max(1, p->info.max_block_chain)), ceil_log2(std::max<int64_t>(1, p->C)));
+    return buf;
+}
+
+hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
+{
+    const std::string key = tune_key(plan);
+    {
+        std::lock_guard<std::mutex> lk(plan->ctx->mu);
+        auto it = plan->ctx->tuned.find(key);
+        if (it != plan->ctx->tuned.end()) return build_tables(plan, it->second, strategy);
+    }
+    const size_t N = (size_t)plan->N;
+    std::vector<Shape> cands;
+    const int min_cap = round_up(std::max(1, plan->info.max_character), 64);
+    for (int cap : {64, 128, 256, 512, 1024, 2048}) {
+        if (strategy != HS_STRATEGY_MULTIPASS && cap < min_cap && strategy == HS_STRATEGY_TILE) continue;
+        if (hs::forward_tile_lds_bytes(cap, true) > plan->ctx->max_lds) continue;
+        for (int w : {1, 2, 4, 8, 16}) {
+            if (w * 64 > cap) continue;
+            if (cap / (w * 64) > 4) continue;  // at most 4 blocks per wave
+            for (int g : {0, 2, 4}) cands.push_back(Shape{cap, w, g});
+        }
+    }
+    if (cands.empty()) return build_tables(plan, base, strategy);
+
+    float *q = nullptr, *t = nullptr, *G = nullptr;
+    hipError_t err;
+    if ((err = hipMalloc(&q, N * 16)) != hipSuccess || (err = hipMalloc(&t, N * 12)) != hipSuccess ||
+        (err = hipMalloc(&G, N * 64)) != hipSuccess) {
+        (void)(void)hipFree(q); (void)hipFree(t); (void)hipFree(G);
+        return fail_hip(err, "hs_plan_create (autotune scratch)");
+    }
+    // identity rotations, zero offsets: values do not affect the timing
+    std::vector<float> hq(N * 4, 0.0f);
+    for (size_t i = 0; i < N; ++i) hq[4 * i + 3] = 1.0f;
+    (void)hipMemcpy(q, hq.data(), N * 16, hipMemcpyHostToDevice);
+    (void)hipMemset(t, 0, N * 12);
+    hipStream_t s;
+    (void)hipStreamCreate(&s);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    hs::PoseArgs pa{};
+    pa.kind = 0;
+    pa.quat = q;
+    pa.trans = t;
+    hs::OutArgs oa{};
+    oa.global_out = G;
+    Shape best = base;
+    float best_ms = 1e30f;
+    hs_status rc = HS_OK;
+    for (const Shape &sh : cands) {
+        if ((rc = build_tables(plan, sh, strategy)) != HS_OK) break;
+        float ms_sum = 0.0f;
+        bool ok = true;
+        for (int it = 0; it < 4 && ok; ++it) {
+            (void)hipEventRecord(e0, s);
+            ok = run_forward(plan, pa, oa, s) == HS_OK;
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (it > 0) ms_sum += ms;  // first run warms up
+        }
+        if (ok && ms_sum < best_ms) {
+            best_ms = ms_sum;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    (void)hipFree(q);
+    (void)hipFree(t);
+    (void)hipFree(G);
+    if (rc != HS_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(plan->ctx->mu);
+        plan->ctx->tuned[key] = best;
+    }
+    return build_tables(plan, best, strategy);
+}
+
+} // namespace
+
+extern "C" {
+
+const char *hs_version(void) { return "hs 0.1.0 (gfx950)"; }
+
+const char *hs_last_error(void) { return g_last_error.c_str(); }
+
+hs_status hs_context_create(int device, hs_context **out)
+{
+    if (!out) return fail(HS_ERR_INVALID_ARG, "hs_context_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t err = hipGetDeviceCount(&count);
+    if (err != hipSuccess) return fail_hip(err, "hs_context_create");
+    if (device < 0 || device >= count)
+        return fail(HS_ERR_INVALID_ARG, "hs_context_create: device %d not in [0, %d)", device, count);
+    hipDeviceProp_t prop;
+    if ((err = hipGetDeviceProperties(&prop, device)) != hipSuccess) return fail_hip(err, "hs_context_create");
+    std::string arch = prop.gcnArchName;
+    if (arch.rfind("gfx950", 0) != 0)
+        return fail(HS_ERR_UNSUPPORTED, "hs_context_create: device %d is %s; this library targets gfx950",
+                    device, arch.c_str());
+    hs_context *ctx = new hs_context();
+    ctx->device = device;
+    ctx->num_cu = prop.multiProcessorCount;
+    ctx->max_lds = prop.sharedMemPerBlock;
+    ctx->arch = arch.substr(0, arch.find(':'));
+    *out = ctx;
+    return HS_OK;
+}
+
+void hs_context_destroy(hs_context *ctx) { delete ctx; }
+
+hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts, hs_plan **out)
+{
+    if (!out) return fail(HS_ERR_INVALID_ARG, "hs_plan_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !batch) return fail(HS_ERR_INVALID_ARG, "hs_plan_create: context and batch must be non-NULL");
+    const int64_t C = batch->num_characters, N = batch->num_joints;
+    if (C < 0 || C >= (int64_t(1) << 31)) return fail(HS_ERR_INVALID_ARG, "num_characters %lld out of range", (long long)C);
+    if (N < 0 || N >= (int64_t(1) << 31) - 1) return fail(HS_ERR_UNSUPPORTED, "num_joints %lld out of range [0, 2^31-1)", (long long)N);
+    if (!batch->joint_offsets) return fail(HS_ERR_INVALID_ARG, "joint_offsets is NULL");
+    if (N > 0 && !batch->parents) return fail(HS_ERR_INVALID_ARG, "parents is NULL");
+    hs_plan_opts o{};
+    if (opts) o = *opts;
+    for (int r : o.reserved)
+        if (r != 0) return fail(HS_ERR_INVALID_ARG, "hs_plan_opts.reserved must be zero");
+    if (o.strategy < HS_STRATEGY_AUTO || o.strategy > HS_STRATEGY_MULTIPASS)
+        return fail(HS_ERR_INVALID_ARG, "unknown strategy %d", o.strategy);
+    if (o.tile_joints < 0 || o.tile_joints % 64 != 0)
+        return fail(HS_ERR_INVALID_ARG, "tile_joints must be a non-negative multiple of 64");
+    if (o.waves_per_tile != 0 && o.waves_per_tile != 1 && o.waves_per_tile != 2 && o.waves_per_tile != 4 &&
+        o.waves_per_tile != 8 && o.waves_per_tile != 16)
+        return fail(HS_ERR_INVALID_ARG, "waves_per_tile must be 0, 1, 2, 4, 8 or 16");
+    if (o.grid_tiles < 0 || o.grid_tiles > 64) return fail(HS_ERR_INVALID_ARG, "grid_tiles must be in [0, 64]");
+
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_plan_create: cannot select device %d", ctx->device);
+
+    hs_plan *plan = new hs_plan();
+    plan->ctx = ctx;
+    plan->C = C;
+    plan->N = N;
+    hipError_t err;
+    if ((err = fetch(plan->h_offsets, batch->joint_offsets, (size_t)C + 1)) != hipSuccess ||
+        (err = fetch(plan->h_parents, batch->parents, (size_t)N)) != hipSuccess) {
+        free_plan(plan);
+        return fail_hip(err, "hs_plan_create (reading topology)");
+    }
+    const auto &off = plan->h_offsets;
+    const auto &par = plan->h_parents;
+    if (off[0] != 0) {
+        free_plan(plan);
+        return fail(HS_ERR_INVALID_ARG, "joint_offsets[0] must be 0");
+    }
+    int max_char = 0, max_depth = 0;
+    std::vector<int32_t> level((size_t)N), gparent((size_t)N);
+    for (int64_t c = 0; c < C; ++c) {
+        if (off[c + 1] < off[c] || off[c + 1] > N) {
+            free_plan(plan);
+            return fail(HS_ERR_INVALID_ARG, "joint_offsets must be non-decreasing and end at num_joints");
+        }
+        const int64_t n = off[c + 1] - off[c];
+        max_char = std::max<int64_t>(max_char, n);
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t g = off[c] + j;
+            const int32_t p = par[g];
+            if (p < -1 || (int64_t)p >= j) {
+                free_plan(plan);
+                return fail(HS_ERR_TOPOLOGY, "character %lld joint %lld has parent %d (need -1 <= parent < %lld)",
+                            (long long)c, (long long)j, p, (long long)j);
+            }
+            gparent[g] = p < 0 ? -1 : (int32_t)(off[c] + p);
+            level[g] = p < 0 ? 1 : level[off[c] + p] + 1;
+            max_depth = std::max(max_depth, level[g]);
+        }
+    }
+    if (off[C] != N) {
+        free_plan(plan);
+        return fail(HS_ERR_INVALID_ARG, "joint_offsets[C] = %lld but num_joints = %lld", (long long)off[C], (long long)N);
+    }
+    plan->info.num_characters = C;
+    plan->info.num_joints = N;
+    plan->info.max_depth = max_depth;
+    plan->info.max_character = max_char;
+    if ((err = upload(&plan->d_offsets, off)) != hipSuccess || (err = upload(&plan->d_parent, gparent)) != hipSuccess ||
+        (err = upload(&plan->d_level, level)) != hipSuccess) {
+        free_plan(plan);
+        return fail_hip(err, "hs_plan_create (upload)");
+    }
+
+    // default launch shape
+    const int lds_cap = hs::kMaxTileJoints;
+    const int min_cap = round_up(std::max(1, max_char), 64);
+    Shape sh;
+    if (o.tile_joints > 0) {
+        sh.tile_cap = o.tile_joints;
+    } else {
+        const int64_t target = (N + 2 * (int64_t)ctx->num_cu - 1) / (2 * (int64_t)ctx->num_cu);
+        sh.tile_cap = (int)std::min<int64_t>(1024, round_up((int)std::max<int64_t>(64, target), 64));
+        sh.tile_cap = std::max(sh.tile_cap, std::min(min_cap, 2048));
+    }
+    if (hs::forward_tile_lds_bytes(sh.tile_cap, true) > ctx->max_lds || sh.tile_cap > lds_cap) {
+        free_plan(plan);
+        return fail(HS_ERR_UNSUPPORTED, "tile of %d joints exceeds the %zu-byte LDS", sh.tile_cap, ctx->max_lds);
+    }
+    if (o.strategy == HS_STRATEGY_TILE && min_cap > sh.tile_cap) {
+        free_plan(plan);
+        return fail(HS_ERR_UNSUPPORTED, "a character of %d joints does not fit a %d-joint tile", max_char,
+                    sh.tile_cap);
+    }
+    sh.waves = o.waves_per_tile > 0 ? o.waves_per_tile : std::min(16, sh.tile_cap / 64);
+    if (sh.waves * 64 > sh.tile_cap) sh.waves = sh.tile_cap / 64;
+    sh.grid_per_cu = o.grid_tiles;
+
+    hs_status rc = build_tables(plan, sh, o.strategy);
+    if (rc == HS_OK && o.autotune && N > 0) rc = autotune(plan, sh, o.strategy);
+    if (rc != HS_OK) {
+        free_plan(plan);
+        return rc;
+    }
+    *out = plan;
+    return HS_OK;
+}
+
+void hs_plan_destroy(hs_plan *plan) { free_plan(plan); }
+
+hs_status hs_plan_get_info(const hs_plan *plan, hs_plan_info *out)
+{
+    if (!plan || !out) return fail(HS_ERR_INVALID_ARG, "hs_plan_get_info: NULL argument");
+    *out = plan->info;
+    return HS_OK;
+}
+
+hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out, const float *inv_bind,
+                          float *skin_out, float *ckpt_out, int32_t ckpt_k, uint32_t flags, hipStream_t stream)
+{
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: plan is NULL");
+    if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: flags must be 0");
+    if (!global_out && !skin_out) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: no output requested");
+    if ((skin_out != nullptr) != (inv_bind != nullptr))
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: inv_bind and skin_out go together");
+    if (ckpt_out && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: ckpt_k must be >= 1");
+    for (const void *p : {(const void *)global_out, (const void *)inv_bind, (const void *)skin_out,
+                          (const void *)ckpt_out})
+        if (p && !aligned(p, 16)) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: outputs and inv_bind must be 16-byte aligned");
+    hs::PoseArgs pa;
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, src, pa, ins, true);
+    if (rc != HS_OK) return rc;
+    const size_t N = (size_t)plan->N;
+    ins.push_back({inv_bind, N * 64, "inv_bind"});
+    std::vector<Range> outs = {{global_out, N * 64, "global_out"}, {skin_out, N * 64, "skin_out"},
+                               {ckpt_out, N * 48, "ckpt_out"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    if (N == 0) return HS_OK;
+    hs::OutArgs oa{};
+    oa.global_out = global_out;
+    oa.inv_bind = inv_bind;
+    oa.skin_out = skin_out;
+    oa.ckpt = ckpt_out;
+    oa.ckpt_k = ckpt_out ? ckpt_k : 1;
+    oa.level = plan->d_level;
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_forward: cannot select device");
+    return run_forward(plan, pa, oa, stream);
+}
+
+hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
+                         float *quat_out, float *trans_out, hipStream_t stream)
+{
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_pose_sample: plan is NULL");
+    if (!quat_out || !trans_out) return fail(HS_ERR_INVALID_ARG, "hs_pose_sample: outputs must be non-NULL");
+    if (!aligned(quat_out, 16) || !aligned(trans_out, 4))
+        return fail(HS_ERR_INVALID_ARG, "hs_pose_sample: quat_out must be 16-byte aligned");
+    hs_pose_src src{};
+    src.kind = HS_POSE_CLIPS;
+    src.clips = lib;
+    src.params = params;
+    hs::PoseArgs pa;
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, &src, pa, ins, true);
+    if (rc != HS_OK) return rc;
+    const size_t N = (size_t)plan->N;
+    std::vector<Range> outs = {{quat_out, N * 16, "quat_out"}, {trans_out, N * 12, "trans_out"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    if (N == 0) return HS_OK;
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_pose_sample: cannot select device");
+    hipError_t err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan), pa, quat_out, trans_out, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_pose_sample");
+    return HS_OK;
+}
+
+hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out, hipStream_t stream)
+{
+    if (n < 0) return fail(HS_ERR_INVALID_ARG, "hs_skin: n must be >= 0");
+    if (n == 0) return HS_OK;
+    if (!global || !inv_bind || !skin_out) return fail(HS_ERR_INVALID_ARG, "hs_skin: NULL array");
+    if (!aligned(global, 16) || !aligned(inv_bind, 16) || !aligned(skin_out, 16))
+        return fail(HS_ERR_INVALID_ARG, "hs_skin: arrays must be 16-byte aligned");
+    hs_status rc = check_aliasing({{skin_out, (size_t)n * 64, "skin_out"}},
+                                  {{global, (size_t)n * 64, "global"}, {inv_bind, (size_t)n * 64, "inv_bind"}});
+    if (rc != HS_OK) return rc;
+    hipError_t err = hs::launch_skin(n, global, inv_bind, skin_out, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_skin");
+    return HS_OK;
+}
+
+hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const float *grad_global, const float *ckpt,
+                           int32_t ckpt_k, float *grad_quat, float *grad_trans, float *grad_scale, uint32_t flags,
+                           hipStream_t stream)
+{
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: plan is NULL");
+    if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: flags must be 0");
+    if (!grad_global || !grad_quat || !grad_trans)
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: grad_global, grad_quat and grad_trans must be non-NULL");
+    if (ckpt && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: ckpt_k must be >= 1");
+    for (const void *p : {(const void *)grad_global, (const void *)grad_quat, (const void *)ckpt})
+        if (p && !aligned(p, 16)) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: grad_global, grad_quat and ckpt must be 16-byte aligned");
+    if (!aligned(grad_trans, 4) || (grad_scale && !aligned(grad_scale, 4)))
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: grad_trans/grad_scale must be 4-byte aligned");
+    hs::PoseArgs pa;
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, src, pa, ins, false);
+    if (rc != HS_OK) return rc;
+    const size_t N = (size_t)plan->N;
+    ins.push_back({grad_global, N * 64, "grad_global"});
+    ins.push_back({ckpt, ckpt ? N * 48 : 0, "ckpt"});
+    std::vector<Range> outs = {{grad_quat, N * 16, "grad_quat"}, {grad_trans, N * 12, "grad_trans"},
+                               {grad_scale, grad_scale ? N * 12 : 0, "grad_scale"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    if (N == 0) return HS_OK;
+    hs::BwdArgs ba{};
+    ba.grad_global = grad_global;
+    ba.ckpt = ckpt;
+    ba.ckpt_k = ckpt ? ckpt_k : 1;
+    ba.level = plan->d_level;
+    ba.grad_quat = grad_quat;
+    ba.grad_trans = grad_trans;
+    ba.grad_scale = grad_scale;
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_backward: cannot select device");
+    hipError_t err = hs::launch_backward_tiles(tile_launch(plan), pa, ba, stream);
+    if (err == hipErrorNotSupported) return fail(HS_ERR_UNSUPPORTED, "hs_scan_backward: not available");
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
+    hs_plan *mp = const_cast<hs_plan *>(plan);
+    err = hs::launch_backward_multipass(mp_launch(plan), pa, ba, mp->d_mp_adj, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (multipass)");
+    return HS_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,110 @@
+// hs_internal.h -- device-table layouts and kernel-launch entry points shared
+// by the C-ABI host code (hs_capi.cpp) and the kernels (hs_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hs {
+
+// Largest tile (joints) a workgroup can hold in the 160 KiB LDS of gfx950,
+// including the per-character table of the fused sampler.
+constexpr int kMaxTileJoints = 3072;
+
+// A tile: a contiguous range of global joint ids holding whole characters,
+// scanned by one workgroup entirely in LDS.
+struct TileDesc {
+    int64_t begin;      // global id of the tile's first joint
+    int32_t count;      // joints in the tile (<= tile capacity)
+    int32_t first_char; // index of the tile's first character
+    int32_t num_chars;  // characters in the tile (empty ones included)
+    int32_t pad[3];
+};
+static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
+
+// A 64-joint block of a character on the multipass path.  Blocks start at
+// the character's first joint, so a block never spans two characters.
+struct MPBlock {
+    int64_t gbegin;  // global id of the block's first joint
+    int64_t cbegin;  // index of that joint in the compact multipass arrays
+    int32_t count;   // joints in the block (1..64)
+    int32_t chr;     // character index
+    int64_t pad;
+};
+static_assert(sizeof(MPBlock) == 32, "MPBlock layout");
+
+// Where local poses come from.
+struct PoseArgs {
+    int32_t kind;          // 0 = TRS arrays, 1 = clips
+    const float *quat;     // [N,4]
+    const float *trans;    // [N,3]
+    const float *scale;    // [N,3] or null
+    // clips
+    const int64_t *offsets; // [C+1] device copy of the CSR offsets
+    int32_t num_clips, num_keys, joints_per_clip;
+    float fps;
+    const float *key_quat;  // [clips][keys][J][4]
+    const float *key_trans; // [clips][keys][J][3]
+    const int32_t *clip_a, *clip_b;
+    const float *time, *weight;
+};
+
+// Outputs of a forward pass.
+struct OutArgs {
+    float *global_out;      // [N,16] or null
+    const float *inv_bind;  // [N,16] or null
+    float *skin_out;        // [N,16] or null
+    float *ckpt;            // [N,12] or null
+    int32_t ckpt_k;
+    const int32_t *level;   // [N] level of each joint (root = 1), for checkpoints
+};
+
+struct TileLaunch {
+    const TileDesc *tiles;
+    int32_t num_tiles;
+    int32_t tile_cap;   // joints
+    int32_t waves;      // 1..16
+    int32_t grid;       // workgroups
+    const int32_t *parent; // [N] global parent id or -1
+};
+
+struct MPLaunch {
+    const MPBlock *blocks;
+    int32_t num_blocks;
+    int32_t rounds;
+    int64_t nmp;              // joints on the multipass path (compact count)
+    const int32_t *parent;    // [N] global parent id or -1
+    float4 *P[2];             // [Nmp*3] ping-pong partial products
+    int32_t *E[2];            // [Nmp]   ping-pong ext pointers (compact ids)
+};
+
+struct BwdArgs {
+    const float *grad_global; // [N,16]
+    const float *ckpt;        // [N,12] or null
+    int32_t ckpt_k;
+    const int32_t *level;     // [N]
+    float *grad_quat;         // [N,4]
+    float *grad_trans;        // [N,3]
+    float *grad_scale;        // [N,3] or null
+};
+
+// Kernel launchers (hs_kernels.hip).  Each returns the hipError_t of the
+// launch; none synchronises or allocates.
+hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                hipStream_t stream);
+hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
+                                    hipStream_t stream);
+hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
+                                 hipStream_t stream);
+hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, const BwdArgs &bwd,
+                                     float4 *adj[2], hipStream_t stream);
+hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const PoseArgs &pose,
+                              float *quat_out, float *trans_out, hipStream_t stream);
+hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,
+                       hipStream_t stream);
+
+// LDS bytes one tiled-forward workgroup needs.
+size_t forward_tile_lds_bytes(int tile_cap, bool sample);
+size_t backward_tile_lds_bytes(int tile_cap);
+
+} // namespace hs

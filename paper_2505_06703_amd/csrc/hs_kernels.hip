@@ -1,0 +1,622 @@
+// hs_kernels.hip -- CDNA4 (gfx950) kernels of the hierarchy scan.
+//
+// Data layout
+//   Local poses are read as structure-of-arrays fields (quat [N,4] as one
+//   16-byte vector per joint, trans/scale [N,3]); 64 consecutive joints are
+//   handled by one 64-lane wave, so every load instruction of a wave reads
+//   one contiguous span.  Affine transforms live in registers as 3x4
+//   row-major fp32 (12 values); the constant bottom row (0,0,0,1) is never
+//   stored or multiplied.
+//
+// Forward scan (tiled path, fwd_tile_kernel)
+//   A workgroup owns a tile: a contiguous id range of whole characters.
+//   The tile is cut into 64-joint blocks (the paper's blocks, Sec. 3.2.1),
+//   one block per wave at a time.
+//   Phase 1: pointer jumping restricted to in-block ancestors (Sec. 3.1 and
+//     Eq. 2, applied inside the block as in Sec. 3.2), done with cross-lane
+//     permutes: the 64 lanes of a wave run in lockstep, so the rounds need
+//     no barrier and read the previous round's registers by construction.
+//     The wave keeps jumping only while some lane still has an in-block
+//     ancestor, i.e. ceil(log2(in-block depth)) rounds.  Each lane ends with
+//     the product over its in-block path and its nearest out-of-block
+//     ancestor (MaxParentOutBlock of Sec. 3.2.1).
+//   Phase 2: instead of walking the out-of-block ancestors' partial
+//     products (one composition per block crossed), each block waits on an
+//     LDS flag until the block holding its out-of-block ancestor is final
+//     and then needs exactly one composition: G_j = G_ext(j) * P_j.  Blocks
+//     only depend on lower-numbered blocks and every wave processes its
+//     blocks in increasing order, so the waits always drain.  Final 3x4
+//     transforms are kept in LDS for later blocks and written to HBM as
+//     contiguous 16-byte rows.
+//
+// Forward scan (multipass path) for characters larger than a tile:
+//   the same phase 1 per 64-joint block into HBM, then ceil(log2 L)
+//   rounds of global pointer jumping over the blocks' out-of-block
+//   pointers (L = longest chain of blocks on a path), then one output pass.
+//
+// All arithmetic is fp32 on the vector ALUs with fused multiply-adds; the
+// 3x4 compositions are far too small for matrix cores.
+
+#include "hs_internal.h"
+
+#include <cmath>
+
+namespace hs {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kSpinLimit = 1 << 22;
+
+// ---------------------------------------------------------------------------
+// 3x4 affine helpers (row-major, m[4*r + c], column 3 = translation)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void aff_identity(float m[12])
+{
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m[k] = (k % 5 == 0) ? 1.0f : 0.0f;
+}
+
+// L = [R(q) diag(s) | t] with the textbook polynomial of q = (x, y, z, w).
+__device__ __forceinline__ void aff_from_trs(float4 q, float tx, float ty, float tz, float sx,
+                                             float sy, float sz, float m[12])
+{
+    const float x = q.x, y = q.y, z = q.z, w = q.w;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float xy = x * y, xz = x * z, yz = y * z;
+    const float wx = w * x, wy = w * y, wz = w * z;
+    m[0] = (1.0f - 2.0f * (yy + zz)) * sx;
+    m[1] = 2.0f * (xy - wz) * sy;
+    m[2] = 2.0f * (xz + wy) * sz;
+    m[3] = tx;
+    m[4] = 2.0f * (xy + wz) * sx;
+    m[5] = (1.0f - 2.0f * (xx + zz)) * sy;
+    m[6] = 2.0f * (yz - wx) * sz;
+    m[7] = ty;
+    m[8] = 2.0f * (xz - wy) * sx;
+    m[9] = 2.0f * (yz + wx) * sy;
+    m[10] = (1.0f - 2.0f * (xx + yy)) * sz;
+    m[11] = tz;
+}
+
+// o = a * b  ([A|u][B|v] = [AB | Av + u]): 36 FMA-class operations.
+__device__ __forceinline__ void aff_mul(const float a[12], const float b[12], float o[12])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float a0 = a[4 * r], a1 = a[4 * r + 1], a2 = a[4 * r + 2], a3 = a[4 * r + 3];
+        o[4 * r + 0] = fmaf(a0, b[0], fmaf(a1, b[4], a2 * b[8]));
+        o[4 * r + 1] = fmaf(a0, b[1], fmaf(a1, b[5], a2 * b[9]));
+        o[4 * r + 2] = fmaf(a0, b[2], fmaf(a1, b[6], a2 * b[10]));
+        o[4 * r + 3] = fmaf(a0, b[3], fmaf(a1, b[7], fmaf(a2, b[11], a3)));
+    }
+}
+
+__device__ __forceinline__ void aff_mul_left(const float a[12], float m[12])
+{
+    float o[12];
+    aff_mul(a, m, o);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m[k] = o[k];
+}
+
+__device__ __forceinline__ void aff_load(const float4 *p, float m[12])
+{
+    const float4 r0 = p[0], r1 = p[1], r2 = p[2];
+    m[0] = r0.x; m[1] = r0.y; m[2] = r0.z; m[3] = r0.w;
+    m[4] = r1.x; m[5] = r1.y; m[6] = r1.z; m[7] = r1.w;
+    m[8] = r2.x; m[9] = r2.y; m[10] = r2.z; m[11] = r2.w;
+}
+
+__device__ __forceinline__ void aff_store(float4 *p, const float m[12])
+{
+    p[0] = make_float4(m[0], m[1], m[2], m[3]);
+    p[1] = make_float4(m[4], m[5], m[6], m[7]);
+    p[2] = make_float4(m[8], m[9], m[10], m[11]);
+}
+
+__device__ __forceinline__ float lane_read(float v, int byte_addr)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
+}
+
+// ---------------------------------------------------------------------------
+// Simulation step: sample two looping clips and blend them.
+// ---------------------------------------------------------------------------
+
+// Normalised lerp of two key quaternions; the shorter-arc sign is taken from
+// an fp64 sum of the exact fp32 products (x, y, z, w order) so that it is
+// reproducible bit for bit on any implementation.
+__device__ __forceinline__ float4 nlerp_keys(float4 a, float4 b, float alpha)
+{
+    double d = (double)a.x * (double)b.x;
+    d = d + (double)a.y * (double)b.y;
+    d = d + (double)a.z * (double)b.z;
+    d = d + (double)a.w * (double)b.w;
+    const float u = 1.0f - alpha;
+    const float v = d < 0.0 ? -alpha : alpha;
+    float4 r = make_float4(fmaf(u, a.x, v * b.x), fmaf(u, a.y, v * b.y), fmaf(u, a.z, v * b.z),
+                           fmaf(u, a.w, v * b.w));
+    const float inv = rsqrtf(fmaf(r.x, r.x, fmaf(r.y, r.y, fmaf(r.z, r.z, r.w * r.w))));
+    return make_float4(r.x * inv, r.y * inv, r.z * inv, r.w * inv);
+}
+
+__device__ __forceinline__ float4 nlerp_blend(float4 a, float4 b, float wgt)
+{
+    const float d = fmaf(a.x, b.x, fmaf(a.y, b.y, fmaf(a.z, b.z, a.w * b.w)));
+    const float u = 1.0f - wgt;
+    const float v = d < 0.0f ? -wgt : wgt;
+    float4 r = make_float4(fmaf(u, a.x, v * b.x), fmaf(u, a.y, v * b.y), fmaf(u, a.z, v * b.z),
+                           fmaf(u, a.w, v * b.w));
+    const float inv = rsqrtf(fmaf(r.x, r.x, fmaf(r.y, r.y, fmaf(r.z, r.z, r.w * r.w))));
+    return make_float4(r.x * inv, r.y * inv, r.z * inv, r.w * inv);
+}
+
+// Sampled local pose of joint j (character-local) of character chr.  An
+// out-of-range clip id or a non-finite time yields NaN poses (never an
+// out-of-bounds read).
+__device__ __forceinline__ void sample_pose(const PoseArgs &P, int chr, int j, float4 &q, float &tx,
+                                            float &ty, float &tz)
+{
+    const int ca = P.clip_a[chr], cb = P.clip_b[chr];
+    const float tau = P.time[chr], wgt = P.weight[chr];
+    const int K = P.num_keys, J = P.joints_per_clip;
+    const float f = __fmul_rn(P.fps, tau);
+    const float fl = floorf(f);
+    const float alpha = f - fl;
+    const bool ok = isfinite(fl) && ca >= 0 && ca < P.num_clips && cb >= 0 && cb < P.num_clips;
+    if (!ok) {
+        const float nan = __int_as_float(0x7fc00000);
+        q = make_float4(nan, nan, nan, nan);
+        tx = ty = tz = nan;
+        return;
+    }
+    float r = fmodf(fl, (float)K);
+    if (r < 0.0f) r += (float)K;
+    int k0 = (int)r;
+    if (k0 >= K) k0 = 0;
+    const int k1 = (k0 + 1 == K) ? 0 : k0 + 1;
+    const int64_t ia0 = ((int64_t)ca * K + k0) * J + j, ia1 = ((int64_t)ca * K + k1) * J + j;
+    const int64_t ib0 = ((int64_t)cb * K + k0) * J + j, ib1 = ((int64_t)cb * K + k1) * J + j;
+    const float4 *kq = reinterpret_cast<const float4 *>(P.key_quat);
+    const float4 qa = nlerp_keys(kq[ia0], kq[ia1], alpha);
+    const float4 qb = nlerp_keys(kq[ib0], kq[ib1], alpha);
+    const float *kt = P.key_trans;
+    const float u = 1.0f - alpha;
+    const float ax = fmaf(u, kt[3 * ia0 + 0], alpha * kt[3 * ia1 + 0]);
+    const float ay = fmaf(u, kt[3 * ia0 + 1], alpha * kt[3 * ia1 + 1]);
+    const float az = fmaf(u, kt[3 * ia0 + 2], alpha * kt[3 * ia1 + 2]);
+    const float bx = fmaf(u, kt[3 * ib0 + 0], alpha * kt[3 * ib1 + 0]);
+    const float by = fmaf(u, kt[3 * ib0 + 1], alpha * kt[3 * ib1 + 1]);
+    const float bz = fmaf(u, kt[3 * ib0 + 2], alpha * kt[3 * ib1 + 2]);
+    q = nlerp_blend(qa, qb, wgt);
+    const float uw = 1.0f - wgt;
+    tx = fmaf(uw, ax, wgt * bx);
+    ty = fmaf(uw, ay, wgt * by);
+    tz = fmaf(uw, az, wgt * bz);
+}
+
+template <bool SAMPLE>
+__device__ __forceinline__ void load_local(const PoseArgs &P, int64_t gid, int chr, int lj, float m[12])
+{
+    if constexpr (SAMPLE) {
+        float4 q;
+        float tx, ty, tz;
+        sample_pose(P, chr, lj, q, tx, ty, tz);
+        aff_from_trs(q, tx, ty, tz, 1.0f, 1.0f, 1.0f, m);
+    } else {
+        const float4 q = reinterpret_cast<const float4 *>(P.quat)[gid];
+        const float *t = P.trans + 3 * gid;
+        float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+        if (P.scale) {
+            const float *s = P.scale + 3 * gid;
+            sx = s[0]; sy = s[1]; sz = s[2];
+        }
+        aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1: in-block pointer jumping across the 64 lanes of a wave.
+//   a : lane of the current in-block jump target, or -1
+//   e : nearest out-of-block ancestor once known (caller's id space), or -1
+// On return every lane holds the product over its in-block path.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_inblock_scan(float m[12], int &a, int &e, int lane)
+{
+    while (__any(a >= 0)) {
+        const int src = (a >= 0 ? a : lane) << 2;
+        float ma[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ma[k] = lane_read(m[k], src);
+        const int aa = __builtin_amdgcn_ds_bpermute(src, a);
+        const int ea = __builtin_amdgcn_ds_bpermute(src, e);
+        if (a >= 0) {
+            aff_mul_left(ma, m);
+            if (aa < 0) e = ea;
+            a = aa;
+        }
+    }
+}
+
+// Find the character of tile-local joint jl: the largest i with cstart[i] <= jl.
+__device__ __forceinline__ int tile_char_of(const int *cstart, int num_chars, int jl)
+{
+    int lo = 0, hi = num_chars - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cstart[mid] <= jl) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t gid, const float m[12])
+{
+    if (out.skin_out) {
+        const float4 *B = reinterpret_cast<const float4 *>(out.inv_bind) + 4 * gid;
+        const float4 b0 = B[0], b1 = B[1], b2 = B[2], b3 = B[3];
+        float4 *S = reinterpret_cast<float4 *>(out.skin_out) + 4 * gid;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float g0 = m[4 * r], g1 = m[4 * r + 1], g2 = m[4 * r + 2], g3 = m[4 * r + 3];
+            S[r] = make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
+                               fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
+                               fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
+                               fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w))));
+        }
+        S[3] = b3;
+    }
+    if (out.ckpt && out.level[gid] % out.ckpt_k == 0)
+        aff_store(reinterpret_cast<float4 *>(out.ckpt) + 3 * gid, m);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled forward kernel.
+// LDS: G[cap][3] float4 | block flags [cap/64] int | (SAMPLE) char starts [cap+1]
+// ---------------------------------------------------------------------------
+template <int WAVES, bool SAMPLE>
+__global__ void __launch_bounds__(WAVES * kWave)
+fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
+{
+    extern __shared__ float4 lds[];
+    const int cap = tl.tile_cap;
+    float4 *Gs = lds;
+    int *flags = reinterpret_cast<int *>(lds + 3 * cap);
+    int *cstart = flags + (cap >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        const int n = td.count;
+        const int nblk = (n + kWave - 1) / kWave;
+        for (int i = threadIdx.x; i < nblk; i += WAVES * kWave) flags[i] = 0;
+        if constexpr (SAMPLE) {
+            for (int i = threadIdx.x; i <= td.num_chars; i += WAVES * kWave)
+                cstart[i] = (int)(pose.offsets[td.first_char + i] - td.begin);
+        }
+        __syncthreads();
+
+        for (int b = wave; b < nblk; b += WAVES) {
+            const int base = b * kWave;
+            const int jl = base + lane;
+            const bool valid = jl < n;
+            const int64_t gid = td.begin + jl;
+            float m[12];
+            int a = -1, e = -1;
+            if (valid) {
+                const int p = tl.parent[gid];
+                const int pl = p < 0 ? -1 : (int)(p - td.begin);
+                if (pl >= base) a = pl - base; else e = pl;
+                int chr = 0, lj = 0;
+                if constexpr (SAMPLE) {
+                    const int c = tile_char_of(cstart, td.num_chars, jl);
+                    chr = td.first_char + c;
+                    lj = jl - cstart[c];
+                }
+                load_local<SAMPLE>(pose, gid, chr, lj, m);
+            } else {
+                aff_identity(m);
+            }
+
+            wave_inblock_scan(m, a, e, lane);
+
+            // Phase 2: one composition with the final transform of the
+            // out-of-block ancestor, once its block has published it.
+            // The wait is bounded so that a broken invariant can never hang
+            // the device: after kSpinLimit polls (far beyond any legitimate
+            // wait) the block proceeds with whatever the LDS holds.
+            const bool need = valid && e >= 0;
+            const int fb = need ? (e / kWave) : 0;
+            for (int spin = 0; spin < kSpinLimit; ++spin) {
+                const int ok = need ? __hip_atomic_load(flags + fb, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_WORKGROUP)
+                                    : 1;
+                if (__all(ok)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (need) {
+                float g[12];
+                aff_load(Gs + 3 * e, g);
+                aff_mul_left(g, m);
+            }
+            if (valid) aff_store(Gs + 3 * jl, m);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0)
+                __hip_atomic_store(flags + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+            if (out.global_out) {
+                // 64 joints x 4 rows = 256 16-byte rows, 4 per lane, each
+                // store instruction covering 1 KiB of contiguous output.
+                float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * (td.begin + base);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = lane + kWave * k;
+                    const int jj = base + (c >> 2);
+                    const int r = c & 3;
+                    if (jj < n) dst[c] = (r == 3) ? bottom : Gs[3 * jj + r];
+                }
+            }
+            if (valid) write_skin_and_ckpt(out, gid, m);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Multipass path.
+// ---------------------------------------------------------------------------
+constexpr int kMPWaves = 4;
+
+template <bool SAMPLE>
+__global__ void __launch_bounds__(kMPWaves * kWave)
+mp_local_kernel(MPLaunch ml, PoseArgs pose)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
+    if (w >= ml.num_blocks) return;  // whole waves leave together
+    const MPBlock bd = ml.blocks[w];
+    const bool valid = lane < bd.count;
+    const int64_t gid = bd.gbegin + lane;
+    const int64_t cid = bd.cbegin + lane;
+    float m[12];
+    int a = -1, e = -1;
+    if (valid) {
+        const int p = ml.parent[gid];
+        if (p >= 0) {
+            const int64_t off = (int64_t)p - bd.gbegin;
+            if (off >= 0) a = (int)off; else e = (int)(off + bd.cbegin);
+        }
+        int lj = 0;
+        if constexpr (SAMPLE) lj = (int)(gid - pose.offsets[bd.chr]);
+        load_local<SAMPLE>(pose, gid, bd.chr, lj, m);
+    } else {
+        aff_identity(m);
+    }
+    wave_inblock_scan(m, a, e, lane);
+    if (valid) {
+        aff_store(ml.P[0] + 3 * cid, m);
+        ml.E[0][cid] = e;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+mp_jump_kernel(int64_t nmp, const float4 *Pin, const int32_t *Ein, float4 *Pout, int32_t *Eout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmp) return;
+    float m[12];
+    aff_load(Pin + 3 * i, m);
+    int e = Ein[i];
+    if (e >= 0) {
+        float g[12];
+        aff_load(Pin + 3 * (int64_t)e, g);
+        aff_mul_left(g, m);
+        e = Ein[e];
+    }
+    aff_store(Pout + 3 * i, m);
+    Eout[i] = e;
+}
+
+__global__ void __launch_bounds__(kMPWaves * kWave)
+mp_out_kernel(MPLaunch ml, const float4 *P, OutArgs out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
+    if (w >= ml.num_blocks) return;
+    const MPBlock bd = ml.blocks[w];
+    if (lane >= bd.count) return;
+    const int64_t gid = bd.gbegin + lane;
+    float m[12];
+    aff_load(P + 3 * (bd.cbegin + lane), m);
+    if (out.global_out) {
+        float4 *G = reinterpret_cast<float4 *>(out.global_out) + 4 * gid;
+        aff_store(G, m);
+        G[3] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    }
+    write_skin_and_ckpt(out, gid, m);
+}
+
+// ---------------------------------------------------------------------------
+// Standalone Simulation step and Bind MeshPose step.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+sample_tile_kernel(TileLaunch tl, PoseArgs pose, float *quat_out, float *trans_out)
+{
+    extern __shared__ float4 lds[];
+    int *cstart = reinterpret_cast<int *>(lds);
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        for (int i = threadIdx.x; i <= td.num_chars; i += blockDim.x)
+            cstart[i] = (int)(pose.offsets[td.first_char + i] - td.begin);
+        __syncthreads();
+        for (int jl = threadIdx.x; jl < td.count; jl += blockDim.x) {
+            const int c = tile_char_of(cstart, td.num_chars, jl);
+            const int64_t gid = td.begin + jl;
+            float4 q;
+            float tx, ty, tz;
+            sample_pose(pose, td.first_char + c, jl - cstart[c], q, tx, ty, tz);
+            reinterpret_cast<float4 *>(quat_out)[gid] = q;
+            trans_out[3 * gid + 0] = tx;
+            trans_out[3 * gid + 1] = ty;
+            trans_out[3 * gid + 2] = tz;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256)
+sample_mp_kernel(MPLaunch ml, PoseArgs pose, float *quat_out, float *trans_out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
+    if (w >= ml.num_blocks) return;
+    const MPBlock bd = ml.blocks[w];
+    if (lane >= bd.count) return;
+    const int64_t gid = bd.gbegin + lane;
+    float4 q;
+    float tx, ty, tz;
+    sample_pose(pose, bd.chr, (int)(gid - pose.offsets[bd.chr]), q, tx, ty, tz);
+    reinterpret_cast<float4 *>(quat_out)[gid] = q;
+    trans_out[3 * gid + 0] = tx;
+    trans_out[3 * gid + 1] = ty;
+    trans_out[3 * gid + 2] = tz;
+}
+
+__global__ void __launch_bounds__(256)
+skin_kernel(int64_t n, const float4 *G, const float4 *B, float4 *S)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 b0 = B[4 * i], b1 = B[4 * i + 1], b2 = B[4 * i + 2], b3 = B[4 * i + 3];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float4 g = G[4 * i + r];
+        S[4 * i + r] = make_float4(fmaf(g.x, b0.x, fmaf(g.y, b1.x, fmaf(g.z, b2.x, g.w * b3.x))),
+                                   fmaf(g.x, b0.y, fmaf(g.y, b1.y, fmaf(g.z, b2.y, g.w * b3.y))),
+                                   fmaf(g.x, b0.z, fmaf(g.y, b1.z, fmaf(g.z, b2.z, g.w * b3.z))),
+                                   fmaf(g.x, b0.w, fmaf(g.y, b1.w, fmaf(g.z, b2.w, g.w * b3.w))));
+    }
+}
+
+template <int WAVES, bool SAMPLE>
+hipError_t launch_fwd_tiles_t(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                              hipStream_t stream)
+{
+    const size_t lds = forward_tile_lds_bytes(tl.tile_cap, SAMPLE);
+    auto kern = fwd_tile_kernel<WAVES, SAMPLE>;
+    static bool lds_attr_set = false;  // the largest tile's LDS, set once per kernel
+    if (!lds_attr_set) {
+        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)forward_tile_lds_bytes(kMaxTileJoints, true));
+        if (err != hipSuccess) return err;
+        lds_attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, out);
+    return hipGetLastError();
+}
+
+template <bool SAMPLE>
+hipError_t launch_fwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                              hipStream_t stream)
+{
+    switch (tl.waves) {
+    case 1: return launch_fwd_tiles_t<1, SAMPLE>(tl, pose, out, stream);
+    case 2: return launch_fwd_tiles_t<2, SAMPLE>(tl, pose, out, stream);
+    case 4: return launch_fwd_tiles_t<4, SAMPLE>(tl, pose, out, stream);
+    case 8: return launch_fwd_tiles_t<8, SAMPLE>(tl, pose, out, stream);
+    case 16: return launch_fwd_tiles_t<16, SAMPLE>(tl, pose, out, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+} // namespace
+
+size_t forward_tile_lds_bytes(int tile_cap, bool sample)
+{
+    size_t bytes = (size_t)tile_cap * 48 + (size_t)(tile_cap / kWave) * 4;
+    if (sample) bytes += (size_t)(tile_cap + 1) * 4;
+    return bytes;
+}
+
+hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                hipStream_t stream)
+{
+    if (tl.num_tiles == 0) return hipSuccess;
+    return pose.kind == 1 ? launch_fwd_tiles_w<true>(tl, pose, out, stream)
+                          : launch_fwd_tiles_w<false>(tl, pose, out, stream);
+}
+
+hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
+                                    hipStream_t stream)
+{
+    if (ml.num_blocks == 0) return hipSuccess;
+    const dim3 blk(kMPWaves * kWave);
+    const dim3 grid((ml.num_blocks + kMPWaves - 1) / kMPWaves);
+    if (pose.kind == 1)
+        hipLaunchKernelGGL(mp_local_kernel<true>, grid, blk, 0, stream, ml, pose);
+    else
+        hipLaunchKernelGGL(mp_local_kernel<false>, grid, blk, 0, stream, ml, pose);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    int cur = 0;
+    const dim3 jgrid((unsigned)((ml.nmp + 255) / 256));
+    for (int r = 0; r < ml.rounds; ++r) {
+        hipLaunchKernelGGL(mp_jump_kernel, jgrid, dim3(256), 0, stream, ml.nmp, ml.P[cur], ml.E[cur],
+                           ml.P[cur ^ 1], ml.E[cur ^ 1]);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(mp_out_kernel, grid, blk, 0, stream, ml, ml.P[cur], out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const PoseArgs &pose,
+                              float *quat_out, float *trans_out, hipStream_t stream)
+{
+    if (tl.num_tiles > 0) {
+        const size_t lds = (size_t)(tl.tile_cap + 1) * 4;
+        hipLaunchKernelGGL(sample_tile_kernel, dim3(tl.num_tiles), dim3(256), lds, stream, tl, pose,
+                           quat_out, trans_out);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (ml.num_blocks > 0) {
+        hipLaunchKernelGGL(sample_mp_kernel, dim3((ml.num_blocks + kMPWaves - 1) / kMPWaves),
+                           dim3(kMPWaves * kWave), 0, stream, ml, pose, quat_out, trans_out);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,
+                       hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(skin_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n,
+                       reinterpret_cast<const float4 *>(global),
+                       reinterpret_cast<const float4 *>(inv_bind),
+                       reinterpret_cast<float4 *>(skin_out));
+    return hipGetLastError();
+}
+
+size_t backward_tile_lds_bytes(int tile_cap)
+{
+    return (size_t)tile_cap * 96 + (size_t)(tile_cap / kWave) * 8;
+}
+
+hipError_t launch_backward_tiles(const TileLaunch &, const PoseArgs &, const BwdArgs &, hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+hipError_t launch_backward_multipass(const MPLaunch &, const PoseArgs &, const BwdArgs &,
+                                     float4 *[2], hipStream_t)
+{
+    return hipErrorNotSupported;
+}
+
+} // namespace hs

@@ -1,0 +1,333 @@
+"""Python binding of the Hierarchy-Scan C ABI (``include/hs.h``).
+
+Argument marshalling only: every function checks tensor shapes, dtypes,
+devices and contiguity, passes raw device pointers and torch's current HIP
+stream to the C library, and raises :class:`HSError` on a non-zero status.
+All computation happens in the library's HIP kernels; there is no fallback.
+If the library is not built this module raises on import.
+
+The function names follow the C names: :func:`hs_plan_create`,
+:func:`hs_pose_sample`, :func:`hs_scan_forward`, :func:`hs_skin`,
+:func:`hs_scan_backward`.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+from .build import LIB
+
+HS_OK = 0
+HS_ERR_INVALID_ARG = 1
+HS_ERR_TOPOLOGY = 2
+HS_ERR_UNSUPPORTED = 3
+HS_ERR_DEVICE = 4
+HS_ERR_OOM = 5
+
+HS_STRATEGY_AUTO = 0
+HS_STRATEGY_TILE = 1
+HS_STRATEGY_MULTIPASS = 2
+
+HS_POSE_TRS = 0
+HS_POSE_CLIPS = 1
+
+SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
+           "hs_plan_create", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
+           "hs_scan_forward", "hs_skin", "hs_scan_backward")
+
+
+class HSError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"hs status {status}: {message}")
+        self.status = status
+
+
+class hs_batch(ctypes.Structure):
+    _fields_ = [("num_characters", ctypes.c_int64), ("num_joints", ctypes.c_int64),
+                ("joint_offsets", ctypes.c_void_p), ("parents", ctypes.c_void_p)]
+
+
+class hs_plan_opts(ctypes.Structure):
+    _fields_ = [("strategy", ctypes.c_int32), ("tile_joints", ctypes.c_int32),
+                ("waves_per_tile", ctypes.c_int32), ("grid_tiles", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class hs_plan_info(ctypes.Structure):
+    _fields_ = [("num_characters", ctypes.c_int64), ("num_joints", ctypes.c_int64),
+                ("tiled_joints", ctypes.c_int64), ("multipass_joints", ctypes.c_int64),
+                ("max_depth", ctypes.c_int32), ("max_character", ctypes.c_int32),
+                ("num_tiles", ctypes.c_int32), ("tile_joints", ctypes.c_int32),
+                ("waves_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("multipass_rounds", ctypes.c_int32), ("max_block_chain", ctypes.c_int32)]
+
+
+class hs_clip_lib(ctypes.Structure):
+    _fields_ = [("num_clips", ctypes.c_int32), ("num_keys", ctypes.c_int32),
+                ("joints_per_clip", ctypes.c_int32), ("fps", ctypes.c_float),
+                ("key_quat", ctypes.c_void_p), ("key_trans", ctypes.c_void_p)]
+
+
+class hs_clip_params(ctypes.Structure):
+    _fields_ = [("clip_a", ctypes.c_void_p), ("clip_b", ctypes.c_void_p),
+                ("time", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+
+
+class hs_pose_src(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("quat", ctypes.c_void_p), ("trans", ctypes.c_void_p),
+                ("scale", ctypes.c_void_p), ("clips", ctypes.POINTER(hs_clip_lib)),
+                ("params", ctypes.POINTER(hs_clip_params))]
+
+
+_lib = None
+
+
+def library_path():
+    return LIB
+
+
+def load_library():
+    """Load ``libhs.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        raise RuntimeError(f"HIP library not built: {LIB} is missing "
+                           "(run __graft_entry__.build() or paper_2505_06703_amd/build.py)")
+    lib = ctypes.CDLL(LIB)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.hs_version.restype = ctypes.c_char_p
+    lib.hs_last_error.restype = ctypes.c_char_p
+    lib.hs_context_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.hs_context_destroy.argtypes = [vp]
+    lib.hs_context_destroy.restype = None
+    lib.hs_plan_create.argtypes = [vp, ctypes.POINTER(hs_batch), ctypes.POINTER(hs_plan_opts),
+                                   ctypes.POINTER(vp)]
+    lib.hs_plan_destroy.argtypes = [vp]
+    lib.hs_plan_destroy.restype = None
+    lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
+    lib.hs_pose_sample.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
+                                   vp, vp, vp]
+    lib.hs_scan_forward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, i32, u32, vp]
+    lib.hs_skin.argtypes = [i64, vp, vp, vp, vp]
+    lib.hs_scan_backward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp, u32, vp]
+    for name in ("hs_context_create", "hs_plan_create", "hs_plan_get_info", "hs_pose_sample",
+                 "hs_scan_forward", "hs_skin", "hs_scan_backward"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != HS_OK:
+        raise HSError(status, load_library().hs_last_error().decode())
+
+
+def hs_version():
+    return load_library().hs_version().decode()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, name, shape, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Context:
+    """A library context bound to one HIP device."""
+
+    def __init__(self, device=0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.hs_context_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            load_library().hs_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device=None):
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+class Plan:
+    """Topology analysis of a CSR batch (see ``hs_plan_create``)."""
+
+    def __init__(self, offsets, parents, ctx=None, strategy=HS_STRATEGY_AUTO, tile_joints=0,
+                 waves_per_tile=0, grid_tiles=0, autotune=False):
+        self.ctx = ctx or default_context()
+        off = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
+                                              dtype=np.int64))
+        par = np.ascontiguousarray(np.asarray(parents.cpu() if isinstance(parents, torch.Tensor) else parents,
+                                              dtype=np.int32))
+        if off.ndim != 1 or off.size < 1:
+            raise ValueError("offsets must be 1-D with C+1 entries")
+        self.num_characters = off.size - 1
+        self.num_joints = par.size
+        batch = hs_batch(self.num_characters, self.num_joints, off.ctypes.data, par.ctypes.data)
+        opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)))
+        h = ctypes.c_void_p()
+        _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),
+                                             ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def info(self):
+        inf = hs_plan_info()
+        _check(load_library().hs_plan_get_info(self.handle, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in hs_plan_info._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hs_plan_create(offsets, parents, **kw):
+    return Plan(offsets, parents, **kw)
+
+
+class ClipLibrary:
+    """Device-resident clip library: key_quat [K,T,J,4], key_trans [K,T,J,3]."""
+
+    def __init__(self, key_quat, key_trans, fps=30.0):
+        K, T, J, _ = key_quat.shape
+        self.key_quat = _need(key_quat, "key_quat", (K, T, J, 4))
+        self.key_trans = _need(key_trans, "key_trans", (K, T, J, 3))
+        self.fps = float(fps)
+        self.c = hs_clip_lib(K, T, J, self.fps, key_quat.data_ptr(), key_trans.data_ptr())
+
+
+def _clip_params(plan, clip_a, clip_b, time, weight):
+    C = plan.num_characters
+    _need(clip_a, "clip_a", (C,), torch.int32)
+    _need(clip_b, "clip_b", (C,), torch.int32)
+    _need(time, "time", (C,))
+    _need(weight, "weight", (C,))
+    return hs_clip_params(clip_a.data_ptr(), clip_b.data_ptr(), time.data_ptr(), weight.data_ptr())
+
+
+def hs_pose_sample(plan, clips, clip_a, clip_b, time, weight, quat_out=None, trans_out=None, stream=None):
+    """Simulation step: sample and blend two clips per character -> (quat [N,4], trans [N,3])."""
+    N = plan.num_joints
+    dev = clips.key_quat.device
+    q = torch.empty((N, 4), device=dev, dtype=torch.float32) if quat_out is None else _need(quat_out, "quat_out", (N, 4))
+    t = torch.empty((N, 3), device=dev, dtype=torch.float32) if trans_out is None else _need(trans_out, "trans_out", (N, 3))
+    params = _clip_params(plan, clip_a, clip_b, time, weight)
+    _check(load_library().hs_pose_sample(plan.handle, ctypes.byref(clips.c), ctypes.byref(params),
+                                         _ptr(q), _ptr(t), _stream(stream)))
+    return q, t
+
+
+def _trs_src(plan, quat, trans, scale):
+    N = plan.num_joints
+    _need(quat, "quat", (N, 4))
+    _need(trans, "trans", (N, 3))
+    if scale is not None:
+        _need(scale, "scale", (N, 3))
+    return hs_pose_src(HS_POSE_TRS, quat.data_ptr(), trans.data_ptr(),
+                       None if scale is None else scale.data_ptr(), None, None)
+
+
+def hs_scan_forward(plan, quat=None, trans=None, scale=None, *, clips=None, clip_a=None, clip_b=None,
+                    time=None, weight=None, global_out=None, want_global=True, inv_bind=None,
+                    skin_out=None, ckpt_out=None, ckpt_k=0, stream=None, device=None):
+    """Hierarchy-Scan with optional fused skin and checkpoints.
+
+    Poses come from ``quat``/``trans``/``scale`` (TRS) or from ``clips`` and
+    the per-character clip parameters (fused Simulation step).  Returns
+    ``(global [N,4,4] or None, skin [N,4,4] or None)``.
+    """
+    N = plan.num_joints
+    if clips is not None:
+        params = _clip_params(plan, clip_a, clip_b, time, weight)
+        src = hs_pose_src(HS_POSE_CLIPS, None, None, None, ctypes.pointer(clips.c), ctypes.pointer(params))
+        dev = clips.key_quat.device
+    else:
+        src = _trs_src(plan, quat, trans, scale)
+        dev = quat.device
+    if global_out is None and want_global:
+        global_out = torch.empty((N, 4, 4), device=dev, dtype=torch.float32)
+    elif global_out is not None:
+        _need(global_out, "global_out", (N, 4, 4))
+    if inv_bind is not None:
+        _need(inv_bind, "inv_bind", (N, 4, 4))
+        if skin_out is None:
+            skin_out = torch.empty((N, 4, 4), device=dev, dtype=torch.float32)
+        else:
+            _need(skin_out, "skin_out", (N, 4, 4))
+    if ckpt_out is not None:
+        _need(ckpt_out, "ckpt_out", (N, 12))
+    _check(load_library().hs_scan_forward(plan.handle, ctypes.byref(src), _ptr(global_out), _ptr(inv_bind),
+                                          _ptr(skin_out), _ptr(ckpt_out), int(ckpt_k), 0, _stream(stream)))
+    return global_out, skin_out
+
+
+def hs_skin(global_, inv_bind, skin_out=None, stream=None):
+    """Bind MeshPose step: skin_j = global_j @ inv_bind_j (full 4x4)."""
+    n = global_.shape[0]
+    _need(global_, "global", (n, 4, 4))
+    _need(inv_bind, "inv_bind", (n, 4, 4))
+    if skin_out is None:
+        skin_out = torch.empty_like(global_)
+    _need(skin_out, "skin_out", (n, 4, 4))
+    _check(load_library().hs_skin(n, _ptr(global_), _ptr(inv_bind), _ptr(skin_out), _stream(stream)))
+    return skin_out
+
+
+def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0, want_scale=True,
+                     grad_quat=None, grad_trans=None, grad_scale=None, stream=None):
+    """Adjoint of the scan: returns (grad_quat [N,4], grad_trans [N,3], grad_scale [N,3] or None)."""
+    N = plan.num_joints
+    src = _trs_src(plan, quat, trans, scale)
+    _need(grad_global, "grad_global", (N, 4, 4))
+    dev = quat.device
+    gq = torch.empty((N, 4), device=dev, dtype=torch.float32) if grad_quat is None else _need(grad_quat, "grad_quat", (N, 4))
+    gt = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_trans is None else _need(grad_trans, "grad_trans", (N, 3))
+    gs = None
+    if want_scale:
+        gs = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_scale is None else _need(grad_scale, "grad_scale", (N, 3))
+    if ckpt is not None:
+        _need(ckpt, "ckpt", (N, 12))
+    _check(load_library().hs_scan_backward(plan.handle, ctypes.byref(src), _ptr(grad_global), _ptr(ckpt),
+                                           int(ckpt_k), _ptr(gq), _ptr(gt), _ptr(gs), 0, _stream(stream)))
+    return gq, gt, gs

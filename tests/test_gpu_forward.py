@@ -1,0 +1,212 @@
+"""GPU parity of the forward scan and skin against the FP64 oracle.
+
+Every test calls the HIP library through its C ABI (via the ctypes binding)
+and compares element by element with the oracle on the same seeded inputs.
+Full-size workloads are checked on seeded samples of whole characters (the
+oracle handles each character independently, so a sample is exact).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2505_06703_amd import hs
+from paper_2505_06703_amd import workloads as wl
+
+from parity import check_global, check_skin, depth_scale, inverse_binds, reference
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def run_forward(batch, inv=None, **plan_kw):
+    plan = hs.Plan(batch.offsets, batch.parents, **plan_kw)
+    G, S = hs.hs_scan_forward(plan, dev(batch.quat), dev(batch.trans), dev(batch.scale),
+                              inv_bind=None if inv is None else dev(inv))
+    torch.cuda.synchronize()
+    return plan, G.cpu().numpy(), (None if S is None else S.cpu().numpy())
+
+
+def test_plain_scan_full_size_with_fused_skin():
+    b = wl.plain_scan()
+    inv = inverse_binds(b)
+    plan, G, S = run_forward(b, inv)
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, "plain_scan")
+    check_skin(S, Gr, inv, lam, "plain_scan skin")
+
+
+def test_skin_at_rest_pose_is_identity():
+    b = wl.plain_scan(num_characters=8)
+    inv = inverse_binds(b)
+    plan = hs.Plan(b.offsets, b.parents)
+    _, S = hs.hs_scan_forward(plan, dev(b.rest_quat), dev(b.rest_trans), dev(b.rest_scale), inv_bind=dev(inv))
+    S = S.cpu().numpy()
+    np.testing.assert_allclose(S, np.broadcast_to(np.eye(4), S.shape), atol=2e-5)
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4),
+                                   dict(tile_joints=2048, waves_per_tile=8, grid_tiles=2),
+                                   dict(strategy=hs.HS_STRATEGY_MULTIPASS),
+                                   dict(tile_joints=256)])
+def test_deep_forward_reduced(shape):
+    b = wl.deep_forward(num_characters=24)
+    plan, G, _ = run_forward(b, **shape)
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, f"deep_forward {shape}")
+
+
+def test_deep_forward_full_size_sampled():
+    b = wl.deep_forward()
+    plan, G, _ = run_forward(b)
+    info = plan.info
+    assert info["num_joints"] == 4096 * 1024 and info["max_depth"] == 246
+    rng = np.random.default_rng(123)
+    chars = np.sort(rng.choice(b.num_characters, 24, replace=False))
+    chars = np.unique(np.concatenate([[0, b.num_characters - 1], chars]))
+    Gr, lam, ids = reference(b, chars=chars)
+    check_global(G[ids], Gr, lam, "deep_forward full (sampled)")
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024),
+                                   dict(strategy=hs.HS_STRATEGY_MULTIPASS)])
+def test_heterogeneous_reduced(shape):
+    b = wl.heterogeneous(num_characters=300, chain_fraction=0.02)
+    plan, G, _ = run_forward(b, **shape)
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, f"heterogeneous {shape}")
+
+
+def test_heterogeneous_full_size_sampled():
+    b = wl.heterogeneous()
+    plan, G, _ = run_forward(b)
+    rng = np.random.default_rng(7)
+    chains = np.nonzero(b.extra["is_chain"])[0]
+    chars = np.unique(np.concatenate([rng.choice(b.num_characters, 40, replace=False), chains[:8],
+                                      [int(np.argmax(np.diff(b.offsets)))]]))
+    Gr, lam, ids = reference(b, chars=chars)
+    check_global(G[ids], Gr, lam, "heterogeneous full (sampled)")
+
+
+def _single(parents, seed=0, angle=0.3):
+    rng = np.random.default_rng(seed)
+    parents = np.asarray(parents, np.int32)
+    n = parents.size
+    q, t, s = wl.random_pose(rng, n, max_angle=angle)
+    rq, rt, rs = wl.random_pose(rng, n)
+    return wl.Batch("single", np.array([0, n], np.int64), parents, q, t, s, rq, rt, rs)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 1000, 2048, 2049, 5000])
+def test_chains_of_many_lengths(n):
+    b = _single(np.arange(-1, n - 1), seed=n, angle=0.1)
+    plan, G, _ = run_forward(b)
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, f"chain {n}")
+
+
+def test_chain_of_100k_joints_multipass_stress():
+    n = 100_000
+    b = _single(np.arange(-1, n - 1), seed=5, angle=0.02)
+    plan, G, _ = run_forward(b)
+    assert plan.info["multipass_joints"] == n and plan.info["multipass_rounds"] == 11
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, "chain 1e5", scale=depth_scale(n))
+
+
+def test_star_forest_and_empty_characters():
+    star = np.zeros(1500, np.int32)
+    star[0] = -1
+    forest = np.array([-1, 0, -1, 2, -1, 4, 4, 0, -1, 8] * 40, np.int32)
+    forest = np.where(forest >= 0, forest + np.repeat(np.arange(40) * 10, 10), -1).astype(np.int32)
+    parts = [star, np.zeros(0, np.int32), forest, np.array([-1], np.int32), np.zeros(0, np.int32)]
+    off = np.concatenate([[0], np.cumsum([p.size for p in parts])]).astype(np.int64)
+    par = np.concatenate(parts)
+    rng = np.random.default_rng(3)
+    q, t, s = wl.random_pose(rng, par.size)
+    s = rng.uniform(0.8, 1.25, s.shape).astype(np.float32)  # non-uniform scale too
+    b = wl.Batch("mixed", off, par, q, t, s, q, t, s)
+    for shape in (dict(), dict(tile_joints=64), dict(strategy=hs.HS_STRATEGY_MULTIPASS)):
+        plan, G, _ = run_forward(b, **shape)
+        Gr, lam, _ = reference(b)
+        check_global(G, Gr, lam, f"star/forest/empty {shape}")
+
+
+def test_identity_pose_is_exact_identity():
+    b = wl.heterogeneous(num_characters=200)
+    N = b.num_joints
+    q = np.tile(np.float32([0, 0, 0, 1]), (N, 1))
+    plan = hs.Plan(b.offsets, b.parents)
+    G, _ = hs.hs_scan_forward(plan, dev(q), dev(np.zeros((N, 3), np.float32)), None)
+    G = G.cpu().numpy()
+    assert np.array_equal(G, np.broadcast_to(np.eye(4, dtype=np.float32), G.shape))
+
+
+def test_null_scale_equals_unit_scale_array():
+    b = wl.plain_scan(num_characters=16)
+    plan = hs.Plan(b.offsets, b.parents)
+    G1, _ = hs.hs_scan_forward(plan, dev(b.quat), dev(b.trans), None)
+    G2, _ = hs.hs_scan_forward(plan, dev(b.quat), dev(b.trans), dev(np.ones_like(b.trans)))
+    assert torch.equal(G1, G2)
+
+
+def test_batching_invariance():
+    """A character scanned alone and inside a batch both meet the oracle bound
+    (block boundaries follow the tile, so the rounding order may differ)."""
+    b = wl.heterogeneous(num_characters=64)
+    plan, G, _ = run_forward(b, tile_joints=2048)
+    for c in (0, 17, 63):
+        lo, hi = b.offsets[c], b.offsets[c + 1]
+        one = wl.Batch("one", np.array([0, hi - lo], np.int64), b.parents[lo:hi], b.quat[lo:hi],
+                       b.trans[lo:hi], b.scale[lo:hi], b.quat[lo:hi], b.trans[lo:hi], b.scale[lo:hi])
+        _, G1, _ = run_forward(one, tile_joints=2048)
+        Gr, lam, _ = reference(one)
+        check_global(G1, Gr, lam, f"alone {c}")
+        check_global(G[lo:hi], Gr, lam, f"in batch {c}")
+
+
+def test_repeat_runs_are_bitwise_deterministic():
+    b = wl.deep_forward(num_characters=32)
+    plan = hs.Plan(b.offsets, b.parents)
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    G0, _ = hs.hs_scan_forward(plan, q, t, s)
+    for _ in range(3):
+        G1, _ = hs.hs_scan_forward(plan, q, t, s)
+        assert torch.equal(G0, G1)
+
+
+def test_checkpoint_rows():
+    b = wl.deep_forward(num_characters=4)
+    N = b.num_joints
+    plan = hs.Plan(b.offsets, b.parents)
+    ck = torch.full((N, 12), 7.0, device=DEV)
+    G, _ = hs.hs_scan_forward(plan, dev(b.quat), dev(b.trans), dev(b.scale), ckpt_out=ck, ckpt_k=8)
+    ck, G = ck.cpu().numpy(), G.cpu().numpy()
+    lev = np.concatenate([wl.levels_of(b.parents[b.offsets[c]:b.offsets[c + 1]]) for c in range(4)])
+    sel = lev % 8 == 0
+    np.testing.assert_array_equal(ck[sel], G[sel, :3, :].reshape(-1, 12))
+    assert np.all(ck[~sel] == 7.0)
+
+
+def test_hs_skin_standalone():
+    rng = np.random.default_rng(4)
+    n = 3001
+    G = rng.standard_normal((n, 4, 4)).astype(np.float32)
+    B = rng.standard_normal((n, 4, 4)).astype(np.float32)
+    S = hs.hs_skin(dev(G), dev(B)).cpu().numpy()
+    ref = oracle.skin(G, B)
+    np.testing.assert_allclose(S, ref, rtol=0, atol=2e-5 * np.abs(ref).max())
+
+
+def test_empty_batch():
+    plan = hs.Plan(np.zeros(1, np.int64), np.zeros(0, np.int32))
+    z = torch.zeros((0, 4), device=DEV)
+    G, _ = hs.hs_scan_forward(plan, z, torch.zeros((0, 3), device=DEV), None)
+    assert G.shape == (0, 4, 4)
+    plan2 = hs.Plan(np.zeros(4, np.int64), np.zeros(0, np.int32))
+    assert plan2.info["num_tiles"] == 0
