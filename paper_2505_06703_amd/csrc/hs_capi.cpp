@@ -644,6 +644,7 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
     }
     sh.waves = o.waves_per_tile > 0 ? o.waves_per_tile : std::min(16, sh.tile_cap / 64);
     if (sh.waves * 64 > sh.tile_cap) sh.waves = sh.tile_cap / 64;
+
     sh.grid_per_cu = o.grid_tiles;
 
     hs_status rc = build_tables(plan, sh, o.strategy);
@@ -670,6 +671,8 @@ hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *gl
 {
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: plan is NULL");
     if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: flags must be 0");
+    if (ckpt_out && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: ckpt_k must be >= 1");
+    if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
     if (!global_out && !skin_out) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: no output requested");
     if ((skin_out != nullptr) != (inv_bind != nullptr))
         return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: inv_bind and skin_out go together");
@@ -703,6 +706,7 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
                          float *quat_out, float *trans_out, hipStream_t stream)
 {
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_pose_sample: plan is NULL");
+    if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
     if (!quat_out || !trans_out) return fail(HS_ERR_INVALID_ARG, "hs_pose_sample: outputs must be non-NULL");
     if (!aligned(quat_out, 16) || !aligned(trans_out, 4))
         return fail(HS_ERR_INVALID_ARG, "hs_pose_sample: quat_out must be 16-byte aligned");
@@ -746,6 +750,8 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
 {
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: plan is NULL");
     if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: flags must be 0");
+    if (ckpt && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: ckpt_k must be >= 1");
+    if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
     if (!grad_global || !grad_quat || !grad_trans)
         return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: grad_global, grad_quat and grad_trans must be non-NULL");
     if (ckpt && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: ckpt_k must be >= 1");

@@ -224,17 +224,25 @@ __device__ __forceinline__ void load_local(const PoseArgs &P, int64_t gid, int c
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_inblock_scan(float m[12], int &a, int &e, int lane)
 {
+    // a (-1..63) and e (-1..2^23) travel packed in one 32-bit permute
+    int code = ((e + 1) << 7) | (a + 1);
     while (__any(a >= 0)) {
-        const int src = (a >= 0 ? a : lane) << 2;
-        float ma[12];
+        const bool act = a >= 0;
+        const int src = (act ? a : lane) << 2;
+        float ma[12], o[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) ma[k] = lane_read(m[k], src);
-        const int aa = __builtin_amdgcn_ds_bpermute(src, a);
-        const int ea = __builtin_amdgcn_ds_bpermute(src, e);
-        if (a >= 0) {
-            aff_mul_left(ma, m);
+        const int ca = __builtin_amdgcn_ds_bpermute(src, code);
+        aff_mul(ma, m, o);
+        // branch-free update keeps the loop free of register copies
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m[k] = act ? o[k] : m[k];
+        const int aa = (ca & 127) - 1;
+        const int ea = (ca >> 7) - 1;
+        if (act) {
             if (aa < 0) e = ea;
             a = aa;
+            code = ((e + 1) << 7) | (a + 1);
         }
     }
 }
@@ -356,7 +364,11 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
                     const int c = lane + kWave * k;
                     const int jj = base + (c >> 2);
                     const int r = c & 3;
-                    if (jj < n) dst[c] = (r == 3) ? bottom : Gs[3 * jj + r];
+                    if (jj < n) {
+                        float4 v = Gs[3 * jj + (r == 3 ? 0 : r)];
+                        if (r == 3) v = bottom;
+                        dst[c] = v;
+                    }
                 }
             }
             if (valid) write_skin_and_ckpt(out, gid, m);
