@@ -62,6 +62,11 @@ def parse():
                     choices=["deep_forward", "plain_scan", "heterogeneous", "fused_sample"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape at plan time")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE run, WRITE_SIZE run) "
+                         "into profiles/traffic.json for --workload and exit")
     return ap.parse_args()
 
 
@@ -77,8 +82,53 @@ BYTES_PER_JOINT = {
 }
 
 
+COPY_BYTES = 256 << 20
+
+
+def summarize_pmc(workload, fetch_csv, write_csv):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the scan kernel,
+    scaled by what the same counters read for the plain copy of COPY_BYTES."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row["Kernel_Name"]
+                key = "scan" if "fwd_tile_kernel" in name else ("copy" if "copy" in name.lower() else None)
+                if key:
+                    vals.setdefault(key, []).append(float(row["Counter_Value"]))
+        # the calibration copy is the largest copy of the run
+        return {"scan": sum(vals["scan"]) / len(vals["scan"]), "copy": max(vals["copy"])}
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    f_scale = COPY_BYTES / (fetch["copy"] * 1024.0)
+    w_scale = COPY_BYTES / (write["copy"] * 1024.0)
+    rec = {"kernel": "fwd_tile_kernel", "source_sha": kernel_source_sha(),
+           "fetch_bytes_per_launch": fetch["scan"] * 1024.0 * f_scale,
+           "write_bytes_per_launch": write["scan"] * 1024.0 * w_scale,
+           "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}
+    rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    try:
+        with open(TRAFFIC_FILE) as f:
+            allrec = json.load(f)
+    except (OSError, ValueError):
+        allrec = {}
+    allrec[workload] = rec
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(allrec, f, indent=1, sort_keys=True)
+    print(json.dumps({workload: rec}))
+
+
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(args.workload, *args.summarize_pmc)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; characters are independent, "
@@ -137,6 +187,12 @@ def main():
         else:
             hs.hs_scan_forward(plan, s["q"], s["t"], s["s"], global_out=s["G"])
 
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()

@@ -136,6 +136,11 @@ struct hs_plan {
     int32_t *d_level = nullptr;
     TileDesc *d_tiles = nullptr;
     std::vector<TileDesc> h_tiles;
+    // adjoint tiles (NULL: the forward tiles are used)
+    TileDesc *d_btiles = nullptr;
+    int32_t num_btiles = 0;
+    int32_t bwd_cap = 0;
+    int64_t bwd_untiled = 0;  // joints the adjoint's tiles do not cover
     // multipass
     MPBlock *d_mp_blocks = nullptr;
     int32_t num_mp_blocks = 0;
@@ -155,6 +160,7 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_parent);
     (void)hipFree(p->d_level);
     (void)hipFree(p->d_tiles);
+    (void)hipFree(p->d_btiles);
     (void)hipFree(p->d_mp_blocks);
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(p->d_mp_P[i]);
@@ -203,18 +209,23 @@ int block_chain_length(const int32_t *par, int64_t n, int64_t align0, std::vecto
     return best;
 }
 
-hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
+struct Packing {
+    std::vector<TileDesc> tiles;  // sorted, heaviest first
+    std::vector<MPBlock> mpb;
+    int64_t nmp = 0, tiled = 0;
+    int max_chain_tiles = 0, max_chain_mp = 0;
+};
+
+// Pack whole characters, in order, into tiles of at most `cap` joints; the
+// characters that do not fit go to the multipass path.
+Packing pack_tiles(const hs_plan *plan, int cap, int strategy)
 {
     const int64_t C = plan->C;
     const auto &off = plan->h_offsets;
     const auto &par = plan->h_parents;
-    const int cap = shape.tile_cap;
-
+    Packing pk;
     std::vector<TileDesc> tiles;
     std::vector<int64_t> tile_cost;
-    std::vector<MPBlock> mpb;
-    int64_t nmp = 0, tiled = 0;
-    int max_chain_tiles = 0, max_chain_mp = 0;
     std::vector<int32_t> top, chain;
 
     TileDesc cur{};
@@ -224,7 +235,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         if (open && cur.count > 0) {
             tiles.push_back(cur);
             tile_cost.push_back((int64_t)cur.count + 48 * (int64_t)cur_chain);
-            max_chain_tiles = std::max(max_chain_tiles, cur_chain);
+            pk.max_chain_tiles = std::max(pk.max_chain_tiles, cur_chain);
         }
         open = false;
         cur_chain = 0;
@@ -236,16 +247,16 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
             flush();
             if (n == 0) continue;
             const int L = block_chain_length(par.data() + off[c], n, 0, top, chain);
-            max_chain_mp = std::max(max_chain_mp, L);
+            pk.max_chain_mp = std::max(pk.max_chain_mp, L);
             for (int64_t k = 0; k < n; k += 64) {
                 MPBlock b{};
                 b.gbegin = off[c] + k;
-                b.cbegin = nmp + k;
+                b.cbegin = pk.nmp + k;
                 b.count = (int32_t)std::min<int64_t>(64, n - k);
                 b.chr = (int32_t)c;
-                mpb.push_back(b);
+                pk.mpb.push_back(b);
             }
-            nmp += n;
+            pk.nmp += n;
             continue;
         }
         if (!open) {
@@ -269,7 +280,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         }
         cur.count += (int32_t)n;
         cur.num_chars += 1;
-        tiled += n;
+        pk.tiled += n;
     }
     flush();
 
@@ -279,8 +290,35 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return tile_cost[a] > tile_cost[b]; });
-    std::vector<TileDesc> sorted(tiles.size());
-    for (size_t i = 0; i < order.size(); ++i) sorted[i] = tiles[order[i]];
+    pk.tiles.resize(tiles.size());
+    for (size_t i = 0; i < order.size(); ++i) pk.tiles[i] = tiles[order[i]];
+    return pk;
+}
+
+hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
+{
+    const int cap = shape.tile_cap;
+    Packing pk = pack_tiles(plan, cap, strategy);
+    std::vector<TileDesc> &sorted = pk.tiles;
+    std::vector<MPBlock> &mpb = pk.mpb;
+    const int64_t nmp = pk.nmp, tiled = pk.tiled;
+    const int max_chain_tiles = pk.max_chain_tiles, max_chain_mp = pk.max_chain_mp;
+
+    // the adjoint keeps twice as much per joint in LDS: it gets its own,
+    // smaller tiles when the forward tiles are too large for it
+    (void)hipFree(plan->d_btiles);
+    plan->d_btiles = nullptr;
+    plan->bwd_cap = std::min(cap, hs::kMaxBwdTileJoints);
+    if (plan->bwd_cap < cap) {
+        Packing pb = pack_tiles(plan, plan->bwd_cap, strategy);
+        plan->num_btiles = (int32_t)pb.tiles.size();
+        plan->bwd_untiled = pb.nmp;
+        hipError_t e2 = upload(&plan->d_btiles, pb.tiles);
+        if (e2 != hipSuccess) return fail_hip(e2, "hs_plan_create");
+    } else {
+        plan->num_btiles = (int32_t)sorted.size();
+        plan->bwd_untiled = nmp;
+    }
 
     hipError_t err;
     (void)hipFree(plan->d_tiles);
@@ -643,7 +681,8 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
                     sh.tile_cap);
     }
     sh.waves = o.waves_per_tile > 0 ? o.waves_per_tile : std::min(16, sh.tile_cap / 64);
-    if (sh.waves * 64 > sh.tile_cap) sh.waves = sh.tile_cap / 64;
+    while (sh.waves > 1 && (sh.waves * 64 > sh.tile_cap || (sh.waves & (sh.waves - 1)) != 0))
+        --sh.waves;  // a power of two with at least one block per wave
 
     sh.grid_per_cu = o.grid_tiles;
 
@@ -780,12 +819,22 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
     ba.grad_scale = grad_scale;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_backward: cannot select device");
-    hipError_t err = hs::launch_backward_tiles(tile_launch(plan), pa, ba, stream);
-    if (err == hipErrorNotSupported) return fail(HS_ERR_UNSUPPORTED, "hs_scan_backward: not available");
+    if (plan->bwd_untiled > 0)
+        return fail(HS_ERR_UNSUPPORTED, "hs_scan_backward: %lld joints belong to characters larger than the "
+                    "%d-joint adjoint tile", (long long)plan->bwd_untiled, plan->bwd_cap);
+    hs::TileLaunch tl = tile_launch(plan);
+    if (plan->d_btiles) {
+        tl.tiles = plan->d_btiles;
+        tl.num_tiles = plan->num_btiles;
+        tl.tile_cap = plan->bwd_cap;
+        tl.waves = std::min(tl.waves, plan->bwd_cap / 64);
+        tl.grid = plan->shape.grid_per_cu > 0
+                      ? std::min<int32_t>(plan->num_btiles, plan->shape.grid_per_cu * plan->ctx->num_cu)
+                      : plan->num_btiles;
+        tl.grid = std::max(1, tl.grid);
+    }
+    hipError_t err = hs::launch_backward_tiles(tl, pa, ba, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
-    hs_plan *mp = const_cast<hs_plan *>(plan);
-    err = hs::launch_backward_multipass(mp_launch(plan), pa, ba, mp->d_mp_adj, stream);
-    if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (multipass)");
     return HS_OK;
 }
 

@@ -11,6 +11,10 @@ namespace hs {
 // including the per-character table of the fused sampler.
 constexpr int kMaxTileJoints = 3072;
 
+// Largest tile of the adjoint kernel, which keeps both the global transforms
+// and the adjoint accumulators of the tile in LDS (96 bytes per joint).
+constexpr int kMaxBwdTileJoints = 1664;
+
 // A tile: a contiguous range of global joint ids holding whole characters,
 // scanned by one workgroup entirely in LDS.
 struct TileDesc {

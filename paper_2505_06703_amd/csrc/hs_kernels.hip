@@ -378,6 +378,288 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the scan (tiled).
+//
+// For G_j = G_p L_j the adjoint X_j of G_j (rows 0-2, a 3x4 matrix; the
+// constant bottom row carries no gradient) gathers the adjoints of all
+// descendants pulled back through the path products between them:
+//     X_j = D_j + sum over children c of  X_c (.) L_c,
+//     X (.) [R'|t] = [X_A R'^T + X_b t^T | X_b],
+// with D_j the incoming dLoss/dG_j.  The gradient of L_j is then
+// [A_p^T X_A | A_p^T X_b] with A_p the parent's global rotation-scale block.
+//
+// Inside a 64-joint block the subtree sums are built by reverse pointer
+// jumping: in round r every joint a adds its partial adjoint S_r(a), pulled
+// back through the round-r jump product M_r(a) of the forward doubling
+// (the product of the 2^r local transforms ending at a), into its 2^r-th
+// in-block ancestor.  After ceil(log2 depth) rounds S(j) sums all in-block
+// descendants.  Fan-in makes this a scatter, done with LDS float atomics.
+// Blocks run in decreasing order; a block's top joints (parent in an
+// earlier block) push X_c (.) L_c into the parent's LDS accumulator and
+// bump that block's arrival counter, which the earlier block waits for.
+// ---------------------------------------------------------------------------
+
+// o = X (.) L  (36 FMA-class operations)
+__device__ __forceinline__ void adj_pull(const float X[12], const float L[12], float o[12])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const float x0 = X[4 * r], x1 = X[4 * r + 1], x2 = X[4 * r + 2], x3 = X[4 * r + 3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            o[4 * r + c] = fmaf(x0, L[4 * c], fmaf(x1, L[4 * c + 1], fmaf(x2, L[4 * c + 2], x3 * L[4 * c + 3])));
+        o[4 * r + 3] = x3;
+    }
+}
+
+__device__ __forceinline__ void lds_atomic_add12(float4 *dst, const float v[12])
+{
+    float *d = reinterpret_cast<float *>(dst);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) atomicAdd(d + k, v[k]);
+}
+
+// Gradients of joint gid from its total adjoint X and the parent's global
+// rotation-scale block Ap (row-major 3x3).
+__device__ __forceinline__ void write_grads(const BwdArgs &B, int64_t gid, const float X[12], const float Ap[9],
+                                            float4 q, float sx, float sy, float sz)
+{
+    float Rb[9], tb[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+            Rb[3 * i + l] = fmaf(Ap[i], X[l], fmaf(Ap[3 + i], X[4 + l], Ap[6 + i] * X[8 + l]));
+        tb[i] = fmaf(Ap[i], X[3], fmaf(Ap[3 + i], X[7], Ap[6 + i] * X[11]));
+    }
+    const float x = q.x, y = q.y, z = q.z, w = q.w;
+    const float sc[3] = {sx, sy, sz};
+    if (B.grad_scale) {
+        const float R[9] = {1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y),
+                            2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x),
+                            2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)};
+        float *gs = B.grad_scale + 3 * gid;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) gs[l] = fmaf(Rb[l], R[l], fmaf(Rb[3 + l], R[3 + l], Rb[6 + l] * R[6 + l]));
+    }
+    // dLoss/dR = dLoss/dR' diag(s), then through the quaternion polynomial
+    float G[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) G[3 * i + l] = Rb[3 * i + l] * sc[l];
+    const float gx = 2.0f * (y * (G[1] + G[3]) + z * (G[2] + G[6]) + w * (G[7] - G[5])) - 4.0f * x * (G[4] + G[8]);
+    const float gy = 2.0f * (x * (G[1] + G[3]) + w * (G[2] - G[6]) + z * (G[5] + G[7])) - 4.0f * y * (G[0] + G[8]);
+    const float gz = 2.0f * (w * (G[3] - G[1]) + x * (G[2] + G[6]) + y * (G[5] + G[7])) - 4.0f * z * (G[0] + G[4]);
+    const float gw = 2.0f * (z * (G[3] - G[1]) + y * (G[2] - G[6]) + x * (G[7] - G[5]));
+    reinterpret_cast<float4 *>(B.grad_quat)[gid] = make_float4(gx, gy, gz, gw);
+    float *gt = B.grad_trans + 3 * gid;
+    gt[0] = tb[0];
+    gt[1] = tb[1];
+    gt[2] = tb[2];
+}
+
+// LDS: G[cap][3] | adjoint accumulators[cap][3] | flags, expected, received [cap/64] each
+template <int WAVES, bool CKPT>
+__global__ void __launch_bounds__(WAVES * kWave)
+bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
+{
+    extern __shared__ float4 lds[];
+    const int cap = tl.tile_cap;
+    float4 *Gs = lds;
+    float4 *Ds = lds + 3 * cap;
+    int *flags = reinterpret_cast<int *>(lds + 6 * cap);
+    int *expect = flags + cap / kWave;
+    int *recv = expect + cap / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        const int n = td.count;
+        const int nblk = (n + kWave - 1) / kWave;
+        for (int i = threadIdx.x; i < nblk; i += WAVES * kWave) {
+            flags[i] = 0;
+            expect[i] = 0;
+            recv[i] = 0;
+        }
+        for (int i = threadIdx.x; i < 3 * n; i += WAVES * kWave) Ds[i] = zero4;
+        __syncthreads();
+
+        // ---- global transforms of the tile into Gs --------------------------
+        if constexpr (!CKPT) {
+            for (int b = wave; b < nblk; b += WAVES) {
+                const int base = b * kWave;
+                const int jl = base + lane;
+                const bool valid = jl < n;
+                const int64_t gid = td.begin + jl;
+                float m[12];
+                int a = -1, e = -1;
+                if (valid) {
+                    const int p = tl.parent[gid];
+                    const int pl = p < 0 ? -1 : (int)(p - td.begin);
+                    if (pl >= base) a = pl - base; else e = pl;
+                    if (pl >= 0 && pl < base) atomicAdd(expect + pl / kWave, 1);
+                    load_local<false>(pose, gid, 0, 0, m);
+                } else {
+                    aff_identity(m);
+                }
+                wave_inblock_scan(m, a, e, lane);
+                const bool need = valid && e >= 0;
+                const int fb = need ? (e / kWave) : 0;
+                for (int spin = 0; spin < kSpinLimit; ++spin) {
+                    const int ok = need ? __hip_atomic_load(flags + fb, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP)
+                                        : 1;
+                    if (__all(ok)) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (need) {
+                    float g[12];
+                    aff_load(Gs + 3 * e, g);
+                    aff_mul_left(g, m);
+                }
+                if (valid) aff_store(Gs + 3 * jl, m);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (lane == 0)
+                    __hip_atomic_store(flags + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        } else {
+            // Checkpoint mode: local transforms first (Gs as scratch) ...
+            for (int jl = threadIdx.x; jl < n; jl += WAVES * kWave) {
+                const int64_t gid = td.begin + jl;
+                const int p = tl.parent[gid];
+                const int pl = p < 0 ? -1 : (int)(p - td.begin);
+                if (pl >= 0 && pl / kWave != jl / kWave) atomicAdd(expect + pl / kWave, 1);
+                float m[12];
+                load_local<false>(pose, gid, 0, 0, m);
+                aff_store(Gs + 3 * jl, m);
+            }
+            __syncthreads();
+            // ... then each joint multiplies the local transforms up to its
+            // nearest checkpointed ancestor (at most ckpt_k - 1 of them) and
+            // that ancestor's stored transform; results staged in Ds.
+            for (int jl = threadIdx.x; jl < n; jl += WAVES * kWave) {
+                const int64_t gid = td.begin + jl;
+                float m[12];
+                if (bwd.level[gid] % bwd.ckpt_k == 0) {
+                    aff_load(reinterpret_cast<const float4 *>(bwd.ckpt) + 3 * gid, m);
+                } else {
+                    aff_load(Gs + 3 * jl, m);
+                    int p = tl.parent[gid];
+                    while (p >= 0) {
+                        float g[12];
+                        if (bwd.level[p] % bwd.ckpt_k == 0) {
+                            aff_load(reinterpret_cast<const float4 *>(bwd.ckpt) + 3 * (int64_t)p, g);
+                            aff_mul_left(g, m);
+                            break;
+                        }
+                        aff_load(Gs + 3 * (int)(p - td.begin), g);
+                        aff_mul_left(g, m);
+                        p = tl.parent[p];
+                    }
+                }
+                aff_store(Ds + 3 * jl, m);
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < 3 * n; i += WAVES * kWave) {
+                Gs[i] = Ds[i];
+                Ds[i] = zero4;
+            }
+        }
+        __syncthreads();
+
+        // ---- reverse sweep over the blocks ------------------------------------
+        for (int idx = wave; idx < nblk; idx += WAVES) {
+            const int b = nblk - 1 - idx;
+            const int base = b * kWave;
+            const int jl = base + lane;
+            const bool valid = jl < n;
+            const int64_t gid = td.begin + jl;
+            const int want = expect[b];
+            for (int spin = 0; spin < kSpinLimit; ++spin) {
+                const int got = __hip_atomic_load(recv + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (__all(got >= want)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+            float L[12], M[12], S[12];
+            float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+            int pl = -1, a = -1;
+            if (valid) {
+                const int p = tl.parent[gid];
+                pl = p < 0 ? -1 : (int)(p - td.begin);
+                if (pl >= base) a = pl - base;
+                q = reinterpret_cast<const float4 *>(pose.quat)[gid];
+                const float *t = pose.trans + 3 * gid;
+                if (pose.scale) {
+                    const float *sp = pose.scale + 3 * gid;
+                    sx = sp[0]; sy = sp[1]; sz = sp[2];
+                }
+                aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, L);
+                const float4 *gg = reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid;
+                float d[12], acc[12];
+                aff_load(gg, d);
+                aff_load(Ds + 3 * jl, acc);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) S[k] = d[k] + acc[k];
+                aff_store(Ds + 3 * jl, S);
+            } else {
+                aff_identity(L);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) S[k] = 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) M[k] = L[k];
+
+            while (__any(a >= 0)) {
+                const bool act = a >= 0;
+                if (act) {
+                    float c[12];
+                    adj_pull(S, M, c);
+                    lds_atomic_add12(Ds + 3 * (base + a), c);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (valid) aff_load(Ds + 3 * jl, S);
+                const int src = (act ? a : lane) << 2;
+                float ma[12], o[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) ma[k] = lane_read(M[k], src);
+                const int aa = __builtin_amdgcn_ds_bpermute(src, a);
+                aff_mul(ma, M, o);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) M[k] = act ? o[k] : M[k];
+                if (act) a = aa;
+            }
+
+            if (valid) {
+                float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+                if (pl >= 0) {
+                    float g[12];
+                    aff_load(Gs + 3 * pl, g);
+                    Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
+                    Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
+                    Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
+                }
+                if (pl >= 0 && pl < base) {
+                    float c[12];
+                    adj_pull(S, L, c);
+                    lds_atomic_add12(Ds + 3 * pl, c);
+                }
+                write_grads(bwd, gid, S, Ap, q, sx, sy, sz);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (valid && pl >= 0 && pl < base) atomicAdd(recv + pl / kWave, 1);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Multipass path.
 // ---------------------------------------------------------------------------
 constexpr int kMPWaves = 4;
@@ -617,12 +899,48 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 
 size_t backward_tile_lds_bytes(int tile_cap)
 {
-    return (size_t)tile_cap * 96 + (size_t)(tile_cap / kWave) * 8;
+    return (size_t)tile_cap * 96 + (size_t)(tile_cap / kWave) * 12;
 }
 
-hipError_t launch_backward_tiles(const TileLaunch &, const PoseArgs &, const BwdArgs &, hipStream_t)
+template <int WAVES, bool CKPT>
+hipError_t launch_bwd_tiles_t(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
+                              hipStream_t stream)
 {
-    return hipErrorNotSupported;
+    const size_t lds = backward_tile_lds_bytes(tl.tile_cap);
+    auto kern = bwd_tile_kernel<WAVES, CKPT>;
+    static bool lds_attr_set = false;
+    if (!lds_attr_set) {
+        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)backward_tile_lds_bytes(kMaxBwdTileJoints));
+        if (err != hipSuccess) return err;
+        lds_attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, bwd);
+    return hipGetLastError();
+}
+
+template <bool CKPT>
+hipError_t launch_bwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
+                              hipStream_t stream)
+{
+    switch (tl.waves) {
+    case 1: return launch_bwd_tiles_t<1, CKPT>(tl, pose, bwd, stream);
+    case 2: return launch_bwd_tiles_t<2, CKPT>(tl, pose, bwd, stream);
+    case 4: return launch_bwd_tiles_t<4, CKPT>(tl, pose, bwd, stream);
+    case 8: return launch_bwd_tiles_t<8, CKPT>(tl, pose, bwd, stream);
+    case 16: return launch_bwd_tiles_t<16, CKPT>(tl, pose, bwd, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
+                                 hipStream_t stream)
+{
+    if (tl.num_tiles == 0) return hipSuccess;
+    if (tl.tile_cap > kMaxBwdTileJoints) return hipErrorInvalidValue;
+    return bwd.ckpt ? launch_bwd_tiles_w<true>(tl, pose, bwd, stream)
+                    : launch_bwd_tiles_w<false>(tl, pose, bwd, stream);
 }
 
 hipError_t launch_backward_multipass(const MPLaunch &, const PoseArgs &, const BwdArgs &,

@@ -1,0 +1,156 @@
+"""GPU parity of the adjoint kernel (hs_scan_backward) and of the autograd
+wrapper against the FP64 oracle's reverse-mode gradients.
+
+Tolerance: per character, max |grad_gpu - grad_fp64| <= 1e-4 * max(1, max
+|grad_fp64|) for each of the quaternion, translation and scale gradients.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2505_06703_amd import hs
+from paper_2505_06703_amd import workloads as wl
+from paper_2505_06703_amd.autograd import hierarchy_scan
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL = 1e-4
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def check_grads(offsets, got, ref, what):
+    for name, g, r in zip(("quat", "trans", "scale"), got, ref):
+        if g is None:
+            continue
+        g = np.asarray(g, np.float64)
+        for c in range(offsets.size - 1):
+            sl = slice(offsets[c], offsets[c + 1])
+            if sl.start == sl.stop:
+                continue
+            scale = max(1.0, float(np.abs(r[sl]).max()))
+            err = float(np.abs(g[sl] - r[sl]).max())
+            assert err <= TOL * scale, f"{what}: {name} grad of character {c}: {err:.3e} > {TOL * scale:.3e}"
+
+
+def effector_grad(batch, G_ref):
+    """dLoss/dG for the sum over end effectors of |b_e - y_e|^2, targets at
+    the rest-pose positions plus seeded offsets within 0.5 units."""
+    Grest = oracle.forward(batch.offsets, batch.parents, batch.rest_quat, batch.rest_trans, batch.rest_scale)
+    eff = batch.extra["effectors"]
+    y = Grest[eff, :3, 3] + batch.extra["target_offsets"]
+    W = np.zeros((batch.num_joints, 4, 4))
+    W[eff, :3, 3] = 2.0 * (G_ref[eff, :3, 3] - y)
+    return W.astype(np.float32)
+
+
+def run(batch, W, ckpt_k=0, want_scale=True, **plan_kw):
+    plan = hs.Plan(batch.offsets, batch.parents, **plan_kw)
+    q, t, s = dev(batch.quat), dev(batch.trans), dev(batch.scale)
+    ckpt = None
+    if ckpt_k:
+        ckpt = torch.empty((batch.num_joints, 12), device=DEV)
+        hs.hs_scan_forward(plan, q, t, s, ckpt_out=ckpt, ckpt_k=ckpt_k)
+    gq, gt, gs = hs.hs_scan_backward(plan, q, t, s, dev(W), ckpt=ckpt, ckpt_k=ckpt_k, want_scale=want_scale)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() if x is not None else None for x in (gq, gt, gs)]
+
+
+def oracle_grads(batch, W):
+    return oracle.backward(batch.offsets, batch.parents, batch.quat, batch.trans, batch.scale, W)
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4), dict(tile_joints=512)])
+def test_differentiable_effector_loss(shape):
+    b = wl.differentiable(num_characters=12)
+    G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+    W = effector_grad(b, G)
+    check_grads(b.offsets, run(b, W, **shape), oracle_grads(b, W), f"differentiable {shape}")
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+def test_level_checkpoint_mode(k):
+    b = wl.differentiable(num_characters=6)
+    G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+    W = effector_grad(b, G)
+    check_grads(b.offsets, run(b, W, ckpt_k=k), oracle_grads(b, W), f"ckpt k={k}")
+
+
+def test_dense_random_gradient_with_scale_and_forests():
+    rng = np.random.default_rng(5)
+    b = wl.heterogeneous(num_characters=40, hi=1500, chain_fraction=0.05)
+    b.scale = rng.uniform(0.8, 1.25, b.scale.shape).astype(np.float32)
+    W = rng.standard_normal((b.num_joints, 4, 4)).astype(np.float32)
+    check_grads(b.offsets, run(b, W), oracle_grads(b, W), "dense random")
+    check_grads(b.offsets, run(b, W, ckpt_k=5), oracle_grads(b, W), "dense random ckpt")
+
+
+def test_plain_scan_trees_and_star():
+    rng = np.random.default_rng(6)
+    star = np.zeros(700, np.int32)
+    star[0] = -1
+    b0 = wl.plain_scan(num_characters=8)
+    par = np.concatenate([b0.parents, star, np.zeros(0, np.int32), np.array([-1, -1, 1], np.int32)])
+    off = np.concatenate([b0.offsets, [b0.offsets[-1] + 700, b0.offsets[-1] + 700, b0.offsets[-1] + 703]])
+    q, t, s = wl.random_pose(rng, par.size)
+    b = wl.Batch("mix", off.astype(np.int64), par, q, t, s, q, t, s)
+    W = rng.standard_normal((par.size, 4, 4)).astype(np.float32)
+    check_grads(b.offsets, run(b, W), oracle_grads(b, W), "trees+star")
+    got = run(b, W, want_scale=False)
+    assert got[2] is None
+
+
+@pytest.mark.parametrize("n", [1, 64, 65, 1000, 1664])
+def test_chains(n):
+    rng = np.random.default_rng(n)
+    par = np.arange(-1, n - 1, dtype=np.int32)
+    q, t, s = wl.random_pose(rng, n, max_angle=0.1)
+    b = wl.Batch("chain", np.array([0, n], np.int64), par, q, t, s, q, t, s)
+    W = np.zeros((n, 4, 4), np.float32)
+    W[-1, :3, 3] = rng.standard_normal(3)
+    W[n // 2, :3, :3] = rng.standard_normal((3, 3))
+    check_grads(b.offsets, run(b, W), oracle_grads(b, W), f"chain {n}")
+
+
+def test_large_forward_tiles_use_smaller_adjoint_tiles():
+    b = wl.heterogeneous(num_characters=30, lo=1200, hi=1600)
+    rng = np.random.default_rng(8)
+    W = rng.standard_normal((b.num_joints, 4, 4)).astype(np.float32)
+    check_grads(b.offsets, run(b, W, tile_joints=3072), oracle_grads(b, W), "3072-joint forward tiles")
+
+
+def test_characters_beyond_adjoint_tile_are_rejected():
+    n = 3000
+    par = np.arange(-1, n - 1, dtype=np.int32)
+    rng = np.random.default_rng(1)
+    q, t, s = wl.random_pose(rng, n)
+    b = wl.Batch("chain", np.array([0, n], np.int64), par, q, t, s, q, t, s)
+    with pytest.raises(hs.HSError) as ei:
+        run(b, np.zeros((n, 4, 4), np.float32))
+    assert ei.value.status == hs.HS_ERR_UNSUPPORTED
+
+
+def test_autograd_matches_oracle_in_both_modes():
+    b = wl.differentiable(num_characters=4)
+    G64 = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+    Grest = oracle.forward(b.offsets, b.parents, b.rest_quat, b.rest_trans, b.rest_scale)
+    eff = b.extra["effectors"]
+    y = dev((Grest[eff, :3, 3] + b.extra["target_offsets"]).astype(np.float32))
+    plan = hs.Plan(b.offsets, b.parents)
+    for k in (0, 4):
+        q = dev(b.quat).requires_grad_(True)
+        t = dev(b.trans).requires_grad_(True)
+        G = hierarchy_scan(plan, q, t, None, ckpt_k=k)
+        loss = ((G[torch.as_tensor(eff, device=DEV), :3, 3] - y) ** 2).sum()
+        loss.backward()
+        # the oracle's gradient at the GPU's own effector positions
+        W = np.zeros((b.num_joints, 4, 4))
+        Gg = G.detach().cpu().numpy().astype(np.float64)
+        W[eff, :3, 3] = 2.0 * (Gg[eff, :3, 3] - y.cpu().numpy())
+        ref = oracle.backward(b.offsets, b.parents, b.quat, b.trans, None, W)
+        check_grads(b.offsets, [q.grad.cpu().numpy(), t.grad.cpu().numpy(), None], ref, f"autograd k={k}")
+        np.testing.assert_allclose(Gg[eff, :3, 3], G64[eff, :3, 3], atol=1e-4 * 30)
