@@ -106,7 +106,10 @@ typedef struct hs_plan_opts {
                                looping over the cost-sorted tiles */
     int32_t autotune;       /* non-zero: time candidate launch shapes on the device when the
                                plan is created (result cached in the context) */
-    int32_t reserved[3];    /* must be zero */
+    int32_t chain_units;    /* non-zero: scan runs of up to four 64-joint blocks that consist of
+                               whole chain segments with four joints per lane (a sequential
+                               product per lane and a segmented scan across the wave) */
+    int32_t reserved[2];    /* must be zero */
 } hs_plan_opts;
 
 typedef struct hs_plan_info {
@@ -205,6 +208,23 @@ hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *gl
  * for n joints. */
 hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,
                   hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * HIP graphs: one frame's forward pass captured once, replayed per frame.
+ * ------------------------------------------------------------------------ */
+
+/* Capture one hs_scan_forward call, with exactly these arguments, into an
+ * instantiated HIP graph (on a private stream of the plan's device).  The
+ * pointers are baked into the graph: every replay reads the current contents
+ * of the same input arrays and rewrites the same outputs.  The plan and the
+ * arrays must outlive the graph.  Argument errors are those of
+ * hs_scan_forward; capture or instantiation failures return HS_ERR_DEVICE. */
+hs_status hs_graph_create_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out,
+                                  const float *inv_bind, float *skin_out, hs_graph **out);
+
+/* Replay the captured work on `stream` (asynchronous, no allocation). */
+hs_status hs_graph_launch(hs_graph *graph, hipStream_t stream);
+void hs_graph_destroy(hs_graph *graph);
 
 /* ------------------------------------------------------------------------
  * Adjoint of the Hierarchy-Scan.

@@ -110,6 +110,7 @@ struct Shape {
     int tile_cap = 0;
     int waves = 0;
     int grid_per_cu = 0;  // 0 = one workgroup per tile
+    bool chain_units = false;
 };
 
 } // namespace
@@ -128,6 +129,7 @@ struct hs_plan {
     int64_t C = 0, N = 0;
     std::vector<int64_t> h_offsets;
     std::vector<int32_t> h_parents;  // character-local
+    std::vector<int32_t> h_gparent;  // global parent id or -1
     hs_plan_info info{};
     Shape shape;
     // device tables
@@ -141,6 +143,7 @@ struct hs_plan {
     int32_t num_btiles = 0;
     int32_t bwd_cap = 0;
     int64_t bwd_untiled = 0;  // joints the adjoint's tiles do not cover
+    int32_t max_units = 0;
     // multipass
     MPBlock *d_mp_blocks = nullptr;
     int32_t num_mp_blocks = 0;
@@ -209,16 +212,56 @@ int block_chain_length(const int32_t *par, int64_t n, int64_t align0, std::vecto
     return best;
 }
 
+// Mark the chain units of a tile: runs of up to 4 blocks (at least 2) in
+// which every joint's parent is the previous joint or lies before the run,
+// and whose longest chain segment has at least 16 joints (below that the
+// per-block doubling needs no more than 4 rounds and is cheaper).
+int mark_chain_units(const std::vector<int32_t> &gparent, TileDesc &t)
+{
+    int units = 0;
+    const int n = t.count;
+    const int nblk = (n + 63) / 64;
+    uint64_t mask = 0;
+    for (int b = 0; b < nblk;) {
+        const int e = std::min(b + 4, nblk);
+        bool ok = e - b >= 2;
+        int longest = 0, seg = 0;
+        for (int j = 64 * b; ok && j < std::min(64 * e, n); ++j) {
+            const int32_t pg = gparent[t.begin + j];
+            const int64_t p = pg < 0 ? -1 : (int64_t)pg - t.begin;
+            if (p == j - 1 && p >= 64 * b) {
+                ++seg;
+            } else if (p < 64 * b) {
+                seg = 1;
+            } else {
+                ok = false;
+            }
+            longest = std::max(longest, seg);
+        }
+        if (ok && longest >= 16) {
+            mask |= uint64_t(1) << b;
+            b = e;
+        } else {
+            ++b;
+        }
+        ++units;
+    }
+    t.chain_lo = (int32_t)(uint32_t)(mask & 0xffffffffu);
+    t.chain_hi = (int32_t)(uint32_t)(mask >> 32);
+    return units;
+}
+
 struct Packing {
     std::vector<TileDesc> tiles;  // sorted, heaviest first
     std::vector<MPBlock> mpb;
     int64_t nmp = 0, tiled = 0;
     int max_chain_tiles = 0, max_chain_mp = 0;
+    int max_units = 0;  // most work units (blocks or chain units) in one tile
 };
 
 // Pack whole characters, in order, into tiles of at most `cap` joints; the
 // characters that do not fit go to the multipass path.
-Packing pack_tiles(const hs_plan *plan, int cap, int strategy)
+Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units)
 {
     const int64_t C = plan->C;
     const auto &off = plan->h_offsets;
@@ -292,13 +335,17 @@ Packing pack_tiles(const hs_plan *plan, int cap, int strategy)
                      [&](size_t a, size_t b) { return tile_cost[a] > tile_cost[b]; });
     pk.tiles.resize(tiles.size());
     for (size_t i = 0; i < order.size(); ++i) pk.tiles[i] = tiles[order[i]];
+    for (TileDesc &t : pk.tiles) {
+        const int units = chain_units ? mark_chain_units(plan->h_gparent, t) : (t.count + 63) / 64;
+        pk.max_units = std::max(pk.max_units, units);
+    }
     return pk;
 }
 
 hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
 {
     const int cap = shape.tile_cap;
-    Packing pk = pack_tiles(plan, cap, strategy);
+    Packing pk = pack_tiles(plan, cap, strategy, shape.chain_units);
     std::vector<TileDesc> &sorted = pk.tiles;
     std::vector<MPBlock> &mpb = pk.mpb;
     const int64_t nmp = pk.nmp, tiled = pk.tiled;
@@ -310,7 +357,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     plan->d_btiles = nullptr;
     plan->bwd_cap = std::min(cap, hs::kMaxBwdTileJoints);
     if (plan->bwd_cap < cap) {
-        Packing pb = pack_tiles(plan, plan->bwd_cap, strategy);
+        Packing pb = pack_tiles(plan, plan->bwd_cap, strategy, false);
         plan->num_btiles = (int32_t)pb.tiles.size();
         plan->bwd_untiled = pb.nmp;
         hipError_t e2 = upload(&plan->d_btiles, pb.tiles);
@@ -341,6 +388,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
                 return fail_hip(err, "hs_plan_create (multipass workspace)");
         }
     }
+    plan->max_units = pk.max_units;
     plan->num_mp_blocks = (int32_t)mpb.size();
     plan->nmp = nmp;
     plan->mp_rounds = ceil_log2(std::max(1, max_chain_mp));
@@ -369,6 +417,7 @@ hs::TileLaunch tile_launch(const hs_plan *p)
     tl.waves = p->shape.waves;
     tl.grid = std::max(1, p->info.grid);
     tl.parent = p->d_parent;
+    tl.chain_units = p->shape.chain_units ? 1 : 0;
     return tl;
 }
 
@@ -485,7 +534,8 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
         for (int w : {1, 2, 4, 8, 16}) {
             if (w * 64 > cap) continue;
             if (cap / (w * 64) > 4) continue;  // at most 4 blocks per wave
-            for (int g : {0, 2, 4}) cands.push_back(Shape{cap, w, g});
+            for (int g : {0, 2, 4})
+                for (bool cu : {false, true}) cands.push_back(Shape{cap, w, g, cu});
         }
     }
     if (cands.empty()) return build_tables(plan, base, strategy);
@@ -571,6 +621,14 @@ hs_status hs_context_create(int device, hs_context **out)
     if (arch.rfind("gfx950", 0) != 0)
         return fail(HS_ERR_UNSUPPORTED, "hs_context_create: device %d is %s; this library targets gfx950",
                     device, arch.c_str());
+    {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        if ((err = hipSetDevice(device)) != hipSuccess) return fail_hip(err, "hs_context_create");
+        err = hs::prepare_kernels();
+        if (prev >= 0) (void)hipSetDevice(prev);
+        if (err != hipSuccess) return fail_hip(err, "hs_context_create (kernel attributes)");
+    }
     hs_context *ctx = new hs_context();
     ctx->device = device;
     ctx->num_cu = prop.multiProcessorCount;
@@ -650,6 +708,7 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
         free_plan(plan);
         return fail(HS_ERR_INVALID_ARG, "joint_offsets[C] = %lld but num_joints = %lld", (long long)off[C], (long long)N);
     }
+    plan->h_gparent = gparent;
     plan->info.num_characters = C;
     plan->info.num_joints = N;
     plan->info.max_depth = max_depth;
@@ -685,8 +744,18 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
         --sh.waves;  // a power of two with at least one block per wave
 
     sh.grid_per_cu = o.grid_tiles;
+    sh.chain_units = o.chain_units != 0;
 
     hs_status rc = build_tables(plan, sh, o.strategy);
+    if (rc == HS_OK && o.waves_per_tile == 0 && plan->max_units > 0) {
+        // no more waves than work units in the largest tile
+        int w = 1;
+        while (w * 2 <= std::min(16, plan->max_units)) w *= 2;
+        if (w != sh.waves) {
+            sh.waves = w;
+            rc = build_tables(plan, sh, o.strategy);
+        }
+    }
     if (rc == HS_OK && o.autotune && N > 0) rc = autotune(plan, sh, o.strategy);
     if (rc != HS_OK) {
         free_plan(plan);
@@ -703,6 +772,65 @@ hs_status hs_plan_get_info(const hs_plan *plan, hs_plan_info *out)
     if (!plan || !out) return fail(HS_ERR_INVALID_ARG, "hs_plan_get_info: NULL argument");
     *out = plan->info;
     return HS_OK;
+}
+
+struct hs_graph {
+    int device = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" hs_status hs_graph_create_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out,
+                                             const float *inv_bind, float *skin_out, hs_graph **out)
+{
+    if (!out) return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward: out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward: plan is NULL");
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_graph_create_forward: cannot select device");
+    hipStream_t s = nullptr;
+    hipError_t err = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (err != hipSuccess) return fail_hip(err, "hs_graph_create_forward (stream)");
+    hs_graph *g = new hs_graph();
+    g->device = plan->ctx->device;
+    err = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        delete g;
+        return fail_hip(err, "hs_graph_create_forward (begin capture)");
+    }
+    hs_status rc = hs_scan_forward(plan, src, global_out, inv_bind, skin_out, nullptr, 0, 0, s);
+    err = hipStreamEndCapture(s, &g->graph);
+    if (rc == HS_OK && err != hipSuccess) rc = fail_hip(err, "hs_graph_create_forward (end capture)");
+    if (rc == HS_OK) {
+        err = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (err != hipSuccess) rc = fail_hip(err, "hs_graph_create_forward (instantiate)");
+    }
+    (void)hipStreamDestroy(s);
+    if (rc != HS_OK) {
+        hs_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return HS_OK;
+}
+
+extern "C" hs_status hs_graph_launch(hs_graph *graph, hipStream_t stream)
+{
+    if (!graph || !graph->exec) return fail(HS_ERR_INVALID_ARG, "hs_graph_launch: graph is NULL");
+    DeviceGuard dg(graph->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_graph_launch: cannot select device");
+    hipError_t err = hipGraphLaunch(graph->exec, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_graph_launch");
+    return HS_OK;
+}
+
+extern "C" void hs_graph_destroy(hs_graph *graph)
+{
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
 }
 
 hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out, const float *inv_bind,

@@ -22,7 +22,11 @@ struct TileDesc {
     int32_t count;      // joints in the tile (<= tile capacity)
     int32_t first_char; // index of the tile's first character
     int32_t num_chars;  // characters in the tile (empty ones included)
-    int32_t pad[3];
+    // bit b of (chain_hi:chain_lo) set: a chain unit of up to 4 blocks starts
+    // at block b (every parent in it is the previous joint or before it)
+    int32_t chain_lo;
+    int32_t chain_hi;
+    int32_t pad;
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
 
@@ -70,6 +74,7 @@ struct TileLaunch {
     int32_t waves;      // 1..16
     int32_t grid;       // workgroups
     const int32_t *parent; // [N] global parent id or -1
+    int32_t chain_units;   // tiles carry chain-unit marks
 };
 
 struct MPLaunch {
@@ -106,6 +111,10 @@ hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const Po
                               float *quat_out, float *trans_out, hipStream_t stream);
 hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,
                        hipStream_t stream);
+
+// Raise the dynamic-LDS limit of every tile kernel to what its largest tile
+// needs (once per process and device, before any launch or capture).
+hipError_t prepare_kernels();
 
 // LDS bytes one tiled-forward workgroup needs.
 size_t forward_tile_lds_bytes(int tile_cap, bool sample);

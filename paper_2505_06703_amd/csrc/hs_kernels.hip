@@ -224,26 +224,25 @@ __device__ __forceinline__ void load_local(const PoseArgs &P, int64_t gid, int c
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_inblock_scan(float m[12], int &a, int &e, int lane)
 {
-    // a (-1..63) and e (-1..2^23) travel packed in one 32-bit permute
-    int code = ((e + 1) << 7) | (a + 1);
-    while (__any(a >= 0)) {
+    // Six rounds at most: a path inside one 64-joint block has at most 64
+    // joints.  The rounds are unrolled so that no value is carried through a
+    // loop back-edge (which would cost a register copy per round); the
+    // update is a per-lane select rather than a branch.
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        if (!__any(a >= 0)) break;
         const bool act = a >= 0;
         const int src = (act ? a : lane) << 2;
         float ma[12], o[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) ma[k] = lane_read(m[k], src);
-        const int ca = __builtin_amdgcn_ds_bpermute(src, code);
+        const int aa = __builtin_amdgcn_ds_bpermute(src, a);
+        const int ea = __builtin_amdgcn_ds_bpermute(src, e);
         aff_mul(ma, m, o);
-        // branch-free update keeps the loop free of register copies
 #pragma unroll
         for (int k = 0; k < 12; ++k) m[k] = act ? o[k] : m[k];
-        const int aa = (ca & 127) - 1;
-        const int ea = (ca >> 7) - 1;
-        if (act) {
-            if (aa < 0) e = ea;
-            a = aa;
-            code = ((e + 1) << 7) | (a + 1);
-        }
+        e = (act && aa < 0) ? ea : e;
+        a = act ? aa : a;
     }
 }
 
@@ -282,7 +281,216 @@ __device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t 
 // Tiled forward kernel.
 // LDS: G[cap][3] float4 | block flags [cap/64] int | (SAMPLE) char starts [cap+1]
 // ---------------------------------------------------------------------------
-template <int WAVES, bool SAMPLE>
+// Bounded wait until the block of tile-local joint e (if e >= 0) has
+// published its final transforms.  The bound only guards against a broken
+// invariant: after kSpinLimit polls (far beyond any legitimate wait) the
+// caller proceeds with whatever the LDS holds instead of hanging the device.
+__device__ __forceinline__ void wait_block_of(const int *flags, int e)
+{
+    const bool need = e >= 0;
+    const int fb = need ? (e / kWave) : 0;
+    for (int spin = 0; spin < kSpinLimit; ++spin) {
+        const int ok = need ? __hip_atomic_load(flags + fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 1;
+        if (__all(ok)) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Publish blocks [b0, b0 + nb) of the tile: their final transforms are in LDS.
+__device__ __forceinline__ void publish_blocks(int *flags, int b0, int nb, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane < nb) __hip_atomic_store(flags + b0 + lane, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Global matrices of tile-local joints [base, base + 64 * nb) leave as 16-byte
+// rows, 4 per joint; each store instruction covers 1 KiB of contiguous output.
+__device__ __forceinline__ void store_rows(const OutArgs &out, const float4 *Gs, int64_t tile_begin, int base,
+                                           int nb, int n, int lane)
+{
+    const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * (tile_begin + base);
+    for (int k = 0; k < 4 * nb; ++k) {
+        const int c = lane + kWave * k;
+        const int jj = base + (c >> 2);
+        const int r = c & 3;
+        if (jj < n) {
+            float4 v = Gs[3 * jj + (r == 3 ? 0 : r)];
+            if (r == 3) v = bottom;
+            dst[c] = v;
+        }
+    }
+}
+
+template <bool SAMPLE>
+__device__ __forceinline__ void char_of(const TileDesc &td, const int *cstart, int jl, int &chr, int &lj)
+{
+    chr = 0;
+    lj = 0;
+    if constexpr (SAMPLE) {
+        const int c = tile_char_of(cstart, td.num_chars, jl);
+        chr = td.first_char + c;
+        lj = jl - cstart[c];
+    }
+}
+
+// One 64-joint block: in-block pointer jumping across the wave, then one
+// composition with the final transform of the nearest out-of-block
+// ancestor once its block has published it.
+template <bool SAMPLE>
+__device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                          const TileDesc &td, int n, int b, float4 *Gs, int *flags,
+                                          const int *cstart, int lane)
+{
+    const int base = b * kWave;
+    const int jl = base + lane;
+    const bool valid = jl < n;
+    const int64_t gid = td.begin + jl;
+    float m[12];
+    int a = -1, e = -1;
+    if (valid) {
+        const int p = tl.parent[gid];
+        const int pl = p < 0 ? -1 : (int)(p - td.begin);
+        if (pl >= base) a = pl - base; else e = pl;
+        int chr, lj;
+        char_of<SAMPLE>(td, cstart, jl, chr, lj);
+        load_local<SAMPLE>(pose, gid, chr, lj, m);
+    } else {
+        aff_identity(m);
+    }
+    wave_inblock_scan(m, a, e, lane);
+    wait_block_of(flags, valid ? e : -1);
+    if (valid && e >= 0) {
+        float g[12];
+        aff_load(Gs + 3 * e, g);
+        aff_mul_left(g, m);
+    }
+    if (valid) aff_store(Gs + 3 * jl, m);
+    publish_blocks(flags, b, 1, lane);
+    if (out.global_out) store_rows(out, Gs, td.begin, base, 1, n, lane);
+    if (valid) write_skin_and_ckpt(out, gid, m);
+}
+
+// A chain unit: kChainK * 64 consecutive joints (up to kChainK blocks) in
+// which every joint's parent is either the previous joint or lies before
+// the unit, i.e. the unit is a set of contiguous chain segments.  Lane l
+// owns joints [kChainK l, kChainK l + kChainK) of the unit:
+//   1. sequential products inside the lane (kChainK - 1 compositions);
+//   2. a segmented scan of the lane products across the wave (log2 64
+//      rounds, restarting at segment heads), carrying each segment's
+//      out-of-unit anchor;
+//   3. one composition per joint with the prefix of the previous lanes,
+//      and one with the anchor's final transform.
+// About 4 compositions per joint instead of 6 + 1 for a 64-deep block.
+constexpr int kChainK = 4;
+
+template <bool SAMPLE>
+__device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                               const TileDesc &td, int n, int b0, int nb, float4 *Gs,
+                                               int *flags, const int *cstart, int lane)
+{
+    const int ubase = b0 * kWave;
+    const int j0 = ubase + lane * kChainK;
+    float P[kChainK][12];
+    // anchor of each joint's segment: tile-local id before the unit, -1 for
+    // a root, or kOpen when the segment continues from the previous lane
+    constexpr int kOpen = -2;
+    int anc[kChainK];
+#pragma unroll
+    for (int s = 0; s < kChainK; ++s) {
+        const int jl = j0 + s;
+        const bool valid = jl < n;
+        const int64_t gid = td.begin + jl;
+        float L[12];
+        int p = -1;
+        if (valid) {
+            const int pg = tl.parent[gid];
+            p = pg < 0 ? -1 : (int)(pg - td.begin);
+            int chr, lj;
+            char_of<SAMPLE>(td, cstart, jl, chr, lj);
+            load_local<SAMPLE>(pose, gid, chr, lj, L);
+        } else {
+            aff_identity(L);
+        }
+        const bool cont = valid && p == jl - 1 && p >= ubase;
+        if (s == 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) P[0][k] = L[k];
+            anc[0] = cont ? kOpen : p;
+        } else {
+            float o[12];
+            aff_mul(P[s - 1], L, o);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) P[s][k] = cont ? o[k] : L[k];
+            anc[s] = cont ? anc[s - 1] : p;
+        }
+    }
+
+    // segmented inclusive scan of the lane products; code = head flag |
+    // (anchor + 1) << 1 for the segment open at the end of the lane
+    float T[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) T[k] = P[kChainK - 1][k];
+    int code = anc[kChainK - 1] == kOpen ? 0 : (1 | ((anc[kChainK - 1] + 1) << 1));
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const bool need = !(code & 1) && lane >= d;
+        if (!__any(need)) break;
+        const int src = (lane >= d ? lane - d : lane) << 2;
+        float ta[12], o[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ta[k] = lane_read(T[k], src);
+        const int ca = __builtin_amdgcn_ds_bpermute(src, code);
+        aff_mul(ta, T, o);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) T[k] = need ? o[k] : T[k];
+        code = need ? ca : code;
+    }
+    // prefix of the segment open at the start of the lane: the inclusive
+    // result of the previous lane (lane 0 always starts with a head)
+    const int src = (lane > 0 ? lane - 1 : 0) << 2;
+    float X[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) X[k] = lane_read(T[k], src);
+    const int xa = (__builtin_amdgcn_ds_bpermute(src, code) >> 1) - 1;
+#pragma unroll
+    for (int s = 0; s < kChainK; ++s) {
+        if (anc[s] == kOpen) {
+            aff_mul_left(X, P[s]);
+            anc[s] = xa;
+        }
+    }
+
+    // one composition with each segment anchor's final transform
+#pragma unroll
+    for (int s = 0; s < kChainK; ++s) {
+        const int jl = j0 + s;
+        const bool valid = jl < n;
+        wait_block_of(flags, valid ? anc[s] : -1);
+        if (valid && anc[s] >= 0) {
+            float g[12];
+            aff_load(Gs + 3 * anc[s], g);
+            aff_mul_left(g, P[s]);
+        }
+        if (valid) aff_store(Gs + 3 * jl, P[s]);
+    }
+    publish_blocks(flags, b0, nb, lane);
+    if (out.global_out) store_rows(out, Gs, td.begin, ubase, nb, n, lane);
+#pragma unroll
+    for (int s = 0; s < kChainK; ++s)
+        if (j0 + s < n) write_skin_and_ckpt(out, td.begin + j0 + s, P[s]);
+}
+
+// ---------------------------------------------------------------------------
+// Tiled forward kernel.
+// LDS: G[cap][3] float4 | block flags [cap/64] int | (SAMPLE) char starts [cap+1]
+// The tile is cut into units -- single 64-joint blocks, or chain units of up
+// to kChainK blocks where the plan found contiguous chain segments -- dealt
+// to the waves round-robin; each wave processes its units in increasing
+// order, and a unit only waits on blocks before it, so the waits drain.
+// ---------------------------------------------------------------------------
+template <int WAVES, bool SAMPLE, bool CHAIN>
 __global__ void __launch_bounds__(WAVES * kWave)
 fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 {
@@ -293,12 +501,12 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
     int *cstart = flags + (cap >> 6);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
 
     for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
         const TileDesc td = tl.tiles[tile];
         const int n = td.count;
         const int nblk = (n + kWave - 1) / kWave;
+        const uint64_t chain_starts = ((uint64_t)(uint32_t)td.chain_hi << 32) | (uint32_t)td.chain_lo;
         for (int i = threadIdx.x; i < nblk; i += WAVES * kWave) flags[i] = 0;
         if constexpr (SAMPLE) {
             for (int i = threadIdx.x; i <= td.num_chars; i += WAVES * kWave)
@@ -306,72 +514,20 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
         }
         __syncthreads();
 
-        for (int b = wave; b < nblk; b += WAVES) {
-            const int base = b * kWave;
-            const int jl = base + lane;
-            const bool valid = jl < n;
-            const int64_t gid = td.begin + jl;
-            float m[12];
-            int a = -1, e = -1;
-            if (valid) {
-                const int p = tl.parent[gid];
-                const int pl = p < 0 ? -1 : (int)(p - td.begin);
-                if (pl >= base) a = pl - base; else e = pl;
-                int chr = 0, lj = 0;
-                if constexpr (SAMPLE) {
-                    const int c = tile_char_of(cstart, td.num_chars, jl);
-                    chr = td.first_char + c;
-                    lj = jl - cstart[c];
-                }
-                load_local<SAMPLE>(pose, gid, chr, lj, m);
-            } else {
-                aff_identity(m);
+        int unit = 0;
+        for (int b = 0; b < nblk; ++unit) {
+            const bool chain = CHAIN && ((chain_starts >> b) & 1);
+            const int nb = chain ? min(kChainK, nblk - b) : 1;
+            if (unit % WAVES == wave) {
+                if constexpr (CHAIN) {
+                    if (chain)
+                        fwd_chain_unit<SAMPLE>(tl, pose, out, td, n, b, nb, Gs, flags, cstart, lane);
+                    else
+                        fwd_block<SAMPLE>(tl, pose, out, td, n, b, Gs, flags, cstart, lane);
+                } else
+                    fwd_block<SAMPLE>(tl, pose, out, td, n, b, Gs, flags, cstart, lane);
             }
-
-            wave_inblock_scan(m, a, e, lane);
-
-            // Phase 2: one composition with the final transform of the
-            // out-of-block ancestor, once its block has published it.
-            // The wait is bounded so that a broken invariant can never hang
-            // the device: after kSpinLimit polls (far beyond any legitimate
-            // wait) the block proceeds with whatever the LDS holds.
-            const bool need = valid && e >= 0;
-            const int fb = need ? (e / kWave) : 0;
-            for (int spin = 0; spin < kSpinLimit; ++spin) {
-                const int ok = need ? __hip_atomic_load(flags + fb, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_WORKGROUP)
-                                    : 1;
-                if (__all(ok)) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if (need) {
-                float g[12];
-                aff_load(Gs + 3 * e, g);
-                aff_mul_left(g, m);
-            }
-            if (valid) aff_store(Gs + 3 * jl, m);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane == 0)
-                __hip_atomic_store(flags + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-
-            if (out.global_out) {
-                // 64 joints x 4 rows = 256 16-byte rows, 4 per lane, each
-                // store instruction covering 1 KiB of contiguous output.
-                float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * (td.begin + base);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = lane + kWave * k;
-                    const int jj = base + (c >> 2);
-                    const int r = c & 3;
-                    if (jj < n) {
-                        float4 v = Gs[3 * jj + (r == 3 ? 0 : r)];
-                        if (r == 3) v = bottom;
-                        dst[c] = v;
-                    }
-                }
-            }
-            if (valid) write_skin_and_ckpt(out, gid, m);
+            b += nb;
         }
         __syncthreads();
     }
@@ -795,39 +951,63 @@ skin_kernel(int64_t n, const float4 *G, const float4 *B, float4 *S)
     }
 }
 
-template <int WAVES, bool SAMPLE>
+template <int WAVES, bool SAMPLE, bool CHAIN>
 hipError_t launch_fwd_tiles_t(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                               hipStream_t stream)
 {
     const size_t lds = forward_tile_lds_bytes(tl.tile_cap, SAMPLE);
-    auto kern = fwd_tile_kernel<WAVES, SAMPLE>;
-    static bool lds_attr_set = false;  // the largest tile's LDS, set once per kernel
-    if (!lds_attr_set) {
-        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)forward_tile_lds_bytes(kMaxTileJoints, true));
-        if (err != hipSuccess) return err;
-        lds_attr_set = true;
-    }
+    auto kern = fwd_tile_kernel<WAVES, SAMPLE, CHAIN>;
     hipLaunchKernelGGL(kern, dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, out);
     return hipGetLastError();
 }
 
-template <bool SAMPLE>
+template <bool SAMPLE, bool CHAIN>
 hipError_t launch_fwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                               hipStream_t stream)
 {
     switch (tl.waves) {
-    case 1: return launch_fwd_tiles_t<1, SAMPLE>(tl, pose, out, stream);
-    case 2: return launch_fwd_tiles_t<2, SAMPLE>(tl, pose, out, stream);
-    case 4: return launch_fwd_tiles_t<4, SAMPLE>(tl, pose, out, stream);
-    case 8: return launch_fwd_tiles_t<8, SAMPLE>(tl, pose, out, stream);
-    case 16: return launch_fwd_tiles_t<16, SAMPLE>(tl, pose, out, stream);
+    case 1: return launch_fwd_tiles_t<1, SAMPLE, CHAIN>(tl, pose, out, stream);
+    case 2: return launch_fwd_tiles_t<2, SAMPLE, CHAIN>(tl, pose, out, stream);
+    case 4: return launch_fwd_tiles_t<4, SAMPLE, CHAIN>(tl, pose, out, stream);
+    case 8: return launch_fwd_tiles_t<8, SAMPLE, CHAIN>(tl, pose, out, stream);
+    case 16: return launch_fwd_tiles_t<16, SAMPLE, CHAIN>(tl, pose, out, stream);
     default: return hipErrorInvalidValue;
     }
 }
 
+template <int WAVES>
+hipError_t set_lds_limits()
+{
+    const int fwd = (int)forward_tile_lds_bytes(kMaxTileJoints, true);
+    const int bwd = (int)backward_tile_lds_bytes(kMaxBwdTileJoints);
+    const void *fk[4] = {reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, false>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, false>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, true>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, true>)};
+    for (const void *k : fk) {
+        hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, fwd);
+        if (err != hipSuccess) return err;
+    }
+    const void *bk[2] = {reinterpret_cast<const void *>(bwd_tile_kernel<WAVES, false>),
+                         reinterpret_cast<const void *>(bwd_tile_kernel<WAVES, true>)};
+    for (const void *k : bk) {
+        hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bwd);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
 } // namespace
+
+hipError_t prepare_kernels()
+{
+    hipError_t err;
+    if ((err = set_lds_limits<1>()) != hipSuccess) return err;
+    if ((err = set_lds_limits<2>()) != hipSuccess) return err;
+    if ((err = set_lds_limits<4>()) != hipSuccess) return err;
+    if ((err = set_lds_limits<8>()) != hipSuccess) return err;
+    return set_lds_limits<16>();
+}
 
 size_t forward_tile_lds_bytes(int tile_cap, bool sample)
 {
@@ -840,8 +1020,11 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
                                 hipStream_t stream)
 {
     if (tl.num_tiles == 0) return hipSuccess;
-    return pose.kind == 1 ? launch_fwd_tiles_w<true>(tl, pose, out, stream)
-                          : launch_fwd_tiles_w<false>(tl, pose, out, stream);
+    if (tl.chain_units)
+        return pose.kind == 1 ? launch_fwd_tiles_w<true, true>(tl, pose, out, stream)
+                              : launch_fwd_tiles_w<false, true>(tl, pose, out, stream);
+    return pose.kind == 1 ? launch_fwd_tiles_w<true, false>(tl, pose, out, stream)
+                          : launch_fwd_tiles_w<false, false>(tl, pose, out, stream);
 }
 
 hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
@@ -908,14 +1091,6 @@ hipError_t launch_bwd_tiles_t(const TileLaunch &tl, const PoseArgs &pose, const 
 {
     const size_t lds = backward_tile_lds_bytes(tl.tile_cap);
     auto kern = bwd_tile_kernel<WAVES, CKPT>;
-    static bool lds_attr_set = false;
-    if (!lds_attr_set) {
-        hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)backward_tile_lds_bytes(kMaxBwdTileJoints));
-        if (err != hipSuccess) return err;
-        lds_attr_set = true;
-    }
     hipLaunchKernelGGL(kern, dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, bwd);
     return hipGetLastError();
 }

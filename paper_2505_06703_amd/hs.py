@@ -34,7 +34,8 @@ HS_POSE_CLIPS = 1
 
 SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
            "hs_plan_create", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
-           "hs_scan_forward", "hs_skin", "hs_scan_backward")
+           "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
+           "hs_graph_launch", "hs_graph_destroy")
 
 
 class HSError(RuntimeError):
@@ -51,7 +52,8 @@ class hs_batch(ctypes.Structure):
 class hs_plan_opts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_int32), ("tile_joints", ctypes.c_int32),
                 ("waves_per_tile", ctypes.c_int32), ("grid_tiles", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("autotune", ctypes.c_int32), ("chain_units", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -112,8 +114,13 @@ def load_library():
     lib.hs_scan_forward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, i32, u32, vp]
     lib.hs_skin.argtypes = [i64, vp, vp, vp, vp]
     lib.hs_scan_backward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp, u32, vp]
+    lib.hs_graph_create_forward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, ctypes.POINTER(vp)]
+    lib.hs_graph_launch.argtypes = [vp, vp]
+    lib.hs_graph_destroy.argtypes = [vp]
+    lib.hs_graph_destroy.restype = None
     for name in ("hs_context_create", "hs_plan_create", "hs_plan_get_info", "hs_pose_sample",
-                 "hs_scan_forward", "hs_skin", "hs_scan_backward"):
+                 "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
+                 "hs_graph_launch"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -187,7 +194,7 @@ class Plan:
     """Topology analysis of a CSR batch (see ``hs_plan_create``)."""
 
     def __init__(self, offsets, parents, ctx=None, strategy=HS_STRATEGY_AUTO, tile_joints=0,
-                 waves_per_tile=0, grid_tiles=0, autotune=False):
+                 waves_per_tile=0, grid_tiles=0, autotune=False, chain_units=False):
         self.ctx = ctx or default_context()
         off = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
                                               dtype=np.int64))
@@ -198,7 +205,8 @@ class Plan:
         self.num_characters = off.size - 1
         self.num_joints = par.size
         batch = hs_batch(self.num_characters, self.num_joints, off.ctypes.data, par.ctypes.data)
-        opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)))
+        opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)),
+                            int(bool(chain_units)))
         h = ctypes.c_void_p()
         _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),
                                              ctypes.byref(h)))
@@ -331,3 +339,47 @@ def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0,
     _check(load_library().hs_scan_backward(plan.handle, ctypes.byref(src), _ptr(grad_global), _ptr(ckpt),
                                            int(ckpt_k), _ptr(gq), _ptr(gt), _ptr(gs), 0, _stream(stream)))
     return gq, gt, gs
+
+
+class ForwardGraph:
+    """One hs_scan_forward call captured into a HIP graph (``hs_graph_create_forward``).
+
+    The arrays passed here are baked into the graph: ``launch()`` re-reads the
+    current contents of the same inputs and rewrites the same outputs.  The
+    object keeps references to them so that they outlive the graph.
+    """
+
+    def __init__(self, plan, quat=None, trans=None, scale=None, *, clips=None, clip_a=None, clip_b=None,
+                 time=None, weight=None, global_out=None, inv_bind=None, skin_out=None):
+        N = plan.num_joints
+        if clips is not None:
+            self._params = _clip_params(plan, clip_a, clip_b, time, weight)
+            src = hs_pose_src(HS_POSE_CLIPS, None, None, None, ctypes.pointer(clips.c),
+                              ctypes.pointer(self._params))
+        else:
+            src = _trs_src(plan, quat, trans, scale)
+        if global_out is not None:
+            _need(global_out, "global_out", (N, 4, 4))
+        if inv_bind is not None:
+            _need(inv_bind, "inv_bind", (N, 4, 4))
+            _need(skin_out, "skin_out", (N, 4, 4))
+        self._keep = (plan, quat, trans, scale, clips, clip_a, clip_b, time, weight, global_out, inv_bind,
+                      skin_out, src)
+        h = ctypes.c_void_p()
+        _check(load_library().hs_graph_create_forward(plan.handle, ctypes.byref(src), _ptr(global_out),
+                                                      _ptr(inv_bind), _ptr(skin_out), ctypes.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(load_library().hs_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hs_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

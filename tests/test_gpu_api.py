@@ -1,0 +1,142 @@
+"""GPU tests of the C-ABI's error handling, HIP-graph capture and plan
+bookkeeping.  Every call goes through the C ABI; invalid inputs are caught
+on the host before anything is launched."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2505_06703_amd import hs
+from paper_2505_06703_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def status_of(fn, *a, **kw):
+    try:
+        fn(*a, **kw)
+    except hs.HSError as e:
+        return e.status
+    return hs.HS_OK
+
+
+def test_topology_and_offsets_are_validated():
+    assert status_of(hs.Plan, np.array([0, 3]), np.array([-1, 1, 0], np.int32)) == hs.HS_ERR_TOPOLOGY
+    assert status_of(hs.Plan, np.array([0, 3]), np.array([-1, -5, 0], np.int32)) == hs.HS_ERR_TOPOLOGY
+    assert status_of(hs.Plan, np.array([0, 2, 1, 3]), np.array([-1, 0, -1], np.int32)) == hs.HS_ERR_INVALID_ARG
+    assert status_of(hs.Plan, np.array([1, 3]), np.array([-1, 0, 0], np.int32)) == hs.HS_ERR_INVALID_ARG
+    assert status_of(hs.Plan, np.array([0, 2]), np.array([-1, 0, 1], np.int32)) == hs.HS_ERR_INVALID_ARG
+    assert status_of(hs.Plan, np.array([0, 3]), np.array([-1, 0, 1], np.int32), tile_joints=100) == hs.HS_ERR_INVALID_ARG
+    assert status_of(hs.Plan, np.array([0, 3]), np.array([-1, 0, 1], np.int32), waves_per_tile=3) == hs.HS_ERR_INVALID_ARG
+    big = np.arange(-1, 4999, dtype=np.int32)
+    assert status_of(hs.Plan, np.array([0, 5000]), big, strategy=hs.HS_STRATEGY_TILE) == hs.HS_ERR_UNSUPPORTED
+
+
+def test_plan_accepts_device_topology():
+    b = wl.plain_scan(num_characters=4)
+    p1 = hs.Plan(b.offsets, b.parents)
+    lib = hs.load_library()
+    off, par = dev(b.offsets), dev(b.parents)
+    batch = hs.hs_batch(4, b.num_joints, off.data_ptr(), par.data_ptr())
+    h = ctypes.c_void_p()
+    assert lib.hs_plan_create(p1.ctx.handle, ctypes.byref(batch), None, ctypes.byref(h)) == hs.HS_OK
+    info = hs.hs_plan_info()
+    assert lib.hs_plan_get_info(h, ctypes.byref(info)) == hs.HS_OK
+    assert info.num_joints == b.num_joints and info.max_depth == p1.info["max_depth"]
+    lib.hs_plan_destroy(h)
+
+
+def _call_forward(plan, q, t, s, G, inv=None, S=None, ckpt=None, k=0, flags=0):
+    src = hs.hs_pose_src(hs.HS_POSE_TRS, q, t, s, None, None)
+    return hs.load_library().hs_scan_forward(plan.handle, ctypes.byref(src), G, inv, S, ckpt, k, flags,
+                                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def test_forward_argument_errors_launch_nothing():
+    b = wl.plain_scan(num_characters=2)
+    plan = hs.Plan(b.offsets, b.parents)
+    N = b.num_joints
+    q, t = dev(b.quat), dev(b.trans)
+    G = torch.full((N + 1, 4, 4), 7.0, device=DEV)
+    qp, tp, Gp = q.data_ptr(), t.data_ptr(), G.data_ptr()
+    assert _call_forward(plan, None, tp, None, Gp) == hs.HS_ERR_INVALID_ARG          # NULL quat
+    assert _call_forward(plan, qp, tp, None, None) == hs.HS_ERR_INVALID_ARG          # no output
+    assert _call_forward(plan, qp + 4, tp, None, Gp) == hs.HS_ERR_INVALID_ARG        # misaligned quat
+    assert _call_forward(plan, qp, tp, None, Gp + 4) == hs.HS_ERR_INVALID_ARG        # misaligned output
+    assert _call_forward(plan, qp, tp, None, qp) == hs.HS_ERR_INVALID_ARG            # output aliases input
+    assert _call_forward(plan, qp, tp, None, Gp, flags=1) == hs.HS_ERR_INVALID_ARG   # unknown flags
+    assert _call_forward(plan, qp, tp, None, Gp, inv=Gp + 64) == hs.HS_ERR_INVALID_ARG  # inv without skin
+    ck = torch.empty((N, 12), device=DEV)
+    assert _call_forward(plan, qp, tp, None, Gp, ckpt=ck.data_ptr(), k=0) == hs.HS_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(G == 7.0), "a rejected call must not write"
+    assert _call_forward(plan, qp, tp, None, Gp) == hs.HS_OK
+
+
+def test_backward_and_sampler_argument_errors():
+    b = wl.fused_sample(num_characters=3)
+    plan = hs.Plan(b.offsets, b.parents)
+    x = b.extra
+    lib = hs.ClipLibrary(dev(x["key_quat"][:, :, :100]), dev(x["key_trans"][:, :, :100]))
+    with pytest.raises(hs.HSError) as ei:  # clips shorter than the characters
+        hs.hs_pose_sample(plan, lib, dev(x["clip_a"]), dev(x["clip_b"]), dev(x["time"]), dev(x["weight"]))
+    assert ei.value.status == hs.HS_ERR_INVALID_ARG
+    N = b.num_joints
+    with pytest.raises(hs.HSError) as ei:
+        hs.hs_scan_backward(plan, dev(b.quat), dev(b.trans), None, torch.zeros((N, 4, 4), device=DEV),
+                            ckpt=torch.zeros((N, 12), device=DEV), ckpt_k=0)
+    assert ei.value.status == hs.HS_ERR_INVALID_ARG
+
+
+def test_graph_replays_track_input_changes():
+    b = wl.deep_forward(num_characters=8)
+    plan = hs.Plan(b.offsets, b.parents)
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    N = b.num_joints
+    G = torch.empty((N, 4, 4), device=DEV)
+    g = hs.ForwardGraph(plan, q, t, s, global_out=G)
+    rng = np.random.default_rng(0)
+    for it in range(4):
+        g.launch()
+        torch.cuda.synchronize()
+        ref, _ = hs.hs_scan_forward(plan, q, t, s)
+        torch.cuda.synchronize()
+        assert torch.equal(G, ref), f"replay {it}"
+        # eager work between replays: new poses in place
+        q.copy_(dev(wl.random_quats(rng, N, 0.3)))
+        t.mul_(1.01)
+    g.close()
+
+
+def test_graph_of_fused_sample_and_skin():
+    b = wl.fused_sample(num_characters=16)
+    x = b.extra
+    lib = hs.ClipLibrary(dev(x["key_quat"]), dev(x["key_trans"]), x["fps"])
+    cp = dict(clip_a=dev(x["clip_a"]), clip_b=dev(x["clip_b"]), time=dev(x["time"]), weight=dev(x["weight"]))
+    plan = hs.Plan(b.offsets, b.parents)
+    N = b.num_joints
+    inv = dev(np.tile(np.eye(4, dtype=np.float32), (N, 1, 1)))
+    S = torch.empty((N, 4, 4), device=DEV)
+    g = hs.ForwardGraph(plan, clips=lib, **cp, inv_bind=inv, skin_out=S)
+    for it in range(3):
+        g.launch()
+        _, ref = hs.hs_scan_forward(plan, clips=lib, **cp, want_global=False, inv_bind=inv)
+        torch.cuda.synchronize()
+        assert torch.equal(S, ref), f"replay {it}"
+        cp["time"].add_(0.173)
+
+
+def test_plan_info_reports_tiles_and_multipass():
+    b = wl.heterogeneous(num_characters=100)
+    p = hs.Plan(b.offsets, b.parents, tile_joints=512)
+    inf = p.info
+    assert inf["tiled_joints"] + inf["multipass_joints"] == b.num_joints
+    assert inf["multipass_joints"] == int(np.sum(np.diff(b.offsets)[np.diff(b.offsets) > 512]))
+    assert inf["tile_joints"] == 512 and inf["num_tiles"] > 0

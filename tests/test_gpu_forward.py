@@ -53,7 +53,8 @@ def test_skin_at_rest_pose_is_identity():
 @pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4),
                                    dict(tile_joints=2048, waves_per_tile=8, grid_tiles=2),
                                    dict(strategy=hs.HS_STRATEGY_MULTIPASS),
-                                   dict(tile_joints=256)])
+                                   dict(tile_joints=256), dict(chain_units=True),
+                                   dict(chain_units=True, tile_joints=2048, waves_per_tile=16, grid_tiles=1)])
 def test_deep_forward_reduced(shape):
     b = wl.deep_forward(num_characters=24)
     plan, G, _ = run_forward(b, **shape)
@@ -105,9 +106,10 @@ def _single(parents, seed=0, angle=0.3):
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 1000, 2048, 2049, 5000])
 def test_chains_of_many_lengths(n):
     b = _single(np.arange(-1, n - 1), seed=n, angle=0.1)
-    plan, G, _ = run_forward(b)
     Gr, lam, _ = reference(b)
-    check_global(G, Gr, lam, f"chain {n}")
+    for cu in (False, True):
+        plan, G, _ = run_forward(b, chain_units=cu)
+        check_global(G, Gr, lam, f"chain {n} chain_units={cu}")
 
 
 def test_chain_of_100k_joints_multipass_stress():
@@ -210,3 +212,29 @@ def test_empty_batch():
     assert G.shape == (0, 4, 4)
     plan2 = hs.Plan(np.zeros(4, np.int64), np.zeros(0, np.int32))
     assert plan2.info["num_tiles"] == 0
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(chain_units=True), dict(chain_units=True, waves_per_tile=1),
+                                   dict(chain_units=True, tile_joints=2048, waves_per_tile=16),
+                                   dict(chain_units=True, tile_joints=3072, waves_per_tile=2)])
+def test_comb_of_chains_with_heads_inside_lanes(shape):
+    """Chains of random lengths whose heads hang off joints >= 300 ids back:
+    every 4-block run is a chain unit, and segment heads fall at arbitrary
+    positions inside the 4-joint lane groups (several per lane at times)."""
+    rng = np.random.default_rng(42)
+    chars = []
+    for n in (2000, 1500, 777, 2900):
+        par = np.arange(-1, n - 1, dtype=np.int32)
+        for j in range(1, n):
+            if rng.uniform() < 1 / 25:
+                par[j] = rng.integers(0, max(1, j - 300)) if j > 300 else -1
+            if rng.uniform() < 0.02 and j > 300:  # short segments, heads close together
+                par[j] = rng.integers(0, j - 300)
+        chars.append(par)
+    par = np.concatenate(chars)
+    off = np.concatenate([[0], np.cumsum([c.size for c in chars])]).astype(np.int64)
+    q, t, s = wl.random_pose(rng, par.size, max_angle=0.2)
+    b = wl.Batch("comb", off, par, q, t, s, q, t, s)
+    plan, G, _ = run_forward(b, **shape)
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, f"comb {shape}")
