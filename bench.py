@@ -8,10 +8,15 @@ resident in HBM.  Two input/output sets alternate between steps so that the
 256 MB last-level cache never holds the next step's data.
 
 Prints one JSON line with the throughput in joint transforms per second, the
-roofline of the scan kernel (algorithmic bytes / measured kernel time against
-8 TB/s HBM), and the FP64 CPU oracle timed on the host as a baseline.
+roofline of the dominant kernel (algorithmic bytes / measured kernel time
+against 8 TB/s HBM), the FP64 CPU oracle timed on the host as a baseline,
+and the error of one GPU step against FP64.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+                    [--no-autotune]
+
+Other workloads (parity presets, not the headline line): plain_scan,
+heterogeneous, fused_sample, differentiable (forward + adjoint).
 """
 import argparse
 import hashlib
@@ -30,6 +35,24 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_06703_amd", "csrc", f)
                   for f in ("hs_kernels.hip", "hs_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+COPY_BYTES = 256 << 20
+WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "differentiable"]
+
+# algorithmic HBM bytes per joint that the dominant kernel of a step must
+# move (read + write)
+BYTES_PER_JOINT = {
+    # quat 16 + trans 12 + scale 12 + parent 4 read, global 64 written
+    "deep_forward": 108,
+    "heterogeneous": 108,
+    # + inverse bind 64 read, skin 64 written
+    "plain_scan": 236,
+    # parent 4 + inverse bind 64 read, skin 64 written (+ clip library once)
+    "fused_sample": 132,
+    # adjoint: read quat, trans, scale, parent 44 + grad_global 64, write
+    # grad_quat 16 + grad_trans 12
+    "differentiable": 136,
+}
+DOMINANT = {"differentiable": "bwd_tile_kernel"}
 
 
 def kernel_source_sha():
@@ -58,10 +81,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="deep_forward",
-                    choices=["deep_forward", "plain_scan", "heterogeneous", "fused_sample"])
+    ap.add_argument("--workload", default="deep_forward", choices=WORKLOADS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape at plan time")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the plan's default launch shape instead of timing candidates at plan time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -70,25 +93,12 @@ def parse():
     return ap.parse_args()
 
 
-# algorithmic HBM bytes per joint that one step must move (read + write)
-BYTES_PER_JOINT = {
-    # quat 16 + trans 12 + scale 12 + parent 4 read, global 64 written
-    "deep_forward": 108,
-    "heterogeneous": 108,
-    # + inverse bind 64 read, skin 64 written
-    "plain_scan": 236,
-    # parent 4 + inverse bind 64 read, skin 64 written (+ clip library once)
-    "fused_sample": 132,
-}
-
-
-COPY_BYTES = 256 << 20
-
-
 def summarize_pmc(workload, fetch_csv, write_csv):
-    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the scan kernel,
-    scaled by what the same counters read for the plain copy of COPY_BYTES."""
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the dominant
+    kernel, scaled by what the same counters read for the plain copy of
+    COPY_BYTES in the same run."""
     import csv
+    kname = DOMINANT.get(workload, "fwd_tile_kernel")
 
     def per_kernel(path, counter):
         vals = {}
@@ -97,7 +107,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
                 if row.get("Counter_Name") != counter:
                     continue
                 name = row["Kernel_Name"]
-                key = "scan" if "fwd_tile_kernel" in name else ("copy" if "copy" in name.lower() else None)
+                key = "scan" if kname in name else ("copy" if "copy" in name.lower() else None)
                 if key:
                     vals.setdefault(key, []).append(float(row["Counter_Value"]))
         # the calibration copy is the largest copy of the run
@@ -107,7 +117,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
     write = per_kernel(write_csv, "WRITE_SIZE")
     f_scale = COPY_BYTES / (fetch["copy"] * 1024.0)
     w_scale = COPY_BYTES / (write["copy"] * 1024.0)
-    rec = {"kernel": "fwd_tile_kernel", "source_sha": kernel_source_sha(),
+    rec = {"kernel": kname, "source_sha": kernel_source_sha(),
            "fetch_bytes_per_launch": fetch["scan"] * 1024.0 * f_scale,
            "write_bytes_per_launch": write["scan"] * 1024.0 * w_scale,
            "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}
@@ -124,6 +134,88 @@ def summarize_pmc(workload, fetch_csv, write_csv):
     print(json.dumps({workload: rec}))
 
 
+class Workload:
+    """Device-resident inputs/outputs of one preset and its step."""
+
+    def __init__(self, name, autotune):
+        import torch
+        from paper_2505_06703_amd import hs
+        from paper_2505_06703_amd import workloads as wl
+        self.torch, self.hs, self.name = torch, hs, name
+        dev = torch.device("cuda:0")
+        up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self.b = b = wl.make(name)
+        N = b.num_joints
+        self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune)
+        self.inv = None
+        self.clips = None
+        if name in ("plain_scan", "fused_sample"):
+            # inverse binds from the rest pose: scan it on the GPU, invert on the host
+            Grest, _ = hs.hs_scan_forward(self.plan, up(b.rest_quat), up(b.rest_trans), up(b.rest_scale))
+            self.inv = up(np.linalg.inv(Grest.cpu().numpy().astype(np.float64)).astype(np.float32))
+            del Grest
+        if name == "fused_sample":
+            x = b.extra
+            self.clips = hs.ClipLibrary(up(x["key_quat"]), up(x["key_trans"]), x["fps"])
+            self.cp = dict(clip_a=up(x["clip_a"]), clip_b=up(x["clip_b"]), time=up(x["time"]),
+                           weight=up(x["weight"]))
+        if name == "differentiable":
+            # targets: rest positions (GPU scan of the rest pose) + seeded offsets
+            Grest, _ = hs.hs_scan_forward(self.plan, up(b.rest_quat), up(b.rest_trans), up(b.rest_scale))
+            self.eff = up(b.extra["effectors"].astype(np.int64))
+            self.target = Grest[self.eff, :3, 3] + up(b.extra["target_offsets"])
+            del Grest
+        self.sets = []
+        for k in range(2):
+            s = {}
+            if self.clips is None:
+                s["q"], s["t"], s["s"] = up(b.quat), up(b.trans), up(b.scale)
+            s["inv"] = None if self.inv is None else (self.inv if k == 0 else self.inv.clone())
+            if name in ("deep_forward", "heterogeneous", "differentiable"):
+                s["G"] = torch.empty((N, 4, 4), device=dev)
+            else:
+                s["S"] = torch.empty((N, 4, 4), device=dev)
+            if name == "differentiable":
+                s["gG"] = torch.zeros((N, 4, 4), device=dev)
+                s["gq"] = torch.empty((N, 4), device=dev)
+                s["gt"] = torch.empty((N, 3), device=dev)
+            self.sets.append(s)
+        self.fwd_ev, self.bwd_ev = [], []
+
+    def step(self, k, timed=False):
+        torch, hs, s = self.torch, self.hs, self.sets[k % 2]
+        if timed:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record()
+        if self.name == "fused_sample":
+            hs.hs_scan_forward(self.plan, clips=self.clips, **self.cp, want_global=False, inv_bind=s["inv"],
+                               skin_out=s["S"])
+        elif self.name == "plain_scan":
+            hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], want_global=False, inv_bind=s["inv"],
+                               skin_out=s["S"])
+        else:
+            hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+        if timed:
+            e[1].record()
+            self.fwd_ev.append(e)
+        if self.name == "differentiable":
+            # loss = sum over effectors |b_e - y_e|^2: its gradient enters the
+            # effector rows of the (otherwise zero) dLoss/dG buffer
+            s["gG"][self.eff, :3, 3] = 2.0 * (s["G"][self.eff, :3, 3] - self.target)
+            if timed:
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                e[0].record()
+            hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
+                                grad_quat=s["gq"], grad_trans=s["gt"])
+            if timed:
+                e[1].record()
+                self.bwd_ev.append(e)
+
+    @staticmethod
+    def mean_ms(evs):
+        return float(np.mean([a.elapsed_time(b) for a, b in evs])) if evs else 0.0
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -137,90 +229,45 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2505_06703_amd import hs
-    from paper_2505_06703_amd import workloads as wl
-
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
-    b = wl.make(args.workload)
+    w = Workload(args.workload, autotune=not args.no_autotune)
+    b, info = w.b, w.plan.info
     N, C = b.num_joints, b.num_characters
-    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-
-    plan = hs.Plan(b.offsets, b.parents, autotune=args.autotune)
-    info = plan.info
-
-    clips = None
-    inv = None
-    if args.workload in ("plain_scan", "fused_sample"):
-        # inverse binds from the rest pose: scan it on the GPU, invert on the host
-        Grest, _ = hs.hs_scan_forward(plan, up(b.rest_quat), up(b.rest_trans), up(b.rest_scale))
-        inv = up(np.linalg.inv(Grest.cpu().numpy().astype(np.float64)).astype(np.float32))
-        del Grest
-    if args.workload == "fused_sample":
-        clips = hs.ClipLibrary(up(b.extra["key_quat"]), up(b.extra["key_trans"]), b.extra["fps"])
-        cp = dict(clip_a=up(b.extra["clip_a"]), clip_b=up(b.extra["clip_b"]), time=up(b.extra["time"]),
-                  weight=up(b.extra["weight"]))
-
-    nsets = 2
-    sets = []
-    for k in range(nsets):
-        s = {}
-        if clips is None:
-            s["q"], s["t"], s["s"] = up(b.quat), up(b.trans), up(b.scale)
-        s["inv"] = None if inv is None else (inv if k == 0 else inv.clone())
-        if args.workload in ("deep_forward", "heterogeneous"):
-            s["G"] = torch.empty((N, 4, 4), device=dev)
-        else:
-            s["S"] = torch.empty((N, 4, 4), device=dev)
-        sets.append(s)
-
-    def step(k):
-        s = sets[k % nsets]
-        if args.workload == "fused_sample":
-            hs.hs_scan_forward(plan, clips=clips, **cp, want_global=False, inv_bind=s["inv"], skin_out=s["S"])
-        elif args.workload == "plain_scan":
-            hs.hs_scan_forward(plan, s["q"], s["t"], s["s"], want_global=False, inv_bind=s["inv"],
-                               skin_out=s["S"])
-        else:
-            hs.hs_scan_forward(plan, s["q"], s["t"], s["s"], global_out=s["G"])
 
     if args.calibrate_copy:
-        src = torch.ones(COPY_BYTES // 4, device=dev)
+        src = torch.ones(COPY_BYTES // 4, device="cuda:0")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
     for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+        w.step(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ev[k][0].record(stream)
-        step(k)
-        ev[k][1].record(stream)
+        w.step(k, timed=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kernel_ms = float(np.mean([a.elapsed_time(e) for a, e in ev]))
 
-    value = N * args.steps / elapsed
+    fwd_ms, bwd_ms = w.mean_ms(w.fwd_ev), w.mean_ms(w.bwd_ev)
+    dominant = DOMINANT.get(args.workload, "fwd_tile_kernel")
+    kernel_ms = bwd_ms if dominant == "bwd_tile_kernel" else fwd_ms
     bytes_per_launch = N * BYTES_PER_JOINT[args.workload]
     if args.workload == "fused_sample":
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload)
-
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+            "kernel": dominant, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": bytes_per_launch}
+    if args.workload == "differentiable":
+        roof["forward_kernel_ms"] = fwd_ms
     out = {
         "metric": METRIC,
-        "value": value,
-        "unit": "joint transforms/s",
+        "value": N * args.steps / elapsed,
+        "unit": "joint transforms/s" + (" (forward + adjoint)" if args.workload == "differentiable" else ""),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -230,34 +277,42 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "characters": C, "joints": N,
-                   "max_depth": info["max_depth"], "tile_joints": info["tile_joints"],
-                   "waves_per_tile": info["waves_per_tile"], "tiles": info["num_tiles"],
-                   "multipass_joints": info["multipass_joints"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fwd_tile_kernel", "kernel_ms": kernel_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "config": {"workload": args.workload, "characters": C, "joints": N, "max_depth": info["max_depth"],
+                   "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
+                   "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
+                   "autotuned": not args.no_autotune},
+        "roofline": roof,
     }
-
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["err_vs_fp64"] = cpu_baseline(b, args.workload, plan, sets, step, nsets)
+        out["cpu_baseline"], out["err_vs_fp64"] = cpu_baseline(w)
     print(json.dumps(out))
 
 
-def cpu_baseline(b, workload, plan, sets, step, nsets):
-    """Time the FP64 oracle on the host (all cores it may use) on repeated
-    passes over the full batch, and compare the last GPU result with it."""
-    import torch
+def cpu_baseline(w):
+    """Time the FP64 oracle on the host (all the cores it may use) on repeated
+    passes over the full batch, and compare one fresh GPU step with it."""
     import oracle
 
+    torch, b, name = w.torch, w.b, w.name
     cores = len(os.sched_getaffinity(0))
     N = b.num_joints
-    if workload == "fused_sample":
+    if name == "fused_sample":
+        x = b.extra
+
         def run():
-            q, t = oracle.pose_sample(b.offsets, b.extra["key_quat"], b.extra["key_trans"], b.extra["clip_a"],
-                                      b.extra["clip_b"], b.extra["time"], b.extra["weight"], b.extra["fps"])
+            q, t = oracle.pose_sample(b.offsets, x["key_quat"], x["key_trans"], x["clip_a"], x["clip_b"], x["time"],
+                                      x["weight"], x["fps"])
             return oracle.forward(b.offsets, b.parents, q, t, None), t
+    elif name == "differentiable":
+        target = w.target.cpu().numpy().astype(np.float64)
+        eff = b.extra["effectors"]
+
+        def run():
+            G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+            W = np.zeros((N, 4, 4))
+            W[eff, :3, 3] = 2.0 * (G[eff, :3, 3] - target)
+            run.grads = oracle.backward(b.offsets, b.parents, b.quat, b.trans, b.scale, W)
+            return G, b.trans
     else:
         def run():
             return oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale), b.trans
@@ -268,22 +323,28 @@ def cpu_baseline(b, workload, plan, sets, step, nsets):
         wall = time.perf_counter() - t0
         if wall >= 10.0 or reps >= 50:
             break
+    what = "forward + adjoint" if name == "differentiable" else "forward"
     base = {"value": N * reps / wall, "unit": "joint transforms/s", "cores": cores, "kind": "oracle",
-            "sample": f"full {workload} batch ({b.num_characters} characters, {N} joints) x {reps} passes, "
-                      f"fp32->fp64 widening included, {wall:.1f} s wall"}
+            "sample": f"full {name} batch ({b.num_characters} characters, {N} joints, FP64 {what}) x {reps} "
+                      f"passes, fp32->fp64 widening included, {wall:.1f} s wall"}
 
-    # error of one fresh GPU step against the oracle
-    step(0)
+    w.step(0)
     torch.cuda.synchronize()
+    s0 = w.sets[0]
     lam = oracle.path_length(b.offsets, b.parents, G, tr)
-    if workload in ("deep_forward", "heterogeneous"):
-        Gg = sets[0]["G"].cpu().numpy().astype(np.float64)
-        dA = float(np.abs(Gg[:, :3, :3] - G[:, :3, :3]).max())
+    if name in ("deep_forward", "heterogeneous", "differentiable"):
+        Gg = s0["G"].cpu().numpy().astype(np.float64)
         db = np.abs(Gg[:, :3, 3] - G[:, :3, 3]).max(axis=1)
-        err = {"rotation_abs_max": dA, "translation_rel_max": float((db / np.maximum(lam, 1e-12)).max())}
+        err = {"rotation_abs_max": float(np.abs(Gg[:, :3, :3] - G[:, :3, :3]).max()),
+               "translation_rel_max": float((db / np.maximum(lam, 1e-12)).max())}
+        if name == "differentiable":
+            gq, gt, _ = run.grads
+            for key, g, r in (("grad_quat", s0["gq"], gq), ("grad_trans", s0["gt"], gt)):
+                g = g.cpu().numpy().astype(np.float64)
+                err[key + "_rel_max"] = float(np.abs(g - r).max() / max(1.0, np.abs(r).max()))
     else:
-        S = oracle.skin(G, sets[0]["inv"].cpu().numpy())
-        Sg = sets[0]["S"].cpu().numpy().astype(np.float64)
+        S = oracle.skin(G, s0["inv"].cpu().numpy())
+        Sg = s0["S"].cpu().numpy().astype(np.float64)
         err = {"skin_rotation_abs_max": float(np.abs(Sg[:, :3, :3] - S[:, :3, :3]).max()),
                "skin_translation_abs_max": float(np.abs(Sg[:, :3, 3] - S[:, :3, 3]).max())}
     return base, err

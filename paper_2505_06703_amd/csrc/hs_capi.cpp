@@ -124,6 +124,35 @@ struct hs_context {
     std::map<std::string, Shape> tuned;  // autotuning cache keyed by arch + size class
 };
 
+// Device tables and workspace of the multipass path.
+struct MPSet {
+    MPBlock *d_blocks = nullptr;
+    int32_t num_blocks = 0;
+    int64_t nmp = 0;
+    int32_t rounds = 0;        // block-level jump rounds
+    int32_t depth_rounds = 0;  // ceil(log2 max depth) (adjoint)
+    float4 *P[2] = {nullptr, nullptr};
+    int32_t *E[2] = {nullptr, nullptr};
+    float4 *S[2] = {nullptr, nullptr};
+    float4 *M[2] = {nullptr, nullptr};
+    int32_t *A[2] = {nullptr, nullptr};
+    float4 *G = nullptr;
+};
+
+void free_mpset(MPSet &m)
+{
+    (void)hipFree(m.d_blocks);
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(m.P[i]);
+        (void)hipFree(m.E[i]);
+        (void)hipFree(m.S[i]);
+        (void)hipFree(m.M[i]);
+        (void)hipFree(m.A[i]);
+    }
+    (void)hipFree(m.G);
+    m = MPSet{};
+}
+
 struct hs_plan {
     hs_context *ctx = nullptr;
     int64_t C = 0, N = 0;
@@ -144,14 +173,10 @@ struct hs_plan {
     int32_t bwd_cap = 0;
     int64_t bwd_untiled = 0;  // joints the adjoint's tiles do not cover
     int32_t max_units = 0;
-    // multipass
-    MPBlock *d_mp_blocks = nullptr;
-    int32_t num_mp_blocks = 0;
-    int64_t nmp = 0;
-    int32_t mp_rounds = 0;
-    float4 *d_mp_P[2] = {nullptr, nullptr};
-    int32_t *d_mp_E[2] = {nullptr, nullptr};
-    float4 *d_mp_adj[2] = {nullptr, nullptr};
+    // multipass: characters larger than the forward tile (mp) and than the
+    // adjoint tile (bmp, with the adjoint workspace)
+    MPSet mp, bmp;
+    std::vector<int32_t> h_level;
 };
 
 namespace {
@@ -164,12 +189,8 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_level);
     (void)hipFree(p->d_tiles);
     (void)hipFree(p->d_btiles);
-    (void)hipFree(p->d_mp_blocks);
-    for (int i = 0; i < 2; ++i) {
-        (void)hipFree(p->d_mp_P[i]);
-        (void)hipFree(p->d_mp_E[i]);
-        (void)hipFree(p->d_mp_adj[i]);
-    }
+    free_mpset(p->mp);
+    free_mpset(p->bmp);
     delete p;
 }
 
@@ -342,12 +363,38 @@ Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units)
     return pk;
 }
 
+// Upload a packing's multipass blocks and allocate the path's workspace
+// (and the adjoint's, if asked).
+hs_status make_mpset(MPSet &m, const Packing &pk, bool adjoint, int depth_rounds)
+{
+    free_mpset(m);
+    m.num_blocks = (int32_t)pk.mpb.size();
+    m.nmp = pk.nmp;
+    m.rounds = ceil_log2(std::max(1, pk.max_chain_mp));
+    m.depth_rounds = depth_rounds;
+    if (pk.nmp == 0) return HS_OK;
+    hipError_t err = upload(&m.d_blocks, pk.mpb);
+    const size_t n = (size_t)pk.nmp;
+    for (int i = 0; i < 2 && err == hipSuccess; ++i) {
+        err = hipMalloc(&m.P[i], n * 3 * sizeof(float4));
+        if (err == hipSuccess) err = hipMalloc(&m.E[i], n * sizeof(int32_t));
+        if (adjoint && err == hipSuccess) err = hipMalloc(&m.S[i], n * 3 * sizeof(float4));
+        if (adjoint && err == hipSuccess) err = hipMalloc(&m.M[i], n * 3 * sizeof(float4));
+        if (adjoint && err == hipSuccess) err = hipMalloc(&m.A[i], n * sizeof(int32_t));
+    }
+    if (adjoint && err == hipSuccess) err = hipMalloc(&m.G, n * 3 * sizeof(float4));
+    if (err != hipSuccess) {
+        free_mpset(m);
+        return fail_hip(err, "hs_plan_create (multipass workspace)");
+    }
+    return HS_OK;
+}
+
 hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
 {
     const int cap = shape.tile_cap;
     Packing pk = pack_tiles(plan, cap, strategy, shape.chain_units);
     std::vector<TileDesc> &sorted = pk.tiles;
-    std::vector<MPBlock> &mpb = pk.mpb;
     const int64_t nmp = pk.nmp, tiled = pk.tiled;
     const int max_chain_tiles = pk.max_chain_tiles, max_chain_mp = pk.max_chain_mp;
 
@@ -356,15 +403,21 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     (void)hipFree(plan->d_btiles);
     plan->d_btiles = nullptr;
     plan->bwd_cap = std::min(cap, hs::kMaxBwdTileJoints);
-    if (plan->bwd_cap < cap) {
-        Packing pb = pack_tiles(plan, plan->bwd_cap, strategy, false);
-        plan->num_btiles = (int32_t)pb.tiles.size();
+    {
+        Packing pb = plan->bwd_cap < cap ? pack_tiles(plan, plan->bwd_cap, strategy, false) : pk;
+        if (plan->bwd_cap < cap) {
+            plan->num_btiles = (int32_t)pb.tiles.size();
+            hipError_t e2 = upload(&plan->d_btiles, pb.tiles);
+            if (e2 != hipSuccess) return fail_hip(e2, "hs_plan_create");
+        } else {
+            plan->num_btiles = (int32_t)sorted.size();
+        }
         plan->bwd_untiled = pb.nmp;
-        hipError_t e2 = upload(&plan->d_btiles, pb.tiles);
-        if (e2 != hipSuccess) return fail_hip(e2, "hs_plan_create");
-    } else {
-        plan->num_btiles = (int32_t)sorted.size();
-        plan->bwd_untiled = nmp;
+        int max_level = 1;
+        for (const MPBlock &mb : pb.mpb)
+            for (int k = 0; k < mb.count; ++k) max_level = std::max(max_level, plan->h_level[mb.gbegin + k]);
+        hs_status rc2 = make_mpset(plan->bmp, pb, true, ceil_log2(max_level));
+        if (rc2 != HS_OK) return rc2;
     }
 
     hipError_t err;
@@ -372,26 +425,9 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     plan->d_tiles = nullptr;
     if ((err = upload(&plan->d_tiles, sorted)) != hipSuccess) return fail_hip(err, "hs_plan_create");
     plan->h_tiles = sorted;
-    (void)hipFree(plan->d_mp_blocks);
-    plan->d_mp_blocks = nullptr;
-    if ((err = upload(&plan->d_mp_blocks, mpb)) != hipSuccess) return fail_hip(err, "hs_plan_create");
-    for (int i = 0; i < 2; ++i) {
-        (void)hipFree(plan->d_mp_P[i]);
-        (void)hipFree(plan->d_mp_E[i]);
-        (void)hipFree(plan->d_mp_adj[i]);
-        plan->d_mp_P[i] = nullptr;
-        plan->d_mp_E[i] = nullptr;
-        plan->d_mp_adj[i] = nullptr;
-        if (nmp > 0) {
-            if ((err = hipMalloc(&plan->d_mp_P[i], (size_t)nmp * 3 * sizeof(float4))) != hipSuccess ||
-                (err = hipMalloc(&plan->d_mp_E[i], (size_t)nmp * sizeof(int32_t))) != hipSuccess)
-                return fail_hip(err, "hs_plan_create (multipass workspace)");
-        }
-    }
+    hs_status rc = make_mpset(plan->mp, pk, false, 0);
+    if (rc != HS_OK) return rc;
     plan->max_units = pk.max_units;
-    plan->num_mp_blocks = (int32_t)mpb.size();
-    plan->nmp = nmp;
-    plan->mp_rounds = ceil_log2(std::max(1, max_chain_mp));
     plan->shape = shape;
 
     hs_plan_info &I = plan->info;
@@ -403,7 +439,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     I.grid = shape.grid_per_cu > 0
                  ? (int32_t)std::min<int64_t>(sorted.size(), (int64_t)shape.grid_per_cu * plan->ctx->num_cu)
                  : (int32_t)sorted.size();
-    I.multipass_rounds = plan->mp_rounds;
+    I.multipass_rounds = plan->mp.rounds;
     I.max_block_chain = std::max(max_chain_tiles, max_chain_mp);
     return HS_OK;
 }
@@ -421,17 +457,22 @@ hs::TileLaunch tile_launch(const hs_plan *p)
     return tl;
 }
 
-hs::MPLaunch mp_launch(const hs_plan *p)
+hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
 {
     hs::MPLaunch ml{};
-    ml.blocks = p->d_mp_blocks;
-    ml.num_blocks = p->num_mp_blocks;
-    ml.rounds = p->mp_rounds;
-    ml.nmp = p->nmp;
+    ml.blocks = m.d_blocks;
+    ml.num_blocks = m.num_blocks;
+    ml.rounds = m.rounds;
+    ml.nmp = m.nmp;
     ml.parent = p->d_parent;
+    ml.depth_rounds = m.depth_rounds;
+    ml.G = m.G;
     for (int i = 0; i < 2; ++i) {
-        ml.P[i] = p->d_mp_P[i];
-        ml.E[i] = p->d_mp_E[i];
+        ml.P[i] = m.P[i];
+        ml.E[i] = m.E[i];
+        ml.S[i] = m.S[i];
+        ml.M[i] = m.M[i];
+        ml.A[i] = m.A[i];
     }
     return ml;
 }
@@ -497,7 +538,7 @@ hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Out
 {
     hipError_t err = hs::launch_forward_tiles(tile_launch(plan), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (tiles)");
-    err = hs::launch_forward_multipass(mp_launch(plan), pa, oa, stream);
+    err = hs::launch_forward_multipass(mp_launch(plan, plan->mp), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (multipass)");
     return HS_OK;
 }
@@ -709,6 +750,7 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
         return fail(HS_ERR_INVALID_ARG, "joint_offsets[C] = %lld but num_joints = %lld", (long long)off[C], (long long)N);
     }
     plan->h_gparent = gparent;
+    plan->h_level = level;
     plan->info.num_characters = C;
     plan->info.num_joints = N;
     plan->info.max_depth = max_depth;
@@ -748,9 +790,12 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
 
     hs_status rc = build_tables(plan, sh, o.strategy);
     if (rc == HS_OK && o.waves_per_tile == 0 && plan->max_units > 0) {
-        // no more waves than work units in the largest tile
+        // no more waves than work units in the largest tile; tiles small
+        // enough for three workgroups per CU take 8 waves (measured faster
+        // than 16 on the deep workload: more workgroups overlap their phases)
+        const int wmax = sh.tile_cap <= 1024 ? 8 : 16;
         int w = 1;
-        while (w * 2 <= std::min(16, plan->max_units)) w *= 2;
+        while (w * 2 <= std::min(wmax, plan->max_units)) w *= 2;
         if (w != sh.waves) {
             sh.waves = w;
             rc = build_tables(plan, sh, o.strategy);
@@ -891,7 +936,7 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
     if (N == 0) return HS_OK;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_pose_sample: cannot select device");
-    hipError_t err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan), pa, quat_out, trans_out, stream);
+    hipError_t err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan, plan->mp), pa, quat_out, trans_out, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_pose_sample");
     return HS_OK;
 }
@@ -947,9 +992,6 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
     ba.grad_scale = grad_scale;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_backward: cannot select device");
-    if (plan->bwd_untiled > 0)
-        return fail(HS_ERR_UNSUPPORTED, "hs_scan_backward: %lld joints belong to characters larger than the "
-                    "%d-joint adjoint tile", (long long)plan->bwd_untiled, plan->bwd_cap);
     hs::TileLaunch tl = tile_launch(plan);
     if (plan->d_btiles) {
         tl.tiles = plan->d_btiles;
@@ -963,6 +1005,8 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
     }
     hipError_t err = hs::launch_backward_tiles(tl, pa, ba, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
+    err = hs::launch_backward_multipass(mp_launch(plan, plan->bmp), pa, ba, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (multipass)");
     return HS_OK;
 }
 

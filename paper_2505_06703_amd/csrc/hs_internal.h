@@ -80,11 +80,17 @@ struct TileLaunch {
 struct MPLaunch {
     const MPBlock *blocks;
     int32_t num_blocks;
-    int32_t rounds;
+    int32_t rounds;           // block-level jump rounds (forward)
     int64_t nmp;              // joints on the multipass path (compact count)
     const int32_t *parent;    // [N] global parent id or -1
     float4 *P[2];             // [Nmp*3] ping-pong partial products
     int32_t *E[2];            // [Nmp]   ping-pong ext pointers (compact ids)
+    // adjoint workspace (NULL when the plan has none)
+    int32_t depth_rounds;     // ceil(log2 max depth) of these characters
+    float4 *S[2];             // [Nmp*3] ping-pong partial adjoints
+    float4 *M[2];             // [Nmp*3] ping-pong jump products
+    int32_t *A[2];            // [Nmp]   ping-pong jump pointers
+    float4 *G;                // [Nmp*3] global transforms
 };
 
 struct BwdArgs {
@@ -106,7 +112,7 @@ hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, co
 hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
                                  hipStream_t stream);
 hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, const BwdArgs &bwd,
-                                     float4 *adj[2], hipStream_t stream);
+                                     hipStream_t stream);
 hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const PoseArgs &pose,
                               float *quat_out, float *trans_out, hipStream_t stream);
 hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,

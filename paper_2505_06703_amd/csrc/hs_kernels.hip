@@ -306,12 +306,15 @@ __device__ __forceinline__ void publish_blocks(int *flags, int b0, int nb, int l
 
 // Global matrices of tile-local joints [base, base + 64 * nb) leave as 16-byte
 // rows, 4 per joint; each store instruction covers 1 KiB of contiguous output.
+template <int MAXNB>
 __device__ __forceinline__ void store_rows(const OutArgs &out, const float4 *Gs, int64_t tile_begin, int base,
                                            int nb, int n, int lane)
 {
     const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * (tile_begin + base);
-    for (int k = 0; k < 4 * nb; ++k) {
+#pragma unroll
+    for (int k = 0; k < 4 * MAXNB; ++k) {
+        if (k >= 4 * nb) break;
         const int c = lane + kWave * k;
         const int jj = base + (c >> 2);
         const int r = c & 3;
@@ -368,7 +371,7 @@ __device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &
     }
     if (valid) aff_store(Gs + 3 * jl, m);
     publish_blocks(flags, b, 1, lane);
-    if (out.global_out) store_rows(out, Gs, td.begin, base, 1, n, lane);
+    if (out.global_out) store_rows<1>(out, Gs, td.begin, base, 1, n, lane);
     if (valid) write_skin_and_ckpt(out, gid, m);
 }
 
@@ -391,47 +394,63 @@ __device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseA
                                                int *flags, const int *cstart, int lane)
 {
     const int ubase = b0 * kWave;
+    const int uend = min(ubase + nb * kWave, n);  // the unit's joints are [ubase, uend)
     const int j0 = ubase + lane * kChainK;
-    float P[kChainK][12];
+
+    // Local transforms, loaded coalesced (lane = joint within each block) and
+    // staged in the unit's own LDS slots, which hold nothing else yet.
+#pragma unroll
+    for (int s = 0; s < kChainK; ++s) {
+        const int jl = ubase + s * kWave + lane;
+        if (jl < uend) {
+            int chr, lj;
+            char_of<SAMPLE>(td, cstart, jl, chr, lj);
+            float L[12];
+            load_local<SAMPLE>(pose, td.begin + jl, chr, lj, L);
+            aff_store(Gs + 3 * jl, L);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    // 1. sequential products over the lane's kChainK consecutive joints.
     // anchor of each joint's segment: tile-local id before the unit, -1 for
-    // a root, or kOpen when the segment continues from the previous lane
+    // a root, or kOpen when the segment continues from the previous lane.
     constexpr int kOpen = -2;
     int anc[kChainK];
+    float T[12];
 #pragma unroll
     for (int s = 0; s < kChainK; ++s) {
         const int jl = j0 + s;
-        const bool valid = jl < n;
-        const int64_t gid = td.begin + jl;
+        const bool valid = jl < uend;
         float L[12];
         int p = -1;
         if (valid) {
-            const int pg = tl.parent[gid];
+            const int pg = tl.parent[td.begin + jl];
             p = pg < 0 ? -1 : (int)(pg - td.begin);
-            int chr, lj;
-            char_of<SAMPLE>(td, cstart, jl, chr, lj);
-            load_local<SAMPLE>(pose, gid, chr, lj, L);
+            aff_load(Gs + 3 * jl, L);
         } else {
             aff_identity(L);
         }
         const bool cont = valid && p == jl - 1 && p >= ubase;
         if (s == 0) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) P[0][k] = L[k];
+            for (int k = 0; k < 12; ++k) T[k] = L[k];
             anc[0] = cont ? kOpen : p;
         } else {
             float o[12];
-            aff_mul(P[s - 1], L, o);
+            aff_mul(T, L, o);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) P[s][k] = cont ? o[k] : L[k];
+            for (int k = 0; k < 12; ++k) T[k] = cont ? o[k] : L[k];
             anc[s] = cont ? anc[s - 1] : p;
         }
+        // the lane's partial products wait in its own slots during the scan
+        if (valid) aff_store(Gs + 3 * jl, T);
     }
 
-    // segmented inclusive scan of the lane products; code = head flag |
+    // 2. segmented inclusive scan of the lane products; code = head flag |
     // (anchor + 1) << 1 for the segment open at the end of the lane
-    float T[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) T[k] = P[kChainK - 1][k];
     int code = anc[kChainK - 1] == kOpen ? 0 : (1 | ((anc[kChainK - 1] + 1) << 1));
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -454,32 +473,32 @@ __device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseA
 #pragma unroll
     for (int k = 0; k < 12; ++k) X[k] = lane_read(T[k], src);
     const int xa = (__builtin_amdgcn_ds_bpermute(src, code) >> 1) - 1;
-#pragma unroll
-    for (int s = 0; s < kChainK; ++s) {
-        if (anc[s] == kOpen) {
-            aff_mul_left(X, P[s]);
-            anc[s] = xa;
-        }
-    }
 
-    // one composition with each segment anchor's final transform
+    // 3. per joint: the previous lanes' prefix if its segment is open, then
+    // one composition with the segment anchor's final transform
 #pragma unroll
     for (int s = 0; s < kChainK; ++s) {
         const int jl = j0 + s;
-        const bool valid = jl < n;
+        const bool valid = jl < uend;
+        float Pm[12];
+        if (valid) aff_load(Gs + 3 * jl, Pm); else aff_identity(Pm);
+        if (anc[s] == kOpen) {
+            aff_mul_left(X, Pm);
+            anc[s] = xa;
+        }
         wait_block_of(flags, valid ? anc[s] : -1);
         if (valid && anc[s] >= 0) {
             float g[12];
             aff_load(Gs + 3 * anc[s], g);
-            aff_mul_left(g, P[s]);
+            aff_mul_left(g, Pm);
         }
-        if (valid) aff_store(Gs + 3 * jl, P[s]);
+        if (valid) {
+            aff_store(Gs + 3 * jl, Pm);
+            write_skin_and_ckpt(out, td.begin + jl, Pm);
+        }
     }
     publish_blocks(flags, b0, nb, lane);
-    if (out.global_out) store_rows(out, Gs, td.begin, ubase, nb, n, lane);
-#pragma unroll
-    for (int s = 0; s < kChainK; ++s)
-        if (j0 + s < n) write_skin_and_ckpt(out, td.begin + j0 + s, P[s]);
+    if (out.global_out) store_rows<kChainK>(out, Gs, td.begin, ubase, nb, n, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -890,6 +909,95 @@ mp_out_kernel(MPLaunch ml, const float4 *P, OutArgs out)
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint on the multipass path (characters larger than an adjoint tile).
+// The global transforms come from the forward multipass; the adjoint is the
+// reverse pointer jumping of the tiled kernel done over HBM: per round every
+// joint adds S(j) (.) M(j) into its current jump target with global float
+// atomics, while M and the targets double (Wyllie), for ceil(log2 depth)
+// rounds.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kMPWaves * kWave)
+mpb_init_kernel(MPLaunch ml, PoseArgs pose, BwdArgs bwd)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
+    if (w >= ml.num_blocks) return;
+    const MPBlock bd = ml.blocks[w];
+    if (lane >= bd.count) return;
+    const int64_t gid = bd.gbegin + lane;
+    const int64_t cid = bd.cbegin + lane;
+    const int p = ml.parent[gid];
+    float L[12], d[12];
+    load_local<false>(pose, gid, 0, 0, L);
+    aff_store(ml.M[0] + 3 * cid, L);
+    aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, d);
+    aff_store(ml.S[0] + 3 * cid, d);
+    ml.A[0][cid] = p < 0 ? -1 : (int32_t)(p - bd.gbegin + bd.cbegin);
+}
+
+__global__ void __launch_bounds__(256)
+mpb_copy_kernel(int64_t n4, const float4 *src, float4 *dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(256)
+mpb_round_kernel(int64_t nmp, const float4 *S, const float4 *M, const int32_t *A, float4 *Snext, float4 *Mnext,
+                 int32_t *Anext)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmp) return;
+    float m[12];
+    aff_load(M + 3 * i, m);
+    const int a = A[i];
+    if (a >= 0) {
+        float x[12], c[12], g[12];
+        aff_load(S + 3 * i, x);
+        adj_pull(x, m, c);
+        float *dst = reinterpret_cast<float *>(Snext + 3 * (int64_t)a);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) atomicAdd(dst + k, c[k]);
+        aff_load(M + 3 * (int64_t)a, g);
+        aff_mul_left(g, m);
+        Anext[i] = A[a];
+    } else {
+        Anext[i] = -1;
+    }
+    aff_store(Mnext + 3 * i, m);
+}
+
+__global__ void __launch_bounds__(kMPWaves * kWave)
+mpb_grads_kernel(MPLaunch ml, PoseArgs pose, BwdArgs bwd, const float4 *S)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
+    if (w >= ml.num_blocks) return;
+    const MPBlock bd = ml.blocks[w];
+    if (lane >= bd.count) return;
+    const int64_t gid = bd.gbegin + lane;
+    const int64_t cid = bd.cbegin + lane;
+    const int p = ml.parent[gid];
+    float X[12];
+    aff_load(S + 3 * cid, X);
+    float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+    if (p >= 0) {
+        float g[12];
+        aff_load(ml.G + 3 * (p - bd.gbegin + bd.cbegin), g);
+        Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
+        Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
+        Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
+    }
+    const float4 q = reinterpret_cast<const float4 *>(pose.quat)[gid];
+    float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+    if (pose.scale) {
+        const float *sp = pose.scale + 3 * gid;
+        sx = sp[0]; sy = sp[1]; sz = sp[2];
+    }
+    write_grads(bwd, gid, X, Ap, q, sx, sy, sz);
+}
+
+// ---------------------------------------------------------------------------
 // Standalone Simulation step and Bind MeshPose step.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
@@ -1118,10 +1226,43 @@ hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, con
                     : launch_bwd_tiles_w<false>(tl, pose, bwd, stream);
 }
 
-hipError_t launch_backward_multipass(const MPLaunch &, const PoseArgs &, const BwdArgs &,
-                                     float4 *[2], hipStream_t)
+hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, const BwdArgs &bwd,
+                                     hipStream_t stream)
 {
-    return hipErrorNotSupported;
+    if (ml.num_blocks == 0) return hipSuccess;
+    if (!ml.G || !ml.S[0]) return hipErrorNotSupported;
+    const dim3 blk(kMPWaves * kWave);
+    const dim3 grid((ml.num_blocks + kMPWaves - 1) / kMPWaves);
+    const dim3 egrid((unsigned)((ml.nmp + 255) / 256));
+    const dim3 cgrid((unsigned)((3 * ml.nmp + 255) / 256));
+    hipError_t err;
+    // global transforms of the multipass characters, compact layout
+    hipLaunchKernelGGL(mp_local_kernel<false>, grid, blk, 0, stream, ml, pose);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    int cur = 0;
+    for (int r = 0; r < ml.rounds; ++r) {
+        hipLaunchKernelGGL(mp_jump_kernel, egrid, dim3(256), 0, stream, ml.nmp, ml.P[cur], ml.E[cur],
+                           ml.P[cur ^ 1], ml.E[cur ^ 1]);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(mpb_copy_kernel, cgrid, dim3(256), 0, stream, 3 * ml.nmp, ml.P[cur], ml.G);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    // reverse pointer jumping over HBM
+    hipLaunchKernelGGL(mpb_init_kernel, grid, blk, 0, stream, ml, pose, bwd);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    cur = 0;
+    for (int r = 0; r < ml.depth_rounds; ++r) {
+        hipLaunchKernelGGL(mpb_copy_kernel, cgrid, dim3(256), 0, stream, 3 * ml.nmp, ml.S[cur], ml.S[cur ^ 1]);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        hipLaunchKernelGGL(mpb_round_kernel, egrid, dim3(256), 0, stream, ml.nmp, ml.S[cur], ml.M[cur], ml.A[cur],
+                           ml.S[cur ^ 1], ml.M[cur ^ 1], ml.A[cur ^ 1]);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(mpb_grads_kernel, grid, blk, 0, stream, ml, pose, bwd, ml.S[cur]);
+    return hipGetLastError();
 }
+
 
 } // namespace hs

@@ -123,15 +123,25 @@ def test_large_forward_tiles_use_smaller_adjoint_tiles():
     check_grads(b.offsets, run(b, W, tile_joints=3072), oracle_grads(b, W), "3072-joint forward tiles")
 
 
-def test_characters_beyond_adjoint_tile_are_rejected():
-    n = 3000
-    par = np.arange(-1, n - 1, dtype=np.int32)
+@pytest.mark.parametrize("shape", [dict(), dict(strategy=hs.HS_STRATEGY_MULTIPASS)])
+def test_multipass_adjoint_for_large_characters(shape):
+    """Characters beyond the adjoint tile (a 3000-joint chain, a 5000-joint
+    random tree) next to small ones go through the multipass adjoint."""
     rng = np.random.default_rng(1)
-    q, t, s = wl.random_pose(rng, n)
-    b = wl.Batch("chain", np.array([0, n], np.int64), par, q, t, s, q, t, s)
-    with pytest.raises(hs.HSError) as ei:
-        run(b, np.zeros((n, 4, 4), np.float32))
-    assert ei.value.status == hs.HS_ERR_UNSUPPORTED
+    chain = np.arange(-1, 2999, dtype=np.int32)
+    tree = np.empty(5000, np.int32)
+    tree[0] = -1
+    for j in range(1, 5000):
+        tree[j] = j - 1 if rng.uniform() < 0.8 else rng.integers(0, j)
+    small = wl.plain_scan(num_characters=3).parents
+    parts = [chain, small, tree]
+    par = np.concatenate(parts)
+    off = np.array([0, 3000, 3000 + 64, 3000 + 128, 3000 + 192, 3000 + 192 + 5000], np.int64)
+    q, t, s = wl.random_pose(rng, par.size, max_angle=0.1)
+    s = rng.uniform(0.9, 1.1, s.shape).astype(np.float32)
+    b = wl.Batch("big", off, par, q, t, s, q, t, s)
+    W = rng.standard_normal((par.size, 4, 4)).astype(np.float32) * 0.1
+    check_grads(b.offsets, run(b, W, **shape), oracle_grads(b, W), f"multipass adjoint {shape}")
 
 
 def test_autograd_matches_oracle_in_both_modes():
