@@ -52,7 +52,7 @@ BYTES_PER_JOINT = {
     # grad_quat 16 + grad_trans 12
     "differentiable": 136,
 }
-DOMINANT = {"differentiable": "bwd_tile_kernel"}
+DOMINANT = {"differentiable": "bwd_sync_kernel"}
 
 
 def kernel_source_sha():
@@ -254,7 +254,7 @@ def main():
 
     fwd_ms, bwd_ms = w.mean_ms(w.fwd_ev), w.mean_ms(w.bwd_ev)
     dominant = DOMINANT.get(args.workload, "fwd_tile_kernel")
-    kernel_ms = bwd_ms if dominant == "bwd_tile_kernel" else fwd_ms
+    kernel_ms = bwd_ms if dominant.startswith("bwd") else fwd_ms
     bytes_per_launch = N * BYTES_PER_JOINT[args.workload]
     if args.workload == "fused_sample":
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
@@ -321,7 +321,7 @@ def cpu_baseline(w):
         G, tr = run()
         reps += 1
         wall = time.perf_counter() - t0
-        if wall >= 10.0 or reps >= 50:
+        if wall >= 10.0 or reps >= 2000:
             break
     what = "forward + adjoint" if name == "differentiable" else "forward"
     base = {"value": N * reps / wall, "unit": "joint transforms/s", "cores": cores, "kind": "oracle",

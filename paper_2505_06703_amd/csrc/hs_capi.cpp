@@ -167,10 +167,13 @@ struct hs_plan {
     int32_t *d_level = nullptr;
     TileDesc *d_tiles = nullptr;
     std::vector<TileDesc> h_tiles;
-    // adjoint tiles (NULL: the forward tiles are used)
+    // adjoint tiles: characters of up to 1024 joints (synchronous-round
+    // kernel) and larger ones up to the dataflow kernel's limit
     TileDesc *d_btiles = nullptr;
     int32_t num_btiles = 0;
     int32_t bwd_cap = 0;
+    TileDesc *d_bbig = nullptr;
+    int32_t num_bbig = 0;
     int64_t bwd_untiled = 0;  // joints the adjoint's tiles do not cover
     int32_t max_units = 0;
     // multipass: characters larger than the forward tile (mp) and than the
@@ -189,6 +192,7 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_level);
     (void)hipFree(p->d_tiles);
     (void)hipFree(p->d_btiles);
+    (void)hipFree(p->d_bbig);
     free_mpset(p->mp);
     free_mpset(p->bmp);
     delete p;
@@ -281,8 +285,11 @@ struct Packing {
 };
 
 // Pack whole characters, in order, into tiles of at most `cap` joints; the
-// characters that do not fit go to the multipass path.
-Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units)
+// characters that do not fit go to the multipass path.  Only characters of
+// lo..hi joints are taken; the others are left out (another packing covers
+// them).
+Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units, int64_t lo = 0,
+                   int64_t hi = INT64_MAX)
 {
     const int64_t C = plan->C;
     const auto &off = plan->h_offsets;
@@ -295,17 +302,24 @@ Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units)
     TileDesc cur{};
     bool open = false;
     int cur_chain = 0;
+    int32_t cur_level = 1;
     auto flush = [&]() {
         if (open && cur.count > 0) {
+            cur.rounds = ceil_log2(cur_level);
             tiles.push_back(cur);
             tile_cost.push_back((int64_t)cur.count + 48 * (int64_t)cur_chain);
             pk.max_chain_tiles = std::max(pk.max_chain_tiles, cur_chain);
         }
         open = false;
         cur_chain = 0;
+        cur_level = 1;
     };
     for (int64_t c = 0; c < C; ++c) {
         const int64_t n = off[c + 1] - off[c];
+        if (n < lo || n > hi) {
+            flush();  // tiles are contiguous id ranges
+            continue;
+        }
         const bool to_mp = strategy == HS_STRATEGY_MULTIPASS || n > cap;
         if (to_mp) {
             flush();
@@ -341,6 +355,7 @@ Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units)
         if (n > 0) {
             const int L = block_chain_length(par.data() + off[c], n, cur.count, top, chain);
             cur_chain = std::max(cur_chain, L);
+            for (int64_t j = off[c]; j < off[c + 1]; ++j) cur_level = std::max(cur_level, plan->h_level[j]);
         }
         cur.count += (int32_t)n;
         cur.num_chars += 1;
@@ -398,20 +413,31 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     const int64_t nmp = pk.nmp, tiled = pk.tiled;
     const int max_chain_tiles = pk.max_chain_tiles, max_chain_mp = pk.max_chain_mp;
 
-    // the adjoint keeps twice as much per joint in LDS: it gets its own,
-    // smaller tiles when the forward tiles are too large for it
+    // The adjoint gets tiles of its own.  Characters of up to 1024 joints go
+    // to the synchronous-round kernel, on tiles of 512 joints unless a
+    // larger character needs more (smaller tiles keep several workgroups per
+    // CU); characters of up to 1664 joints to the dataflow kernel; the rest
+    // to the multipass adjoint.
     (void)hipFree(plan->d_btiles);
-    plan->d_btiles = nullptr;
-    plan->bwd_cap = std::min(cap, hs::kMaxBwdTileJoints);
+    (void)hipFree(plan->d_bbig);
+    plan->d_btiles = plan->d_bbig = nullptr;
+    plan->num_btiles = plan->num_bbig = 0;
     {
-        Packing pb = plan->bwd_cap < cap ? pack_tiles(plan, plan->bwd_cap, strategy, false) : pk;
-        if (plan->bwd_cap < cap) {
-            plan->num_btiles = (int32_t)pb.tiles.size();
-            hipError_t e2 = upload(&plan->d_btiles, pb.tiles);
-            if (e2 != hipSuccess) return fail_hip(e2, "hs_plan_create");
-        } else {
-            plan->num_btiles = (int32_t)sorted.size();
+        int64_t m_sync = 0;
+        for (int64_t c = 0; c < plan->C; ++c) {
+            const int64_t n = plan->h_offsets[c + 1] - plan->h_offsets[c];
+            if (n <= hs::kMaxSyncTileJoints) m_sync = std::max(m_sync, n);
         }
+        plan->bwd_cap = std::max(512, round_up((int)m_sync, 64));
+        const bool mp_all = strategy == HS_STRATEGY_MULTIPASS;
+        Packing ps, pb;
+        if (!mp_all) ps = pack_tiles(plan, plan->bwd_cap, strategy, false, 0, hs::kMaxSyncTileJoints);
+        pb = pack_tiles(plan, hs::kMaxBwdTileJoints, strategy, false, mp_all ? 0 : hs::kMaxSyncTileJoints + 1);
+        plan->num_btiles = (int32_t)ps.tiles.size();
+        plan->num_bbig = (int32_t)pb.tiles.size();
+        hipError_t e2 = upload(&plan->d_btiles, ps.tiles);
+        if (e2 == hipSuccess) e2 = upload(&plan->d_bbig, pb.tiles);
+        if (e2 != hipSuccess) return fail_hip(e2, "hs_plan_create");
         plan->bwd_untiled = pb.nmp;
         int max_level = 1;
         for (const MPBlock &mb : pb.mpb)
@@ -585,7 +611,7 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     hipError_t err;
     if ((err = hipMalloc(&q, N * 16)) != hipSuccess || (err = hipMalloc(&t, N * 12)) != hipSuccess ||
         (err = hipMalloc(&G, N * 64)) != hipSuccess) {
-        (void)(void)hipFree(q); (void)hipFree(t); (void)hipFree(G);
+        (void)hipFree(q); (void)hipFree(t); (void)hipFree(G);
         return fail_hip(err, "hs_plan_create (autotune scratch)");
     }
     // identity rotations, zero offsets: values do not affect the timing
@@ -604,25 +630,36 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     pa.trans = t;
     hs::OutArgs oa{};
     oa.global_out = G;
-    Shape best = base;
-    float best_ms = 1e30f;
-    hs_status rc = HS_OK;
-    for (const Shape &sh : cands) {
-        if ((rc = build_tables(plan, sh, strategy)) != HS_OK) break;
-        float ms_sum = 0.0f;
-        bool ok = true;
-        for (int it = 0; it < 4 && ok; ++it) {
+    // median of 10 timed runs after 3 warm-up runs per candidate; the
+    // default shape (timed first) is kept unless a candidate beats it by 3%
+    auto time_shape = [&](const Shape &sh, float &ms_out) -> hs_status {
+        hs_status rc2 = build_tables(plan, sh, strategy);
+        if (rc2 != HS_OK) return rc2;
+        std::vector<float> ms;
+        for (int it = 0; it < 13; ++it) {
             (void)hipEventRecord(e0, s);
-            ok = run_forward(plan, pa, oa, s) == HS_OK;
+            rc2 = run_forward(plan, pa, oa, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (it > 0) ms_sum += ms;  // first run warms up
+            if (rc2 != HS_OK) return rc2;
+            float m = 0.0f;
+            (void)hipEventElapsedTime(&m, e0, e1);
+            if (it >= 3) ms.push_back(m);
         }
-        if (ok && ms_sum < best_ms) {
-            best_ms = ms_sum;
-            best = sh;
+        std::sort(ms.begin(), ms.end());
+        ms_out = ms[ms.size() / 2];
+        return HS_OK;
+    };
+    Shape best = base;
+    float best_ms = 1e30f;
+    hs_status rc = time_shape(base, best_ms);
+    const float default_ms = best_ms;
+    for (size_t i = 0; rc == HS_OK && i < cands.size(); ++i) {
+        float ms = 0.0f;
+        if ((rc = time_shape(cands[i], ms)) != HS_OK) break;
+        if (ms < best_ms && ms < 0.97f * default_ms) {
+            best_ms = ms;
+            best = cands[i];
         }
     }
     (void)hipEventDestroy(e0);
@@ -993,18 +1030,25 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_backward: cannot select device");
     hs::TileLaunch tl = tile_launch(plan);
-    if (plan->d_btiles) {
+    tl.chain_units = 0;
+    hipError_t err = hipSuccess;
+    if (plan->num_btiles > 0) {
         tl.tiles = plan->d_btiles;
         tl.num_tiles = plan->num_btiles;
         tl.tile_cap = plan->bwd_cap;
-        tl.waves = std::min(tl.waves, plan->bwd_cap / 64);
-        tl.grid = plan->shape.grid_per_cu > 0
-                      ? std::min<int32_t>(plan->num_btiles, plan->shape.grid_per_cu * plan->ctx->num_cu)
-                      : plan->num_btiles;
-        tl.grid = std::max(1, tl.grid);
+        tl.grid = plan->num_btiles;
+        err = hs::launch_backward_tiles(tl, pa, ba, stream);
+        if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
     }
-    hipError_t err = hs::launch_backward_tiles(tl, pa, ba, stream);
-    if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
+    if (plan->num_bbig > 0) {
+        tl.tiles = plan->d_bbig;
+        tl.num_tiles = plan->num_bbig;
+        tl.tile_cap = hs::kMaxBwdTileJoints;
+        tl.waves = 16;
+        tl.grid = plan->num_bbig;
+        err = hs::launch_backward_tiles(tl, pa, ba, stream);
+        if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (large tiles)");
+    }
     err = hs::launch_backward_multipass(mp_launch(plan, plan->bmp), pa, ba, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (multipass)");
     return HS_OK;

@@ -11,9 +11,15 @@ namespace hs {
 // including the per-character table of the fused sampler.
 constexpr int kMaxTileJoints = 3072;
 
-// Largest tile of the adjoint kernel, which keeps both the global transforms
-// and the adjoint accumulators of the tile in LDS (96 bytes per joint).
+// Largest tile of the dataflow adjoint kernel, which keeps both the global
+// transforms and the adjoint accumulators of the tile in LDS (96 bytes per
+// joint).
 constexpr int kMaxBwdTileJoints = 1664;
+
+// Largest tile of the synchronous-round adjoint kernel: one joint per
+// thread, 104 bytes of LDS per joint (jump product, accumulator, pointer,
+// owner word).
+constexpr int kMaxSyncTileJoints = 1024;
 
 // A tile: a contiguous range of global joint ids holding whole characters,
 // scanned by one workgroup entirely in LDS.
@@ -26,7 +32,9 @@ struct TileDesc {
     // at block b (every parent in it is the previous joint or before it)
     int32_t chain_lo;
     int32_t chain_hi;
-    int32_t pad;
+    // pointer-jumping rounds that cover the deepest joint of the tile:
+    // ceil(log2(max level)), the root at level 1
+    int32_t rounds;
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
 
@@ -125,5 +133,6 @@ hipError_t prepare_kernels();
 // LDS bytes one tiled-forward workgroup needs.
 size_t forward_tile_lds_bytes(int tile_cap, bool sample);
 size_t backward_tile_lds_bytes(int tile_cap);
+size_t backward_sync_lds_bytes(int tile_cap);
 
 } // namespace hs

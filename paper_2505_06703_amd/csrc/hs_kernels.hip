@@ -39,6 +39,7 @@
 
 #include "hs_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace hs {
@@ -835,6 +836,128 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint of the scan (tiled), recompute mode: tile-wide synchronous rounds.
+//
+// Every joint keeps, in registers, its partial adjoint S and the jump
+// product M of the forward doubling; LDS holds M (for the jump targets), the
+// adjoint accumulators and the jump pointers.  Round r moves S_r(j) (.) M_r(j)
+// from each joint j to its jump target a = anc_r(j), while the forward
+// doubling forms M_{r+1}(j) = M_r(a) M_r(j) and anc_{r+1}(j) = anc_r(a).
+// After ceil(log2 L) rounds (L: deepest level of the tile, from the tile
+// descriptor) S is the total adjoint X_j and M = G_j.  No block waits for
+// later blocks' work, so the rounds of all joints of the tile run side by
+// side.
+//
+// Several joints can push to one target in a round (the descendants of a
+// at distance 2^r).  LDS float atomics are slow, so they are kept for
+// those collisions only: every pusher first stores its id into the
+// target's owner word (plain stores, one of them lands); the owner adds its
+// contribution with a plain read-modify-write, the others with atomics one
+// barrier later.  Owner words carry the round (id | r << 10), which also
+// tells a joint whether anything arrived for it this round.
+// LDS: M[cap][3] float4 | accumulators[cap][3] float4 | anc[cap] | owner[cap]
+// ---------------------------------------------------------------------------
+constexpr int kOwnerShift = 10;  // tile-local ids < 1024
+
+__device__ __forceinline__ void owner_claim(int *w, int v)
+{
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int owner_read(const int *w)
+{
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(WAVES * kWave)
+bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
+{
+    extern __shared__ float4 lds[];
+    const int cap = tl.tile_cap;
+    float4 *Ms = lds;
+    float4 *Sa = lds + 3 * cap;
+    int *Ac = reinterpret_cast<int *>(lds + 6 * cap);
+    int *Own = Ac + cap;
+    const int jl = threadIdx.x;
+
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        const bool live = jl < td.count;
+        const int64_t gid = td.begin + jl;
+        float M[12], S[12];
+        int a = -1, p = -1;
+        if (live) {
+            p = tl.parent[gid];
+            a = p < 0 ? -1 : (int)(p - td.begin);
+            load_local<false>(pose, gid, 0, 0, M);
+            aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
+            aff_store(Ms + 3 * jl, M);
+            aff_store(Sa + 3 * jl, S);
+            Ac[jl] = a;
+            owner_claim(Own + jl, -1);
+        }
+        __syncthreads();
+        if (a >= 0) owner_claim(Own + a, jl);
+        // the trip count comes from the tile descriptor, so it is uniform
+        // across the workgroup and every wave meets the same barriers
+        for (int r = 0; r < td.rounds; ++r) {
+            __syncthreads();  // claims, products and pointers of round r
+            const int tag = r << kOwnerShift;
+            int aa = -1;
+            bool lose = false;
+            float c[12];
+            if (a >= 0) {
+                adj_pull(S, M, c);
+                lose = owner_read(Own + a) != (tag | jl);
+                if (!lose) {
+                    float acc[12];
+                    aff_load(Sa + 3 * a, acc);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) acc[k] += c[k];
+                    aff_store(Sa + 3 * a, acc);
+                }
+                float ma[12];
+                aff_load(Ms + 3 * a, ma);
+                aa = Ac[a];
+                aff_mul_left(ma, M);  // published after the barriers
+            }
+            __syncthreads();
+            if (lose) lds_atomic_add12(Sa + 3 * a, c);
+            const bool recv = live && (owner_read(Own + jl) >> kOwnerShift) == r;
+            __syncthreads();
+            if (recv) aff_load(Sa + 3 * jl, S);
+            if (a >= 0) {
+                a = aa;
+                aff_store(Ms + 3 * jl, M);
+                Ac[jl] = a;
+                if (a >= 0) owner_claim(Own + a, (tag + (1 << kOwnerShift)) | jl);
+            }
+        }
+        __syncthreads();
+        // M = G_j and S = X_j now; the gradients need the parent's G
+        if (live) {
+            float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+            if (p >= 0) {
+                float g[12];
+                aff_load(Ms + 3 * (int)(p - td.begin), g);
+                Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
+                Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
+                Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
+            }
+            const float4 q = reinterpret_cast<const float4 *>(pose.quat)[gid];
+            float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+            if (pose.scale) {
+                const float *sp = pose.scale + 3 * gid;
+                sx = sp[0]; sy = sp[1]; sz = sp[2];
+            }
+            write_grads(bwd, gid, S, Ap, q, sx, sy, sz);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Multipass path.
 // ---------------------------------------------------------------------------
 constexpr int kMPWaves = 4;
@@ -1102,7 +1225,9 @@ hipError_t set_lds_limits()
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bwd);
         if (err != hipSuccess) return err;
     }
-    return hipSuccess;
+    const int bs = (int)backward_sync_lds_bytes(std::min(kMaxSyncTileJoints, WAVES * kWave));
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bs);
 }
 
 } // namespace
@@ -1188,6 +1313,11 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
     return hipGetLastError();
 }
 
+size_t backward_sync_lds_bytes(int tile_cap)
+{
+    return (size_t)tile_cap * 104;
+}
+
 size_t backward_tile_lds_bytes(int tile_cap)
 {
     return (size_t)tile_cap * 96 + (size_t)(tile_cap / kWave) * 12;
@@ -1217,13 +1347,36 @@ hipError_t launch_bwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const 
     }
 }
 
+template <int WAVES>
+hipError_t launch_bwd_sync_w(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd, hipStream_t stream)
+{
+    if (tl.tile_cap > WAVES * kWave) return hipErrorInvalidValue;
+    const size_t lds = backward_sync_lds_bytes(tl.tile_cap);
+    hipLaunchKernelGGL((bwd_sync_kernel<WAVES>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, bwd);
+    return hipGetLastError();
+}
+
 hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
                                  hipStream_t stream)
 {
     if (tl.num_tiles == 0) return hipSuccess;
     if (tl.tile_cap > kMaxBwdTileJoints) return hipErrorInvalidValue;
-    return bwd.ckpt ? launch_bwd_tiles_w<true>(tl, pose, bwd, stream)
-                    : launch_bwd_tiles_w<false>(tl, pose, bwd, stream);
+    if (tl.tile_cap > kMaxSyncTileJoints)
+        return bwd.ckpt ? launch_bwd_tiles_w<true>(tl, pose, bwd, stream)
+                        : launch_bwd_tiles_w<false>(tl, pose, bwd, stream);
+    // tiles of up to 1024 joints: one joint per thread; the jump products
+    // give every G_j on chip, so checkpoints are not read here
+    TileLaunch t2 = tl;
+    t2.waves = 1;
+    while (t2.waves < 16 && t2.tile_cap > kWave * t2.waves) t2.waves *= 2;
+    switch (t2.waves) {
+    case 1: return launch_bwd_sync_w<1>(t2, pose, bwd, stream);
+    case 2: return launch_bwd_sync_w<2>(t2, pose, bwd, stream);
+    case 4: return launch_bwd_sync_w<4>(t2, pose, bwd, stream);
+    case 8: return launch_bwd_sync_w<8>(t2, pose, bwd, stream);
+    case 16: return launch_bwd_sync_w<16>(t2, pose, bwd, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, const BwdArgs &bwd,

@@ -104,8 +104,10 @@ def test_plain_scan_trees_and_star():
     assert got[2] is None
 
 
-@pytest.mark.parametrize("n", [1, 64, 65, 1000, 1664])
+@pytest.mark.parametrize("n", [1, 64, 65, 1000, 1024, 1025, 1664])
 def test_chains(n):
+    """Chains up to 1024 joints take the synchronous-round tiles, longer
+    ones (to 1664) the dataflow tiles, in both memory modes."""
     rng = np.random.default_rng(n)
     par = np.arange(-1, n - 1, dtype=np.int32)
     q, t, s = wl.random_pose(rng, n, max_angle=0.1)
@@ -113,7 +115,28 @@ def test_chains(n):
     W = np.zeros((n, 4, 4), np.float32)
     W[-1, :3, 3] = rng.standard_normal(3)
     W[n // 2, :3, :3] = rng.standard_normal((3, 3))
-    check_grads(b.offsets, run(b, W), oracle_grads(b, W), f"chain {n}")
+    ref = oracle_grads(b, W)
+    check_grads(b.offsets, run(b, W), ref, f"chain {n}")
+    check_grads(b.offsets, run(b, W, ckpt_k=4), ref, f"chain {n} ckpt 4")
+
+
+@pytest.mark.parametrize("n", [1024, 1025])
+def test_stars_and_brooms_collide_on_one_target(n):
+    """Every joint of a star pushes to the root in one round; a broom (a
+    chain whose last joint fans out) sends ever more joints to one target as
+    the jump distance grows."""
+    rng = np.random.default_rng(n + 1)
+    star = np.zeros(n, np.int32)
+    star[0] = -1
+    broom = np.arange(-1, n - 1, dtype=np.int32)
+    broom[300:] = 299
+    broom[600:] = np.arange(300, n - 300) - 1 + 300
+    par = np.concatenate([star, broom])
+    off = np.array([0, n, 2 * n], np.int64)
+    q, t, s = wl.random_pose(rng, par.size, max_angle=0.2)
+    b = wl.Batch("star", off, par, q, t, s, q, t, s)
+    W = rng.standard_normal((par.size, 4, 4)).astype(np.float32)
+    check_grads(b.offsets, run(b, W), oracle_grads(b, W), f"star/broom {n}")
 
 
 def test_large_forward_tiles_use_smaller_adjoint_tiles():
