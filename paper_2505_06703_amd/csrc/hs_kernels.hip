@@ -280,7 +280,8 @@ __device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t 
 
 // ---------------------------------------------------------------------------
 // Tiled forward kernel.
-// LDS: G[cap][3] float4 | block flags [cap/64] int | (SAMPLE) char starts [cap+1]
+// LDS: G[cap][3] float4 | unit partials [cap/64][3] float4 | block flags,
+// partial flags, partial anchors [cap/64] int | (SAMPLE) char starts [cap+1]
 // ---------------------------------------------------------------------------
 // Bounded wait until the block of tile-local joint e (if e >= 0) has
 // published its final transforms.  The bound only guards against a broken
@@ -296,6 +297,50 @@ __device__ __forceinline__ void wait_block_of(const int *flags, int e)
         __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// LDS of the tiled forward kernel.
+struct FwdShared {
+    float4 *G;       // [cap][3] final transforms (rows 0-2)
+    float4 *part;    // [cap/64][3] partial product of a chain unit's last segment
+    int *flags;      // [cap/64] block published its final transforms
+    int *pflag;      // [cap/64] partial of the unit ending with this block published
+    int *panc;       // [cap/64] anchor of that partial (tile-local id, or -1)
+    int *cstart;     // (pose sampling) character starts
+};
+
+// m <- G_e m for tile-local joint e (no-op for e < 0), waiting (bounded, as
+// above) until e's transform is known: either e's block has published, or
+// e ends a chain unit that has published the partial product P of its last
+// segment, in which case G_e = G_a P with a the segment's anchor, and the
+// wait moves on to a.  Partials let a unit start as soon as the earlier
+// unit's scan is done instead of after its final pass.
+__device__ __forceinline__ void compose_final(const FwdShared &sh, int e, float m[12])
+{
+    for (int spin = 0; spin < kSpinLimit; ++spin) {
+        if (__all(e < 0)) break;
+        int fin = 0, step = 0;
+        if (e >= 0) {
+            const int be = e >> 6;
+            fin = __hip_atomic_load(sh.flags + be, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (!fin && (e & (kWave - 1)) == kWave - 1)
+                step = __hip_atomic_load(sh.pflag + be, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (fin) {
+            float g[12];
+            aff_load(sh.G + 3 * e, g);
+            aff_mul_left(g, m);
+            e = -1;
+        } else if (step) {
+            const int be = e >> 6;
+            float pp[12];
+            aff_load(sh.part + 3 * be, pp);
+            aff_mul_left(pp, m);
+            e = sh.panc[be];
+        }
+        if (!__any(fin | step)) __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 // Publish blocks [b0, b0 + nb) of the tile: their final transforms are in LDS.
@@ -342,11 +387,15 @@ __device__ __forceinline__ void char_of(const TileDesc &td, const int *cstart, i
 // One 64-joint block: in-block pointer jumping across the wave, then one
 // composition with the final transform of the nearest out-of-block
 // ancestor once its block has published it.
+// One 64-joint block: in-block pointer jumping across the wave, then one
+// composition with the final transform of the nearest out-of-block
+// ancestor once its block has published it.
 template <bool SAMPLE>
 __device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
-                                          const TileDesc &td, int n, int b, float4 *Gs, int *flags,
-                                          const int *cstart, int lane)
+                                          const TileDesc &td, int n, int b, const FwdShared &sh, int lane)
 {
+    float4 *Gs = sh.G;
+    const int *cstart = sh.cstart;
     const int base = b * kWave;
     const int jl = base + lane;
     const bool valid = jl < n;
@@ -364,93 +413,124 @@ __device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &
         aff_identity(m);
     }
     wave_inblock_scan(m, a, e, lane);
-    wait_block_of(flags, valid ? e : -1);
+    wait_block_of(sh.flags, valid ? e : -1);
     if (valid && e >= 0) {
         float g[12];
         aff_load(Gs + 3 * e, g);
         aff_mul_left(g, m);
     }
     if (valid) aff_store(Gs + 3 * jl, m);
-    publish_blocks(flags, b, 1, lane);
+    publish_blocks(sh.flags, b, 1, lane);
     if (out.global_out) store_rows<1>(out, Gs, td.begin, base, 1, n, lane);
     if (valid) write_skin_and_ckpt(out, gid, m);
+}
+
+// The K local transforms of unit joints [i0, i0 + K) from the
+// component-major staging area (stride S).  Lanes that own no joints read
+// the first K slots instead; their values are never stored.
+template <int K>
+__device__ __forceinline__ void read_staged(const float *stage, int S, int i0, bool owns, float L[K][12])
+{
+    static_assert(K == 4, "one float4 per component");
+    const int i = owns ? i0 : 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const float4 v = *reinterpret_cast<const float4 *>(stage + k * S + i);
+        L[0][k] = v.x;
+        L[1][k] = v.y;
+        L[2][k] = v.z;
+        L[3][k] = v.w;
+    }
 }
 
 // A chain unit: kChainK * 64 consecutive joints (up to kChainK blocks) in
 // which every joint's parent is either the previous joint or lies before
 // the unit, i.e. the unit is a set of contiguous chain segments.  Lane l
 // owns joints [kChainK l, kChainK l + kChainK) of the unit:
-//   1. sequential products inside the lane (kChainK - 1 compositions);
-//   2. a segmented scan of the lane products across the wave (log2 64
-//      rounds, restarting at segment heads), carrying each segment's
-//      out-of-unit anchor;
-//   3. one composition per joint with the prefix of the previous lanes,
-//      and one with the anchor's final transform.
-// About 4 compositions per joint instead of 6 + 1 for a 64-deep block.
+//   1. the lane's local transforms arrive through LDS (loaded coalesced,
+//      staged component-major so that both the staging writes and each
+//      lane's 16-byte reads of its kChainK joints are free of bank
+//      conflicts) and stay in registers;
+//   2. the product of the lane's open segment (kChainK - 1 compositions);
+//   3. a segmented scan of those products across the wave (log2 64 rounds,
+//      restarting at segment heads), carrying each segment's out-of-unit
+//      anchor;
+//   4. the transform preceding the lane's first joint (anchor's final
+//      transform times the previous lanes' prefix, one composition), then
+//      one composition per joint, in order.
+// About 3.5 compositions per joint instead of 6 + 1 for a 64-deep block.
 constexpr int kChainK = 4;
 
 template <bool SAMPLE>
 __device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
-                                               const TileDesc &td, int n, int b0, int nb, float4 *Gs,
-                                               int *flags, const int *cstart, int lane)
+                                               const TileDesc &td, int n, int b0, int nb, const FwdShared &sh,
+                                               int lane)
 {
+    float4 *Gs = sh.G;
+    const int *cstart = sh.cstart;
     const int ubase = b0 * kWave;
-    const int uend = min(ubase + nb * kWave, n);  // the unit's joints are [ubase, uend)
-    const int j0 = ubase + lane * kChainK;
+    const int S = nb * kWave;  // joints the unit spans; the staging stride
+    float *stage = reinterpret_cast<float *>(Gs + 3 * ubase);  // 12 * S floats, the unit's own slots
 
-    // Local transforms, loaded coalesced (lane = joint within each block) and
-    // staged in the unit's own LDS slots, which hold nothing else yet.
+    // 1. staging: component k of unit joint i at stage[k * S + i]
 #pragma unroll
     for (int s = 0; s < kChainK; ++s) {
-        const int jl = ubase + s * kWave + lane;
-        if (jl < uend) {
+        if (s >= nb) break;
+        const int i = s * kWave + lane;
+        const int jl = ubase + i;
+        float L[12];
+        if (jl < n) {
             int chr, lj;
             char_of<SAMPLE>(td, cstart, jl, chr, lj);
-            float L[12];
             load_local<SAMPLE>(pose, td.begin + jl, chr, lj, L);
-            aff_store(Gs + 3 * jl, L);
+        } else {
+            aff_identity(L);
         }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) stage[k * S + i] = L[k];
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // 1. sequential products over the lane's kChainK consecutive joints.
-    // anchor of each joint's segment: tile-local id before the unit, -1 for
-    // a root, or kOpen when the segment continues from the previous lane.
+    const int i0 = kChainK * lane;
+    const bool owns = i0 < S;
+    // the lane's local transforms are read again after the scan (the
+    // staging slots stay intact until step 4 writes) to keep register use low
+    // 2. product of the lane's open segment.  anc: tile-local anchor of each
+    // joint's segment (parent before the unit, or -1 for a root), or kOpen
+    // while the segment continues from the previous lane.
     constexpr int kOpen = -2;
-    int anc[kChainK];
+    bool valid[kChainK], head[kChainK];
+    int par[kChainK], anc[kChainK];
     float T[12];
+    float L[kChainK][12];
+    read_staged<kChainK>(stage, S, i0, owns, L);
 #pragma unroll
     for (int s = 0; s < kChainK; ++s) {
-        const int jl = j0 + s;
-        const bool valid = jl < uend;
-        float L[12];
+        const int jl = ubase + i0 + s;
+        valid[s] = owns && jl < n;
         int p = -1;
-        if (valid) {
+        if (valid[s]) {
             const int pg = tl.parent[td.begin + jl];
             p = pg < 0 ? -1 : (int)(pg - td.begin);
-            aff_load(Gs + 3 * jl, L);
-        } else {
-            aff_identity(L);
         }
-        const bool cont = valid && p == jl - 1 && p >= ubase;
+        par[s] = p;
+        head[s] = !(valid[s] && p == jl - 1 && p >= ubase);
         if (s == 0) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k) T[k] = L[k];
-            anc[0] = cont ? kOpen : p;
+            for (int k = 0; k < 12; ++k) T[k] = L[0][k];
+            anc[0] = head[0] ? p : kOpen;
         } else {
             float o[12];
-            aff_mul(T, L, o);
+            aff_mul(T, L[s], o);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) T[k] = cont ? o[k] : L[k];
-            anc[s] = cont ? anc[s - 1] : p;
+            for (int k = 0; k < 12; ++k) T[k] = head[s] ? L[s][k] : o[k];
+            anc[s] = head[s] ? p : anc[s - 1];
         }
-        // the lane's partial products wait in its own slots during the scan
-        if (valid) aff_store(Gs + 3 * jl, T);
     }
 
-    // 2. segmented inclusive scan of the lane products; code = head flag |
+    // 3. segmented inclusive scan of the lane products; code = head flag |
     // (anchor + 1) << 1 for the segment open at the end of the lane
     int code = anc[kChainK - 1] == kOpen ? 0 : (1 | ((anc[kChainK - 1] + 1) << 1));
 #pragma unroll
@@ -467,44 +547,57 @@ __device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseA
         for (int k = 0; k < 12; ++k) T[k] = need ? o[k] : T[k];
         code = need ? ca : code;
     }
-    // prefix of the segment open at the start of the lane: the inclusive
-    // result of the previous lane (lane 0 always starts with a head)
-    const int src = (lane > 0 ? lane - 1 : 0) << 2;
-    float X[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) X[k] = lane_read(T[k], src);
-    const int xa = (__builtin_amdgcn_ds_bpermute(src, code) >> 1) - 1;
 
-    // 3. per joint: the previous lanes' prefix if its segment is open, then
-    // one composition with the segment anchor's final transform
+    // the partial product of the segment open at the unit's last joint
+    // lets the next unit go ahead before this one finishes
+    const int last = S / kChainK - 1;
+    if (lane == last && ubase + S <= n) {
+        const int bl = b0 + nb - 1;
+        aff_store(sh.part + 3 * bl, T);
+        sh.panc[bl] = (code >> 1) - 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __hip_atomic_store(sh.pflag + bl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    // 4. the transform before the lane's first joint: the previous lane's
+    // inclusive prefix (lane 0 always starts with a head) behind its anchor
+    const int src = (lane > 0 ? lane - 1 : 0) << 2;
+    float pre[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) pre[k] = lane_read(T[k], src);
+    const int xa = (__builtin_amdgcn_ds_bpermute(src, code) >> 1) - 1;
+    const bool open = owns && anc[0] == kOpen;
+    compose_final(sh, open ? xa : -1, pre);
+    read_staged<kChainK>(stage, S, i0, owns, L);
 #pragma unroll
     for (int s = 0; s < kChainK; ++s) {
-        const int jl = j0 + s;
-        const bool valid = jl < uend;
-        float Pm[12];
-        if (valid) aff_load(Gs + 3 * jl, Pm); else aff_identity(Pm);
-        if (anc[s] == kOpen) {
-            aff_mul_left(X, Pm);
-            anc[s] = xa;
-        }
-        wait_block_of(flags, valid ? anc[s] : -1);
-        if (valid && anc[s] >= 0) {
+        const bool h = valid[s] && head[s];
+        if (h) aff_identity(pre);
+        compose_final(sh, h ? par[s] : -1, pre);
+        float o[12];
+        aff_mul(pre, L[s], o);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) pre[k] = o[k];
+        if (valid[s]) aff_store(Gs + 3 * (ubase + i0 + s), pre);
+    }
+    if (out.skin_out || out.ckpt) {
+#pragma unroll 1
+        for (int s = 0; s < kChainK; ++s) {
+            const int jl = ubase + i0 + s;
+            if (!owns || jl >= n) break;
             float g[12];
-            aff_load(Gs + 3 * anc[s], g);
-            aff_mul_left(g, Pm);
-        }
-        if (valid) {
-            aff_store(Gs + 3 * jl, Pm);
-            write_skin_and_ckpt(out, td.begin + jl, Pm);
+            aff_load(Gs + 3 * jl, g);
+            write_skin_and_ckpt(out, td.begin + jl, g);
         }
     }
-    publish_blocks(flags, b0, nb, lane);
+    publish_blocks(sh.flags, b0, nb, lane);
     if (out.global_out) store_rows<kChainK>(out, Gs, td.begin, ubase, nb, n, lane);
 }
 
 // ---------------------------------------------------------------------------
 // Tiled forward kernel.
-// LDS: G[cap][3] float4 | block flags [cap/64] int | (SAMPLE) char starts [cap+1]
+// LDS: G[cap][3] float4 | unit partials [cap/64][3] float4 | block flags,
+// partial flags, partial anchors [cap/64] int | (SAMPLE) char starts [cap+1]
 // The tile is cut into units -- single 64-joint blocks, or chain units of up
 // to kChainK blocks where the plan found contiguous chain segments -- dealt
 // to the waves round-robin; each wave processes its units in increasing
@@ -516,9 +609,15 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 {
     extern __shared__ float4 lds[];
     const int cap = tl.tile_cap;
-    float4 *Gs = lds;
-    int *flags = reinterpret_cast<int *>(lds + 3 * cap);
-    int *cstart = flags + (cap >> 6);
+    const int nbk = cap >> 6;
+    FwdShared sh;
+    sh.G = lds;
+    sh.part = lds + 3 * cap;
+    sh.flags = reinterpret_cast<int *>(sh.part + 3 * nbk);
+    sh.pflag = sh.flags + nbk;
+    sh.panc = sh.pflag + nbk;
+    sh.cstart = sh.panc + nbk;
+    int *cstart = sh.cstart;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
 
@@ -527,7 +626,10 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
         const int n = td.count;
         const int nblk = (n + kWave - 1) / kWave;
         const uint64_t chain_starts = ((uint64_t)(uint32_t)td.chain_hi << 32) | (uint32_t)td.chain_lo;
-        for (int i = threadIdx.x; i < nblk; i += WAVES * kWave) flags[i] = 0;
+        for (int i = threadIdx.x; i < nblk; i += WAVES * kWave) {
+            sh.flags[i] = 0;
+            sh.pflag[i] = 0;
+        }
         if constexpr (SAMPLE) {
             for (int i = threadIdx.x; i <= td.num_chars; i += WAVES * kWave)
                 cstart[i] = (int)(pose.offsets[td.first_char + i] - td.begin);
@@ -541,11 +643,11 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
             if (unit % WAVES == wave) {
                 if constexpr (CHAIN) {
                     if (chain)
-                        fwd_chain_unit<SAMPLE>(tl, pose, out, td, n, b, nb, Gs, flags, cstart, lane);
+                        fwd_chain_unit<SAMPLE>(tl, pose, out, td, n, b, nb, sh, lane);
                     else
-                        fwd_block<SAMPLE>(tl, pose, out, td, n, b, Gs, flags, cstart, lane);
+                        fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
                 } else
-                    fwd_block<SAMPLE>(tl, pose, out, td, n, b, Gs, flags, cstart, lane);
+                    fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
             }
             b += nb;
         }
@@ -1244,7 +1346,7 @@ hipError_t prepare_kernels()
 
 size_t forward_tile_lds_bytes(int tile_cap, bool sample)
 {
-    size_t bytes = (size_t)tile_cap * 48 + (size_t)(tile_cap / kWave) * 4;
+    size_t bytes = (size_t)tile_cap * 48 + (size_t)(tile_cap / kWave) * (48 + 3 * 4);
     if (sample) bytes += (size_t)(tile_cap + 1) * 4;
     return bytes;
 }
@@ -1253,11 +1355,12 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
                                 hipStream_t stream)
 {
     if (tl.num_tiles == 0) return hipSuccess;
+    const bool sample = pose.kind == 1;
     if (tl.chain_units)
-        return pose.kind == 1 ? launch_fwd_tiles_w<true, true>(tl, pose, out, stream)
-                              : launch_fwd_tiles_w<false, true>(tl, pose, out, stream);
-    return pose.kind == 1 ? launch_fwd_tiles_w<true, false>(tl, pose, out, stream)
-                          : launch_fwd_tiles_w<false, false>(tl, pose, out, stream);
+        return sample ? launch_fwd_tiles_w<true, true>(tl, pose, out, stream)
+                      : launch_fwd_tiles_w<false, true>(tl, pose, out, stream);
+    return sample ? launch_fwd_tiles_w<true, false>(tl, pose, out, stream)
+                  : launch_fwd_tiles_w<false, false>(tl, pose, out, stream);
 }
 
 hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
