@@ -4,19 +4,23 @@
 Default workload: the deep-skeleton forward scan, 4096 characters x 1024
 joints (a 64-joint humanoid plus four 240-joint chains, depth 246), fp32.
 A step is one hs_scan_forward over the whole batch with every input already
-resident in HBM.  Two input/output sets alternate between steps so that the
-256 MB last-level cache never holds the next step's data.
+resident in HBM, replayed from a HIP graph that holds eight such passes
+(one light host call per eight steps, so launches run back to back).  Two input/output
+sets alternate between steps so that the 256 MB last-level cache never holds
+the next step's data.
 
 Prints one JSON line with the throughput in joint transforms per second, the
-roofline of the dominant kernel (algorithmic bytes / measured kernel time
-against 8 TB/s HBM), the FP64 CPU oracle timed on the host as a baseline,
-and the error of one GPU step against FP64.
+roofline of the dominant kernel (algorithmic bytes / mean kernel duration
+from HIP events around the timed region, against 8 TB/s HBM), the FP64 CPU
+oracle timed on the host as a baseline, and the error of one GPU step
+against FP64.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
                     [--no-autotune]
 
 Other workloads (parity presets, not the headline line): plain_scan,
-heterogeneous, fused_sample, differentiable (forward + adjoint).
+heterogeneous (the batched form: one captured HIP graph per input set),
+fused_sample, differentiable (forward + adjoint).
 """
 import argparse
 import hashlib
@@ -53,6 +57,7 @@ BYTES_PER_JOINT = {
     "differentiable": 136,
 }
 DOMINANT = {"differentiable": "bwd_sync_kernel"}
+CHUNK = 8  # forward passes per captured graph replay
 
 
 def kernel_source_sha():
@@ -180,36 +185,68 @@ class Workload:
                 s["gq"] = torch.empty((N, 4), device=dev)
                 s["gt"] = torch.empty((N, 3), device=dev)
             self.sets.append(s)
-        self.fwd_ev, self.bwd_ev = [], []
+        # forward-only steps replay captured HIP graphs: CHUNK passes that
+        # alternate the two input sets in one graph (one light host call per
+        # CHUNK steps, so launches run back to back), plus one single-pass
+        # graph per set for a remainder
+        self.graphs = None
+        if name != "differentiable":
+            calls = []
+            for st in self.sets:
+                if name == "fused_sample":
+                    calls.append(dict(clips=self.clips, **self.cp, inv_bind=st["inv"], skin_out=st["S"]))
+                elif name == "plain_scan":
+                    calls.append(dict(quat=st["q"], trans=st["t"], scale=st["s"], inv_bind=st["inv"],
+                                      skin_out=st["S"]))
+                else:
+                    calls.append(dict(quat=st["q"], trans=st["t"], scale=st["s"], global_out=st["G"]))
+            self.graphs = [hs.ForwardGraph.sequence(self.plan, [c]) for c in calls]
+            self.chunk_graph = hs.ForwardGraph.sequence(self.plan, [calls[k % 2] for k in range(CHUNK)])
+        self.bwd_ev = []
 
-    def step(self, k, timed=False):
-        torch, hs, s = self.torch, self.hs, self.sets[k % 2]
-        if timed:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-            e[0].record()
-        if self.name == "fused_sample":
-            hs.hs_scan_forward(self.plan, clips=self.clips, **self.cp, want_global=False, inv_bind=s["inv"],
-                               skin_out=s["S"])
-        elif self.name == "plain_scan":
-            hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], want_global=False, inv_bind=s["inv"],
-                               skin_out=s["S"])
-        else:
-            hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
-        if timed:
-            e[1].record()
-            self.fwd_ev.append(e)
-        if self.name == "differentiable":
-            # loss = sum over effectors |b_e - y_e|^2: its gradient enters the
-            # effector rows of the (otherwise zero) dLoss/dG buffer
-            s["gG"][self.eff, :3, 3] = 2.0 * (s["G"][self.eff, :3, 3] - self.target)
-            if timed:
-                e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-                e[0].record()
-            hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
-                                grad_quat=s["gq"], grad_trans=s["gt"])
-            if timed:
-                e[1].record()
-                self.bwd_ev.append(e)
+    def run(self, steps, evs=None):
+        """`steps` steps from set 0 on; evs: pre-created event pairs that
+        bracket the adjoint launches (differentiable workload)."""
+        if self.graphs is None:
+            for k in range(steps):
+                self.step(k, None if evs is None else evs[k])
+            return
+        full = steps // CHUNK
+        for _ in range(full):
+            self.chunk_graph.launch()
+        for k in range(full * CHUNK, steps):
+            self.graphs[k % 2].launch()
+
+    def step(self, k, ev=None):
+        """One step on set k % 2; ev: a pre-created event pair to bracket the
+        adjoint launch with (differentiable workload)."""
+        hs, s = self.hs, self.sets[k % 2]
+        if self.graphs is not None:
+            self.graphs[k % 2].launch()
+            return
+        hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+        # loss = sum over effectors |b_e - y_e|^2: its gradient enters the
+        # effector rows of the (otherwise zero) dLoss/dG buffer
+        s["gG"][self.eff, :3, 3] = 2.0 * (s["G"][self.eff, :3, 3] - self.target)
+        if ev is not None:
+            ev[0].record()
+        hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
+                            grad_quat=s["gq"], grad_trans=s["gt"])
+        if ev is not None:
+            ev[1].record()
+            self.bwd_ev.append(ev)
+
+    def forward_ms(self, reps=50):
+        """Mean duration of the forward launch alone, back to back (the
+        differentiable step interleaves it with other work)."""
+        torch, s = self.torch, self.sets[0]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            self.hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
 
     @staticmethod
     def mean_ms(evs):
@@ -243,18 +280,28 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for k in range(args.warmup):
-        w.step(k)
+    w.run(args.warmup)
+    diff = args.workload == "differentiable"
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)] \
+        if diff else None
+    region = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
-        w.step(k, timed=True)
+    region[0].record()
+    w.run(args.steps, evs)
+    region[1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    fwd_ms, bwd_ms = w.mean_ms(w.fwd_ev), w.mean_ms(w.bwd_ev)
     dominant = DOMINANT.get(args.workload, "fwd_tile_kernel")
-    kernel_ms = bwd_ms if dominant.startswith("bwd") else fwd_ms
+    if diff:
+        # adjoint launches bracketed one by one; the forward timed on its own
+        kernel_ms = w.mean_ms(w.bwd_ev)
+        fwd_ms = w.forward_ms()
+    else:
+        # forward-only step = one kernel, launched back to back: HIP events
+        # around the timed region give its mean launch duration
+        kernel_ms = region[0].elapsed_time(region[1]) / args.steps
     bytes_per_launch = N * BYTES_PER_JOINT[args.workload]
     if args.workload == "fused_sample":
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
@@ -280,7 +327,7 @@ def main():
         "config": {"workload": args.workload, "characters": C, "joints": N, "max_depth": info["max_depth"],
                    "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
                    "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
-                   "autotuned": not args.no_autotune},
+                   "autotuned": not args.no_autotune, "hip_graph": w.graphs is not None},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

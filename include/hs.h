@@ -222,6 +222,17 @@ hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *
 hs_status hs_graph_create_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out,
                                   const float *inv_bind, float *skin_out, hs_graph **out);
 
+/* Capture n hs_scan_forward calls, in order, into one graph: call i takes
+ * srcs[i] and global_outs[i], inv_binds[i], skin_outs[i] (host arrays of n
+ * entries each; a NULL array stands for n NULL pointers).  One replay runs
+ * the n passes back to back for a single host call, e.g. several frames of
+ * a serving loop, or ping-pong buffers.  n >= 1; otherwise the rules and
+ * errors of hs_graph_create_forward, checked for every call before any
+ * capture starts.  hs_graph_create_forward is the case n = 1. */
+hs_status hs_graph_create_forward_n(const hs_plan *plan, int32_t n, const hs_pose_src *srcs,
+                                    float *const *global_outs, const float *const *inv_binds,
+                                    float *const *skin_outs, hs_graph **out);
+
 /* Replay the captured work on `stream` (asynchronous, no allocation). */
 hs_status hs_graph_launch(hs_graph *graph, hipStream_t stream);
 void hs_graph_destroy(hs_graph *graph);

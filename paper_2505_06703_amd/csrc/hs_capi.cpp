@@ -676,6 +676,42 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     return build_tables(plan, best, strategy);
 }
 
+// Validation of a forward call and its kernel arguments; HS_OK with
+// *empty set when there is nothing to launch (an empty batch).
+hs_status prepare_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out, const float *inv_bind,
+                          float *skin_out, float *ckpt_out, int32_t ckpt_k, uint32_t flags, hs::PoseArgs &pa,
+                          hs::OutArgs &oa, bool *empty)
+{
+    *empty = true;
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: plan is NULL");
+    if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: flags must be 0");
+    if (ckpt_out && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: ckpt_k must be >= 1");
+    if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
+    if (!global_out && !skin_out) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: no output requested");
+    if ((skin_out != nullptr) != (inv_bind != nullptr))
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: inv_bind and skin_out go together");
+    for (const void *p : {(const void *)global_out, (const void *)inv_bind, (const void *)skin_out,
+                          (const void *)ckpt_out})
+        if (p && !aligned(p, 16)) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: outputs and inv_bind must be 16-byte aligned");
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, src, pa, ins, true);
+    if (rc != HS_OK) return rc;
+    const size_t N = (size_t)plan->N;
+    ins.push_back({inv_bind, N * 64, "inv_bind"});
+    std::vector<Range> outs = {{global_out, N * 64, "global_out"}, {skin_out, N * 64, "skin_out"},
+                               {ckpt_out, N * 48, "ckpt_out"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    oa = hs::OutArgs{};
+    oa.global_out = global_out;
+    oa.inv_bind = inv_bind;
+    oa.skin_out = skin_out;
+    oa.ckpt = ckpt_out;
+    oa.ckpt_k = ckpt_out ? ckpt_k : 1;
+    oa.level = plan->d_level;
+    *empty = false;
+    return HS_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -865,11 +901,36 @@ struct hs_graph {
 extern "C" hs_status hs_graph_create_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out,
                                              const float *inv_bind, float *skin_out, hs_graph **out)
 {
+    if (!src) {
+        if (out) *out = nullptr;
+        return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward: src is NULL");
+    }
+    return hs_graph_create_forward_n(plan, 1, src, &global_out, &inv_bind, &skin_out, out);
+}
+
+extern "C" hs_status hs_graph_create_forward_n(const hs_plan *plan, int32_t n, const hs_pose_src *srcs,
+                                               float *const *global_outs, const float *const *inv_binds,
+                                               float *const *skin_outs, hs_graph **out)
+{
     if (!out) return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward: out is NULL");
     *out = nullptr;
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward: plan is NULL");
+    if (n < 1) return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward_n: n = %d, need n >= 1", n);
+    if (!srcs) return fail(HS_ERR_INVALID_ARG, "hs_graph_create_forward_n: srcs is NULL");
+    auto gout = [&](int i) { return global_outs ? global_outs[i] : nullptr; };
+    auto ibind = [&](int i) { return inv_binds ? inv_binds[i] : nullptr; };
+    auto sout = [&](int i) { return skin_outs ? skin_outs[i] : nullptr; };
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_graph_create_forward: cannot select device");
+    // argument errors surface before a capture is opened: a validation-only
+    // pass (no launch) per call
+    for (int i = 0; i < n; ++i) {
+        hs::PoseArgs pa;
+        hs::OutArgs oa;
+        bool empty = true;
+        hs_status rc0 = prepare_forward(plan, &srcs[i], gout(i), ibind(i), sout(i), nullptr, 0, 0, pa, oa, &empty);
+        if (rc0 != HS_OK) return rc0;
+    }
     hipStream_t s = nullptr;
     hipError_t err = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (err != hipSuccess) return fail_hip(err, "hs_graph_create_forward (stream)");
@@ -881,7 +942,9 @@ extern "C" hs_status hs_graph_create_forward(const hs_plan *plan, const hs_pose_
         delete g;
         return fail_hip(err, "hs_graph_create_forward (begin capture)");
     }
-    hs_status rc = hs_scan_forward(plan, src, global_out, inv_bind, skin_out, nullptr, 0, 0, s);
+    hs_status rc = HS_OK;
+    for (int i = 0; i < n && rc == HS_OK; ++i)
+        rc = hs_scan_forward(plan, &srcs[i], gout(i), ibind(i), sout(i), nullptr, 0, 0, s);
     err = hipStreamEndCapture(s, &g->graph);
     if (rc == HS_OK && err != hipSuccess) rc = fail_hip(err, "hs_graph_create_forward (end capture)");
     if (rc == HS_OK) {
@@ -918,34 +981,11 @@ extern "C" void hs_graph_destroy(hs_graph *graph)
 hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out, const float *inv_bind,
                           float *skin_out, float *ckpt_out, int32_t ckpt_k, uint32_t flags, hipStream_t stream)
 {
-    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: plan is NULL");
-    if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: flags must be 0");
-    if (ckpt_out && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: ckpt_k must be >= 1");
-    if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
-    if (!global_out && !skin_out) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: no output requested");
-    if ((skin_out != nullptr) != (inv_bind != nullptr))
-        return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: inv_bind and skin_out go together");
-    if (ckpt_out && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: ckpt_k must be >= 1");
-    for (const void *p : {(const void *)global_out, (const void *)inv_bind, (const void *)skin_out,
-                          (const void *)ckpt_out})
-        if (p && !aligned(p, 16)) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: outputs and inv_bind must be 16-byte aligned");
     hs::PoseArgs pa;
-    std::vector<Range> ins;
-    hs_status rc = check_pose_src(plan, src, pa, ins, true);
-    if (rc != HS_OK) return rc;
-    const size_t N = (size_t)plan->N;
-    ins.push_back({inv_bind, N * 64, "inv_bind"});
-    std::vector<Range> outs = {{global_out, N * 64, "global_out"}, {skin_out, N * 64, "skin_out"},
-                               {ckpt_out, N * 48, "ckpt_out"}};
-    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
-    if (N == 0) return HS_OK;
-    hs::OutArgs oa{};
-    oa.global_out = global_out;
-    oa.inv_bind = inv_bind;
-    oa.skin_out = skin_out;
-    oa.ckpt = ckpt_out;
-    oa.ckpt_k = ckpt_out ? ckpt_k : 1;
-    oa.level = plan->d_level;
+    hs::OutArgs oa;
+    bool empty = true;
+    hs_status rc = prepare_forward(plan, src, global_out, inv_bind, skin_out, ckpt_out, ckpt_k, flags, pa, oa, &empty);
+    if (rc != HS_OK || empty) return rc;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_forward: cannot select device");
     return run_forward(plan, pa, oa, stream);

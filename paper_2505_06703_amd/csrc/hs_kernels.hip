@@ -384,35 +384,40 @@ __device__ __forceinline__ void char_of(const TileDesc &td, const int *cstart, i
     }
 }
 
-// One 64-joint block: in-block pointer jumping across the wave, then one
-// composition with the final transform of the nearest out-of-block
-// ancestor once its block has published it.
-// One 64-joint block: in-block pointer jumping across the wave, then one
-// composition with the final transform of the nearest out-of-block
-// ancestor once its block has published it.
+// One lane's joint of a 64-joint block: local transform, in-block ancestor
+// lane a and nearest out-of-block ancestor e (tile-local), as the in-block
+// scan expects them.
 template <bool SAMPLE>
-__device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
-                                          const TileDesc &td, int n, int b, const FwdShared &sh, int lane)
+__device__ __forceinline__ void block_begin(const TileLaunch &tl, const PoseArgs &pose, const TileDesc &td, int n,
+                                            int b, const FwdShared &sh, int lane, float m[12], int &a, int &e)
 {
-    float4 *Gs = sh.G;
-    const int *cstart = sh.cstart;
     const int base = b * kWave;
     const int jl = base + lane;
-    const bool valid = jl < n;
-    const int64_t gid = td.begin + jl;
-    float m[12];
-    int a = -1, e = -1;
-    if (valid) {
+    a = -1;
+    e = -1;
+    if (jl < n) {
+        const int64_t gid = td.begin + jl;
         const int p = tl.parent[gid];
         const int pl = p < 0 ? -1 : (int)(p - td.begin);
         if (pl >= base) a = pl - base; else e = pl;
         int chr, lj;
-        char_of<SAMPLE>(td, cstart, jl, chr, lj);
+        char_of<SAMPLE>(td, sh.cstart, jl, chr, lj);
         load_local<SAMPLE>(pose, gid, chr, lj, m);
     } else {
         aff_identity(m);
     }
-    wave_inblock_scan(m, a, e, lane);
+}
+
+// After the in-block scan: one composition with the final transform of the
+// nearest out-of-block ancestor once its block has published it, then the
+// block's own publication and outputs.
+__device__ __forceinline__ void block_finish(const OutArgs &out, const TileDesc &td, int n, int b,
+                                             const FwdShared &sh, int lane, float m[12], int e)
+{
+    float4 *Gs = sh.G;
+    const int base = b * kWave;
+    const int jl = base + lane;
+    const bool valid = jl < n;
     wait_block_of(sh.flags, valid ? e : -1);
     if (valid && e >= 0) {
         float g[12];
@@ -422,7 +427,20 @@ __device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &
     if (valid) aff_store(Gs + 3 * jl, m);
     publish_blocks(sh.flags, b, 1, lane);
     if (out.global_out) store_rows<1>(out, Gs, td.begin, base, 1, n, lane);
-    if (valid) write_skin_and_ckpt(out, gid, m);
+    if (valid) write_skin_and_ckpt(out, td.begin + jl, m);
+}
+
+// One 64-joint block: in-block pointer jumping across the wave, then the
+// cross-block composition.
+template <bool SAMPLE>
+__device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                          const TileDesc &td, int n, int b, const FwdShared &sh, int lane)
+{
+    float m[12];
+    int a, e;
+    block_begin<SAMPLE>(tl, pose, td, n, b, sh, lane, m, a, e);
+    wave_inblock_scan(m, a, e, lane);
+    block_finish(out, td, n, b, sh, lane, m, e);
 }
 
 // The K local transforms of unit joints [i0, i0 + K) from the
@@ -636,20 +654,21 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
         }
         __syncthreads();
 
-        int unit = 0;
-        for (int b = 0; b < nblk; ++unit) {
-            const bool chain = CHAIN && ((chain_starts >> b) & 1);
-            const int nb = chain ? min(kChainK, nblk - b) : 1;
-            if (unit % WAVES == wave) {
-                if constexpr (CHAIN) {
+        if constexpr (CHAIN) {
+            int unit = 0;
+            for (int b = 0; b < nblk; ++unit) {
+                const bool chain = (chain_starts >> b) & 1;
+                const int nb = chain ? min(kChainK, nblk - b) : 1;
+                if (unit % WAVES == wave) {
                     if (chain)
                         fwd_chain_unit<SAMPLE>(tl, pose, out, td, n, b, nb, sh, lane);
                     else
                         fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
-                } else
-                    fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
+                }
+                b += nb;
             }
-            b += nb;
+        } else {
+            for (int b = wave; b < nblk; b += WAVES) fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
         }
         __syncthreads();
     }

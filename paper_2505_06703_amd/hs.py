@@ -35,7 +35,7 @@ HS_POSE_CLIPS = 1
 SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
            "hs_plan_create", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
-           "hs_graph_launch", "hs_graph_destroy")
+           "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy")
 
 
 class HSError(RuntimeError):
@@ -115,6 +115,8 @@ def load_library():
     lib.hs_skin.argtypes = [i64, vp, vp, vp, vp]
     lib.hs_scan_backward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp, u32, vp]
     lib.hs_graph_create_forward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, ctypes.POINTER(vp)]
+    lib.hs_graph_create_forward_n.argtypes = [vp, i32, ctypes.POINTER(hs_pose_src), ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.hs_graph_launch.argtypes = [vp, vp]
     lib.hs_graph_destroy.argtypes = [vp]
     lib.hs_graph_destroy.restype = None
@@ -342,32 +344,56 @@ def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0,
 
 
 class ForwardGraph:
-    """One hs_scan_forward call captured into a HIP graph (``hs_graph_create_forward``).
+    """hs_scan_forward calls captured into one HIP graph
+    (``hs_graph_create_forward`` / ``hs_graph_create_forward_n``).
 
-    The arrays passed here are baked into the graph: ``launch()`` re-reads the
-    current contents of the same inputs and rewrites the same outputs.  The
-    object keeps references to them so that they outlive the graph.
+    ``ForwardGraph(plan, quat, trans, scale, global_out=...)`` captures one
+    call; ``ForwardGraph.sequence(plan, [kwargs, ...])`` captures several, in
+    order (same keyword arguments as the single form).  The arrays are baked
+    into the graph: ``launch()`` re-reads the current contents of the same
+    inputs and rewrites the same outputs.  The object keeps references to
+    them so that they outlive the graph.
     """
 
     def __init__(self, plan, quat=None, trans=None, scale=None, *, clips=None, clip_a=None, clip_b=None,
                  time=None, weight=None, global_out=None, inv_bind=None, skin_out=None):
+        self._create(plan, [dict(quat=quat, trans=trans, scale=scale, clips=clips, clip_a=clip_a, clip_b=clip_b,
+                                 time=time, weight=weight, global_out=global_out, inv_bind=inv_bind,
+                                 skin_out=skin_out)])
+
+    @classmethod
+    def sequence(cls, plan, calls):
+        self = cls.__new__(cls)
+        self._create(plan, [dict(c) for c in calls])
+        return self
+
+    def _create(self, plan, calls):
         N = plan.num_joints
-        if clips is not None:
-            self._params = _clip_params(plan, clip_a, clip_b, time, weight)
-            src = hs_pose_src(HS_POSE_CLIPS, None, None, None, ctypes.pointer(clips.c),
-                              ctypes.pointer(self._params))
-        else:
-            src = _trs_src(plan, quat, trans, scale)
-        if global_out is not None:
-            _need(global_out, "global_out", (N, 4, 4))
-        if inv_bind is not None:
-            _need(inv_bind, "inv_bind", (N, 4, 4))
-            _need(skin_out, "skin_out", (N, 4, 4))
-        self._keep = (plan, quat, trans, scale, clips, clip_a, clip_b, time, weight, global_out, inv_bind,
-                      skin_out, src)
+        n = len(calls)
+        if n < 1:
+            raise ValueError("at least one call to capture")
+        srcs = (hs_pose_src * n)()
+        gouts, binds, souts = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+        keep = [plan, srcs]
+        for i, c in enumerate(calls):
+            if c.get("clips") is not None:
+                params = _clip_params(plan, c["clip_a"], c["clip_b"], c["time"], c["weight"])
+                srcs[i] = hs_pose_src(HS_POSE_CLIPS, None, None, None, ctypes.pointer(c["clips"].c),
+                                      ctypes.pointer(params))
+                keep.append(params)
+            else:
+                srcs[i] = _trs_src(plan, c.get("quat"), c.get("trans"), c.get("scale"))
+            if c.get("global_out") is not None:
+                _need(c["global_out"], "global_out", (N, 4, 4))
+            if c.get("inv_bind") is not None:
+                _need(c["inv_bind"], "inv_bind", (N, 4, 4))
+                _need(c.get("skin_out"), "skin_out", (N, 4, 4))
+            gouts[i], binds[i], souts[i] = (_ptr(c.get("global_out")), _ptr(c.get("inv_bind")),
+                                           _ptr(c.get("skin_out")))
+            keep.append(c)
+        self._keep = keep
         h = ctypes.c_void_p()
-        _check(load_library().hs_graph_create_forward(plan.handle, ctypes.byref(src), _ptr(global_out),
-                                                      _ptr(inv_bind), _ptr(skin_out), ctypes.byref(h)))
+        _check(load_library().hs_graph_create_forward_n(plan.handle, n, srcs, gouts, binds, souts, ctypes.byref(h)))
         self.handle = h
 
     def launch(self, stream=None):

@@ -133,6 +133,38 @@ def test_graph_of_fused_sample_and_skin():
         cp["time"].add_(0.173)
 
 
+def test_graph_sequence_of_calls_on_several_buffers():
+    """hs_graph_create_forward_n: three captured passes over different input
+    and output buffers (one of them skin-only), replayed with eager changes
+    in between; every output equals its own eager call."""
+    b = wl.deep_forward(num_characters=6)
+    plan = hs.Plan(b.offsets, b.parents)
+    N = b.num_joints
+    rng = np.random.default_rng(3)
+    ins = [(dev(wl.random_quats(rng, N, 0.3)), dev(b.trans), dev(b.scale)) for _ in range(3)]
+    inv = dev(np.tile(np.eye(4, dtype=np.float32), (N, 1, 1)))
+    outs = [torch.empty((N, 4, 4), device=DEV) for _ in range(3)]
+    calls = [dict(quat=ins[0][0], trans=ins[0][1], scale=ins[0][2], global_out=outs[0]),
+             dict(quat=ins[1][0], trans=ins[1][1], scale=None, inv_bind=inv, skin_out=outs[1]),
+             dict(quat=ins[2][0], trans=ins[2][1], scale=ins[2][2], global_out=outs[2])]
+    g = hs.ForwardGraph.sequence(plan, calls)
+    for it in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        r0, _ = hs.hs_scan_forward(plan, *ins[0])
+        _, r1 = hs.hs_scan_forward(plan, ins[1][0], ins[1][1], None, want_global=False, inv_bind=inv)
+        r2, _ = hs.hs_scan_forward(plan, *ins[2])
+        torch.cuda.synchronize()
+        for k, r in enumerate((r0, r1, r2)):
+            assert torch.equal(outs[k], r), f"replay {it}, call {k}"
+        for q, t, _ in ins:
+            q.copy_(dev(wl.random_quats(rng, N, 0.3)))
+            t.mul_(0.99)
+    g.close()
+    with pytest.raises(ValueError):
+        hs.ForwardGraph.sequence(plan, [])
+
+
 def test_plan_info_reports_tiles_and_multipass():
     b = wl.heterogeneous(num_characters=100)
     p = hs.Plan(b.offsets, b.parents, tile_joints=512)
