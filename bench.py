@@ -57,7 +57,9 @@ BYTES_PER_JOINT = {
     "differentiable": 136,
 }
 DOMINANT = {"differentiable": "bwd_sync_kernel"}
-CHUNK = 8  # forward passes per captured graph replay
+CHUNK = 8  # at least this many forward passes per captured graph replay
+SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
+MAX_SETS = 64
 
 
 def kernel_source_sha():
@@ -170,21 +172,32 @@ class Workload:
             self.eff = up(b.extra["effectors"].astype(np.int64))
             self.target = Grest[self.eff, :3, 3] + up(b.extra["target_offsets"])
             del Grest
-        self.sets = []
-        for k in range(2):
-            s = {}
+        # input/output sets cycled step by step: enough of them that one
+        # cycle touches at least SWEEP_BYTES, so the 256 MB last-level cache
+        # never holds the next step's data (the 4096-joint plain_scan fits
+        # the cache whatever the count; it is reported as latency-bound)
+        def make_set(k):
+            st = {}
             if self.clips is None:
-                s["q"], s["t"], s["s"] = up(b.quat), up(b.trans), up(b.scale)
-            s["inv"] = None if self.inv is None else (self.inv if k == 0 else self.inv.clone())
+                st["q"], st["t"], st["s"] = up(b.quat), up(b.trans), up(b.scale)
+            st["inv"] = None if self.inv is None else (self.inv if k == 0 else self.inv.clone())
             if name in ("deep_forward", "heterogeneous", "differentiable"):
-                s["G"] = torch.empty((N, 4, 4), device=dev)
+                st["G"] = torch.empty((N, 4, 4), device=dev)
             else:
-                s["S"] = torch.empty((N, 4, 4), device=dev)
+                st["S"] = torch.empty((N, 4, 4), device=dev)
             if name == "differentiable":
-                s["gG"] = torch.zeros((N, 4, 4), device=dev)
-                s["gq"] = torch.empty((N, 4), device=dev)
-                s["gt"] = torch.empty((N, 3), device=dev)
-            self.sets.append(s)
+                st["gG"] = torch.zeros((N, 4, 4), device=dev)
+                st["gq"] = torch.empty((N, 4), device=dev)
+                st["gt"] = torch.empty((N, 3), device=dev)
+            return st
+
+        first = make_set(0)
+        set_bytes = sum(v.numel() * v.element_size() for v in first.values() if v is not None)
+        if self.clips is not None:
+            set_bytes += (self.clips.key_quat.numel() + self.clips.key_trans.numel()) * 4
+        n_sets = int(min(MAX_SETS, max(2, -(-SWEEP_BYTES // max(1, set_bytes)))))
+        self.sets = [first] + [make_set(k) for k in range(1, n_sets)]
+        self.set_bytes = set_bytes
         # forward-only steps replay captured HIP graphs: CHUNK passes that
         # alternate the two input sets in one graph (one light host call per
         # CHUNK steps, so launches run back to back), plus one single-pass
@@ -201,7 +214,9 @@ class Workload:
                 else:
                     calls.append(dict(quat=st["q"], trans=st["t"], scale=st["s"], global_out=st["G"]))
             self.graphs = [hs.ForwardGraph.sequence(self.plan, [c]) for c in calls]
-            self.chunk_graph = hs.ForwardGraph.sequence(self.plan, [calls[k % 2] for k in range(CHUNK)])
+            S = len(calls)
+            self.chunk = S * max(1, -(-CHUNK // S))
+            self.chunk_graph = hs.ForwardGraph.sequence(self.plan, [calls[k % S] for k in range(self.chunk)])
         self.bwd_ev = []
 
     def run(self, steps, evs=None):
@@ -211,18 +226,19 @@ class Workload:
             for k in range(steps):
                 self.step(k, None if evs is None else evs[k])
             return
-        full = steps // CHUNK
+        S = len(self.sets)
+        full = steps // self.chunk
         for _ in range(full):
             self.chunk_graph.launch()
-        for k in range(full * CHUNK, steps):
-            self.graphs[k % 2].launch()
+        for k in range(full * self.chunk, steps):
+            self.graphs[k % S].launch()
 
     def step(self, k, ev=None):
-        """One step on set k % 2; ev: a pre-created event pair to bracket the
-        adjoint launch with (differentiable workload)."""
-        hs, s = self.hs, self.sets[k % 2]
+        """One step on set k (cycled); ev: a pre-created event pair to bracket
+        the adjoint launch with (differentiable workload)."""
+        hs, s = self.hs, self.sets[k % len(self.sets)]
         if self.graphs is not None:
-            self.graphs[k % 2].launch()
+            self.graphs[k % len(self.sets)].launch()
             return
         hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
         # loss = sum over effectors |b_e - y_e|^2: its gradient enters the
@@ -235,6 +251,27 @@ class Workload:
         if ev is not None:
             ev[1].record()
             self.bwd_ev.append(ev)
+
+    def plain_launch_ms(self, reps=50):
+        """Mean time per step when each step is one plain hs_scan_forward call
+        from Python instead of a graph replay (forward-only workloads)."""
+        torch, hs = self.torch, self.hs
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(reps):
+            s = self.sets[k % len(self.sets)]
+            if self.name == "fused_sample":
+                hs.hs_scan_forward(self.plan, clips=self.clips, **self.cp, want_global=False, inv_bind=s["inv"],
+                                   skin_out=s["S"])
+            elif self.name == "plain_scan":
+                hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], want_global=False, inv_bind=s["inv"],
+                                   skin_out=s["S"])
+            else:
+                hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
 
     def forward_ms(self, reps=50):
         """Mean duration of the forward launch alone, back to back (the
@@ -306,11 +343,16 @@ def main():
     if args.workload == "fused_sample":
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    copy_gbs = device_copy_gbs(torch)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
-            "kernel": dominant, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": bytes_per_launch}
+            "kernel": dominant, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
     if args.workload == "differentiable":
         roof["forward_kernel_ms"] = fwd_ms
+    launch = None
+    if not diff:
+        launch = {"graph_ms_per_step": elapsed * 1e3 / args.steps, "plain_call_ms_per_step": w.plain_launch_ms()}
     out = {
         "metric": METRIC,
         "value": N * args.steps / elapsed,
@@ -327,12 +369,33 @@ def main():
         "config": {"workload": args.workload, "characters": C, "joints": N, "max_depth": info["max_depth"],
                    "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
                    "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
-                   "autotuned": not args.no_autotune, "hip_graph": w.graphs is not None},
+                   "autotuned": not args.no_autotune, "hip_graph": w.graphs is not None,
+                   "input_sets": len(w.sets)},
         "roofline": roof,
     }
+    if launch is not None:
+        out["launch_modes"] = launch
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["err_vs_fp64"] = cpu_baseline(w)
     print(json.dumps(out))
+
+
+def device_copy_gbs(torch, nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device-to-device copy (bytes read + written per
+    second), the practical HBM ceiling the kernel is also compared with."""
+    src = torch.empty(nbytes // 4, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(w):
@@ -363,17 +426,25 @@ def cpu_baseline(w):
     else:
         def run():
             return oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale), b.trans
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        G, tr = run()
-        reps += 1
-        wall = time.perf_counter() - t0
-        if wall >= 10.0 or reps >= 2000:
-            break
+    def timed(seconds):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            out = run()
+            reps += 1
+            wall = time.perf_counter() - t0
+            if wall >= seconds or reps >= 2000:
+                return out, reps, wall
+
+    threads = oracle.set_threads(cores)
+    (G, tr), reps, wall = timed(10.0)
+    oracle.set_threads(1)
+    _, reps1, wall1 = timed(5.0)
+    oracle.set_threads(threads)
     what = "forward + adjoint" if name == "differentiable" else "forward"
-    base = {"value": N * reps / wall, "unit": "joint transforms/s", "cores": cores, "kind": "oracle",
+    base = {"value": N * reps / wall, "unit": "joint transforms/s", "cores": threads, "kind": "oracle",
             "sample": f"full {name} batch ({b.num_characters} characters, {N} joints, FP64 {what}) x {reps} "
-                      f"passes, fp32->fp64 widening included, {wall:.1f} s wall"}
+                      f"passes on {threads} threads, fp32->fp64 widening included, {wall:.1f} s wall",
+            "value_1thread": N * reps1 / wall1}
 
     w.step(0)
     torch.cuda.synchronize()

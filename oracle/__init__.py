@@ -54,8 +54,9 @@ def _load():
                                         _f64p, _f64p]
         lib.hso_backward.argtypes = [i64, _i64p, _i32p, _f64p, _f64p, _f64p, _f64p,
                                      _f64p, _f64p, _f64p, _f64p, _f64p]
+        lib.hso_set_threads.argtypes = [i32]
         for name in ("hso_trs_to_local", "hso_scan_matrices", "hso_forward", "hso_skin",
-                     "hso_path_length", "hso_pose_sample", "hso_backward"):
+                     "hso_path_length", "hso_pose_sample", "hso_backward", "hso_set_threads"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -63,6 +64,13 @@ def _load():
 
 class OracleError(RuntimeError):
     pass
+
+
+def set_threads(n):
+    """Threads of the parallel loops over characters (n < 1 only queries);
+    returns the count in effect.  Characters are independent, so results do
+    not depend on it."""
+    return int(_load().hso_set_threads(int(n)))
 
 
 def _check(rc, what):

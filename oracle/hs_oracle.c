@@ -22,6 +22,7 @@
  * Return codes: 0 ok, 1 invalid argument, 2 topology violation.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stddef.h>
 #include <string.h>
@@ -349,4 +350,12 @@ int hso_backward(int64_t C, const int64_t *offsets, const int32_t *parents,
         }
     }
     return HSO_OK;
+}
+
+/* Thread count for the parallel loops over characters (n >= 1); returns the
+ * count now in effect.  Changes no arithmetic: characters are independent. */
+int hso_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

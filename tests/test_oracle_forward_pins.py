@@ -321,3 +321,23 @@ def test_path_length_unit_scale_sums_offsets():
                 acc += np.linalg.norm(b.trans[o + cur].astype(np.float64))
                 cur = b.parents[o + cur]
             assert abs(lam[o + j] - acc) < 1e-6
+
+
+def test_thread_count_does_not_change_results():
+    """Characters are independent: the parallel oracle gives the same bits
+    on one thread and on several (the CPU baseline is timed both ways)."""
+    b = wl.heterogeneous(num_characters=40, hi=300)
+    W = np.random.default_rng(2).standard_normal((b.num_joints, 4, 4))
+    prev = oracle.set_threads(0)  # 0: query only
+    oracle.set_threads(1)
+    try:
+        G1 = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+        g1 = oracle.backward(b.offsets, b.parents, b.quat, b.trans, b.scale, W)
+        oracle.set_threads(4)
+        G4 = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+        g4 = oracle.backward(b.offsets, b.parents, b.quat, b.trans, b.scale, W)
+    finally:
+        oracle.set_threads(prev)
+    assert np.array_equal(G1, G4)
+    for a, c in zip(g1, g4):
+        assert np.array_equal(a, c)
