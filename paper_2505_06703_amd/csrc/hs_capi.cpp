@@ -129,10 +129,14 @@ struct MPSet {
     MPBlock *d_blocks = nullptr;
     int32_t num_blocks = 0;
     int64_t nmp = 0;
-    int32_t rounds = 0;        // block-level jump rounds
     int32_t depth_rounds = 0;  // ceil(log2 max depth) (adjoint)
-    float4 *P[2] = {nullptr, nullptr};
-    int32_t *E[2] = {nullptr, nullptr};
+    float4 *P = nullptr;
+    int32_t *d_janc = nullptr;
+    int32_t *d_anchors = nullptr;
+    int32_t num_anchors = 0;
+    int32_t rounds = 0;        // anchor-level jump rounds
+    float4 *AP[2] = {nullptr, nullptr};
+    int32_t *AE[2] = {nullptr, nullptr};
     float4 *S[2] = {nullptr, nullptr};
     float4 *M[2] = {nullptr, nullptr};
     int32_t *A[2] = {nullptr, nullptr};
@@ -142,9 +146,12 @@ struct MPSet {
 void free_mpset(MPSet &m)
 {
     (void)hipFree(m.d_blocks);
+    (void)hipFree(m.P);
+    (void)hipFree(m.d_janc);
+    (void)hipFree(m.d_anchors);
     for (int i = 0; i < 2; ++i) {
-        (void)hipFree(m.P[i]);
-        (void)hipFree(m.E[i]);
+        (void)hipFree(m.AP[i]);
+        (void)hipFree(m.AE[i]);
         (void)hipFree(m.S[i]);
         (void)hipFree(m.M[i]);
         (void)hipFree(m.A[i]);
@@ -380,19 +387,67 @@ Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units,
 
 // Upload a packing's multipass blocks and allocate the path's workspace
 // (and the adjoint's, if asked).
-hs_status make_mpset(MPSet &m, const Packing &pk, bool adjoint, int depth_rounds)
+// Anchors of the multipass characters: e(c), the nearest out-of-block
+// ancestor of compact joint c (one pass in joint order: the parent's own
+// e when the parent lies in the same block); the anchors are the distinct
+// e values, janc(c) is the index of e(c) among them, and the anchor-level
+// rounds cover the longest anchor chain.
+void build_anchors(const hs_plan *plan, const Packing &pk, std::vector<int32_t> &janc,
+                   std::vector<int32_t> &anchors, int &rounds)
+{
+    const auto &gpar = plan->h_gparent;
+    std::vector<int32_t> e((size_t)pk.nmp, -1);
+    for (const MPBlock &bd : pk.mpb)
+        for (int l = 0; l < bd.count; ++l) {
+            const int64_t g = bd.gbegin + l, c = bd.cbegin + l;
+            const int64_t p = gpar[g];
+            if (p < 0) e[c] = -1;
+            else if (p >= bd.gbegin) e[c] = e[bd.cbegin + (p - bd.gbegin)];
+            else e[c] = (int32_t)(bd.cbegin + (p - bd.gbegin));  // same character, earlier block
+        }
+    std::vector<int32_t> aidx((size_t)pk.nmp, -1);
+    for (int64_t c = 0; c < pk.nmp; ++c)
+        if (e[c] >= 0) aidx[e[c]] = 0;
+    anchors.clear();
+    for (int64_t c = 0; c < pk.nmp; ++c)
+        if (aidx[c] == 0) {
+            aidx[c] = (int32_t)anchors.size();
+            anchors.push_back((int32_t)c);
+        }
+    janc.assign((size_t)pk.nmp, -1);
+    for (int64_t c = 0; c < pk.nmp; ++c) janc[c] = e[c] >= 0 ? aidx[e[c]] : -1;
+    // anchors come in joint order and e(a) < a, so a chain's depth is known
+    // when its anchor is reached
+    std::vector<int32_t> depth(anchors.size(), 1);
+    int maxd = 1;
+    for (size_t i = 0; i < anchors.size(); ++i) {
+        const int32_t j = janc[anchors[i]];
+        depth[i] = j < 0 ? 1 : depth[j] + 1;
+        maxd = std::max(maxd, depth[i]);
+    }
+    rounds = ceil_log2(maxd);
+}
+
+// Upload a packing's multipass blocks and anchors and allocate the path's
+// workspace (and the adjoint's, if asked).
+hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjoint, int depth_rounds)
 {
     free_mpset(m);
     m.num_blocks = (int32_t)pk.mpb.size();
     m.nmp = pk.nmp;
-    m.rounds = ceil_log2(std::max(1, pk.max_chain_mp));
     m.depth_rounds = depth_rounds;
     if (pk.nmp == 0) return HS_OK;
+    std::vector<int32_t> janc, anchors;
+    build_anchors(plan, pk, janc, anchors, m.rounds);
+    m.num_anchors = (int32_t)anchors.size();
     hipError_t err = upload(&m.d_blocks, pk.mpb);
-    const size_t n = (size_t)pk.nmp;
+    if (err == hipSuccess) err = upload(&m.d_janc, janc);
+    if (err == hipSuccess && !anchors.empty()) err = upload(&m.d_anchors, anchors);
+    const size_t n = (size_t)pk.nmp, na = std::max<size_t>(1, anchors.size());
+    if (err == hipSuccess) err = hipMalloc(&m.P, n * 3 * sizeof(float4));
     for (int i = 0; i < 2 && err == hipSuccess; ++i) {
-        err = hipMalloc(&m.P[i], n * 3 * sizeof(float4));
-        if (err == hipSuccess) err = hipMalloc(&m.E[i], n * sizeof(int32_t));
+        err = hipMalloc(&m.AP[i], na * 3 * sizeof(float4));
+        if (err == hipSuccess) err = hipMalloc(&m.AE[i], na * sizeof(int32_t));
         if (adjoint && err == hipSuccess) err = hipMalloc(&m.S[i], n * 3 * sizeof(float4));
         if (adjoint && err == hipSuccess) err = hipMalloc(&m.M[i], n * 3 * sizeof(float4));
         if (adjoint && err == hipSuccess) err = hipMalloc(&m.A[i], n * sizeof(int32_t));
@@ -442,7 +497,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         int max_level = 1;
         for (const MPBlock &mb : pb.mpb)
             for (int k = 0; k < mb.count; ++k) max_level = std::max(max_level, plan->h_level[mb.gbegin + k]);
-        hs_status rc2 = make_mpset(plan->bmp, pb, true, ceil_log2(max_level));
+        hs_status rc2 = make_mpset(plan->bmp, plan, pb, true, ceil_log2(max_level));
         if (rc2 != HS_OK) return rc2;
     }
 
@@ -451,7 +506,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     plan->d_tiles = nullptr;
     if ((err = upload(&plan->d_tiles, sorted)) != hipSuccess) return fail_hip(err, "hs_plan_create");
     plan->h_tiles = sorted;
-    hs_status rc = make_mpset(plan->mp, pk, false, 0);
+    hs_status rc = make_mpset(plan->mp, plan, pk, false, 0);
     if (rc != HS_OK) return rc;
     plan->max_units = pk.max_units;
     plan->shape = shape;
@@ -488,14 +543,18 @@ hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
     hs::MPLaunch ml{};
     ml.blocks = m.d_blocks;
     ml.num_blocks = m.num_blocks;
-    ml.rounds = m.rounds;
     ml.nmp = m.nmp;
     ml.parent = p->d_parent;
+    ml.P = m.P;
+    ml.janc = m.d_janc;
+    ml.anchors = m.d_anchors;
+    ml.num_anchors = m.num_anchors;
+    ml.rounds = m.rounds;
     ml.depth_rounds = m.depth_rounds;
     ml.G = m.G;
     for (int i = 0; i < 2; ++i) {
-        ml.P[i] = m.P[i];
-        ml.E[i] = m.E[i];
+        ml.AP[i] = m.AP[i];
+        ml.AE[i] = m.AE[i];
         ml.S[i] = m.S[i];
         ml.M[i] = m.M[i];
         ml.A[i] = m.A[i];

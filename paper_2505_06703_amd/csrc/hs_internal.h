@@ -88,11 +88,17 @@ struct TileLaunch {
 struct MPLaunch {
     const MPBlock *blocks;
     int32_t num_blocks;
-    int32_t rounds;           // block-level jump rounds (forward)
     int64_t nmp;              // joints on the multipass path (compact count)
     const int32_t *parent;    // [N] global parent id or -1
-    float4 *P[2];             // [Nmp*3] ping-pong partial products
-    int32_t *E[2];            // [Nmp]   ping-pong ext pointers (compact ids)
+    float4 *P;                // [Nmp*3] in-block partial products (phase 1)
+    // anchors: the joints that are some joint's nearest out-of-block
+    // ancestor; the cross-block phase jumps over these only
+    const int32_t *janc;      // [Nmp] anchor index of the joint's out-of-block ancestor, or -1
+    const int32_t *anchors;   // [num_anchors] compact id of each anchor
+    int32_t num_anchors;
+    int32_t rounds;           // anchor-level jump rounds
+    float4 *AP[2];            // [num_anchors*3] ping-pong anchor products
+    int32_t *AE[2];           // [num_anchors] ping-pong anchor pointers
     // adjoint workspace (NULL when the plan has none)
     int32_t depth_rounds;     // ceil(log2 max depth) of these characters
     float4 *S[2];             // [Nmp*3] ping-pong partial adjoints

@@ -1109,23 +1109,36 @@ mp_local_kernel(MPLaunch ml, PoseArgs pose)
         aff_identity(m);
     }
     wave_inblock_scan(m, a, e, lane);
-    if (valid) {
-        aff_store(ml.P[0] + 3 * cid, m);
-        ml.E[0][cid] = e;
-    }
+    if (valid) aff_store(ml.P + 3 * cid, m);
 }
 
+// Anchor i starts from its own phase-1 product and the anchor index of its
+// nearest out-of-block ancestor.
 __global__ void __launch_bounds__(256)
-mp_jump_kernel(int64_t nmp, const float4 *Pin, const int32_t *Ein, float4 *Pout, int32_t *Eout)
+mp_anchor_gather_kernel(MPLaunch ml)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmp) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ml.num_anchors) return;
+    const int64_t c = ml.anchors[i];
+    float m[12];
+    aff_load(ml.P + 3 * c, m);
+    aff_store(ml.AP[0] + 3 * i, m);
+    ml.AE[0][i] = ml.janc[c];
+}
+
+// One pointer-jumping round over the anchors (Eq. 2 applied to the anchor
+// tree): product with the target's product, target's target.
+__global__ void __launch_bounds__(256)
+mp_anchor_round_kernel(int32_t na, const float4 *Pin, const int32_t *Ein, float4 *Pout, int32_t *Eout)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= na) return;
     float m[12];
     aff_load(Pin + 3 * i, m);
     int e = Ein[i];
     if (e >= 0) {
         float g[12];
-        aff_load(Pin + 3 * (int64_t)e, g);
+        aff_load(Pin + 3 * e, g);
         aff_mul_left(g, m);
         e = Ein[e];
     }
@@ -1133,8 +1146,10 @@ mp_jump_kernel(int64_t nmp, const float4 *Pin, const int32_t *Ein, float4 *Pout,
     Eout[i] = e;
 }
 
+// Final pass: G_j = G_anchor P_j, one composition per joint.  Writes the
+// outputs, or (Gc non-NULL) the compact global transforms the adjoint reads.
 __global__ void __launch_bounds__(kMPWaves * kWave)
-mp_out_kernel(MPLaunch ml, const float4 *P, OutArgs out)
+mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
@@ -1142,8 +1157,19 @@ mp_out_kernel(MPLaunch ml, const float4 *P, OutArgs out)
     const MPBlock bd = ml.blocks[w];
     if (lane >= bd.count) return;
     const int64_t gid = bd.gbegin + lane;
+    const int64_t cid = bd.cbegin + lane;
     float m[12];
-    aff_load(P + 3 * (bd.cbegin + lane), m);
+    aff_load(ml.P + 3 * cid, m);
+    const int a = ml.janc[cid];
+    if (a >= 0) {
+        float g[12];
+        aff_load(AP + 3 * a, g);
+        aff_mul_left(g, m);
+    }
+    if (Gc) {
+        aff_store(Gc + 3 * cid, m);
+        return;
+    }
     if (out.global_out) {
         float4 *G = reinterpret_cast<float4 *>(out.global_out) + 4 * gid;
         aff_store(G, m);
@@ -1382,10 +1408,11 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
                   : launch_fwd_tiles_w<false, false>(tl, pose, out, stream);
 }
 
-hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
-                                    hipStream_t stream)
+// Phase 1 per block, anchor rounds, final pass; Gc non-NULL: compact global
+// transforms for the adjoint instead of the outputs.
+hipError_t run_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out, float4 *Gc,
+                         hipStream_t stream)
 {
-    if (ml.num_blocks == 0) return hipSuccess;
     const dim3 blk(kMPWaves * kWave);
     const dim3 grid((ml.num_blocks + kMPWaves - 1) / kMPWaves);
     if (pose.kind == 1)
@@ -1395,15 +1422,26 @@ hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, co
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     int cur = 0;
-    const dim3 jgrid((unsigned)((ml.nmp + 255) / 256));
-    for (int r = 0; r < ml.rounds; ++r) {
-        hipLaunchKernelGGL(mp_jump_kernel, jgrid, dim3(256), 0, stream, ml.nmp, ml.P[cur], ml.E[cur],
-                           ml.P[cur ^ 1], ml.E[cur ^ 1]);
+    if (ml.num_anchors > 0) {
+        const dim3 agrid((unsigned)((ml.num_anchors + 255) / 256));
+        hipLaunchKernelGGL(mp_anchor_gather_kernel, agrid, dim3(256), 0, stream, ml);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        cur ^= 1;
+        for (int r = 0; r < ml.rounds; ++r) {
+            hipLaunchKernelGGL(mp_anchor_round_kernel, agrid, dim3(256), 0, stream, ml.num_anchors, ml.AP[cur],
+                               ml.AE[cur], ml.AP[cur ^ 1], ml.AE[cur ^ 1]);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            cur ^= 1;
+        }
     }
-    hipLaunchKernelGGL(mp_out_kernel, grid, blk, 0, stream, ml, ml.P[cur], out);
+    hipLaunchKernelGGL(mp_out_kernel, grid, blk, 0, stream, ml, ml.AP[cur], out, Gc);
     return hipGetLastError();
+}
+
+hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
+                                    hipStream_t stream)
+{
+    if (ml.num_blocks == 0) return hipSuccess;
+    return run_multipass(ml, pose, out, nullptr, stream);
 }
 
 hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const PoseArgs &pose,
@@ -1512,21 +1550,11 @@ hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, c
     const dim3 cgrid((unsigned)((3 * ml.nmp + 255) / 256));
     hipError_t err;
     // global transforms of the multipass characters, compact layout
-    hipLaunchKernelGGL(mp_local_kernel<false>, grid, blk, 0, stream, ml, pose);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    int cur = 0;
-    for (int r = 0; r < ml.rounds; ++r) {
-        hipLaunchKernelGGL(mp_jump_kernel, egrid, dim3(256), 0, stream, ml.nmp, ml.P[cur], ml.E[cur],
-                           ml.P[cur ^ 1], ml.E[cur ^ 1]);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-        cur ^= 1;
-    }
-    hipLaunchKernelGGL(mpb_copy_kernel, cgrid, dim3(256), 0, stream, 3 * ml.nmp, ml.P[cur], ml.G);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = run_multipass(ml, pose, OutArgs{}, ml.G, stream)) != hipSuccess) return err;
     // reverse pointer jumping over HBM
     hipLaunchKernelGGL(mpb_init_kernel, grid, blk, 0, stream, ml, pose, bwd);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    cur = 0;
+    int cur = 0;
     for (int r = 0; r < ml.depth_rounds; ++r) {
         hipLaunchKernelGGL(mpb_copy_kernel, cgrid, dim3(256), 0, stream, 3 * ml.nmp, ml.S[cur], ml.S[cur ^ 1]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
