@@ -19,8 +19,9 @@ against FP64.
                     [--no-autotune]
 
 Other workloads (parity presets, not the headline line): plain_scan,
-heterogeneous (the batched form: one captured HIP graph per input set),
-fused_sample, differentiable (forward + adjoint).
+heterogeneous (the batched form), fused_sample, differentiable (forward +
+adjoint), long_chains (64 chains of 65536 joints: the multipass path, whose
+step is several kernels, all counted in kernel_ms).
 """
 import argparse
 import hashlib
@@ -40,7 +41,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_06703_amd", "csrc", f)
                   for f in ("hs_kernels.hip", "hs_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 256 << 20
-WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "differentiable"]
+WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "differentiable", "long_chains"]
 
 # algorithmic HBM bytes per joint that the dominant kernel of a step must
 # move (read + write)
@@ -48,6 +49,8 @@ BYTES_PER_JOINT = {
     # quat 16 + trans 12 + scale 12 + parent 4 read, global 64 written
     "deep_forward": 108,
     "heterogeneous": 108,
+    # multipass path: the same contract, several kernels per step
+    "long_chains": 108,
     # + inverse bind 64 read, skin 64 written
     "plain_scan": 236,
     # parent 4 + inverse bind 64 read, skin 64 written (+ clip library once)
@@ -56,7 +59,8 @@ BYTES_PER_JOINT = {
     # grad_quat 16 + grad_trans 12
     "differentiable": 136,
 }
-DOMINANT = {"differentiable": "bwd_sync_kernel"}
+DOMINANT = {"differentiable": "bwd_sync_kernel",
+            "long_chains": "multipass step (mp_local, anchor rounds, mp_out)"}
 CHUNK = 8  # at least this many forward passes per captured graph replay
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
 MAX_SETS = 64
@@ -181,7 +185,7 @@ class Workload:
             if self.clips is None:
                 st["q"], st["t"], st["s"] = up(b.quat), up(b.trans), up(b.scale)
             st["inv"] = None if self.inv is None else (self.inv if k == 0 else self.inv.clone())
-            if name in ("deep_forward", "heterogeneous", "differentiable"):
+            if name in ("deep_forward", "heterogeneous", "differentiable", "long_chains"):
                 st["G"] = torch.empty((N, 4, 4), device=dev)
             else:
                 st["S"] = torch.empty((N, 4, 4), device=dev)
@@ -450,7 +454,7 @@ def cpu_baseline(w):
     torch.cuda.synchronize()
     s0 = w.sets[0]
     lam = oracle.path_length(b.offsets, b.parents, G, tr)
-    if name in ("deep_forward", "heterogeneous", "differentiable"):
+    if name in ("deep_forward", "heterogeneous", "differentiable", "long_chains"):
         Gg = s0["G"].cpu().numpy().astype(np.float64)
         db = np.abs(Gg[:, :3, 3] - G[:, :3, 3]).max(axis=1)
         err = {"rotation_abs_max": float(np.abs(Gg[:, :3, :3] - G[:, :3, :3]).max()),

@@ -328,12 +328,26 @@ def differentiable(seed=4, num_characters=1024, chain_len=112, radius=0.5):
     return b
 
 
+def long_chains(seed=5, num_characters=64, chain_len=65536, angle=0.01):
+    """Single chains far beyond one workgroup's LDS (the multipass path):
+    64 x 65536 joints, rotation angles U[-0.01, 0.01] so that fp32 rounding
+    along 65536 compositions stays within the depth-scaled bound."""
+    rng = np.random.default_rng(seed)
+    offsets = np.arange(num_characters + 1, dtype=np.int64) * chain_len
+    parents = np.tile(np.arange(-1, chain_len - 1, dtype=np.int32), num_characters)
+    N = int(offsets[-1])
+    q, t, s = random_pose(rng, N, max_angle=angle)
+    rq, rt, rs = random_pose(rng, N, max_angle=angle)
+    return Batch("long_chains", offsets, parents, q, t, s, rq, rt, rs)
+
+
 PRESETS = {
     "plain_scan": plain_scan,
     "deep_forward": deep_forward,
     "heterogeneous": heterogeneous,
     "fused_sample": fused_sample,
     "differentiable": differentiable,
+    "long_chains": long_chains,
 }
 
 

@@ -66,3 +66,12 @@ def test_heterogeneous_small():
 def test_seeds_are_reproducible():
     a, b = wl.plain_scan(seed=0), wl.plain_scan(seed=0)
     assert np.array_equal(a.parents, b.parents) and np.array_equal(a.quat, b.quat)
+
+
+def test_long_chains_small():
+    b = wl.long_chains(num_characters=2, chain_len=300)
+    _valid(b)
+    assert b.num_joints == 600 and b.depth() == 300
+    q = b.quat.astype(np.float64)
+    ang = 2 * np.arccos(np.clip(np.abs(q[:, 3]), 0, 1))
+    assert ang.max() <= 0.01 + 2e-4  # fp32 arccos near 1 loses ~1e-4
