@@ -174,6 +174,14 @@ struct hs_plan {
     int32_t *d_level = nullptr;
     TileDesc *d_tiles = nullptr;
     std::vector<TileDesc> h_tiles;
+    int32_t main_grid = 0;
+    // smaller characters on smaller tiles of their own (more workgroups per
+    // CU), launched before the main set: {tiles, count, cap, waves, grid}
+    struct ClassSet {
+        TileDesc *d_tiles = nullptr;
+        int32_t num_tiles = 0, cap = 0, waves = 0, grid = 0;
+    };
+    std::vector<ClassSet> small;
     // adjoint tiles: characters of up to 1024 joints (synchronous-round
     // kernel) and larger ones up to the dataflow kernel's limit
     TileDesc *d_btiles = nullptr;
@@ -198,6 +206,7 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_parent);
     (void)hipFree(p->d_level);
     (void)hipFree(p->d_tiles);
+    for (auto &c : p->small) (void)hipFree(c.d_tiles);
     (void)hipFree(p->d_btiles);
     (void)hipFree(p->d_bbig);
     free_mpset(p->mp);
@@ -463,9 +472,45 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
 hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
 {
     const int cap = shape.tile_cap;
-    Packing pk = pack_tiles(plan, cap, strategy, shape.chain_units);
+    const int ncu = plan->ctx->num_cu;
+    auto grid_of = [&](size_t ntiles) {
+        return shape.grid_per_cu > 0 ? (int32_t)std::min<int64_t>(ntiles, (int64_t)shape.grid_per_cu * ncu)
+                                     : (int32_t)ntiles;
+    };
+    // Size classes: with tiles larger than 1024 joints, characters of up to
+    // 1024 joints get 1024-joint tiles (8 waves; three workgroups fit a CU)
+    // and, under 1664-joint tiles or larger, characters of 1025-1664 joints
+    // get 1664-joint tiles (16 waves; two per CU).  The main set holds the
+    // rest.  Each set is one launch with its own LDS size.
+    for (auto &c : plan->small) (void)hipFree(c.d_tiles);
+    plan->small.clear();
+    int64_t main_lo = 0;
+    int64_t small_tiled = 0;
+    int32_t small_tiles = 0, small_grid = 0;
+    if (strategy != HS_STRATEGY_MULTIPASS && cap > 1024) {
+        struct Cls { int64_t lo, hi; int cap, waves; };
+        std::vector<Cls> cls = {{0, 1024, 1024, 8}};
+        if (cap > 1664) cls.push_back({1025, 1664, 1664, 16});
+        for (const Cls &c : cls) {
+            Packing ps = pack_tiles(plan, c.cap, strategy, shape.chain_units, c.lo, c.hi);
+            main_lo = c.hi + 1;
+            if (ps.tiles.empty()) continue;
+            hs_plan::ClassSet cs;
+            cs.num_tiles = (int32_t)ps.tiles.size();
+            cs.cap = c.cap;
+            cs.waves = c.waves;
+            cs.grid = grid_of(ps.tiles.size());
+            hipError_t e0 = upload(&cs.d_tiles, ps.tiles);
+            if (e0 != hipSuccess) return fail_hip(e0, "hs_plan_create");
+            plan->small.push_back(cs);
+            small_tiled += ps.tiled;
+            small_tiles += cs.num_tiles;
+            small_grid += cs.grid;
+        }
+    }
+    Packing pk = pack_tiles(plan, cap, strategy, shape.chain_units, main_lo);
     std::vector<TileDesc> &sorted = pk.tiles;
-    const int64_t nmp = pk.nmp, tiled = pk.tiled;
+    const int64_t nmp = pk.nmp, tiled = pk.tiled + small_tiled;
     const int max_chain_tiles = pk.max_chain_tiles, max_chain_mp = pk.max_chain_mp;
 
     // The adjoint gets tiles of its own.  Characters of up to 1024 joints go
@@ -511,28 +556,38 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     plan->max_units = pk.max_units;
     plan->shape = shape;
 
+    plan->main_grid = grid_of(sorted.size());
+
     hs_plan_info &I = plan->info;
     I.tiled_joints = tiled;
     I.multipass_joints = nmp;
-    I.num_tiles = (int32_t)sorted.size();
+    I.num_tiles = (int32_t)sorted.size() + small_tiles;
     I.tile_joints = cap;
     I.waves_per_tile = shape.waves;
-    I.grid = shape.grid_per_cu > 0
-                 ? (int32_t)std::min<int64_t>(sorted.size(), (int64_t)shape.grid_per_cu * plan->ctx->num_cu)
-                 : (int32_t)sorted.size();
+    I.grid = plan->main_grid + small_grid;
     I.multipass_rounds = plan->mp.rounds;
     I.max_block_chain = std::max(max_chain_tiles, max_chain_mp);
     return HS_OK;
 }
 
-hs::TileLaunch tile_launch(const hs_plan *p)
+// The main tile set (k < 0) or size class k.
+hs::TileLaunch tile_launch(const hs_plan *p, int k = -1)
 {
     hs::TileLaunch tl{};
-    tl.tiles = p->d_tiles;
-    tl.num_tiles = p->info.num_tiles;
-    tl.tile_cap = p->shape.tile_cap;
-    tl.waves = p->shape.waves;
-    tl.grid = std::max(1, p->info.grid);
+    if (k < 0) {
+        tl.tiles = p->d_tiles;
+        tl.num_tiles = (int32_t)p->h_tiles.size();
+        tl.tile_cap = p->shape.tile_cap;
+        tl.waves = p->shape.waves;
+        tl.grid = std::max(1, p->main_grid);
+    } else {
+        const auto &c = p->small[k];
+        tl.tiles = c.d_tiles;
+        tl.num_tiles = c.num_tiles;
+        tl.tile_cap = c.cap;
+        tl.waves = c.waves;
+        tl.grid = std::max(1, c.grid);
+    }
     tl.parent = p->d_parent;
     tl.chain_units = p->shape.chain_units ? 1 : 0;
     return tl;
@@ -621,7 +676,10 @@ hs_status check_pose_src(const hs_plan *plan, const hs_pose_src *src, hs::PoseAr
 hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::OutArgs &oa,
                       hipStream_t stream)
 {
-    hipError_t err = hs::launch_forward_tiles(tile_launch(plan), pa, oa, stream);
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
+        err = hs::launch_forward_tiles(tile_launch(plan, k), pa, oa, stream);
+    if (err == hipSuccess) err = hs::launch_forward_tiles(tile_launch(plan), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (tiles)");
     err = hs::launch_forward_multipass(mp_launch(plan, plan->mp), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (multipass)");
@@ -1072,7 +1130,11 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
     if (N == 0) return HS_OK;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_pose_sample: cannot select device");
-    hipError_t err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan, plan->mp), pa, quat_out, trans_out, stream);
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
+        err = hs::launch_pose_sample(tile_launch(plan, k), hs::MPLaunch{}, pa, quat_out, trans_out, stream);
+    if (err == hipSuccess)
+        err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan, plan->mp), pa, quat_out, trans_out, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_pose_sample");
     return HS_OK;
 }
