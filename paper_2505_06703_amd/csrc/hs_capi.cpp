@@ -129,7 +129,6 @@ struct MPSet {
     MPBlock *d_blocks = nullptr;
     int32_t num_blocks = 0;
     int64_t nmp = 0;
-    int32_t depth_rounds = 0;  // ceil(log2 max depth) (adjoint)
     float4 *P = nullptr;
     int32_t *d_janc = nullptr;
     int32_t *d_anchors = nullptr;
@@ -137,9 +136,9 @@ struct MPSet {
     int32_t rounds = 0;        // anchor-level jump rounds
     float4 *AP[2] = {nullptr, nullptr};
     int32_t *AE[2] = {nullptr, nullptr};
+    // adjoint: each joint's own anchor index, anchor adjoints, compact G
+    int32_t *d_aself = nullptr;
     float4 *S[2] = {nullptr, nullptr};
-    float4 *M[2] = {nullptr, nullptr};
-    int32_t *A[2] = {nullptr, nullptr};
     float4 *G = nullptr;
 };
 
@@ -149,12 +148,11 @@ void free_mpset(MPSet &m)
     (void)hipFree(m.P);
     (void)hipFree(m.d_janc);
     (void)hipFree(m.d_anchors);
+    (void)hipFree(m.d_aself);
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(m.AP[i]);
         (void)hipFree(m.AE[i]);
         (void)hipFree(m.S[i]);
-        (void)hipFree(m.M[i]);
-        (void)hipFree(m.A[i]);
     }
     (void)hipFree(m.G);
     m = MPSet{};
@@ -439,12 +437,11 @@ void build_anchors(const hs_plan *plan, const Packing &pk, std::vector<int32_t> 
 
 // Upload a packing's multipass blocks and anchors and allocate the path's
 // workspace (and the adjoint's, if asked).
-hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjoint, int depth_rounds)
+hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjoint)
 {
     free_mpset(m);
     m.num_blocks = (int32_t)pk.mpb.size();
     m.nmp = pk.nmp;
-    m.depth_rounds = depth_rounds;
     if (pk.nmp == 0) return HS_OK;
     std::vector<int32_t> janc, anchors;
     build_anchors(plan, pk, janc, anchors, m.rounds);
@@ -457,11 +454,14 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
     for (int i = 0; i < 2 && err == hipSuccess; ++i) {
         err = hipMalloc(&m.AP[i], na * 3 * sizeof(float4));
         if (err == hipSuccess) err = hipMalloc(&m.AE[i], na * sizeof(int32_t));
-        if (adjoint && err == hipSuccess) err = hipMalloc(&m.S[i], n * 3 * sizeof(float4));
-        if (adjoint && err == hipSuccess) err = hipMalloc(&m.M[i], n * 3 * sizeof(float4));
-        if (adjoint && err == hipSuccess) err = hipMalloc(&m.A[i], n * sizeof(int32_t));
+        if (adjoint && err == hipSuccess) err = hipMalloc(&m.S[i], na * 3 * sizeof(float4));
     }
     if (adjoint && err == hipSuccess) err = hipMalloc(&m.G, n * 3 * sizeof(float4));
+    if (adjoint && err == hipSuccess) {
+        std::vector<int32_t> aself((size_t)pk.nmp, -1);
+        for (size_t i = 0; i < anchors.size(); ++i) aself[anchors[i]] = (int32_t)i;
+        err = upload(&m.d_aself, aself);
+    }
     if (err != hipSuccess) {
         free_mpset(m);
         return fail_hip(err, "hs_plan_create (multipass workspace)");
@@ -539,10 +539,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         if (e2 == hipSuccess) e2 = upload(&plan->d_bbig, pb.tiles);
         if (e2 != hipSuccess) return fail_hip(e2, "hs_plan_create");
         plan->bwd_untiled = pb.nmp;
-        int max_level = 1;
-        for (const MPBlock &mb : pb.mpb)
-            for (int k = 0; k < mb.count; ++k) max_level = std::max(max_level, plan->h_level[mb.gbegin + k]);
-        hs_status rc2 = make_mpset(plan->bmp, plan, pb, true, ceil_log2(max_level));
+        hs_status rc2 = make_mpset(plan->bmp, plan, pb, true);
         if (rc2 != HS_OK) return rc2;
     }
 
@@ -551,7 +548,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     plan->d_tiles = nullptr;
     if ((err = upload(&plan->d_tiles, sorted)) != hipSuccess) return fail_hip(err, "hs_plan_create");
     plan->h_tiles = sorted;
-    hs_status rc = make_mpset(plan->mp, plan, pk, false, 0);
+    hs_status rc = make_mpset(plan->mp, plan, pk, false);
     if (rc != HS_OK) return rc;
     plan->max_units = pk.max_units;
     plan->shape = shape;
@@ -605,14 +602,12 @@ hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
     ml.anchors = m.d_anchors;
     ml.num_anchors = m.num_anchors;
     ml.rounds = m.rounds;
-    ml.depth_rounds = m.depth_rounds;
+    ml.aself = m.d_aself;
     ml.G = m.G;
     for (int i = 0; i < 2; ++i) {
         ml.AP[i] = m.AP[i];
         ml.AE[i] = m.AE[i];
         ml.S[i] = m.S[i];
-        ml.M[i] = m.M[i];
-        ml.A[i] = m.A[i];
     }
     return ml;
 }

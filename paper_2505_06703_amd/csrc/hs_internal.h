@@ -100,10 +100,8 @@ struct MPLaunch {
     float4 *AP[2];            // [num_anchors*3] ping-pong anchor products
     int32_t *AE[2];           // [num_anchors] ping-pong anchor pointers
     // adjoint workspace (NULL when the plan has none)
-    int32_t depth_rounds;     // ceil(log2 max depth) of these characters
-    float4 *S[2];             // [Nmp*3] ping-pong partial adjoints
-    float4 *M[2];             // [Nmp*3] ping-pong jump products
-    int32_t *A[2];            // [Nmp]   ping-pong jump pointers
+    const int32_t *aself;     // [Nmp] the joint's own anchor index, or -1
+    float4 *S[2];             // [num_anchors*3] ping-pong anchor adjoints
     float4 *G;                // [Nmp*3] global transforms
 };
 

@@ -1180,91 +1180,196 @@ mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
 
 // ---------------------------------------------------------------------------
 // Adjoint on the multipass path (characters larger than an adjoint tile).
-// The global transforms come from the forward multipass; the adjoint is the
-// reverse pointer jumping of the tiled kernel done over HBM: per round every
-// joint adds S(j) (.) M(j) into its current jump target with global float
-// atomics, while M and the targets double (Wyllie), for ceil(log2 depth)
-// rounds.
+//
+// With D the incoming dLoss/dG, the in-block adjoint Z = R_B(Y) of a block
+// sums Y over in-block subtrees (Z_j = Y_j + sum over in-block children c of
+// Z_c (.) L_c).  A head h (parent outside the block, an anchor e) hands
+// X_h (.) L_h to e.  Writing U_e for what anchor e receives from all its
+// out-of-block children, and P_a for an anchor's phase-1 product (the local
+// transforms from its own anchor e_a, exclusive, down to a):
+//     U_e = B_e + sum over anchors a with e_a = e of  U_a (.) P_a,
+//     B_e = sum over heads h with parent e of  R_B(D)_h (.) L_h,
+// the adjoint recursion again, on the anchor tree with P as the locals; and
+// X = R_B(D + U) block by block.  So: R_B(D) with heads pushing into B
+// (global float atomics, one push per head), reverse pointer jumping over
+// the anchors, then R_B(D + U) and the gradients.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kMPWaves * kWave)
-mpb_init_kernel(MPLaunch ml, PoseArgs pose, BwdArgs bwd)
+__device__ __forceinline__ void wave_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// R_B for one 64-joint block held by one wave: S in (Y_j), S out (Z_j).
+// a: lane of the in-block parent, or -1.  Reverse pointer jumping over the
+// in-block ancestors with the forward doubling alongside, collisions
+// resolved with owner words as in the tiled adjoint.  Wave-private LDS:
+// Ms[64][3], Sa[64][3] float4, Ac[64], Own[64] int.
+__device__ __forceinline__ void wave_block_reverse(float S[12], const float L[12], int a, int lane, float4 *Ms,
+                                                   float4 *Sa, int *Ac, int *Own)
+{
+    float M[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) M[k] = L[k];
+    aff_store(Ms + 3 * lane, M);
+    aff_store(Sa + 3 * lane, S);
+    Ac[lane] = a;
+    owner_claim(Own + lane, -1);
+    wave_sync();
+    if (a >= 0) owner_claim(Own + a, lane);
+    wave_sync();
+#pragma unroll 1
+    for (int r = 0; r < 6; ++r) {
+        if (!__any(a >= 0)) break;
+        const int tag = r << kOwnerShift;
+        int aa = -1;
+        bool lose = false;
+        float c[12];
+        if (a >= 0) {
+            adj_pull(S, M, c);
+            lose = owner_read(Own + a) != (tag | lane);
+            if (!lose) {
+                float acc[12];
+                aff_load(Sa + 3 * a, acc);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] += c[k];
+                aff_store(Sa + 3 * a, acc);
+            }
+            float ma[12];
+            aff_load(Ms + 3 * a, ma);
+            aa = Ac[a];
+            aff_mul_left(ma, M);
+        }
+        wave_sync();
+        if (lose) lds_atomic_add12(Sa + 3 * a, c);
+        const bool recv = (owner_read(Own + lane) >> kOwnerShift) == r;
+        wave_sync();
+        if (recv) aff_load(Sa + 3 * lane, S);
+        if (a >= 0) {
+            a = aa;
+            aff_store(Ms + 3 * lane, M);
+            Ac[lane] = a;
+            if (a >= 0) owner_claim(Own + a, (tag + (1 << kOwnerShift)) | lane);
+        }
+        wave_sync();
+    }
+}
+
+constexpr int kRevWaveFloat4 = 64 * 6 + 32;  // per-wave LDS of wave_block_reverse, in float4
+
+// FINAL = false: R_B(D) per block, heads push into the anchor accumulators
+// Sanc.  FINAL = true: R_B(D + U) with U = Sanc injected at the anchors, then
+// the gradients (the parent's global transform from the compact table G).
+template <bool FINAL>
+__global__ void __launch_bounds__(kMPWaves * kWave)
+mpr_block_kernel(MPLaunch ml, PoseArgs pose, BwdArgs bwd, float4 *Sanc)
+{
+    extern __shared__ float4 lds[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
-    if (w >= ml.num_blocks) return;
+    const int wv = threadIdx.x / kWave;
+    float4 *Ms = lds + wv * kRevWaveFloat4;
+    float4 *Sa = Ms + 3 * kWave;
+    int *Ac = reinterpret_cast<int *>(Sa + 3 * kWave);
+    int *Own = Ac + kWave;
+    const int w = blockIdx.x * kMPWaves + wv;
+    if (w >= ml.num_blocks) return;  // whole waves leave together; no workgroup barriers here
     const MPBlock bd = ml.blocks[w];
-    if (lane >= bd.count) return;
+    const bool valid = lane < bd.count;
     const int64_t gid = bd.gbegin + lane;
     const int64_t cid = bd.cbegin + lane;
-    const int p = ml.parent[gid];
-    float L[12], d[12];
-    load_local<false>(pose, gid, 0, 0, L);
-    aff_store(ml.M[0] + 3 * cid, L);
-    aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, d);
-    aff_store(ml.S[0] + 3 * cid, d);
-    ml.A[0][cid] = p < 0 ? -1 : (int32_t)(p - bd.gbegin + bd.cbegin);
+    int a = -1, p = -1;
+    bool head = false;
+    float L[12], S[12];
+    if (valid) {
+        p = ml.parent[gid];
+        if (p >= 0) {
+            if (p >= bd.gbegin) a = (int)(p - bd.gbegin); else head = true;
+        }
+        load_local<false>(pose, gid, 0, 0, L);
+        aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
+        if constexpr (FINAL) {
+            const int ai = ml.aself[cid];
+            if (ai >= 0) {
+                float u[12];
+                aff_load(Sanc + 3 * ai, u);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) S[k] += u[k];
+            }
+        }
+    } else {
+        aff_identity(L);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) S[k] = 0.0f;
+    }
+    wave_block_reverse(S, L, a, lane, Ms, Sa, Ac, Own);
+    if constexpr (!FINAL) {
+        if (valid && head) {
+            float c[12];
+            adj_pull(S, L, c);
+            float *dst = reinterpret_cast<float *>(Sanc + 3 * (int64_t)ml.janc[cid]);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) atomicAdd(dst + k, c[k]);
+        }
+    } else if (valid) {
+        float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+        if (p >= 0) {
+            float g[12];
+            aff_load(ml.G + 3 * (bd.cbegin + (p - bd.gbegin)), g);  // same character
+            Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
+            Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
+            Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
+        }
+        const float4 q = reinterpret_cast<const float4 *>(pose.quat)[gid];
+        float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+        if (pose.scale) {
+            const float *sp = pose.scale + 3 * gid;
+            sx = sp[0]; sy = sp[1]; sz = sp[2];
+        }
+        write_grads(bwd, gid, S, Ap, q, sx, sy, sz);
+    }
 }
 
 __global__ void __launch_bounds__(256)
-mpb_copy_kernel(int64_t n4, const float4 *src, float4 *dst)
+mpr_fill_zero_kernel(int64_t n4, float4 *dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) dst[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+__global__ void __launch_bounds__(256)
+mpr_copy_kernel(int64_t n4, const float4 *src, float4 *dst)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n4) dst[i] = src[i];
 }
 
+// One reverse round over the anchor tree: anchor i adds S_r(i) (.) M_r(i)
+// into its current target (global float atomics into the next buffer,
+// which starts as a copy of S_r), while M and the targets double.
 __global__ void __launch_bounds__(256)
-mpb_round_kernel(int64_t nmp, const float4 *S, const float4 *M, const int32_t *A, float4 *Snext, float4 *Mnext,
-                 int32_t *Anext)
+mpr_anchor_round_kernel(int32_t na, const float4 *S, const float4 *M, const int32_t *A, float4 *Snext,
+                        float4 *Mnext, int32_t *Anext)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nmp) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= na) return;
     float m[12];
     aff_load(M + 3 * i, m);
-    const int a = A[i];
-    if (a >= 0) {
+    const int t = A[i];
+    if (t >= 0) {
         float x[12], c[12], g[12];
         aff_load(S + 3 * i, x);
         adj_pull(x, m, c);
-        float *dst = reinterpret_cast<float *>(Snext + 3 * (int64_t)a);
+        float *dst = reinterpret_cast<float *>(Snext + 3 * t);
 #pragma unroll
         for (int k = 0; k < 12; ++k) atomicAdd(dst + k, c[k]);
-        aff_load(M + 3 * (int64_t)a, g);
+        aff_load(M + 3 * t, g);
         aff_mul_left(g, m);
-        Anext[i] = A[a];
+        Anext[i] = A[t];
     } else {
         Anext[i] = -1;
     }
     aff_store(Mnext + 3 * i, m);
-}
-
-__global__ void __launch_bounds__(kMPWaves * kWave)
-mpb_grads_kernel(MPLaunch ml, PoseArgs pose, BwdArgs bwd, const float4 *S)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
-    if (w >= ml.num_blocks) return;
-    const MPBlock bd = ml.blocks[w];
-    if (lane >= bd.count) return;
-    const int64_t gid = bd.gbegin + lane;
-    const int64_t cid = bd.cbegin + lane;
-    const int p = ml.parent[gid];
-    float X[12];
-    aff_load(S + 3 * cid, X);
-    float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
-    if (p >= 0) {
-        float g[12];
-        aff_load(ml.G + 3 * (p - bd.gbegin + bd.cbegin), g);
-        Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
-        Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
-        Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
-    }
-    const float4 q = reinterpret_cast<const float4 *>(pose.quat)[gid];
-    float sx = 1.0f, sy = 1.0f, sz = 1.0f;
-    if (pose.scale) {
-        const float *sp = pose.scale + 3 * gid;
-        sx = sp[0]; sy = sp[1]; sz = sp[2];
-    }
-    write_grads(bwd, gid, X, Ap, q, sx, sy, sz);
 }
 
 // ---------------------------------------------------------------------------
@@ -1543,29 +1648,37 @@ hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, c
                                      hipStream_t stream)
 {
     if (ml.num_blocks == 0) return hipSuccess;
-    if (!ml.G || !ml.S[0]) return hipErrorNotSupported;
+    if (!ml.G || !ml.aself || (ml.num_anchors > 0 && !ml.S[0])) return hipErrorNotSupported;
     const dim3 blk(kMPWaves * kWave);
     const dim3 grid((ml.num_blocks + kMPWaves - 1) / kMPWaves);
-    const dim3 egrid((unsigned)((ml.nmp + 255) / 256));
-    const dim3 cgrid((unsigned)((3 * ml.nmp + 255) / 256));
+    const size_t lds = (size_t)kMPWaves * kRevWaveFloat4 * sizeof(float4);
     hipError_t err;
-    // global transforms of the multipass characters, compact layout
+    // global transforms of the multipass characters (compact), and P
     if ((err = run_multipass(ml, pose, OutArgs{}, ml.G, stream)) != hipSuccess) return err;
-    // reverse pointer jumping over HBM
-    hipLaunchKernelGGL(mpb_init_kernel, grid, blk, 0, stream, ml, pose, bwd);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int na = ml.num_anchors;
+    const dim3 agrid((unsigned)((na + 255) / 256));
+    const dim3 cgrid((unsigned)((3 * (int64_t)na + 255) / 256));
     int cur = 0;
-    for (int r = 0; r < ml.depth_rounds; ++r) {
-        hipLaunchKernelGGL(mpb_copy_kernel, cgrid, dim3(256), 0, stream, 3 * ml.nmp, ml.S[cur], ml.S[cur ^ 1]);
+    if (na > 0) {
+        hipLaunchKernelGGL(mpr_fill_zero_kernel, cgrid, dim3(256), 0, stream, 3 * (int64_t)na, ml.S[0]);
         if ((err = hipGetLastError()) != hipSuccess) return err;
-        hipLaunchKernelGGL(mpb_round_kernel, egrid, dim3(256), 0, stream, ml.nmp, ml.S[cur], ml.M[cur], ml.A[cur],
-                           ml.S[cur ^ 1], ml.M[cur ^ 1], ml.A[cur ^ 1]);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
-        cur ^= 1;
     }
-    hipLaunchKernelGGL(mpb_grads_kernel, grid, blk, 0, stream, ml, pose, bwd, ml.S[cur]);
+    hipLaunchKernelGGL(mpr_block_kernel<false>, grid, blk, lds, stream, ml, pose, bwd, ml.S[0]);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (na > 0) {
+        hipLaunchKernelGGL(mp_anchor_gather_kernel, agrid, dim3(256), 0, stream, ml);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        for (int r = 0; r < ml.rounds; ++r) {
+            hipLaunchKernelGGL(mpr_copy_kernel, cgrid, dim3(256), 0, stream, 3 * (int64_t)na, ml.S[cur], ml.S[cur ^ 1]);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            hipLaunchKernelGGL(mpr_anchor_round_kernel, agrid, dim3(256), 0, stream, na, ml.S[cur], ml.AP[cur],
+                               ml.AE[cur], ml.S[cur ^ 1], ml.AP[cur ^ 1], ml.AE[cur ^ 1]);
+            if ((err = hipGetLastError()) != hipSuccess) return err;
+            cur ^= 1;
+        }
+    }
+    hipLaunchKernelGGL(mpr_block_kernel<true>, grid, blk, lds, stream, ml, pose, bwd, ml.S[cur]);
     return hipGetLastError();
 }
-
 
 } // namespace hs

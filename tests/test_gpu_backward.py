@@ -187,3 +187,34 @@ def test_autograd_matches_oracle_in_both_modes():
         ref = oracle.backward(b.offsets, b.parents, b.quat, b.trans, None, W)
         check_grads(b.offsets, [q.grad.cpu().numpy(), t.grad.cpu().numpy(), None], ref, f"autograd k={k}")
         np.testing.assert_allclose(Gg[eff, :3, 3], G64[eff, :3, 3], atol=1e-4 * 30)
+
+
+def test_multipass_adjoint_comb_with_shared_anchors():
+    """A 20 000-joint spine with a 150-joint side chain hung every 300 joints,
+    plus fingers of 3 joints every 50: blocks with several heads, heads of
+    different blocks on one anchor, anchor chains across hundreds of blocks
+    (the anchor-level reverse scan and its fan-in)."""
+    rng = np.random.default_rng(11)
+    par = list(range(-1, 19999))
+    for base in range(300, 20000, 300):
+        start = len(par)
+        par.append(base)
+        par.extend(range(start, start + 149))
+    for base in range(50, 20000, 50):
+        start = len(par)
+        par.append(base)
+        par.extend(range(start, start + 2))
+    par = np.array(par, np.int32)
+    n = par.size
+    q, t, s = wl.random_pose(rng, n, max_angle=0.02)
+    b = wl.Batch("comb", np.array([0, n], np.int64), par, q, t, s, q, t, s)
+    W = np.zeros((n, 4, 4), np.float32)
+    idx = rng.choice(n, 400, replace=False)
+    W[idx, :3, :] = rng.standard_normal((400, 3, 4)).astype(np.float32) * 0.1
+    got = run(b, W)
+    ref = oracle_grads(b, W)
+    for name, g, r in zip(("quat", "trans", "scale"), got, ref):
+        g = np.asarray(g, np.float64)
+        tol = TOL * max(1.0, float(np.abs(r).max())) * np.sqrt(20000 / 2048)
+        err = float(np.abs(g - r).max())
+        assert err <= tol, f"{name}: {err:.3e} > {tol:.3e}"
