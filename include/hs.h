@@ -245,8 +245,13 @@ void hs_graph_destroy(hs_graph *graph);
  * bottom row is constant), writes dLoss/dq (grad_quat [N,4], derivative of
  * the rotation polynomial in the raw quaternion components), dLoss/dt
  * (grad_trans [N,3]) and, if non-NULL, dLoss/ds (grad_scale [N,3]).  The
- * global transforms the adjoint needs are recomputed on chip (ckpt NULL) or
- * rebuilt from the checkpoints hs_scan_forward stored with the same ckpt_k.
+ * global transforms the adjoint needs are recomputed (ckpt NULL) or, for
+ * characters of 1025-1664 joints, rebuilt from the checkpoints that
+ * hs_scan_forward stored with the same ckpt_k; characters of up to 1024
+ * joints get them as a by-product of the adjoint's own doubling, and larger
+ * ones from one forward pass over their anchors, so ckpt is not read there.
+ * The results agree up to rounding either way.  Not bitwise reproducible
+ * across runs where pushes collide (float atomics).
  * src must be HS_POSE_TRS.  flags must be 0. */
 hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const float *grad_global,
                            const float *ckpt, int32_t ckpt_k, float *grad_quat, float *grad_trans,
