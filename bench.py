@@ -98,6 +98,9 @@ def parse():
                     help="use the plan's default launch shape instead of timing candidates at plan time")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--depth-sweep", action="store_true",
+                    help="the paper's depth experiment: 10000 characters of 300 joints, depth 15..120, "
+                         "this library's scan against the paper's Algorithms 1-4; one JSON line per point")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE run, WRITE_SIZE run) "
                          "into profiles/traffic.json for --workload and exit")
@@ -311,6 +314,9 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.depth_sweep:
+        depth_sweep(args)
+        return
     w = Workload(args.workload, autotune=not args.no_autotune)
     b, info = w.b, w.plan.info
     N, C = b.num_joints, b.num_characters
@@ -382,6 +388,44 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["err_vs_fp64"] = cpu_baseline(w)
     print(json.dumps(out))
+
+
+ALG_NAMES = ["scan (this library)", "1: walk to root", "2: pointer jumping", "3: blocks + walk",
+             "4: window + hops + walk"]
+
+
+def depth_sweep(args):
+    """Forward time per step for each depth and tile algorithm (inputs in
+    HBM, two input sets alternating, eight passes per graph replay)."""
+    import torch
+    from paper_2505_06703_amd import hs
+    from paper_2505_06703_amd import workloads as wl
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for depth in (15, 30, 60, 90, 120):
+        b = wl.depth_sweep(depth=depth)
+        N = b.num_joints
+        sets = [dict(quat=up(b.quat), trans=up(b.trans), scale=up(b.scale),
+                     global_out=torch.empty((N, 4, 4), device="cuda:0")) for _ in range(2)]
+        for alg in range(5):
+            plan = hs.Plan(b.offsets, b.parents, algorithm=alg, autotune=(alg == 0 and not args.no_autotune))
+            g = hs.ForwardGraph.sequence(plan, [sets[k % 2] for k in range(CHUNK)])
+            reps = max(1, args.steps // CHUNK)
+            for _ in range(max(1, args.warmup // CHUNK)):
+                g.launch()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                g.launch()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (reps * CHUNK)
+            print(json.dumps({"depth": depth, "algorithm": ALG_NAMES[alg], "characters": b.num_characters,
+                              "joints": N, "us_per_step": ms * 1e3, "joints_per_s": N / (ms * 1e-3),
+                              "hbm_frac": N * BYTES_PER_JOINT["deep_forward"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "tile_joints": plan.info["tile_joints"]}), flush=True)
+            g.close()
+            plan.close()
 
 
 def device_copy_gbs(torch, nbytes=1 << 30, reps=10):

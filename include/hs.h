@@ -109,8 +109,24 @@ typedef struct hs_plan_opts {
     int32_t chain_units;    /* non-zero: scan runs of up to four 64-joint blocks that consist of
                                whole chain segments with four joints per lane (a sequential
                                product per lane and a segmented scan across the wave) */
-    int32_t reserved[2];    /* must be zero */
+    int32_t algorithm;      /* HS_ALG_*: the scan that tiles run (forward, stored TRS poses) */
+    int32_t reserved[1];    /* must be zero */
 } hs_plan_opts;
+
+/* Tile algorithms.  HS_ALG_SCAN is this library's scan (wave-level pointer
+ * jumping per 64-joint block, dataflow between blocks).  HS_ALG_WALK ..
+ * HS_ALG_COMPRESSED are the paper's Algorithms 1-4 (per-joint walk to the
+ * root, Sec. 2; barrier-synchronous pointer jumping, Sec. 3.1, Eq. 2;
+ * 64-joint blocks with a walk over out-of-block partials, Sec. 3.2.1; the
+ * 8-joint window and hops of 8, Sec. 3.2.2), one joint per thread on tiles
+ * of at most 1024 joints, kept for comparison on this hardware.  They need
+ * HS_POSE_TRS sources (HS_ERR_UNSUPPORTED otherwise) and no chain units;
+ * characters larger than 1024 joints take the multipass path. */
+#define HS_ALG_SCAN 0
+#define HS_ALG_WALK 1
+#define HS_ALG_JUMP 2
+#define HS_ALG_BLOCKS 3
+#define HS_ALG_COMPRESSED 4
 
 typedef struct hs_plan_info {
     int64_t num_characters;

@@ -111,6 +111,7 @@ struct Shape {
     int waves = 0;
     int grid_per_cu = 0;  // 0 = one workgroup per tile
     bool chain_units = false;
+    int algorithm = HS_ALG_SCAN;
 };
 
 } // namespace
@@ -587,6 +588,7 @@ hs::TileLaunch tile_launch(const hs_plan *p, int k = -1)
     }
     tl.parent = p->d_parent;
     tl.chain_units = p->shape.chain_units ? 1 : 0;
+    tl.algorithm = p->shape.algorithm;
     return tl;
 }
 
@@ -808,6 +810,8 @@ hs_status prepare_forward(const hs_plan *plan, const hs_pose_src *src, float *gl
     std::vector<Range> ins;
     hs_status rc = check_pose_src(plan, src, pa, ins, true);
     if (rc != HS_OK) return rc;
+    if (plan->shape.algorithm != HS_ALG_SCAN && src->kind != HS_POSE_TRS)
+        return fail(HS_ERR_UNSUPPORTED, "hs_scan_forward: the paper's algorithms take stored TRS poses only");
     const size_t N = (size_t)plan->N;
     ins.push_back({inv_bind, N * 64, "inv_bind"});
     std::vector<Range> outs = {{global_out, N * 64, "global_out"}, {skin_out, N * 64, "skin_out"},
@@ -888,6 +892,10 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
         o.waves_per_tile != 8 && o.waves_per_tile != 16)
         return fail(HS_ERR_INVALID_ARG, "waves_per_tile must be 0, 1, 2, 4, 8 or 16");
     if (o.grid_tiles < 0 || o.grid_tiles > 64) return fail(HS_ERR_INVALID_ARG, "grid_tiles must be in [0, 64]");
+    if (o.algorithm < HS_ALG_SCAN || o.algorithm > HS_ALG_COMPRESSED)
+        return fail(HS_ERR_INVALID_ARG, "unknown algorithm %d", o.algorithm);
+    if (o.algorithm != HS_ALG_SCAN && o.chain_units)
+        return fail(HS_ERR_INVALID_ARG, "chain units belong to the library's own scan (algorithm 0)");
 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_plan_create: cannot select device %d", ctx->device);
@@ -972,9 +980,20 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
 
     sh.grid_per_cu = o.grid_tiles;
     sh.chain_units = o.chain_units != 0;
+    sh.algorithm = o.algorithm;
+    if (sh.algorithm != HS_ALG_SCAN) {
+        // the paper's algorithms: one joint per thread, 1024-thread workgroups
+        if (o.strategy == HS_STRATEGY_TILE && min_cap > hs::kPaperAlgTileJoints) {
+            free_plan(plan);
+            return fail(HS_ERR_UNSUPPORTED, "the paper's algorithms tile characters of at most %d joints",
+                        hs::kPaperAlgTileJoints);
+        }
+        sh.tile_cap = std::min(sh.tile_cap, hs::kPaperAlgTileJoints);
+        sh.waves = 16;
+    }
 
     hs_status rc = build_tables(plan, sh, o.strategy);
-    if (rc == HS_OK && o.waves_per_tile == 0 && plan->max_units > 0) {
+    if (rc == HS_OK && sh.algorithm == HS_ALG_SCAN && o.waves_per_tile == 0 && plan->max_units > 0) {
         // no more waves than work units in the largest tile; tiles small
         // enough for three workgroups per CU take 8 waves (measured faster
         // than 16 on the deep workload: more workgroups overlap their phases)
@@ -986,7 +1005,7 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
             rc = build_tables(plan, sh, o.strategy);
         }
     }
-    if (rc == HS_OK && o.autotune && N > 0) rc = autotune(plan, sh, o.strategy);
+    if (rc == HS_OK && o.autotune && N > 0 && sh.algorithm == HS_ALG_SCAN) rc = autotune(plan, sh, o.strategy);
     if (rc != HS_OK) {
         free_plan(plan);
         return rc;

@@ -83,6 +83,7 @@ struct TileLaunch {
     int32_t grid;       // workgroups
     const int32_t *parent; // [N] global parent id or -1
     int32_t chain_units;   // tiles carry chain-unit marks
+    int32_t algorithm;     // 0: this library's scan; 1-4: the paper's Algorithms 1-4
 };
 
 struct MPLaunch {
@@ -134,9 +135,13 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 // needs (once per process and device, before any launch or capture).
 hipError_t prepare_kernels();
 
+// Tiles of the paper's Algorithms 1-4 (one joint per thread).
+constexpr int kPaperAlgTileJoints = 1024;
+
 // LDS bytes one tiled-forward workgroup needs.
 size_t forward_tile_lds_bytes(int tile_cap, bool sample);
 size_t backward_tile_lds_bytes(int tile_cap);
 size_t backward_sync_lds_bytes(int tile_cap);
+size_t paper_alg_lds_bytes(int tile_cap, int alg);
 
 } // namespace hs

@@ -675,6 +675,182 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 }
 
 // ---------------------------------------------------------------------------
+// The paper's Algorithms 1-4 as tile kernels (plan option `algorithm`), for
+// comparison with the scan above on this hardware.  One workgroup of 1024
+// threads per tile, one joint per thread, the tile's local transforms in
+// LDS, barriers where the algorithms synchronise, coalesced row stores at
+// the end.  Rounds are synchronous (read phase, barrier, write phase), the
+// reading under which the printed in-place updates do not race.
+//   1 (Sec. 2): every joint walks to its root, multiplying the ancestors'
+//     local transforms on the left.
+//   2 (Sec. 3.1, Eq. 2): pointer jumping over the whole tile,
+//     ceil(log2 depth) rounds.
+//   3 (Sec. 3.2.1): blocks of 64; log2(64) = 6 rounds of pointer jumping over
+//     in-block ancestors; then each joint walks its chain of nearest
+//     out-of-block ancestors (MaxParentOutBlock), multiplying their in-block
+//     partial products.
+//   4 (Sec. 3.2.2): in-block, up to 7 single parent steps (a window of 8),
+//     then up to 7 hops of 8 levels over those windows; then the walk of 3.
+// LDS: A[cap][3] float4 | B[cap][3] float4 (Algorithm 4) | par, up, mpob [cap] int
+// ---------------------------------------------------------------------------
+template <int ALG>
+__global__ void __launch_bounds__(1024)
+paper_alg_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
+{
+    extern __shared__ float4 lds[];
+    const int cap = tl.tile_cap;
+    float4 *As = lds;
+    float4 *Bs = lds + 3 * cap;
+    int *par = reinterpret_cast<int *>(lds + (ALG == 4 ? 6 : 3) * cap);
+    int *up = par + cap;
+    int *mp = up + cap;
+    const int jl = threadIdx.x;
+    constexpr int kBlock = 64;
+
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        const bool live = jl < td.count;
+        const int64_t gid = td.begin + jl;
+        float L[12];
+        int p = -1;
+        if (live) {
+            const int pg = tl.parent[gid];
+            p = pg < 0 ? -1 : (int)(pg - td.begin);
+            load_local<false>(pose, gid, 0, 0, L);
+            aff_store(As + 3 * jl, L);
+            par[jl] = p;
+        } else {
+            aff_identity(L);
+        }
+        __syncthreads();
+        float m[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m[k] = L[k];
+
+        if constexpr (ALG == 1) {
+            if (live) {
+                int cur = p;
+                for (int guard = 0; cur >= 0 && guard < cap; ++guard) {
+                    float g[12];
+                    aff_load(As + 3 * cur, g);
+                    aff_mul_left(g, m);
+                    cur = par[cur];
+                }
+            }
+        } else if constexpr (ALG == 2) {
+            int a = p;
+            if (live) up[jl] = a;
+            for (int r = 0; r < td.rounds; ++r) {
+                __syncthreads();
+                int aa = -1;
+                if (a >= 0) {
+                    float g[12];
+                    aff_load(As + 3 * a, g);
+                    aa = up[a];
+                    aff_mul_left(g, m);
+                }
+                __syncthreads();
+                if (a >= 0) {
+                    a = aa;
+                    aff_store(As + 3 * jl, m);
+                    up[jl] = a;
+                }
+            }
+        } else {
+            // in-block parent pointer (-1 at a block boundary or a root) and
+            // the nearest out-of-block ancestor (the parent of the topmost
+            // in-block ancestor), found by the same rounds
+            const int base = jl & ~(kBlock - 1);
+            int a = (p >= base) ? p : -1;
+            int e = (p >= 0 && p < base) ? p : -1;
+            if (live) {
+                up[jl] = a;
+                mp[jl] = e;
+            }
+            if constexpr (ALG == 3) {
+#pragma unroll 1
+                for (int r = 0; r < 6; ++r) {
+                    __syncthreads();
+                    int aa = -1, ea = -1;
+                    if (a >= 0) {
+                        float g[12];
+                        aff_load(As + 3 * a, g);
+                        aa = up[a];
+                        ea = mp[a];
+                        aff_mul_left(g, m);
+                    }
+                    __syncthreads();
+                    if (a >= 0) {
+                        if (aa < 0) e = ea;
+                        a = aa;
+                        aff_store(As + 3 * jl, m);
+                        up[jl] = a;
+                        mp[jl] = e;
+                    }
+                }
+            } else {
+                // window: up to 7 single steps over the untouched locals
+                int cur = a;
+                for (int s = 0; s < 7 && cur >= 0; ++s) {
+                    float g[12];
+                    aff_load(As + 3 * cur, g);
+                    aff_mul_left(g, m);
+                    if (up[cur] < 0) e = mp[cur];
+                    cur = up[cur];
+                }
+                // cur: the in-block ancestor 8 levels up (or -1)
+                if (live) aff_store(Bs + 3 * jl, m);
+                __syncthreads();
+                // hops of 8 over the windows (read-only during this phase)
+                for (int h = 0; h < 7 && cur >= 0; ++h) {
+                    float g[12];
+                    aff_load(Bs + 3 * cur, g);
+                    aff_mul_left(g, m);
+                    int nxt = cur;
+                    for (int s = 0; s < 8 && nxt >= 0; ++s) {
+                        if (up[nxt] < 0) e = mp[nxt];
+                        nxt = up[nxt];
+                    }
+                    cur = nxt;
+                }
+                __syncthreads();
+                if (live) {
+                    aff_store(As + 3 * jl, m);
+                    mp[jl] = e;
+                }
+            }
+            // the walk over out-of-block ancestors' partials (a snapshot)
+            __syncthreads();
+            if (live) {
+                int cur = e;
+                for (int guard = 0; cur >= 0 && guard < cap; ++guard) {
+                    float g[12];
+                    aff_load(As + 3 * cur, g);
+                    aff_mul_left(g, m);
+                    cur = mp[cur];
+                }
+            }
+        }
+        // outputs: the final transforms through LDS for coalesced row stores
+        __syncthreads();
+        if (live) aff_store(As + 3 * jl, m);
+        __syncthreads();
+        if (out.global_out) {
+            const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * td.begin;
+            for (int c = jl; c < 4 * td.count; c += 1024) {
+                const int r = c & 3;
+                float4 v = As[3 * (c >> 2) + (r == 3 ? 0 : r)];
+                if (r == 3) v = bottom;
+                dst[c] = v;
+            }
+        }
+        if (live) write_skin_and_ckpt(out, gid, m);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint of the scan (tiled).
 //
 // For G_j = G_p L_j the adjoint X_j of G_j (rows 0-2, a 3x4 matrix; the
@@ -1478,8 +1654,19 @@ hipError_t set_lds_limits()
         if (err != hipSuccess) return err;
     }
     const int bs = (int)backward_sync_lds_bytes(std::min(kMaxSyncTileJoints, WAVES * kWave));
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bs);
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, bs);
+    if (err != hipSuccess || WAVES != 16) return err;
+    const void *pk[4] = {reinterpret_cast<const void *>(paper_alg_kernel<1>),
+                         reinterpret_cast<const void *>(paper_alg_kernel<2>),
+                         reinterpret_cast<const void *>(paper_alg_kernel<3>),
+                         reinterpret_cast<const void *>(paper_alg_kernel<4>)};
+    for (int k = 0; k < 4; ++k) {
+        err = hipFuncSetAttribute(pk[k], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)paper_alg_lds_bytes(kPaperAlgTileJoints, k + 1));
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 } // namespace
@@ -1501,10 +1688,31 @@ size_t forward_tile_lds_bytes(int tile_cap, bool sample)
     return bytes;
 }
 
+size_t paper_alg_lds_bytes(int tile_cap, int alg)
+{
+    return (size_t)tile_cap * ((alg == 4 ? 96 : 48) + 3 * 4);
+}
+
+hipError_t launch_paper_alg(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out, hipStream_t stream)
+{
+    if (tl.tile_cap > kPaperAlgTileJoints || pose.kind != 0) return hipErrorInvalidValue;
+    const size_t lds = paper_alg_lds_bytes(tl.tile_cap, tl.algorithm);
+    const dim3 grid(tl.grid), blk(1024);
+    switch (tl.algorithm) {
+    case 1: hipLaunchKernelGGL(paper_alg_kernel<1>, grid, blk, lds, stream, tl, pose, out); break;
+    case 2: hipLaunchKernelGGL(paper_alg_kernel<2>, grid, blk, lds, stream, tl, pose, out); break;
+    case 3: hipLaunchKernelGGL(paper_alg_kernel<3>, grid, blk, lds, stream, tl, pose, out); break;
+    case 4: hipLaunchKernelGGL(paper_alg_kernel<4>, grid, blk, lds, stream, tl, pose, out); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                                 hipStream_t stream)
 {
     if (tl.num_tiles == 0) return hipSuccess;
+    if (tl.algorithm != 0) return launch_paper_alg(tl, pose, out, stream);
     const bool sample = pose.kind == 1;
     if (tl.chain_units)
         return sample ? launch_fwd_tiles_w<true, true>(tl, pose, out, stream)

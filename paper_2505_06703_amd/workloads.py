@@ -341,6 +341,37 @@ def long_chains(seed=5, num_characters=64, chain_len=65536, angle=0.01):
     return Batch("long_chains", offsets, parents, q, t, s, rq, rt, rs)
 
 
+def depth_tree(rng, n, depth):
+    """A tree of n joints and exactly `depth` levels: a spine from the root,
+    then every further joint under a uniformly drawn earlier joint whose
+    level is below `depth`."""
+    depth = max(1, min(depth, n))
+    par = np.empty(n, np.int32)
+    lev = np.empty(n, np.int64)
+    par[0], lev[0] = -1, 1
+    for i in range(1, depth):
+        par[i], lev[i] = i - 1, i + 1
+    for i in range(depth, n):
+        cand = np.nonzero(lev[:i] < depth)[0]
+        p = int(cand[rng.integers(0, cand.size)])
+        par[i], lev[i] = p, lev[p] + 1
+    return par
+
+
+def depth_sweep(seed=6, num_characters=10000, joints=300, depth=60, templates=64):
+    """The paper's experiment scene (Sec. 4): characters of about 300 joints,
+    hierarchies of a chosen depth (15 to 120 in the sweep); 64 seeded
+    topologies cycled over the characters, poses as in plain_scan."""
+    rng = np.random.default_rng(seed * 1000 + depth)
+    tmpl = [depth_tree(rng, joints, depth) for _ in range(min(templates, num_characters))]
+    parents = np.concatenate([tmpl[c % len(tmpl)] for c in range(num_characters)]).astype(np.int32)
+    offsets = np.arange(num_characters + 1, dtype=np.int64) * joints
+    N = int(offsets[-1])
+    q, t, s = random_pose(rng, N)
+    rq, rt, rs = random_pose(rng, N)
+    return Batch("depth_sweep", offsets, parents, q, t, s, rq, rt, rs)
+
+
 PRESETS = {
     "plain_scan": plain_scan,
     "deep_forward": deep_forward,
@@ -348,6 +379,7 @@ PRESETS = {
     "fused_sample": fused_sample,
     "differentiable": differentiable,
     "long_chains": long_chains,
+    "depth_sweep": depth_sweep,
 }
 
 

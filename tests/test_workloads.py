@@ -75,3 +75,10 @@ def test_long_chains_small():
     q = b.quat.astype(np.float64)
     ang = 2 * np.arccos(np.clip(np.abs(q[:, 3]), 0, 1))
     assert ang.max() <= 0.01 + 2e-4  # fp32 arccos near 1 loses ~1e-4
+
+
+def test_depth_sweep_depths():
+    for d in (15, 120):
+        b = wl.depth_sweep(num_characters=5, depth=d, templates=5)
+        _valid(b)
+        assert b.num_joints == 1500 and b.depth() == d
