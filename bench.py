@@ -96,6 +96,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the plan's default launch shape instead of timing candidates at plan time")
+    ap.add_argument("--adjoint", default="auto", choices=("auto", "rounds", "dataflow"),
+                    help="adjoint kernel for characters of up to 1024 joints (differentiable workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--depth-sweep", action="store_true",
@@ -151,7 +153,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
 class Workload:
     """Device-resident inputs/outputs of one preset and its step."""
 
-    def __init__(self, name, autotune):
+    def __init__(self, name, autotune, adjoint="auto"):
         import torch
         from paper_2505_06703_amd import hs
         from paper_2505_06703_amd import workloads as wl
@@ -160,7 +162,8 @@ class Workload:
         up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         self.b = b = wl.make(name)
         N = b.num_joints
-        self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune)
+        adj = {"auto": hs.HS_ADJ_AUTO, "rounds": hs.HS_ADJ_ROUNDS, "dataflow": hs.HS_ADJ_DATAFLOW}[adjoint]
+        self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune, adjoint=adj)
         self.inv = None
         self.clips = None
         if name in ("plain_scan", "fused_sample"):
@@ -317,7 +320,7 @@ def main():
     if args.depth_sweep:
         depth_sweep(args)
         return
-    w = Workload(args.workload, autotune=not args.no_autotune)
+    w = Workload(args.workload, autotune=not args.no_autotune, adjoint=args.adjoint)
     b, info = w.b, w.plan.info
     N, C = b.num_joints, b.num_characters
 
@@ -380,7 +383,8 @@ def main():
                    "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
                    "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
                    "autotuned": not args.no_autotune, "hip_graph": w.graphs is not None,
-                   "input_sets": len(w.sets)},
+                   "input_sets": len(w.sets),
+                   **({"adjoint": args.adjoint} if args.workload == "differentiable" else {})},
         "roofline": roof,
     }
     if launch is not None:

@@ -110,8 +110,23 @@ typedef struct hs_plan_opts {
                                whole chain segments with four joints per lane (a sequential
                                product per lane and a segmented scan across the wave) */
     int32_t algorithm;      /* HS_ALG_*: the scan that tiles run (forward, stored TRS poses) */
+    int32_t adjoint;        /* HS_ADJ_*: the kernel that runs the adjoint of characters of up to
+                               1024 joints */
     int32_t reserved[1];    /* must be zero */
 } hs_plan_opts;
+
+/* Adjoint kernels for characters of up to 1024 joints (larger ones always
+ * take the dataflow kernel up to 1664 joints, then the multipass adjoint).
+ * HS_ADJ_ROUNDS: tile-wide synchronous reverse pointer-jumping rounds, one
+ * joint per thread, workgroup barriers between rounds; recomputes every G_j
+ * on chip and reads no checkpoints.  HS_ADJ_DATAFLOW: wave-level rounds per
+ * 64-joint block, blocks ordered by LDS flags (no workgroup barriers between
+ * rounds); reads checkpoints when given.  HS_ADJ_AUTO picks HS_ADJ_ROUNDS
+ * (measured faster: blocks of long chains wait for each other in turn under
+ * HS_ADJ_DATAFLOW). */
+#define HS_ADJ_AUTO 0
+#define HS_ADJ_ROUNDS 1
+#define HS_ADJ_DATAFLOW 2
 
 /* Tile algorithms.  HS_ALG_SCAN is this library's scan (wave-level pointer
  * jumping per 64-joint block, dataflow between blocks).  HS_ALG_WALK ..

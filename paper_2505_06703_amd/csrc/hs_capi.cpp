@@ -106,12 +106,15 @@ int ceil_log2(int64_t v)
     return r;
 }
 
+static_assert(hs::kAdjRounds == HS_ADJ_ROUNDS && hs::kAdjDataflow == HS_ADJ_DATAFLOW, "adjoint kinds");
+
 struct Shape {
     int tile_cap = 0;
     int waves = 0;
     int grid_per_cu = 0;  // 0 = one workgroup per tile
     bool chain_units = false;
     int algorithm = HS_ALG_SCAN;
+    int adjoint = HS_ADJ_ROUNDS;
 };
 
 } // namespace
@@ -704,7 +707,11 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     {
         std::lock_guard<std::mutex> lk(plan->ctx->mu);
         auto it = plan->ctx->tuned.find(key);
-        if (it != plan->ctx->tuned.end()) return build_tables(plan, it->second, strategy);
+        if (it != plan->ctx->tuned.end()) {
+            Shape sh = it->second;  // the forward's launch shape; the adjoint kind is this plan's
+            sh.adjoint = base.adjoint;
+            return build_tables(plan, sh, strategy);
+        }
     }
     const size_t N = (size_t)plan->N;
     std::vector<Shape> cands;
@@ -716,7 +723,14 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
             if (w * 64 > cap) continue;
             if (cap / (w * 64) > 4) continue;  // at most 4 blocks per wave
             for (int g : {0, 2, 4})
-                for (bool cu : {false, true}) cands.push_back(Shape{cap, w, g, cu});
+                for (bool cu : {false, true}) {
+                    Shape c = base;
+                    c.tile_cap = cap;
+                    c.waves = w;
+                    c.grid_per_cu = g;
+                    c.chain_units = cu;
+                    cands.push_back(c);
+                }
         }
     }
     if (cands.empty()) return build_tables(plan, base, strategy);
@@ -894,6 +908,8 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
     if (o.grid_tiles < 0 || o.grid_tiles > 64) return fail(HS_ERR_INVALID_ARG, "grid_tiles must be in [0, 64]");
     if (o.algorithm < HS_ALG_SCAN || o.algorithm > HS_ALG_COMPRESSED)
         return fail(HS_ERR_INVALID_ARG, "unknown algorithm %d", o.algorithm);
+    if (o.adjoint < HS_ADJ_AUTO || o.adjoint > HS_ADJ_DATAFLOW)
+        return fail(HS_ERR_INVALID_ARG, "unknown adjoint kernel %d", o.adjoint);
     if (o.algorithm != HS_ALG_SCAN && o.chain_units)
         return fail(HS_ERR_INVALID_ARG, "chain units belong to the library's own scan (algorithm 0)");
 
@@ -981,6 +997,7 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
     sh.grid_per_cu = o.grid_tiles;
     sh.chain_units = o.chain_units != 0;
     sh.algorithm = o.algorithm;
+    sh.adjoint = o.adjoint == HS_ADJ_AUTO ? HS_ADJ_ROUNDS : o.adjoint;
     if (sh.algorithm != HS_ALG_SCAN) {
         // the paper's algorithms: one joint per thread, 1024-thread workgroups
         if (o.strategy == HS_STRATEGY_TILE && min_cap > hs::kPaperAlgTileJoints) {
@@ -1211,7 +1228,10 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
         tl.tiles = plan->d_btiles;
         tl.num_tiles = plan->num_btiles;
         tl.tile_cap = plan->bwd_cap;
+        tl.adjoint = plan->shape.adjoint;
         tl.grid = plan->num_btiles;
+        tl.waves = 1;  // dataflow: a power of two, at most one wave per block
+        while (tl.waves < 16 && tl.waves * 2 * 64 <= plan->bwd_cap) tl.waves *= 2;
         err = hs::launch_backward_tiles(tl, pa, ba, stream);
         if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
     }

@@ -75,6 +75,11 @@ struct OutArgs {
     const int32_t *level;   // [N] level of each joint (root = 1), for checkpoints
 };
 
+// adjoint kernels for tiles of up to kMaxSyncTileJoints joints (the values
+// of HS_ADJ_ROUNDS and HS_ADJ_DATAFLOW)
+constexpr int32_t kAdjRounds = 1;
+constexpr int32_t kAdjDataflow = 2;
+
 struct TileLaunch {
     const TileDesc *tiles;
     int32_t num_tiles;
@@ -84,6 +89,7 @@ struct TileLaunch {
     const int32_t *parent; // [N] global parent id or -1
     int32_t chain_units;   // tiles carry chain-unit marks
     int32_t algorithm;     // 0: this library's scan; 1-4: the paper's Algorithms 1-4
+    int32_t adjoint;       // kAdjRounds or kAdjDataflow
 };
 
 struct MPLaunch {

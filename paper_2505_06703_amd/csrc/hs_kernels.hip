@@ -866,7 +866,9 @@ paper_alg_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 // back through the round-r jump product M_r(a) of the forward doubling
 // (the product of the 2^r local transforms ending at a), into its 2^r-th
 // in-block ancestor.  After ceil(log2 depth) rounds S(j) sums all in-block
-// descendants.  Fan-in makes this a scatter, done with LDS float atomics.
+// descendants.  Fan-in makes this a scatter: each pusher claims its target's
+// owner word with a plain store, the pusher whose claim landed adds with a
+// plain read-modify-write, the others with LDS float atomics after it.
 // Blocks run in decreasing order; a block's top joints (parent in an
 // earlier block) push X_c (.) L_c into the parent's LDS accumulator and
 // bump that block's arrival counter, which the earlier block waits for.
@@ -932,7 +934,30 @@ __device__ __forceinline__ void write_grads(const BwdArgs &B, int64_t gid, const
     gt[2] = tb[2];
 }
 
-// LDS: G[cap][3] | adjoint accumulators[cap][3] | flags, expected, received [cap/64] each
+// LDS: G[cap][3] | adjoint accumulators[cap][3] float4 | owner words[cap] uint16 |
+// flags, expected, received [cap/64] int each
+// 16-bit owner words of the dataflow adjoint: (round << 6) | lane, or
+// kOwnFree.  Plain stores from several lanes to one word: one lands.
+constexpr int kOwn16Shift = 6;
+constexpr uint16_t kOwnFree = 0xFFFF;
+
+__device__ __forceinline__ void own16_claim(uint16_t *w, uint16_t v)
+{
+    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int own16_read(const uint16_t *w)
+{
+    return (int)__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int WAVES, bool CKPT>
 __global__ void __launch_bounds__(WAVES * kWave)
 bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
@@ -941,7 +966,8 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
     const int cap = tl.tile_cap;
     float4 *Gs = lds;
     float4 *Ds = lds + 3 * cap;
-    int *flags = reinterpret_cast<int *>(lds + 6 * cap);
+    uint16_t *Own = reinterpret_cast<uint16_t *>(lds + 6 * cap);
+    int *flags = reinterpret_cast<int *>(Own + cap);
     int *expect = flags + cap / kWave;
     int *recv = expect + cap / kWave;
     const int lane = threadIdx.x & (kWave - 1);
@@ -1051,15 +1077,9 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             const int jl = base + lane;
             const bool valid = jl < n;
             const int64_t gid = td.begin + jl;
-            const int want = expect[b];
-            for (int spin = 0; spin < kSpinLimit; ++spin) {
-                const int got = __hip_atomic_load(recv + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (__all(got >= want)) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-
-            float L[12], M[12], S[12];
+            // this block's inputs are fetched before the wait for the later
+            // blocks' pushes, so their latency overlaps it
+            float M[12], S[12];
             float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
             float sx = 1.0f, sy = 1.0f, sz = 1.0f;
             int pl = -1, a = -1;
@@ -1073,42 +1093,82 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
                     const float *sp = pose.scale + 3 * gid;
                     sx = sp[0]; sy = sp[1]; sz = sp[2];
                 }
-                aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, L);
-                const float4 *gg = reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid;
-                float d[12], acc[12];
-                aff_load(gg, d);
-                aff_load(Ds + 3 * jl, acc);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) S[k] = d[k] + acc[k];
-                aff_store(Ds + 3 * jl, S);
+                aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, M);
+                aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
             } else {
-                aff_identity(L);
+                aff_identity(M);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) S[k] = 0.0f;
             }
+            const int want = expect[b];
+            for (int spin = 0; spin < kSpinLimit; ++spin) {
+                const int got = __hip_atomic_load(recv + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (__all(got >= want)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (valid) {
+                float acc[12];
+                aff_load(Ds + 3 * jl, acc);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) M[k] = L[k];
+                for (int k = 0; k < 12; ++k) S[k] += acc[k];
+                aff_store(Ds + 3 * jl, S);
+            }
 
-            while (__any(a >= 0)) {
+            // in-block reverse pointer jumping; colliding pushes resolved
+            // with this block's owner words (touched by this wave only)
+            Own[jl] = kOwnFree;
+            wave_sync();
+            if (a >= 0) own16_claim(Own + base + a, (uint16_t)lane);
+            wave_sync();
+#pragma unroll 1
+            for (int r = 0; __any(a >= 0); ++r) {
                 const bool act = a >= 0;
+                const int tag = r << kOwn16Shift;
+                bool lose = false;
+                float c[12];
                 if (act) {
-                    float c[12];
                     adj_pull(S, M, c);
-                    lds_atomic_add12(Ds + 3 * (base + a), c);
+                    lose = own16_read(Own + base + a) != (tag | lane);
+                    if (!lose) {
+                        float acc[12];
+                        aff_load(Ds + 3 * (base + a), acc);
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) acc[k] += c[k];
+                        aff_store(Ds + 3 * (base + a), acc);
+                    }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                if (valid) aff_load(Ds + 3 * jl, S);
+                wave_sync();
+                if (lose) lds_atomic_add12(Ds + 3 * (base + a), c);
+                // forward doubling: M_{r+1}(j) = M_r(a) M_r(j), a's values read
+                // across lanes before any lane updates its own
                 const int src = (act ? a : lane) << 2;
-                float ma[12], o[12];
+                float ma[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) ma[k] = lane_read(M[k], src);
                 const int aa = __builtin_amdgcn_ds_bpermute(src, a);
-                aff_mul(ma, M, o);
-#pragma unroll
-                for (int k = 0; k < 12; ++k) M[k] = act ? o[k] : M[k];
-                if (act) a = aa;
+                if (act) aff_mul_left(ma, M);
+                const bool recv_r = valid && (own16_read(Own + jl) >> kOwn16Shift) == r;
+                wave_sync();
+                if (recv_r) aff_load(Ds + 3 * jl, S);
+                if (act) {
+                    a = aa;
+                    if (a >= 0) own16_claim(Own + base + a, (uint16_t)(tag + (1 << kOwn16Shift) + lane));
+                }
+                wave_sync();
             }
 
+            // heads push into their out-of-block parents and signal first;
+            // the gradient stores follow, off the earlier blocks' critical path
+            if (valid && pl >= 0 && pl < base) {
+                const float *t = pose.trans + 3 * gid;  // the local transform again
+                float L[12], c[12];
+                aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, L);
+                adj_pull(S, L, c);
+                lds_atomic_add12(Ds + 3 * pl, c);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (valid && pl >= 0 && pl < base) atomicAdd(recv + pl / kWave, 1);
             if (valid) {
                 float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
                 if (pl >= 0) {
@@ -1118,15 +1178,8 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
                     Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
                     Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
                 }
-                if (pl >= 0 && pl < base) {
-                    float c[12];
-                    adj_pull(S, L, c);
-                    lds_atomic_add12(Ds + 3 * pl, c);
-                }
                 write_grads(bwd, gid, S, Ap, q, sx, sy, sz);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (valid && pl >= 0 && pl < base) atomicAdd(recv + pl / kWave, 1);
         }
         __syncthreads();
     }
@@ -1370,13 +1423,6 @@ mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
 // (global float atomics, one push per head), reverse pointer jumping over
 // the anchors, then R_B(D + U) and the gradients.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // R_B for one 64-joint block held by one wave: S in (Y_j), S out (Z_j).
 // a: lane of the in-block parent, or -1.  Reverse pointer jumping over the
 // in-block ancestors with the forward doubling alongside, collisions
@@ -1793,7 +1839,7 @@ size_t backward_sync_lds_bytes(int tile_cap)
 
 size_t backward_tile_lds_bytes(int tile_cap)
 {
-    return (size_t)tile_cap * 96 + (size_t)(tile_cap / kWave) * 12;
+    return (size_t)tile_cap * 98 + (size_t)(tile_cap / kWave) * 12;
 }
 
 template <int WAVES, bool CKPT>
@@ -1834,7 +1880,7 @@ hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, con
 {
     if (tl.num_tiles == 0) return hipSuccess;
     if (tl.tile_cap > kMaxBwdTileJoints) return hipErrorInvalidValue;
-    if (tl.tile_cap > kMaxSyncTileJoints)
+    if (tl.tile_cap > kMaxSyncTileJoints || tl.adjoint == kAdjDataflow)
         return bwd.ckpt ? launch_bwd_tiles_w<true>(tl, pose, bwd, stream)
                         : launch_bwd_tiles_w<false>(tl, pose, bwd, stream);
     // tiles of up to 1024 joints: one joint per thread; the jump products

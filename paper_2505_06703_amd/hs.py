@@ -29,6 +29,7 @@ HS_STRATEGY_AUTO = 0
 HS_STRATEGY_TILE = 1
 HS_STRATEGY_MULTIPASS = 2
 HS_ALG_SCAN, HS_ALG_WALK, HS_ALG_JUMP, HS_ALG_BLOCKS, HS_ALG_COMPRESSED = 0, 1, 2, 3, 4
+HS_ADJ_AUTO, HS_ADJ_ROUNDS, HS_ADJ_DATAFLOW = 0, 1, 2
 
 HS_POSE_TRS = 0
 HS_POSE_CLIPS = 1
@@ -54,7 +55,8 @@ class hs_plan_opts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_int32), ("tile_joints", ctypes.c_int32),
                 ("waves_per_tile", ctypes.c_int32), ("grid_tiles", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("chain_units", ctypes.c_int32),
-                ("algorithm", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("algorithm", ctypes.c_int32), ("adjoint", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -197,7 +199,8 @@ class Plan:
     """Topology analysis of a CSR batch (see ``hs_plan_create``)."""
 
     def __init__(self, offsets, parents, ctx=None, strategy=HS_STRATEGY_AUTO, tile_joints=0,
-                 waves_per_tile=0, grid_tiles=0, autotune=False, chain_units=False, algorithm=HS_ALG_SCAN):
+                 waves_per_tile=0, grid_tiles=0, autotune=False, chain_units=False, algorithm=HS_ALG_SCAN,
+                 adjoint=HS_ADJ_AUTO):
         self.ctx = ctx or default_context()
         off = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
                                               dtype=np.int64))
@@ -209,7 +212,7 @@ class Plan:
         self.num_joints = par.size
         batch = hs_batch(self.num_characters, self.num_joints, off.ctypes.data, par.ctypes.data)
         opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)),
-                            int(bool(chain_units)), int(algorithm))
+                            int(bool(chain_units)), int(algorithm), int(adjoint))
         h = ctypes.c_void_p()
         _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),
                                              ctypes.byref(h)))

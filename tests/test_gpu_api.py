@@ -80,6 +80,13 @@ def test_forward_argument_errors_launch_nothing():
     assert _call_forward(plan, qp, tp, None, Gp) == hs.HS_OK
 
 
+def test_unknown_adjoint_kernel_is_rejected():
+    b = wl.plain_scan(num_characters=2)
+    with pytest.raises(hs.HSError) as ei:
+        hs.Plan(b.offsets, b.parents, adjoint=3)
+    assert ei.value.status == hs.HS_ERR_INVALID_ARG
+
+
 def test_backward_and_sampler_argument_errors():
     b = wl.fused_sample(num_characters=3)
     plan = hs.Plan(b.offsets, b.parents)

@@ -64,12 +64,16 @@ def oracle_grads(batch, W):
     return oracle.backward(batch.offsets, batch.parents, batch.quat, batch.trans, batch.scale, W)
 
 
+ADJ = [hs.HS_ADJ_ROUNDS, hs.HS_ADJ_DATAFLOW]
+
+
+@pytest.mark.parametrize("adj", ADJ)
 @pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4), dict(tile_joints=512)])
-def test_differentiable_effector_loss(shape):
+def test_differentiable_effector_loss(shape, adj):
     b = wl.differentiable(num_characters=12)
     G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
     W = effector_grad(b, G)
-    check_grads(b.offsets, run(b, W, **shape), oracle_grads(b, W), f"differentiable {shape}")
+    check_grads(b.offsets, run(b, W, adjoint=adj, **shape), oracle_grads(b, W), f"differentiable {shape} adj {adj}")
 
 
 @pytest.mark.parametrize("k", [1, 3, 8])
@@ -80,16 +84,18 @@ def test_level_checkpoint_mode(k):
     check_grads(b.offsets, run(b, W, ckpt_k=k), oracle_grads(b, W), f"ckpt k={k}")
 
 
-def test_dense_random_gradient_with_scale_and_forests():
+@pytest.mark.parametrize("adj", ADJ)
+def test_dense_random_gradient_with_scale_and_forests(adj):
     rng = np.random.default_rng(5)
     b = wl.heterogeneous(num_characters=40, hi=1500, chain_fraction=0.05)
     b.scale = rng.uniform(0.8, 1.25, b.scale.shape).astype(np.float32)
     W = rng.standard_normal((b.num_joints, 4, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W), oracle_grads(b, W), "dense random")
-    check_grads(b.offsets, run(b, W, ckpt_k=5), oracle_grads(b, W), "dense random ckpt")
+    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), "dense random")
+    check_grads(b.offsets, run(b, W, ckpt_k=5, adjoint=adj), oracle_grads(b, W), "dense random ckpt")
 
 
-def test_plain_scan_trees_and_star():
+@pytest.mark.parametrize("adj", ADJ)
+def test_plain_scan_trees_and_star(adj):
     rng = np.random.default_rng(6)
     star = np.zeros(700, np.int32)
     star[0] = -1
@@ -99,15 +105,16 @@ def test_plain_scan_trees_and_star():
     q, t, s = wl.random_pose(rng, par.size)
     b = wl.Batch("mix", off.astype(np.int64), par, q, t, s, q, t, s)
     W = rng.standard_normal((par.size, 4, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W), oracle_grads(b, W), "trees+star")
-    got = run(b, W, want_scale=False)
+    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), "trees+star")
+    got = run(b, W, want_scale=False, adjoint=adj)
     assert got[2] is None
 
 
+@pytest.mark.parametrize("adj", ADJ)
 @pytest.mark.parametrize("n", [1, 64, 65, 1000, 1024, 1025, 1664])
-def test_chains(n):
-    """Chains up to 1024 joints take the synchronous-round tiles, longer
-    ones (to 1664) the dataflow tiles, in both memory modes."""
+def test_chains(n, adj):
+    """Chains up to 1024 joints take the chosen adjoint kernel, longer ones
+    (to 1664) the dataflow tiles, in both memory modes."""
     rng = np.random.default_rng(n)
     par = np.arange(-1, n - 1, dtype=np.int32)
     q, t, s = wl.random_pose(rng, n, max_angle=0.1)
@@ -116,12 +123,13 @@ def test_chains(n):
     W[-1, :3, 3] = rng.standard_normal(3)
     W[n // 2, :3, :3] = rng.standard_normal((3, 3))
     ref = oracle_grads(b, W)
-    check_grads(b.offsets, run(b, W), ref, f"chain {n}")
-    check_grads(b.offsets, run(b, W, ckpt_k=4), ref, f"chain {n} ckpt 4")
+    check_grads(b.offsets, run(b, W, adjoint=adj), ref, f"chain {n}")
+    check_grads(b.offsets, run(b, W, ckpt_k=4, adjoint=adj), ref, f"chain {n} ckpt 4")
 
 
+@pytest.mark.parametrize("adj", ADJ)
 @pytest.mark.parametrize("n", [1024, 1025])
-def test_stars_and_brooms_collide_on_one_target(n):
+def test_stars_and_brooms_collide_on_one_target(n, adj):
     """Every joint of a star pushes to the root in one round; a broom (a
     chain whose last joint fans out) sends ever more joints to one target as
     the jump distance grows."""
@@ -136,7 +144,7 @@ def test_stars_and_brooms_collide_on_one_target(n):
     q, t, s = wl.random_pose(rng, par.size, max_angle=0.2)
     b = wl.Batch("star", off, par, q, t, s, q, t, s)
     W = rng.standard_normal((par.size, 4, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W), oracle_grads(b, W), f"star/broom {n}")
+    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), f"star/broom {n}")
 
 
 def test_large_forward_tiles_use_smaller_adjoint_tiles():
@@ -218,3 +226,15 @@ def test_multipass_adjoint_comb_with_shared_anchors():
         tol = TOL * max(1.0, float(np.abs(r).max())) * np.sqrt(20000 / 2048)
         err = float(np.abs(g - r).max())
         assert err <= tol, f"{name}: {err:.3e} > {tol:.3e}"
+
+
+@pytest.mark.parametrize("adj", ADJ)
+def test_more_tiles_than_resident_workgroups(adj):
+    """1300 characters of 512 joints: more adjoint tiles than the device
+    holds at once (workgroups dispatched as others finish)."""
+    b = wl.differentiable(num_characters=1300)
+    G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+    W = effector_grad(b, G)
+    rng = np.random.default_rng(13)
+    W[:, :3, :] += 0.01 * rng.standard_normal((b.num_joints, 3, 4)).astype(np.float32)
+    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), f"1300 characters adj {adj}")
