@@ -41,7 +41,9 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_06703_amd", "csrc", f)
                   for f in ("hs_kernels.hip", "hs_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 256 << 20
-WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "differentiable", "long_chains"]
+WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "fused_sample_instanced",
+             "differentiable", "long_chains"]
+FUSED = ("fused_sample", "fused_sample_instanced")
 
 # algorithmic HBM bytes per joint that the dominant kernel of a step must
 # move (read + write)
@@ -55,6 +57,9 @@ BYTES_PER_JOINT = {
     "plain_scan": 236,
     # parent 4 + inverse bind 64 read, skin 64 written (+ clip library once)
     "fused_sample": 132,
+    # instanced: parents and inverse binds are the one skeleton's (256 rows,
+    # cache-resident), so only the skin is per joint in HBM
+    "fused_sample_instanced": 64,
     # adjoint: read quat, trans, scale, parent 44 + grad_global 64, write
     # grad_quat 16 + grad_trans 12
     "differentiable": 136,
@@ -163,15 +168,24 @@ class Workload:
         self.b = b = wl.make(name)
         N = b.num_joints
         adj = {"auto": hs.HS_ADJ_AUTO, "rounds": hs.HS_ADJ_ROUNDS, "dataflow": hs.HS_ADJ_DATAFLOW}[adjoint]
-        self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune, adjoint=adj)
         self.inv = None
         self.clips = None
+        if name == "fused_sample_instanced":
+            x = b.extra
+            self.plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"], autotune=autotune)
+            # one skeleton: inverse binds of its rest pose (a one-character plan)
+            one = hs.Plan(x["skel_offsets"], x["skel_parents"])
+            Grest, _ = hs.hs_scan_forward(one, *(up(a) for a in x["skel_rest"]))
+            self.inv = up(np.linalg.inv(Grest.cpu().numpy().astype(np.float64)).astype(np.float32))
+            del Grest, one
+        else:
+            self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune, adjoint=adj)
         if name in ("plain_scan", "fused_sample"):
             # inverse binds from the rest pose: scan it on the GPU, invert on the host
             Grest, _ = hs.hs_scan_forward(self.plan, up(b.rest_quat), up(b.rest_trans), up(b.rest_scale))
             self.inv = up(np.linalg.inv(Grest.cpu().numpy().astype(np.float64)).astype(np.float32))
             del Grest
-        if name == "fused_sample":
+        if name in FUSED:
             x = b.extra
             self.clips = hs.ClipLibrary(up(x["key_quat"]), up(x["key_trans"]), x["fps"])
             self.cp = dict(clip_a=up(x["clip_a"]), clip_b=up(x["clip_b"]), time=up(x["time"]),
@@ -216,7 +230,7 @@ class Workload:
         if name != "differentiable":
             calls = []
             for st in self.sets:
-                if name == "fused_sample":
+                if name in FUSED:
                     calls.append(dict(clips=self.clips, **self.cp, inv_bind=st["inv"], skin_out=st["S"]))
                 elif name == "plain_scan":
                     calls.append(dict(quat=st["q"], trans=st["t"], scale=st["s"], inv_bind=st["inv"],
@@ -271,7 +285,7 @@ class Workload:
         e0.record()
         for k in range(reps):
             s = self.sets[k % len(self.sets)]
-            if self.name == "fused_sample":
+            if self.name in FUSED:
                 hs.hs_scan_forward(self.plan, clips=self.clips, **self.cp, want_global=False, inv_bind=s["inv"],
                                    skin_out=s["S"])
             elif self.name == "plain_scan":
@@ -353,7 +367,7 @@ def main():
         # around the timed region give its mean launch duration
         kernel_ms = region[0].elapsed_time(region[1]) / args.steps
     bytes_per_launch = N * BYTES_PER_JOINT[args.workload]
-    if args.workload == "fused_sample":
+    if args.workload in FUSED:
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     copy_gbs = device_copy_gbs(torch)
@@ -458,7 +472,7 @@ def cpu_baseline(w):
     torch, b, name = w.torch, w.b, w.name
     cores = len(os.sched_getaffinity(0))
     N = b.num_joints
-    if name == "fused_sample":
+    if name in FUSED:
         x = b.extra
 
         def run():
@@ -513,7 +527,11 @@ def cpu_baseline(w):
                 g = g.cpu().numpy().astype(np.float64)
                 err[key + "_rel_max"] = float(np.abs(g - r).max() / max(1.0, np.abs(r).max()))
     else:
-        S = oracle.skin(G, s0["inv"].cpu().numpy())
+        inv = s0["inv"].cpu().numpy()
+        if name == "fused_sample_instanced":  # one row per skeleton joint: expand
+            soff = b.extra["skel_offsets"]
+            inv = inv[np.concatenate([np.arange(soff[k], soff[k + 1]) for k in b.extra["skeleton_id"]])]
+        S = oracle.skin(G, inv)
         Sg = s0["S"].cpu().numpy().astype(np.float64)
         err = {"skin_rotation_abs_max": float(np.abs(Sg[:, :3, :3] - S[:, :3, :3]).max()),
                "skin_translation_abs_max": float(np.abs(Sg[:, :3, 3] - S[:, :3, 3]).max())}

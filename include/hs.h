@@ -165,6 +165,34 @@ typedef struct hs_plan_info {
  * NULL.  Synchronises the device once. */
 hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts,
                          hs_plan **out);
+
+/* Skeletons shared by many characters.  In the paper's pipeline (Sec. 1:
+ * Simulation, Hierarchy-Scan, Bind MeshPose) characters of one kind share
+ * the joint hierarchy and the bind pose; only the local poses differ.
+ * Host arrays: skeleton k owns joints offsets[k] .. offsets[k+1]-1 of the
+ * skeleton arrays (offsets[0] = 0, offsets[num_skeletons] = num_joints);
+ * parents[] are skeleton-local as in hs_batch. */
+typedef struct hs_skeleton_set {
+    int32_t num_skeletons;
+    int64_t num_joints;         /* joints over all skeletons */
+    const int64_t *offsets;     /* host [num_skeletons + 1] */
+    const int32_t *parents;     /* host [num_joints] */
+} hs_skeleton_set;
+
+/* A plan for num_characters instances: character c is a copy of skeleton
+ * skeleton_id[c] (host array), so its joints are numbered as in hs_batch
+ * with the skeleton's size.  The forward tiles read each joint's parent and
+ * inverse bind through its skeleton (arrays small enough to stay in the
+ * caches) instead of per-joint rows in HBM: hs_scan_forward's inv_bind is
+ * then [skel->num_joints, 4, 4], one row per skeleton joint.  Everything
+ * else (pose arrays, outputs, hs_pose_sample, hs_scan_backward) is per
+ * joint as for hs_plan_create.  Chain units, the paper's algorithms and
+ * the multipass strategy are not available (HS_ERR_UNSUPPORTED), and every
+ * character must fit a tile (HS_ERR_UNSUPPORTED otherwise).  Errors:
+ * HS_ERR_INVALID_ARG for bad offsets or a skeleton_id out of range,
+ * HS_ERR_TOPOLOGY as hs_plan_create. */
+hs_status hs_plan_create_instanced(hs_context *ctx, const hs_skeleton_set *skel, int32_t num_characters,
+                                   const int32_t *skeleton_id, const hs_plan_opts *opts, hs_plan **out);
 void hs_plan_destroy(hs_plan *plan);
 hs_status hs_plan_get_info(const hs_plan *plan, hs_plan_info *out);
 

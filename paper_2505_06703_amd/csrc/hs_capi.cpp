@@ -197,6 +197,12 @@ struct hs_plan {
     // adjoint tile (bmp, with the adjoint workspace)
     MPSet mp, bmp;
     std::vector<int32_t> h_level;
+    // instanced plans: skeleton-local parents and each character's first
+    // skeleton joint (the forward tiles read these instead of d_parent)
+    bool inst = false;
+    int64_t skel_joints = 0;
+    int32_t *d_skel_parent = nullptr;
+    int32_t *d_char_skel = nullptr;
 };
 
 namespace {
@@ -213,6 +219,8 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_bbig);
     free_mpset(p->mp);
     free_mpset(p->bmp);
+    (void)hipFree(p->d_skel_parent);
+    (void)hipFree(p->d_char_skel);
     delete p;
 }
 
@@ -592,6 +600,10 @@ hs::TileLaunch tile_launch(const hs_plan *p, int k = -1)
     tl.parent = p->d_parent;
     tl.chain_units = p->shape.chain_units ? 1 : 0;
     tl.algorithm = p->shape.algorithm;
+    if (p->inst) {
+        tl.skel_parent = p->d_skel_parent;
+        tl.char_skel = p->d_char_skel;
+    }
     return tl;
 }
 
@@ -695,9 +707,10 @@ std::string tune_key(const hs_plan *p)
     // size class: number of joints (log2), largest character and deepest
     // block chain, rounded so that similar batches share an entry
     char buf[160];
-    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d", p->ctx->arch.c_str(),
+    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d|inst%d", p->ctx->arch.c_str(),
              ceil_log2(std::max<int64_t>(1, p->N)), round_up(std::max(1, p->info.max_character), 64),
-             ceil_log2(std::max(1, p->info.max_block_chain)), ceil_log2(std::max<int64_t>(1, p->C)));
+             ceil_log2(std::max(1, p->info.max_block_chain)), ceil_log2(std::max<int64_t>(1, p->C)),
+             p->inst ? 1 : 0);
     return buf;
 }
 
@@ -710,6 +723,7 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
         if (it != plan->ctx->tuned.end()) {
             Shape sh = it->second;  // the forward's launch shape; the adjoint kind is this plan's
             sh.adjoint = base.adjoint;
+            if (plan->inst) sh.chain_units = false;
             return build_tables(plan, sh, strategy);
         }
     }
@@ -724,6 +738,7 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
             if (cap / (w * 64) > 4) continue;  // at most 4 blocks per wave
             for (int g : {0, 2, 4})
                 for (bool cu : {false, true}) {
+                    if (cu && plan->inst) continue;  // instanced tiles run whole blocks
                     Shape c = base;
                     c.tile_cap = cap;
                     c.waves = w;
@@ -756,6 +771,7 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     pa.kind = 0;
     pa.quat = q;
     pa.trans = t;
+    pa.offsets = plan->d_offsets;  // the character map of instanced tiles reads these
     hs::OutArgs oa{};
     oa.global_out = G;
     // median of 10 timed runs after 3 warm-up runs per candidate; the
@@ -827,7 +843,7 @@ hs_status prepare_forward(const hs_plan *plan, const hs_pose_src *src, float *gl
     if (plan->shape.algorithm != HS_ALG_SCAN && src->kind != HS_POSE_TRS)
         return fail(HS_ERR_UNSUPPORTED, "hs_scan_forward: the paper's algorithms take stored TRS poses only");
     const size_t N = (size_t)plan->N;
-    ins.push_back({inv_bind, N * 64, "inv_bind"});
+    ins.push_back({inv_bind, (plan->inst ? (size_t)plan->skel_joints : N) * 64, "inv_bind"});
     std::vector<Range> outs = {{global_out, N * 64, "global_out"}, {skin_out, N * 64, "skin_out"},
                                {ckpt_out, N * 48, "ckpt_out"}};
     if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
@@ -884,7 +900,76 @@ hs_status hs_context_create(int device, hs_context **out)
 
 void hs_context_destroy(hs_context *ctx) { delete ctx; }
 
+} // extern "C"
+
+namespace {
+
+// Skeleton tables of an instanced plan (host arrays): skeleton-local
+// parents and each character's first skeleton joint.
+struct SkelTables {
+    const std::vector<int32_t> *parents;
+    const std::vector<int32_t> *char_first;
+};
+
+hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts, hs_plan **out,
+                      const SkelTables *inst);
+
+} // namespace
+
+extern "C" {
+
 hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts, hs_plan **out)
+{
+    return create_plan(ctx, batch, opts, out, nullptr);
+}
+
+hs_status hs_plan_create_instanced(hs_context *ctx, const hs_skeleton_set *skel, int32_t num_characters,
+                                   const int32_t *skeleton_id, const hs_plan_opts *opts, hs_plan **out)
+{
+    if (!out) return fail(HS_ERR_INVALID_ARG, "hs_plan_create_instanced: out is NULL");
+    *out = nullptr;
+    if (!ctx || !skel) return fail(HS_ERR_INVALID_ARG, "hs_plan_create_instanced: context and skeletons must be non-NULL");
+    const int32_t S = skel->num_skeletons;
+    const int64_t NS = skel->num_joints;
+    if (S < 0 || NS < 0 || NS >= (int64_t(1) << 31) - 1)
+        return fail(HS_ERR_INVALID_ARG, "skeleton counts out of range");
+    if (num_characters < 0) return fail(HS_ERR_INVALID_ARG, "num_characters must be >= 0");
+    if (!skel->offsets || (NS > 0 && !skel->parents) || (num_characters > 0 && !skeleton_id))
+        return fail(HS_ERR_INVALID_ARG, "skeleton offsets, parents and skeleton_id must be non-NULL");
+    const int64_t *so = skel->offsets;
+    if (so[0] != 0 || so[S] != NS) return fail(HS_ERR_INVALID_ARG, "skeleton offsets must run from 0 to num_joints");
+    for (int32_t k = 0; k < S; ++k)
+        if (so[k + 1] < so[k]) return fail(HS_ERR_INVALID_ARG, "skeleton offsets must be non-decreasing");
+    hs_plan_opts o{};
+    if (opts) o = *opts;
+    if (o.chain_units || o.algorithm != HS_ALG_SCAN || o.strategy == HS_STRATEGY_MULTIPASS)
+        return fail(HS_ERR_UNSUPPORTED, "instanced plans run the library's block scan on tiles "
+                                        "(no chain units, paper algorithms or multipass strategy)");
+    // the batch the instances make: character c is a copy of skeleton skeleton_id[c]
+    std::vector<int64_t> off((size_t)num_characters + 1, 0);
+    std::vector<int32_t> first((size_t)num_characters);
+    for (int32_t c = 0; c < num_characters; ++c) {
+        const int32_t k = skeleton_id[c];
+        if (k < 0 || k >= S) return fail(HS_ERR_INVALID_ARG, "skeleton_id[%d] = %d out of range", c, k);
+        first[c] = (int32_t)so[k];
+        off[c + 1] = off[c] + (so[k + 1] - so[k]);
+        if (off[c + 1] >= (int64_t(1) << 31) - 1) return fail(HS_ERR_UNSUPPORTED, "instances exceed 2^31-1 joints");
+    }
+    std::vector<int32_t> par((size_t)off[num_characters]);
+    for (int32_t c = 0; c < num_characters; ++c)
+        std::copy(skel->parents + first[c], skel->parents + first[c] + (off[c + 1] - off[c]), par.begin() + off[c]);
+    std::vector<int32_t> sp(skel->parents, skel->parents + NS);
+    const hs_batch b{num_characters, off[num_characters], off.data(), par.data()};
+    const SkelTables t{&sp, &first};
+    return create_plan(ctx, &b, &o, out, &t);
+}
+
+} // extern "C"
+
+namespace {
+
+hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts, hs_plan **out,
+                      const SkelTables *inst)
 {
     if (!out) return fail(HS_ERR_INVALID_ARG, "hs_plan_create: out is NULL");
     *out = nullptr;
@@ -970,6 +1055,16 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
         return fail_hip(err, "hs_plan_create (upload)");
     }
 
+    if (inst) {
+        plan->inst = true;
+        plan->skel_joints = (int64_t)inst->parents->size();
+        if ((err = upload(&plan->d_skel_parent, *inst->parents)) != hipSuccess ||
+            (err = upload(&plan->d_char_skel, *inst->char_first)) != hipSuccess) {
+            free_plan(plan);
+            return fail_hip(err, "hs_plan_create_instanced (upload)");
+        }
+    }
+
     // default launch shape
     const int lds_cap = hs::kMaxTileJoints;
     const int min_cap = round_up(std::max(1, max_char), 64);
@@ -1023,6 +1118,9 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
         }
     }
     if (rc == HS_OK && o.autotune && N > 0 && sh.algorithm == HS_ALG_SCAN) rc = autotune(plan, sh, o.strategy);
+    if (rc == HS_OK && plan->inst && plan->mp.nmp > 0)
+        rc = fail(HS_ERR_UNSUPPORTED, "instanced plans need every character on a tile (%d joints at most here)",
+                  plan->shape.tile_cap);
     if (rc != HS_OK) {
         free_plan(plan);
         return rc;
@@ -1030,6 +1128,10 @@ hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_o
     *out = plan;
     return HS_OK;
 }
+
+} // namespace
+
+extern "C" {
 
 void hs_plan_destroy(hs_plan *plan) { free_plan(plan); }
 

@@ -68,7 +68,7 @@ struct PoseArgs {
 // Outputs of a forward pass.
 struct OutArgs {
     float *global_out;      // [N,16] or null
-    const float *inv_bind;  // [N,16] or null
+    const float *inv_bind;  // [N,16] or null ([skeleton joints,16] for instanced plans)
     float *skin_out;        // [N,16] or null
     float *ckpt;            // [N,12] or null
     int32_t ckpt_k;
@@ -90,6 +90,10 @@ struct TileLaunch {
     int32_t chain_units;   // tiles carry chain-unit marks
     int32_t algorithm;     // 0: this library's scan; 1-4: the paper's Algorithms 1-4
     int32_t adjoint;       // kAdjRounds or kAdjDataflow
+    // instanced plans (non-null): characters share their skeleton's parents
+    // and inverse binds; both are read through the skeleton's first joint
+    const int32_t *skel_parent; // [skeleton joints] skeleton-local parent or -1
+    const int32_t *char_skel;   // [C] first skeleton joint of each character's skeleton
 };
 
 struct MPLaunch {
@@ -145,7 +149,9 @@ hipError_t prepare_kernels();
 constexpr int kPaperAlgTileJoints = 1024;
 
 // LDS bytes one tiled-forward workgroup needs.
-size_t forward_tile_lds_bytes(int tile_cap, bool sample);
+// char_map: the tile also holds its characters' start offsets (clip
+// sampling, instanced plans)
+size_t forward_tile_lds_bytes(int tile_cap, bool char_map);
 size_t backward_tile_lds_bytes(int tile_cap);
 size_t backward_sync_lds_bytes(int tile_cap);
 size_t paper_alg_lds_bytes(int tile_cap, int alg);

@@ -258,10 +258,12 @@ __device__ __forceinline__ int tile_char_of(const int *cstart, int num_chars, in
     return lo;
 }
 
-__device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t gid, const float m[12])
+// bidx: row of the joint's inverse bind (gid, or the skeleton joint of an
+// instanced plan)
+__device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t gid, int64_t bidx, const float m[12])
 {
     if (out.skin_out) {
-        const float4 *B = reinterpret_cast<const float4 *>(out.inv_bind) + 4 * gid;
+        const float4 *B = reinterpret_cast<const float4 *>(out.inv_bind) + 4 * bidx;
         const float4 b0 = B[0], b1 = B[1], b2 = B[2], b3 = B[3];
         float4 *S = reinterpret_cast<float4 *>(out.skin_out) + 4 * gid;
 #pragma unroll
@@ -372,12 +374,12 @@ __device__ __forceinline__ void store_rows(const OutArgs &out, const float4 *Gs,
     }
 }
 
-template <bool SAMPLE>
+template <bool MAP>
 __device__ __forceinline__ void char_of(const TileDesc &td, const int *cstart, int jl, int &chr, int &lj)
 {
     chr = 0;
     lj = 0;
-    if constexpr (SAMPLE) {
+    if constexpr (MAP) {
         const int c = tile_char_of(cstart, td.num_chars, jl);
         chr = td.first_char + c;
         lj = jl - cstart[c];
@@ -386,22 +388,34 @@ __device__ __forceinline__ void char_of(const TileDesc &td, const int *cstart, i
 
 // One lane's joint of a 64-joint block: local transform, in-block ancestor
 // lane a and nearest out-of-block ancestor e (tile-local), as the in-block
-// scan expects them.
-template <bool SAMPLE>
+// scan expects them, and the joint's inverse-bind row.  INST: the parent
+// comes from the character's skeleton (shared by many characters, so the
+// reads hit the caches), as does the inverse bind.
+template <bool SAMPLE, bool INST>
 __device__ __forceinline__ void block_begin(const TileLaunch &tl, const PoseArgs &pose, const TileDesc &td, int n,
-                                            int b, const FwdShared &sh, int lane, float m[12], int &a, int &e)
+                                            int b, const FwdShared &sh, int lane, float m[12], int &a, int &e,
+                                            int64_t &bidx)
 {
     const int base = b * kWave;
     const int jl = base + lane;
     a = -1;
     e = -1;
+    bidx = td.begin + jl;
     if (jl < n) {
         const int64_t gid = td.begin + jl;
-        const int p = tl.parent[gid];
-        const int pl = p < 0 ? -1 : (int)(p - td.begin);
-        if (pl >= base) a = pl - base; else e = pl;
         int chr, lj;
-        char_of<SAMPLE>(td, sh.cstart, jl, chr, lj);
+        char_of<SAMPLE || INST>(td, sh.cstart, jl, chr, lj);
+        int pl;
+        if constexpr (INST) {
+            const int sj = tl.char_skel[chr] + lj;
+            const int ps = tl.skel_parent[sj];
+            pl = ps < 0 ? -1 : jl - lj + ps;
+            bidx = sj;
+        } else {
+            const int p = tl.parent[gid];
+            pl = p < 0 ? -1 : (int)(p - td.begin);
+        }
+        if (pl >= base) a = pl - base; else e = pl;
         load_local<SAMPLE>(pose, gid, chr, lj, m);
     } else {
         aff_identity(m);
@@ -412,7 +426,7 @@ __device__ __forceinline__ void block_begin(const TileLaunch &tl, const PoseArgs
 // nearest out-of-block ancestor once its block has published it, then the
 // block's own publication and outputs.
 __device__ __forceinline__ void block_finish(const OutArgs &out, const TileDesc &td, int n, int b,
-                                             const FwdShared &sh, int lane, float m[12], int e)
+                                             const FwdShared &sh, int lane, float m[12], int e, int64_t bidx)
 {
     float4 *Gs = sh.G;
     const int base = b * kWave;
@@ -427,20 +441,21 @@ __device__ __forceinline__ void block_finish(const OutArgs &out, const TileDesc 
     if (valid) aff_store(Gs + 3 * jl, m);
     publish_blocks(sh.flags, b, 1, lane);
     if (out.global_out) store_rows<1>(out, Gs, td.begin, base, 1, n, lane);
-    if (valid) write_skin_and_ckpt(out, td.begin + jl, m);
+    if (valid) write_skin_and_ckpt(out, td.begin + jl, bidx, m);
 }
 
 // One 64-joint block: in-block pointer jumping across the wave, then the
 // cross-block composition.
-template <bool SAMPLE>
+template <bool SAMPLE, bool INST>
 __device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                                           const TileDesc &td, int n, int b, const FwdShared &sh, int lane)
 {
     float m[12];
     int a, e;
-    block_begin<SAMPLE>(tl, pose, td, n, b, sh, lane, m, a, e);
+    int64_t bidx;
+    block_begin<SAMPLE, INST>(tl, pose, td, n, b, sh, lane, m, a, e, bidx);
     wave_inblock_scan(m, a, e, lane);
-    block_finish(out, td, n, b, sh, lane, m, e);
+    block_finish(out, td, n, b, sh, lane, m, e, bidx);
 }
 
 // The K local transforms of unit joints [i0, i0 + K) from the
@@ -605,7 +620,7 @@ __device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseA
             if (!owns || jl >= n) break;
             float g[12];
             aff_load(Gs + 3 * jl, g);
-            write_skin_and_ckpt(out, td.begin + jl, g);
+            write_skin_and_ckpt(out, td.begin + jl, td.begin + jl, g);
         }
     }
     publish_blocks(sh.flags, b0, nb, lane);
@@ -621,10 +636,13 @@ __device__ __forceinline__ void fwd_chain_unit(const TileLaunch &tl, const PoseA
 // to the waves round-robin; each wave processes its units in increasing
 // order, and a unit only waits on blocks before it, so the waits drain.
 // ---------------------------------------------------------------------------
-template <int WAVES, bool SAMPLE, bool CHAIN>
+// MODE 0: blocks; 1: chain units; 2: blocks of an instanced plan
+template <int WAVES, bool SAMPLE, int MODE>
 __global__ void __launch_bounds__(WAVES * kWave)
 fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 {
+    constexpr bool CHAIN = MODE == 1;
+    constexpr bool INST = MODE == 2;
     extern __shared__ float4 lds[];
     const int cap = tl.tile_cap;
     const int nbk = cap >> 6;
@@ -648,7 +666,7 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
             sh.flags[i] = 0;
             sh.pflag[i] = 0;
         }
-        if constexpr (SAMPLE) {
+        if constexpr (SAMPLE || INST) {
             for (int i = threadIdx.x; i <= td.num_chars; i += WAVES * kWave)
                 cstart[i] = (int)(pose.offsets[td.first_char + i] - td.begin);
         }
@@ -663,12 +681,12 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
                     if (chain)
                         fwd_chain_unit<SAMPLE>(tl, pose, out, td, n, b, nb, sh, lane);
                     else
-                        fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
+                        fwd_block<SAMPLE, false>(tl, pose, out, td, n, b, sh, lane);
                 }
                 b += nb;
             }
         } else {
-            for (int b = wave; b < nblk; b += WAVES) fwd_block<SAMPLE>(tl, pose, out, td, n, b, sh, lane);
+            for (int b = wave; b < nblk; b += WAVES) fwd_block<SAMPLE, INST>(tl, pose, out, td, n, b, sh, lane);
         }
         __syncthreads();
     }
@@ -845,7 +863,7 @@ paper_alg_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
                 dst[c] = v;
             }
         }
-        if (live) write_skin_and_ckpt(out, gid, m);
+        if (live) write_skin_and_ckpt(out, gid, gid, m);
         __syncthreads();
     }
 }
@@ -1404,7 +1422,7 @@ mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
         aff_store(G, m);
         G[3] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     }
-    write_skin_and_ckpt(out, gid, m);
+    write_skin_and_ckpt(out, gid, gid, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -1656,26 +1674,26 @@ skin_kernel(int64_t n, const float4 *G, const float4 *B, float4 *S)
     }
 }
 
-template <int WAVES, bool SAMPLE, bool CHAIN>
+template <int WAVES, bool SAMPLE, int MODE>
 hipError_t launch_fwd_tiles_t(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                               hipStream_t stream)
 {
-    const size_t lds = forward_tile_lds_bytes(tl.tile_cap, SAMPLE);
-    auto kern = fwd_tile_kernel<WAVES, SAMPLE, CHAIN>;
+    const size_t lds = forward_tile_lds_bytes(tl.tile_cap, SAMPLE || MODE == 2);
+    auto kern = fwd_tile_kernel<WAVES, SAMPLE, MODE>;
     hipLaunchKernelGGL(kern, dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, out);
     return hipGetLastError();
 }
 
-template <bool SAMPLE, bool CHAIN>
+template <bool SAMPLE, int MODE>
 hipError_t launch_fwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                               hipStream_t stream)
 {
     switch (tl.waves) {
-    case 1: return launch_fwd_tiles_t<1, SAMPLE, CHAIN>(tl, pose, out, stream);
-    case 2: return launch_fwd_tiles_t<2, SAMPLE, CHAIN>(tl, pose, out, stream);
-    case 4: return launch_fwd_tiles_t<4, SAMPLE, CHAIN>(tl, pose, out, stream);
-    case 8: return launch_fwd_tiles_t<8, SAMPLE, CHAIN>(tl, pose, out, stream);
-    case 16: return launch_fwd_tiles_t<16, SAMPLE, CHAIN>(tl, pose, out, stream);
+    case 1: return launch_fwd_tiles_t<1, SAMPLE, MODE>(tl, pose, out, stream);
+    case 2: return launch_fwd_tiles_t<2, SAMPLE, MODE>(tl, pose, out, stream);
+    case 4: return launch_fwd_tiles_t<4, SAMPLE, MODE>(tl, pose, out, stream);
+    case 8: return launch_fwd_tiles_t<8, SAMPLE, MODE>(tl, pose, out, stream);
+    case 16: return launch_fwd_tiles_t<16, SAMPLE, MODE>(tl, pose, out, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1685,10 +1703,12 @@ hipError_t set_lds_limits()
 {
     const int fwd = (int)forward_tile_lds_bytes(kMaxTileJoints, true);
     const int bwd = (int)backward_tile_lds_bytes(kMaxBwdTileJoints);
-    const void *fk[4] = {reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, false>),
-                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, false>),
-                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, true>),
-                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, true>)};
+    const void *fk[6] = {reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, 0>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, 0>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, 1>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, 1>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, false, 2>),
+                         reinterpret_cast<const void *>(fwd_tile_kernel<WAVES, true, 2>)};
     for (const void *k : fk) {
         hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, fwd);
         if (err != hipSuccess) return err;
@@ -1727,10 +1747,10 @@ hipError_t prepare_kernels()
     return set_lds_limits<16>();
 }
 
-size_t forward_tile_lds_bytes(int tile_cap, bool sample)
+size_t forward_tile_lds_bytes(int tile_cap, bool char_map)
 {
     size_t bytes = (size_t)tile_cap * 48 + (size_t)(tile_cap / kWave) * (48 + 3 * 4);
-    if (sample) bytes += (size_t)(tile_cap + 1) * 4;
+    if (char_map) bytes += (size_t)(tile_cap + 1) * 4;
     return bytes;
 }
 
@@ -1760,11 +1780,18 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
     if (tl.num_tiles == 0) return hipSuccess;
     if (tl.algorithm != 0) return launch_paper_alg(tl, pose, out, stream);
     const bool sample = pose.kind == 1;
+    // tiles that map joints to characters read the CSR offsets
+    if ((sample || tl.skel_parent) && !pose.offsets) return hipErrorInvalidValue;
+    if (tl.skel_parent) {
+        if (tl.chain_units || !tl.char_skel) return hipErrorInvalidValue;
+        return sample ? launch_fwd_tiles_w<true, 2>(tl, pose, out, stream)
+                      : launch_fwd_tiles_w<false, 2>(tl, pose, out, stream);
+    }
     if (tl.chain_units)
-        return sample ? launch_fwd_tiles_w<true, true>(tl, pose, out, stream)
-                      : launch_fwd_tiles_w<false, true>(tl, pose, out, stream);
-    return sample ? launch_fwd_tiles_w<true, false>(tl, pose, out, stream)
-                  : launch_fwd_tiles_w<false, false>(tl, pose, out, stream);
+        return sample ? launch_fwd_tiles_w<true, 1>(tl, pose, out, stream)
+                      : launch_fwd_tiles_w<false, 1>(tl, pose, out, stream);
+    return sample ? launch_fwd_tiles_w<true, 0>(tl, pose, out, stream)
+                  : launch_fwd_tiles_w<false, 0>(tl, pose, out, stream);
 }
 
 // Phase 1 per block, anchor rounds, final pass; Gc non-NULL: compact global

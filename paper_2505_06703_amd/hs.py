@@ -35,7 +35,7 @@ HS_POSE_TRS = 0
 HS_POSE_CLIPS = 1
 
 SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
-           "hs_plan_create", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
+           "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy")
 
@@ -49,6 +49,11 @@ class HSError(RuntimeError):
 class hs_batch(ctypes.Structure):
     _fields_ = [("num_characters", ctypes.c_int64), ("num_joints", ctypes.c_int64),
                 ("joint_offsets", ctypes.c_void_p), ("parents", ctypes.c_void_p)]
+
+
+class hs_skeleton_set(ctypes.Structure):
+    _fields_ = [("num_skeletons", ctypes.c_int32), ("num_joints", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("parents", ctypes.c_void_p)]
 
 
 class hs_plan_opts(ctypes.Structure):
@@ -109,6 +114,8 @@ def load_library():
     lib.hs_context_destroy.restype = None
     lib.hs_plan_create.argtypes = [vp, ctypes.POINTER(hs_batch), ctypes.POINTER(hs_plan_opts),
                                    ctypes.POINTER(vp)]
+    lib.hs_plan_create_instanced.argtypes = [vp, ctypes.POINTER(hs_skeleton_set), i32, vp,
+                                             ctypes.POINTER(hs_plan_opts), ctypes.POINTER(vp)]
     lib.hs_plan_destroy.argtypes = [vp]
     lib.hs_plan_destroy.restype = None
     lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
@@ -200,7 +207,7 @@ class Plan:
 
     def __init__(self, offsets, parents, ctx=None, strategy=HS_STRATEGY_AUTO, tile_joints=0,
                  waves_per_tile=0, grid_tiles=0, autotune=False, chain_units=False, algorithm=HS_ALG_SCAN,
-                 adjoint=HS_ADJ_AUTO):
+                 adjoint=HS_ADJ_AUTO, skeletons=None):
         self.ctx = ctx or default_context()
         off = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
                                               dtype=np.int64))
@@ -214,9 +221,34 @@ class Plan:
         opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)),
                             int(bool(chain_units)), int(algorithm), int(adjoint))
         h = ctypes.c_void_p()
-        _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),
-                                             ctypes.byref(h)))
+        if skeletons is None:
+            _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),
+                                                 ctypes.byref(h)))
+            self.bind_rows = self.num_joints
+        else:
+            soff, spar, sid = skeletons
+            sk = hs_skeleton_set(soff.size - 1, spar.size, soff.ctypes.data, spar.ctypes.data)
+            _check(load_library().hs_plan_create_instanced(self.ctx.handle, ctypes.byref(sk), sid.size,
+                                                           sid.ctypes.data, ctypes.byref(opts), ctypes.byref(h)))
+            self.bind_rows = spar.size  # inverse binds: one row per skeleton joint
         self.handle = h
+
+    @classmethod
+    def instanced(cls, skel_offsets, skel_parents, skeleton_id, **kw):
+        """Plan for characters that are copies of shared skeletons (see
+        ``hs_plan_create_instanced``): character c is skeleton
+        ``skeleton_id[c]``; inverse binds are then given per skeleton joint."""
+        soff = np.ascontiguousarray(np.asarray(skel_offsets, dtype=np.int64))
+        spar = np.ascontiguousarray(np.asarray(skel_parents, dtype=np.int32))
+        sid = np.ascontiguousarray(np.asarray(skeleton_id, dtype=np.int32))
+        if soff.ndim != 1 or soff.size < 1 or spar.ndim != 1 or sid.ndim != 1:
+            raise ValueError("skeleton offsets, parents and ids must be 1-D")
+        if sid.size and (sid.min() < 0 or sid.max() >= soff.size - 1):
+            raise ValueError("skeleton_id out of range")
+        sizes = np.diff(soff)
+        off = np.concatenate([[0], np.cumsum(sizes[sid])]).astype(np.int64)
+        par = np.concatenate([spar[soff[k]:soff[k + 1]] for k in sid]) if sid.size else np.zeros(0, np.int32)
+        return cls(off, par, skeletons=(soff, spar, sid), **kw)
 
     @property
     def info(self):
@@ -304,7 +336,7 @@ def hs_scan_forward(plan, quat=None, trans=None, scale=None, *, clips=None, clip
     elif global_out is not None:
         _need(global_out, "global_out", (N, 4, 4))
     if inv_bind is not None:
-        _need(inv_bind, "inv_bind", (N, 4, 4))
+        _need(inv_bind, "inv_bind", (plan.bind_rows, 4, 4))
         if skin_out is None:
             skin_out = torch.empty((N, 4, 4), device=dev, dtype=torch.float32)
         else:
@@ -390,7 +422,7 @@ class ForwardGraph:
             if c.get("global_out") is not None:
                 _need(c["global_out"], "global_out", (N, 4, 4))
             if c.get("inv_bind") is not None:
-                _need(c["inv_bind"], "inv_bind", (N, 4, 4))
+                _need(c["inv_bind"], "inv_bind", (plan.bind_rows, 4, 4))
                 _need(c.get("skin_out"), "skin_out", (N, 4, 4))
             gouts[i], binds[i], souts[i] = (_ptr(c.get("global_out")), _ptr(c.get("inv_bind")),
                                            _ptr(c.get("skin_out")))

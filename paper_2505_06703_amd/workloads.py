@@ -8,7 +8,7 @@ computed by the caller from ``rest_*`` arrays returned here.
 
 The shapes follow the paper's benchmark (Sec. 4, Table 1: thousands of
 characters of a few hundred joints, hierarchies 15-120 levels deep) and the
-five workload presets below:
+workload presets below:
 
 * ``plain_scan``      -- 64 random trees of 64 joints, depth <= 16;
 * ``deep_forward``    -- 4096 x (humanoid-64 + 4 chains of 240), depth 246;
@@ -16,8 +16,13 @@ five workload presets below:
                          branching probability 0.3, 1% pure chains;
 * ``fused_sample``    -- 10000 x (humanoid-64 + 3 chains of 64) sampling a
                          library of 64 clips x 30 keys;
+* ``fused_sample_instanced`` -- fused_sample with all characters instances
+                         of one skeleton (shared hierarchy and rest pose);
 * ``differentiable``  -- 1024 x (humanoid-64 + 4 chains of 112) with 16
-                         end effectors and targets.
+                         end effectors and targets;
+* ``long_chains``     -- 64 chains of 65536 joints (the multipass path);
+* ``depth_sweep``     -- the paper's experiment scene: 10000 characters of
+                         300 joints at a chosen depth (15 to 120 levels).
 """
 from dataclasses import dataclass, field
 from typing import Optional
@@ -307,6 +312,24 @@ def fused_sample(seed=3, num_characters=10000, num_clips=64, num_keys=30, fps=30
     return b
 
 
+def fused_sample_instanced(seed=3, num_characters=10000, **kw):
+    """fused_sample with every character an instance of one skeleton: the
+    hierarchy and the rest pose (so the inverse binds) are the skeleton's,
+    shared by all characters; poses still come from per-character clips."""
+    b = fused_sample(seed=seed, num_characters=num_characters, **kw)
+    tmpl = b.extra["template"]
+    J = tmpl.size
+    rng = np.random.default_rng(seed * 1000 + 7)
+    rq, rt, rs = random_pose(rng, J)
+    b.name = "fused_sample_instanced"
+    b.rest_quat = np.tile(rq, (num_characters, 1))
+    b.rest_trans = np.tile(rt, (num_characters, 1))
+    b.rest_scale = np.tile(rs, (num_characters, 1))
+    b.extra.update(skel_offsets=np.array([0, J], np.int64), skel_parents=tmpl.astype(np.int32),
+                   skeleton_id=np.zeros(num_characters, np.int32), skel_rest=(rq, rt, rs))
+    return b
+
+
 def differentiable(seed=4, num_characters=1024, chain_len=112, radius=0.5):
     """Humanoid-64 + 4 chains of 112 (512 joints, depth 118); 16 end
     effectors (4 chain tips, 10 fingertips, 2 toe ends) with target offsets
@@ -377,6 +400,7 @@ PRESETS = {
     "deep_forward": deep_forward,
     "heterogeneous": heterogeneous,
     "fused_sample": fused_sample,
+    "fused_sample_instanced": fused_sample_instanced,
     "differentiable": differentiable,
     "long_chains": long_chains,
     "depth_sweep": depth_sweep,

@@ -82,3 +82,15 @@ def test_depth_sweep_depths():
         b = wl.depth_sweep(num_characters=5, depth=d, templates=5)
         _valid(b)
         assert b.num_joints == 1500 and b.depth() == d
+
+
+def test_fused_sample_instanced_shares_one_skeleton():
+    b = wl.fused_sample_instanced(num_characters=5)
+    x = b.extra
+    J = x["skel_parents"].size
+    assert list(x["skel_offsets"]) == [0, J] and np.all(x["skeleton_id"] == 0)
+    np.testing.assert_array_equal(b.parents, np.tile(x["skel_parents"], 5))
+    np.testing.assert_array_equal(b.rest_quat, np.tile(x["skel_rest"][0], (5, 1)))
+    # the per-character clip choices are those of fused_sample with the same seed
+    ref = wl.fused_sample(num_characters=5)
+    np.testing.assert_array_equal(x["clip_a"], ref.extra["clip_a"])
