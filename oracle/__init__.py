@@ -20,6 +20,9 @@ the plain C routines in ``hs_oracle.c``; those follow the definitions:
   local quaternions, translations and scales;
 * ``path_length`` -- root-to-joint polyline length used to scale tolerances.
 
+``oracle.vertex_skin`` (NumPy, FP64) holds the vertex-skinning oracle: linear
+blend and dual quaternion skinning of mesh vertices with the S_j.
+
 Parity status: pinned by the ``-m "not gpu"`` tests (brute force, closed
 forms, invariants, finite differences); the paper prints no numeric values.
 """
