@@ -42,7 +42,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_06703_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 256 << 20
 WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "fused_sample_instanced",
-             "differentiable", "long_chains"]
+             "differentiable", "long_chains", "mesh_skinning"]
 FUSED = ("fused_sample", "fused_sample_instanced")
 
 # algorithmic HBM bytes per joint that the dominant kernel of a step must
@@ -334,6 +334,9 @@ def main():
     if args.depth_sweep:
         depth_sweep(args)
         return
+    if args.workload == "mesh_skinning":
+        mesh_bench(args)
+        return
     w = Workload(args.workload, autotune=not args.no_autotune, adjoint=args.adjoint)
     b, info = w.b, w.plan.info
     N, C = b.num_joints, b.num_characters
@@ -444,6 +447,67 @@ def depth_sweep(args):
                               "tile_joints": plan.info["tile_joints"]}), flush=True)
             g.close()
             plan.close()
+
+
+def mesh_bench(args):
+    """The mesh_skinning workload: per step, the fused forward of the
+    instanced batch (clip sampling, scan, skin matrices) and vertex skinning
+    of every character's mesh; one JSON line per skinning method.  Output
+    sets cycled so that one cycle touches at least SWEEP_BYTES."""
+    import torch
+    from paper_2505_06703_amd import hs
+    from paper_2505_06703_amd import workloads as wl
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    b = wl.mesh_skinning()
+    x = b.extra
+    N, C = b.num_joints, b.num_characters
+    plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"], autotune=not args.no_autotune)
+    one = hs.Plan(x["skel_offsets"], x["skel_parents"])
+    Grest, _ = hs.hs_scan_forward(one, *(up(a) for a in x["skel_rest"]))
+    inv = up(np.linalg.inv(Grest.cpu().numpy().astype(np.float64)).astype(np.float32))
+    lib = hs.ClipLibrary(up(x["key_quat"]), up(x["key_trans"]), x["fps"])
+    cp = dict(clip_a=up(x["clip_a"]), clip_b=up(x["clip_b"]), time=up(x["time"]), weight=up(x["weight"]))
+    mesh = hs.Mesh(plan, x["vertex_offsets"], x["mesh_first"], x["mesh_positions"], x["mesh_joints"],
+                   x["mesh_weights"])
+    V = mesh.num_vertices
+    set_bytes = N * 64 + V * 12
+    n_sets = int(min(MAX_SETS, max(2, -(-SWEEP_BYTES // set_bytes))))
+    sets = [(torch.empty((N, 4, 4), device="cuda:0"), torch.empty((V, 3), device="cuda:0")) for _ in range(n_sets)]
+    rows = x["mesh_positions"].shape[0]
+    # algorithmic bytes of one vertex-skinning launch: rows 0-2 of every skin
+    # matrix read, every vertex written, the shared mesh rows read once
+    vbytes = N * 48 + V * 12 + rows * 44 + C * 20
+    for method, name in ((hs.HS_SKIN_LINEAR, "linear"), (hs.HS_SKIN_DUAL_QUAT, "dual_quat")):
+        def step(k, ev=None):
+            S, out = sets[k % n_sets]
+            hs.hs_scan_forward(plan, clips=lib, **cp, want_global=False, inv_bind=inv, skin_out=S)
+            if ev is not None:
+                ev[0].record()
+            hs.hs_skin_vertices(mesh, S, method, out)
+            if ev is not None:
+                ev[1].record()
+        for k in range(args.warmup):
+            step(k)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(k, evs[k])
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+        achieved = vbytes / (kms * 1e-3) / 1e9
+        print(json.dumps({
+            "metric": "skinned vertices/s (clip sampling + scan + skin + vertex skinning) on 1 GPU",
+            "value": V * args.steps / elapsed, "unit": "vertices/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "mesh_skinning", "method": name, "characters": C, "joints": N,
+                       "vertices": V, "faces_per_mesh": 2 * (V // C) - 4, "input_sets": n_sets},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "vertex_skin_kernel",
+                         "kernel_ms": kms, "algorithmic_bytes_per_launch": vbytes}}), flush=True)
 
 
 def device_copy_gbs(torch, nbytes=1 << 30, reps=10):

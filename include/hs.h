@@ -316,6 +316,56 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
                            const float *ckpt, int32_t ckpt_k, float *grad_quat, float *grad_trans,
                            float *grad_scale, uint32_t flags, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Vertex skinning: the stage after Bind MeshPose.  The paper's pipeline
+ * skins meshes with the skin matrices on the GPU (Sec. 3; Sec. 5 uses
+ * meshes of 1000-3000 faces); each vertex moves by a weighted blend of the
+ * S_j = G_j B_j^-1 of up to four joints of its character.
+ * ------------------------------------------------------------------------ */
+
+/* HS_SKIN_LINEAR: linear blend, p' = (sum_i w_i S_{j_i}) [p, 1], weights as
+ * given.  HS_SKIN_DUAL_QUAT: dual quaternion skinning (Kavan, Collins,
+ * Zara, O'Sullivan 2008): each S_j read as a rigid transform (its 3x3 block
+ * as a rotation) and turned into a unit dual quaternion, the influences
+ * summed with w_i times the sign of their rotation quaternion's dot product
+ * with influence 0's (influence 0 is the pivot), normalised by the real
+ * part, applied as a rigid transform; a row whose weights sum the real parts
+ * to zero gives NaN. */
+#define HS_SKIN_LINEAR 0
+#define HS_SKIN_DUAL_QUAT 1
+
+/* Meshes of a plan's characters.  Character c's skinned vertices are
+ * output rows vertex_offsets[c] .. vertex_offsets[c+1]-1 (vertex_offsets[0]
+ * = 0, non-decreasing); its k-th vertex is row mesh_first[c] + k of the mesh
+ * arrays, so characters of one kind share their rows.  joints[] are
+ * character-local joint ids (unused slots: any valid id with weight 0).
+ * All pointers may be host or device memory; hs_mesh_create copies them. */
+typedef struct hs_mesh_batch {
+    const int64_t *vertex_offsets; /* [C+1] */
+    const int32_t *mesh_first;     /* [C] */
+    int64_t num_rows;              /* rows of the mesh arrays */
+    const float *positions;        /* [num_rows, 3] bind-space positions */
+    const int32_t *joints;         /* [num_rows, 4] */
+    const float *weights;          /* [num_rows, 4] */
+} hs_mesh_batch;
+
+typedef struct hs_mesh hs_mesh;
+
+/* Validate and copy a mesh batch for the plan's characters: mesh rows in
+ * range, every joint id in [0, joints of its character), characters with
+ * vertices at most 2048 joints (HS_ERR_UNSUPPORTED beyond), total vertices
+ * below 2^31.  Errors: HS_ERR_INVALID_ARG.  Synchronises the device once. */
+hs_status hs_mesh_create(const hs_plan *plan, const hs_mesh_batch *mesh, hs_mesh **out);
+void hs_mesh_destroy(hs_mesh *mesh);
+
+/* Skin every vertex: skin[N,4,4] (device, 16-byte aligned; rows 0-2 read)
+ * from hs_scan_forward / hs_skin, out[V,3] (device, 4-byte aligned, V =
+ * vertex_offsets[C]).  Asynchronous on stream; allocates nothing.  Errors:
+ * HS_ERR_INVALID_ARG (NULL or misaligned arrays, unknown method, out
+ * overlapping skin). */
+hs_status hs_skin_vertices(const hs_mesh *mesh, const float *skin, int32_t method, float *out,
+                           hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

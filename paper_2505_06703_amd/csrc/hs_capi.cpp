@@ -1287,6 +1287,132 @@ hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *
     return HS_OK;
 }
 
+} // extern "C"
+
+struct hs_mesh {
+    int device = 0;
+    int64_t N = 0, V = 0, rows = 0;
+    hs::VertexLaunch vl{};
+    int64_t *d_offsets = nullptr, *d_voff = nullptr;
+    int32_t *d_mfirst = nullptr, *d_joints = nullptr;
+    float *d_pos = nullptr, *d_weights = nullptr;
+};
+
+namespace {
+
+void free_mesh(hs_mesh *m)
+{
+    if (!m) return;
+    (void)hipFree(m->d_offsets);
+    (void)hipFree(m->d_voff);
+    (void)hipFree(m->d_mfirst);
+    (void)hipFree(m->d_joints);
+    (void)hipFree(m->d_pos);
+    (void)hipFree(m->d_weights);
+    delete m;
+}
+
+} // namespace
+
+extern "C" {
+
+hs_status hs_mesh_create(const hs_plan *plan, const hs_mesh_batch *mb, hs_mesh **out)
+{
+    if (!out) return fail(HS_ERR_INVALID_ARG, "hs_mesh_create: out is NULL");
+    *out = nullptr;
+    if (!plan || !mb) return fail(HS_ERR_INVALID_ARG, "hs_mesh_create: plan and mesh must be non-NULL");
+    const int64_t C = plan->C, R = mb->num_rows;
+    if (R < 0 || R >= (int64_t(1) << 31)) return fail(HS_ERR_INVALID_ARG, "num_rows %lld out of range", (long long)R);
+    if (!mb->vertex_offsets || (C > 0 && !mb->mesh_first) ||
+        (R > 0 && (!mb->positions || !mb->joints || !mb->weights)))
+        return fail(HS_ERR_INVALID_ARG, "hs_mesh_create: NULL mesh array");
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_mesh_create: cannot select device");
+    std::vector<int64_t> voff;
+    std::vector<int32_t> mfirst, joints;
+    std::vector<float> pos, wts;
+    hipError_t err;
+    if ((err = fetch(voff, mb->vertex_offsets, (size_t)C + 1)) != hipSuccess ||
+        (err = fetch(mfirst, mb->mesh_first, (size_t)C)) != hipSuccess ||
+        (err = fetch(joints, mb->joints, (size_t)R * 4)) != hipSuccess ||
+        (err = fetch(pos, mb->positions, (size_t)R * 3)) != hipSuccess ||
+        (err = fetch(wts, mb->weights, (size_t)R * 4)) != hipSuccess)
+        return fail_hip(err, "hs_mesh_create (reading the mesh)");
+    if (voff[0] != 0) return fail(HS_ERR_INVALID_ARG, "vertex_offsets[0] must be 0");
+    if (voff[C] >= (int64_t(1) << 31)) return fail(HS_ERR_INVALID_ARG, "more than 2^31-1 vertices");
+    // joint-id range of each distinct run of mesh rows, computed once
+    std::map<std::pair<int64_t, int64_t>, std::pair<int32_t, int32_t>> ranges;
+    int max_joints = 0;
+    for (int64_t c = 0; c < C; ++c) {
+        const int64_t nv = voff[c + 1] - voff[c];
+        if (nv < 0) return fail(HS_ERR_INVALID_ARG, "vertex_offsets must be non-decreasing");
+        if (nv == 0) continue;
+        if (mfirst[c] < 0 || mfirst[c] + nv > R)
+            return fail(HS_ERR_INVALID_ARG, "character %lld: mesh rows [%d, %lld) outside [0, %lld)", (long long)c,
+                        mfirst[c], (long long)(mfirst[c] + nv), (long long)R);
+        const int64_t nj = plan->h_offsets[c + 1] - plan->h_offsets[c];
+        if (nj > hs::kMaxSkinJoints)
+            return fail(HS_ERR_UNSUPPORTED, "character %lld has %lld joints; vertex skinning stages at most %d",
+                        (long long)c, (long long)nj, hs::kMaxSkinJoints);
+        max_joints = std::max<int>(max_joints, (int)nj);
+        auto key = std::make_pair((int64_t)mfirst[c], nv);
+        auto it = ranges.find(key);
+        if (it == ranges.end()) {
+            int32_t lo = INT32_MAX, hi = INT32_MIN;
+            for (int64_t k = 4 * (int64_t)mfirst[c]; k < 4 * (mfirst[c] + nv); ++k) {
+                lo = std::min(lo, joints[k]);
+                hi = std::max(hi, joints[k]);
+            }
+            it = ranges.emplace(key, std::make_pair(lo, hi)).first;
+        }
+        if (it->second.first < 0 || it->second.second >= nj)
+            return fail(HS_ERR_INVALID_ARG, "character %lld: joint ids in [%d, %d] but it has %lld joints",
+                        (long long)c, it->second.first, it->second.second, (long long)nj);
+    }
+    hs_mesh *m = new hs_mesh();
+    m->device = plan->ctx->device;
+    m->N = plan->N;
+    m->V = voff[C];
+    m->rows = R;
+    if ((err = upload(&m->d_offsets, plan->h_offsets)) != hipSuccess || (err = upload(&m->d_voff, voff)) != hipSuccess ||
+        (err = upload(&m->d_mfirst, mfirst)) != hipSuccess || (err = upload(&m->d_joints, joints)) != hipSuccess ||
+        (err = upload(&m->d_pos, pos)) != hipSuccess || (err = upload(&m->d_weights, wts)) != hipSuccess) {
+        free_mesh(m);
+        return fail_hip(err, "hs_mesh_create (upload)");
+    }
+    hs::VertexLaunch &vl = m->vl;
+    vl.offsets = m->d_offsets;
+    vl.voff = m->d_voff;
+    vl.mfirst = m->d_mfirst;
+    vl.pos = m->d_pos;
+    vl.joints = m->d_joints;
+    vl.weights = m->d_weights;
+    vl.C = (int32_t)C;
+    vl.max_joints = max_joints;
+    *out = m;
+    return HS_OK;
+}
+
+void hs_mesh_destroy(hs_mesh *mesh) { free_mesh(mesh); }
+
+hs_status hs_skin_vertices(const hs_mesh *mesh, const float *skin, int32_t method, float *out, hipStream_t stream)
+{
+    if (!mesh) return fail(HS_ERR_INVALID_ARG, "hs_skin_vertices: mesh is NULL");
+    if (method != HS_SKIN_LINEAR && method != HS_SKIN_DUAL_QUAT)
+        return fail(HS_ERR_INVALID_ARG, "hs_skin_vertices: unknown method %d", method);
+    if (mesh->V == 0) return HS_OK;
+    if (!skin || !out) return fail(HS_ERR_INVALID_ARG, "hs_skin_vertices: skin and out must be non-NULL");
+    if (!aligned(skin, 16) || !aligned(out, 4))
+        return fail(HS_ERR_INVALID_ARG, "hs_skin_vertices: skin must be 16-byte and out 4-byte aligned");
+    hs_status rc = check_aliasing({{out, (size_t)mesh->V * 12, "out"}}, {{skin, (size_t)mesh->N * 64, "skin"}});
+    if (rc != HS_OK) return rc;
+    DeviceGuard dg(mesh->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_skin_vertices: cannot select device");
+    hipError_t err = hs::launch_vertex_skin(mesh->vl, method, skin, out, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_skin_vertices");
+    return HS_OK;
+}
+
 hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const float *grad_global, const float *ckpt,
                            int32_t ckpt_k, float *grad_quat, float *grad_trans, float *grad_scale, uint32_t flags,
                            hipStream_t stream)

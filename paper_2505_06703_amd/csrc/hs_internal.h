@@ -145,6 +145,25 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 // needs (once per process and device, before any launch or capture).
 hipError_t prepare_kernels();
 
+// Vertex skinning (after the Bind MeshPose step): character c's vertices
+// are output rows voff[c] .. voff[c+1]-1; its k-th vertex reads mesh row
+// mfirst[c] + k; joint ids are character-local (checked when the mesh is
+// created: 0 <= id < the character's joint count <= kMaxSkinJoints).
+constexpr int kMaxSkinJoints = 2048;
+struct VertexLaunch {
+    const int64_t *offsets;  // [C+1] joint CSR offsets
+    const int64_t *voff;     // [C+1] vertex offsets
+    const int32_t *mfirst;   // [C] first mesh row of each character
+    const float *pos;        // [rows,3] bind-space positions
+    const int32_t *joints;   // [rows,4]
+    const float *weights;    // [rows,4]
+    int32_t C;
+    int32_t max_joints;      // largest character with vertices (LDS staging)
+};
+// method 0: linear blend; 1: dual quaternions
+hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *skin, float *out,
+                              hipStream_t stream);
+
 // Tiles of the paper's Algorithms 1-4 (one joint per thread).
 constexpr int kPaperAlgTileJoints = 1024;
 

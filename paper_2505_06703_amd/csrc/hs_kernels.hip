@@ -1326,6 +1326,158 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 }
 
 // ---------------------------------------------------------------------------
+// Vertex skinning: each mesh vertex moves by a weighted blend of the skin
+// matrices S_j of up to four joints of its character.
+//   linear blend: p' = (sum_i w_i S_{j_i}) [p, 1];
+//   dual quaternions (Kavan, Collins, Zara, O'Sullivan 2008): every rigid
+//     S_j as a unit dual quaternion (q_r, q_d = 1/2 (t, 0) q_r); the
+//     influences summed with w_i times the sign of q_r,i . q_r,0, divided by
+//     the norm of the real part, applied as a rigid transform.
+// One workgroup per character: its skin matrices (or their dual
+// quaternions, converted once per joint) are staged in LDS, then every
+// thread takes vertices; the mesh arrays are shared by the characters of
+// a kind and stay in cache.
+// LDS: [max_joints][3] float4 (linear) or [max_joints][2] float4 (dual)
+// ---------------------------------------------------------------------------
+constexpr int kSkinThreads = 256;
+
+// Quaternion (x, y, z, w) of the rotation block of a rigid transform given
+// by its rows (Shepperd's method: divide by the largest of the four
+// 4 q_k^2 that the diagonal determines), then the dual part 1/2 (t, 0) q.
+__device__ __forceinline__ void rigid_to_dual_quat(float4 r0, float4 r1, float4 r2, float4 &qr, float4 &qd)
+{
+    const float m00 = r0.x, m01 = r0.y, m02 = r0.z, m10 = r1.x, m11 = r1.y, m12 = r1.z;
+    const float m20 = r2.x, m21 = r2.y, m22 = r2.z;
+    const float tr = m00 + m11 + m22;
+    float x, y, z, w;
+    if (tr > 0.0f) {
+        const float s = 2.0f * sqrtf(tr + 1.0f);
+        const float is = 1.0f / s;
+        w = 0.25f * s;
+        x = (m21 - m12) * is;
+        y = (m02 - m20) * is;
+        z = (m10 - m01) * is;
+    } else if (m00 > m11 && m00 > m22) {
+        const float s = 2.0f * sqrtf(1.0f + m00 - m11 - m22);
+        const float is = 1.0f / s;
+        w = (m21 - m12) * is;
+        x = 0.25f * s;
+        y = (m01 + m10) * is;
+        z = (m02 + m20) * is;
+    } else if (m11 > m22) {
+        const float s = 2.0f * sqrtf(1.0f + m11 - m00 - m22);
+        const float is = 1.0f / s;
+        w = (m02 - m20) * is;
+        x = (m01 + m10) * is;
+        y = 0.25f * s;
+        z = (m12 + m21) * is;
+    } else {
+        const float s = 2.0f * sqrtf(1.0f + m22 - m00 - m11);
+        const float is = 1.0f / s;
+        w = (m10 - m01) * is;
+        x = (m02 + m20) * is;
+        y = (m12 + m21) * is;
+        z = 0.25f * s;
+    }
+    const float n = 1.0f / sqrtf(x * x + y * y + z * z + w * w);
+    x *= n; y *= n; z *= n; w *= n;
+    qr = make_float4(x, y, z, w);
+    const float tx = r0.w, ty = r1.w, tz = r2.w;
+    qd = make_float4(0.5f * (tx * w + ty * z - tz * y), 0.5f * (-tx * z + ty * w + tz * x),
+                     0.5f * (tx * y - ty * x + tz * w), -0.5f * (tx * x + ty * y + tz * z));
+}
+
+__device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+
+__device__ __forceinline__ void fma4(float4 &acc, float s, float4 v)
+{
+    acc.x = fmaf(s, v.x, acc.x);
+    acc.y = fmaf(s, v.y, acc.y);
+    acc.z = fmaf(s, v.z, acc.z);
+    acc.w = fmaf(s, v.w, acc.w);
+}
+
+template <int METHOD>
+__global__ void __launch_bounds__(kSkinThreads)
+vertex_skin_kernel(VertexLaunch vl, const float4 *skin, float *out)
+{
+    extern __shared__ float4 lds[];
+    for (int c = blockIdx.x; c < vl.C; c += gridDim.x) {
+        const int64_t v0 = vl.voff[c];
+        const int nv = (int)(vl.voff[c + 1] - v0);
+        if (nv == 0) continue;  // uniform across the workgroup
+        const int64_t j0 = vl.offsets[c];
+        const int nj = (int)(vl.offsets[c + 1] - j0);
+        for (int j = threadIdx.x; j < nj; j += kSkinThreads) {
+            const float4 *S = skin + 4 * (j0 + j);
+            const float4 r0 = S[0], r1 = S[1], r2 = S[2];
+            if constexpr (METHOD == 0) {
+                lds[3 * j] = r0;
+                lds[3 * j + 1] = r1;
+                lds[3 * j + 2] = r2;
+            } else {
+                float4 qr, qd;
+                rigid_to_dual_quat(r0, r1, r2, qr, qd);
+                lds[2 * j] = qr;
+                lds[2 * j + 1] = qd;
+            }
+        }
+        __syncthreads();
+        const int64_t m0 = vl.mfirst[c];
+        for (int v = threadIdx.x; v < nv; v += kSkinThreads) {
+            const int64_t m = m0 + v;
+            const float px = vl.pos[3 * m], py = vl.pos[3 * m + 1], pz = vl.pos[3 * m + 2];
+            const int4 ji = reinterpret_cast<const int4 *>(vl.joints)[m];
+            const float4 wt = reinterpret_cast<const float4 *>(vl.weights)[m];
+            const int jk[4] = {ji.x, ji.y, ji.z, ji.w};
+            const float wk[4] = {wt.x, wt.y, wt.z, wt.w};
+            float ox, oy, oz;
+            if constexpr (METHOD == 0) {
+                float4 a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), a1 = a0, a2 = a0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    fma4(a0, wk[k], lds[3 * jk[k]]);
+                    fma4(a1, wk[k], lds[3 * jk[k] + 1]);
+                    fma4(a2, wk[k], lds[3 * jk[k] + 2]);
+                }
+                ox = fmaf(a0.x, px, fmaf(a0.y, py, fmaf(a0.z, pz, a0.w)));
+                oy = fmaf(a1.x, px, fmaf(a1.y, py, fmaf(a1.z, pz, a1.w)));
+                oz = fmaf(a2.x, px, fmaf(a2.y, py, fmaf(a2.z, pz, a2.w)));
+            } else {
+                const float4 q0 = lds[2 * jk[0]];
+                float4 br = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bd = br;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float4 q = lds[2 * jk[k]], d = lds[2 * jk[k] + 1];
+                    const float s = dot4(q, q0) < 0.0f ? -wk[k] : wk[k];
+                    fma4(br, s, q);
+                    fma4(bd, s, d);
+                }
+                const float inv = 1.0f / sqrtf(dot4(br, br));
+                const float rx = br.x * inv, ry = br.y * inv, rz = br.z * inv, rw = br.w * inv;
+                const float dx = bd.x * inv, dy = bd.y * inv, dz = bd.z * inv, dw = bd.w * inv;
+                // p + 2 r x (r x p + w p)
+                const float cx = ry * pz - rz * py + rw * px;
+                const float cy = rz * px - rx * pz + rw * py;
+                const float cz = rx * py - ry * px + rw * pz;
+                // translation 2 (w_r d - w_d r + r x d)
+                const float tx = 2.0f * (rw * dx - dw * rx + ry * dz - rz * dy);
+                const float ty = 2.0f * (rw * dy - dw * ry + rz * dx - rx * dz);
+                const float tz = 2.0f * (rw * dz - dw * rz + rx * dy - ry * dx);
+                ox = px + 2.0f * (ry * cz - rz * cy) + tx;
+                oy = py + 2.0f * (rz * cx - rx * cz) + ty;
+                oz = pz + 2.0f * (rx * cy - ry * cx) + tz;
+            }
+            float *dst = out + 3 * (v0 + v);
+            dst[0] = ox;
+            dst[1] = oy;
+            dst[2] = oz;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Multipass path.
 // ---------------------------------------------------------------------------
 constexpr int kMPWaves = 4;
@@ -1740,6 +1892,11 @@ hipError_t set_lds_limits()
 hipError_t prepare_kernels()
 {
     hipError_t err;
+    if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_skin_kernel<0>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSkinJoints * 48)) != hipSuccess ||
+        (err = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_skin_kernel<1>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSkinJoints * 32)) != hipSuccess)
+        return err;
     if ((err = set_lds_limits<1>()) != hipSuccess) return err;
     if ((err = set_lds_limits<2>()) != hipSuccess) return err;
     if ((err = set_lds_limits<4>()) != hipSuccess) return err;
@@ -1856,6 +2013,20 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
                        reinterpret_cast<const float4 *>(global),
                        reinterpret_cast<const float4 *>(inv_bind),
                        reinterpret_cast<float4 *>(skin_out));
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *skin, float *out,
+                              hipStream_t stream)
+{
+    if (vl.C == 0) return hipSuccess;
+    if (vl.max_joints > kMaxSkinJoints || (method != 0 && method != 1)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)vl.C), blk(kSkinThreads);
+    const float4 *S = reinterpret_cast<const float4 *>(skin);
+    if (method == 0)
+        hipLaunchKernelGGL(vertex_skin_kernel<0>, grid, blk, (size_t)vl.max_joints * 48, stream, vl, S, out);
+    else
+        hipLaunchKernelGGL(vertex_skin_kernel<1>, grid, blk, (size_t)vl.max_joints * 32, stream, vl, S, out);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ HS_STRATEGY_TILE = 1
 HS_STRATEGY_MULTIPASS = 2
 HS_ALG_SCAN, HS_ALG_WALK, HS_ALG_JUMP, HS_ALG_BLOCKS, HS_ALG_COMPRESSED = 0, 1, 2, 3, 4
 HS_ADJ_AUTO, HS_ADJ_ROUNDS, HS_ADJ_DATAFLOW = 0, 1, 2
+HS_SKIN_LINEAR, HS_SKIN_DUAL_QUAT = 0, 1
 
 HS_POSE_TRS = 0
 HS_POSE_CLIPS = 1
@@ -37,7 +38,8 @@ HS_POSE_CLIPS = 1
 SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
            "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
-           "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy")
+           "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
+           "hs_mesh_destroy", "hs_skin_vertices")
 
 
 class HSError(RuntimeError):
@@ -54,6 +56,11 @@ class hs_batch(ctypes.Structure):
 class hs_skeleton_set(ctypes.Structure):
     _fields_ = [("num_skeletons", ctypes.c_int32), ("num_joints", ctypes.c_int64),
                 ("offsets", ctypes.c_void_p), ("parents", ctypes.c_void_p)]
+
+
+class hs_mesh_batch(ctypes.Structure):
+    _fields_ = [("vertex_offsets", ctypes.c_void_p), ("mesh_first", ctypes.c_void_p), ("num_rows", ctypes.c_int64),
+                ("positions", ctypes.c_void_p), ("joints", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
 
 
 class hs_plan_opts(ctypes.Structure):
@@ -116,6 +123,10 @@ def load_library():
                                    ctypes.POINTER(vp)]
     lib.hs_plan_create_instanced.argtypes = [vp, ctypes.POINTER(hs_skeleton_set), i32, vp,
                                              ctypes.POINTER(hs_plan_opts), ctypes.POINTER(vp)]
+    lib.hs_mesh_create.argtypes = [vp, ctypes.POINTER(hs_mesh_batch), ctypes.POINTER(vp)]
+    lib.hs_mesh_destroy.argtypes = [vp]
+    lib.hs_mesh_destroy.restype = None
+    lib.hs_skin_vertices.argtypes = [vp, vp, i32, vp, vp]
     lib.hs_plan_destroy.argtypes = [vp]
     lib.hs_plan_destroy.restype = None
     lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
@@ -358,6 +369,52 @@ def hs_skin(global_, inv_bind, skin_out=None, stream=None):
     _need(skin_out, "skin_out", (n, 4, 4))
     _check(load_library().hs_skin(n, _ptr(global_), _ptr(inv_bind), _ptr(skin_out), _stream(stream)))
     return skin_out
+
+
+class Mesh:
+    """Meshes of a plan's characters (see ``hs_mesh_create``): character c's
+    vertices are output rows ``vertex_offsets[c]`` .. ``vertex_offsets[c+1]-1``
+    and read mesh rows from ``mesh_first[c]`` on (host arrays; the library
+    copies them)."""
+
+    def __init__(self, plan, vertex_offsets, mesh_first, positions, joints, weights):
+        voff = np.ascontiguousarray(np.asarray(vertex_offsets, np.int64))
+        mf = np.ascontiguousarray(np.asarray(mesh_first, np.int32))
+        pos = np.ascontiguousarray(np.asarray(positions, np.float32))
+        jt = np.ascontiguousarray(np.asarray(joints, np.int32))
+        wt = np.ascontiguousarray(np.asarray(weights, np.float32))
+        rows = pos.shape[0]
+        if pos.shape != (rows, 3) or jt.shape != (rows, 4) or wt.shape != (rows, 4):
+            raise ValueError("positions, joints and weights must be [rows,3], [rows,4], [rows,4]")
+        if voff.shape != (plan.num_characters + 1,) or mf.shape != (plan.num_characters,):
+            raise ValueError("vertex_offsets and mesh_first must have C+1 and C entries")
+        self.num_vertices = int(voff[-1])
+        mb = hs_mesh_batch(voff.ctypes.data, mf.ctypes.data, rows, pos.ctypes.data, jt.ctypes.data, wt.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(load_library().hs_mesh_create(plan.handle, ctypes.byref(mb), ctypes.byref(h)))
+        self.handle = h
+        self.num_joints = plan.num_joints
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hs_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hs_skin_vertices(mesh, skin, method=HS_SKIN_LINEAR, out=None, stream=None):
+    """Skinned vertex positions [V,3] from the skin matrices [N,4,4]."""
+    _need(skin, "skin", (mesh.num_joints, 4, 4))
+    if out is None:
+        out = torch.empty((mesh.num_vertices, 3), device=skin.device)
+    _need(out, "out", (mesh.num_vertices, 3))
+    _check(load_library().hs_skin_vertices(mesh.handle, _ptr(skin), int(method), _ptr(out), _stream(stream)))
+    return out
 
 
 def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0, want_scale=True,

@@ -18,6 +18,8 @@ workload presets below:
                          library of 64 clips x 30 keys;
 * ``fused_sample_instanced`` -- fused_sample with all characters instances
                          of one skeleton (shared hierarchy and rest pose);
+* ``mesh_skinning``   -- fused_sample_instanced with a 2000-face mesh bound
+                         to the skeleton (vertex skinning);
 * ``differentiable``  -- 1024 x (humanoid-64 + 4 chains of 112) with 16
                          end effectors and targets;
 * ``long_chains``     -- 64 chains of 65536 joints (the multipass path);
@@ -330,6 +332,41 @@ def fused_sample_instanced(seed=3, num_characters=10000, **kw):
     return b
 
 
+def skin_mesh(rng, parents, num_faces=2000, radius=1.0):
+    """A synthetic mesh bound to one skeleton: V = num_faces / 2 + 2 vertices
+    (a closed genus-0 triangle mesh has F = 2V - 4 faces), each with four
+    influences -- a joint drawn uniformly, its parent, its grandparent and a
+    second uniform draw (a root stands in for missing ancestors) -- with
+    Dirichlet(1) weights sorted so that influence 0 weighs most.  Positions
+    are uniform in a ball in bind space.  Returns (positions [V,3] f32,
+    joints [V,4] i32, weights [V,4] f32)."""
+    parents = np.asarray(parents)
+    n = parents.size
+    V = num_faces // 2 + 2
+    j0 = rng.integers(0, n, V)
+    p1 = np.where(parents[j0] < 0, j0, parents[j0])
+    p2 = np.where(parents[p1] < 0, p1, parents[p1])
+    j3 = rng.integers(0, n, V)
+    joints = np.stack([j0, p1, p2, j3], axis=1).astype(np.int32)
+    w = np.sort(rng.dirichlet(np.ones(4), V), axis=1)[:, ::-1]
+    pos = ball_offsets(rng, V, radius)
+    return pos, joints, np.ascontiguousarray(w, dtype=np.float32)
+
+
+def mesh_skinning(seed=8, num_characters=10000, num_faces=2000, **kw):
+    """fused_sample_instanced plus one mesh of ``num_faces`` faces bound to
+    the shared skeleton (every character skins the same mesh rows)."""
+    b = fused_sample_instanced(seed=seed, num_characters=num_characters, **kw)
+    rng = np.random.default_rng(seed * 1000 + 11)
+    pos, joints, weights = skin_mesh(rng, b.extra["skel_parents"], num_faces)
+    V = pos.shape[0]
+    b.name = "mesh_skinning"
+    b.extra.update(mesh_positions=pos, mesh_joints=joints, mesh_weights=weights,
+                   vertex_offsets=np.arange(num_characters + 1, dtype=np.int64) * V,
+                   mesh_first=np.zeros(num_characters, np.int32))
+    return b
+
+
 def differentiable(seed=4, num_characters=1024, chain_len=112, radius=0.5):
     """Humanoid-64 + 4 chains of 112 (512 joints, depth 118); 16 end
     effectors (4 chain tips, 10 fingertips, 2 toe ends) with target offsets
@@ -401,6 +438,7 @@ PRESETS = {
     "heterogeneous": heterogeneous,
     "fused_sample": fused_sample,
     "fused_sample_instanced": fused_sample_instanced,
+    "mesh_skinning": mesh_skinning,
     "differentiable": differentiable,
     "long_chains": long_chains,
     "depth_sweep": depth_sweep,

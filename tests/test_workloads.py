@@ -94,3 +94,17 @@ def test_fused_sample_instanced_shares_one_skeleton():
     # the per-character clip choices are those of fused_sample with the same seed
     ref = wl.fused_sample(num_characters=5)
     np.testing.assert_array_equal(x["clip_a"], ref.extra["clip_a"])
+
+
+def test_skin_mesh_influences_and_weights():
+    rng = np.random.default_rng(0)
+    par = wl.humanoid_with_chains(["tail"], 8)[0]
+    pos, joints, w = wl.skin_mesh(rng, par, num_faces=1000)
+    assert pos.shape == (502, 3) and joints.shape == (502, 4) and w.shape == (502, 4)
+    assert joints.min() >= 0 and joints.max() < par.size
+    np.testing.assert_allclose(w.sum(axis=1), 1.0, atol=1e-6)
+    assert np.all(np.diff(w, axis=1) <= 0)  # influence 0 weighs most
+    # influences 1 and 2 are the parent and grandparent (roots stand in)
+    p1 = np.where(par[joints[:, 0]] < 0, joints[:, 0], par[joints[:, 0]])
+    np.testing.assert_array_equal(joints[:, 1], p1)
+    assert np.linalg.norm(pos, axis=1).max() <= 1.0 + 1e-6
