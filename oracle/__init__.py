@@ -22,6 +22,8 @@ the plain C routines in ``hs_oracle.c``; those follow the definitions:
 
 ``oracle.vertex_skin`` (NumPy, FP64) holds the vertex-skinning oracle: linear
 blend and dual quaternion skinning of mesh vertices with the S_j.
+``oracle.sample_backward`` (NumPy, FP64) is the reverse mode of the sampler:
+gradients of the keyframes, the clip time and the blend weight.
 
 Parity status: pinned by the ``-m "not gpu"`` tests (brute force, closed
 forms, invariants, finite differences); the paper prints no numeric values.
