@@ -233,6 +233,22 @@ typedef struct hs_clip_params {
 hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
                          float *quat_out, float *trans_out, hipStream_t stream);
 
+/* Reverse mode of hs_pose_sample: given dLoss/dquat [N,4] (raw components,
+ * 16-byte aligned) and dLoss/dtrans [N,3] of the sampled local poses,
+ * writes dLoss/dkey_quat [num_clips, num_keys, joints_per_clip, 4] and
+ * dLoss/dkey_trans [..., 3] (each the sum over every character and joint
+ * that reads the key; zeroed first, then accumulated with float atomics,
+ * so not bitwise reproducible), dLoss/dtime [C] and dLoss/dweight [C].  The
+ * arc signs and the key index floor(f) are held fixed (the derivative away
+ * from their switching points); d alpha / d time = fps.  Any output may be
+ * NULL (not computed).  A character with an invalid clip id or a
+ * non-finite time gets NaN time and weight gradients and adds nothing to
+ * the keys.  Asynchronous on stream; allocates nothing. */
+hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
+                                  const float *grad_quat, const float *grad_trans, float *grad_key_quat,
+                                  float *grad_key_trans, float *grad_time, float *grad_weight,
+                                  hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Hierarchy-Scan (Sec. 1 step 2; Eq. 1; Sec. 3) with optional fused skin.
  * ------------------------------------------------------------------------ */

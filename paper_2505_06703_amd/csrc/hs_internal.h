@@ -145,6 +145,18 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 // needs (once per process and device, before any launch or capture).
 hipError_t prepare_kernels();
 
+// Reverse mode of the sampler (see hs_pose_sample_backward).
+struct SampleBwdArgs {
+    const float *grad_quat;    // [N,4]
+    const float *grad_trans;   // [N,3]
+    float *grad_key_quat;      // [clips*keys*J*4] or null
+    float *grad_key_trans;     // [clips*keys*J*3] or null
+    float *grad_time;          // [C] or null
+    float *grad_weight;        // [C] or null
+    int32_t C;
+};
+hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs &A, hipStream_t stream);
+
 // Vertex skinning (after the Bind MeshPose step): character c's vertices
 // are output rows voff[c] .. voff[c+1]-1; its k-th vertex reads mesh row
 // mfirst[c] + k; joint ids are character-local (checked when the mesh is

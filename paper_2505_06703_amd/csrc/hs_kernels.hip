@@ -153,6 +153,26 @@ __device__ __forceinline__ float4 nlerp_blend(float4 a, float4 b, float wgt)
     return make_float4(r.x * inv, r.y * inv, r.z * inv, r.w * inv);
 }
 
+// Keys and interpolation parameter of character chr: frame f = fps * time
+// (one fp32 multiply), k0 = floor(f) mod K, k1 = k0 + 1 mod K, alpha =
+// f - floor(f).  False for an out-of-range clip id or a non-finite time.
+__device__ __forceinline__ bool sample_frame(const PoseArgs &P, int chr, int &k0, int &k1, float &alpha)
+{
+    const int ca = P.clip_a[chr], cb = P.clip_b[chr];
+    const int K = P.num_keys;
+    const float f = __fmul_rn(P.fps, P.time[chr]);
+    const float fl = floorf(f);
+    alpha = f - fl;
+    k0 = k1 = 0;
+    if (!(isfinite(fl) && ca >= 0 && ca < P.num_clips && cb >= 0 && cb < P.num_clips)) return false;
+    float r = fmodf(fl, (float)K);
+    if (r < 0.0f) r += (float)K;
+    k0 = (int)r;
+    if (k0 >= K) k0 = 0;
+    k1 = (k0 + 1 == K) ? 0 : k0 + 1;
+    return true;
+}
+
 // Sampled local pose of joint j (character-local) of character chr.  An
 // out-of-range clip id or a non-finite time yields NaN poses (never an
 // out-of-bounds read).
@@ -160,23 +180,16 @@ __device__ __forceinline__ void sample_pose(const PoseArgs &P, int chr, int j, f
                                             float &ty, float &tz)
 {
     const int ca = P.clip_a[chr], cb = P.clip_b[chr];
-    const float tau = P.time[chr], wgt = P.weight[chr];
+    const float wgt = P.weight[chr];
     const int K = P.num_keys, J = P.joints_per_clip;
-    const float f = __fmul_rn(P.fps, tau);
-    const float fl = floorf(f);
-    const float alpha = f - fl;
-    const bool ok = isfinite(fl) && ca >= 0 && ca < P.num_clips && cb >= 0 && cb < P.num_clips;
-    if (!ok) {
+    int k0, k1;
+    float alpha;
+    if (!sample_frame(P, chr, k0, k1, alpha)) {
         const float nan = __int_as_float(0x7fc00000);
         q = make_float4(nan, nan, nan, nan);
         tx = ty = tz = nan;
         return;
     }
-    float r = fmodf(fl, (float)K);
-    if (r < 0.0f) r += (float)K;
-    int k0 = (int)r;
-    if (k0 >= K) k0 = 0;
-    const int k1 = (k0 + 1 == K) ? 0 : k0 + 1;
     const int64_t ia0 = ((int64_t)ca * K + k0) * J + j, ia1 = ((int64_t)ca * K + k1) * J + j;
     const int64_t ib0 = ((int64_t)cb * K + k0) * J + j, ib1 = ((int64_t)cb * K + k1) * J + j;
     const float4 *kq = reinterpret_cast<const float4 *>(P.key_quat);
@@ -1326,6 +1339,151 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 }
 
 // ---------------------------------------------------------------------------
+// Reverse mode of the Simulation step.  One workgroup per character; each
+// thread takes joints, recomputes the two clips' key interpolations and the
+// blend, and applies the reverse rules
+//   q = v / |v|:            vbar = (qbar - q (q . qbar)) / |v|,
+//   y = (1 - x) a + x b:    abar = (1 - x) ybar, bbar = x ybar, xbar = ybar . (b - a),
+// with the arc signs and the key index held fixed.  Key gradients are
+// summed over all readers with float atomics; the time and weight
+// gradients are reduced over the character's joints in the workgroup.
+// ---------------------------------------------------------------------------
+constexpr int kSampleBwdThreads = 256;
+
+__global__ void __launch_bounds__(256) fill_zero_f32_kernel(int64_t n, float *dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = 0.0f;
+}
+
+__device__ __forceinline__ float4 unit_back(float4 q, float inv_norm, float4 qbar)
+{
+    const float d = q.x * qbar.x + q.y * qbar.y + q.z * qbar.z + q.w * qbar.w;
+    return make_float4((qbar.x - q.x * d) * inv_norm, (qbar.y - q.y * d) * inv_norm,
+                       (qbar.z - q.z * d) * inv_norm, (qbar.w - q.w * d) * inv_norm);
+}
+
+__device__ __forceinline__ void atomic_add4(float *dst, float s, float4 v)
+{
+    unsafeAtomicAdd(dst + 0, s * v.x);
+    unsafeAtomicAdd(dst + 1, s * v.y);
+    unsafeAtomicAdd(dst + 2, s * v.z);
+    unsafeAtomicAdd(dst + 3, s * v.w);
+}
+
+__device__ __forceinline__ float block_sum(float v, float *red)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int wave = threadIdx.x / kWave;
+    __syncthreads();  // red is reused by consecutive calls
+    if ((threadIdx.x & (kWave - 1)) == 0) red[wave] = v;
+    __syncthreads();
+    float t = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kSampleBwdThreads / kWave; ++k) t += red[k];
+    return t;
+}
+
+__global__ void __launch_bounds__(kSampleBwdThreads)
+sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
+{
+    __shared__ float red[kSampleBwdThreads / kWave];
+    const int K = P.num_keys, J = P.joints_per_clip;
+    const float4 *kq = reinterpret_cast<const float4 *>(P.key_quat);
+    const float *kt = P.key_trans;
+    for (int c = blockIdx.x; c < A.C; c += gridDim.x) {
+        const int64_t base = P.offsets[c];
+        const int n = (int)(P.offsets[c + 1] - base);
+        int k0, k1;
+        float alpha;
+        const bool ok = sample_frame(P, c, k0, k1, alpha);  // uniform in the workgroup
+        const float w = P.weight[c], uw = 1.0f - w, ua = 1.0f - alpha;
+        const int clip[2] = {P.clip_a[c], P.clip_b[c]};
+        float g_alpha = 0.0f, g_w = 0.0f;
+        for (int j = ok ? (int)threadIdx.x : n; j < n; j += kSampleBwdThreads) {
+            const int64_t gid = base + j;
+            const float4 gq = reinterpret_cast<const float4 *>(A.grad_quat)[gid];
+            const float gtx = A.grad_trans[3 * gid], gty = A.grad_trans[3 * gid + 1], gtz = A.grad_trans[3 * gid + 2];
+            int64_t r0[2], r1[2];
+            float4 qX[2], a[2], b[2];
+            float invX[2], sX[2], t0[2][3], t1[2][3];
+            for (int X = 0; X < 2; ++X) {
+                r0[X] = ((int64_t)clip[X] * K + k0) * J + j;
+                r1[X] = ((int64_t)clip[X] * K + k1) * J + j;
+                a[X] = kq[r0[X]];
+                b[X] = kq[r1[X]];
+                double d = (double)a[X].x * (double)b[X].x;
+                d = d + (double)a[X].y * (double)b[X].y;
+                d = d + (double)a[X].z * (double)b[X].z;
+                d = d + (double)a[X].w * (double)b[X].w;
+                sX[X] = d < 0.0 ? -1.0f : 1.0f;
+                const float v = alpha * sX[X];
+                const float4 r = make_float4(fmaf(ua, a[X].x, v * b[X].x), fmaf(ua, a[X].y, v * b[X].y),
+                                             fmaf(ua, a[X].z, v * b[X].z), fmaf(ua, a[X].w, v * b[X].w));
+                invX[X] = 1.0f / sqrtf(fmaf(r.x, r.x, fmaf(r.y, r.y, fmaf(r.z, r.z, r.w * r.w))));
+                qX[X] = make_float4(r.x * invX[X], r.y * invX[X], r.z * invX[X], r.w * invX[X]);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    t0[X][i] = kt[3 * r0[X] + i];
+                    t1[X][i] = kt[3 * r1[X] + i];
+                }
+            }
+            const float dab = qX[0].x * qX[1].x + qX[0].y * qX[1].y + qX[0].z * qX[1].z + qX[0].w * qX[1].w;
+            const float sb = dab < 0.0f ? -1.0f : 1.0f;
+            const float4 u = make_float4(fmaf(uw, qX[0].x, w * sb * qX[1].x), fmaf(uw, qX[0].y, w * sb * qX[1].y),
+                                         fmaf(uw, qX[0].z, w * sb * qX[1].z), fmaf(uw, qX[0].w, w * sb * qX[1].w));
+            const float inv_u = 1.0f / sqrtf(u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w);
+            const float4 q = make_float4(u.x * inv_u, u.y * inv_u, u.z * inv_u, u.w * inv_u);
+            const float4 ub = unit_back(q, inv_u, gq);
+            const float gt3[3] = {gtx, gty, gtz};
+            // blend weight: d/dw of (1-w) qA + w sb qB and of (1-w) tA + w tB
+            g_w += ub.x * (sb * qX[1].x - qX[0].x) + ub.y * (sb * qX[1].y - qX[0].y) +
+                   ub.z * (sb * qX[1].z - qX[0].z) + ub.w * (sb * qX[1].w - qX[0].w);
+            for (int X = 0; X < 2; ++X) {
+                const float sw = X == 0 ? uw : w * sb;  // the clip's factor in u
+                const float tw = X == 0 ? uw : w;       // and in t
+                const float4 qb = make_float4(sw * ub.x, sw * ub.y, sw * ub.z, sw * ub.w);
+                const float4 vb = unit_back(qX[X], invX[X], qb);
+                float tX[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    tX[i] = fmaf(ua, t0[X][i], alpha * t1[X][i]);
+                    g_alpha += tw * gt3[i] * (t1[X][i] - t0[X][i]);
+                }
+                if (X == 1) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const float tA = fmaf(ua, t0[0][i], alpha * t1[0][i]);
+                        g_w += gt3[i] * (tX[i] - tA);
+                    }
+                }
+                g_alpha += vb.x * (sX[X] * b[X].x - a[X].x) + vb.y * (sX[X] * b[X].y - a[X].y) +
+                           vb.z * (sX[X] * b[X].z - a[X].z) + vb.w * (sX[X] * b[X].w - a[X].w);
+                if (A.grad_key_quat) {
+                    atomic_add4(A.grad_key_quat + 4 * r0[X], ua, vb);
+                    atomic_add4(A.grad_key_quat + 4 * r1[X], alpha * sX[X], vb);
+                }
+                if (A.grad_key_trans) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        unsafeAtomicAdd(A.grad_key_trans + 3 * r0[X] + i, ua * tw * gt3[i]);
+                        unsafeAtomicAdd(A.grad_key_trans + 3 * r1[X] + i, alpha * tw * gt3[i]);
+                    }
+                }
+            }
+        }
+        const float sum_a = block_sum(g_alpha, red);
+        const float sum_w = block_sum(g_w, red);
+        if (threadIdx.x == 0) {
+            const float nan = __int_as_float(0x7fc00000);
+            if (A.grad_time) A.grad_time[c] = ok ? P.fps * sum_a : nan;
+            if (A.grad_weight) A.grad_weight[c] = ok ? sum_w : nan;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Vertex skinning: each mesh vertex moves by a weighted blend of the skin
 // matrices S_j of up to four joints of its character.
 //   linear blend: p' = (sum_i w_i S_{j_i}) [p, 1];
@@ -2003,6 +2161,18 @@ hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const Po
         return hipGetLastError();
     }
     return hipSuccess;
+}
+
+hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs &A, hipStream_t stream)
+{
+    const int64_t keys = (int64_t)pose.num_clips * pose.num_keys * pose.joints_per_clip;
+    const dim3 fgrid((unsigned)std::min<int64_t>(4096, (4 * keys + 255) / 256 + 1));
+    if (A.grad_key_quat) hipLaunchKernelGGL(fill_zero_f32_kernel, fgrid, dim3(256), 0, stream, 4 * keys, A.grad_key_quat);
+    if (A.grad_key_trans) hipLaunchKernelGGL(fill_zero_f32_kernel, fgrid, dim3(256), 0, stream, 3 * keys, A.grad_key_trans);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || A.C == 0) return err;
+    hipLaunchKernelGGL(sample_bwd_kernel, dim3((unsigned)A.C), dim3(kSampleBwdThreads), 0, stream, pose, A);
+    return hipGetLastError();
 }
 
 hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,

@@ -39,7 +39,7 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
-           "hs_mesh_destroy", "hs_skin_vertices")
+           "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward")
 
 
 class HSError(RuntimeError):
@@ -127,6 +127,8 @@ def load_library():
     lib.hs_mesh_destroy.argtypes = [vp]
     lib.hs_mesh_destroy.restype = None
     lib.hs_skin_vertices.argtypes = [vp, vp, i32, vp, vp]
+    lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
+                                            vp, vp, vp, vp, vp, vp, vp]
     lib.hs_plan_destroy.argtypes = [vp]
     lib.hs_plan_destroy.restype = None
     lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
@@ -313,6 +315,26 @@ def hs_pose_sample(plan, clips, clip_a, clip_b, time, weight, quat_out=None, tra
     _check(load_library().hs_pose_sample(plan.handle, ctypes.byref(clips.c), ctypes.byref(params),
                                          _ptr(q), _ptr(t), _stream(stream)))
     return q, t
+
+
+def hs_pose_sample_backward(plan, clips, clip_a, clip_b, time, weight, grad_quat, grad_trans,
+                            want_keys=True, stream=None):
+    """Reverse mode of the Simulation step -> (grad_key_quat [K,T,J,4],
+    grad_key_trans [K,T,J,3], grad_time [C], grad_weight [C]); the key
+    gradients are None when ``want_keys`` is false."""
+    N, C = plan.num_joints, plan.num_characters
+    _need(grad_quat, "grad_quat", (N, 4))
+    _need(grad_trans, "grad_trans", (N, 3))
+    dev = clips.key_quat.device
+    gkq = torch.empty_like(clips.key_quat) if want_keys else None
+    gkt = torch.empty_like(clips.key_trans) if want_keys else None
+    gtime = torch.empty((C,), device=dev, dtype=torch.float32)
+    gw = torch.empty((C,), device=dev, dtype=torch.float32)
+    params = _clip_params(plan, clip_a, clip_b, time, weight)
+    _check(load_library().hs_pose_sample_backward(plan.handle, ctypes.byref(clips.c), ctypes.byref(params),
+                                                  _ptr(grad_quat), _ptr(grad_trans), _ptr(gkq), _ptr(gkt),
+                                                  _ptr(gtime), _ptr(gw), _stream(stream)))
+    return gkq, gkt, gtime, gw
 
 
 def _trs_src(plan, quat, trans, scale):
