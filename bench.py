@@ -42,7 +42,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2505_06703_amd", "csrc", f)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 COPY_BYTES = 256 << 20
 WORKLOADS = ["deep_forward", "plain_scan", "heterogeneous", "fused_sample", "fused_sample_instanced",
-             "differentiable", "long_chains", "mesh_skinning"]
+             "differentiable", "long_chains", "mesh_skinning", "sample_gradients"]
 FUSED = ("fused_sample", "fused_sample_instanced")
 
 # algorithmic HBM bytes per joint that the dominant kernel of a step must
@@ -337,6 +337,9 @@ def main():
     if args.workload == "mesh_skinning":
         mesh_bench(args)
         return
+    if args.workload == "sample_gradients":
+        sampler_grad_bench(args)
+        return
     w = Workload(args.workload, autotune=not args.no_autotune, adjoint=args.adjoint)
     b, info = w.b, w.plan.info
     N, C = b.num_joints, b.num_characters
@@ -508,6 +511,75 @@ def mesh_bench(args):
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "vertex_skin_kernel",
                          "kernel_ms": kms, "algorithmic_bytes_per_launch": vbytes}}), flush=True)
+
+
+def sampler_grad_bench(args):
+    """Gradients through the Simulation step on the fused_sample batch: per
+    step the sampler, the scan, the scan's adjoint and the sampler's reverse
+    mode (keyframes, times, weights), with a fixed dLoss/dG (the effector
+    loss gradient at the start: the kernels' work does not depend on its
+    values).  Sets cycled so that one cycle touches at least SWEEP_BYTES."""
+    import torch
+    from paper_2505_06703_amd import hs
+    from paper_2505_06703_amd import workloads as wl
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    b = wl.fused_sample()
+    x = b.extra
+    N, C = b.num_joints, b.num_characters
+    plan = hs.Plan(b.offsets, b.parents, autotune=not args.no_autotune)
+    lib = hs.ClipLibrary(up(x["key_quat"]), up(x["key_trans"]), x["fps"])
+    ca, cb, tm, wt = up(x["clip_a"]), up(x["clip_b"]), up(x["time"]), up(x["weight"])
+    rng = np.random.default_rng(0)
+    W = np.zeros((N, 4, 4), np.float32)
+    tips = np.arange(C) * 256 + 255  # one effector per chain tip of the hair
+    W[tips, :3, 3] = rng.standard_normal((C, 3))
+    set_bytes = N * (16 + 12 + 64 + 64 + 16 + 12)
+    n_sets = int(min(MAX_SETS, max(2, -(-SWEEP_BYTES // set_bytes))))
+    sets = []
+    for _ in range(n_sets):
+        sets.append(dict(q=torch.empty((N, 4), device="cuda:0"), t=torch.empty((N, 3), device="cuda:0"),
+                         G=torch.empty((N, 4, 4), device="cuda:0"), gG=up(W),
+                         gq=torch.empty((N, 4), device="cuda:0"), gt=torch.empty((N, 3), device="cuda:0")))
+
+    def step(k, ev=None):
+        st = sets[k % n_sets]
+        hs.hs_pose_sample(plan, lib, ca, cb, tm, wt, quat_out=st["q"], trans_out=st["t"])
+        hs.hs_scan_forward(plan, st["q"], st["t"], None, global_out=st["G"])
+        hs.hs_scan_backward(plan, st["q"], st["t"], None, st["gG"], want_scale=False, grad_quat=st["gq"],
+                            grad_trans=st["gt"])
+        if ev is not None:
+            ev[0].record()
+        out = hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, st["gq"], st["gt"])
+        if ev is not None:
+            ev[1].record()
+        return out
+
+    for k in range(args.warmup):
+        step(k)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k, evs[k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    # algorithmic bytes of one reverse-mode launch: dLoss/dq and dLoss/dt
+    # read, the key gradients zeroed and written back once, per-character
+    # parameters read and gradients written
+    keys = x["key_quat"].nbytes + x["key_trans"].nbytes
+    sbytes = N * 28 + 2 * keys + C * 24
+    achieved = sbytes / (kms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "joint transforms/s through sampler, scan, adjoint and sampler reverse mode on 1 GPU",
+        "value": N * args.steps / elapsed, "unit": "joint transforms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "sample_gradients", "characters": C, "joints": N, "clips": int(x["key_quat"].shape[0]),
+                   "keys": int(x["key_quat"].shape[1]), "input_sets": n_sets},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sample_bwd_kernel",
+                     "kernel_ms": kms, "algorithmic_bytes_per_launch": sbytes}}), flush=True)
 
 
 def device_copy_gbs(torch, nbytes=1 << 30, reps=10):

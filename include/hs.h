@@ -243,7 +243,9 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
  * from their switching points); d alpha / d time = fps.  Any output may be
  * NULL (not computed).  A character with an invalid clip id or a
  * non-finite time gets NaN time and weight gradients and adds nothing to
- * the keys.  Asynchronous on stream; allocates nothing. */
+ * the keys.  Key gradients need joints_per_clip <= 10240
+ * (HS_ERR_UNSUPPORTED otherwise).  Asynchronous on stream; allocates
+ * nothing. */
 hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
                                   const float *grad_quat, const float *grad_trans, float *grad_key_quat,
                                   float *grad_key_trans, float *grad_time, float *grad_weight,

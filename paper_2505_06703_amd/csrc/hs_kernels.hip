@@ -1363,14 +1363,6 @@ __device__ __forceinline__ float4 unit_back(float4 q, float inv_norm, float4 qba
                        (qbar.z - q.z * d) * inv_norm, (qbar.w - q.w * d) * inv_norm);
 }
 
-__device__ __forceinline__ void atomic_add4(float *dst, float s, float4 v)
-{
-    unsafeAtomicAdd(dst + 0, s * v.x);
-    unsafeAtomicAdd(dst + 1, s * v.y);
-    unsafeAtomicAdd(dst + 2, s * v.z);
-    unsafeAtomicAdd(dst + 3, s * v.w);
-}
-
 __device__ __forceinline__ float block_sum(float v, float *red)
 {
 #pragma unroll
@@ -1460,15 +1452,28 @@ sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
                 }
                 g_alpha += vb.x * (sX[X] * b[X].x - a[X].x) + vb.y * (sX[X] * b[X].y - a[X].y) +
                            vb.z * (sX[X] * b[X].z - a[X].z) + vb.w * (sX[X] * b[X].w - a[X].w);
+                // component-major inside each (clip, key) block: the lanes of
+                // a wave (consecutive joints) add to consecutive floats; the
+                // blocks are transposed to joint-major afterwards
+                const int64_t b0 = r0[X] - j, b1 = r1[X] - j;  // first row of each block
                 if (A.grad_key_quat) {
-                    atomic_add4(A.grad_key_quat + 4 * r0[X], ua, vb);
-                    atomic_add4(A.grad_key_quat + 4 * r1[X], alpha * sX[X], vb);
+                    float *d0 = A.grad_key_quat + 4 * b0 + j, *d1 = A.grad_key_quat + 4 * b1 + j;
+                    const float s1 = alpha * sX[X];
+                    unsafeAtomicAdd(d0, ua * vb.x);
+                    unsafeAtomicAdd(d0 + J, ua * vb.y);
+                    unsafeAtomicAdd(d0 + 2 * J, ua * vb.z);
+                    unsafeAtomicAdd(d0 + 3 * J, ua * vb.w);
+                    unsafeAtomicAdd(d1, s1 * vb.x);
+                    unsafeAtomicAdd(d1 + J, s1 * vb.y);
+                    unsafeAtomicAdd(d1 + 2 * J, s1 * vb.z);
+                    unsafeAtomicAdd(d1 + 3 * J, s1 * vb.w);
                 }
                 if (A.grad_key_trans) {
+                    float *d0 = A.grad_key_trans + 3 * b0 + j, *d1 = A.grad_key_trans + 3 * b1 + j;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        unsafeAtomicAdd(A.grad_key_trans + 3 * r0[X] + i, ua * tw * gt3[i]);
-                        unsafeAtomicAdd(A.grad_key_trans + 3 * r1[X] + i, alpha * tw * gt3[i]);
+                        unsafeAtomicAdd(d0 + i * J, ua * tw * gt3[i]);
+                        unsafeAtomicAdd(d1 + i * J, alpha * tw * gt3[i]);
                     }
                 }
             }
@@ -1480,6 +1485,22 @@ sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
             if (A.grad_time) A.grad_time[c] = ok ? P.fps * sum_a : nan;
             if (A.grad_weight) A.grad_weight[c] = ok ? sum_w : nan;
         }
+    }
+}
+
+// In-place transpose of each (clip, key) block of J rows x W components
+// from component-major [W][J] to joint-major [J][W]; one workgroup per
+// block, staged through LDS (J * W floats).
+__global__ void __launch_bounds__(256) key_block_transpose_kernel(float *data, int64_t blocks, int J, int W)
+{
+    extern __shared__ float stage[];
+    const int n = J * W;
+    for (int64_t blk = blockIdx.x; blk < blocks; blk += gridDim.x) {
+        float *d = data + blk * n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) stage[i] = d[i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = stage[(i % W) * J + i / W];
+        __syncthreads();
     }
 }
 
@@ -2050,6 +2071,9 @@ hipError_t set_lds_limits()
 hipError_t prepare_kernels()
 {
     hipError_t err;
+    if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(key_block_transpose_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxClipJoints * 16)) != hipSuccess)
+        return err;
     if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_skin_kernel<0>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSkinJoints * 48)) != hipSuccess ||
         (err = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_skin_kernel<1>),
@@ -2172,6 +2196,16 @@ hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || A.C == 0) return err;
     hipLaunchKernelGGL(sample_bwd_kernel, dim3((unsigned)A.C), dim3(kSampleBwdThreads), 0, stream, pose, A);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    const int64_t blocks = (int64_t)pose.num_clips * pose.num_keys;
+    const dim3 tgrid((unsigned)std::min<int64_t>(blocks, 65536));
+    const int J = pose.joints_per_clip;
+    if (A.grad_key_quat)
+        hipLaunchKernelGGL(key_block_transpose_kernel, tgrid, dim3(256), (size_t)J * 4 * 4, stream,
+                           A.grad_key_quat, blocks, J, 4);
+    if (A.grad_key_trans)
+        hipLaunchKernelGGL(key_block_transpose_kernel, tgrid, dim3(256), (size_t)J * 3 * 4, stream,
+                           A.grad_key_trans, blocks, J, 3);
     return hipGetLastError();
 }
 
