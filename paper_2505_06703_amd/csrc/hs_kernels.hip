@@ -109,6 +109,19 @@ __device__ __forceinline__ void aff_load(const float4 *p, float m[12])
     m[8] = r2.x; m[9] = r2.y; m[10] = r2.z; m[11] = r2.w;
 }
 
+// Streaming stores of outputs that no kernel of the call reads again (and
+// streaming loads of inputs read once): the non-temporal hint keeps them
+// from displacing cached inputs and tables.
+typedef float native_float4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store_stream(float4 *p, float4 v)
+{
+    const native_float4 n = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(n, reinterpret_cast<native_float4 *>(p));
+}
+
+__device__ __forceinline__ void store_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ void aff_store(float4 *p, const float m[12])
 {
     p[0] = make_float4(m[0], m[1], m[2], m[3]);
@@ -219,14 +232,19 @@ __device__ __forceinline__ void load_local(const PoseArgs &P, int64_t gid, int c
         sample_pose(P, chr, lj, q, tx, ty, tz);
         aff_from_trs(q, tx, ty, tz, 1.0f, 1.0f, 1.0f, m);
     } else {
-        const float4 q = reinterpret_cast<const float4 *>(P.quat)[gid];
+        // each pose value is read once per call: streaming loads
+        const native_float4 qn = __builtin_nontemporal_load(reinterpret_cast<const native_float4 *>(P.quat) + gid);
+        const float4 q = make_float4(qn.x, qn.y, qn.z, qn.w);
         const float *t = P.trans + 3 * gid;
         float sx = 1.0f, sy = 1.0f, sz = 1.0f;
         if (P.scale) {
             const float *s = P.scale + 3 * gid;
-            sx = s[0]; sy = s[1]; sz = s[2];
+            sx = __builtin_nontemporal_load(s);
+            sy = __builtin_nontemporal_load(s + 1);
+            sz = __builtin_nontemporal_load(s + 2);
         }
-        aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, m);
+        aff_from_trs(q, __builtin_nontemporal_load(t), __builtin_nontemporal_load(t + 1),
+                     __builtin_nontemporal_load(t + 2), sx, sy, sz, m);
     }
 }
 
@@ -282,12 +300,12 @@ __device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t 
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const float g0 = m[4 * r], g1 = m[4 * r + 1], g2 = m[4 * r + 2], g3 = m[4 * r + 3];
-            S[r] = make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
-                               fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
-                               fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
-                               fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w))));
+            store_stream(S + r, make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
+                                            fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
+                                            fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
+                                            fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w)))));
         }
-        S[3] = b3;
+        store_stream(S + 3, b3);
     }
     if (out.ckpt && out.level[gid] % out.ckpt_k == 0)
         aff_store(reinterpret_cast<float4 *>(out.ckpt) + 3 * gid, m);
@@ -382,7 +400,7 @@ __device__ __forceinline__ void store_rows(const OutArgs &out, const float4 *Gs,
         if (jj < n) {
             float4 v = Gs[3 * jj + (r == 3 ? 0 : r)];
             if (r == 3) v = bottom;
-            dst[c] = v;
+            store_stream(dst + c, v);
         }
     }
 }
@@ -873,7 +891,7 @@ paper_alg_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
                 const int r = c & 3;
                 float4 v = As[3 * (c >> 2) + (r == 3 ? 0 : r)];
                 if (r == 3) v = bottom;
-                dst[c] = v;
+                store_stream(dst + c, v);
             }
         }
         if (live) write_skin_and_ckpt(out, gid, gid, m);
@@ -1648,9 +1666,9 @@ vertex_skin_kernel(VertexLaunch vl, const float4 *skin, float *out)
                 oz = pz + 2.0f * (rx * cy - ry * cx) + tz;
             }
             float *dst = out + 3 * (v0 + v);
-            dst[0] = ox;
-            dst[1] = oy;
-            dst[2] = oz;
+            store_stream(dst, ox);
+            store_stream(dst + 1, oy);
+            store_stream(dst + 2, oz);
         }
         __syncthreads();
     }
@@ -1750,8 +1768,10 @@ mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
     }
     if (out.global_out) {
         float4 *G = reinterpret_cast<float4 *>(out.global_out) + 4 * gid;
-        aff_store(G, m);
-        G[3] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        store_stream(G, make_float4(m[0], m[1], m[2], m[3]));
+        store_stream(G + 1, make_float4(m[4], m[5], m[6], m[7]));
+        store_stream(G + 2, make_float4(m[8], m[9], m[10], m[11]));
+        store_stream(G + 3, make_float4(0.0f, 0.0f, 0.0f, 1.0f));
     }
     write_skin_and_ckpt(out, gid, gid, m);
 }
