@@ -111,7 +111,10 @@ __device__ __forceinline__ void aff_load(const float4 *p, float m[12])
 
 // Streaming stores of outputs that no kernel of the call reads again (and
 // streaming loads of inputs read once): the non-temporal hint keeps them
-// from displacing cached inputs and tables.
+// from displacing cached inputs and tables.  Used only where a wave writes
+// whole contiguous lines (coalesced 16-byte rows): per-lane rows 64 bytes
+// apart measured slower with the hint (their partial lines are no longer
+// merged in the cache before going to HBM).
 typedef float native_float4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void store_stream(float4 *p, float4 v)
@@ -119,8 +122,6 @@ __device__ __forceinline__ void store_stream(float4 *p, float4 v)
     const native_float4 n = {v.x, v.y, v.z, v.w};
     __builtin_nontemporal_store(n, reinterpret_cast<native_float4 *>(p));
 }
-
-__device__ __forceinline__ void store_stream(float *p, float v) { __builtin_nontemporal_store(v, p); }
 
 __device__ __forceinline__ void aff_store(float4 *p, const float m[12])
 {
@@ -300,12 +301,12 @@ __device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t 
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const float g0 = m[4 * r], g1 = m[4 * r + 1], g2 = m[4 * r + 2], g3 = m[4 * r + 3];
-            store_stream(S + r, make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
-                                            fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
-                                            fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
-                                            fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w)))));
+            S[r] = make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
+                               fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
+                               fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
+                               fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w))));
         }
-        store_stream(S + 3, b3);
+        S[3] = b3;
     }
     if (out.ckpt && out.level[gid] % out.ckpt_k == 0)
         aff_store(reinterpret_cast<float4 *>(out.ckpt) + 3 * gid, m);
@@ -1666,9 +1667,9 @@ vertex_skin_kernel(VertexLaunch vl, const float4 *skin, float *out)
                 oz = pz + 2.0f * (rx * cy - ry * cx) + tz;
             }
             float *dst = out + 3 * (v0 + v);
-            store_stream(dst, ox);
-            store_stream(dst + 1, oy);
-            store_stream(dst + 2, oz);
+            dst[0] = ox;
+            dst[1] = oy;
+            dst[2] = oz;
         }
         __syncthreads();
     }
@@ -1768,10 +1769,8 @@ mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
     }
     if (out.global_out) {
         float4 *G = reinterpret_cast<float4 *>(out.global_out) + 4 * gid;
-        store_stream(G, make_float4(m[0], m[1], m[2], m[3]));
-        store_stream(G + 1, make_float4(m[4], m[5], m[6], m[7]));
-        store_stream(G + 2, make_float4(m[8], m[9], m[10], m[11]));
-        store_stream(G + 3, make_float4(0.0f, 0.0f, 0.0f, 1.0f));
+        aff_store(G, m);
+        G[3] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     }
     write_skin_and_ckpt(out, gid, gid, m);
 }
