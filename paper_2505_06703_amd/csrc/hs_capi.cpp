@@ -133,15 +133,15 @@ struct MPSet {
     MPBlock *d_blocks = nullptr;
     int32_t num_blocks = 0;
     int64_t nmp = 0;
-    float4 *P = nullptr;
     int32_t *d_janc = nullptr;
-    int32_t *d_anchors = nullptr;
+    int32_t *d_aself = nullptr;  // each joint's own anchor index, or -1
     int32_t num_anchors = 0;
     int32_t rounds = 0;        // anchor-level jump rounds
+    float4 *A1 = nullptr;      // anchors' phase-1 products
+    int32_t *E1 = nullptr;
     float4 *AP[2] = {nullptr, nullptr};
     int32_t *AE[2] = {nullptr, nullptr};
-    // adjoint: each joint's own anchor index, anchor adjoints, compact G
-    int32_t *d_aself = nullptr;
+    // adjoint: anchor adjoints, compact G
     float4 *S[2] = {nullptr, nullptr};
     float4 *G = nullptr;
 };
@@ -149,10 +149,10 @@ struct MPSet {
 void free_mpset(MPSet &m)
 {
     (void)hipFree(m.d_blocks);
-    (void)hipFree(m.P);
     (void)hipFree(m.d_janc);
-    (void)hipFree(m.d_anchors);
     (void)hipFree(m.d_aself);
+    (void)hipFree(m.A1);
+    (void)hipFree(m.E1);
     for (int i = 0; i < 2; ++i) {
         (void)hipFree(m.AP[i]);
         (void)hipFree(m.AE[i]);
@@ -458,22 +458,20 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
     std::vector<int32_t> janc, anchors;
     build_anchors(plan, pk, janc, anchors, m.rounds);
     m.num_anchors = (int32_t)anchors.size();
+    std::vector<int32_t> aself((size_t)pk.nmp, -1);
+    for (size_t i = 0; i < anchors.size(); ++i) aself[anchors[i]] = (int32_t)i;
     hipError_t err = upload(&m.d_blocks, pk.mpb);
     if (err == hipSuccess) err = upload(&m.d_janc, janc);
-    if (err == hipSuccess && !anchors.empty()) err = upload(&m.d_anchors, anchors);
+    if (err == hipSuccess) err = upload(&m.d_aself, aself);
     const size_t n = (size_t)pk.nmp, na = std::max<size_t>(1, anchors.size());
-    if (err == hipSuccess) err = hipMalloc(&m.P, n * 3 * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&m.A1, na * 3 * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&m.E1, na * sizeof(int32_t));
     for (int i = 0; i < 2 && err == hipSuccess; ++i) {
         err = hipMalloc(&m.AP[i], na * 3 * sizeof(float4));
         if (err == hipSuccess) err = hipMalloc(&m.AE[i], na * sizeof(int32_t));
         if (adjoint && err == hipSuccess) err = hipMalloc(&m.S[i], na * 3 * sizeof(float4));
     }
     if (adjoint && err == hipSuccess) err = hipMalloc(&m.G, n * 3 * sizeof(float4));
-    if (adjoint && err == hipSuccess) {
-        std::vector<int32_t> aself((size_t)pk.nmp, -1);
-        for (size_t i = 0; i < anchors.size(); ++i) aself[anchors[i]] = (int32_t)i;
-        err = upload(&m.d_aself, aself);
-    }
     if (err != hipSuccess) {
         free_mpset(m);
         return fail_hip(err, "hs_plan_create (multipass workspace)");
@@ -614,9 +612,9 @@ hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
     ml.num_blocks = m.num_blocks;
     ml.nmp = m.nmp;
     ml.parent = p->d_parent;
-    ml.P = m.P;
     ml.janc = m.d_janc;
-    ml.anchors = m.d_anchors;
+    ml.A1 = m.A1;
+    ml.E1 = m.E1;
     ml.num_anchors = m.num_anchors;
     ml.rounds = m.rounds;
     ml.aself = m.d_aself;

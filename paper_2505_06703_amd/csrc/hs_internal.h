@@ -101,17 +101,17 @@ struct MPLaunch {
     int32_t num_blocks;
     int64_t nmp;              // joints on the multipass path (compact count)
     const int32_t *parent;    // [N] global parent id or -1
-    float4 *P;                // [Nmp*3] in-block partial products (phase 1)
     // anchors: the joints that are some joint's nearest out-of-block
     // ancestor; the cross-block phase jumps over these only
     const int32_t *janc;      // [Nmp] anchor index of the joint's out-of-block ancestor, or -1
-    const int32_t *anchors;   // [num_anchors] compact id of each anchor
+    const int32_t *aself;     // [Nmp] the joint's own anchor index, or -1
     int32_t num_anchors;
     int32_t rounds;           // anchor-level jump rounds
+    float4 *A1;               // [num_anchors*3] anchors' in-block products (phase 1)
+    int32_t *E1;              // [num_anchors] anchor index of each anchor's own anchor, or -1
     float4 *AP[2];            // [num_anchors*3] ping-pong anchor products
     int32_t *AE[2];           // [num_anchors] ping-pong anchor pointers
     // adjoint workspace (NULL when the plan has none)
-    const int32_t *aself;     // [Nmp] the joint's own anchor index, or -1
     float4 *S[2];             // [num_anchors*3] ping-pong anchor adjoints
     float4 *G;                // [Nmp*3] global transforms
 };

@@ -1706,21 +1706,14 @@ mp_local_kernel(MPLaunch ml, PoseArgs pose)
         aff_identity(m);
     }
     wave_inblock_scan(m, a, e, lane);
-    if (valid) aff_store(ml.P + 3 * cid, m);
-}
-
-// Anchor i starts from its own phase-1 product and the anchor index of its
-// nearest out-of-block ancestor.
-__global__ void __launch_bounds__(256)
-mp_anchor_gather_kernel(MPLaunch ml)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ml.num_anchors) return;
-    const int64_t c = ml.anchors[i];
-    float m[12];
-    aff_load(ml.P + 3 * c, m);
-    aff_store(ml.AP[0] + 3 * i, m);
-    ml.AE[0][i] = ml.janc[c];
+    // only the anchors' in-block products leave the kernel (the output pass
+    // recomputes the others from the poses): anchor i starts the rounds from
+    // its phase-1 product and the anchor index of its own anchor
+    const int ai = valid ? ml.aself[cid] : -1;
+    if (ai >= 0) {
+        aff_store(ml.A1 + 3 * ai, m);
+        ml.E1[ai] = ml.janc[cid];
+    }
 }
 
 // One pointer-jumping round over the anchors (Eq. 2 applied to the anchor
@@ -1743,36 +1736,65 @@ mp_anchor_round_kernel(int32_t na, const float4 *Pin, const int32_t *Ein, float4
     Eout[i] = e;
 }
 
-// Final pass: G_j = G_anchor P_j, one composition per joint.  Writes the
-// outputs, or (Gc non-NULL) the compact global transforms the adjoint reads.
+// Final pass: the in-block scan again from the poses (cheaper than storing
+// and re-reading every partial), then G_j = G_anchor P_j, one composition
+// per joint.  Writes the outputs -- G through the wave's LDS slice as
+// coalesced 16-byte rows -- or (Gc non-NULL) the compact global transforms
+// the adjoint reads.  LDS: [kMPWaves][64][3] float4.
+template <bool SAMPLE>
 __global__ void __launch_bounds__(kMPWaves * kWave)
-mp_out_kernel(MPLaunch ml, const float4 *AP, OutArgs out, float4 *Gc)
+mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 *Gc)
 {
+    __shared__ float4 stage[kMPWaves * kWave * 3];
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
-    if (w >= ml.num_blocks) return;
+    const int wv = threadIdx.x / kWave;
+    const int w = blockIdx.x * kMPWaves + wv;
+    if (w >= ml.num_blocks) return;  // whole waves leave together; no workgroup barriers here
     const MPBlock bd = ml.blocks[w];
-    if (lane >= bd.count) return;
+    const bool valid = lane < bd.count;
     const int64_t gid = bd.gbegin + lane;
     const int64_t cid = bd.cbegin + lane;
     float m[12];
-    aff_load(ml.P + 3 * cid, m);
-    const int a = ml.janc[cid];
-    if (a >= 0) {
+    int a = -1, e = -1;
+    if (valid) {
+        const int p = ml.parent[gid];
+        if (p >= 0) {
+            const int64_t off = (int64_t)p - bd.gbegin;
+            if (off >= 0) a = (int)off; else e = (int)(off + bd.cbegin);
+        }
+        int lj = 0;
+        if constexpr (SAMPLE) lj = (int)(gid - pose.offsets[bd.chr]);
+        load_local<SAMPLE>(pose, gid, bd.chr, lj, m);
+    } else {
+        aff_identity(m);
+    }
+    wave_inblock_scan(m, a, e, lane);
+    const int an = valid ? ml.janc[cid] : -1;
+    if (an >= 0) {
         float g[12];
-        aff_load(AP + 3 * a, g);
+        aff_load(AP + 3 * an, g);
         aff_mul_left(g, m);
     }
     if (Gc) {
-        aff_store(Gc + 3 * cid, m);
+        if (valid) aff_store(Gc + 3 * cid, m);
         return;
     }
     if (out.global_out) {
-        float4 *G = reinterpret_cast<float4 *>(out.global_out) + 4 * gid;
-        aff_store(G, m);
-        G[3] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        float4 *st = stage + wv * kWave * 3;
+        aff_store(st + 3 * lane, m);
+        wave_sync();
+        const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * bd.gbegin;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = lane + kWave * k;
+            if ((c >> 2) < bd.count) {
+                const int r = c & 3;
+                store_stream(dst + c, r == 3 ? bottom : st[3 * (c >> 2) + r]);
+            }
+        }
     }
-    write_skin_and_ckpt(out, gid, gid, m);
+    if (valid) write_skin_and_ckpt(out, gid, gid, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -2165,19 +2187,24 @@ hipError_t run_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs
         hipLaunchKernelGGL(mp_local_kernel<false>, grid, blk, 0, stream, ml, pose);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    int cur = 0;
+    // rounds over the anchors, from the phase-1 products (A1, E1) into the
+    // ping-pong buffers; with no rounds the phase-1 products are final
+    const float4 *pin = ml.A1;
+    const int32_t *ein = ml.E1;
     if (ml.num_anchors > 0) {
         const dim3 agrid((unsigned)((ml.num_anchors + 255) / 256));
-        hipLaunchKernelGGL(mp_anchor_gather_kernel, agrid, dim3(256), 0, stream, ml);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
         for (int r = 0; r < ml.rounds; ++r) {
-            hipLaunchKernelGGL(mp_anchor_round_kernel, agrid, dim3(256), 0, stream, ml.num_anchors, ml.AP[cur],
-                               ml.AE[cur], ml.AP[cur ^ 1], ml.AE[cur ^ 1]);
+            hipLaunchKernelGGL(mp_anchor_round_kernel, agrid, dim3(256), 0, stream, ml.num_anchors, pin, ein,
+                               ml.AP[r & 1], ml.AE[r & 1]);
             if ((err = hipGetLastError()) != hipSuccess) return err;
-            cur ^= 1;
+            pin = ml.AP[r & 1];
+            ein = ml.AE[r & 1];
         }
     }
-    hipLaunchKernelGGL(mp_out_kernel, grid, blk, 0, stream, ml, ml.AP[cur], out, Gc);
+    if (pose.kind == 1)
+        hipLaunchKernelGGL(mp_out_kernel<true>, grid, blk, 0, stream, ml, pose, pin, out, Gc);
+    else
+        hipLaunchKernelGGL(mp_out_kernel<false>, grid, blk, 0, stream, ml, pose, pin, out, Gc);
     return hipGetLastError();
 }
 
@@ -2341,14 +2368,18 @@ hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, c
     hipLaunchKernelGGL(mpr_block_kernel<false>, grid, blk, lds, stream, ml, pose, bwd, ml.S[0]);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (na > 0) {
-        hipLaunchKernelGGL(mp_anchor_gather_kernel, agrid, dim3(256), 0, stream, ml);
-        if ((err = hipGetLastError()) != hipSuccess) return err;
+        // the anchors' phase-1 products and pointers (A1, E1, left by the
+        // forward pass above) start the reverse rounds
+        const float4 *min = ml.A1;
+        const int32_t *ein = ml.E1;
         for (int r = 0; r < ml.rounds; ++r) {
             hipLaunchKernelGGL(mpr_copy_kernel, cgrid, dim3(256), 0, stream, 3 * (int64_t)na, ml.S[cur], ml.S[cur ^ 1]);
             if ((err = hipGetLastError()) != hipSuccess) return err;
-            hipLaunchKernelGGL(mpr_anchor_round_kernel, agrid, dim3(256), 0, stream, na, ml.S[cur], ml.AP[cur],
-                               ml.AE[cur], ml.S[cur ^ 1], ml.AP[cur ^ 1], ml.AE[cur ^ 1]);
+            hipLaunchKernelGGL(mpr_anchor_round_kernel, agrid, dim3(256), 0, stream, na, ml.S[cur], min, ein,
+                               ml.S[cur ^ 1], ml.AP[r & 1], ml.AE[r & 1]);
             if ((err = hipGetLastError()) != hipSuccess) return err;
+            min = ml.AP[r & 1];
+            ein = ml.AE[r & 1];
             cur ^= 1;
         }
     }
