@@ -196,3 +196,30 @@ def test_instanced_plan_errors():
     rc = lib.hs_plan_create_instanced(hs.default_context().handle, ctypes.byref(sk), 2, ids.ctypes.data,
                                       ctypes.byref(opts), ctypes.byref(h))
     assert rc == hs.HS_ERR_INVALID_ARG and not h.value
+
+
+def test_fused_sample_instanced_full_size_sampled():
+    """The benchmark configuration (10 000 instances of one 256-joint
+    skeleton, clip sampling, skin only) in its autotuned launch; 32 seeded
+    characters checked against the oracle."""
+    b = wl.fused_sample_instanced()
+    x = b.extra
+    soff, spar, sid = x["skel_offsets"], x["skel_parents"], x["skeleton_id"]
+    inv_s = skeleton_inverse_binds(soff, spar, x["skel_rest"])
+    lib = hs.ClipLibrary(dev(x["key_quat"]), dev(x["key_trans"]), x["fps"])
+    plan = hs.Plan.instanced(soff, spar, sid, autotune=True)
+    _, S = hs.hs_scan_forward(plan, clips=lib, clip_a=dev(x["clip_a"]), clip_b=dev(x["clip_b"]),
+                              time=dev(x["time"]), weight=dev(x["weight"]), want_global=False,
+                              inv_bind=dev(inv_s))
+    torch.cuda.synchronize()
+    chars = np.sort(np.random.default_rng(25).choice(b.num_characters, 32, replace=False))
+    J = spar.size
+    sub = lambda a: a[chars]
+    sub_off = np.arange(chars.size + 1) * J
+    q, tr = oracle.pose_sample(sub_off, x["key_quat"], x["key_trans"], sub(x["clip_a"]), sub(x["clip_b"]),
+                               sub(x["time"]), sub(x["weight"]), x["fps"])
+    par = np.tile(spar, chars.size)
+    Gr = oracle.forward(sub_off, par, q, tr, None)
+    lam = oracle.path_length(sub_off, par, Gr, tr)
+    S_sub = np.concatenate([S[c * J:(c + 1) * J].cpu().numpy() for c in chars])
+    check_skin(S_sub, Gr, np.tile(inv_s, (chars.size, 1, 1)), lam, "full-size instanced fused skin")

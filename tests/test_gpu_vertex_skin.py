@@ -145,3 +145,32 @@ def test_mesh_errors():
     with pytest.raises(hs.HSError) as ei:  # too many joints to stage
         hs.Mesh(plan2, [0, V], [0], pos, joints, weights)
     assert ei.value.status == hs.HS_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("method", [hs.HS_SKIN_LINEAR, hs.HS_SKIN_DUAL_QUAT])
+def test_mesh_skinning_full_size_sampled(method):
+    """The benchmark configuration (10 000 instances, 10.0 M vertices) in
+    the launch the benchmark times; 24 seeded characters' vertices checked
+    against the oracle on the same skin matrices."""
+    b = wl.mesh_skinning()
+    x = b.extra
+    import oracle
+    inv_s = np.linalg.inv(oracle.forward(x["skel_offsets"], x["skel_parents"], *x["skel_rest"])).astype(np.float32)
+    plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"])
+    lib = hs.ClipLibrary(dev(x["key_quat"]), dev(x["key_trans"]), x["fps"])
+    _, S = hs.hs_scan_forward(plan, clips=lib, clip_a=dev(x["clip_a"]), clip_b=dev(x["clip_b"]),
+                              time=dev(x["time"]), weight=dev(x["weight"]), want_global=False,
+                              inv_bind=dev(inv_s))
+    mesh = hs.Mesh(plan, x["vertex_offsets"], x["mesh_first"], x["mesh_positions"], x["mesh_joints"],
+                   x["mesh_weights"])
+    out = hs.hs_skin_vertices(mesh, S, method)
+    torch.cuda.synchronize()
+    chars = np.sort(np.random.default_rng(34).choice(b.num_characters, 24, replace=False))
+    J = x["skel_parents"].size
+    V = x["mesh_positions"].shape[0]
+    S_sub = np.concatenate([S[c * J:(c + 1) * J].cpu().numpy() for c in chars])
+    out_sub = np.concatenate([out[c * V:(c + 1) * V].cpu().numpy() for c in chars])
+    sub_off = np.arange(chars.size + 1) * J
+    sub_voff = np.arange(chars.size + 1, dtype=np.int64) * V
+    check(out_sub, sub_off, S_sub, sub_voff, np.zeros(chars.size, np.int32), x["mesh_positions"],
+          x["mesh_joints"], x["mesh_weights"], method, f"full size method {method}")
