@@ -384,6 +384,20 @@ void hs_mesh_destroy(hs_mesh *mesh);
 hs_status hs_skin_vertices(const hs_mesh *mesh, const float *skin, int32_t method, float *out,
                            hipStream_t stream);
 
+/* The whole pipeline in one pass per tile: local poses (TRS arrays or
+ * clips, as hs_scan_forward), the scan, the skin matrices S_j = G_j B_j^-1
+ * (inv_bind as in hs_scan_forward: per joint, or per skeleton joint for an
+ * instanced plan) and vertex skinning of the mesh, which must have been
+ * made for this plan.  S stays on chip; skin_out (nullable, [N,4,4]) also
+ * writes it.  vertices_out [V,3] as hs_skin_vertices, bitwise the same
+ * result as hs_scan_forward followed by hs_skin_vertices.  Every character
+ * must be on a tile and tiles may hold at most 2048 joints
+ * (HS_ERR_UNSUPPORTED otherwise: use the two calls).  Errors as
+ * hs_scan_forward and hs_skin_vertices.  Asynchronous; allocates nothing. */
+hs_status hs_scan_skin_vertices(const hs_plan *plan, const hs_pose_src *src, const float *inv_bind,
+                                const hs_mesh *mesh, int32_t method, float *vertices_out, float *skin_out,
+                                hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1327,6 +1327,7 @@ hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *
 } // extern "C"
 
 struct hs_mesh {
+    const hs_plan *plan = nullptr;  // the plan it was made for
     int device = 0;
     int64_t N = 0, V = 0, rows = 0;
     hs::VertexLaunch vl{};
@@ -1407,6 +1408,7 @@ hs_status hs_mesh_create(const hs_plan *plan, const hs_mesh_batch *mb, hs_mesh *
                         (long long)c, it->second.first, it->second.second, (long long)nj);
     }
     hs_mesh *m = new hs_mesh();
+    m->plan = plan;
     m->device = plan->ctx->device;
     m->N = plan->N;
     m->V = voff[C];
@@ -1447,6 +1449,46 @@ hs_status hs_skin_vertices(const hs_mesh *mesh, const float *skin, int32_t metho
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_skin_vertices: cannot select device");
     hipError_t err = hs::launch_vertex_skin(mesh->vl, method, skin, out, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_skin_vertices");
+    return HS_OK;
+}
+
+hs_status hs_scan_skin_vertices(const hs_plan *plan, const hs_pose_src *src, const float *inv_bind,
+                                const hs_mesh *mesh, int32_t method, float *vertices_out, float *skin_out,
+                                hipStream_t stream)
+{
+    if (!plan || !mesh) return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: plan and mesh must be non-NULL");
+    if (mesh->plan != plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: the mesh was made for another plan");
+    if (method != HS_SKIN_LINEAR && method != HS_SKIN_DUAL_QUAT)
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: unknown method %d", method);
+    if (plan->mp.nmp > 0)
+        return fail(HS_ERR_UNSUPPORTED, "hs_scan_skin_vertices: every character must be on a tile (no multipass)");
+    if (plan->shape.tile_cap > hs::kMaxVertexTileJoints)
+        return fail(HS_ERR_UNSUPPORTED, "hs_scan_skin_vertices: tiles of at most %d joints (plan has %d)",
+                    hs::kMaxVertexTileJoints, plan->shape.tile_cap);
+    hs::PoseArgs pa;
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, src, pa, ins, true);
+    if (rc != HS_OK) return rc;
+    const size_t N = (size_t)plan->N, V = (size_t)mesh->V;
+    if (N == 0) return HS_OK;
+    if (!inv_bind || (V > 0 && !vertices_out))
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: inv_bind and vertices_out must be non-NULL");
+    if (!aligned(inv_bind, 16) || !aligned(skin_out, 16) || !aligned(vertices_out, 4))
+        return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: inv_bind and skin_out must be 16-byte aligned");
+    ins.push_back({inv_bind, (plan->inst ? (size_t)plan->skel_joints : N) * 64, "inv_bind"});
+    std::vector<Range> outs = {{vertices_out, V * 12, "vertices_out"}, {skin_out, skin_out ? N * 64 : 0, "skin_out"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_skin_vertices: cannot select device");
+    hs::OutArgs oa{};
+    oa.inv_bind = inv_bind;
+    oa.skin_out = skin_out;
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
+        err = hs::launch_forward_vertices(tile_launch(plan, k), pa, oa, mesh->vl, method, vertices_out, stream);
+    if (err == hipSuccess)
+        err = hs::launch_forward_vertices(tile_launch(plan), pa, oa, mesh->vl, method, vertices_out, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_skin_vertices");
     return HS_OK;
 }
 

@@ -178,6 +178,12 @@ struct VertexLaunch {
 // method 0: linear blend; 1: dual quaternions
 hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *skin, float *out,
                               hipStream_t stream);
+// Scan + skin + vertex skinning per tile (tiles of at most
+// kMaxVertexTileJoints joints; out.inv_bind required, out.skin_out optional).
+constexpr int kMaxVertexTileJoints = 2048;
+size_t forward_vertex_lds_bytes(int tile_cap);
+hipError_t launch_forward_vertices(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                   const VertexLaunch &vl, int method, float *vout, hipStream_t stream);
 
 // Tiles of the paper's Algorithms 1-4 (one joint per thread).
 constexpr int kPaperAlgTileJoints = 1024;

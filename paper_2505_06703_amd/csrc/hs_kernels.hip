@@ -1587,6 +1587,50 @@ __device__ __forceinline__ void rigid_to_dual_quat(float4 r0, float4 r1, float4 
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
+__device__ __forceinline__ void fma4(float4 &acc, float s, float4 v);
+
+// Dual quaternion blend of four influences (real part at X[STRIDE j], dual
+// part at X[STRIDE j + 1]) applied to p: signs against influence 0, the
+// normalised blend, then p + 2 r x (r x p + w p) + 2 (w_r d - w_d r + r x d).
+template <int STRIDE>
+__device__ __forceinline__ void dq_blend_apply(const float4 *X, const int jk[4], const float wk[4], float px, float py,
+                                               float pz, float &ox, float &oy, float &oz)
+{
+    const float4 q0 = X[STRIDE * jk[0]];
+    float4 br = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bd = br;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float4 q = X[STRIDE * jk[k]], d = X[STRIDE * jk[k] + 1];
+        const float s = dot4(q, q0) < 0.0f ? -wk[k] : wk[k];
+        fma4(br, s, q);
+        fma4(bd, s, d);
+    }
+    const float inv = 1.0f / sqrtf(dot4(br, br));
+    const float rx = br.x * inv, ry = br.y * inv, rz = br.z * inv, rw = br.w * inv;
+    const float dx = bd.x * inv, dy = bd.y * inv, dz = bd.z * inv, dw = bd.w * inv;
+    const float cx = ry * pz - rz * py + rw * px;
+    const float cy = rz * px - rx * pz + rw * py;
+    const float cz = rx * py - ry * px + rw * pz;
+    const float tx = 2.0f * (rw * dx - dw * rx + ry * dz - rz * dy);
+    const float ty = 2.0f * (rw * dy - dw * ry + rz * dx - rx * dz);
+    const float tz = 2.0f * (rw * dz - dw * rz + rx * dy - ry * dx);
+    ox = px + 2.0f * (ry * cz - rz * cy) + tx;
+    oy = py + 2.0f * (rz * cx - rx * cz) + ty;
+    oz = pz + 2.0f * (rx * cy - ry * cx) + tz;
+}
+
+__device__ __forceinline__ void dq_apply2(const float4 *X, const int jk[4], const float wk[4], float px, float py,
+                                          float pz, float &ox, float &oy, float &oz)
+{
+    dq_blend_apply<2>(X, jk, wk, px, py, pz, ox, oy, oz);
+}
+
+__device__ __forceinline__ void dq_apply(const float4 *X, const int jk[4], const float wk[4], float px, float py,
+                                         float pz, float &ox, float &oy, float &oz)
+{
+    dq_blend_apply<3>(X, jk, wk, px, py, pz, ox, oy, oz);
+}
+
 __device__ __forceinline__ void fma4(float4 &acc, float s, float4 v)
 {
     acc.x = fmaf(s, v.x, acc.x);
@@ -1642,31 +1686,130 @@ vertex_skin_kernel(VertexLaunch vl, const float4 *skin, float *out)
                 oy = fmaf(a1.x, px, fmaf(a1.y, py, fmaf(a1.z, pz, a1.w)));
                 oz = fmaf(a2.x, px, fmaf(a2.y, py, fmaf(a2.z, pz, a2.w)));
             } else {
-                const float4 q0 = lds[2 * jk[0]];
-                float4 br = make_float4(0.0f, 0.0f, 0.0f, 0.0f), bd = br;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float4 q = lds[2 * jk[k]], d = lds[2 * jk[k] + 1];
-                    const float s = dot4(q, q0) < 0.0f ? -wk[k] : wk[k];
-                    fma4(br, s, q);
-                    fma4(bd, s, d);
-                }
-                const float inv = 1.0f / sqrtf(dot4(br, br));
-                const float rx = br.x * inv, ry = br.y * inv, rz = br.z * inv, rw = br.w * inv;
-                const float dx = bd.x * inv, dy = bd.y * inv, dz = bd.z * inv, dw = bd.w * inv;
-                // p + 2 r x (r x p + w p)
-                const float cx = ry * pz - rz * py + rw * px;
-                const float cy = rz * px - rx * pz + rw * py;
-                const float cz = rx * py - ry * px + rw * pz;
-                // translation 2 (w_r d - w_d r + r x d)
-                const float tx = 2.0f * (rw * dx - dw * rx + ry * dz - rz * dy);
-                const float ty = 2.0f * (rw * dy - dw * ry + rz * dx - rx * dz);
-                const float tz = 2.0f * (rw * dz - dw * rz + rx * dy - ry * dx);
-                ox = px + 2.0f * (ry * cz - rz * cy) + tx;
-                oy = py + 2.0f * (rz * cx - rx * cz) + ty;
-                oz = pz + 2.0f * (rx * cy - ry * cx) + tz;
+                // real parts staged at lds[2 j], dual parts at lds[2 j + 1]
+                dq_apply2(lds, jk, wk, px, py, pz, ox, oy, oz);
             }
             float *dst = out + 3 * (v0 + v);
+            dst[0] = ox;
+            dst[1] = oy;
+            dst[2] = oz;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scan, skin matrices and vertex skinning in one pass per tile: the tile's
+// blocks run the scan as in fwd_tile_kernel (G in LDS, no outputs); then
+// each thread turns its joints' G_j into S_j = G_j B_j^-1 in place (or into
+// S_j's unit dual quaternion), optionally writing S; then the threads take
+// the vertices of the tile's characters and blend the staged transforms as
+// vertex_skin_kernel does.  S never has to leave the chip.
+// LDS: that of fwd_tile_kernel with the character map, plus the tile's
+// vertex starts [cap + 1].
+// ---------------------------------------------------------------------------
+template <int WAVES, bool SAMPLE, bool INST, int METHOD>
+__global__ void __launch_bounds__(WAVES * kWave)
+fwd_vertex_kernel(TileLaunch tl, PoseArgs pose, OutArgs out, VertexLaunch vl, float *vout)
+{
+    extern __shared__ float4 lds[];
+    constexpr int T = WAVES * kWave;
+    const int cap = tl.tile_cap;
+    const int nbk = cap >> 6;
+    FwdShared sh;
+    sh.G = lds;
+    sh.part = lds + 3 * cap;
+    sh.flags = reinterpret_cast<int *>(sh.part + 3 * nbk);
+    sh.pflag = sh.flags + nbk;
+    sh.panc = sh.pflag + nbk;
+    sh.cstart = sh.panc + nbk;
+    int *cstart = sh.cstart;
+    int *vstart = cstart + cap + 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const OutArgs none{};
+
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        const int n = td.count;
+        const int nblk = (n + kWave - 1) / kWave;
+        for (int i = threadIdx.x; i < nblk; i += T) {
+            sh.flags[i] = 0;
+            sh.pflag[i] = 0;
+        }
+        const int64_t vbase = vl.voff[td.first_char];
+        for (int i = threadIdx.x; i <= td.num_chars; i += T) {
+            cstart[i] = (int)(pose.offsets[td.first_char + i] - td.begin);
+            vstart[i] = (int)(vl.voff[td.first_char + i] - vbase);
+        }
+        __syncthreads();
+        for (int b = wave; b < nblk; b += WAVES) fwd_block<SAMPLE, INST>(tl, pose, none, td, n, b, sh, lane);
+        __syncthreads();
+        // G -> S (or its dual quaternion), in place
+        for (int jl = threadIdx.x; jl < n; jl += T) {
+            int64_t bidx = td.begin + jl;
+            if constexpr (INST) {
+                const int c = tile_char_of(cstart, td.num_chars, jl);
+                bidx = tl.char_skel[td.first_char + c] + (jl - cstart[c]);
+            }
+            float m[12];
+            aff_load(sh.G + 3 * jl, m);
+            const float4 *B = reinterpret_cast<const float4 *>(out.inv_bind) + 4 * bidx;
+            const float4 b0 = B[0], b1 = B[1], b2 = B[2], b3 = B[3];
+            float4 S[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const float g0 = m[4 * r], g1 = m[4 * r + 1], g2 = m[4 * r + 2], g3 = m[4 * r + 3];
+                S[r] = make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
+                                   fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
+                                   fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
+                                   fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w))));
+            }
+            if (out.skin_out) {
+                float4 *Sd = reinterpret_cast<float4 *>(out.skin_out) + 4 * (td.begin + jl);
+                Sd[0] = S[0];
+                Sd[1] = S[1];
+                Sd[2] = S[2];
+                Sd[3] = b3;
+            }
+            if constexpr (METHOD == 0) {
+                sh.G[3 * jl] = S[0];
+                sh.G[3 * jl + 1] = S[1];
+                sh.G[3 * jl + 2] = S[2];
+            } else {
+                float4 qr, qd;
+                rigid_to_dual_quat(S[0], S[1], S[2], qr, qd);
+                sh.G[3 * jl] = qr;
+                sh.G[3 * jl + 1] = qd;
+            }
+        }
+        __syncthreads();
+        const int nv = vstart[td.num_chars];
+        for (int v = threadIdx.x; v < nv; v += T) {
+            const int c = tile_char_of(vstart, td.num_chars, v);
+            const int64_t mrow = vl.mfirst[td.first_char + c] + (v - vstart[c]);
+            const float4 *X = sh.G + 3 * cstart[c];
+            const float px = vl.pos[3 * mrow], py = vl.pos[3 * mrow + 1], pz = vl.pos[3 * mrow + 2];
+            const int4 ji = reinterpret_cast<const int4 *>(vl.joints)[mrow];
+            const float4 wt = reinterpret_cast<const float4 *>(vl.weights)[mrow];
+            const int jk[4] = {ji.x, ji.y, ji.z, ji.w};
+            const float wk[4] = {wt.x, wt.y, wt.z, wt.w};
+            float ox, oy, oz;
+            if constexpr (METHOD == 0) {
+                float4 a0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), a1 = a0, a2 = a0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    fma4(a0, wk[k], X[3 * jk[k]]);
+                    fma4(a1, wk[k], X[3 * jk[k] + 1]);
+                    fma4(a2, wk[k], X[3 * jk[k] + 2]);
+                }
+                ox = fmaf(a0.x, px, fmaf(a0.y, py, fmaf(a0.z, pz, a0.w)));
+                oy = fmaf(a1.x, px, fmaf(a1.y, py, fmaf(a1.z, pz, a1.w)));
+                oz = fmaf(a2.x, px, fmaf(a2.y, py, fmaf(a2.z, pz, a2.w)));
+            } else {
+                dq_apply(X, jk, wk, px, py, pz, ox, oy, oz);
+            }
+            float *dst = vout + 3 * (vbase + v);
             dst[0] = ox;
             dst[1] = oy;
             dst[2] = oz;
@@ -2070,6 +2213,27 @@ hipError_t launch_fwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const 
     }
 }
 
+template <int WAVES, bool SAMPLE, bool INST>
+hipError_t set_vertex_lds_limits()
+{
+    const int bytes = (int)forward_vertex_lds_bytes(kMaxVertexTileJoints);
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(fwd_vertex_kernel<WAVES, SAMPLE, INST, 0>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (err != hipSuccess) return err;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fwd_vertex_kernel<WAVES, SAMPLE, INST, 1>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+template <int WAVES>
+hipError_t set_vertex_lds_limits_all()
+{
+    hipError_t err;
+    if ((err = set_vertex_lds_limits<WAVES, false, false>()) != hipSuccess) return err;
+    if ((err = set_vertex_lds_limits<WAVES, false, true>()) != hipSuccess) return err;
+    if ((err = set_vertex_lds_limits<WAVES, true, false>()) != hipSuccess) return err;
+    return set_vertex_lds_limits<WAVES, true, true>();
+}
+
 template <int WAVES>
 hipError_t set_lds_limits()
 {
@@ -2114,6 +2278,9 @@ hipError_t prepare_kernels()
     hipError_t err;
     if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(key_block_transpose_kernel),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxClipJoints * 16)) != hipSuccess)
+        return err;
+    if ((err = set_vertex_lds_limits_all<4>()) != hipSuccess || (err = set_vertex_lds_limits_all<8>()) != hipSuccess ||
+        (err = set_vertex_lds_limits_all<16>()) != hipSuccess)
         return err;
     if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_skin_kernel<0>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSkinJoints * 48)) != hipSuccess ||
@@ -2264,6 +2431,54 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
                        reinterpret_cast<const float4 *>(inv_bind),
                        reinterpret_cast<float4 *>(skin_out));
     return hipGetLastError();
+}
+
+size_t forward_vertex_lds_bytes(int tile_cap)
+{
+    return forward_tile_lds_bytes(tile_cap, true) + (size_t)(tile_cap + 1) * 4;
+}
+
+template <int WAVES, bool SAMPLE, bool INST>
+hipError_t launch_fwd_vertex_t(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                               const VertexLaunch &vl, int method, float *vout, hipStream_t stream)
+{
+    const size_t lds = forward_vertex_lds_bytes(tl.tile_cap);
+    const dim3 grid(tl.grid), blk(WAVES * kWave);
+    if (method == 0)
+        hipLaunchKernelGGL((fwd_vertex_kernel<WAVES, SAMPLE, INST, 0>), grid, blk, lds, stream, tl, pose, out, vl, vout);
+    else
+        hipLaunchKernelGGL((fwd_vertex_kernel<WAVES, SAMPLE, INST, 1>), grid, blk, lds, stream, tl, pose, out, vl, vout);
+    return hipGetLastError();
+}
+
+template <bool SAMPLE, bool INST>
+hipError_t launch_fwd_vertex_w(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                               const VertexLaunch &vl, int method, float *vout, hipStream_t stream)
+{
+    // 4 to 16 waves: at least one block per wave in the scan when the tile
+    // allows, and enough threads for the vertex phase
+    int waves = 4;
+    while (waves < 16 && waves * 2 * kWave <= tl.tile_cap) waves *= 2;
+    switch (waves) {
+    case 4: return launch_fwd_vertex_t<4, SAMPLE, INST>(tl, pose, out, vl, method, vout, stream);
+    case 8: return launch_fwd_vertex_t<8, SAMPLE, INST>(tl, pose, out, vl, method, vout, stream);
+    default: return launch_fwd_vertex_t<16, SAMPLE, INST>(tl, pose, out, vl, method, vout, stream);
+    }
+}
+
+hipError_t launch_forward_vertices(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                   const VertexLaunch &vl, int method, float *vout, hipStream_t stream)
+{
+    if (tl.num_tiles == 0) return hipSuccess;
+    if (tl.tile_cap > kMaxVertexTileJoints || !pose.offsets || !out.inv_bind || (method != 0 && method != 1))
+        return hipErrorInvalidValue;
+    const bool sample = pose.kind == 1, inst = tl.skel_parent != nullptr;
+    if (inst && !tl.char_skel) return hipErrorInvalidValue;
+    if (sample)
+        return inst ? launch_fwd_vertex_w<true, true>(tl, pose, out, vl, method, vout, stream)
+                    : launch_fwd_vertex_w<true, false>(tl, pose, out, vl, method, vout, stream);
+    return inst ? launch_fwd_vertex_w<false, true>(tl, pose, out, vl, method, vout, stream)
+                : launch_fwd_vertex_w<false, false>(tl, pose, out, vl, method, vout, stream);
 }
 
 hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *skin, float *out,

@@ -39,7 +39,7 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
-           "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward")
+           "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices")
 
 
 class HSError(RuntimeError):
@@ -127,6 +127,7 @@ def load_library():
     lib.hs_mesh_destroy.argtypes = [vp]
     lib.hs_mesh_destroy.restype = None
     lib.hs_skin_vertices.argtypes = [vp, vp, i32, vp, vp]
+    lib.hs_scan_skin_vertices.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp]
     lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
                                             vp, vp, vp, vp, vp, vp, vp]
     lib.hs_plan_destroy.argtypes = [vp]
@@ -437,6 +438,30 @@ def hs_skin_vertices(mesh, skin, method=HS_SKIN_LINEAR, out=None, stream=None):
     _need(out, "out", (mesh.num_vertices, 3))
     _check(load_library().hs_skin_vertices(mesh.handle, _ptr(skin), int(method), _ptr(out), _stream(stream)))
     return out
+
+
+def hs_scan_skin_vertices(plan, mesh, inv_bind, quat=None, trans=None, scale=None, *, clips=None, clip_a=None,
+                          clip_b=None, time=None, weight=None, method=HS_SKIN_LINEAR, vertices_out=None,
+                          skin_out=None, stream=None):
+    """Poses, scan, skin matrices and vertex skinning in one pass per tile
+    (``hs_scan_skin_vertices``) -> vertices [V,3] (and ``skin_out`` if given)."""
+    N = plan.num_joints
+    if clips is not None:
+        params = _clip_params(plan, clip_a, clip_b, time, weight)
+        src = hs_pose_src(HS_POSE_CLIPS, None, None, None, ctypes.pointer(clips.c), ctypes.pointer(params))
+        dev = clips.key_quat.device
+    else:
+        src = _trs_src(plan, quat, trans, scale)
+        dev = quat.device
+    _need(inv_bind, "inv_bind", (plan.bind_rows, 4, 4))
+    if vertices_out is None:
+        vertices_out = torch.empty((mesh.num_vertices, 3), device=dev, dtype=torch.float32)
+    _need(vertices_out, "vertices_out", (mesh.num_vertices, 3))
+    if skin_out is not None:
+        _need(skin_out, "skin_out", (N, 4, 4))
+    _check(load_library().hs_scan_skin_vertices(plan.handle, ctypes.byref(src), _ptr(inv_bind), mesh.handle,
+                                                int(method), _ptr(vertices_out), _ptr(skin_out), _stream(stream)))
+    return vertices_out
 
 
 def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0, want_scale=True,

@@ -174,3 +174,83 @@ def test_mesh_skinning_full_size_sampled(method):
     sub_voff = np.arange(chars.size + 1, dtype=np.int64) * V
     check(out_sub, sub_off, S_sub, sub_voff, np.zeros(chars.size, np.int32), x["mesh_positions"],
           x["mesh_joints"], x["mesh_weights"], method, f"full size method {method}")
+
+
+@pytest.mark.parametrize("method", [hs.HS_SKIN_LINEAR, hs.HS_SKIN_DUAL_QUAT])
+@pytest.mark.parametrize("instanced", [False, True])
+def test_one_pass_pipeline_equals_two_calls(method, instanced):
+    """hs_scan_skin_vertices (clip sampling, scan, skin and vertex skinning
+    per tile, S kept on chip) gives bitwise the output of hs_scan_forward
+    followed by hs_skin_vertices, and its optional skin rows equal the
+    forward's."""
+    b = wl.mesh_skinning(num_characters=300)
+    x = b.extra
+    import oracle
+    inv_s = np.linalg.inv(oracle.forward(x["skel_offsets"], x["skel_parents"], *x["skel_rest"])).astype(np.float32)
+    if instanced:
+        plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"])
+        inv = dev(inv_s)
+    else:
+        plan = hs.Plan(b.offsets, b.parents)
+        inv = dev(np.tile(inv_s, (b.num_characters, 1, 1)))
+    lib = hs.ClipLibrary(dev(x["key_quat"]), dev(x["key_trans"]), x["fps"])
+    cp = dict(clip_a=dev(x["clip_a"]), clip_b=dev(x["clip_b"]), time=dev(x["time"]), weight=dev(x["weight"]))
+    mesh = hs.Mesh(plan, x["vertex_offsets"], x["mesh_first"], x["mesh_positions"], x["mesh_joints"],
+                   x["mesh_weights"])
+    _, S = hs.hs_scan_forward(plan, clips=lib, **cp, want_global=False, inv_bind=inv)
+    two = hs.hs_skin_vertices(mesh, S, method)
+    S1 = torch.empty_like(S)
+    one = hs.hs_scan_skin_vertices(plan, mesh, inv, clips=lib, **cp, method=method, skin_out=S1)
+    torch.cuda.synchronize()
+    assert torch.equal(one, two)
+    assert torch.equal(S1, S)
+    check(one.cpu().numpy(), b.offsets, S.cpu().numpy(), x["vertex_offsets"], x["mesh_first"], x["mesh_positions"],
+          x["mesh_joints"], x["mesh_weights"], method, f"one pass method {method}")
+
+
+def test_one_pass_pipeline_on_several_size_classes_and_trs_poses():
+    """Characters of 64 to 1600 joints (three tile size classes under
+    2048-joint tiles), TRS poses, meshes on some characters only."""
+    rng = np.random.default_rng(35)
+    sizes = [64, 300, 1100, 1600, 2000]
+    tm = []
+    for n in sizes:
+        p = np.empty(n, np.int32)
+        p[0] = -1
+        for j in range(1, n):
+            p[j] = j - 1 if rng.uniform() < 0.7 else rng.integers(0, j)
+        tm.append(p)
+    sid = rng.integers(0, len(sizes), 40)
+    par = np.concatenate([tm[k] for k in sid]).astype(np.int32)
+    off = np.concatenate([[0], np.cumsum([sizes[k] for k in sid])]).astype(np.int64)
+    N = int(off[-1])
+    q, t, s = wl.random_pose(rng, N)
+    import oracle
+    rq, rt, rs = wl.random_pose(rng, N)
+    inv = np.linalg.inv(oracle.forward(off, par, rq, rt, rs)).astype(np.float32)
+    meshes = [wl.skin_mesh(rng, p, 1000) for p in tm]
+    mrow = np.concatenate([[0], np.cumsum([m[0].shape[0] for m in meshes])])
+    pos = np.concatenate([m[0] for m in meshes])
+    joints = np.concatenate([m[1] for m in meshes])
+    weights = np.concatenate([m[2] for m in meshes])
+    counts = np.array([meshes[k][0].shape[0] for k in sid]) * (rng.uniform(size=sid.size) < 0.8)
+    voff = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    mfirst = mrow[sid].astype(np.int32)
+    plan = hs.Plan(off, par, tile_joints=2048)
+    assert plan.info["multipass_joints"] == 0
+    mesh = hs.Mesh(plan, voff, mfirst, pos, joints, weights)
+    _, S = hs.hs_scan_forward(plan, dev(q), dev(t), dev(s), inv_bind=dev(inv), want_global=False)
+    for method in (hs.HS_SKIN_LINEAR, hs.HS_SKIN_DUAL_QUAT):
+        two = hs.hs_skin_vertices(mesh, S, method)
+        one = hs.hs_scan_skin_vertices(plan, mesh, dev(inv), dev(q), dev(t), dev(s), method=method)
+        torch.cuda.synchronize()
+        assert torch.equal(one, two), method
+    # a plan with multipass characters is refused
+    big = hs.Plan(off, par, tile_joints=1024)
+    mesh_big = hs.Mesh(big, voff, mfirst, pos, joints, weights)
+    with pytest.raises(hs.HSError) as ei:
+        hs.hs_scan_skin_vertices(big, mesh_big, dev(inv), dev(q), dev(t), dev(s))
+    assert ei.value.status == hs.HS_ERR_UNSUPPORTED
+    with pytest.raises(hs.HSError) as ei:  # a mesh made for another plan
+        hs.hs_scan_skin_vertices(plan, mesh_big, dev(inv), dev(q), dev(t), dev(s))
+    assert ei.value.status == hs.HS_ERR_INVALID_ARG
