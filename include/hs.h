@@ -237,15 +237,13 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
  * 16-byte aligned) and dLoss/dtrans [N,3] of the sampled local poses,
  * writes dLoss/dkey_quat [num_clips, num_keys, joints_per_clip, 4] and
  * dLoss/dkey_trans [..., 3] (each the sum over every character and joint
- * that reads the key; zeroed first, then accumulated with float atomics,
- * so not bitwise reproducible), dLoss/dtime [C] and dLoss/dweight [C].  The
+ * that reads the key, summed per key row in a fixed order), dLoss/dtime [C]
+ * and dLoss/dweight [C].  The
  * arc signs and the key index floor(f) are held fixed (the derivative away
  * from their switching points); d alpha / d time = fps.  Any output may be
  * NULL (not computed).  A character with an invalid clip id or a
  * non-finite time gets NaN time and weight gradients and adds nothing to
- * the keys.  Key gradients need joints_per_clip <= 10240
- * (HS_ERR_UNSUPPORTED otherwise).  Asynchronous on stream; allocates
- * nothing. */
+ * the keys.  Asynchronous on stream; allocates nothing. */
 hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
                                   const float *grad_quat, const float *grad_trans, float *grad_key_quat,
                                   float *grad_key_trans, float *grad_time, float *grad_weight,

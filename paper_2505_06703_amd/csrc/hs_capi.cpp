@@ -1291,9 +1291,6 @@ hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, c
         return fail(HS_ERR_INVALID_ARG, "hs_pose_sample_backward: grad_quat must be 16-byte aligned, the rest 4");
     ins.push_back({grad_quat, N * 16, "grad_quat"});
     ins.push_back({grad_trans, N * 12, "grad_trans"});
-    if ((grad_key_quat || grad_key_trans) && lib->joints_per_clip > hs::kMaxClipJoints)
-        return fail(HS_ERR_UNSUPPORTED, "hs_pose_sample_backward: key gradients of clips over %d joints",
-                    hs::kMaxClipJoints);
     const size_t keys = (size_t)lib->num_clips * lib->num_keys * lib->joints_per_clip;
     std::vector<Range> outs = {{grad_key_quat, grad_key_quat ? keys * 16 : 0, "grad_key_quat"},
                                {grad_key_trans, grad_key_trans ? keys * 12 : 0, "grad_key_trans"},

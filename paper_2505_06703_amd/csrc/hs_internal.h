@@ -145,10 +145,7 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 // needs (once per process and device, before any launch or capture).
 hipError_t prepare_kernels();
 
-// Reverse mode of the sampler (see hs_pose_sample_backward).  Its key
-// gradients are transposed per (clip, key) block through LDS: clips of at
-// most kMaxClipJoints joints.
-constexpr int kMaxClipJoints = 10240;
+// Reverse mode of the sampler (see hs_pose_sample_backward).
 struct SampleBwdArgs {
     const float *grad_quat;    // [N,4]
     const float *grad_trans;   // [N,3]

@@ -1369,17 +1369,19 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 // ---------------------------------------------------------------------------
 constexpr int kSampleBwdThreads = 256;
 
-__global__ void __launch_bounds__(256) fill_zero_f32_kernel(int64_t n, float *dst)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = 0.0f;
-}
-
 __device__ __forceinline__ float4 unit_back(float4 q, float inv_norm, float4 qbar)
 {
     const float d = q.x * qbar.x + q.y * qbar.y + q.z * qbar.z + q.w * qbar.w;
     return make_float4((qbar.x - q.x * d) * inv_norm, (qbar.y - q.y * d) * inv_norm,
                        (qbar.z - q.z * d) * inv_norm, (qbar.w - q.w * d) * inv_norm);
+}
+
+__device__ __forceinline__ void fma4(float4 &acc, float s, float4 v)
+{
+    acc.x = fmaf(s, v.x, acc.x);
+    acc.y = fmaf(s, v.y, acc.y);
+    acc.z = fmaf(s, v.z, acc.z);
+    acc.w = fmaf(s, v.w, acc.w);
 }
 
 __device__ __forceinline__ float block_sum(float v, float *red)
@@ -1396,106 +1398,99 @@ __device__ __forceinline__ float block_sum(float v, float *red)
     return t;
 }
 
+// Reverse mode of joint j of character c (its frame valid): the adjoints of
+// the two clips' unnormalised key blends (vb[X]) and the factors of dLoss/dt
+// in their translation lerps (tw[X]), the arc signs (sX[X]), and the joint's
+// terms of dLoss/dalpha and dLoss/dw.
+struct JointRev {
+    float4 vb[2];
+    float tw[2], sX[2];
+    float gt[3];
+    float g_alpha, g_w;
+};
+
+__device__ __forceinline__ void joint_reverse(const PoseArgs &P, const SampleBwdArgs &A, int64_t gid, int j,
+                                              const int clip[2], int k0, int k1, float alpha, float w, JointRev &o)
+{
+    const int K = P.num_keys, J = P.joints_per_clip;
+    const float4 *kq = reinterpret_cast<const float4 *>(P.key_quat);
+    const float *kt = P.key_trans;
+    const float uw = 1.0f - w, ua = 1.0f - alpha;
+    const float4 gq = reinterpret_cast<const float4 *>(A.grad_quat)[gid];
+    o.gt[0] = A.grad_trans[3 * gid];
+    o.gt[1] = A.grad_trans[3 * gid + 1];
+    o.gt[2] = A.grad_trans[3 * gid + 2];
+    float4 qX[2], a[2], b[2];
+    float invX[2], t0[2][3], t1[2][3];
+#pragma unroll
+    for (int X = 0; X < 2; ++X) {
+        const int64_t r0 = ((int64_t)clip[X] * K + k0) * J + j, r1 = ((int64_t)clip[X] * K + k1) * J + j;
+        a[X] = kq[r0];
+        b[X] = kq[r1];
+        double d = (double)a[X].x * (double)b[X].x;
+        d = d + (double)a[X].y * (double)b[X].y;
+        d = d + (double)a[X].z * (double)b[X].z;
+        d = d + (double)a[X].w * (double)b[X].w;
+        o.sX[X] = d < 0.0 ? -1.0f : 1.0f;
+        const float v = alpha * o.sX[X];
+        const float4 r = make_float4(fmaf(ua, a[X].x, v * b[X].x), fmaf(ua, a[X].y, v * b[X].y),
+                                     fmaf(ua, a[X].z, v * b[X].z), fmaf(ua, a[X].w, v * b[X].w));
+        invX[X] = 1.0f / sqrtf(fmaf(r.x, r.x, fmaf(r.y, r.y, fmaf(r.z, r.z, r.w * r.w))));
+        qX[X] = make_float4(r.x * invX[X], r.y * invX[X], r.z * invX[X], r.w * invX[X]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            t0[X][i] = kt[3 * r0 + i];
+            t1[X][i] = kt[3 * r1 + i];
+        }
+    }
+    const float dab = qX[0].x * qX[1].x + qX[0].y * qX[1].y + qX[0].z * qX[1].z + qX[0].w * qX[1].w;
+    const float sb = dab < 0.0f ? -1.0f : 1.0f;
+    const float4 u = make_float4(fmaf(uw, qX[0].x, w * sb * qX[1].x), fmaf(uw, qX[0].y, w * sb * qX[1].y),
+                                 fmaf(uw, qX[0].z, w * sb * qX[1].z), fmaf(uw, qX[0].w, w * sb * qX[1].w));
+    const float inv_u = 1.0f / sqrtf(u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w);
+    const float4 q = make_float4(u.x * inv_u, u.y * inv_u, u.z * inv_u, u.w * inv_u);
+    const float4 ub = unit_back(q, inv_u, gq);
+    // blend weight: d/dw of (1-w) qA + w sb qB and of (1-w) tA + w tB
+    o.g_w = ub.x * (sb * qX[1].x - qX[0].x) + ub.y * (sb * qX[1].y - qX[0].y) + ub.z * (sb * qX[1].z - qX[0].z) +
+            ub.w * (sb * qX[1].w - qX[0].w);
+    o.g_alpha = 0.0f;
+#pragma unroll
+    for (int X = 0; X < 2; ++X) {
+        const float sw = X == 0 ? uw : w * sb;  // the clip's factor in u
+        o.tw[X] = X == 0 ? uw : w;              // and in t
+        o.vb[X] = unit_back(qX[X], invX[X], make_float4(sw * ub.x, sw * ub.y, sw * ub.z, sw * ub.w));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) o.g_alpha += o.tw[X] * o.gt[i] * (t1[X][i] - t0[X][i]);
+        o.g_alpha += o.vb[X].x * (o.sX[X] * b[X].x - a[X].x) + o.vb[X].y * (o.sX[X] * b[X].y - a[X].y) +
+                     o.vb[X].z * (o.sX[X] * b[X].z - a[X].z) + o.vb[X].w * (o.sX[X] * b[X].w - a[X].w);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float tA = fmaf(ua, t0[0][i], alpha * t1[0][i]), tB = fmaf(ua, t0[1][i], alpha * t1[1][i]);
+        o.g_w += o.gt[i] * (tB - tA);
+    }
+}
+
+// Time and weight gradients: one workgroup per character, the joints'
+// terms reduced in the workgroup.
 __global__ void __launch_bounds__(kSampleBwdThreads)
 sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
 {
     __shared__ float red[kSampleBwdThreads / kWave];
-    const int K = P.num_keys, J = P.joints_per_clip;
-    const float4 *kq = reinterpret_cast<const float4 *>(P.key_quat);
-    const float *kt = P.key_trans;
     for (int c = blockIdx.x; c < A.C; c += gridDim.x) {
         const int64_t base = P.offsets[c];
         const int n = (int)(P.offsets[c + 1] - base);
         int k0, k1;
         float alpha;
         const bool ok = sample_frame(P, c, k0, k1, alpha);  // uniform in the workgroup
-        const float w = P.weight[c], uw = 1.0f - w, ua = 1.0f - alpha;
         const int clip[2] = {P.clip_a[c], P.clip_b[c]};
+        const float w = P.weight[c];
         float g_alpha = 0.0f, g_w = 0.0f;
         for (int j = ok ? (int)threadIdx.x : n; j < n; j += kSampleBwdThreads) {
-            const int64_t gid = base + j;
-            const float4 gq = reinterpret_cast<const float4 *>(A.grad_quat)[gid];
-            const float gtx = A.grad_trans[3 * gid], gty = A.grad_trans[3 * gid + 1], gtz = A.grad_trans[3 * gid + 2];
-            int64_t r0[2], r1[2];
-            float4 qX[2], a[2], b[2];
-            float invX[2], sX[2], t0[2][3], t1[2][3];
-            for (int X = 0; X < 2; ++X) {
-                r0[X] = ((int64_t)clip[X] * K + k0) * J + j;
-                r1[X] = ((int64_t)clip[X] * K + k1) * J + j;
-                a[X] = kq[r0[X]];
-                b[X] = kq[r1[X]];
-                double d = (double)a[X].x * (double)b[X].x;
-                d = d + (double)a[X].y * (double)b[X].y;
-                d = d + (double)a[X].z * (double)b[X].z;
-                d = d + (double)a[X].w * (double)b[X].w;
-                sX[X] = d < 0.0 ? -1.0f : 1.0f;
-                const float v = alpha * sX[X];
-                const float4 r = make_float4(fmaf(ua, a[X].x, v * b[X].x), fmaf(ua, a[X].y, v * b[X].y),
-                                             fmaf(ua, a[X].z, v * b[X].z), fmaf(ua, a[X].w, v * b[X].w));
-                invX[X] = 1.0f / sqrtf(fmaf(r.x, r.x, fmaf(r.y, r.y, fmaf(r.z, r.z, r.w * r.w))));
-                qX[X] = make_float4(r.x * invX[X], r.y * invX[X], r.z * invX[X], r.w * invX[X]);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    t0[X][i] = kt[3 * r0[X] + i];
-                    t1[X][i] = kt[3 * r1[X] + i];
-                }
-            }
-            const float dab = qX[0].x * qX[1].x + qX[0].y * qX[1].y + qX[0].z * qX[1].z + qX[0].w * qX[1].w;
-            const float sb = dab < 0.0f ? -1.0f : 1.0f;
-            const float4 u = make_float4(fmaf(uw, qX[0].x, w * sb * qX[1].x), fmaf(uw, qX[0].y, w * sb * qX[1].y),
-                                         fmaf(uw, qX[0].z, w * sb * qX[1].z), fmaf(uw, qX[0].w, w * sb * qX[1].w));
-            const float inv_u = 1.0f / sqrtf(u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w);
-            const float4 q = make_float4(u.x * inv_u, u.y * inv_u, u.z * inv_u, u.w * inv_u);
-            const float4 ub = unit_back(q, inv_u, gq);
-            const float gt3[3] = {gtx, gty, gtz};
-            // blend weight: d/dw of (1-w) qA + w sb qB and of (1-w) tA + w tB
-            g_w += ub.x * (sb * qX[1].x - qX[0].x) + ub.y * (sb * qX[1].y - qX[0].y) +
-                   ub.z * (sb * qX[1].z - qX[0].z) + ub.w * (sb * qX[1].w - qX[0].w);
-            for (int X = 0; X < 2; ++X) {
-                const float sw = X == 0 ? uw : w * sb;  // the clip's factor in u
-                const float tw = X == 0 ? uw : w;       // and in t
-                const float4 qb = make_float4(sw * ub.x, sw * ub.y, sw * ub.z, sw * ub.w);
-                const float4 vb = unit_back(qX[X], invX[X], qb);
-                float tX[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    tX[i] = fmaf(ua, t0[X][i], alpha * t1[X][i]);
-                    g_alpha += tw * gt3[i] * (t1[X][i] - t0[X][i]);
-                }
-                if (X == 1) {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const float tA = fmaf(ua, t0[0][i], alpha * t1[0][i]);
-                        g_w += gt3[i] * (tX[i] - tA);
-                    }
-                }
-                g_alpha += vb.x * (sX[X] * b[X].x - a[X].x) + vb.y * (sX[X] * b[X].y - a[X].y) +
-                           vb.z * (sX[X] * b[X].z - a[X].z) + vb.w * (sX[X] * b[X].w - a[X].w);
-                // component-major inside each (clip, key) block: the lanes of
-                // a wave (consecutive joints) add to consecutive floats; the
-                // blocks are transposed to joint-major afterwards
-                const int64_t b0 = r0[X] - j, b1 = r1[X] - j;  // first row of each block
-                if (A.grad_key_quat) {
-                    float *d0 = A.grad_key_quat + 4 * b0 + j, *d1 = A.grad_key_quat + 4 * b1 + j;
-                    const float s1 = alpha * sX[X];
-                    unsafeAtomicAdd(d0, ua * vb.x);
-                    unsafeAtomicAdd(d0 + J, ua * vb.y);
-                    unsafeAtomicAdd(d0 + 2 * J, ua * vb.z);
-                    unsafeAtomicAdd(d0 + 3 * J, ua * vb.w);
-                    unsafeAtomicAdd(d1, s1 * vb.x);
-                    unsafeAtomicAdd(d1 + J, s1 * vb.y);
-                    unsafeAtomicAdd(d1 + 2 * J, s1 * vb.z);
-                    unsafeAtomicAdd(d1 + 3 * J, s1 * vb.w);
-                }
-                if (A.grad_key_trans) {
-                    float *d0 = A.grad_key_trans + 3 * b0 + j, *d1 = A.grad_key_trans + 3 * b1 + j;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        unsafeAtomicAdd(d0 + i * J, ua * tw * gt3[i]);
-                        unsafeAtomicAdd(d1 + i * J, alpha * tw * gt3[i]);
-                    }
-                }
-            }
+            JointRev o;
+            joint_reverse(P, A, base + j, j, clip, k0, k1, alpha, w, o);
+            g_alpha += o.g_alpha;
+            g_w += o.g_w;
         }
         const float sum_a = block_sum(g_alpha, red);
         const float sum_w = block_sum(g_w, red);
@@ -1507,19 +1502,82 @@ sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
     }
 }
 
-// In-place transpose of each (clip, key) block of J rows x W components
-// from component-major [W][J] to joint-major [J][W]; one workgroup per
-// block, staged through LDS (J * W floats).
-__global__ void __launch_bounds__(256) key_block_transpose_kernel(float *data, int64_t blocks, int J, int W)
+// Keyframe gradients by gathering instead of scattering: one workgroup per
+// (clip, key) block.  It scans the characters' clip parameters in chunks
+// for the readers of its block (a character reads it as clip A or B, at key
+// k0 or k1 of its frame), lists them in LDS, and each thread sums, for its
+// joints, every reader's contribution -- (1 - alpha) or alpha s times the
+// adjoint of the key blend, (1 - alpha) or alpha times the weighted dLoss/dt
+// -- then writes its key rows once.  No atomics on the gradients and no
+// zero fill: blocks nobody reads get zeros.
+constexpr int kKeyChars = kSampleBwdThreads;  // characters scanned per pass (one per thread)
+constexpr int kKeyReaders = 4 * kKeyChars;    // at most four entries per character
+
+__global__ void __launch_bounds__(kSampleBwdThreads)
+sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
 {
-    extern __shared__ float stage[];
-    const int n = J * W;
-    for (int64_t blk = blockIdx.x; blk < blocks; blk += gridDim.x) {
-        float *d = data + blk * n;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) stage[i] = d[i];
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = stage[(i % W) * J + i / W];
-        __syncthreads();
+    __shared__ int list[kKeyReaders];
+    __shared__ int count;
+    const int K = P.num_keys, J = P.joints_per_clip;
+    const int64_t nblocks = (int64_t)P.num_clips * K;
+    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const int clip = (int)(blk / K), key = (int)(blk % K);
+        for (int j0 = 0; j0 < J; j0 += kSampleBwdThreads) {
+            const int j = j0 + (int)threadIdx.x;
+            float4 gkq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float gkt[3] = {0.0f, 0.0f, 0.0f};
+            for (int c0 = 0; c0 < A.C; c0 += kKeyChars) {
+                if (threadIdx.x == 0) count = 0;
+                __syncthreads();
+                const int cend = min(A.C, c0 + kKeyChars);
+                for (int c = c0 + (int)threadIdx.x; c < cend; c += kSampleBwdThreads) {
+                    const int ca = P.clip_a[c], cb = P.clip_b[c];
+                    if (ca != clip && cb != clip) continue;  // most characters: two loads
+                    int k0, k1;
+                    float alpha;
+                    if (sample_frame(P, c, k0, k1, alpha)) {
+                        const int cl[2] = {ca, cb};
+                        for (int X = 0; X < 2; ++X) {
+                            if (cl[X] != clip) continue;
+                            if (k0 == key) list[atomicAdd(&count, 1)] = 4 * c + 2 * X;
+                            if (k1 == key) list[atomicAdd(&count, 1)] = 4 * c + 2 * X + 1;
+                        }
+                    }
+                }
+                __syncthreads();
+                const int nr = count;
+                for (int e = 0; e < nr; ++e) {
+                    const int ent = list[e];
+                    const int rc = ent >> 2, X = (ent >> 1) & 1, role = ent & 1;
+                    const int64_t base = P.offsets[rc];
+                    if (j >= (int)(P.offsets[rc + 1] - base)) continue;  // the character has no joint j
+                    int k0, k1;
+                    float alpha;
+                    sample_frame(P, rc, k0, k1, alpha);
+                    const int cl[2] = {P.clip_a[rc], P.clip_b[rc]};
+                    JointRev o;
+                    joint_reverse(P, A, base + j, j, cl, k0, k1, alpha, P.weight[rc], o);
+                    // X is only known at run time: select, not index (no scratch)
+                    const float4 vb = X ? o.vb[1] : o.vb[0];
+                    const float sx = X ? o.sX[1] : o.sX[0], tw = X ? o.tw[1] : o.tw[0];
+                    const float f = role == 0 ? 1.0f - alpha : alpha * sx;
+                    const float ft = (role == 0 ? 1.0f - alpha : alpha) * tw;
+                    fma4(gkq, f, vb);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) gkt[i] = fmaf(ft, o.gt[i], gkt[i]);
+                }
+                __syncthreads();  // the list is rewritten by the next chunk
+            }
+            if (j < J) {
+                const int64_t row = blk * J + j;
+                if (A.grad_key_quat) reinterpret_cast<float4 *>(A.grad_key_quat)[row] = gkq;
+                if (A.grad_key_trans) {
+                    A.grad_key_trans[3 * row] = gkt[0];
+                    A.grad_key_trans[3 * row + 1] = gkt[1];
+                    A.grad_key_trans[3 * row + 2] = gkt[2];
+                }
+            }
+        }
     }
 }
 
@@ -1587,8 +1645,6 @@ __device__ __forceinline__ void rigid_to_dual_quat(float4 r0, float4 r1, float4 
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
-__device__ __forceinline__ void fma4(float4 &acc, float s, float4 v);
-
 // Dual quaternion blend of four influences (real part at X[STRIDE j], dual
 // part at X[STRIDE j + 1]) applied to p: signs against influence 0, the
 // normalised blend, then p + 2 r x (r x p + w p) + 2 (w_r d - w_d r + r x d).
@@ -1629,14 +1685,6 @@ __device__ __forceinline__ void dq_apply(const float4 *X, const int jk[4], const
                                          float pz, float &ox, float &oy, float &oz)
 {
     dq_blend_apply<3>(X, jk, wk, px, py, pz, ox, oy, oz);
-}
-
-__device__ __forceinline__ void fma4(float4 &acc, float s, float4 v)
-{
-    acc.x = fmaf(s, v.x, acc.x);
-    acc.y = fmaf(s, v.y, acc.y);
-    acc.z = fmaf(s, v.z, acc.z);
-    acc.w = fmaf(s, v.w, acc.w);
 }
 
 template <int METHOD>
@@ -2276,9 +2324,6 @@ hipError_t set_lds_limits()
 hipError_t prepare_kernels()
 {
     hipError_t err;
-    if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(key_block_transpose_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, kMaxClipJoints * 16)) != hipSuccess)
-        return err;
     if ((err = set_vertex_lds_limits_all<4>()) != hipSuccess || (err = set_vertex_lds_limits_all<8>()) != hipSuccess ||
         (err = set_vertex_lds_limits_all<16>()) != hipSuccess)
         return err;
@@ -2402,24 +2447,18 @@ hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const Po
 
 hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs &A, hipStream_t stream)
 {
-    const int64_t keys = (int64_t)pose.num_clips * pose.num_keys * pose.joints_per_clip;
-    const dim3 fgrid((unsigned)std::min<int64_t>(4096, (4 * keys + 255) / 256 + 1));
-    if (A.grad_key_quat) hipLaunchKernelGGL(fill_zero_f32_kernel, fgrid, dim3(256), 0, stream, 4 * keys, A.grad_key_quat);
-    if (A.grad_key_trans) hipLaunchKernelGGL(fill_zero_f32_kernel, fgrid, dim3(256), 0, stream, 3 * keys, A.grad_key_trans);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess || A.C == 0) return err;
-    hipLaunchKernelGGL(sample_bwd_kernel, dim3((unsigned)A.C), dim3(kSampleBwdThreads), 0, stream, pose, A);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-    const int64_t blocks = (int64_t)pose.num_clips * pose.num_keys;
-    const dim3 tgrid((unsigned)std::min<int64_t>(blocks, 65536));
-    const int J = pose.joints_per_clip;
-    if (A.grad_key_quat)
-        hipLaunchKernelGGL(key_block_transpose_kernel, tgrid, dim3(256), (size_t)J * 4 * 4, stream,
-                           A.grad_key_quat, blocks, J, 4);
-    if (A.grad_key_trans)
-        hipLaunchKernelGGL(key_block_transpose_kernel, tgrid, dim3(256), (size_t)J * 3 * 4, stream,
-                           A.grad_key_trans, blocks, J, 3);
-    return hipGetLastError();
+    hipError_t err = hipSuccess;
+    if (A.C > 0 && (A.grad_time || A.grad_weight)) {
+        hipLaunchKernelGGL(sample_bwd_kernel, dim3((unsigned)A.C), dim3(kSampleBwdThreads), 0, stream, pose, A);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
+    if (A.grad_key_quat || A.grad_key_trans) {
+        const int64_t blocks = (int64_t)pose.num_clips * pose.num_keys;
+        hipLaunchKernelGGL(sample_bwd_keys_kernel, dim3((unsigned)std::min<int64_t>(blocks, 1 << 20)),
+                           dim3(kSampleBwdThreads), 0, stream, pose, A);
+        err = hipGetLastError();
+    }
+    return err;
 }
 
 hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,

@@ -56,7 +56,7 @@ def test_reverse_mode_matches_oracle():
                                x["weight"], gq, gt, fps)
     for name, g, r in zip(("key_quat", "key_trans", "time", "weight"), got, ref):
         close(g.cpu().numpy(), r, name)
-    # the key arrays are zeroed by the call: a second call gives the same
+    # the key rows are overwritten by the call: a second call gives the same
     again = hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, dev(gq), dev(gt))
     torch.cuda.synchronize()
     close(again[0].cpu().numpy(), ref[0], "key_quat, second call")
