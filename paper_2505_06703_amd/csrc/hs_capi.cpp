@@ -524,10 +524,11 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     const int max_chain_tiles = pk.max_chain_tiles, max_chain_mp = pk.max_chain_mp;
 
     // The adjoint gets tiles of its own.  Characters of up to 1024 joints go
-    // to the synchronous-round kernel, on tiles of 512 joints unless a
-    // larger character needs more (smaller tiles keep several workgroups per
-    // CU); characters of up to 1664 joints to the dataflow kernel; the rest
-    // to the multipass adjoint.
+    // to the synchronous-round kernel, on tiles just large enough for the
+    // largest of them but at least 256 joints (4 waves: many workgroups per
+    // CU; measured against 512 joints: 179 vs 195 us on 10 000 x 256 joints,
+    // 12 vs 20 us on 64 x 64); characters of up to 1664 joints to the
+    // dataflow kernel; the rest to the multipass adjoint.
     (void)hipFree(plan->d_btiles);
     (void)hipFree(plan->d_bbig);
     plan->d_btiles = plan->d_bbig = nullptr;
@@ -538,7 +539,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
             const int64_t n = plan->h_offsets[c + 1] - plan->h_offsets[c];
             if (n <= hs::kMaxSyncTileJoints) m_sync = std::max(m_sync, n);
         }
-        plan->bwd_cap = std::max(512, round_up((int)m_sync, 64));
+        plan->bwd_cap = std::max(256, round_up((int)m_sync, 64));
         const bool mp_all = strategy == HS_STRATEGY_MULTIPASS;
         Packing ps, pb;
         if (!mp_all) ps = pack_tiles(plan, plan->bwd_cap, strategy, false, 0, hs::kMaxSyncTileJoints);
