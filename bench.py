@@ -241,14 +241,33 @@ class Workload:
             S = len(calls)
             self.chunk = S * max(1, -(-CHUNK // S))
             self.chunk_graph = hs.ForwardGraph.sequence(self.plan, [calls[k % S] for k in range(self.chunk)])
-        self.bwd_ev = []
+        else:
+            # the whole differentiable step (forward, loss gradient, adjoint)
+            # captured for CHUNK steps over the sets: nothing in it allocates
+            # or synchronises
+            S = len(self.sets)
+            self.chunk = S * max(1, -(-CHUNK // S))
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                for k in range(S):
+                    self.diff_step(self.sets[k])
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            self.diff_graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.diff_graph):
+                for k in range(self.chunk):
+                    self.diff_step(self.sets[k % S])
 
-    def run(self, steps, evs=None):
-        """`steps` steps from set 0 on; evs: pre-created event pairs that
-        bracket the adjoint launches (differentiable workload)."""
+    def run(self, steps):
+        """`steps` steps from set 0 on, from captured graphs of `chunk` steps
+        (the remainder issued call by call)."""
         if self.graphs is None:
-            for k in range(steps):
-                self.step(k, None if evs is None else evs[k])
+            full = steps // self.chunk
+            for _ in range(full):
+                self.diff_graph.replay()
+            for k in range(full * self.chunk, steps):
+                self.step(k)
             return
         S = len(self.sets)
         full = steps // self.chunk
@@ -257,24 +276,48 @@ class Workload:
         for k in range(full * self.chunk, steps):
             self.graphs[k % S].launch()
 
-    def step(self, k, ev=None):
-        """One step on set k (cycled); ev: a pre-created event pair to bracket
-        the adjoint launch with (differentiable workload)."""
-        hs, s = self.hs, self.sets[k % len(self.sets)]
+    def step(self, k):
+        """One step on set k (cycled)."""
+        s = self.sets[k % len(self.sets)]
         if self.graphs is not None:
             self.graphs[k % len(self.sets)].launch()
             return
+        self.diff_step(s)
+
+    def diff_step(self, s):
+        """Forward, loss gradient, adjoint on set s (differentiable workload)."""
+        hs = self.hs
         hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
         # loss = sum over effectors |b_e - y_e|^2: its gradient enters the
         # effector rows of the (otherwise zero) dLoss/dG buffer
-        s["gG"][self.eff, :3, 3] = 2.0 * (s["G"][self.eff, :3, 3] - self.target)
-        if ev is not None:
-            ev[0].record()
+        hs.hs_effector_loss_grad(s["G"], self.eff, self.target, s["gG"])
         hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
                             grad_quat=s["gq"], grad_trans=s["gt"])
-        if ev is not None:
-            ev[1].record()
-            self.bwd_ev.append(ev)
+
+    def backward_ms(self, reps=50):
+        """Mean duration of the adjoint launch alone, back to back."""
+        torch, s = self.torch, self.sets[0]
+        self.diff_step(s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            self.hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
+                                     grad_quat=s["gq"], grad_trans=s["gt"])
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def eager_step_ms(self, reps=50):
+        """Mean time per step issued call by call from Python (no graph)."""
+        torch = self.torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(reps):
+            self.diff_step(self.sets[k % len(self.sets)])
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
 
     def plain_launch_ms(self, reps=50):
         """Mean time per step when each step is one plain hs_scan_forward call
@@ -309,9 +352,6 @@ class Workload:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    @staticmethod
-    def mean_ms(evs):
-        return float(np.mean([a.elapsed_time(b) for a, b in evs])) if evs else 0.0
 
 
 def main():
@@ -352,21 +392,19 @@ def main():
         del src, dst
     w.run(args.warmup)
     diff = args.workload == "differentiable"
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)] \
-        if diff else None
     region = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     region[0].record()
-    w.run(args.steps, evs)
+    w.run(args.steps)
     region[1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
     dominant = DOMINANT.get(args.workload, "fwd_tile_kernel")
     if diff:
-        # adjoint launches bracketed one by one; the forward timed on its own
-        kernel_ms = w.mean_ms(w.bwd_ev)
+        # the adjoint and the forward timed on their own, back to back
+        kernel_ms = w.backward_ms()
         fwd_ms = w.forward_ms()
     else:
         # forward-only step = one kernel, launched back to back: HIP events
@@ -383,9 +421,8 @@ def main():
             "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
     if args.workload == "differentiable":
         roof["forward_kernel_ms"] = fwd_ms
-    launch = None
-    if not diff:
-        launch = {"graph_ms_per_step": elapsed * 1e3 / args.steps, "plain_call_ms_per_step": w.plain_launch_ms()}
+    launch = {"graph_ms_per_step": elapsed * 1e3 / args.steps,
+              "plain_call_ms_per_step": w.eager_step_ms() if diff else w.plain_launch_ms()}
     out = {
         "metric": METRIC,
         "value": N * args.steps / elapsed,
@@ -402,7 +439,7 @@ def main():
         "config": {"workload": args.workload, "characters": C, "joints": N, "max_depth": info["max_depth"],
                    "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
                    "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
-                   "autotuned": not args.no_autotune, "hip_graph": w.graphs is not None,
+                   "autotuned": not args.no_autotune, "hip_graph": True,
                    "input_sets": len(w.sets),
                    **({"adjoint": args.adjoint} if args.workload == "differentiable" else {})},
         "roofline": roof,

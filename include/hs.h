@@ -332,6 +332,18 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
                            const float *ckpt, int32_t ckpt_k, float *grad_quat, float *grad_trans,
                            float *grad_scale, uint32_t flags, hipStream_t stream);
 
+/* Gradient of the end-effector loss sum_e |b_e - y_e|^2, with b_e the
+ * translation column of G_e (the loss of the adjoint's workload and of
+ * IK-style loops): writes 2 (b_e - y_e) into column 3 of rows 0-2 of
+ * grad_global[e] for every effector e (device int64 ids in [0,
+ * num_joints), distinct; targets [num_effectors, 3]) and leaves the rest of
+ * grad_global untouched (keep it zero).  Ids outside [0, num_joints) are
+ * skipped.  Errors: HS_ERR_INVALID_ARG for NULL or misaligned arrays and
+ * for grad_global overlapping an input.
+ * Asynchronous; allocates nothing. */
+hs_status hs_effector_loss_grad(int64_t num_joints, int64_t num_effectors, const int64_t *effectors,
+                                const float *global, const float *targets, float *grad_global, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Vertex skinning: the stage after Bind MeshPose.  The paper's pipeline
  * skins meshes with the skin matrices on the GPU (Sec. 3; Sec. 5 uses

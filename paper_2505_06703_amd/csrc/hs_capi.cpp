@@ -1307,6 +1307,26 @@ hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, c
     return HS_OK;
 }
 
+hs_status hs_effector_loss_grad(int64_t num_joints, int64_t num_effectors, const int64_t *effectors,
+                                const float *global, const float *targets, float *grad_global, hipStream_t stream)
+{
+    if (num_joints < 0 || num_effectors < 0)
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_loss_grad: sizes must be >= 0");
+    if (num_effectors == 0) return HS_OK;
+    if (!effectors || !global || !targets || !grad_global)
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_loss_grad: NULL array");
+    if (!aligned(effectors, 8) || !aligned(global, 4) || !aligned(targets, 4) || !aligned(grad_global, 4))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_loss_grad: misaligned array");
+    const size_t N = (size_t)num_joints, E = (size_t)num_effectors;
+    hs_status rc = check_aliasing({{grad_global, N * 64, "grad_global"}},
+                                  {{global, N * 64, "global"}, {targets, E * 12, "targets"}, {effectors, E * 8, "effectors"}});
+    if (rc != HS_OK) return rc;
+    hipError_t err = hs::launch_effector_grad(num_joints, num_effectors, effectors, global, targets, grad_global,
+                                              stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_effector_loss_grad");
+    return HS_OK;
+}
+
 hs_status hs_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out, hipStream_t stream)
 {
     if (n < 0) return fail(HS_ERR_INVALID_ARG, "hs_skin: n must be >= 0");

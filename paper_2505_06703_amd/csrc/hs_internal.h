@@ -145,6 +145,9 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 // needs (once per process and device, before any launch or capture).
 hipError_t prepare_kernels();
 
+hipError_t launch_effector_grad(int64_t n, int64_t ne, const int64_t *eff, const float *G, const float *target,
+                                float *grad, hipStream_t stream);
+
 // Reverse mode of the sampler (see hs_pose_sample_backward).
 struct SampleBwdArgs {
     const float *grad_quat;    // [N,4]

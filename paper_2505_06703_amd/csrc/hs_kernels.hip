@@ -1867,6 +1867,23 @@ fwd_vertex_kernel(TileLaunch tl, PoseArgs pose, OutArgs out, VertexLaunch vl, fl
 }
 
 // ---------------------------------------------------------------------------
+// End-effector loss sum_e |b_e - y_e|^2 (b_e the translation of G_e): its
+// gradient with respect to G is 2 (b_e - y_e) in column 3 of rows 0-2 of
+// each effector's G and zero elsewhere.  One thread per effector writes
+// those three values; the caller keeps the other entries zero.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+effector_grad_kernel(int64_t n, int64_t ne, const int64_t *eff, const float *G, const float *target, float *grad)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const int64_t e = eff[i];
+    if (e < 0 || e >= n) return;  // ids outside the batch are skipped
+#pragma unroll
+    for (int r = 0; r < 3; ++r) grad[16 * e + 4 * r + 3] = 2.0f * (G[16 * e + 4 * r + 3] - target[3 * i + r]);
+}
+
+// ---------------------------------------------------------------------------
 // Multipass path.
 // ---------------------------------------------------------------------------
 constexpr int kMPWaves = 4;
@@ -2459,6 +2476,15 @@ hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs
         err = hipGetLastError();
     }
     return err;
+}
+
+hipError_t launch_effector_grad(int64_t n, int64_t ne, const int64_t *eff, const float *G, const float *target,
+                                float *grad, hipStream_t stream)
+{
+    if (ne == 0) return hipSuccess;
+    hipLaunchKernelGGL(effector_grad_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, n, ne, eff,
+                       G, target, grad);
+    return hipGetLastError();
 }
 
 hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,

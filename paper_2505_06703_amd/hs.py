@@ -39,7 +39,8 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
-           "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices")
+           "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices",
+           "hs_effector_loss_grad")
 
 
 class HSError(RuntimeError):
@@ -127,6 +128,7 @@ def load_library():
     lib.hs_mesh_destroy.argtypes = [vp]
     lib.hs_mesh_destroy.restype = None
     lib.hs_skin_vertices.argtypes = [vp, vp, i32, vp, vp]
+    lib.hs_effector_loss_grad.argtypes = [i64, i64, vp, vp, vp, vp, vp]
     lib.hs_scan_skin_vertices.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp]
     lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
                                             vp, vp, vp, vp, vp, vp, vp]
@@ -462,6 +464,20 @@ def hs_scan_skin_vertices(plan, mesh, inv_bind, quat=None, trans=None, scale=Non
     _check(load_library().hs_scan_skin_vertices(plan.handle, ctypes.byref(src), _ptr(inv_bind), mesh.handle,
                                                 int(method), _ptr(vertices_out), _ptr(skin_out), _stream(stream)))
     return vertices_out
+
+
+def hs_effector_loss_grad(global_, effectors, targets, grad_global, stream=None):
+    """dLoss/dG of sum_e |b_e - y_e|^2 written into the effector rows of
+    ``grad_global`` (whose other entries the caller keeps zero)."""
+    N = global_.shape[0]
+    _need(global_, "global", (N, 4, 4))
+    _need(grad_global, "grad_global", (N, 4, 4))
+    E = effectors.shape[0]
+    _need(effectors, "effectors", (E,), torch.int64)
+    _need(targets, "targets", (E, 3))
+    _check(load_library().hs_effector_loss_grad(N, E, _ptr(effectors), _ptr(global_), _ptr(targets),
+                                                _ptr(grad_global), _stream(stream)))
+    return grad_global
 
 
 def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0, want_scale=True,

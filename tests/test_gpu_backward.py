@@ -238,3 +238,71 @@ def test_more_tiles_than_resident_workgroups(adj):
     rng = np.random.default_rng(13)
     W[:, :3, :] += 0.01 * rng.standard_normal((b.num_joints, 3, 4)).astype(np.float32)
     check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), f"1300 characters adj {adj}")
+
+
+def test_effector_loss_gradient_kernel():
+    """hs_effector_loss_grad writes 2 (b_e - y_e) into column 3 of rows 0-2
+    of each effector's row and nothing else; ids outside the batch are
+    skipped."""
+    rng = np.random.default_rng(14)
+    N = 1000
+    G = torch.randn((N, 4, 4), device=DEV)
+    eff = np.sort(rng.choice(N, 37, replace=False)).astype(np.int64)
+    tgt = rng.standard_normal((37, 3)).astype(np.float32)
+    gG = torch.zeros((N, 4, 4), device=DEV)
+    hs.hs_effector_loss_grad(G, dev(eff), dev(tgt), gG)
+    bad = np.concatenate([eff, [-1, N, N + 5]]).astype(np.int64)
+    gG2 = torch.zeros((N, 4, 4), device=DEV)
+    hs.hs_effector_loss_grad(G, dev(bad), dev(np.concatenate([tgt, np.zeros((3, 3), np.float32)])), gG2)
+    torch.cuda.synchronize()
+    ref = np.zeros((N, 4, 4), np.float32)
+    ref[eff, :3, 3] = 2.0 * (G.cpu().numpy()[eff, :3, 3] - tgt)
+    np.testing.assert_array_equal(gG.cpu().numpy(), ref)
+    np.testing.assert_array_equal(gG2.cpu().numpy(), ref)
+
+
+def test_captured_differentiable_step_replays_match_eager():
+    """Forward, loss gradient and adjoint captured in one HIP graph (as the
+    benchmark runs them): every replay, with eager work and input changes
+    between replays, matches the eager calls."""
+    b = wl.differentiable(num_characters=64)
+    N = b.num_joints
+    plan = hs.Plan(b.offsets, b.parents)
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    eff = dev(b.extra["effectors"].astype(np.int64))
+    tgt = dev(np.random.default_rng(15).standard_normal((eff.shape[0], 3)).astype(np.float32))
+    G = torch.empty((N, 4, 4), device=DEV)
+    gG = torch.zeros((N, 4, 4), device=DEV)
+    gq = torch.empty((N, 4), device=DEV)
+    gt = torch.empty((N, 3), device=DEV)
+
+    def step(G, gG, gq, gt):
+        hs.hs_scan_forward(plan, q, t, s, global_out=G)
+        hs.hs_effector_loss_grad(G, eff, tgt, gG)
+        hs.hs_scan_backward(plan, q, t, s, gG, want_scale=False, grad_quat=gq, grad_trans=gt)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(G, gG, gq, gt)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(G, gG, gq, gt)
+    rng = np.random.default_rng(16)
+    for rep in range(4):
+        q.copy_(dev(wl.random_quats(rng, N, 0.3)))  # eager work between replays
+        gq.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        G2, gG2 = torch.empty_like(G), torch.zeros_like(gG)
+        gq2, gt2 = torch.empty_like(gq), torch.empty_like(gt)
+        step(G2, gG2, gq2, gt2)
+        torch.cuda.synchronize()
+        assert torch.equal(G, G2), rep
+        # the adjoint sums colliding pushes in arrival order: equal to
+        # rounding, held to the adjoint's tolerance
+        for x, y in ((gq, gq2), (gt, gt2)):
+            tol = TOL * max(1.0, float(y.abs().max()))
+            assert float((x - y).abs().max()) <= tol, rep
