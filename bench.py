@@ -122,17 +122,20 @@ def summarize_pmc(workload, fetch_csv, write_csv):
     kname = DOMINANT.get(workload, "fwd_tile_kernel")
 
     def per_kernel(path, counter):
-        vals = {}
+        scan, copy = [], None
         with open(path) as f:
-            for row in csv.DictReader(f):
-                if row.get("Counter_Name") != counter:
-                    continue
-                name = row["Kernel_Name"]
-                key = "scan" if kname in name else ("copy" if "copy" in name.lower() else None)
-                if key:
-                    vals.setdefault(key, []).append(float(row["Counter_Value"]))
-        # the calibration copy is the largest copy of the run
-        return {"scan": sum(vals["scan"]) / len(vals["scan"]), "copy": max(vals["copy"])}
+            rows = [r for r in csv.DictReader(f) if r.get("Counter_Name") == counter]
+        rows.sort(key=lambda r: int(r.get("Dispatch_Id", 0)))
+        for row in rows:
+            name, kib = row["Kernel_Name"], float(row["Counter_Value"])
+            if kname in name:
+                scan.append(kib)
+            # the calibration copy (--calibrate-copy) is the first large copy
+            # of the run: small setup copies come before it, the 1 GiB
+            # device-copy bandwidth probe after it
+            elif copy is None and "copy" in name.lower() and kib * 1024.0 >= COPY_BYTES / 16:
+                copy = (kib, int(row["Dispatch_Id"]))
+        return {"scan": sum(scan) / len(scan), "copy": copy[0], "copy_dispatch": copy[1]}
 
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
@@ -141,7 +144,8 @@ def summarize_pmc(workload, fetch_csv, write_csv):
     rec = {"kernel": kname, "source_sha": kernel_source_sha(),
            "fetch_bytes_per_launch": fetch["scan"] * 1024.0 * f_scale,
            "write_bytes_per_launch": write["scan"] * 1024.0 * w_scale,
-           "copy_fetch_scale": f_scale, "copy_write_scale": w_scale}
+           "copy_fetch_scale": f_scale, "copy_write_scale": w_scale,
+           "copy_dispatch": [fetch["copy_dispatch"], write["copy_dispatch"]]}
     rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     try:
         with open(TRAFFIC_FILE) as f:
