@@ -17,8 +17,8 @@ constexpr int kMaxTileJoints = 3072;
 constexpr int kMaxBwdTileJoints = 1664;
 
 // Largest tile of the synchronous-round adjoint kernel: one joint per
-// thread, 104 bytes of LDS per joint (jump product, accumulator, pointer,
-// owner word).
+// thread, 104 bytes of LDS per joint (jump product, inbox, pointer, owner
+// word).
 constexpr int kMaxSyncTileJoints = 1024;
 
 // A tile: a contiguous range of global joint ids holding whole characters,

@@ -1251,11 +1251,13 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 // Several joints can push to one target in a round (the descendants of a
 // at distance 2^r).  LDS float atomics are slow, so they are kept for
 // those collisions only: every pusher first stores its id into the
-// target's owner word (plain stores, one of them lands); the owner adds its
-// contribution with a plain read-modify-write, the others with atomics one
-// barrier later.  Owner words carry the round (id | r << 10), which also
-// tells a joint whether anything arrived for it this round.
-// LDS: M[cap][3] float4 | accumulators[cap][3] float4 | anc[cap] | owner[cap]
+// target's owner word (plain stores, one of them lands); the owner stores
+// its contribution into the target's inbox with a plain store, the others
+// add theirs with atomics one barrier later, and the target adds the inbox
+// to the S it keeps in registers.  Owner words carry the round
+// (id | r << 10), which also tells a joint whether anything arrived for it
+// this round (an inbox is read only in a round that its owner wrote).
+// LDS: M[cap][3] float4 | inboxes[cap][3] float4 | anc[cap] | owner[cap]
 // ---------------------------------------------------------------------------
 constexpr int kOwnerShift = 10;  // tile-local ids < 1024
 
@@ -1276,7 +1278,7 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
     extern __shared__ float4 lds[];
     const int cap = tl.tile_cap;
     float4 *Ms = lds;
-    float4 *Sa = lds + 3 * cap;
+    float4 *In = lds + 3 * cap;
     int *Ac = reinterpret_cast<int *>(lds + 6 * cap);
     int *Own = Ac + cap;
     const int jl = threadIdx.x;
@@ -1287,13 +1289,27 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
         const int64_t gid = td.begin + jl;
         float M[12], S[12];
         int a = -1, p = -1;
+        // the rotation and scale are kept for the gradient step: each pose
+        // value is read from HBM once (streaming loads)
+        float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        float sx = 1.0f, sy = 1.0f, sz = 1.0f;
         if (live) {
             p = tl.parent[gid];
             a = p < 0 ? -1 : (int)(p - td.begin);
-            load_local<false>(pose, gid, 0, 0, M);
+            const native_float4 qn =
+                __builtin_nontemporal_load(reinterpret_cast<const native_float4 *>(pose.quat) + gid);
+            q = make_float4(qn.x, qn.y, qn.z, qn.w);
+            const float *t = pose.trans + 3 * gid;
+            if (pose.scale) {
+                const float *sp = pose.scale + 3 * gid;
+                sx = __builtin_nontemporal_load(sp);
+                sy = __builtin_nontemporal_load(sp + 1);
+                sz = __builtin_nontemporal_load(sp + 2);
+            }
+            aff_from_trs(q, __builtin_nontemporal_load(t), __builtin_nontemporal_load(t + 1),
+                         __builtin_nontemporal_load(t + 2), sx, sy, sz, M);
             aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
             aff_store(Ms + 3 * jl, M);
-            aff_store(Sa + 3 * jl, S);
             Ac[jl] = a;
             owner_claim(Own + jl, -1);
         }
@@ -1310,23 +1326,22 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             if (a >= 0) {
                 adj_pull(S, M, c);
                 lose = owner_read(Own + a) != (tag | jl);
-                if (!lose) {
-                    float acc[12];
-                    aff_load(Sa + 3 * a, acc);
-#pragma unroll
-                    for (int k = 0; k < 12; ++k) acc[k] += c[k];
-                    aff_store(Sa + 3 * a, acc);
-                }
+                if (!lose) aff_store(In + 3 * a, c);
                 float ma[12];
                 aff_load(Ms + 3 * a, ma);
                 aa = Ac[a];
                 aff_mul_left(ma, M);  // published after the barriers
             }
             __syncthreads();
-            if (lose) lds_atomic_add12(Sa + 3 * a, c);
+            if (lose) lds_atomic_add12(In + 3 * a, c);
             const bool recv = live && (owner_read(Own + jl) >> kOwnerShift) == r;
             __syncthreads();
-            if (recv) aff_load(Sa + 3 * jl, S);
+            if (recv) {
+                float in[12];
+                aff_load(In + 3 * jl, in);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) S[k] += in[k];
+            }
             if (a >= 0) {
                 a = aa;
                 aff_store(Ms + 3 * jl, M);
@@ -1344,12 +1359,6 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
                 Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
                 Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
                 Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
-            }
-            const float4 q = reinterpret_cast<const float4 *>(pose.quat)[gid];
-            float sx = 1.0f, sy = 1.0f, sz = 1.0f;
-            if (pose.scale) {
-                const float *sp = pose.scale + 3 * gid;
-                sx = sp[0]; sy = sp[1]; sz = sp[2];
             }
             write_grads(bwd, gid, S, Ap, q, sx, sy, sz);
         }
