@@ -60,9 +60,9 @@ BYTES_PER_JOINT = {
     # instanced: parents and inverse binds are the one skeleton's (256 rows,
     # cache-resident), so only the skin is per joint in HBM
     "fused_sample_instanced": 64,
-    # adjoint: read quat, trans, scale, parent 44 + grad_global 64, write
-    # grad_quat 16 + grad_trans 12
-    "differentiable": 136,
+    # end-effector adjoint: read quat, trans, scale, parent 44, write
+    # grad_quat 16 + grad_trans 12 (+ 24 B per effector: b_e and y_e)
+    "differentiable": 72,
 }
 DOMINANT = {"differentiable": "bwd_sync_kernel",
             "long_chains": "multipass step (mp_local, anchor rounds, mp_out)"}
@@ -199,6 +199,10 @@ class Workload:
             Grest, _ = hs.hs_scan_forward(self.plan, up(b.rest_quat), up(b.rest_trans), up(b.rest_scale))
             self.eff = up(b.extra["effectors"].astype(np.int64))
             self.target = Grest[self.eff, :3, 3] + up(b.extra["target_offsets"])
+            self.effset = hs.Effectors(self.plan, b.extra["effectors"])
+            # the dense route (loss gradient into dLoss/dG, general adjoint),
+            # timed beside the step for comparison
+            self.gG = torch.zeros((N, 4, 4), device=dev)
             del Grest
         # input/output sets cycled step by step: enough of them that one
         # cycle touches at least SWEEP_BYTES, so the 256 MB last-level cache
@@ -214,7 +218,6 @@ class Workload:
             else:
                 st["S"] = torch.empty((N, 4, 4), device=dev)
             if name == "differentiable":
-                st["gG"] = torch.zeros((N, 4, 4), device=dev)
                 st["gq"] = torch.empty((N, 4), device=dev)
                 st["gt"] = torch.empty((N, 3), device=dev)
             return st
@@ -246,9 +249,9 @@ class Workload:
             self.chunk = S * max(1, -(-CHUNK // S))
             self.chunk_graph = hs.ForwardGraph.sequence(self.plan, [calls[k % S] for k in range(self.chunk)])
         else:
-            # the whole differentiable step (forward, loss gradient, adjoint)
+            # the whole differentiable step (forward, end-effector adjoint)
             # captured for CHUNK steps over the sets: nothing in it allocates
-            # or synchronises
+            # or synchronises; the dense route likewise
             S = len(self.sets)
             self.chunk = S * max(1, -(-CHUNK // S))
             side = torch.cuda.Stream()
@@ -256,12 +259,17 @@ class Workload:
             with torch.cuda.stream(side):
                 for k in range(S):
                     self.diff_step(self.sets[k])
+                    self.dense_step(self.sets[k])
             torch.cuda.current_stream().wait_stream(side)
             torch.cuda.synchronize()
             self.diff_graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(self.diff_graph):
                 for k in range(self.chunk):
                     self.diff_step(self.sets[k % S])
+            self.dense_graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.dense_graph):
+                for k in range(self.chunk):
+                    self.dense_step(self.sets[k % S])
 
     def run(self, steps):
         """`steps` steps from set 0 on, from captured graphs of `chunk` steps
@@ -289,14 +297,36 @@ class Workload:
         self.diff_step(s)
 
     def diff_step(self, s):
-        """Forward, loss gradient, adjoint on set s (differentiable workload)."""
+        """Forward and the adjoint of loss = sum over effectors |b_e - y_e|^2
+        on set s (differentiable workload): the adjoint forms the loss
+        gradient at the effectors itself, from the forward's output."""
         hs = self.hs
         hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
-        # loss = sum over effectors |b_e - y_e|^2: its gradient enters the
-        # effector rows of the (otherwise zero) dLoss/dG buffer
-        hs.hs_effector_loss_grad(s["G"], self.eff, self.target, s["gG"])
-        hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
+        hs.hs_effector_backward(self.plan, self.effset, s["q"], s["t"], s["s"], s["G"], self.target,
+                                want_scale=False, grad_quat=s["gq"], grad_trans=s["gt"])
+
+    def dense_step(self, s):
+        """The same step through a dense dLoss/dG: the loss gradient enters
+        the effector rows of the (otherwise zero) buffer, which the general
+        adjoint reads whole."""
+        hs = self.hs
+        hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+        hs.hs_effector_loss_grad(s["G"], self.eff, self.target, self.gG)
+        hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], self.gG, want_scale=False,
                             grad_quat=s["gq"], grad_trans=s["gt"])
+
+    def dense_step_ms(self, reps=5):
+        """Mean time per step of the dense route (captured like the step)."""
+        torch = self.torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        self.dense_graph.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            self.dense_graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / (reps * self.chunk)
 
     def backward_ms(self, reps=50):
         """Mean duration of the adjoint launch alone, back to back."""
@@ -305,8 +335,8 @@ class Workload:
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            self.hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], s["gG"], want_scale=False,
-                                     grad_quat=s["gq"], grad_trans=s["gt"])
+            self.hs.hs_effector_backward(self.plan, self.effset, s["q"], s["t"], s["s"], s["G"], self.target,
+                                         want_scale=False, grad_quat=s["gq"], grad_trans=s["gt"])
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
@@ -415,6 +445,8 @@ def main():
         # around the timed region give its mean launch duration
         kernel_ms = region[0].elapsed_time(region[1]) / args.steps
     bytes_per_launch = N * BYTES_PER_JOINT[args.workload]
+    if diff:
+        bytes_per_launch += 24 * w.effset.num_effectors
     if args.workload in FUSED:
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
@@ -425,6 +457,7 @@ def main():
             "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
     if args.workload == "differentiable":
         roof["forward_kernel_ms"] = fwd_ms
+        roof["dense_seed_ms_per_step"] = w.dense_step_ms()
     launch = {"graph_ms_per_step": elapsed * 1e3 / args.steps,
               "plain_call_ms_per_step": w.eager_step_ms() if diff else w.plain_launch_ms()}
     out = {

@@ -344,6 +344,44 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
 hs_status hs_effector_loss_grad(int64_t num_joints, int64_t num_effectors, const int64_t *effectors,
                                 const float *global, const float *targets, float *grad_global, hipStream_t stream);
 
+/* The adjoint of an end-effector loss without a dense dLoss/dG.  With
+ * loss = sum_e |b_e - y_e|^2 over a fixed set of joints e (b_e the
+ * translation column of G_e), dLoss/dG is zero except in column 3 of rows
+ * 0-2 of the effectors' rows; the adjoint's reverse accumulation
+ * (X_j = D_j + sum over children c of X_c (.) L_c, derived for this library
+ * from Eq. 1, since the paper has no backward) can start from those few
+ * seeds.
+ *
+ * hs_effectors_create takes the effectors' global joint ids on the HOST
+ * (num_effectors of them, distinct, in [0, num_joints); HS_ERR_INVALID_ARG
+ * otherwise), sorts them and, when every adjoint tile of the plan runs the
+ * synchronous-round kernel (characters of up to 1024 joints and the default
+ * adjoint option), records each tile's share; hs_effectors_sparse then
+ * returns 1.  Otherwise the set keeps a zeroed dense dLoss/dG buffer of
+ * 64 bytes per joint.  It synchronises the device once; the set belongs to
+ * the plan and must be destroyed before it.
+ *
+ * hs_effector_backward writes what hs_effector_loss_grad followed by
+ * hs_scan_backward (recompute mode) would write, up to rounding: dLoss/dq,
+ * dLoss/dt and, if grad_scale is non-NULL, dLoss/ds.  global is the
+ * forward's output for the same pose ([N,4,4], 16-byte aligned), targets
+ * [num_effectors, 3] the y_e in the order the ids were given.  On a sparse
+ * set the synchronous-round tiles form each seed 2 (b_e - y_e) in LDS from
+ * global and targets and dLoss/dG is never stored; otherwise the loss
+ * gradient kernel fills the set's dense buffer and the general adjoint
+ * reads it.  src must be HS_POSE_TRS.  Errors: HS_ERR_INVALID_ARG for NULL
+ * or misaligned arrays, a set made for another plan or outputs overlapping
+ * inputs.  Asynchronous; allocates nothing.  Calls with one dense set must
+ * not overlap (they share its buffer). */
+typedef struct hs_effectors hs_effectors;
+hs_status hs_effectors_create(const hs_plan *plan, int64_t num_effectors, const int64_t *joint_ids,
+                              hs_effectors **out);
+void hs_effectors_destroy(hs_effectors *effectors);
+int32_t hs_effectors_sparse(const hs_effectors *effectors);
+hs_status hs_effector_backward(const hs_plan *plan, const hs_effectors *effectors, const hs_pose_src *src,
+                               const float *global, const float *targets, float *grad_quat, float *grad_trans,
+                               float *grad_scale, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Vertex skinning: the stage after Bind MeshPose.  The paper's pipeline
  * skins meshes with the skin matrices on the GPU (Sec. 3; Sec. 5 uses

@@ -187,6 +187,7 @@ struct hs_plan {
     // adjoint tiles: characters of up to 1024 joints (synchronous-round
     // kernel) and larger ones up to the dataflow kernel's limit
     TileDesc *d_btiles = nullptr;
+    std::vector<TileDesc> h_btiles;
     int32_t num_btiles = 0;
     int32_t bwd_cap = 0;
     TileDesc *d_bbig = nullptr;
@@ -545,6 +546,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         if (!mp_all) ps = pack_tiles(plan, plan->bwd_cap, strategy, false, 0, hs::kMaxSyncTileJoints);
         pb = pack_tiles(plan, hs::kMaxBwdTileJoints, strategy, false, mp_all ? 0 : hs::kMaxSyncTileJoints + 1);
         plan->num_btiles = (int32_t)ps.tiles.size();
+        plan->h_btiles = ps.tiles;
         plan->num_bbig = (int32_t)pb.tiles.size();
         hipError_t e2 = upload(&plan->d_btiles, ps.tiles);
         if (e2 == hipSuccess) e2 = upload(&plan->d_bbig, pb.tiles);
@@ -1370,6 +1372,43 @@ void free_mesh(hs_mesh *m)
 
 } // namespace
 
+namespace {
+
+// The adjoint's launches: synchronous-round (or dataflow) tiles, the large
+// dataflow tiles, then the multipass characters.
+hs_status run_backward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::BwdArgs &ba, hipStream_t stream,
+                       const char *what)
+{
+    hs::TileLaunch tl = tile_launch(plan);
+    tl.chain_units = 0;
+    hipError_t err = hipSuccess;
+    if (plan->num_btiles > 0) {
+        tl.tiles = plan->d_btiles;
+        tl.num_tiles = plan->num_btiles;
+        tl.tile_cap = plan->bwd_cap;
+        tl.adjoint = plan->shape.adjoint;
+        tl.grid = plan->num_btiles;
+        tl.waves = 1;  // dataflow: a power of two, at most one wave per block
+        while (tl.waves < 16 && tl.waves * 2 * 64 <= plan->bwd_cap) tl.waves *= 2;
+        err = hs::launch_backward_tiles(tl, pa, ba, stream);
+        if (err != hipSuccess) return fail_hip(err, (std::string(what) + " (tiles)").c_str());
+    }
+    if (plan->num_bbig > 0) {
+        tl.tiles = plan->d_bbig;
+        tl.num_tiles = plan->num_bbig;
+        tl.tile_cap = hs::kMaxBwdTileJoints;
+        tl.waves = 16;
+        tl.grid = plan->num_bbig;
+        err = hs::launch_backward_tiles(tl, pa, ba, stream);
+        if (err != hipSuccess) return fail_hip(err, (std::string(what) + " (large tiles)").c_str());
+    }
+    err = hs::launch_backward_multipass(mp_launch(plan, plan->bmp), pa, ba, stream);
+    if (err != hipSuccess) return fail_hip(err, (std::string(what) + " (multipass)").c_str());
+    return HS_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 hs_status hs_mesh_create(const hs_plan *plan, const hs_mesh_batch *mb, hs_mesh **out)
@@ -1546,32 +1585,167 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
     ba.grad_scale = grad_scale;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_backward: cannot select device");
-    hs::TileLaunch tl = tile_launch(plan);
-    tl.chain_units = 0;
+    return run_backward(plan, pa, ba, stream, "hs_scan_backward");
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// End-effector losses: the adjoint seeded from a list of joints.
+// ---------------------------------------------------------------------------
+struct hs_effectors {
+    const hs_plan *plan = nullptr;  // the plan it was made for
+    int device = 0;
+    int64_t E = 0;
+    // every adjoint tile runs the synchronous-round kernel: the seeds are
+    // formed inside it from these tables
+    bool sparse = false;
+    int64_t *d_ids = nullptr;   // ascending (sparse) or in the caller's order (dense)
+    int32_t *d_row = nullptr;   // target row of each sorted id
+    int32_t *d_tile = nullptr;  // [num_btiles][2]: each tile's range of d_ids
+    float *d_dense = nullptr;   // dense seed [N,16], zero outside the effector rows
+};
+
+namespace {
+
+void free_effectors(hs_effectors *e)
+{
+    if (!e) return;
+    (void)hipFree(e->d_ids);
+    (void)hipFree(e->d_row);
+    (void)hipFree(e->d_tile);
+    (void)hipFree(e->d_dense);
+    delete e;
+}
+
+} // namespace
+
+extern "C" {
+
+hs_status hs_effectors_create(const hs_plan *plan, int64_t num_effectors, const int64_t *joint_ids,
+                              hs_effectors **out)
+{
+    if (!out) return fail(HS_ERR_INVALID_ARG, "hs_effectors_create: out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_effectors_create: plan is NULL");
+    if (num_effectors < 0 || num_effectors >= (int64_t(1) << 31))
+        return fail(HS_ERR_INVALID_ARG, "hs_effectors_create: num_effectors %lld out of range",
+                    (long long)num_effectors);
+    if (num_effectors > 0 && !joint_ids) return fail(HS_ERR_INVALID_ARG, "hs_effectors_create: joint_ids is NULL");
+    const int64_t E = num_effectors, N = plan->N;
+    std::vector<int64_t> ids(joint_ids, joint_ids + E);
+    std::vector<int32_t> order((size_t)E);
+    for (int64_t i = 0; i < E; ++i) {
+        if (ids[i] < 0 || ids[i] >= N)
+            return fail(HS_ERR_INVALID_ARG, "hs_effectors_create: joint id %lld outside [0, %lld)",
+                        (long long)ids[i], (long long)N);
+        order[i] = (int32_t)i;
+    }
+    std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ids[a] < ids[b]; });
+    for (int64_t i = 1; i < E; ++i)
+        if (ids[order[i]] == ids[order[i - 1]])
+            return fail(HS_ERR_INVALID_ARG, "hs_effectors_create: joint %lld listed twice", (long long)ids[order[i]]);
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_effectors_create: cannot select device");
+    hs_effectors *e = new hs_effectors();
+    e->plan = plan;
+    e->device = plan->ctx->device;
+    e->E = E;
+    e->sparse = plan->num_btiles > 0 && plan->num_bbig == 0 && plan->bmp.num_blocks == 0 &&
+                plan->bwd_untiled == 0 && plan->shape.adjoint != hs::kAdjDataflow;
     hipError_t err = hipSuccess;
-    if (plan->num_btiles > 0) {
-        tl.tiles = plan->d_btiles;
-        tl.num_tiles = plan->num_btiles;
-        tl.tile_cap = plan->bwd_cap;
-        tl.adjoint = plan->shape.adjoint;
-        tl.grid = plan->num_btiles;
-        tl.waves = 1;  // dataflow: a power of two, at most one wave per block
-        while (tl.waves < 16 && tl.waves * 2 * 64 <= plan->bwd_cap) tl.waves *= 2;
-        err = hs::launch_backward_tiles(tl, pa, ba, stream);
-        if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (tiles)");
+    if (e->sparse) {
+        std::vector<int64_t> sorted((size_t)std::max<int64_t>(E, 1), 0);  // never an empty (NULL) table
+        std::vector<int32_t> row((size_t)std::max<int64_t>(E, 1), 0);
+        for (int64_t i = 0; i < E; ++i) {
+            sorted[i] = ids[order[i]];
+            row[i] = order[i];
+        }
+        // each adjoint tile's range [lo, hi) of the sorted ids
+        std::vector<int32_t> tile(2 * plan->h_btiles.size(), 0);
+        int64_t covered = 0;
+        for (size_t t = 0; t < plan->h_btiles.size(); ++t) {
+            const hs::TileDesc &td = plan->h_btiles[t];
+            const auto lo = std::lower_bound(sorted.begin(), sorted.begin() + E, td.begin);
+            const auto hi = std::lower_bound(sorted.begin(), sorted.begin() + E, td.begin + td.count);
+            tile[2 * t] = (int32_t)(lo - sorted.begin());
+            tile[2 * t + 1] = (int32_t)(hi - sorted.begin());
+            covered += hi - lo;
+        }
+        if (covered != E) {  // the adjoint's tiles cover every joint of such a plan
+            free_effectors(e);
+            return fail(HS_ERR_DEVICE, "hs_effectors_create: %lld ids outside the adjoint's tiles",
+                        (long long)(E - covered));
+        }
+        if ((err = upload(&e->d_ids, sorted)) != hipSuccess || (err = upload(&e->d_row, row)) != hipSuccess ||
+            (err = upload(&e->d_tile, tile)) != hipSuccess) {
+            free_effectors(e);
+            return fail_hip(err, "hs_effectors_create (upload)");
+        }
+    } else if (N > 0) {
+        // the general adjoint reads a dense seed: the loss gradient kernel
+        // writes the effector rows of this zeroed buffer on every call
+        if ((err = upload(&e->d_ids, ids)) != hipSuccess ||
+            (err = hipMalloc(reinterpret_cast<void **>(&e->d_dense), (size_t)N * 64)) != hipSuccess ||
+            (err = hipMemset(e->d_dense, 0, (size_t)N * 64)) != hipSuccess ||
+            (err = hipDeviceSynchronize()) != hipSuccess) {
+            free_effectors(e);
+            return fail_hip(err, "hs_effectors_create (dense seed)");
+        }
     }
-    if (plan->num_bbig > 0) {
-        tl.tiles = plan->d_bbig;
-        tl.num_tiles = plan->num_bbig;
-        tl.tile_cap = hs::kMaxBwdTileJoints;
-        tl.waves = 16;
-        tl.grid = plan->num_bbig;
-        err = hs::launch_backward_tiles(tl, pa, ba, stream);
-        if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (large tiles)");
-    }
-    err = hs::launch_backward_multipass(mp_launch(plan, plan->bmp), pa, ba, stream);
-    if (err != hipSuccess) return fail_hip(err, "hs_scan_backward (multipass)");
+    *out = e;
     return HS_OK;
+}
+
+void hs_effectors_destroy(hs_effectors *effectors) { free_effectors(effectors); }
+
+int32_t hs_effectors_sparse(const hs_effectors *effectors) { return effectors && effectors->sparse ? 1 : 0; }
+
+hs_status hs_effector_backward(const hs_plan *plan, const hs_effectors *effectors, const hs_pose_src *src,
+                               const float *global, const float *targets, float *grad_quat, float *grad_trans,
+                               float *grad_scale, hipStream_t stream)
+{
+    if (!plan || !effectors) return fail(HS_ERR_INVALID_ARG, "hs_effector_backward: plan and effectors must be non-NULL");
+    if (effectors->plan != plan)
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_backward: the effectors were made for another plan");
+    if (plan->N == 0) return HS_OK;
+    const size_t N = (size_t)plan->N, E = (size_t)effectors->E;
+    if (!global || !grad_quat || !grad_trans || (E > 0 && !targets))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_backward: global, targets, grad_quat and grad_trans must be non-NULL");
+    if (!aligned(global, 16) || !aligned(grad_quat, 16))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_backward: global and grad_quat must be 16-byte aligned");
+    if (!aligned(targets, 4) || !aligned(grad_trans, 4) || (grad_scale && !aligned(grad_scale, 4)))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_backward: targets/grad_trans/grad_scale must be 4-byte aligned");
+    hs::PoseArgs pa;
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, src, pa, ins, false);
+    if (rc != HS_OK) return rc;
+    ins.push_back({global, N * 64, "global"});
+    ins.push_back({targets, E * 12, "targets"});
+    std::vector<Range> outs = {{grad_quat, N * 16, "grad_quat"}, {grad_trans, N * 12, "grad_trans"},
+                               {grad_scale, grad_scale ? N * 12 : 0, "grad_scale"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_effector_backward: cannot select device");
+    hs::BwdArgs ba{};
+    ba.ckpt_k = 1;
+    ba.level = plan->d_level;
+    ba.grad_quat = grad_quat;
+    ba.grad_trans = grad_trans;
+    ba.grad_scale = grad_scale;
+    if (effectors->sparse) {
+        ba.eff_ids = effectors->d_ids;
+        ba.eff_row = effectors->d_row;
+        ba.eff_tile = effectors->d_tile;
+        ba.eff_global = global;
+        ba.eff_target = targets;
+    } else {
+        hipError_t err = hs::launch_effector_grad(plan->N, effectors->E, effectors->d_ids, global, targets,
+                                                  effectors->d_dense, stream);
+        if (err != hipSuccess) return fail_hip(err, "hs_effector_backward (seed)");
+        ba.grad_global = effectors->d_dense;
+    }
+    return run_backward(plan, pa, ba, stream, "hs_effector_backward");
 }
 
 } // extern "C"

@@ -124,6 +124,15 @@ struct BwdArgs {
     float *grad_quat;         // [N,4]
     float *grad_trans;        // [N,3]
     float *grad_scale;        // [N,3] or null
+    // Sparse end-effector loss sum_e |b_e - y_e|^2 (synchronous-round tiles
+    // only; grad_global is then not read): the adjoint's seed is
+    // 2 (b_e - y_e) in the translation column of each listed joint e, with
+    // b_e read from the forward output, and zero elsewhere.
+    const int64_t *eff_ids;   // [E] global joint ids, ascending, distinct; null = dense seed
+    const int32_t *eff_row;   // [E] row of eff_target for each id
+    const int32_t *eff_tile;  // [tiles][2] range [lo, hi) of eff_ids in each adjoint tile
+    const float *eff_global;  // [N,16] forward output
+    const float *eff_target;  // [E,3]
 };
 
 // Kernel launchers (hs_kernels.hip).  Each returns the hipError_t of the

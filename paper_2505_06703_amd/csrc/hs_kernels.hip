@@ -1271,7 +1271,7 @@ __device__ __forceinline__ int owner_read(const int *w)
     return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int WAVES>
+template <int WAVES, bool EFF>
 __global__ void __launch_bounds__(WAVES * kWave)
 bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 {
@@ -1308,10 +1308,35 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             }
             aff_from_trs(q, __builtin_nontemporal_load(t), __builtin_nontemporal_load(t + 1),
                          __builtin_nontemporal_load(t + 2), sx, sy, sz, M);
-            aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
+            if constexpr (EFF) {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) S[k] = 0.0f;
+                aff_store(In + 3 * jl, S);
+            } else {
+                aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
+            }
             aff_store(Ms + 3 * jl, M);
             Ac[jl] = a;
             owner_claim(Own + jl, -1);
+        }
+        if constexpr (EFF) {
+            // the seeds of this tile's end effectors, through the inboxes
+            __syncthreads();
+            const int e1 = bwd.eff_tile[2 * tile + 1];
+            for (int k = bwd.eff_tile[2 * tile] + jl; k < e1; k += WAVES * kWave) {
+                const int64_t e = bwd.eff_ids[k];
+                const float *g = bwd.eff_global + 16 * e;
+                const float *y = bwd.eff_target + 3 * (int64_t)bwd.eff_row[k];
+                float d[12];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    d[4 * r] = d[4 * r + 1] = d[4 * r + 2] = 0.0f;
+                    d[4 * r + 3] = 2.0f * (g[4 * r + 3] - y[r]);
+                }
+                aff_store(In + 3 * (int)(e - td.begin), d);
+            }
+            __syncthreads();
+            if (live) aff_load(In + 3 * jl, S);
         }
         __syncthreads();
         if (a >= 0) owner_claim(Own + a, jl);
@@ -2330,8 +2355,11 @@ hipError_t set_lds_limits()
         if (err != hipSuccess) return err;
     }
     const int bs = (int)backward_sync_lds_bytes(std::min(kMaxSyncTileJoints, WAVES * kWave));
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES>),
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, false>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, bs);
+    if (err == hipSuccess)
+        err = hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bs);
     if (err != hipSuccess || WAVES != 16) return err;
     const void *pk[4] = {reinterpret_cast<const void *>(paper_alg_kernel<1>),
                          reinterpret_cast<const void *>(paper_alg_kernel<2>),
@@ -2608,7 +2636,12 @@ hipError_t launch_bwd_sync_w(const TileLaunch &tl, const PoseArgs &pose, const B
 {
     if (tl.tile_cap > WAVES * kWave) return hipErrorInvalidValue;
     const size_t lds = backward_sync_lds_bytes(tl.tile_cap);
-    hipLaunchKernelGGL((bwd_sync_kernel<WAVES>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose, bwd);
+    if (bwd.eff_ids)
+        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, true>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose,
+                           bwd);
+    else
+        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, false>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose,
+                           bwd);
     return hipGetLastError();
 }
 
@@ -2617,9 +2650,11 @@ hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, con
 {
     if (tl.num_tiles == 0) return hipSuccess;
     if (tl.tile_cap > kMaxBwdTileJoints) return hipErrorInvalidValue;
-    if (tl.tile_cap > kMaxSyncTileJoints || tl.adjoint == kAdjDataflow)
+    if (tl.tile_cap > kMaxSyncTileJoints || tl.adjoint == kAdjDataflow) {
+        if (bwd.eff_ids) return hipErrorInvalidValue;  // sparse seeds: synchronous tiles only
         return bwd.ckpt ? launch_bwd_tiles_w<true>(tl, pose, bwd, stream)
                         : launch_bwd_tiles_w<false>(tl, pose, bwd, stream);
+    }
     // tiles of up to 1024 joints: one joint per thread; the jump products
     // give every G_j on chip, so checkpoints are not read here
     TileLaunch t2 = tl;
@@ -2640,6 +2675,7 @@ hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, c
 {
     if (ml.num_blocks == 0) return hipSuccess;
     if (!ml.G || !ml.aself || (ml.num_anchors > 0 && !ml.S[0])) return hipErrorNotSupported;
+    if (bwd.eff_ids) return hipErrorInvalidValue;  // sparse seeds: synchronous tiles only
     const dim3 blk(kMPWaves * kWave);
     const dim3 grid((ml.num_blocks + kMPWaves - 1) / kMPWaves);
     const size_t lds = (size_t)kMPWaves * kRevWaveFloat4 * sizeof(float4);

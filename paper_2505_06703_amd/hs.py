@@ -40,7 +40,8 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
            "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices",
-           "hs_effector_loss_grad")
+           "hs_effector_loss_grad", "hs_effectors_create", "hs_effectors_destroy", "hs_effectors_sparse",
+           "hs_effector_backward")
 
 
 class HSError(RuntimeError):
@@ -129,6 +130,12 @@ def load_library():
     lib.hs_mesh_destroy.restype = None
     lib.hs_skin_vertices.argtypes = [vp, vp, i32, vp, vp]
     lib.hs_effector_loss_grad.argtypes = [i64, i64, vp, vp, vp, vp, vp]
+    lib.hs_effectors_create.argtypes = [vp, i64, vp, ctypes.POINTER(vp)]
+    lib.hs_effectors_destroy.argtypes = [vp]
+    lib.hs_effectors_destroy.restype = None
+    lib.hs_effectors_sparse.argtypes = [vp]
+    lib.hs_effectors_sparse.restype = i32
+    lib.hs_effector_backward.argtypes = [vp, vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, vp, vp]
     lib.hs_scan_skin_vertices.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp]
     lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
                                             vp, vp, vp, vp, vp, vp, vp]
@@ -478,6 +485,55 @@ def hs_effector_loss_grad(global_, effectors, targets, grad_global, stream=None)
     _check(load_library().hs_effector_loss_grad(N, E, _ptr(effectors), _ptr(global_), _ptr(targets),
                                                 _ptr(grad_global), _stream(stream)))
     return grad_global
+
+
+class Effectors:
+    """A fixed set of end-effector joints of a plan (``hs_effectors_create``;
+    global joint ids, host array, distinct), for ``hs_effector_backward``."""
+
+    def __init__(self, plan, joint_ids):
+        ids = np.ascontiguousarray(np.asarray(joint_ids, np.int64).reshape(-1))
+        h = ctypes.c_void_p()
+        _check(load_library().hs_effectors_create(plan.handle, ids.shape[0], ids.ctypes.data, ctypes.byref(h)))
+        self.handle = h
+        self.plan = plan
+        self.num_effectors = int(ids.shape[0])
+
+    @property
+    def sparse(self):
+        """True when the adjoint forms the seeds on chip (no dense dLoss/dG)."""
+        return bool(load_library().hs_effectors_sparse(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().hs_effectors_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hs_effector_backward(plan, effectors, quat, trans, scale, global_, targets, want_scale=True, grad_quat=None,
+                         grad_trans=None, grad_scale=None, stream=None):
+    """Adjoint of sum_e |b_e - y_e|^2 over ``effectors`` (an ``Effectors``),
+    given the forward output ``global_`` [N,4,4] and targets [E,3]: returns
+    (grad_quat [N,4], grad_trans [N,3], grad_scale [N,3] or None)."""
+    N = plan.num_joints
+    src = _trs_src(plan, quat, trans, scale)
+    _need(global_, "global", (N, 4, 4))
+    _need(targets, "targets", (effectors.num_effectors, 3))
+    dev = quat.device
+    gq = torch.empty((N, 4), device=dev, dtype=torch.float32) if grad_quat is None else _need(grad_quat, "grad_quat", (N, 4))
+    gt = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_trans is None else _need(grad_trans, "grad_trans", (N, 3))
+    gs = None
+    if want_scale:
+        gs = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_scale is None else _need(grad_scale, "grad_scale", (N, 3))
+    _check(load_library().hs_effector_backward(plan.handle, effectors.handle, ctypes.byref(src), _ptr(global_),
+                                               _ptr(targets), _ptr(gq), _ptr(gt), _ptr(gs), _stream(stream)))
+    return gq, gt, gs
 
 
 def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0, want_scale=True,
