@@ -66,6 +66,10 @@ BYTES_PER_JOINT = {
 }
 DOMINANT = {"differentiable": "bwd_sync_kernel",
             "long_chains": "multipass step (mp_local, anchor rounds, mp_out)"}
+# what a --pmc dispatch's kernel name must contain to be the dominant
+# kernel: the differentiable run also times the dense route, whose adjoint
+# is the other instance of the same template
+PMC_MATCH = {"differentiable": ("bwd_sync_kernel<", ", true>")}
 CHUNK = 8  # at least this many forward passes per captured graph replay
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
 MAX_SETS = 64
@@ -120,6 +124,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
     COPY_BYTES in the same run."""
     import csv
     kname = DOMINANT.get(workload, "fwd_tile_kernel")
+    match = PMC_MATCH.get(workload, (kname,))
 
     def per_kernel(path, counter):
         scan, copy = [], None
@@ -128,7 +133,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
         rows.sort(key=lambda r: int(r.get("Dispatch_Id", 0)))
         for row in rows:
             name, kib = row["Kernel_Name"], float(row["Counter_Value"])
-            if kname in name:
+            if all(m in name for m in match):
                 scan.append(kib)
             # the calibration copy (--calibrate-copy) is the first large copy
             # of the run: small setup copies come before it, the 1 GiB
