@@ -1537,49 +1537,122 @@ sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
 }
 
 // Keyframe gradients by gathering instead of scattering: one workgroup per
-// (clip, key) block.  It scans the characters' clip parameters in chunks
-// for the readers of its block (a character reads it as clip A or B, at key
-// k0 or k1 of its frame), lists them in LDS, and each thread sums, for its
+// (clip, key) block.  Its readers are the characters that read the block as
+// clip A or B, at key k0 or k1 of their frame: up to four entries each.
+// Every thread counts the entries of its characters (scan_key_readers) in
+// one pass over the clip parameters; a workgroup prefix sum
+// gives each thread the place of its first entry, and a second pass writes
+// the entries there, so the list is in a fixed order (by thread, then by
+// character) whatever the scheduling.  Each thread then sums, for its
 // joints, every reader's contribution -- (1 - alpha) or alpha s times the
 // adjoint of the key blend, (1 - alpha) or alpha times the weighted dLoss/dt
-// -- then writes its key rows once.  No atomics on the gradients and no
-// zero fill: blocks nobody reads get zeros.
-constexpr int kKeyChars = kSampleBwdThreads;  // characters scanned per pass (one per thread)
-constexpr int kKeyReaders = 4 * kKeyChars;    // at most four entries per character
+// -- and writes its key rows once.  No atomics on the gradients, no zero
+// fill (blocks nobody reads get zeros), and the sums are bitwise
+// reproducible.  A block with more readers than the list holds takes them
+// in rounds of kKeyReaders.
+constexpr int kKeyReaders = 1024;
+
+// Calls emit(entry) for each entry of character c in block (clip, key), in
+// a fixed order; entry = 4 c + 2 X + role (X: clip A or B, role: key k0 or
+// k1 of the character's frame).
+template <typename Emit>
+__device__ __forceinline__ void key_block_entries(const PoseArgs &P, int c, int clip, int key, Emit &&emit)
+{
+    const int cl[2] = {P.clip_a[c], P.clip_b[c]};
+    if (cl[0] != clip && cl[1] != clip) return;  // most characters: two loads
+    int k0, k1;
+    float alpha;
+    if (!sample_frame(P, c, k0, k1, alpha)) return;
+#pragma unroll
+    for (int X = 0; X < 2; ++X) {
+        if (cl[X] != clip) continue;
+        if (k0 == key) emit(4 * c + 2 * X);
+        if (k1 == key) emit(4 * c + 2 * X + 1);
+    }
+}
+
+// This thread's readers of block (clip, key), in a fixed order: characters
+// c = seg + 256 k + thread, segment by segment.  The clip ids of a
+// segment's 16 characters are loaded together (no branch between the
+// loads, so one memory latency per segment), then only the characters
+// that use the clip are examined.
+constexpr int kScanPer = 16;
+
+template <typename Emit>
+__device__ __forceinline__ void scan_key_readers(const PoseArgs &P, int C, int clip, int key, Emit &&emit)
+{
+    for (int seg = 0; seg < C; seg += kSampleBwdThreads * kScanPer) {
+        const int c0 = seg + (int)threadIdx.x;
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int c = c0 + k * kSampleBwdThreads;
+            const int ca = c < C ? P.clip_a[c] : -1;
+            const int cb = c < C ? P.clip_b[c] : -1;
+            m |= (uint32_t)((ca == clip) | (cb == clip)) << k;
+        }
+        while (m) {
+            const int k = __builtin_ctz(m);
+            m &= m - 1;
+            key_block_entries(P, c0 + k * kSampleBwdThreads, clip, key, emit);
+        }
+    }
+}
+
+// Entries [r0, r0 + kKeyReaders) of the block's list, this thread's share
+// (its entries are numbered from `start` in the order of scan_key_readers).
+__device__ __forceinline__ void fill_key_list(const PoseArgs &P, int C, int clip, int key, int start, int r0,
+                                              int *list)
+{
+    int idx = start;
+    const int r1 = r0 + kKeyReaders;
+    scan_key_readers(P, C, clip, key, [&](int e) {
+        if (idx >= r0 && idx < r1) list[idx - r0] = e;
+        ++idx;
+    });
+}
 
 __global__ void __launch_bounds__(kSampleBwdThreads)
 sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
 {
     __shared__ int list[kKeyReaders];
-    __shared__ int count;
+    __shared__ int wsum[kSampleBwdThreads / kWave];
     const int K = P.num_keys, J = P.joints_per_clip;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t nblocks = (int64_t)P.num_clips * K;
     for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
         const int clip = (int)(blk / K), key = (int)(blk % K);
+        // this thread's entries, then their place in the list
+        int mine = 0;
+        scan_key_readers(P, A.C, clip, key, [&](int) { ++mine; });
+        int incl = mine;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        int start = incl - mine, total = 0;
+#pragma unroll
+        for (int w = 0; w < kSampleBwdThreads / kWave; ++w) {
+            if (w < wave) start += wsum[w];
+            total += wsum[w];
+        }
+        const bool once = total <= kKeyReaders;  // uniform in the workgroup
+        if (once) fill_key_list(P, A.C, clip, key, start, 0, list);
+        __syncthreads();
         for (int j0 = 0; j0 < J; j0 += kSampleBwdThreads) {
             const int j = j0 + (int)threadIdx.x;
             float4 gkq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float gkt[3] = {0.0f, 0.0f, 0.0f};
-            for (int c0 = 0; c0 < A.C; c0 += kKeyChars) {
-                if (threadIdx.x == 0) count = 0;
-                __syncthreads();
-                const int cend = min(A.C, c0 + kKeyChars);
-                for (int c = c0 + (int)threadIdx.x; c < cend; c += kSampleBwdThreads) {
-                    const int ca = P.clip_a[c], cb = P.clip_b[c];
-                    if (ca != clip && cb != clip) continue;  // most characters: two loads
-                    int k0, k1;
-                    float alpha;
-                    if (sample_frame(P, c, k0, k1, alpha)) {
-                        const int cl[2] = {ca, cb};
-                        for (int X = 0; X < 2; ++X) {
-                            if (cl[X] != clip) continue;
-                            if (k0 == key) list[atomicAdd(&count, 1)] = 4 * c + 2 * X;
-                            if (k1 == key) list[atomicAdd(&count, 1)] = 4 * c + 2 * X + 1;
-                        }
-                    }
+            for (int r0 = 0; r0 < total; r0 += kKeyReaders) {
+                if (!once) {
+                    __syncthreads();  // the previous round's entries are read
+                    fill_key_list(P, A.C, clip, key, start, r0, list);
+                    __syncthreads();
                 }
-                __syncthreads();
-                const int nr = count;
+                const int nr = min(kKeyReaders, total - r0);
                 for (int e = 0; e < nr; ++e) {
                     const int ent = list[e];
                     const int rc = ent >> 2, X = (ent >> 1) & 1, role = ent & 1;
@@ -1600,7 +1673,6 @@ sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
 #pragma unroll
                     for (int i = 0; i < 3; ++i) gkt[i] = fmaf(ft, o.gt[i], gkt[i]);
                 }
-                __syncthreads();  // the list is rewritten by the next chunk
             }
             if (j < J) {
                 const int64_t row = blk * J + j;
@@ -1612,6 +1684,7 @@ sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
                 }
             }
         }
+        __syncthreads();  // the list and the wave sums are rewritten by the next block
     }
 }
 

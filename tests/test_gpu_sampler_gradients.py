@@ -155,3 +155,35 @@ def test_clip_parameters_are_recovered_from_effector_targets():
                                      fps=fps, iters=200, lr=0.002)
     assert losses[-1] < 0.05 * losses[0], (losses[0], losses[-1])
     assert np.abs(w.cpu().numpy() - true_w).max() < 0.1
+
+
+def test_keyframe_gather_with_more_readers_than_one_list():
+    """1500 characters of 8 joints on two clips, most of them reading the
+    same two keys of clip 0 as both clip A and clip B: a (clip, key) block
+    gets about 3000 entries, more than one reader list holds, so the gather
+    takes them in rounds; another 1100 characters share a block of clip 1."""
+    rng = np.random.default_rng(45)
+    C, n, clips, keys, fps = 2600, 8, 2, 5, 30.0
+    offsets = (np.arange(C + 1) * n).astype(np.int64)
+    parents = np.tile(np.arange(-1, n - 1, dtype=np.int32), C)
+    kq = wl.random_quats(rng, clips * keys * n, 0.6).reshape(clips, keys, n, 4).astype(np.float32)
+    kt = wl.random_offsets(rng, clips * keys * n).reshape(clips, keys, n, 3).astype(np.float32)
+    ca = np.zeros(C, np.int32)
+    ca[1500:] = 1
+    cb = ca.copy()
+    cb[::7] = 1 - ca[::7]
+    tau = ((2 + rng.uniform(0.2, 0.8, C)) / fps).astype(np.float32)
+    w = rng.uniform(0.1, 0.9, C).astype(np.float32)
+    gq = rng.standard_normal((C * n, 4)).astype(np.float32)
+    gt = rng.standard_normal((C * n, 3)).astype(np.float32)
+    plan = hs.Plan(offsets, parents)
+    lib = hs.ClipLibrary(dev(kq), dev(kt), fps)
+    got = hs.hs_pose_sample_backward(plan, lib, dev(ca), dev(cb), dev(tau), dev(w), dev(gq), dev(gt))
+    again = hs.hs_pose_sample_backward(plan, lib, dev(ca), dev(cb), dev(tau), dev(w), dev(gq), dev(gt))
+    torch.cuda.synchronize()
+    ref = pose_sample_backward(offsets, kq, kt, ca, cb, tau, w, gq, gt, fps)
+    for name, g, r in zip(("key_quat", "key_trans", "time", "weight"), got, ref):
+        close(g.cpu().numpy(), r, name)
+    # the gather's order is fixed: a second call is bitwise equal
+    for g, h in zip(got, again):
+        assert torch.equal(g, h)
