@@ -635,6 +635,8 @@ def sampler_grad_bench(args):
         sets.append(dict(q=torch.empty((N, 4), device="cuda:0"), t=torch.empty((N, 3), device="cuda:0"),
                          G=torch.empty((N, 4, 4), device="cuda:0"), gG=up(W),
                          gq=torch.empty((N, 4), device="cuda:0"), gt=torch.empty((N, 3), device="cuda:0")))
+    # each joint's reverse step stored once, the key gather reads it
+    ws = hs.sample_backward_workspace(plan, "cuda:0")
 
     def step(k, ev=None):
         st = sets[k % n_sets]
@@ -644,7 +646,7 @@ def sampler_grad_bench(args):
                             grad_trans=st["gt"])
         if ev is not None:
             ev[0].record()
-        out = hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, st["gq"], st["gt"])
+        out = hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, st["gq"], st["gt"], workspace=ws)
         if ev is not None:
             ev[1].record()
         return out
@@ -659,11 +661,21 @@ def sampler_grad_bench(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    # the same reverse mode without the workspace (the gather recomputes
+    # each reader's reverse step), for comparison
+    st = sets[0]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, st["gq"], st["gt"])
+    e1.record()
+    torch.cuda.synchronize()
+    recompute_ms = e0.elapsed_time(e1) / 10
     # algorithmic bytes of one reverse-mode launch: dLoss/dq and dLoss/dt
-    # read, the key gradients zeroed and written back once, per-character
-    # parameters read and gradients written
+    # read, the key gradients written once, per-character parameters read
+    # and gradients written
     keys = x["key_quat"].nbytes + x["key_trans"].nbytes
-    sbytes = N * 28 + 2 * keys + C * 24
+    sbytes = N * 28 + keys + C * 24
     achieved = sbytes / (kms * 1e-3) / 1e9
     print(json.dumps({
         "metric": "joint transforms/s through sampler, scan, adjoint and sampler reverse mode on 1 GPU",
@@ -674,7 +686,8 @@ def sampler_grad_bench(args):
                    "keys": int(x["key_quat"].shape[1]), "input_sets": n_sets},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sample_bwd_kernel",
-                     "kernel_ms": kms, "algorithmic_bytes_per_launch": sbytes}}), flush=True)
+                     "kernel_ms": kms, "algorithmic_bytes_per_launch": sbytes,
+                     "recompute_gather_ms": recompute_ms}}), flush=True)
 
 
 def device_copy_gbs(torch, nbytes=1 << 30, reps=10):

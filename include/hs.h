@@ -243,10 +243,18 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
  * from their switching points); d alpha / d time = fps.  Any output may be
  * NULL (not computed).  A character with an invalid clip id or a
  * non-finite time gets NaN time and weight gradients and adds nothing to
- * the keys.  Asynchronous on stream; allocates nothing. */
+ * the keys.  workspace: NULL, or caller-owned device memory of 32 bytes per
+ * joint ([N,2,4] fp32, 16-byte aligned, not overlapping any other array):
+ * with it each joint's reverse step runs once (storing the adjoints of its
+ * two clips' unnormalised key blends there) and the key gradients are
+ * gathered from it; without it the gather recomputes each reader's reverse
+ * step.  The results agree up to rounding (each route is bitwise
+ * reproducible on its own).  Calls that
+ * share a workspace must not overlap.  Asynchronous on stream; allocates
+ * nothing. */
 hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
                                   const float *grad_quat, const float *grad_trans, float *grad_key_quat,
-                                  float *grad_key_trans, float *grad_time, float *grad_weight,
+                                  float *grad_key_trans, float *grad_time, float *grad_weight, float *workspace,
                                   hipStream_t stream);
 
 /* ------------------------------------------------------------------------

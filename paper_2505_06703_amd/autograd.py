@@ -71,8 +71,9 @@ class HSSample(torch.autograd.Function):
         gq = torch.zeros_like(time.new_empty((ctx.plan.num_joints, 4))) if grad_q is None else grad_q.contiguous()
         gt = torch.zeros_like(time.new_empty((ctx.plan.num_joints, 3))) if grad_t is None else grad_t.contiguous()
         want_keys = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        ws = hs.sample_backward_workspace(ctx.plan, time.device) if want_keys else None
         gkq, gkt, gtime, gw = hs.hs_pose_sample_backward(ctx.plan, lib, clip_a, clip_b, time, weight, gq, gt,
-                                                         want_keys=want_keys)
+                                                         want_keys=want_keys, workspace=ws)
         return None, gkq, gkt, None, None, gtime, gw, None
 
 

@@ -1275,7 +1275,8 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
 
 hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
                                   const float *grad_quat, const float *grad_trans, float *grad_key_quat,
-                                  float *grad_key_trans, float *grad_time, float *grad_weight, hipStream_t stream)
+                                  float *grad_key_trans, float *grad_time, float *grad_weight, float *workspace,
+                                  hipStream_t stream)
 {
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_pose_sample_backward: plan is NULL");
     hs_pose_src src{};
@@ -1290,20 +1291,23 @@ hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, c
     if (N > 0 && (!grad_quat || !grad_trans))
         return fail(HS_ERR_INVALID_ARG, "hs_pose_sample_backward: grad_quat and grad_trans must be non-NULL");
     if (!aligned(grad_quat, 16) || !aligned(grad_trans, 4) || !aligned(grad_key_quat, 4) ||
-        !aligned(grad_key_trans, 4) || !aligned(grad_time, 4) || !aligned(grad_weight, 4))
-        return fail(HS_ERR_INVALID_ARG, "hs_pose_sample_backward: grad_quat must be 16-byte aligned, the rest 4");
+        !aligned(grad_key_trans, 4) || !aligned(grad_time, 4) || !aligned(grad_weight, 4) ||
+        !aligned(workspace, 16))
+        return fail(HS_ERR_INVALID_ARG,
+                    "hs_pose_sample_backward: grad_quat and workspace must be 16-byte aligned, the rest 4");
     ins.push_back({grad_quat, N * 16, "grad_quat"});
     ins.push_back({grad_trans, N * 12, "grad_trans"});
     const size_t keys = (size_t)lib->num_clips * lib->num_keys * lib->joints_per_clip;
     std::vector<Range> outs = {{grad_key_quat, grad_key_quat ? keys * 16 : 0, "grad_key_quat"},
                                {grad_key_trans, grad_key_trans ? keys * 12 : 0, "grad_key_trans"},
                                {grad_time, grad_time ? C * 4 : 0, "grad_time"},
-                               {grad_weight, grad_weight ? C * 4 : 0, "grad_weight"}};
+                               {grad_weight, grad_weight ? C * 4 : 0, "grad_weight"},
+                               {workspace, workspace ? N * 32 : 0, "workspace"}};
     if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_pose_sample_backward: cannot select device");
     hs::SampleBwdArgs A{grad_quat, grad_trans, grad_key_quat, grad_key_trans, grad_time, grad_weight,
-                        (int32_t)plan->C};
+                        (int32_t)plan->C, reinterpret_cast<float4 *>(workspace)};
     hipError_t err = hs::launch_pose_sample_backward(pa, A, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_pose_sample_backward");
     return HS_OK;

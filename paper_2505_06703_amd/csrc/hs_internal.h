@@ -166,6 +166,10 @@ struct SampleBwdArgs {
     float *grad_time;          // [C] or null
     float *grad_weight;        // [C] or null
     int32_t C;
+    // [N][2] adjoints of each joint's two unnormalised key blends, or null:
+    // when given, the time/weight kernel stores them and the key gather
+    // reads them instead of recomputing each reader's reverse step
+    float4 *ws;
 };
 hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs &A, hipStream_t stream);
 

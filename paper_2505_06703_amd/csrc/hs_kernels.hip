@@ -1525,6 +1525,10 @@ sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
             joint_reverse(P, A, base + j, j, clip, k0, k1, alpha, w, o);
             g_alpha += o.g_alpha;
             g_w += o.g_w;
+            if (A.ws) {
+                A.ws[2 * (base + j)] = o.vb[0];
+                A.ws[2 * (base + j) + 1] = o.vb[1];
+            }
         }
         const float sum_a = block_sum(g_alpha, red);
         const float sum_w = block_sum(g_w, red);
@@ -1552,9 +1556,9 @@ sample_bwd_kernel(PoseArgs P, SampleBwdArgs A)
 // in rounds of kKeyReaders.
 constexpr int kKeyReaders = 1024;
 
-// Calls emit(entry) for each entry of character c in block (clip, key), in
-// a fixed order; entry = 4 c + 2 X + role (X: clip A or B, role: key k0 or
-// k1 of the character's frame).
+// Calls emit(entry, alpha) for each entry of character c in block (clip,
+// key), in a fixed order; entry = 4 c + 2 X + role (X: clip A or B, role:
+// key k0 or k1 of the character's frame), alpha the frame's fraction.
 template <typename Emit>
 __device__ __forceinline__ void key_block_entries(const PoseArgs &P, int c, int clip, int key, Emit &&emit)
 {
@@ -1566,8 +1570,8 @@ __device__ __forceinline__ void key_block_entries(const PoseArgs &P, int c, int 
 #pragma unroll
     for (int X = 0; X < 2; ++X) {
         if (cl[X] != clip) continue;
-        if (k0 == key) emit(4 * c + 2 * X);
-        if (k1 == key) emit(4 * c + 2 * X + 1);
+        if (k0 == key) emit(4 * c + 2 * X, alpha);
+        if (k1 == key) emit(4 * c + 2 * X + 1, alpha);
     }
 }
 
@@ -1599,23 +1603,51 @@ __device__ __forceinline__ void scan_key_readers(const PoseArgs &P, int C, int c
     }
 }
 
+// The block's reader list in LDS.  With the workspace (WS) each entry also
+// carries the reader's first joint, joint count and its two factors, the
+// key-blend factor ((1 - alpha), or alpha, which the k1 role multiplies by
+// the arc sign) and the translation factor ((1 - alpha) or alpha, times
+// 1 - w or w), so that summing an entry takes two loads.
+template <bool WS>
+struct KeyList {
+    int entry[kKeyReaders];
+    int64_t base[WS ? kKeyReaders : 1];
+    int count[WS ? kKeyReaders : 1];
+    float fq[WS ? kKeyReaders : 1], ft[WS ? kKeyReaders : 1];
+};
+
 // Entries [r0, r0 + kKeyReaders) of the block's list, this thread's share
 // (its entries are numbered from `start` in the order of scan_key_readers).
+template <bool WS>
 __device__ __forceinline__ void fill_key_list(const PoseArgs &P, int C, int clip, int key, int start, int r0,
-                                              int *list)
+                                              KeyList<WS> &L)
 {
     int idx = start;
     const int r1 = r0 + kKeyReaders;
-    scan_key_readers(P, C, clip, key, [&](int e) {
-        if (idx >= r0 && idx < r1) list[idx - r0] = e;
+    scan_key_readers(P, C, clip, key, [&](int e, float alpha) {
+        if (idx >= r0 && idx < r1) {
+            const int i = idx - r0;
+            L.entry[i] = e;
+            if constexpr (WS) {
+                const int c = e >> 2, X = (e >> 1) & 1, role = e & 1;
+                const int64_t b = P.offsets[c];
+                L.base[i] = b;
+                L.count[i] = (int)(P.offsets[c + 1] - b);
+                const float w = P.weight[c];
+                const float a = role == 0 ? 1.0f - alpha : alpha;
+                L.fq[i] = a;
+                L.ft[i] = a * (X ? w : 1.0f - w);
+            }
+        }
         ++idx;
     });
 }
 
+template <bool WS>
 __global__ void __launch_bounds__(kSampleBwdThreads)
 sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
 {
-    __shared__ int list[kKeyReaders];
+    __shared__ KeyList<WS> L;
     __shared__ int wsum[kSampleBwdThreads / kWave];
     const int K = P.num_keys, J = P.joints_per_clip;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -1624,7 +1656,7 @@ sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
         const int clip = (int)(blk / K), key = (int)(blk % K);
         // this thread's entries, then their place in the list
         int mine = 0;
-        scan_key_readers(P, A.C, clip, key, [&](int) { ++mine; });
+        scan_key_readers(P, A.C, clip, key, [&](int, float) { ++mine; });
         int incl = mine;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
@@ -1640,38 +1672,65 @@ sample_bwd_keys_kernel(PoseArgs P, SampleBwdArgs A)
             total += wsum[w];
         }
         const bool once = total <= kKeyReaders;  // uniform in the workgroup
-        if (once) fill_key_list(P, A.C, clip, key, start, 0, list);
+        if (once) fill_key_list<WS>(P, A.C, clip, key, start, 0, L);
         __syncthreads();
         for (int j0 = 0; j0 < J; j0 += kSampleBwdThreads) {
             const int j = j0 + (int)threadIdx.x;
             float4 gkq = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float gkt[3] = {0.0f, 0.0f, 0.0f};
+            // a reader of this block as its k1 has k0 = key - 1: the arc sign
+            // of its clip blend depends on the two key rows alone (the same
+            // fp64 decision as the reverse step's)
+            float s1 = 1.0f;
+            if (WS && j < J) {
+                const float4 *kq = reinterpret_cast<const float4 *>(P.key_quat);
+                const float4 a = kq[((int64_t)clip * K + (key == 0 ? K - 1 : key - 1)) * J + j];
+                const float4 b = kq[((int64_t)clip * K + key) * J + j];
+                double d = (double)a.x * (double)b.x;
+                d = d + (double)a.y * (double)b.y;
+                d = d + (double)a.z * (double)b.z;
+                d = d + (double)a.w * (double)b.w;
+                s1 = d < 0.0 ? -1.0f : 1.0f;
+            }
             for (int r0 = 0; r0 < total; r0 += kKeyReaders) {
                 if (!once) {
                     __syncthreads();  // the previous round's entries are read
-                    fill_key_list(P, A.C, clip, key, start, r0, list);
+                    fill_key_list<WS>(P, A.C, clip, key, start, r0, L);
                     __syncthreads();
                 }
                 const int nr = min(kKeyReaders, total - r0);
                 for (int e = 0; e < nr; ++e) {
-                    const int ent = list[e];
-                    const int rc = ent >> 2, X = (ent >> 1) & 1, role = ent & 1;
-                    const int64_t base = P.offsets[rc];
-                    if (j >= (int)(P.offsets[rc + 1] - base)) continue;  // the character has no joint j
-                    int k0, k1;
-                    float alpha;
-                    sample_frame(P, rc, k0, k1, alpha);
-                    const int cl[2] = {P.clip_a[rc], P.clip_b[rc]};
-                    JointRev o;
-                    joint_reverse(P, A, base + j, j, cl, k0, k1, alpha, P.weight[rc], o);
-                    // X is only known at run time: select, not index (no scratch)
-                    const float4 vb = X ? o.vb[1] : o.vb[0];
-                    const float sx = X ? o.sX[1] : o.sX[0], tw = X ? o.tw[1] : o.tw[0];
-                    const float f = role == 0 ? 1.0f - alpha : alpha * sx;
-                    const float ft = (role == 0 ? 1.0f - alpha : alpha) * tw;
-                    fma4(gkq, f, vb);
+                    const int ent = L.entry[e];
+                    const int X = (ent >> 1) & 1, role = ent & 1;
+                    if constexpr (WS) {
+                        // the reader's reverse step, stored by the time/weight kernel
+                        if (j >= L.count[e]) continue;  // the character has no joint j
+                        const int64_t g = L.base[e] + j;
+                        const float4 vb = A.ws[2 * g + X];
+                        const float f = role == 0 ? L.fq[e] : L.fq[e] * s1;
+                        const float ft = L.ft[e];
+                        fma4(gkq, f, vb);
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) gkt[i] = fmaf(ft, o.gt[i], gkt[i]);
+                        for (int i = 0; i < 3; ++i) gkt[i] = fmaf(ft, A.grad_trans[3 * g + i], gkt[i]);
+                    } else {
+                        const int rc = ent >> 2;
+                        const int64_t base = P.offsets[rc];
+                        if (j >= (int)(P.offsets[rc + 1] - base)) continue;  // the character has no joint j
+                        int k0, k1;
+                        float alpha;
+                        sample_frame(P, rc, k0, k1, alpha);
+                        const int cl[2] = {P.clip_a[rc], P.clip_b[rc]};
+                        JointRev o;
+                        joint_reverse(P, A, base + j, j, cl, k0, k1, alpha, P.weight[rc], o);
+                        // X is only known at run time: select, not index (no scratch)
+                        const float4 vb = X ? o.vb[1] : o.vb[0];
+                        const float sx = X ? o.sX[1] : o.sX[0], tw = X ? o.tw[1] : o.tw[0];
+                        const float f = role == 0 ? 1.0f - alpha : alpha * sx;
+                        const float ft = (role == 0 ? 1.0f - alpha : alpha) * tw;
+                        fma4(gkq, f, vb);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) gkt[i] = fmaf(ft, o.gt[i], gkt[i]);
+                    }
                 }
             }
             if (j < J) {
@@ -2575,14 +2634,20 @@ hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const Po
 hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs &A, hipStream_t stream)
 {
     hipError_t err = hipSuccess;
-    if (A.C > 0 && (A.grad_time || A.grad_weight)) {
-        hipLaunchKernelGGL(sample_bwd_kernel, dim3((unsigned)A.C), dim3(kSampleBwdThreads), 0, stream, pose, A);
+    const bool keys = A.grad_key_quat || A.grad_key_trans;
+    SampleBwdArgs a = A;
+    if (!keys) a.ws = nullptr;  // nothing would read it
+    if (A.C > 0 && (A.grad_time || A.grad_weight || a.ws)) {
+        hipLaunchKernelGGL(sample_bwd_kernel, dim3((unsigned)A.C), dim3(kSampleBwdThreads), 0, stream, pose, a);
         if ((err = hipGetLastError()) != hipSuccess) return err;
     }
-    if (A.grad_key_quat || A.grad_key_trans) {
+    if (keys) {
         const int64_t blocks = (int64_t)pose.num_clips * pose.num_keys;
-        hipLaunchKernelGGL(sample_bwd_keys_kernel, dim3((unsigned)std::min<int64_t>(blocks, 1 << 20)),
-                           dim3(kSampleBwdThreads), 0, stream, pose, A);
+        const dim3 grid((unsigned)std::min<int64_t>(blocks, 1 << 20));
+        if (a.ws)
+            hipLaunchKernelGGL(sample_bwd_keys_kernel<true>, grid, dim3(kSampleBwdThreads), 0, stream, pose, a);
+        else
+            hipLaunchKernelGGL(sample_bwd_keys_kernel<false>, grid, dim3(kSampleBwdThreads), 0, stream, pose, a);
         err = hipGetLastError();
     }
     return err;

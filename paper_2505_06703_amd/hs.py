@@ -138,7 +138,7 @@ def load_library():
     lib.hs_effector_backward.argtypes = [vp, vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, vp, vp]
     lib.hs_scan_skin_vertices.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp]
     lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
-                                            vp, vp, vp, vp, vp, vp, vp]
+                                            vp, vp, vp, vp, vp, vp, vp, vp]
     lib.hs_plan_destroy.argtypes = [vp]
     lib.hs_plan_destroy.restype = None
     lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
@@ -327,11 +327,18 @@ def hs_pose_sample(plan, clips, clip_a, clip_b, time, weight, quat_out=None, tra
     return q, t
 
 
+def sample_backward_workspace(plan, device):
+    """Workspace for ``hs_pose_sample_backward`` ([N,2,4] fp32): with it
+    each joint's reverse step runs once."""
+    return torch.empty((plan.num_joints, 2, 4), device=device, dtype=torch.float32)
+
+
 def hs_pose_sample_backward(plan, clips, clip_a, clip_b, time, weight, grad_quat, grad_trans,
-                            want_keys=True, stream=None):
+                            want_keys=True, workspace=None, stream=None):
     """Reverse mode of the Simulation step -> (grad_key_quat [K,T,J,4],
     grad_key_trans [K,T,J,3], grad_time [C], grad_weight [C]); the key
-    gradients are None when ``want_keys`` is false."""
+    gradients are None when ``want_keys`` is false.  ``workspace``: None
+    or ``sample_backward_workspace(plan, device)``."""
     N, C = plan.num_joints, plan.num_characters
     _need(grad_quat, "grad_quat", (N, 4))
     _need(grad_trans, "grad_trans", (N, 3))
@@ -340,10 +347,12 @@ def hs_pose_sample_backward(plan, clips, clip_a, clip_b, time, weight, grad_quat
     gkt = torch.empty_like(clips.key_trans) if want_keys else None
     gtime = torch.empty((C,), device=dev, dtype=torch.float32)
     gw = torch.empty((C,), device=dev, dtype=torch.float32)
+    if workspace is not None:
+        _need(workspace, "workspace", (N, 2, 4))
     params = _clip_params(plan, clip_a, clip_b, time, weight)
     _check(load_library().hs_pose_sample_backward(plan.handle, ctypes.byref(clips.c), ctypes.byref(params),
                                                   _ptr(grad_quat), _ptr(grad_trans), _ptr(gkq), _ptr(gkt),
-                                                  _ptr(gtime), _ptr(gw), _stream(stream)))
+                                                  _ptr(gtime), _ptr(gw), _ptr(workspace), _stream(stream)))
     return gkq, gkt, gtime, gw
 
 

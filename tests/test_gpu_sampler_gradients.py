@@ -35,6 +35,15 @@ def close(got, ref, what):
     assert err <= tol, f"{what}: {err:.3e} > {tol:.3e}"
 
 
+def same_rounding(g, h, what):
+    """Two GPU routes to the same sums: equal up to the rounding of the
+    reverse step, which the compiler may contract differently in the two
+    kernels that inline it."""
+    tol = 1e-5 * max(1.0, float(h.abs().max()))
+    err = float((g - h).abs().max())
+    assert err <= tol, f"{what}: {err:.3e} > {tol:.3e}"
+
+
 def clip_inputs(b):
     x = b.extra
     return (dev(x["key_quat"]), dev(x["key_trans"]), dev(x["clip_a"]), dev(x["clip_b"]), dev(x["time"]),
@@ -65,6 +74,27 @@ def test_reverse_mode_matches_oracle():
     torch.cuda.synchronize()
     close(gtime.cpu().numpy(), ref[2], "time without keys")
     close(gw.cpu().numpy(), ref[3], "weight without keys")
+    # with a workspace each joint's reverse step runs once (in the time and
+    # weight kernel); the gather reads it
+    ws = hs.sample_backward_workspace(plan, DEV)
+    with_ws = hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, dev(gq), dev(gt), workspace=ws)
+    torch.cuda.synchronize()
+    for name, g, h, r in zip(("key_quat", "key_trans", "time", "weight"), got, with_ws, ref):
+        close(h.cpu().numpy(), r, f"{name} with workspace")
+        same_rounding(h, g, f"{name} with and without workspace")
+
+
+def test_workspace_must_not_overlap():
+    b = wl.fused_sample(num_characters=2)
+    N = b.num_joints
+    plan = hs.Plan(b.offsets, b.parents)
+    kq, kt, ca, cb, tm, wt, fps = clip_inputs(b)
+    lib = hs.ClipLibrary(kq, kt, fps)
+    base = torch.zeros(N * 8, device=DEV)
+    gq = base[:N * 4].view(N, 4)
+    ws = base.view(N, 2, 4)
+    with pytest.raises(hs.HSError):
+        hs.hs_pose_sample_backward(plan, lib, ca, cb, tm, wt, gq, torch.zeros((N, 3), device=DEV), workspace=ws)
 
 
 def test_invalid_clip_gives_nan_and_no_key_contribution():
@@ -79,7 +109,12 @@ def test_invalid_clip_gives_nan_and_no_key_contribution():
     ca_bad[1] = 10_000
     lib = hs.ClipLibrary(kq, kt, fps)
     gkq, gkt, gtime, gw = hs.hs_pose_sample_backward(plan, lib, ca_bad, cb, tm, wt, dev(gq), dev(gt))
+    ws = hs.sample_backward_workspace(plan, DEV)
+    with_ws = hs.hs_pose_sample_backward(plan, lib, ca_bad, cb, tm, wt, dev(gq), dev(gt), workspace=ws)
     torch.cuda.synchronize()
+    for g, h in zip((gkq, gkt, gtime, gw), with_ws):  # NaN where NaN
+        assert torch.equal(torch.isnan(g), torch.isnan(h))
+        same_rounding(torch.nan_to_num(g), torch.nan_to_num(h), "invalid clip, with and without workspace")
     assert torch.isnan(gtime[1]) and torch.isnan(gw[1])
     assert torch.isfinite(gtime[[0, 2]]).all() and torch.isfinite(gkq).all()
     # the keys hold exactly the other two characters' contributions
@@ -180,10 +215,17 @@ def test_keyframe_gather_with_more_readers_than_one_list():
     lib = hs.ClipLibrary(dev(kq), dev(kt), fps)
     got = hs.hs_pose_sample_backward(plan, lib, dev(ca), dev(cb), dev(tau), dev(w), dev(gq), dev(gt))
     again = hs.hs_pose_sample_backward(plan, lib, dev(ca), dev(cb), dev(tau), dev(w), dev(gq), dev(gt))
+    ws = hs.sample_backward_workspace(plan, DEV)
+    w1 = hs.hs_pose_sample_backward(plan, lib, dev(ca), dev(cb), dev(tau), dev(w), dev(gq), dev(gt), workspace=ws)
+    w2 = hs.hs_pose_sample_backward(plan, lib, dev(ca), dev(cb), dev(tau), dev(w), dev(gq), dev(gt), workspace=ws)
     torch.cuda.synchronize()
     ref = pose_sample_backward(offsets, kq, kt, ca, cb, tau, w, gq, gt, fps)
     for name, g, r in zip(("key_quat", "key_trans", "time", "weight"), got, ref):
         close(g.cpu().numpy(), r, name)
-    # the gather's order is fixed: a second call is bitwise equal
+    # the gather's order is fixed: repeated calls are bitwise equal, with or
+    # without the workspace
     for g, h in zip(got, again):
         assert torch.equal(g, h)
+    for name, g, h, r in zip(("key_quat", "key_trans", "time", "weight"), w1, w2, ref):
+        assert torch.equal(g, h)
+        close(g.cpu().numpy(), r, f"{name} with workspace")
