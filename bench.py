@@ -5,9 +5,10 @@ Default workload: the deep-skeleton forward scan, 4096 characters x 1024
 joints (a 64-joint humanoid plus four 240-joint chains, depth 246), fp32.
 A step is one hs_scan_forward over the whole batch with every input already
 resident in HBM, replayed from a HIP graph that holds eight such passes
-(one light host call per eight steps, so launches run back to back).  Two input/output
-sets alternate between steps so that the 256 MB last-level cache never holds
-the next step's data.
+(one light host call per eight steps, so launches run back to back).  The
+steps cycle through as many input/output sets as it takes to touch at least
+1 GiB per cycle, so that the 256 MB last-level cache never holds the next
+step's data.
 
 Prints one JSON line with the throughput in joint transforms per second, the
 roofline of the dominant kernel (algorithmic bytes / mean kernel duration
@@ -19,9 +20,12 @@ against FP64.
                     [--no-autotune]
 
 Other workloads (parity presets, not the headline line): plain_scan,
-heterogeneous (the batched form), fused_sample, differentiable (forward +
+heterogeneous (the batched form), fused_sample and fused_sample_instanced
+(clip sampling + scan + skin), differentiable (forward + end-effector
 adjoint), long_chains (64 chains of 65536 joints: the multipass path, whose
-step is several kernels, all counted in kernel_ms).
+step is several kernels, all counted in kernel_ms), mesh_skinning (vertex
+skinning, two calls and one pass), sample_gradients (gradients through the
+sampler); --depth-sweep runs the paper's depth experiment.
 """
 import argparse
 import hashlib
@@ -235,7 +239,7 @@ class Workload:
         self.sets = [first] + [make_set(k) for k in range(1, n_sets)]
         self.set_bytes = set_bytes
         # forward-only steps replay captured HIP graphs: CHUNK passes that
-        # alternate the two input sets in one graph (one light host call per
+        # cycle through the input sets in one graph (one light host call per
         # CHUNK steps, so launches run back to back), plus one single-pass
         # graph per set for a remainder
         self.graphs = None
