@@ -64,16 +64,17 @@ BYTES_PER_JOINT = {
     # instanced: parents and inverse binds are the one skeleton's (256 rows,
     # cache-resident), so only the skin is per joint in HBM
     "fused_sample_instanced": 64,
-    # end-effector adjoint: read quat, trans, scale, parent 44, write
-    # grad_quat 16 + grad_trans 12 (+ 24 B per effector: b_e and y_e)
-    "differentiable": 72,
+    # forward scan and end-effector adjoint in one launch: read quat,
+    # trans, scale, parent 44, write G 64, grad_quat 16 + grad_trans 12
+    # (+ 12 B of targets per effector)
+    "differentiable": 136,
 }
 DOMINANT = {"differentiable": "bwd_sync_kernel",
             "long_chains": "multipass step (mp_local, anchor rounds, mp_out)"}
 # what a --pmc dispatch's kernel name must contain to be the dominant
 # kernel: the differentiable run also times the dense route, whose adjoint
 # is the other instance of the same template
-PMC_MATCH = {"differentiable": ("bwd_sync_kernel<", ", true>")}
+PMC_MATCH = {"differentiable": ("bwd_sync_kernel<", ", 2>")}
 CHUNK = 8  # at least this many forward passes per captured graph replay
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
 MAX_SETS = 64
@@ -258,9 +259,10 @@ class Workload:
             self.chunk = S * max(1, -(-CHUNK // S))
             self.chunk_graph = hs.ForwardGraph.sequence(self.plan, [calls[k % S] for k in range(self.chunk)])
         else:
-            # the whole differentiable step (forward, end-effector adjoint)
-            # captured for CHUNK steps over the sets: nothing in it allocates
-            # or synchronises; the dense route likewise
+            # the whole differentiable step (one launch: forward scan and
+            # end-effector adjoint per tile) captured for CHUNK steps over the
+            # sets: nothing in it allocates or synchronises; the two-call and
+            # the dense routes likewise
             S = len(self.sets)
             self.chunk = S * max(1, -(-CHUNK // S))
             side = torch.cuda.Stream()
@@ -268,6 +270,7 @@ class Workload:
             with torch.cuda.stream(side):
                 for k in range(S):
                     self.diff_step(self.sets[k])
+                    self.two_call_step(self.sets[k])
                     self.dense_step(self.sets[k])
             torch.cuda.current_stream().wait_stream(side)
             torch.cuda.synchronize()
@@ -279,6 +282,10 @@ class Workload:
             with torch.cuda.graph(self.dense_graph):
                 for k in range(self.chunk):
                     self.dense_step(self.sets[k % S])
+            self.two_call_graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.two_call_graph):
+                for k in range(self.chunk):
+                    self.two_call_step(self.sets[k % S])
 
     def run(self, steps):
         """`steps` steps from set 0 on, from captured graphs of `chunk` steps
@@ -307,8 +314,15 @@ class Workload:
 
     def diff_step(self, s):
         """Forward and the adjoint of loss = sum over effectors |b_e - y_e|^2
-        on set s (differentiable workload): the adjoint forms the loss
-        gradient at the effectors itself, from the forward's output."""
+        on set s (differentiable workload), in one launch: each adjoint tile
+        scans its characters, writes G, forms the loss gradient at the
+        effectors and runs the reverse rounds."""
+        self.hs.hs_effector_step(self.plan, self.effset, s["q"], s["t"], s["s"], self.target, global_out=s["G"],
+                                 want_scale=False, grad_quat=s["gq"], grad_trans=s["gt"])
+
+    def two_call_step(self, s):
+        """The same step as two launches: the forward, then the adjoint
+        seeded from the forward's output."""
         hs = self.hs
         hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
         hs.hs_effector_backward(self.plan, self.effset, s["q"], s["t"], s["s"], s["G"], self.target,
@@ -324,28 +338,27 @@ class Workload:
         hs.hs_scan_backward(self.plan, s["q"], s["t"], s["s"], self.gG, want_scale=False,
                             grad_quat=s["gq"], grad_trans=s["gt"])
 
-    def dense_step_ms(self, reps=5):
-        """Mean time per step of the dense route (captured like the step)."""
+    def graph_step_ms(self, graph, reps=5):
+        """Mean time per step of a captured comparison route."""
         torch = self.torch
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        self.dense_graph.replay()
+        graph.replay()
         torch.cuda.synchronize()
         e0.record()
         for _ in range(reps):
-            self.dense_graph.replay()
+            graph.replay()
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / (reps * self.chunk)
 
     def backward_ms(self, reps=50):
-        """Mean duration of the adjoint launch alone, back to back."""
+        """Mean duration of the step's one launch, back to back."""
         torch, s = self.torch, self.sets[0]
         self.diff_step(s)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            self.hs.hs_effector_backward(self.plan, self.effset, s["q"], s["t"], s["s"], s["G"], self.target,
-                                         want_scale=False, grad_quat=s["gq"], grad_trans=s["gt"])
+            self.diff_step(s)
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
@@ -385,7 +398,7 @@ class Workload:
 
     def forward_ms(self, reps=50):
         """Mean duration of the forward launch alone, back to back (the
-        differentiable step interleaves it with other work)."""
+        two-call route's first launch)."""
         torch, s = self.torch, self.sets[0]
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -455,7 +468,7 @@ def main():
         kernel_ms = region[0].elapsed_time(region[1]) / args.steps
     bytes_per_launch = N * BYTES_PER_JOINT[args.workload]
     if diff:
-        bytes_per_launch += 24 * w.effset.num_effectors
+        bytes_per_launch += 12 * w.effset.num_effectors
     if args.workload in FUSED:
         bytes_per_launch += b.extra["key_quat"].nbytes + b.extra["key_trans"].nbytes + 16 * C
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
@@ -466,7 +479,8 @@ def main():
             "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
     if args.workload == "differentiable":
         roof["forward_kernel_ms"] = fwd_ms
-        roof["dense_seed_ms_per_step"] = w.dense_step_ms()
+        roof["two_call_ms_per_step"] = w.graph_step_ms(w.two_call_graph)
+        roof["dense_seed_ms_per_step"] = w.graph_step_ms(w.dense_graph)
     launch = {"graph_ms_per_step": elapsed * 1e3 / args.steps,
               "plain_call_ms_per_step": w.eager_step_ms() if diff else w.plain_launch_ms()}
     out = {

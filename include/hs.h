@@ -390,6 +390,19 @@ hs_status hs_effector_backward(const hs_plan *plan, const hs_effectors *effector
                                const float *global, const float *targets, float *grad_quat, float *grad_trans,
                                float *grad_scale, hipStream_t stream);
 
+/* Forward scan and end-effector adjoint in one launch: each adjoint tile
+ * first runs the forward scan of its characters in LDS (the blocks of
+ * hs_scan_forward, Sec. 3.2.1), takes the seeds 2 (b_e - y_e) from it,
+ * then runs the reverse rounds.  Writes what hs_scan_forward (global_out,
+ * if non-NULL: G [N,4,4], 16-byte aligned) followed by hs_effector_backward
+ * would write, up to rounding, without a separate forward launch or a
+ * read of G.  Needs a sparse effector set (hs_effectors_sparse = 1):
+ * HS_ERR_UNSUPPORTED otherwise.  src must be HS_POSE_TRS.  Other errors as
+ * for hs_effector_backward.  Asynchronous; allocates nothing. */
+hs_status hs_effector_step(const hs_plan *plan, const hs_effectors *effectors, const hs_pose_src *src,
+                           const float *targets, float *global_out, float *grad_quat, float *grad_trans,
+                           float *grad_scale, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Vertex skinning: the stage after Bind MeshPose.  The paper's pipeline
  * skins meshes with the skin matrices on the GPU (Sec. 3; Sec. 5 uses

@@ -1752,4 +1752,49 @@ hs_status hs_effector_backward(const hs_plan *plan, const hs_effectors *effector
     return run_backward(plan, pa, ba, stream, "hs_effector_backward");
 }
 
+hs_status hs_effector_step(const hs_plan *plan, const hs_effectors *effectors, const hs_pose_src *src,
+                           const float *targets, float *global_out, float *grad_quat, float *grad_trans,
+                           float *grad_scale, hipStream_t stream)
+{
+    if (!plan || !effectors) return fail(HS_ERR_INVALID_ARG, "hs_effector_step: plan and effectors must be non-NULL");
+    if (effectors->plan != plan)
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_step: the effectors were made for another plan");
+    if (!effectors->sparse)
+        return fail(HS_ERR_UNSUPPORTED, "hs_effector_step: the plan's adjoint does not run on synchronous tiles only "
+                                        "(characters over 1024 joints, the dataflow option or multipass); use "
+                                        "hs_scan_forward and hs_effector_backward");
+    if (plan->N == 0) return HS_OK;
+    const size_t N = (size_t)plan->N, E = (size_t)effectors->E;
+    if (!grad_quat || !grad_trans || (E > 0 && !targets))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_step: targets, grad_quat and grad_trans must be non-NULL");
+    if (!aligned(global_out, 16) || !aligned(grad_quat, 16))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_step: global_out and grad_quat must be 16-byte aligned");
+    if (!aligned(targets, 4) || !aligned(grad_trans, 4) || (grad_scale && !aligned(grad_scale, 4)))
+        return fail(HS_ERR_INVALID_ARG, "hs_effector_step: targets/grad_trans/grad_scale must be 4-byte aligned");
+    hs::PoseArgs pa;
+    std::vector<Range> ins;
+    hs_status rc = check_pose_src(plan, src, pa, ins, false);
+    if (rc != HS_OK) return rc;
+    ins.push_back({targets, E * 12, "targets"});
+    std::vector<Range> outs = {{global_out, global_out ? N * 64 : 0, "global_out"},
+                               {grad_quat, N * 16, "grad_quat"}, {grad_trans, N * 12, "grad_trans"},
+                               {grad_scale, grad_scale ? N * 12 : 0, "grad_scale"}};
+    if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_effector_step: cannot select device");
+    hs::BwdArgs ba{};
+    ba.ckpt_k = 1;
+    ba.level = plan->d_level;
+    ba.grad_quat = grad_quat;
+    ba.grad_trans = grad_trans;
+    ba.grad_scale = grad_scale;
+    ba.eff_ids = effectors->d_ids;
+    ba.eff_row = effectors->d_row;
+    ba.eff_tile = effectors->d_tile;
+    ba.eff_target = targets;
+    ba.eff_forward = 1;
+    ba.eff_global_out = global_out;
+    return run_backward(plan, pa, ba, stream, "hs_effector_step");
+}
+
 } // extern "C"

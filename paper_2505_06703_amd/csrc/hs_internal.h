@@ -18,7 +18,7 @@ constexpr int kMaxBwdTileJoints = 1664;
 
 // Largest tile of the synchronous-round adjoint kernel: one joint per
 // thread, 104 bytes of LDS per joint (jump product, inbox, pointer, owner
-// word).
+// word) and a flag per 64-joint block.
 constexpr int kMaxSyncTileJoints = 1024;
 
 // A tile: a contiguous range of global joint ids holding whole characters,
@@ -131,8 +131,13 @@ struct BwdArgs {
     const int64_t *eff_ids;   // [E] global joint ids, ascending, distinct; null = dense seed
     const int32_t *eff_row;   // [E] row of eff_target for each id
     const int32_t *eff_tile;  // [tiles][2] range [lo, hi) of eff_ids in each adjoint tile
-    const float *eff_global;  // [N,16] forward output
+    const float *eff_global;  // [N,16] forward output (not read when eff_forward)
     const float *eff_target;  // [E,3]
+    // the forward scan runs inside each adjoint tile (blocks of the forward
+    // kernel, G in LDS) and the seeds come from it; eff_global_out, if not
+    // null, receives G [N,16]
+    int32_t eff_forward;
+    float *eff_global_out;
 };
 
 // Kernel launchers (hs_kernels.hip).  Each returns the hipError_t of the

@@ -1271,16 +1271,25 @@ __device__ __forceinline__ int owner_read(const int *w)
     return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int WAVES, bool EFF>
+// SEED: 0 dense dLoss/dG; 1 end-effector seeds from a given forward output;
+// 2 end-effector seeds from the tile's own forward scan, run first with the
+// forward kernel's blocks (one per wave: a tile has at most WAVES of them),
+// G in the inbox array, which the seeds then overwrite in place.
+constexpr int kSeedDense = 0, kSeedEffectors = 1, kSeedForward = 2;
+constexpr int kOwnSeeded = -2;  // owner word of a seeded joint before the rounds
+
+template <int WAVES, int SEED>
 __global__ void __launch_bounds__(WAVES * kWave)
 bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 {
+    constexpr bool EFF = SEED != kSeedDense;
     extern __shared__ float4 lds[];
     const int cap = tl.tile_cap;
     float4 *Ms = lds;
     float4 *In = lds + 3 * cap;
     int *Ac = reinterpret_cast<int *>(lds + 6 * cap);
     int *Own = Ac + cap;
+    int *Fl = Own + cap;  // SEED 2: the forward's block flags [cap / 64]
     const int jl = threadIdx.x;
 
     for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
@@ -1311,7 +1320,7 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             if constexpr (EFF) {
 #pragma unroll
                 for (int k = 0; k < 12; ++k) S[k] = 0.0f;
-                aff_store(In + 3 * jl, S);
+                if constexpr (SEED == kSeedEffectors) aff_store(In + 3 * jl, S);
             } else {
                 aff_load(reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid, S);
             }
@@ -1319,7 +1328,42 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             Ac[jl] = a;
             owner_claim(Own + jl, -1);
         }
-        if constexpr (EFF) {
+        if constexpr (SEED == kSeedForward) {
+            // the tile's forward scan, G into the inbox array
+            const int nblk = (td.count + kWave - 1) / kWave;
+            if (jl < nblk) Fl[jl] = 0;
+            __syncthreads();
+            FwdShared sh{};
+            sh.G = In;
+            sh.flags = Fl;
+            OutArgs out{};
+            out.global_out = bwd.eff_global_out;
+            const int wave = jl / kWave;
+            if (wave < nblk) fwd_block<false, false>(tl, pose, out, td, td.count, wave, sh, jl & (kWave - 1));
+            __syncthreads();
+            // each effector's seed over its own row of G, marked in its owner word
+            const int e1 = bwd.eff_tile[2 * tile + 1];
+            for (int k = bwd.eff_tile[2 * tile] + jl; k < e1; k += WAVES * kWave) {
+                const int le = (int)(bwd.eff_ids[k] - td.begin);
+                const float *y = bwd.eff_target + 3 * (int64_t)bwd.eff_row[k];
+                float g[12];
+                aff_load(In + 3 * le, g);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float b = g[4 * r + 3];
+                    g[4 * r] = g[4 * r + 1] = g[4 * r + 2] = 0.0f;
+                    g[4 * r + 3] = 2.0f * (b - y[r]);
+                }
+                aff_store(In + 3 * le, g);
+                owner_claim(Own + le, kOwnSeeded);
+            }
+            __syncthreads();
+            if (live && owner_read(Own + jl) == kOwnSeeded) {
+                aff_load(In + 3 * jl, S);
+                owner_claim(Own + jl, -1);
+            }
+        }
+        if constexpr (SEED == kSeedEffectors) {
             // the seeds of this tile's end effectors, through the inboxes
             __syncthreads();
             const int e1 = bwd.eff_tile[2 * tile + 1];
@@ -2487,11 +2531,12 @@ hipError_t set_lds_limits()
         if (err != hipSuccess) return err;
     }
     const int bs = (int)backward_sync_lds_bytes(std::min(kMaxSyncTileJoints, WAVES * kWave));
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, false>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, bs);
-    if (err == hipSuccess)
-        err = hipFuncSetAttribute(reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, true>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, bs);
+    const void *sk[3] = {reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, kSeedDense>),
+                         reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, kSeedEffectors>),
+                         reinterpret_cast<const void *>(bwd_sync_kernel<WAVES, kSeedForward>)};
+    hipError_t err = hipSuccess;
+    for (const void *k : sk)
+        if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bs);
     if (err != hipSuccess || WAVES != 16) return err;
     const void *pk[4] = {reinterpret_cast<const void *>(paper_alg_kernel<1>),
                          reinterpret_cast<const void *>(paper_alg_kernel<2>),
@@ -2737,7 +2782,7 @@ hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *s
 
 size_t backward_sync_lds_bytes(int tile_cap)
 {
-    return (size_t)tile_cap * 104;
+    return (size_t)tile_cap * 104 + (size_t)(tile_cap / kWave + 1) * 4;
 }
 
 size_t backward_tile_lds_bytes(int tile_cap)
@@ -2774,12 +2819,15 @@ hipError_t launch_bwd_sync_w(const TileLaunch &tl, const PoseArgs &pose, const B
 {
     if (tl.tile_cap > WAVES * kWave) return hipErrorInvalidValue;
     const size_t lds = backward_sync_lds_bytes(tl.tile_cap);
-    if (bwd.eff_ids)
-        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, true>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose,
-                           bwd);
+    if (bwd.eff_ids && bwd.eff_forward)
+        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, kSeedForward>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream,
+                           tl, pose, bwd);
+    else if (bwd.eff_ids)
+        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, kSeedEffectors>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream,
+                           tl, pose, bwd);
     else
-        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, false>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl, pose,
-                           bwd);
+        hipLaunchKernelGGL((bwd_sync_kernel<WAVES, kSeedDense>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream, tl,
+                           pose, bwd);
     return hipGetLastError();
 }
 

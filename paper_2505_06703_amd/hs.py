@@ -41,7 +41,7 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
            "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices",
            "hs_effector_loss_grad", "hs_effectors_create", "hs_effectors_destroy", "hs_effectors_sparse",
-           "hs_effector_backward")
+           "hs_effector_backward", "hs_effector_step")
 
 
 class HSError(RuntimeError):
@@ -136,6 +136,7 @@ def load_library():
     lib.hs_effectors_sparse.argtypes = [vp]
     lib.hs_effectors_sparse.restype = i32
     lib.hs_effector_backward.argtypes = [vp, vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, vp, vp]
+    lib.hs_effector_step.argtypes = [vp, vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, vp, vp]
     lib.hs_scan_skin_vertices.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp]
     lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
                                             vp, vp, vp, vp, vp, vp, vp, vp]
@@ -542,6 +543,27 @@ def hs_effector_backward(plan, effectors, quat, trans, scale, global_, targets, 
         gs = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_scale is None else _need(grad_scale, "grad_scale", (N, 3))
     _check(load_library().hs_effector_backward(plan.handle, effectors.handle, ctypes.byref(src), _ptr(global_),
                                                _ptr(targets), _ptr(gq), _ptr(gt), _ptr(gs), _stream(stream)))
+    return gq, gt, gs
+
+
+def hs_effector_step(plan, effectors, quat, trans, scale, targets, global_out=None, want_scale=True,
+                     grad_quat=None, grad_trans=None, grad_scale=None, stream=None):
+    """Forward scan and the adjoint of sum_e |b_e - y_e|^2 in one launch
+    (``hs_effector_step``; needs ``effectors.sparse``): returns (grad_quat,
+    grad_trans, grad_scale or None); G goes to ``global_out`` if given."""
+    N = plan.num_joints
+    src = _trs_src(plan, quat, trans, scale)
+    _need(targets, "targets", (effectors.num_effectors, 3))
+    if global_out is not None:
+        _need(global_out, "global_out", (N, 4, 4))
+    dev = quat.device
+    gq = torch.empty((N, 4), device=dev, dtype=torch.float32) if grad_quat is None else _need(grad_quat, "grad_quat", (N, 4))
+    gt = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_trans is None else _need(grad_trans, "grad_trans", (N, 3))
+    gs = None
+    if want_scale:
+        gs = torch.empty((N, 3), device=dev, dtype=torch.float32) if grad_scale is None else _need(grad_scale, "grad_scale", (N, 3))
+    _check(load_library().hs_effector_step(plan.handle, effectors.handle, ctypes.byref(src), _ptr(targets),
+                                           _ptr(global_out), _ptr(gq), _ptr(gt), _ptr(gs), _stream(stream)))
     return gq, gt, gs
 
 

@@ -1,5 +1,6 @@
 """GPU parity of the end-effector adjoint (hs_effectors_create,
-hs_effector_backward) against the FP64 oracle's reverse mode.
+hs_effector_backward, and hs_effector_step, which runs the forward scan in
+the same launch) against the FP64 oracle.
 
 The call forms its seed 2 (b_e - y_e) from the forward output it is given,
 so the oracle is handed the same seed, computed here in fp32 from the GPU's
@@ -16,6 +17,7 @@ import torch
 import oracle
 from paper_2505_06703_amd import hs
 from paper_2505_06703_amd import workloads as wl
+from parity import check_global, reference
 
 pytestmark = pytest.mark.gpu
 
@@ -217,3 +219,110 @@ def test_errors():
         # an output overlapping an input
         hs.hs_effector_backward(plan, E, q, t, s, G, y, grad_quat=q)
     del gq
+
+
+# ---------------------------------------------------------------------------
+# hs_effector_step: the forward scan inside each adjoint tile, then the
+# adjoint seeded from it.  Its G (global_out) is held to the forward's
+# tolerance against the oracle, and its gradients to the oracle's reverse
+# mode fed the seed made from that G.
+# ---------------------------------------------------------------------------
+def run_step(b, eff, y, want_global=True, **plan_kw):
+    plan = hs.Plan(b.offsets, b.parents, **plan_kw)
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    E = hs.Effectors(plan, eff)
+    assert E.sparse
+    G = torch.empty((b.num_joints, 4, 4), device=DEV) if want_global else None
+    got = hs.hs_effector_step(plan, E, q, t, s, dev(y), global_out=G)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy() for x in got]
+    if want_global:
+        Gr, lam, _ = reference(b)
+        check_global(G.cpu().numpy(), Gr, lam, "effector step G")
+        return G.cpu().numpy(), got
+    return None, got
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4), dict(tile_joints=512)])
+def test_fused_step_matches_oracle(shape):
+    b = wl.differentiable(num_characters=12)
+    eff = b.extra["effectors"]
+    y = targets(b, eff, np.random.default_rng(30))
+    G, got = run_step(b, eff, y, **shape)
+    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), f"effector step {shape}")
+
+
+def test_fused_step_mixed_small_characters_and_unsorted_ids():
+    b = wl.heterogeneous(num_characters=40, lo=32, hi=1000)
+    rng = np.random.default_rng(31)
+    off = b.offsets
+    eff = set()
+    for c in range(off.size - 1):
+        if off[c + 1] > off[c]:
+            eff.update({int(off[c]), int(off[c + 1] - 1), int(rng.integers(off[c], off[c + 1]))})
+    eff = np.array(sorted(eff), np.int64)
+    rng.shuffle(eff)
+    y = rng.standard_normal((eff.size, 3)).astype(np.float32)
+    G, got = run_step(b, eff, y)
+    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), "effector step, mixed characters")
+
+
+def test_fused_step_without_global_agrees_with_two_calls():
+    b = wl.differentiable(num_characters=16)
+    eff = b.extra["effectors"]
+    y = targets(b, eff, np.random.default_rng(32))
+    _, got = run_step(b, eff, y, want_global=False)
+    _, two, _ = run(b, eff, y)
+    for name, x, r in zip(("quat", "trans", "scale"), got, two):
+        bound = TOL * max(1.0, float(np.abs(r).max()))
+        assert float(np.abs(x - r).max()) <= bound, name
+
+
+def test_fused_step_needs_a_sparse_set():
+    b = wl.differentiable(num_characters=2)
+    plan = hs.Plan(b.offsets, b.parents, adjoint=hs.HS_ADJ_DATAFLOW)
+    E = hs.Effectors(plan, b.extra["effectors"])
+    assert not E.sparse
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    with pytest.raises(hs.HSError) as ei:
+        hs.hs_effector_step(plan, E, q, t, s, torch.zeros((E.num_effectors, 3), device=DEV))
+    assert ei.value.status == 3  # HS_ERR_UNSUPPORTED
+
+
+def test_fused_step_captured_replays_match_eager():
+    b = wl.differentiable(num_characters=64)
+    N = b.num_joints
+    plan = hs.Plan(b.offsets, b.parents)
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    E = hs.Effectors(plan, b.extra["effectors"])
+    tgt = dev(np.random.default_rng(33).standard_normal((E.num_effectors, 3)).astype(np.float32))
+    G = torch.empty((N, 4, 4), device=DEV)
+    gq = torch.empty((N, 4), device=DEV)
+    gt = torch.empty((N, 3), device=DEV)
+
+    def step(G, gq, gt):
+        hs.hs_effector_step(plan, E, q, t, s, tgt, global_out=G, want_scale=False, grad_quat=gq, grad_trans=gt)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(G, gq, gt)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step(G, gq, gt)
+    rng = np.random.default_rng(34)
+    for rep in range(4):
+        q.copy_(dev(wl.random_quats(rng, N, 0.3)))
+        tgt.copy_(dev(rng.standard_normal((E.num_effectors, 3)).astype(np.float32)))
+        gq.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        G2, gq2, gt2 = torch.empty_like(G), torch.empty_like(gq), torch.empty_like(gt)
+        step(G2, gq2, gt2)
+        torch.cuda.synchronize()
+        assert torch.equal(G, G2), rep
+        for x, y in ((gq, gq2), (gt, gt2)):
+            bound = TOL * max(1.0, float(y.abs().max()))
+            assert float((x - y).abs().max()) <= bound, rep
