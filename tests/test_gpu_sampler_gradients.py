@@ -154,16 +154,23 @@ def test_loss_through_sampler_and_scan_matches_oracle_chain():
         close(g.cpu().numpy(), r, f"chain {name}")
 
 
-def test_ik_on_local_rotations_reaches_targets():
+@pytest.mark.parametrize("fused", [True, False])
+def test_ik_on_local_rotations_reaches_targets(fused):
+    """One hs_effector_step launch per iteration (fused), or the autograd
+    route: both bring the loss down, and their first losses agree (the
+    same forward)."""
     b = wl.differentiable(num_characters=8)
     Grest = oracle.forward(b.offsets, b.parents, b.rest_quat, b.rest_trans, b.rest_scale)
     eff = b.extra["effectors"]
     y = dev((Grest[eff, :3, 3] + b.extra["target_offsets"]).astype(np.float32))
     plan = hs.Plan(b.offsets, b.parents)
     q, losses = solve_effectors(plan, dev(b.quat), dev(b.trans), dev(b.scale), torch.as_tensor(eff, device=DEV), y,
-                                iters=150)
+                                iters=150, fused=fused)
     assert losses[-1] < 0.1 * losses[0], (losses[0], losses[-1])
     np.testing.assert_allclose(q.norm(dim=1).cpu().numpy(), 1.0, atol=1e-5)
+    G64 = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+    loss0 = float(((G64[eff, :3, 3] - y.cpu().numpy().astype(np.float64)) ** 2).sum())
+    assert abs(losses[0] - loss0) <= 1e-4 * max(1.0, loss0), (losses[0], loss0)
 
 
 def test_clip_parameters_are_recovered_from_effector_targets():
