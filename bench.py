@@ -418,7 +418,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; characters are independent, "
-                                   "so a multi-GPU run would split them with no exchange (see DESIGN.md)",
+                                   "so a multi-GPU run would split the batch into contiguous character "
+                                   "ranges, one plan per GPU, with no exchange",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
