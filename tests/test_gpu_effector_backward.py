@@ -326,3 +326,28 @@ def test_fused_step_captured_replays_match_eager():
         for x, y in ((gq, gq2), (gt, gt2)):
             bound = TOL * max(1.0, float(y.abs().max()))
             assert float((x - y).abs().max()) <= bound, rep
+
+
+def test_fused_step_without_effectors_writes_g_and_zero_gradients():
+    b = wl.differentiable(num_characters=3)
+    G, got = run_step(b, np.zeros(0, np.int64), np.zeros((0, 3), np.float32))
+    for g in got:
+        assert np.all(g == 0.0)
+
+
+def test_fused_step_on_single_joint_and_empty_characters():
+    """Characters of 0, 1, 2 and 64 joints next to a 512-joint one, with
+    effectors on roots and leaves: the tiles' forward and seeds at the
+    smallest sizes."""
+    rng = np.random.default_rng(35)
+    big = wl.differentiable(num_characters=1)
+    chars = [np.zeros(0, np.int32), np.array([-1], np.int32), np.array([-1, 0], np.int32),
+             wl.plain_scan(num_characters=1).parents, big.parents]
+    par = np.concatenate(chars)
+    off = np.concatenate([[0], np.cumsum([c.size for c in chars])]).astype(np.int64)
+    q, t, s = wl.random_pose(rng, par.size, max_angle=0.3)
+    b = wl.Batch("small", off, par, q, t, s, q, t, s)
+    eff = np.array([0, 1, 2, 3, 66, off[4] + 5, off[4] + 300, par.size - 1], np.int64)
+    y = rng.standard_normal((eff.size, 3)).astype(np.float32)
+    G, got = run_step(b, eff, y)
+    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), "small characters")
