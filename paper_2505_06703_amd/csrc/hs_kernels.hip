@@ -490,6 +490,43 @@ __device__ __forceinline__ void fwd_block(const TileLaunch &tl, const PoseArgs &
     block_finish(out, td, n, b, sh, lane, m, e, bidx);
 }
 
+// A block of the forward scan inside an adjoint tile (one block per wave,
+// lane = the tile thread of the same joint): as fwd_block, and the joint's
+// local transform also goes to L (the adjoint's first jump products) while
+// its rotation and scale stay in the caller's registers for the gradients,
+// so that each pose is read once.
+__device__ __forceinline__ void fwd_block_keep(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
+                                               const TileDesc &td, int n, int b, const FwdShared &sh, int lane,
+                                               float4 *L, float4 &q, float &sx, float &sy, float &sz)
+{
+    const int base = b * kWave;
+    const int jl = base + lane;
+    float m[12];
+    int a = -1, e = -1;
+    if (jl < n) {
+        const int64_t gid = td.begin + jl;
+        const int p = tl.parent[gid];
+        const int pl = p < 0 ? -1 : (int)(p - td.begin);
+        if (pl >= base) a = pl - base; else e = pl;
+        const native_float4 qn = __builtin_nontemporal_load(reinterpret_cast<const native_float4 *>(pose.quat) + gid);
+        q = make_float4(qn.x, qn.y, qn.z, qn.w);
+        const float *t = pose.trans + 3 * gid;
+        if (pose.scale) {
+            const float *sp = pose.scale + 3 * gid;
+            sx = __builtin_nontemporal_load(sp);
+            sy = __builtin_nontemporal_load(sp + 1);
+            sz = __builtin_nontemporal_load(sp + 2);
+        }
+        aff_from_trs(q, __builtin_nontemporal_load(t), __builtin_nontemporal_load(t + 1),
+                     __builtin_nontemporal_load(t + 2), sx, sy, sz, m);
+        aff_store(L + 3 * jl, m);
+    } else {
+        aff_identity(m);
+    }
+    wave_inblock_scan(m, a, e, lane);
+    block_finish(out, td, n, b, sh, lane, m, e, td.begin + jl);
+}
+
 // The K local transforms of unit joints [i0, i0 + K) from the
 // component-major staging area (stride S).  Lanes that own no joints read
 // the first K slots instead; their values are never stored.
@@ -1302,7 +1339,15 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
         // value is read from HBM once (streaming loads)
         float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
         float sx = 1.0f, sy = 1.0f, sz = 1.0f;
-        if (live) {
+        if (live && SEED == kSeedForward) {
+            // the pose comes with the tile's forward scan below
+            p = tl.parent[gid];
+            a = p < 0 ? -1 : (int)(p - td.begin);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) S[k] = 0.0f;
+            Ac[jl] = a;
+            owner_claim(Own + jl, -1);
+        } else if (live) {
             p = tl.parent[gid];
             a = p < 0 ? -1 : (int)(p - td.begin);
             const native_float4 qn =
@@ -1339,8 +1384,10 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             OutArgs out{};
             out.global_out = bwd.eff_global_out;
             const int wave = jl / kWave;
-            if (wave < nblk) fwd_block<false, false>(tl, pose, out, td, td.count, wave, sh, jl & (kWave - 1));
+            if (wave < nblk)
+                fwd_block_keep(tl, pose, out, td, td.count, wave, sh, jl & (kWave - 1), Ms, q, sx, sy, sz);
             __syncthreads();
+            if (live) aff_load(Ms + 3 * jl, M);
             // each effector's seed over its own row of G, marked in its owner word
             const int e1 = bwd.eff_tile[2 * tile + 1];
             for (int k = bwd.eff_tile[2 * tile] + jl; k < e1; k += WAVES * kWave) {
