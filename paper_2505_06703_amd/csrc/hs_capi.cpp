@@ -135,6 +135,8 @@ struct MPSet {
     int64_t nmp = 0;
     int32_t *d_janc = nullptr;
     int32_t *d_aself = nullptr;  // each joint's own anchor index, or -1
+    int32_t *d_aseg = nullptr;   // in-LDS segments of the anchor rounds (offsets)
+    int32_t num_aseg = 0;
     int32_t num_anchors = 0;
     int32_t rounds = 0;        // anchor-level jump rounds
     float4 *A1 = nullptr;      // anchors' phase-1 products
@@ -151,6 +153,7 @@ void free_mpset(MPSet &m)
     (void)hipFree(m.d_blocks);
     (void)hipFree(m.d_janc);
     (void)hipFree(m.d_aself);
+    (void)hipFree(m.d_aseg);
     (void)hipFree(m.A1);
     (void)hipFree(m.E1);
     for (int i = 0; i < 2; ++i) {
@@ -461,7 +464,36 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
     m.num_anchors = (int32_t)anchors.size();
     std::vector<int32_t> aself((size_t)pk.nmp, -1);
     for (size_t i = 0; i < anchors.size(); ++i) aself[anchors[i]] = (int32_t)i;
+    // Segments for the in-LDS anchor rounds: a cut before anchor k is valid
+    // when no anchor from k on points below k (anchors point to earlier
+    // anchors of their character); segments take the furthest valid cut
+    // within kAnchorSegCap anchors.  If some stretch has no valid cut that
+    // close, the rounds stay global.
+    std::vector<int32_t> aseg;
+    {
+        const int64_t na = (int64_t)anchors.size();
+        std::vector<int64_t> sufmin((size_t)na + 1, INT64_MAX);
+        for (int64_t i = na - 1; i >= 0; --i) {
+            const int32_t pa = janc[anchors[i]];
+            sufmin[i] = std::min<int64_t>(sufmin[i + 1], pa < 0 ? INT64_MAX : pa);
+        }
+        aseg.push_back(0);
+        int64_t s = 0;
+        while (s < na) {
+            int64_t k = std::min<int64_t>(na, s + hs::kAnchorSegCap);
+            while (k > s && !(k == na || sufmin[k] >= k)) --k;
+            if (k == s) {
+                aseg.clear();
+                break;
+            }
+            aseg.push_back((int32_t)k);
+            s = k;
+        }
+        if (aseg.size() < 2 || m.rounds == 0) aseg.clear();
+        m.num_aseg = aseg.empty() ? 0 : (int32_t)aseg.size() - 1;
+    }
     hipError_t err = upload(&m.d_blocks, pk.mpb);
+    if (err == hipSuccess) err = upload(&m.d_aseg, aseg);
     if (err == hipSuccess) err = upload(&m.d_janc, janc);
     if (err == hipSuccess) err = upload(&m.d_aself, aself);
     const size_t n = (size_t)pk.nmp, na = std::max<size_t>(1, anchors.size());
@@ -621,6 +653,8 @@ hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
     ml.num_anchors = m.num_anchors;
     ml.rounds = m.rounds;
     ml.aself = m.d_aself;
+    ml.aseg = m.d_aseg;
+    ml.num_aseg = m.num_aseg;
     ml.G = m.G;
     for (int i = 0; i < 2; ++i) {
         ml.AP[i] = m.AP[i];

@@ -21,6 +21,10 @@ constexpr int kMaxBwdTileJoints = 1664;
 // word) and a flag per 64-joint block.
 constexpr int kMaxSyncTileJoints = 1024;
 
+// Most anchors of one in-LDS segment of the multipass anchor rounds (one
+// thread each; 52 bytes of LDS per anchor).
+constexpr int kAnchorSegCap = 1024;
+
 // A tile: a contiguous range of global joint ids holding whole characters,
 // scanned by one workgroup entirely in LDS.
 struct TileDesc {
@@ -111,6 +115,11 @@ struct MPLaunch {
     int32_t *E1;              // [num_anchors] anchor index of each anchor's own anchor, or -1
     float4 *AP[2];            // [num_anchors*3] ping-pong anchor products
     int32_t *AE[2];           // [num_anchors] ping-pong anchor pointers
+    // segments of at most kAnchorSegCap consecutive anchors that no anchor
+    // points out of ([num_aseg + 1] offsets): each segment's rounds run in
+    // one workgroup's LDS; num_aseg = 0: rounds over all anchors in HBM
+    const int32_t *aseg;
+    int32_t num_aseg;
     // adjoint workspace (NULL when the plan has none)
     float4 *S[2];             // [num_anchors*3] ping-pong anchor adjoints
     float4 *G;                // [Nmp*3] global transforms

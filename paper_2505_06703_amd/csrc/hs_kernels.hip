@@ -2201,6 +2201,52 @@ mp_anchor_round_kernel(int32_t na, const float4 *Pin, const int32_t *Ein, float4
     Eout[i] = e;
 }
 
+// The same rounds for segments of at most kAnchorSegCap consecutive anchors
+// that no anchor points out of (the plan cuts them, at character
+// boundaries or inside a long chain's anchor list where allowed): one
+// workgroup per segment, one thread per anchor, the products and pointers
+// in LDS, read phase and write phase of each round separated by barriers.
+// The trip count is the plan's, uniform across the workgroup.
+__global__ void __launch_bounds__(kAnchorSegCap)
+mp_anchor_seg_kernel(const int32_t *aseg, int32_t rounds, const float4 *Pin, const int32_t *Ein, float4 *Pout,
+                     int32_t *Eout)
+{
+    __shared__ float4 M[kAnchorSegCap * 3];
+    __shared__ int32_t E[kAnchorSegCap];
+    const int s = aseg[blockIdx.x], n = aseg[blockIdx.x + 1] - s;
+    const int t = threadIdx.x;
+    const bool live = t < n;
+    float m[12];
+    int e = -1;
+    if (live) {
+        aff_load(Pin + 3 * (s + t), m);
+        const int g = Ein[s + t];
+        e = (g >= s && g < s + n) ? g - s : -1;  // the plan's cuts keep every pointer inside
+        aff_store(M + 3 * t, m);
+        E[t] = e;
+    }
+    for (int r = 0; r < rounds; ++r) {
+        __syncthreads();  // products and pointers of round r
+        float g[12];
+        int ee = -1;
+        if (e >= 0) {
+            aff_load(M + 3 * e, g);
+            ee = E[e];
+        }
+        __syncthreads();  // every read of round r done
+        if (e >= 0) {
+            aff_mul_left(g, m);
+            e = ee;
+            aff_store(M + 3 * t, m);
+            E[t] = e;
+        }
+    }
+    if (live) {
+        aff_store(Pout + 3 * (s + t), m);
+        Eout[s + t] = e < 0 ? -1 : s + e;
+    }
+}
+
 // Final pass: the in-block scan again from the poses (cheaper than storing
 // and re-reading every partial), then G_j = G_anchor P_j, one composition
 // per joint.  Writes the outputs -- G through the wave's LDS slice as
@@ -2681,7 +2727,12 @@ hipError_t run_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs
     // ping-pong buffers; with no rounds the phase-1 products are final
     const float4 *pin = ml.A1;
     const int32_t *ein = ml.E1;
-    if (ml.num_anchors > 0) {
+    if (ml.num_anchors > 0 && ml.num_aseg > 0) {
+        hipLaunchKernelGGL(mp_anchor_seg_kernel, dim3((unsigned)ml.num_aseg), dim3(kAnchorSegCap), 0, stream,
+                           ml.aseg, ml.rounds, ml.A1, ml.E1, ml.AP[0], ml.AE[0]);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        pin = ml.AP[0];
+    } else if (ml.num_anchors > 0) {
         const dim3 agrid((unsigned)((ml.num_anchors + 255) / 256));
         for (int r = 0; r < ml.rounds; ++r) {
             hipLaunchKernelGGL(mp_anchor_round_kernel, agrid, dim3(256), 0, stream, ml.num_anchors, pin, ein,
