@@ -2495,6 +2495,77 @@ mpr_anchor_round_kernel(int32_t na, const float4 *S, const float4 *M, const int3
     aff_store(Mnext + 3 * i, m);
 }
 
+// The reverse rounds for one segment of anchors that no anchor points out
+// of (the segments of the forward's anchor rounds): one workgroup, one
+// thread per anchor, inboxes, jump products, pointers and owner words in
+// LDS.  Each round every pusher sends S (.) M to its current target the
+// way the synchronous tile adjoint does: the target's owner word names one
+// pusher, which stores into the inbox; the others (fan-in) add to it
+// atomically after a barrier; the target adds its inbox to S in registers.
+// S holds the anchors' adjoints before the rounds and receives them after.
+// LDS: inbox [cap][3] | M [cap][3] float4 | pointers [cap] | owners [cap]
+size_t mpr_seg_lds_bytes() { return (size_t)kAnchorSegCap * (6 * sizeof(float4) + 2 * sizeof(int32_t)); }
+
+__global__ void __launch_bounds__(kAnchorSegCap)
+mpr_anchor_seg_kernel(const int32_t *aseg, int32_t rounds, float4 *S, const float4 *M0, const int32_t *A0)
+{
+    static_assert(kAnchorSegCap <= (1 << kOwnerShift), "owner words hold a segment-local id");
+    extern __shared__ float4 lds[];
+    float4 *In = lds;
+    float4 *Ms = lds + 3 * kAnchorSegCap;
+    int32_t *As = reinterpret_cast<int32_t *>(lds + 6 * kAnchorSegCap);
+    int32_t *Own = As + kAnchorSegCap;
+    const int s = aseg[blockIdx.x], n = aseg[blockIdx.x + 1] - s;
+    const int t = threadIdx.x;
+    const bool live = t < n;
+    float x[12], m[12];
+    int a = -1;
+    if (live) {
+        aff_load(S + 3 * (s + t), x);
+        aff_load(M0 + 3 * (s + t), m);
+        const int g = A0[s + t];
+        a = (g >= s && g < s + n) ? g - s : -1;  // the plan's cuts keep every pointer inside
+        aff_store(Ms + 3 * t, m);
+        As[t] = a;
+        owner_claim(Own + t, -1);
+    }
+    __syncthreads();
+    if (a >= 0) owner_claim(Own + a, t);
+    for (int r = 0; r < rounds; ++r) {
+        __syncthreads();  // claims, products and pointers of round r
+        const int tag = r << kOwnerShift;
+        int aa = -1;
+        bool lose = false;
+        float c[12];
+        if (a >= 0) {
+            adj_pull(x, m, c);
+            lose = owner_read(Own + a) != (tag | t);
+            if (!lose) aff_store(In + 3 * a, c);
+            float g[12];
+            aff_load(Ms + 3 * a, g);
+            aa = As[a];
+            aff_mul_left(g, m);  // published after the barriers
+        }
+        __syncthreads();
+        if (lose) lds_atomic_add12(In + 3 * a, c);
+        const bool recv = live && (owner_read(Own + t) >> kOwnerShift) == r;
+        __syncthreads();
+        if (recv) {
+            float in[12];
+            aff_load(In + 3 * t, in);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) x[k] += in[k];
+        }
+        if (a >= 0) {
+            a = aa;
+            aff_store(Ms + 3 * t, m);
+            As[t] = a;
+            if (a >= 0) owner_claim(Own + a, (tag + (1 << kOwnerShift)) | t);
+        }
+    }
+    if (live) aff_store(S + 3 * (s + t), x);
+}
+
 // ---------------------------------------------------------------------------
 // Standalone Simulation step and Bind MeshPose step.
 // ---------------------------------------------------------------------------
@@ -2655,6 +2726,9 @@ hipError_t prepare_kernels()
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSkinJoints * 48)) != hipSuccess ||
         (err = hipFuncSetAttribute(reinterpret_cast<const void *>(vertex_skin_kernel<1>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, kMaxSkinJoints * 32)) != hipSuccess)
+        return err;
+    if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(mpr_anchor_seg_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)mpr_seg_lds_bytes())) != hipSuccess)
         return err;
     if ((err = set_lds_limits<1>()) != hipSuccess) return err;
     if ((err = set_lds_limits<2>()) != hipSuccess) return err;
@@ -2976,7 +3050,13 @@ hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, c
     }
     hipLaunchKernelGGL(mpr_block_kernel<false>, grid, blk, lds, stream, ml, pose, bwd, ml.S[0]);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    if (na > 0) {
+    if (na > 0 && ml.num_aseg > 0) {
+        // per segment in one workgroup's LDS, from the phase-1 products and
+        // pointers (A1, E1, left by the forward pass above); in place in S[0]
+        hipLaunchKernelGGL(mpr_anchor_seg_kernel, dim3((unsigned)ml.num_aseg), dim3(kAnchorSegCap),
+                           mpr_seg_lds_bytes(), stream, ml.aseg, ml.rounds, ml.S[0], ml.A1, ml.E1);
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+    } else if (na > 0) {
         // the anchors' phase-1 products and pointers (A1, E1, left by the
         // forward pass above) start the reverse rounds
         const float4 *min = ml.A1;

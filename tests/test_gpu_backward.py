@@ -228,6 +228,34 @@ def test_multipass_adjoint_comb_with_shared_anchors():
         assert err <= tol, f"{name}: {err:.3e} > {tol:.3e}"
 
 
+@pytest.mark.parametrize("lengths", [[100_000], [30_000] * 4])
+def test_multipass_adjoint_anchor_rounds(lengths):
+    """The anchors' reverse rounds: a 100 000-joint chain has more anchors
+    than one workgroup holds, so its rounds run over the whole anchor array;
+    four 30 000-joint chains run them per segment of whole characters in
+    one workgroup's LDS (two characters a segment)."""
+    rng = np.random.default_rng(len(lengths))
+    par = np.concatenate([np.arange(-1, n - 1, dtype=np.int32) for n in lengths])
+    off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    n = par.size
+    q, t, s = wl.random_pose(rng, n, max_angle=0.02)
+    b = wl.Batch("chains", off, par, q, t, s, q, t, s)
+    plan = hs.Plan(b.offsets, b.parents)
+    assert plan.info["multipass_joints"] == n
+    W = np.zeros((n, 4, 4), np.float32)
+    idx = rng.choice(n, 400, replace=False)
+    W[idx, :3, :] = rng.standard_normal((400, 3, 4)).astype(np.float32) * 0.1
+    got = run(b, W)
+    ref = oracle_grads(b, W)
+    for name, g, r in zip(("quat", "trans", "scale"), got, ref):
+        g = np.asarray(g, np.float64)
+        for c in range(len(lengths)):
+            sl = slice(off[c], off[c + 1])
+            tol = TOL * max(1.0, float(np.abs(r[sl]).max())) * np.sqrt(lengths[c] / 2048)
+            err = float(np.abs(g[sl] - r[sl]).max())
+            assert err <= tol, f"{name} of character {c}: {err:.3e} > {tol:.3e}"
+
+
 @pytest.mark.parametrize("adj", ADJ)
 def test_more_tiles_than_resident_workgroups(adj):
     """1300 characters of 512 joints: more adjoint tiles than the device
