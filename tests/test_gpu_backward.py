@@ -228,12 +228,14 @@ def test_multipass_adjoint_comb_with_shared_anchors():
         assert err <= tol, f"{name}: {err:.3e} > {tol:.3e}"
 
 
-@pytest.mark.parametrize("lengths", [[100_000], [30_000] * 4])
+@pytest.mark.parametrize("lengths", [[100_000], [30_000] * 4, [30_000, 5_000, 20_000, 3_000]])
 def test_multipass_adjoint_anchor_rounds(lengths):
     """The anchors' reverse rounds: a 100 000-joint chain has more anchors
     than one workgroup holds, so its rounds run over the whole anchor array;
     four 30 000-joint chains run them per segment of whole characters in
-    one workgroup's LDS (two characters a segment)."""
+    one workgroup's LDS (two characters a segment); chains of four lengths
+    share one segment, their anchors' pointers running out after different
+    rounds."""
     rng = np.random.default_rng(len(lengths))
     par = np.concatenate([np.arange(-1, n - 1, dtype=np.int32) for n in lengths])
     off = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
