@@ -405,7 +405,7 @@ hs_status hs_effector_step(const hs_plan *plan, const hs_effectors *effectors, c
 
 /* ------------------------------------------------------------------------
  * Vertex skinning: the stage after Bind MeshPose.  The paper's pipeline
- * skins meshes with the skin matrices on the GPU (Sec. 3; Sec. 5 uses
+ * skins meshes with the skin matrices on the GPU (Sec. 3; Sec. 4 uses
  * meshes of 1000-3000 faces); each vertex moves by a weighted blend of the
  * S_j = G_j B_j^-1 of up to four joints of its character.
  * ------------------------------------------------------------------------ */

@@ -243,10 +243,10 @@ int hso_pose_sample(int64_t C, const int64_t *offsets,
     }
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < C; ++c) {
-        /* frame position in fp32 exactly as a single fp32 multiply rounds it */
-        const float f = (float)((double)fps * (double)time[c]);
-        const double fl = floor((double)f);
-        const double alpha = (double)f - fl;
+        /* frame position f = fps * tau in FP64 from the fp32 inputs */
+        const double f = (double)fps * (double)time[c];
+        const double fl = floor(f);
+        const double alpha = f - fl;
         int64_t k0 = (int64_t)fl % num_keys;
         if (k0 < 0) k0 += num_keys;
         const int64_t k1 = (k0 + 1) % num_keys;

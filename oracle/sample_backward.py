@@ -1,7 +1,7 @@
 """FP64 reverse mode of the Simulation step -- TEST INFRASTRUCTURE ONLY.
 
 The sampler (Sec. 1, step 1; the reading of R15): per character c, frame
-f = fps * time_c (one fp32 multiply), alpha = f - floor(f), keys
+f = fps * time_c (in FP64), alpha = f - floor(f), keys
 k0 = floor(f) mod K and k1 = k0 + 1 mod K; per clip X in {A, B}
     q_X = normalize((1 - alpha) a + alpha s b),  s = sign(a . b),
     t_X = (1 - alpha) t_a + alpha t_b,
@@ -53,7 +53,7 @@ def pose_sample_backward(offsets, key_quat, key_trans, clip_a, clip_b, time, wei
         if n == 0:
             continue
         sl = slice(int(offsets[c]), int(offsets[c + 1]))
-        f = float(np.float32(np.float64(fps) * np.float64(np.float32(time[c]))))
+        f = float(np.float64(np.float32(fps)) * np.float64(np.float32(time[c])))
         fl = np.floor(f)
         alpha = f - fl
         k0 = int(fl) % T

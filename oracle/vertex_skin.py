@@ -1,7 +1,7 @@
 """FP64 oracle of vertex skinning -- TEST INFRASTRUCTURE ONLY.
 
 The step after the paper's pipeline (Sec. 3 names skinning among the GPU
-stages; the experiment of Sec. 5 skins meshes of 1000-3000 faces): each
+stages; the experiment of Sec. 4 skins meshes of 1000-3000 faces): each
 vertex of a character's mesh is moved by a weighted blend of the skin
 matrices S_j = G_j B_j^-1 of up to four joints.
 

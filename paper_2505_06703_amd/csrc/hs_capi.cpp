@@ -737,21 +737,22 @@ hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Out
 // Launch-shape autotuning: time the candidates on scratch poses of the
 // plan's own topology and keep the fastest.
 // ---------------------------------------------------------------------------
-std::string tune_key(const hs_plan *p)
+std::string tune_key(const hs_plan *p, int strategy)
 {
     // size class: number of joints (log2), largest character and deepest
-    // block chain, rounded so that similar batches share an entry
+    // block chain, rounded so that similar batches share an entry; the
+    // strategy and the instancing decide which candidates are allowed
     char buf[160];
-    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d|inst%d", p->ctx->arch.c_str(),
+    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d|inst%d|strat%d", p->ctx->arch.c_str(),
              ceil_log2(std::max<int64_t>(1, p->N)), round_up(std::max(1, p->info.max_character), 64),
              ceil_log2(std::max(1, p->info.max_block_chain)), ceil_log2(std::max<int64_t>(1, p->C)),
-             p->inst ? 1 : 0);
+             p->inst ? 1 : 0, strategy);
     return buf;
 }
 
 hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
 {
-    const std::string key = tune_key(plan);
+    const std::string key = tune_key(plan, strategy);
     {
         std::lock_guard<std::mutex> lk(plan->ctx->mu);
         auto it = plan->ctx->tuned.find(key);
@@ -766,7 +767,9 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     std::vector<Shape> cands;
     const int min_cap = round_up(std::max(1, plan->info.max_character), 64);
     for (int cap : {64, 128, 256, 512, 1024, 2048}) {
-        if (strategy != HS_STRATEGY_MULTIPASS && cap < min_cap && strategy == HS_STRATEGY_TILE) continue;
+        // every character must stay on a tile for the tile strategy and for
+        // instanced plans (which have no multipass path)
+        if (cap < min_cap && (strategy == HS_STRATEGY_TILE || plan->inst)) continue;
         if (hs::forward_tile_lds_bytes(cap, true) > plan->ctx->max_lds) continue;
         for (int w : {1, 2, 4, 8, 16}) {
             if (w * 64 > cap) continue;

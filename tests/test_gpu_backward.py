@@ -188,10 +188,10 @@ def test_autograd_matches_oracle_in_both_modes():
         G = hierarchy_scan(plan, q, t, None, ckpt_k=k)
         loss = ((G[torch.as_tensor(eff, device=DEV), :3, 3] - y) ** 2).sum()
         loss.backward()
-        # the oracle's gradient at the GPU's own effector positions
+        # the oracle's gradient of the same loss (its own FP64 forward)
         W = np.zeros((b.num_joints, 4, 4))
         Gg = G.detach().cpu().numpy().astype(np.float64)
-        W[eff, :3, 3] = 2.0 * (Gg[eff, :3, 3] - y.cpu().numpy())
+        W[eff, :3, 3] = 2.0 * (G64[eff, :3, 3] - y.cpu().numpy())
         ref = oracle.backward(b.offsets, b.parents, b.quat, b.trans, None, W)
         check_grads(b.offsets, [q.grad.cpu().numpy(), t.grad.cpu().numpy(), None], ref, f"autograd k={k}")
         np.testing.assert_allclose(Gg[eff, :3, 3], G64[eff, :3, 3], atol=1e-4 * 30)

@@ -2,9 +2,9 @@
 hs_effector_backward, and hs_effector_step, which runs the forward scan in
 the same launch) against the FP64 oracle.
 
-The call forms its seed 2 (b_e - y_e) from the forward output it is given,
-so the oracle is handed the same seed, computed here in fp32 from the GPU's
-G: the comparison then measures the adjoint alone.  Tolerance as for
+The reference is the oracle's alone: its seed 2 (b_e - y_e) comes from the
+FP64 forward of the same poses, so an error of the GPU forward (whose G
+the call's seed is formed from) shows in the comparison too.  Tolerance as for
 hs_scan_backward: per character, max |grad_gpu - grad_fp64| <= 1e-4 *
 max(1, max |grad_fp64|) for each gradient array.  Against the dense route
 (hs_effector_loss_grad + hs_scan_backward) on the same inputs the only
@@ -43,10 +43,11 @@ def check(offsets, got, ref, what):
             assert err <= bound, f"{what}: {name} grad of character {c}: {err:.3e} > {bound:.3e}"
 
 
-def seed(G, eff, y):
-    """The dense dLoss/dG the call stands for, in fp32 as the kernels form it."""
-    W = np.zeros(G.shape, np.float32)
-    W[eff, :3, 3] = np.float32(2.0) * (G[eff, :3, 3] - y)
+def seed(b, eff, y):
+    """The dense dLoss/dG of the loss, from the FP64 oracle's forward."""
+    G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
+    W = np.zeros(G.shape)
+    W[eff, :3, 3] = 2.0 * (G[eff, :3, 3] - np.asarray(y, np.float64))
     return W
 
 
@@ -79,7 +80,7 @@ def test_effector_loss_matches_oracle(shape):
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(20))
     G, got, _ = run(b, eff, y, expect_sparse=True, **shape)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), f"effector adjoint {shape}")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector adjoint {shape}")
 
 
 def test_ids_in_any_order_with_their_targets():
@@ -97,7 +98,7 @@ def test_ids_in_any_order_with_their_targets():
     rng.shuffle(eff)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
     G, got, _ = run(b, eff, y, expect_sparse=True)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), "unsorted ids")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), "unsorted ids")
 
 
 def test_no_effectors_gives_zero_gradients():
@@ -114,7 +115,7 @@ def test_dense_route_for_other_adjoint_kernels(plan_kw):
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(22))
     G, got, _ = run(b, eff, y, expect_sparse=False, **plan_kw)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), f"dense route {plan_kw}")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"dense route {plan_kw}")
 
 
 def test_dense_route_for_large_characters():
@@ -130,7 +131,7 @@ def test_dense_route_for_large_characters():
     eff = np.array([1499, 700, 1500, 1600, 4627, 3000], np.int64)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
     G, got, _ = run(b, eff, y, expect_sparse=False)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), "large characters")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), "large characters")
 
 
 def test_agrees_with_dense_calls_and_repeats():
@@ -249,7 +250,7 @@ def test_fused_step_matches_oracle(shape):
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(30))
     G, got = run_step(b, eff, y, **shape)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), f"effector step {shape}")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector step {shape}")
 
 
 def test_fused_step_mixed_small_characters_and_unsorted_ids():
@@ -264,7 +265,7 @@ def test_fused_step_mixed_small_characters_and_unsorted_ids():
     rng.shuffle(eff)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
     G, got = run_step(b, eff, y)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), "effector step, mixed characters")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), "effector step, mixed characters")
 
 
 def test_fused_step_without_global_agrees_with_two_calls():
@@ -350,4 +351,4 @@ def test_fused_step_on_single_joint_and_empty_characters():
     eff = np.array([0, 1, 2, 3, 66, off[4] + 5, off[4] + 300, par.size - 1], np.int64)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
     G, got = run_step(b, eff, y)
-    check(b.offsets, got, oracle_grads(b, seed(G, eff, y)), "small characters")
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), "small characters")

@@ -172,6 +172,38 @@ def test_batching_invariance():
         check_global(G[lo:hi], Gr, lam, f"in batch {c}")
 
 
+def test_batching_invariance_bitwise_on_block_aligned_characters():
+    """A character whose first joint falls on a 64-joint block boundary of its
+    tile is cut into the same blocks as when it is scanned alone, so every
+    composition runs in the same order: its transforms are bitwise those of
+    the character alone, whatever the rest of the batch and the tile size.
+    (Characters of sizes that are multiples of 64 all start on a boundary;
+    for others the in-block rounds group the joints differently, and only
+    the tolerance holds, as tested above.)"""
+    rng = np.random.default_rng(61)
+    sizes = 64 * rng.integers(1, 17, 48)
+    pars = []
+    for n in sizes:
+        p = np.empty(n, np.int32)
+        p[0] = -1
+        for j in range(1, n):
+            p[j] = j - 1 if rng.uniform() < 0.7 else rng.integers(0, j)
+        pars.append(p)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    par = np.concatenate(pars)
+    q, t, s = wl.random_pose(rng, int(off[-1]))
+    b = wl.Batch("aligned", off, par, q, t, s, q, t, s)
+    _, G, _ = run_forward(b)
+    _, G2, _ = run_forward(b, tile_joints=2048)
+    for c in (0, 5, 23, 47):
+        lo, hi = off[c], off[c + 1]
+        one = wl.Batch("one", np.array([0, hi - lo], np.int64), par[lo:hi], q[lo:hi], t[lo:hi], s[lo:hi],
+                       q[lo:hi], t[lo:hi], s[lo:hi])
+        _, G1, _ = run_forward(one)
+        assert np.array_equal(G[lo:hi], G1), f"character {c} in the batch"
+        assert np.array_equal(G2[lo:hi], G1), f"character {c} on 2048-joint tiles"
+
+
 def test_repeat_runs_are_bitwise_deterministic():
     b = wl.deep_forward(num_characters=32)
     plan = hs.Plan(b.offsets, b.parents)

@@ -1,18 +1,29 @@
-"""GPU parity of vertex skinning (hs_mesh_create / hs_skin_vertices) against
-the FP64 oracle (oracle/vertex_skin.py), both fed the same fp32 skin
-matrices from the library's own forward pass.
+"""GPU parity of vertex skinning (hs_mesh_create / hs_skin_vertices and the
+one-pass hs_scan_skin_vertices) against the FP64 oracle.
 
-Tolerance, per vertex: |p'_gpu - p'_fp64|_inf <= 1e-5 * (1 + |p| + max_i
-|t_i|), with t_i the translations of the vertex's four skin matrices.  A
-linear blend sums at most 16 fp32 products per coordinate (error below
-16 u |terms|, u = 6e-8); dual quaternions add a square root, a division and
-two cross products per vertex (a few tens of u); 1e-5 leaves a margin of
-about 3 over both.
+End to end (check_e2e): the reference is the oracle's alone -- its
+sampler (for clip poses), its forward scan, its skin step and its vertex
+skinning (oracle/vertex_skin.py), all in FP64 from the same fp32 inputs.
+The skin matrices carry the scan's tolerance (rotation entries within
+1e-4, translations within 1e-4 (lambda_j + |t(B^-1_j)|)); a blend of
+influences with weights summing to one moves a vertex by at most the
+largest influence's error, |dA| 3|p|_inf + |dt|, so per vertex
+|p'_gpu - p'_fp64|_inf <= 1e-4 (3 |p|_inf + max_i (lambda_i + |t(B^-1_i)|))
+plus the blend's own rounding below.
+
+The vertex kernel alone (check): both sides fed the same fp32 skin
+matrices from the library's own forward pass, |p'_gpu - p'_fp64|_inf <=
+1e-5 * (1 + |p| + max_i |t_i|), with t_i the translations of the vertex's
+four skin matrices.  A linear blend sums at most 16 fp32 products per
+coordinate (error below 16 u |terms|, u = 6e-8); dual quaternions add a
+square root, a division and two cross products per vertex (a few tens of
+u); 1e-5 leaves a margin of about 3 over both.
 """
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from oracle import vertex_skin as ovs
 from paper_2505_06703_amd import hs
 from paper_2505_06703_amd import workloads as wl
@@ -39,6 +50,50 @@ def check(out, offsets, S, voff, mfirst, pos, joints, weights, method, what):
     assert np.all(err <= 1e-5 * scale), f"{what}: vertex {worst} error {err[worst]:.3e} (scale {scale[worst]:.2f})"
 
 
+def check_e2e(out, offsets, parents, q, t, s, inv_rows, voff, mfirst, pos, joints, weights, method, what):
+    """out against the oracle's own pipeline: FP64 forward of the fp32 poses,
+    skin matrices with the per-joint inverse binds inv_rows, vertex
+    skinning."""
+    G = oracle.forward(offsets, parents, q, t, s)
+    lam = oracle.path_length(offsets, parents, G, t)
+    S = oracle.skin(G, inv_rows)
+    ref = ovs.skin_vertices(method, offsets, S, voff, mfirst, pos, joints, weights)
+    counts = np.diff(voff)
+    rows = np.concatenate([np.arange(mfirst[c], mfirst[c] + counts[c]) for c in range(len(counts))])
+    char = np.repeat(np.arange(len(counts)), counts)
+    gj = np.asarray(offsets)[char][:, None] + joints[rows].astype(np.int64)
+    tb = np.linalg.norm(np.asarray(inv_rows, np.float64)[gj, :3, 3], axis=2)
+    p = np.asarray(pos[rows], np.float64)
+    ts = np.linalg.norm(S[gj, :3, 3], axis=2).max(axis=1)
+    bound = (1e-4 * (3.0 * np.abs(p).max(axis=1) + (lam[gj] + tb).max(axis=1))
+             + 1e-5 * (1.0 + np.linalg.norm(p, axis=1) + ts))
+    err = np.abs(np.asarray(out, np.float64) - ref).max(axis=1)
+    worst = int(np.argmax(err / bound))
+    assert np.all(np.isfinite(out)), f"{what}: non-finite output"
+    assert np.all(err <= bound), f"{what} (oracle end to end): vertex {worst} error {err[worst]:.3e} > {bound[worst]:.3e}"
+
+
+def sampled_poses(b, chars=None):
+    """The oracle's sampled local poses (FP64) of a clip-driven batch, for
+    all characters or the listed ones (with their sub-batch offsets)."""
+    x = b.extra
+    if chars is None:
+        return b.offsets, oracle.pose_sample(b.offsets, x["key_quat"], x["key_trans"], x["clip_a"], x["clip_b"],
+                                             x["time"], x["weight"], x["fps"])
+    sub_off = np.concatenate([[0], np.cumsum(np.diff(b.offsets)[chars])]).astype(np.int64)
+    return sub_off, oracle.pose_sample(sub_off, x["key_quat"], x["key_trans"], x["clip_a"][chars],
+                                       x["clip_b"][chars], x["time"][chars], x["weight"][chars], x["fps"])
+
+
+def instanced_rows(b, inv_s, chars=None):
+    """Per-joint inverse binds of an instanced batch (one row per skeleton
+    joint expanded to every instance)."""
+    x = b.extra
+    soff = x["skel_offsets"]
+    sid = x["skeleton_id"] if chars is None else x["skeleton_id"][chars]
+    return np.concatenate([inv_s[soff[k]:soff[k + 1]] for k in sid])
+
+
 def posed_skins(plan, batch, inv_rows):
     G, S = hs.hs_scan_forward(plan, dev(batch.quat), dev(batch.trans), dev(batch.scale), inv_bind=dev(inv_rows))
     torch.cuda.synchronize()
@@ -61,7 +116,6 @@ def test_meshes_of_several_skeletons(method):
     b = wl.Batch("meshes", off, par, q, t, s, q, t, s)
     # skin matrices of an arbitrary rigid bind pose: inverse binds of a second
     # random pose, computed in FP64 on the host
-    import oracle
     rq, rt, rs = wl.random_pose(rng, N)
     inv = np.linalg.inv(oracle.forward(off, par, rq, rt, rs)).astype(np.float32)
     plan = hs.Plan(off, par)
@@ -78,6 +132,8 @@ def test_meshes_of_several_skeletons(method):
     out = hs.hs_skin_vertices(mesh, dev(S.astype(np.float32)), method)
     torch.cuda.synchronize()
     check(out.cpu().numpy(), off, S, voff, mfirst, pos, joints, weights, method, f"method {method}")
+    check_e2e(out.cpu().numpy(), off, par, q, t, s, inv, voff, mfirst, pos, joints, weights, method,
+              f"method {method}")
 
 
 @pytest.mark.parametrize("method", [hs.HS_SKIN_LINEAR, hs.HS_SKIN_DUAL_QUAT])
@@ -86,7 +142,6 @@ def test_mesh_skinning_workload_sampled(method):
     poses, skin matrices from the fused forward, one shared mesh."""
     b = wl.mesh_skinning(num_characters=200)
     x = b.extra
-    import oracle
     inv_s = np.linalg.inv(oracle.forward(x["skel_offsets"], x["skel_parents"], *x["skel_rest"])).astype(np.float32)
     plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"])
     lib = hs.ClipLibrary(dev(x["key_quat"]), dev(x["key_trans"]), x["fps"])
@@ -99,6 +154,10 @@ def test_mesh_skinning_workload_sampled(method):
     torch.cuda.synchronize()
     check(out.cpu().numpy(), b.offsets, S.cpu().numpy(), x["vertex_offsets"], x["mesh_first"], x["mesh_positions"],
           x["mesh_joints"], x["mesh_weights"], method, f"mesh_skinning method {method}")
+    off, (qr, tr) = sampled_poses(b)
+    check_e2e(out.cpu().numpy(), off, b.parents, qr, tr, None, instanced_rows(b, inv_s), x["vertex_offsets"],
+              x["mesh_first"], x["mesh_positions"], x["mesh_joints"], x["mesh_weights"], method,
+              f"mesh_skinning method {method}")
 
 
 def test_rest_pose_leaves_vertices_in_place():
@@ -107,7 +166,6 @@ def test_rest_pose_leaves_vertices_in_place():
     rng = np.random.default_rng(32)
     par = wl.humanoid_with_chains(["tail"], 30)[0]
     q, t, s = wl.random_pose(rng, par.size)
-    import oracle
     inv = np.linalg.inv(oracle.forward(np.array([0, par.size]), par, q, t, s)).astype(np.float32)
     plan = hs.Plan(np.array([0, par.size]), par)
     b = wl.Batch("rest", np.array([0, par.size]), par, q, t, s, q, t, s)
@@ -154,7 +212,6 @@ def test_mesh_skinning_full_size_sampled(method):
     against the oracle on the same skin matrices."""
     b = wl.mesh_skinning()
     x = b.extra
-    import oracle
     inv_s = np.linalg.inv(oracle.forward(x["skel_offsets"], x["skel_parents"], *x["skel_rest"])).astype(np.float32)
     plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"])
     lib = hs.ClipLibrary(dev(x["key_quat"]), dev(x["key_trans"]), x["fps"])
@@ -174,6 +231,11 @@ def test_mesh_skinning_full_size_sampled(method):
     sub_voff = np.arange(chars.size + 1, dtype=np.int64) * V
     check(out_sub, sub_off, S_sub, sub_voff, np.zeros(chars.size, np.int32), x["mesh_positions"],
           x["mesh_joints"], x["mesh_weights"], method, f"full size method {method}")
+    ids = np.concatenate([np.arange(b.offsets[c], b.offsets[c + 1]) for c in chars])
+    off_r, (qr, tr) = sampled_poses(b, chars)
+    check_e2e(out_sub, off_r, b.parents[ids], qr, tr, None, instanced_rows(b, inv_s, chars), sub_voff,
+              np.zeros(chars.size, np.int32), x["mesh_positions"], x["mesh_joints"], x["mesh_weights"], method,
+              f"full size method {method}")
 
 
 @pytest.mark.parametrize("method", [hs.HS_SKIN_LINEAR, hs.HS_SKIN_DUAL_QUAT])
@@ -185,7 +247,6 @@ def test_one_pass_pipeline_equals_two_calls(method, instanced):
     forward's."""
     b = wl.mesh_skinning(num_characters=300)
     x = b.extra
-    import oracle
     inv_s = np.linalg.inv(oracle.forward(x["skel_offsets"], x["skel_parents"], *x["skel_rest"])).astype(np.float32)
     if instanced:
         plan = hs.Plan.instanced(x["skel_offsets"], x["skel_parents"], x["skeleton_id"])
@@ -206,6 +267,10 @@ def test_one_pass_pipeline_equals_two_calls(method, instanced):
     assert torch.equal(S1, S)
     check(one.cpu().numpy(), b.offsets, S.cpu().numpy(), x["vertex_offsets"], x["mesh_first"], x["mesh_positions"],
           x["mesh_joints"], x["mesh_weights"], method, f"one pass method {method}")
+    off, (qr, tr) = sampled_poses(b)
+    check_e2e(one.cpu().numpy(), off, b.parents, qr, tr, None, instanced_rows(b, inv_s), x["vertex_offsets"],
+              x["mesh_first"], x["mesh_positions"], x["mesh_joints"], x["mesh_weights"], method,
+              f"one pass method {method}")
 
 
 def test_one_pass_pipeline_on_several_size_classes_and_trs_poses():
@@ -225,7 +290,6 @@ def test_one_pass_pipeline_on_several_size_classes_and_trs_poses():
     off = np.concatenate([[0], np.cumsum([sizes[k] for k in sid])]).astype(np.int64)
     N = int(off[-1])
     q, t, s = wl.random_pose(rng, N)
-    import oracle
     rq, rt, rs = wl.random_pose(rng, N)
     inv = np.linalg.inv(oracle.forward(off, par, rq, rt, rs)).astype(np.float32)
     meshes = [wl.skin_mesh(rng, p, 1000) for p in tm]
@@ -245,6 +309,8 @@ def test_one_pass_pipeline_on_several_size_classes_and_trs_poses():
         one = hs.hs_scan_skin_vertices(plan, mesh, dev(inv), dev(q), dev(t), dev(s), method=method)
         torch.cuda.synchronize()
         assert torch.equal(one, two), method
+        check_e2e(one.cpu().numpy(), off, par, q, t, s, inv, voff, mfirst, pos, joints, weights, method,
+                  f"size classes method {method}")
     # a plan with multipass characters is refused
     big = hs.Plan(off, par, tile_joints=1024)
     mesh_big = hs.Mesh(big, voff, mfirst, pos, joints, weights)

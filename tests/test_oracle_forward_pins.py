@@ -323,6 +323,45 @@ def test_path_length_unit_scale_sums_offsets():
             assert abs(lam[o + j] - acc) < 1e-6
 
 
+def test_path_length_scaled_chain_is_a_geometric_series():
+    """Tolerance scale lambda_j = sum over the path of |A_parent(k) t_k|.  A
+    chain with uniform scale s and arbitrary rotations has A_k = s^(k+1) R,
+    so |A_(k-1) t_k| = s^k l and lambda_j = l (1 - s^(j+1)) / (1 - s): the
+    rotations drop out, and using A_k instead of A_parent(k) (one more
+    factor s) or leaving out the scale both change every term but the
+    root's."""
+    rng = np.random.default_rng(11)
+    n, ell = 40, 0.2
+    for s_val in (0.8, 1.25):
+        q = unit_quats64(rng, n)
+        d = rng.standard_normal((n, 3))
+        t = ell * d / np.linalg.norm(d, axis=1, keepdims=True)
+        s = np.full((n, 3), s_val)
+        off = np.array([0, n])
+        par = np.arange(-1, n - 1, dtype=np.int32)
+        G = oracle.forward(off, par, q, t, s)
+        lam = oracle.path_length(off, par, G, t)
+        k = np.arange(n)
+        expect = ell * (1.0 - s_val ** (k + 1)) / (1.0 - s_val)
+        np.testing.assert_allclose(lam, expect, rtol=1e-12)
+
+
+def test_path_length_non_uniform_scale_takes_the_parents_columns():
+    """A root with rotation R and axis scale (sx, sy, sz): A_root t = R (s * t)
+    (the scale acts on the offset's components before the rotation, L =
+    T R diag(s)), so a child offset along axis i adds s_i |t| to the root's
+    own |t_root|; diag(s) R (a transposed factor order) would not."""
+    rng = np.random.default_rng(12)
+    q = unit_quats64(rng, 4)
+    sc = np.array([[2.0, 0.5, 3.0], [1.0, 1.0, 1.0], [1.0, 1.0, 1.0], [1.0, 1.0, 1.0]])
+    t = np.array([[0.3, -0.4, 0.0], [0.7, 0.0, 0.0], [0.0, 0.7, 0.0], [0.0, 0.0, 0.7]])
+    off = np.array([0, 4])
+    par = np.array([-1, 0, 0, 0], np.int32)
+    G = oracle.forward(off, par, q, t, sc)
+    lam = oracle.path_length(off, par, G, t)
+    np.testing.assert_allclose(lam, [0.5, 0.5 + 1.4, 0.5 + 0.35, 0.5 + 2.1], rtol=1e-12)
+
+
 def test_thread_count_does_not_change_results():
     """Characters are independent: the parallel oracle gives the same bits
     on one thread and on several (the CPU baseline is timed both ways)."""

@@ -99,8 +99,8 @@ def test_same_axis_nlerp_closed_form_and_translation_lerp():
         kt[0, k, 0] = [k, 2 * k, -k]
     tau = np.float32(4.25 / 30.0)  # between keys 4 and 5
     q, t = oracle.pose_sample(_one_char(1), kq, kt, [0], [0], [tau], [0.0])
-    f = np.float32(np.float32(30.0) * tau)
-    u = float(f) - math.floor(float(f))
+    f = 30.0 * float(tau)  # the frame position in FP64
+    u = f - math.floor(f)
     qa, qb = kq[0, 4, 0].astype(np.float64), kq[0, 5, 0].astype(np.float64)
     half = math.atan2((1 - u) * np.linalg.norm(qa[:3]) + u * np.linalg.norm(qb[:3]),
                       (1 - u) * qa[3] + u * qb[3])

@@ -101,11 +101,10 @@ def test_torch_autograd_of_an_independent_forward():
     total = torch.zeros((), dtype=torch.float64)
     for c in range(len(offsets) - 1):
         n = offsets[c + 1] - offsets[c]
-        # the frame position is one fp32 multiply (R15); its rounding is a
-        # constant offset here, so d alpha / d time stays fps
-        f32 = float(np.float32(FPS * tau[c]))
-        f = FPS * ttau[c] + (f32 - FPS * tau[c])
-        fl = float(np.floor(f32))
+        # the frame position f = fps * tau in float64; floor(f) is held
+        # fixed, so d alpha / d time = fps
+        f = FPS * ttau[c]
+        fl = float(np.floor(FPS * tau[c]))
         k0 = int(fl) % T
         k1 = (k0 + 1) % T
         al = f - fl
@@ -134,13 +133,14 @@ def test_special_points():
     w0 = np.zeros(1)
     g_kq, g_kt, _, _ = pose_sample_backward(offsets, kq, kt, ca, cb, tau, w0, gq, gt, FPS)
     assert np.all(g_kq[cb[0]] == 0.0) and np.all(g_kt[cb[0]] == 0.0)
-    on_key = np.array([3.0 / FPS])  # f = 3 exactly in fp32 and fp64
+    on_key = np.array([0.5])  # f = 15 exactly (0.5 is an fp32 value): k0 = 15 mod 6 = 3
     g_kq, g_kt, _, _ = pose_sample_backward(offsets, kq, kt, ca, cb, on_key, w, gq, gt, FPS)
     assert np.all(g_kq[:, 4] == 0.0) and np.all(g_kt[:, 4] == 0.0)
+    assert np.any(g_kq[:, 3] != 0.0)
     # translations only: g_kt[A, k0] = (1 - w)(1 - alpha) gt, g_kt[B, k1] = w alpha gt
     zero_q = np.zeros_like(gq)
     g_kq, g_kt, g_tau, g_w = pose_sample_backward(offsets, kq, kt, ca, cb, tau, w, zero_q, gt, FPS)
-    f = float(np.float32(FPS * np.float32(tau[0])))
+    f = FPS * float(np.float32(tau[0]))
     al, k0 = f - np.floor(f), int(np.floor(f)) % kq.shape[1]
     np.testing.assert_allclose(g_kt[ca[0], k0], (1 - w[0]) * (1 - al) * gt, atol=1e-12)
     np.testing.assert_allclose(g_kt[cb[0], (k0 + 1) % kq.shape[1]], w[0] * al * gt, atol=1e-12)
