@@ -39,9 +39,12 @@
  * Errors
  *   Every call returns an hs_status.  Argument, alignment, aliasing and
  *   topology errors are detected on the host before anything is launched;
- *   a failed launch returns HS_ERR_DEVICE.  hs_last_error() returns a
- *   thread-local description of the last failure on the calling thread.
- *   NaN and Inf inputs are not errors: they propagate into the outputs.
+ *   a failed launch returns HS_ERR_DEVICE.  What goes wrong inside a kernel
+ *   is recorded in the plan's device status word, which hs_plan_status
+ *   reads after synchronising (HS_ERR_DEVICE if any bit is set).
+ *   hs_last_error() returns a thread-local description of the last failure
+ *   on the calling thread.  NaN and Inf inputs are not errors: they
+ *   propagate into the outputs.
  */
 #ifndef HS_H_
 #define HS_H_
@@ -115,15 +118,17 @@ typedef struct hs_plan_opts {
     int32_t reserved[1];    /* must be zero */
 } hs_plan_opts;
 
-/* Adjoint kernels for characters of up to 1024 joints (larger ones always
- * take the dataflow kernel up to 1664 joints, then the multipass adjoint).
+/* Adjoint kernels for characters of up to 1024 joints in recompute mode
+ * (hs_scan_backward without checkpoints; larger characters always take the
+ * dataflow kernel up to 1664 joints, then the multipass adjoint).
  * HS_ADJ_ROUNDS: tile-wide synchronous reverse pointer-jumping rounds, one
  * joint per thread, workgroup barriers between rounds; recomputes every G_j
- * on chip and reads no checkpoints.  HS_ADJ_DATAFLOW: wave-level rounds per
- * 64-joint block, blocks ordered by LDS flags (no workgroup barriers between
- * rounds); reads checkpoints when given.  HS_ADJ_AUTO picks HS_ADJ_ROUNDS
- * (measured faster: blocks of long chains wait for each other in turn under
- * HS_ADJ_DATAFLOW). */
+ * on chip.  HS_ADJ_DATAFLOW: wave-level rounds per 64-joint block, blocks
+ * ordered by LDS flags (no workgroup barriers between rounds).  HS_ADJ_AUTO
+ * picks HS_ADJ_ROUNDS (measured faster: blocks of long chains wait for each
+ * other in turn under HS_ADJ_DATAFLOW).  Given checkpoints, characters of
+ * up to 1664 joints always run the dataflow kernel, which rebuilds each G_j
+ * from them. */
 #define HS_ADJ_AUTO 0
 #define HS_ADJ_ROUNDS 1
 #define HS_ADJ_DATAFLOW 2
@@ -195,6 +200,51 @@ hs_status hs_plan_create_instanced(hs_context *ctx, const hs_skeleton_set *skel,
                                    const int32_t *skeleton_id, const hs_plan_opts *opts, hs_plan **out);
 void hs_plan_destroy(hs_plan *plan);
 hs_status hs_plan_get_info(const hs_plan *plan, hs_plan_info *out);
+
+/* ------------------------------------------------------------------------
+ * Device status.  The scan relies on the ordering the paper obtains from a
+ * tree traversal (Sec. 3.2.1): every parent precedes its children, so a
+ * block of the tile only ever waits for earlier blocks.  The plan checks
+ * this on the host at creation; on the device two things are recorded in a
+ * status word the plan owns (one per plan, shared by all its calls):
+ *   HS_DEV_WAIT_TIMEOUT  a kernel's bounded wait for an earlier block gave
+ *                        up (the ordering was broken, or the plan's wait
+ *                        limit was lowered); the kernel went on with
+ *                        whatever it held, so outputs since are unreliable;
+ *   HS_DEV_TOPOLOGY      a call with HS_FLAG_VALIDATE found the plan's
+ *                        device tables breaking the ordering: some joint's
+ *                        parent outside [-1, j) of its character, or its
+ *                        level not its parent's plus one.  That call's
+ *                        kernels then do nothing (outputs unwritten).
+ * ------------------------------------------------------------------------ */
+#define HS_DEV_WAIT_TIMEOUT 1u
+#define HS_DEV_TOPOLOGY 2u
+
+/* Flag of hs_scan_forward and hs_scan_backward: re-check the plan's device
+ * topology tables (one extra pass over parents and levels, on the call's
+ * stream, ahead of the scan) into the status word. */
+#define HS_FLAG_VALIDATE 1u
+
+/* Synchronise the plan's device, then read its status word: *bits (if
+ * non-NULL) receives the HS_DEV_* bits, *joint (if non-NULL) the lowest
+ * global joint id that failed the topology check, or -1.  clear != 0 resets
+ * the word.  Returns HS_OK when no bit is set, HS_ERR_DEVICE with a
+ * description (hs_last_error) otherwise. */
+hs_status hs_plan_status(const hs_plan *plan, uint32_t *bits, int64_t *joint, int32_t clear);
+
+/* The number of polls after which a kernel's bounded wait gives up and
+ * records HS_DEV_WAIT_TIMEOUT (default 4194304, far beyond any wait the
+ * ordering allows).  For tests of the error path: with 0 every wait that
+ * is needed at all gives up at once.  Every kernel still runs to its end.
+ * Takes effect for calls made after it. */
+hs_status hs_plan_set_wait_limit(hs_plan *plan, int32_t polls);
+
+/* For tests of HS_FLAG_VALIDATE: overwrites joint's entry of the plan's
+ * device parent table with the joint itself (a parent that does not
+ * precede its child), as a stray device write might.  Synchronous.  Only
+ * calls with HS_FLAG_VALIDATE should follow: they detect it and launch no
+ * scan work; destroy the plan afterwards. */
+hs_status hs_plan_debug_break_parent(hs_plan *plan, int64_t joint);
 
 /* ------------------------------------------------------------------------
  * Simulation step (Sec. 1, step 1): looping clips, sampled and blended.
@@ -282,7 +332,8 @@ typedef struct hs_pose_src {
  *                        for joints whose level (root = 1) is a multiple of
  *                        ckpt_k, other rows untouched -- the checkpoints
  *                        hs_scan_backward may read instead of recomputing.
- * At least one of global_out, skin_out must be non-NULL.  flags must be 0. */
+ * At least one of global_out, skin_out must be non-NULL.  flags: 0 or
+ * HS_FLAG_VALIDATE. */
 hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *global_out,
                           const float *inv_bind, float *skin_out, float *ckpt_out, int32_t ckpt_k,
                           uint32_t flags, hipStream_t stream);
@@ -328,14 +379,16 @@ void hs_graph_destroy(hs_graph *graph);
  * bottom row is constant), writes dLoss/dq (grad_quat [N,4], derivative of
  * the rotation polynomial in the raw quaternion components), dLoss/dt
  * (grad_trans [N,3]) and, if non-NULL, dLoss/ds (grad_scale [N,3]).  The
- * global transforms the adjoint needs are recomputed (ckpt NULL) or, for
- * characters of 1025-1664 joints, rebuilt from the checkpoints that
- * hs_scan_forward stored with the same ckpt_k; characters of up to 1024
- * joints get them as a by-product of the adjoint's own doubling, and larger
- * ones from one forward pass over their anchors, so ckpt is not read there.
- * The results agree up to rounding either way.  Not bitwise reproducible
+ * global transforms the adjoint needs are recomputed (ckpt NULL: for
+ * characters of up to 1024 joints as a by-product of the adjoint's own
+ * doubling) or, for characters of up to 1664 joints, rebuilt from the
+ * checkpoints that hs_scan_forward stored with the same ckpt_k, each G_j
+ * as its nearest checkpointed ancestor's rows times at most ckpt_k - 1
+ * local transforms (the dataflow kernel).  Larger characters get them from
+ * one forward pass over their anchors, so ckpt is not read there.  The
+ * results agree up to rounding either way.  Not bitwise reproducible
  * across runs where pushes collide (float atomics).
- * src must be HS_POSE_TRS.  flags must be 0. */
+ * src must be HS_POSE_TRS.  flags: 0 or HS_FLAG_VALIDATE. */
 hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const float *grad_global,
                            const float *ckpt, int32_t ckpt_k, float *grad_quat, float *grad_trans,
                            float *grad_scale, uint32_t flags, hipStream_t stream);

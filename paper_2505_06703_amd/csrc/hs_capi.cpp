@@ -107,6 +107,7 @@ int ceil_log2(int64_t v)
 }
 
 static_assert(hs::kAdjRounds == HS_ADJ_ROUNDS && hs::kAdjDataflow == HS_ADJ_DATAFLOW, "adjoint kinds");
+static_assert(hs::kStatusWaitTimeout == HS_DEV_WAIT_TIMEOUT && hs::kStatusTopology == HS_DEV_TOPOLOGY, "status bits");
 
 struct Shape {
     int tile_cap = 0;
@@ -207,6 +208,10 @@ struct hs_plan {
     int64_t skel_joints = 0;
     int32_t *d_skel_parent = nullptr;
     int32_t *d_char_skel = nullptr;
+    // device status word (bits, lowest failing joint) and the polls of the
+    // kernels' bounded waits
+    uint32_t *d_status = nullptr;
+    int32_t spin_limit = hs::kDefaultSpinLimit;
 };
 
 namespace {
@@ -225,6 +230,7 @@ void free_plan(hs_plan *p)
     free_mpset(p->bmp);
     (void)hipFree(p->d_skel_parent);
     (void)hipFree(p->d_char_skel);
+    (void)hipFree(p->d_status);
     delete p;
 }
 
@@ -505,6 +511,11 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
         if (adjoint && err == hipSuccess) err = hipMalloc(&m.S[i], na * 3 * sizeof(float4));
     }
     if (adjoint && err == hipSuccess) err = hipMalloc(&m.G, n * 3 * sizeof(float4));
+    // anchor pointers start as "none": the rounds index with them, so they
+    // never hold uninitialised values (even if a validating call's check
+    // keeps the first pass from writing them)
+    if (err == hipSuccess) err = hipMemset(m.E1, 0xFF, na * sizeof(int32_t));
+    for (int i = 0; i < 2 && err == hipSuccess; ++i) err = hipMemset(m.AE[i], 0xFF, na * sizeof(int32_t));
     if (err != hipSuccess) {
         free_mpset(m);
         return fail_hip(err, "hs_plan_create (multipass workspace)");
@@ -612,8 +623,10 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     return HS_OK;
 }
 
-// The main tile set (k < 0) or size class k.
-hs::TileLaunch tile_launch(const hs_plan *p, int k = -1)
+// The main tile set (k < 0) or size class k.  validate: the call checked
+// the topology on the device first; its kernels then do nothing if the
+// check failed.
+hs::TileLaunch tile_launch(const hs_plan *p, int k = -1, bool validate = false)
 {
     hs::TileLaunch tl{};
     if (k < 0) {
@@ -637,10 +650,13 @@ hs::TileLaunch tile_launch(const hs_plan *p, int k = -1)
         tl.skel_parent = p->d_skel_parent;
         tl.char_skel = p->d_char_skel;
     }
+    tl.status = p->d_status;
+    tl.spin_limit = p->spin_limit;
+    tl.gate = validate ? p->d_status : nullptr;
     return tl;
 }
 
-hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
+hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m, bool validate = false)
 {
     hs::MPLaunch ml{};
     ml.blocks = m.d_blocks;
@@ -661,7 +677,18 @@ hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m)
         ml.AE[i] = m.AE[i];
         ml.S[i] = m.S[i];
     }
+    ml.gate = validate ? p->d_status : nullptr;
     return ml;
+}
+
+// HS_FLAG_VALIDATE: the topology check of the plan's device tables, on the
+// call's stream ahead of its kernels.
+hs_status launch_validate(const hs_plan *plan, hipStream_t stream, const char *what)
+{
+    hipError_t err = hs::launch_validate(plan->d_offsets, plan->C, plan->d_parent, plan->d_level, plan->d_status,
+                                         stream);
+    if (err != hipSuccess) return fail_hip(err, what);
+    return HS_OK;
 }
 
 hs_status check_pose_src(const hs_plan *plan, const hs_pose_src *src, hs::PoseArgs &pa,
@@ -721,14 +748,18 @@ hs_status check_pose_src(const hs_plan *plan, const hs_pose_src *src, hs::PoseAr
 }
 
 hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::OutArgs &oa,
-                      hipStream_t stream)
+                      hipStream_t stream, bool validate = false)
 {
+    if (validate) {
+        hs_status rc = launch_validate(plan, stream, "hs_scan_forward (validate)");
+        if (rc != HS_OK) return rc;
+    }
     hipError_t err = hipSuccess;
     for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
-        err = hs::launch_forward_tiles(tile_launch(plan, k), pa, oa, stream);
-    if (err == hipSuccess) err = hs::launch_forward_tiles(tile_launch(plan), pa, oa, stream);
+        err = hs::launch_forward_tiles(tile_launch(plan, k, validate), pa, oa, stream);
+    if (err == hipSuccess) err = hs::launch_forward_tiles(tile_launch(plan, -1, validate), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (tiles)");
-    err = hs::launch_forward_multipass(mp_launch(plan, plan->mp), pa, oa, stream);
+    err = hs::launch_forward_multipass(mp_launch(plan, plan->mp, validate), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (multipass)");
     return HS_OK;
 }
@@ -866,7 +897,7 @@ hs_status prepare_forward(const hs_plan *plan, const hs_pose_src *src, float *gl
 {
     *empty = true;
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: plan is NULL");
-    if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: flags must be 0");
+    if (flags & ~HS_FLAG_VALIDATE) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: unknown flags 0x%x", flags);
     if (ckpt_out && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: ckpt_k must be >= 1");
     if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
     if (!global_out && !skin_out) return fail(HS_ERR_INVALID_ARG, "hs_scan_forward: no output requested");
@@ -1093,6 +1124,14 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
         return fail_hip(err, "hs_plan_create (upload)");
     }
 
+    {
+        // status word: no bits, no failing joint
+        const std::vector<uint32_t> st = {0u, 0xFFFFFFFFu};
+        if ((err = upload(&plan->d_status, st)) != hipSuccess) {
+            free_plan(plan);
+            return fail_hip(err, "hs_plan_create (status word)");
+        }
+    }
     if (inst) {
         plan->inst = true;
         plan->skel_joints = (int64_t)inst->parents->size();
@@ -1177,6 +1216,60 @@ hs_status hs_plan_get_info(const hs_plan *plan, hs_plan_info *out)
 {
     if (!plan || !out) return fail(HS_ERR_INVALID_ARG, "hs_plan_get_info: NULL argument");
     *out = plan->info;
+    return HS_OK;
+}
+
+hs_status hs_plan_status(const hs_plan *plan, uint32_t *bits, int64_t *joint, int32_t clear)
+{
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_plan_status: plan is NULL");
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_plan_status: cannot select device");
+    hipError_t err = hipDeviceSynchronize();
+    if (err != hipSuccess) return fail_hip(err, "hs_plan_status (synchronize)");
+    uint32_t st[2];
+    if ((err = hipMemcpy(st, plan->d_status, sizeof st, hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail_hip(err, "hs_plan_status (read)");
+    if (bits) *bits = st[0];
+    if (joint) *joint = st[1] == 0xFFFFFFFFu ? -1 : (int64_t)st[1];
+    if (clear && st[0] != 0) {
+        const uint32_t fresh[2] = {0u, 0xFFFFFFFFu};
+        if ((err = hipMemcpy(plan->d_status, fresh, sizeof fresh, hipMemcpyHostToDevice)) != hipSuccess)
+            return fail_hip(err, "hs_plan_status (clear)");
+    }
+    if (st[0] == 0) return HS_OK;
+    std::string msg;
+    if (st[0] & HS_DEV_TOPOLOGY) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "device topology check failed (first bad joint %lld)",
+                 st[1] == 0xFFFFFFFFu ? -1LL : (long long)st[1]);
+        msg += buf;
+    }
+    if (st[0] & HS_DEV_WAIT_TIMEOUT) {
+        if (!msg.empty()) msg += "; ";
+        msg += "a kernel's bounded wait gave up (outputs of the calls since the last clear are unreliable)";
+    }
+    return fail(HS_ERR_DEVICE, "hs_plan_status: %s", msg.c_str());
+}
+
+hs_status hs_plan_set_wait_limit(hs_plan *plan, int32_t polls)
+{
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_plan_set_wait_limit: plan is NULL");
+    if (polls < 0) return fail(HS_ERR_INVALID_ARG, "hs_plan_set_wait_limit: polls must be >= 0");
+    plan->spin_limit = polls;
+    return HS_OK;
+}
+
+hs_status hs_plan_debug_break_parent(hs_plan *plan, int64_t joint)
+{
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_plan_debug_break_parent: plan is NULL");
+    if (joint < 0 || joint >= plan->N)
+        return fail(HS_ERR_INVALID_ARG, "hs_plan_debug_break_parent: joint %lld outside [0, %lld)",
+                    (long long)joint, (long long)plan->N);
+    DeviceGuard dg(plan->ctx->device);
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_plan_debug_break_parent: cannot select device");
+    const int32_t self = (int32_t)joint;
+    hipError_t err = hipMemcpy(plan->d_parent + joint, &self, sizeof self, hipMemcpyHostToDevice);
+    if (err != hipSuccess) return fail_hip(err, "hs_plan_debug_break_parent");
     return HS_OK;
 }
 
@@ -1276,7 +1369,7 @@ hs_status hs_scan_forward(const hs_plan *plan, const hs_pose_src *src, float *gl
     if (rc != HS_OK || empty) return rc;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_forward: cannot select device");
-    return run_forward(plan, pa, oa, stream);
+    return run_forward(plan, pa, oa, stream, (flags & HS_FLAG_VALIDATE) != 0);
 }
 
 hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
@@ -1418,16 +1511,23 @@ namespace {
 // The adjoint's launches: synchronous-round (or dataflow) tiles, the large
 // dataflow tiles, then the multipass characters.
 hs_status run_backward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::BwdArgs &ba, hipStream_t stream,
-                       const char *what)
+                       const char *what, bool validate = false)
 {
-    hs::TileLaunch tl = tile_launch(plan);
+    if (validate) {
+        hs_status rc = launch_validate(plan, stream, what);
+        if (rc != HS_OK) return rc;
+    }
+    hs::TileLaunch tl = tile_launch(plan, -1, validate);
     tl.chain_units = 0;
     hipError_t err = hipSuccess;
     if (plan->num_btiles > 0) {
         tl.tiles = plan->d_btiles;
         tl.num_tiles = plan->num_btiles;
         tl.tile_cap = plan->bwd_cap;
-        tl.adjoint = plan->shape.adjoint;
+        // with checkpoints the dataflow kernel rebuilds every G_j from its
+        // nearest checkpointed ancestor; without, the plan's kernel
+        // recomputes them (the synchronous rounds: as their jump products)
+        tl.adjoint = ba.ckpt ? hs::kAdjDataflow : plan->shape.adjoint;
         tl.grid = plan->num_btiles;
         tl.waves = 1;  // dataflow: a power of two, at most one wave per block
         while (tl.waves < 16 && tl.waves * 2 * 64 <= plan->bwd_cap) tl.waves *= 2;
@@ -1443,7 +1543,7 @@ hs_status run_backward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Bw
         err = hs::launch_backward_tiles(tl, pa, ba, stream);
         if (err != hipSuccess) return fail_hip(err, (std::string(what) + " (large tiles)").c_str());
     }
-    err = hs::launch_backward_multipass(mp_launch(plan, plan->bmp), pa, ba, stream);
+    err = hs::launch_backward_multipass(mp_launch(plan, plan->bmp, validate), pa, ba, stream);
     if (err != hipSuccess) return fail_hip(err, (std::string(what) + " (multipass)").c_str());
     return HS_OK;
 }
@@ -1595,7 +1695,7 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
                            hipStream_t stream)
 {
     if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: plan is NULL");
-    if (flags != 0) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: flags must be 0");
+    if (flags & ~HS_FLAG_VALIDATE) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: unknown flags 0x%x", flags);
     if (ckpt && ckpt_k < 1) return fail(HS_ERR_INVALID_ARG, "hs_scan_backward: ckpt_k must be >= 1");
     if (plan->N == 0) return HS_OK;  // zero-size arrays may be NULL
     if (!grad_global || !grad_quat || !grad_trans)
@@ -1626,7 +1726,7 @@ hs_status hs_scan_backward(const hs_plan *plan, const hs_pose_src *src, const fl
     ba.grad_scale = grad_scale;
     DeviceGuard dg(plan->ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_scan_backward: cannot select device");
-    return run_backward(plan, pa, ba, stream, "hs_scan_backward");
+    return run_backward(plan, pa, ba, stream, "hs_scan_backward", (flags & HS_FLAG_VALIDATE) != 0);
 }
 
 } // extern "C"

@@ -25,6 +25,15 @@ constexpr int kMaxSyncTileJoints = 1024;
 // thread each; 52 bytes of LDS per anchor).
 constexpr int kAnchorSegCap = 1024;
 
+// Device status word of a plan (two 32-bit words): word 0 collects the bits
+// below, word 1 the lowest global joint id that failed the topology check
+// (0xFFFFFFFF while none has).  The values equal HS_DEV_* of hs.h.
+constexpr uint32_t kStatusWaitTimeout = 1u; // a bounded wait gave up
+constexpr uint32_t kStatusTopology = 2u;    // the device topology check failed
+
+// Polls a bounded wait makes before it gives up (the plan's default).
+constexpr int kDefaultSpinLimit = 1 << 22;
+
 // A tile: a contiguous range of global joint ids holding whole characters,
 // scanned by one workgroup entirely in LDS.
 struct TileDesc {
@@ -98,6 +107,12 @@ struct TileLaunch {
     // and inverse binds; both are read through the skeleton's first joint
     const int32_t *skel_parent; // [skeleton joints] skeleton-local parent or -1
     const int32_t *char_skel;   // [C] first skeleton joint of each character's skeleton
+    // the plan's status word and the polls of a bounded wait; gate (null
+    // unless the call validates): the kernels do nothing once its topology
+    // bit is set
+    uint32_t *status;
+    int32_t spin_limit;
+    const uint32_t *gate;
 };
 
 struct MPLaunch {
@@ -123,6 +138,7 @@ struct MPLaunch {
     // adjoint workspace (NULL when the plan has none)
     float4 *S[2];             // [num_anchors*3] ping-pong anchor adjoints
     float4 *G;                // [Nmp*3] global transforms
+    const uint32_t *gate;     // as TileLaunch::gate
 };
 
 struct BwdArgs {
@@ -167,6 +183,14 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 // Raise the dynamic-LDS limit of every tile kernel to what its largest tile
 // needs (once per process and device, before any launch or capture).
 hipError_t prepare_kernels();
+
+// Topology check of a plan's device tables (HS_FLAG_VALIDATE): for every
+// joint g of character c, parent[g] is -1 with level[g] = 1, or lies in
+// [offsets[c], g) with level[g] = level[parent[g]] + 1; offsets must be
+// non-decreasing.  Failures set kStatusTopology in status[0] and the lowest
+// failing joint in status[1].
+hipError_t launch_validate(const int64_t *offsets, int64_t num_chars, const int32_t *parent, const int32_t *level,
+                           uint32_t *status, hipStream_t stream);
 
 hipError_t launch_effector_grad(int64_t n, int64_t ne, const int64_t *eff, const float *G, const float *target,
                                 float *grad, hipStream_t stream);

@@ -46,7 +46,20 @@ namespace hs {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kSpinLimit = 1 << 22;
+
+// Record status bits in the plan's status word (device scope).
+__device__ __forceinline__ void note_status(uint32_t *status, uint32_t bits)
+{
+    __hip_atomic_fetch_or(status, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True when the call validates and the device topology check has failed:
+// the kernel then does nothing (the check ran earlier on the same stream,
+// so every thread of the launch reads the same final value).
+__device__ __forceinline__ bool gated(const uint32_t *gate)
+{
+    return gate && (__hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusTopology);
+}
 
 // ---------------------------------------------------------------------------
 // 3x4 affine helpers (row-major, m[4*r + c], column 3 = translation)
@@ -317,23 +330,7 @@ __device__ __forceinline__ void write_skin_and_ckpt(const OutArgs &out, int64_t 
 // LDS: G[cap][3] float4 | unit partials [cap/64][3] float4 | block flags,
 // partial flags, partial anchors [cap/64] int | (SAMPLE) char starts [cap+1]
 // ---------------------------------------------------------------------------
-// Bounded wait until the block of tile-local joint e (if e >= 0) has
-// published its final transforms.  The bound only guards against a broken
-// invariant: after kSpinLimit polls (far beyond any legitimate wait) the
-// caller proceeds with whatever the LDS holds instead of hanging the device.
-__device__ __forceinline__ void wait_block_of(const int *flags, int e)
-{
-    const bool need = e >= 0;
-    const int fb = need ? (e / kWave) : 0;
-    for (int spin = 0; spin < kSpinLimit; ++spin) {
-        const int ok = need ? __hip_atomic_load(flags + fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 1;
-        if (__all(ok)) break;
-        __builtin_amdgcn_s_sleep(1);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// LDS of the tiled forward kernel.
+// LDS of the tiled forward kernel, and the bound of its waits.
 struct FwdShared {
     float4 *G;       // [cap][3] final transforms (rows 0-2)
     float4 *part;    // [cap/64][3] partial product of a chain unit's last segment
@@ -341,7 +338,28 @@ struct FwdShared {
     int *pflag;      // [cap/64] partial of the unit ending with this block published
     int *panc;       // [cap/64] anchor of that partial (tile-local id, or -1)
     int *cstart;     // (pose sampling) character starts
+    uint32_t *status; // the plan's status word
+    int spin;         // polls of a bounded wait
 };
+
+// Bounded wait until the block of tile-local joint e (if e >= 0) has
+// published its final transforms.  The bound only guards against a broken
+// invariant: after sh.spin polls (far beyond any legitimate wait) the wave
+// records kStatusWaitTimeout in the plan's status word and proceeds with
+// whatever the LDS holds instead of hanging the device.
+__device__ __forceinline__ void wait_block_of(const FwdShared &sh, int e)
+{
+    const bool need = e >= 0;
+    const int fb = need ? (e / kWave) : 0;
+    bool done = !__any(need);
+    for (int spin = 0; !done && spin < sh.spin; ++spin) {
+        const int ok = need ? __hip_atomic_load(sh.flags + fb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 1;
+        done = __all(ok);
+        if (!done) __builtin_amdgcn_s_sleep(1);
+    }
+    if (!done) note_status(sh.status, kStatusWaitTimeout);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 // m <- G_e m for tile-local joint e (no-op for e < 0), waiting (bounded, as
 // above) until e's transform is known: either e's block has published, or
@@ -351,7 +369,7 @@ struct FwdShared {
 // unit's scan is done instead of after its final pass.
 __device__ __forceinline__ void compose_final(const FwdShared &sh, int e, float m[12])
 {
-    for (int spin = 0; spin < kSpinLimit; ++spin) {
+    for (int spin = 0; spin < sh.spin; ++spin) {
         if (__all(e < 0)) break;
         int fin = 0, step = 0;
         if (e >= 0) {
@@ -375,6 +393,7 @@ __device__ __forceinline__ void compose_final(const FwdShared &sh, int e, float 
         }
         if (!__any(fin | step)) __builtin_amdgcn_s_sleep(1);
     }
+    if (__any(e >= 0)) note_status(sh.status, kStatusWaitTimeout);
 }
 
 // Publish blocks [b0, b0 + nb) of the tile: their final transforms are in LDS.
@@ -464,7 +483,7 @@ __device__ __forceinline__ void block_finish(const OutArgs &out, const TileDesc 
     const int base = b * kWave;
     const int jl = base + lane;
     const bool valid = jl < n;
-    wait_block_of(sh.flags, valid ? e : -1);
+    wait_block_of(sh, valid ? e : -1);
     if (valid && e >= 0) {
         float g[12];
         aff_load(Gs + 3 * e, g);
@@ -713,6 +732,7 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
     constexpr bool CHAIN = MODE == 1;
     constexpr bool INST = MODE == 2;
     extern __shared__ float4 lds[];
+    if (gated(tl.gate)) return;
     const int cap = tl.tile_cap;
     const int nbk = cap >> 6;
     FwdShared sh;
@@ -722,6 +742,8 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
     sh.pflag = sh.flags + nbk;
     sh.panc = sh.pflag + nbk;
     sh.cstart = sh.panc + nbk;
+    sh.status = tl.status;
+    sh.spin = tl.spin_limit;
     int *cstart = sh.cstart;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -785,6 +807,7 @@ __global__ void __launch_bounds__(1024)
 paper_alg_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 {
     extern __shared__ float4 lds[];
+    if (gated(tl.gate)) return;
     const int cap = tl.tile_cap;
     float4 *As = lds;
     float4 *Bs = lds + 3 * cap;
@@ -1050,6 +1073,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
 bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 {
     extern __shared__ float4 lds[];
+    if (gated(tl.gate)) return;
     const int cap = tl.tile_cap;
     float4 *Gs = lds;
     float4 *Ds = lds + 3 * cap;
@@ -1094,13 +1118,15 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
                 wave_inblock_scan(m, a, e, lane);
                 const bool need = valid && e >= 0;
                 const int fb = need ? (e / kWave) : 0;
-                for (int spin = 0; spin < kSpinLimit; ++spin) {
+                bool done = !__any(need);
+                for (int spin = 0; !done && spin < tl.spin_limit; ++spin) {
                     const int ok = need ? __hip_atomic_load(flags + fb, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_WORKGROUP)
                                         : 1;
-                    if (__all(ok)) break;
-                    __builtin_amdgcn_s_sleep(1);
+                    done = __all(ok);
+                    if (!done) __builtin_amdgcn_s_sleep(1);
                 }
+                if (!done) note_status(tl.status, kStatusWaitTimeout);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                 if (need) {
                     float g[12];
@@ -1188,11 +1214,13 @@ bwd_tile_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
                 for (int k = 0; k < 12; ++k) S[k] = 0.0f;
             }
             const int want = expect[b];
-            for (int spin = 0; spin < kSpinLimit; ++spin) {
+            bool done = want == 0;
+            for (int spin = 0; !done && spin < tl.spin_limit; ++spin) {
                 const int got = __hip_atomic_load(recv + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (__all(got >= want)) break;
-                __builtin_amdgcn_s_sleep(1);
+                done = __all(got >= want);
+                if (!done) __builtin_amdgcn_s_sleep(1);
             }
+            if (!done) note_status(tl.status, kStatusWaitTimeout);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             if (valid) {
                 float acc[12];
@@ -1321,6 +1349,7 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 {
     constexpr bool EFF = SEED != kSeedDense;
     extern __shared__ float4 lds[];
+    if (gated(tl.gate)) return;
     const int cap = tl.tile_cap;
     float4 *Ms = lds;
     float4 *In = lds + 3 * cap;
@@ -1381,6 +1410,8 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             FwdShared sh{};
             sh.G = In;
             sh.flags = Fl;
+            sh.status = tl.status;
+            sh.spin = tl.spin_limit;
             OutArgs out{};
             out.global_out = bwd.eff_global_out;
             const int wave = jl / kWave;
@@ -2018,6 +2049,7 @@ __global__ void __launch_bounds__(WAVES * kWave)
 fwd_vertex_kernel(TileLaunch tl, PoseArgs pose, OutArgs out, VertexLaunch vl, float *vout)
 {
     extern __shared__ float4 lds[];
+    if (gated(tl.gate)) return;
     constexpr int T = WAVES * kWave;
     const int cap = tl.tile_cap;
     const int nbk = cap >> 6;
@@ -2028,6 +2060,8 @@ fwd_vertex_kernel(TileLaunch tl, PoseArgs pose, OutArgs out, VertexLaunch vl, fl
     sh.pflag = sh.flags + nbk;
     sh.panc = sh.pflag + nbk;
     sh.cstart = sh.panc + nbk;
+    sh.status = tl.status;
+    sh.spin = tl.spin_limit;
     int *cstart = sh.cstart;
     int *vstart = cstart + cap + 1;
     const int lane = threadIdx.x & (kWave - 1);
@@ -2149,6 +2183,7 @@ template <bool SAMPLE>
 __global__ void __launch_bounds__(kMPWaves * kWave)
 mp_local_kernel(MPLaunch ml, PoseArgs pose)
 {
+    if (gated(ml.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
     if (w >= ml.num_blocks) return;  // whole waves leave together
@@ -2257,6 +2292,7 @@ __global__ void __launch_bounds__(kMPWaves * kWave)
 mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 *Gc)
 {
     __shared__ float4 stage[kMPWaves * kWave * 3];
+    if (gated(ml.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int w = blockIdx.x * kMPWaves + wv;
@@ -2389,6 +2425,7 @@ __global__ void __launch_bounds__(kMPWaves * kWave)
 mpr_block_kernel(MPLaunch ml, PoseArgs pose, BwdArgs bwd, float4 *Sanc)
 {
     extern __shared__ float4 lds[];
+    if (gated(ml.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     float4 *Ms = lds + wv * kRevWaveFloat4;
@@ -2876,6 +2913,42 @@ hipError_t launch_effector_grad(int64_t n, int64_t ne, const int64_t *eff, const
     if (ne == 0) return hipSuccess;
     hipLaunchKernelGGL(effector_grad_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, stream, n, ne, eff,
                        G, target, grad);
+    return hipGetLastError();
+}
+
+// Device topology check (HS_FLAG_VALIDATE): one workgroup per character,
+// its threads over the character's joints.
+__global__ void __launch_bounds__(256)
+validate_kernel(const int64_t *offsets, int64_t num_chars, const int32_t *parent, const int32_t *level,
+                uint32_t *status)
+{
+    for (int64_t c = blockIdx.x; c < num_chars; c += gridDim.x) {
+        const int64_t b = offsets[c], e = offsets[c + 1];
+        if (e < b) {
+            if (threadIdx.x == 0) {
+                note_status(status, kStatusTopology);
+                atomicMin(status + 1, (uint32_t)b);
+            }
+            continue;
+        }
+        for (int64_t g = b + threadIdx.x; g < e; g += blockDim.x) {
+            const int32_t p = parent[g];
+            const bool ok = p < 0 ? (p == -1 && level[g] == 1)
+                                  : ((int64_t)p >= b && (int64_t)p < g && level[g] == level[p] + 1);
+            if (!ok) {
+                note_status(status, kStatusTopology);
+                atomicMin(status + 1, (uint32_t)g);
+            }
+        }
+    }
+}
+
+hipError_t launch_validate(const int64_t *offsets, int64_t num_chars, const int32_t *parent, const int32_t *level,
+                           uint32_t *status, hipStream_t stream)
+{
+    if (num_chars <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<int64_t>(num_chars, 65536);
+    hipLaunchKernelGGL(validate_kernel, dim3(grid), dim3(256), 0, stream, offsets, num_chars, parent, level, status);
     return hipGetLastError();
 }
 

@@ -35,13 +35,18 @@ HS_SKIN_LINEAR, HS_SKIN_DUAL_QUAT = 0, 1
 HS_POSE_TRS = 0
 HS_POSE_CLIPS = 1
 
+HS_DEV_WAIT_TIMEOUT = 1
+HS_DEV_TOPOLOGY = 2
+HS_FLAG_VALIDATE = 1
+
 SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
            "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
            "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
            "hs_graph_create_forward_n", "hs_graph_launch", "hs_graph_destroy", "hs_mesh_create",
            "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices",
            "hs_effector_loss_grad", "hs_effectors_create", "hs_effectors_destroy", "hs_effectors_sparse",
-           "hs_effector_backward", "hs_effector_step")
+           "hs_effector_backward", "hs_effector_step", "hs_plan_status", "hs_plan_set_wait_limit",
+           "hs_plan_debug_break_parent")
 
 
 class HSError(RuntimeError):
@@ -143,6 +148,9 @@ def load_library():
     lib.hs_plan_destroy.argtypes = [vp]
     lib.hs_plan_destroy.restype = None
     lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
+    lib.hs_plan_status.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(i64), i32]
+    lib.hs_plan_set_wait_limit.argtypes = [vp, i32]
+    lib.hs_plan_debug_break_parent.argtypes = [vp, i64]
     lib.hs_pose_sample.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
                                    vp, vp, vp]
     lib.hs_scan_forward.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, vp, vp, i32, u32, vp]
@@ -156,7 +164,7 @@ def load_library():
     lib.hs_graph_destroy.restype = None
     for name in ("hs_context_create", "hs_plan_create", "hs_plan_get_info", "hs_pose_sample",
                  "hs_scan_forward", "hs_skin", "hs_scan_backward", "hs_graph_create_forward",
-                 "hs_graph_launch"):
+                 "hs_graph_launch", "hs_plan_status", "hs_plan_set_wait_limit", "hs_plan_debug_break_parent"):
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -274,6 +282,26 @@ class Plan:
         par = np.concatenate([spar[soff[k]:soff[k + 1]] for k in sid]) if sid.size else np.zeros(0, np.int32)
         return cls(off, par, skeletons=(soff, spar, sid), **kw)
 
+    def status(self, clear=False):
+        """Synchronise and read the plan's device status word
+        (``hs_plan_status``): returns ``(status, bits, joint)`` -- the
+        hs_status (HS_OK, or HS_ERR_DEVICE when a bit is set), the HS_DEV_*
+        bits and the lowest joint that failed the topology check (-1 if
+        none).  Does not raise on HS_ERR_DEVICE."""
+        bits, joint = ctypes.c_uint32(), ctypes.c_int64()
+        rc = load_library().hs_plan_status(self.handle, ctypes.byref(bits), ctypes.byref(joint), int(bool(clear)))
+        if rc not in (HS_OK, HS_ERR_DEVICE):
+            _check(rc)
+        return rc, bits.value, joint.value
+
+    def set_wait_limit(self, polls):
+        """Polls after which a kernel's bounded wait gives up (``hs_plan_set_wait_limit``)."""
+        _check(load_library().hs_plan_set_wait_limit(self.handle, int(polls)))
+
+    def debug_break_parent(self, joint):
+        """Corrupt one entry of the plan's device parent table (``hs_plan_debug_break_parent``)."""
+        _check(load_library().hs_plan_debug_break_parent(self.handle, int(joint)))
+
     @property
     def info(self):
         inf = hs_plan_info()
@@ -369,7 +397,7 @@ def _trs_src(plan, quat, trans, scale):
 
 def hs_scan_forward(plan, quat=None, trans=None, scale=None, *, clips=None, clip_a=None, clip_b=None,
                     time=None, weight=None, global_out=None, want_global=True, inv_bind=None,
-                    skin_out=None, ckpt_out=None, ckpt_k=0, stream=None, device=None):
+                    skin_out=None, ckpt_out=None, ckpt_k=0, validate=False, stream=None, device=None):
     """Hierarchy-Scan with optional fused skin and checkpoints.
 
     Poses come from ``quat``/``trans``/``scale`` (TRS) or from ``clips`` and
@@ -397,7 +425,8 @@ def hs_scan_forward(plan, quat=None, trans=None, scale=None, *, clips=None, clip
     if ckpt_out is not None:
         _need(ckpt_out, "ckpt_out", (N, 12))
     _check(load_library().hs_scan_forward(plan.handle, ctypes.byref(src), _ptr(global_out), _ptr(inv_bind),
-                                          _ptr(skin_out), _ptr(ckpt_out), int(ckpt_k), 0, _stream(stream)))
+                                          _ptr(skin_out), _ptr(ckpt_out), int(ckpt_k),
+                                          HS_FLAG_VALIDATE if validate else 0, _stream(stream)))
     return global_out, skin_out
 
 
@@ -568,7 +597,7 @@ def hs_effector_step(plan, effectors, quat, trans, scale, targets, global_out=No
 
 
 def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0, want_scale=True,
-                     grad_quat=None, grad_trans=None, grad_scale=None, stream=None):
+                     grad_quat=None, grad_trans=None, grad_scale=None, validate=False, stream=None):
     """Adjoint of the scan: returns (grad_quat [N,4], grad_trans [N,3], grad_scale [N,3] or None)."""
     N = plan.num_joints
     src = _trs_src(plan, quat, trans, scale)
@@ -582,7 +611,8 @@ def hs_scan_backward(plan, quat, trans, scale, grad_global, ckpt=None, ckpt_k=0,
     if ckpt is not None:
         _need(ckpt, "ckpt", (N, 12))
     _check(load_library().hs_scan_backward(plan.handle, ctypes.byref(src), _ptr(grad_global), _ptr(ckpt),
-                                           int(ckpt_k), _ptr(gq), _ptr(gt), _ptr(gs), 0, _stream(stream)))
+                                           int(ckpt_k), _ptr(gq), _ptr(gt), _ptr(gs),
+                                           HS_FLAG_VALIDATE if validate else 0, _stream(stream)))
     return gq, gt, gs
 
 

@@ -71,7 +71,7 @@ def test_forward_argument_errors_launch_nothing():
     assert _call_forward(plan, qp + 4, tp, None, Gp) == hs.HS_ERR_INVALID_ARG        # misaligned quat
     assert _call_forward(plan, qp, tp, None, Gp + 4) == hs.HS_ERR_INVALID_ARG        # misaligned output
     assert _call_forward(plan, qp, tp, None, qp) == hs.HS_ERR_INVALID_ARG            # output aliases input
-    assert _call_forward(plan, qp, tp, None, Gp, flags=1) == hs.HS_ERR_INVALID_ARG   # unknown flags
+    assert _call_forward(plan, qp, tp, None, Gp, flags=4) == hs.HS_ERR_INVALID_ARG   # unknown flags
     assert _call_forward(plan, qp, tp, None, Gp, inv=Gp + 64) == hs.HS_ERR_INVALID_ARG  # inv without skin
     ck = torch.empty((N, 12), device=DEV)
     assert _call_forward(plan, qp, tp, None, Gp, ckpt=ck.data_ptr(), k=0) == hs.HS_ERR_INVALID_ARG
