@@ -307,6 +307,26 @@ hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, c
                                   float *grad_key_trans, float *grad_time, float *grad_weight, float *workspace,
                                   hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * reverse mode of hs_pose_sample with hs_pose_sample_backward's workspace
+ * route, the workspace being a static device array of the library
+ * (HS_NOALLOC_MAX_JOINTS joints x 32 bytes = 16 MiB, one copy per device,
+ * held until the process ends) instead of caller memory.  Arguments,
+ * layouts and outputs are those of hs_pose_sample_backward without
+ * `workspace`; the results equal that call's with a workspace, bit for bit
+ * (the same kernels).  The call allocates nothing.  A plan of more than
+ * HS_NOALLOC_MAX_JOINTS joints returns HS_ERR_INVALID_ARG with nothing
+ * launched.  The array needs no clearing: each call writes every entry it
+ * reads.  All calls on one device share that array, so calls that overlap
+ * in time on one device (other streams, other threads) race; serialise
+ * them. */
+#define HS_NOALLOC_MAX_JOINTS (1 << 19)
+hs_status hs_pose_sample_backward_noalloc(const hs_plan *plan, const hs_clip_lib *lib,
+                                          const hs_clip_params *params, const float *grad_quat,
+                                          const float *grad_trans, float *grad_key_quat, float *grad_key_trans,
+                                          float *grad_time, float *grad_weight, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Hierarchy-Scan (Sec. 1 step 2; Eq. 1; Sec. 3) with optional fused skin.
  * ------------------------------------------------------------------------ */

@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+static_assert(hs::kNoAllocMaxJoints == HS_NOALLOC_MAX_JOINTS, "static workspace size");
+
 using hs::MPBlock;
 using hs::TileDesc;
 
@@ -127,6 +129,7 @@ struct hs_context {
     std::string arch;
     std::mutex mu;
     std::map<std::string, Shape> tuned;  // autotuning cache keyed by arch + size class
+    float4 *noalloc_ws = nullptr;        // this device's static workspace (hs_pose_sample_backward_noalloc)
 };
 
 // Device tables and workspace of the multipass path.
@@ -950,15 +953,18 @@ hs_status hs_context_create(int device, hs_context **out)
     if (arch.rfind("gfx950", 0) != 0)
         return fail(HS_ERR_UNSUPPORTED, "hs_context_create: device %d is %s; this library targets gfx950",
                     device, arch.c_str());
+    float4 *noalloc_ws = nullptr;
     {
         int prev = -1;
         (void)hipGetDevice(&prev);
         if ((err = hipSetDevice(device)) != hipSuccess) return fail_hip(err, "hs_context_create");
         err = hs::prepare_kernels();
+        if (err == hipSuccess) err = hs::noalloc_workspace(device, &noalloc_ws);
         if (prev >= 0) (void)hipSetDevice(prev);
-        if (err != hipSuccess) return fail_hip(err, "hs_context_create (kernel attributes)");
+        if (err != hipSuccess) return fail_hip(err, "hs_context_create (kernel attributes, static workspace)");
     }
     hs_context *ctx = new hs_context();
+    ctx->noalloc_ws = noalloc_ws;
     ctx->device = device;
     ctx->num_cu = prop.multiProcessorCount;
     ctx->max_lds = prop.sharedMemPerBlock;
@@ -1403,12 +1409,29 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
     return HS_OK;
 }
 
-hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
-                                  const float *grad_quat, const float *grad_trans, float *grad_key_quat,
-                                  float *grad_key_trans, float *grad_time, float *grad_weight, float *workspace,
-                                  hipStream_t stream)
+} // extern "C"
+
+namespace {
+
+// Both routes of the sampler's reverse mode: `workspace` is caller memory
+// (hs_pose_sample_backward) or the device's static array
+// (hs_pose_sample_backward_noalloc, `noalloc`), in which case the batch
+// must fit the array.
+hs_status sample_backward(const char *name, const hs_plan *plan, const hs_clip_lib *lib,
+                          const hs_clip_params *params, const float *grad_quat, const float *grad_trans,
+                          float *grad_key_quat, float *grad_key_trans, float *grad_time, float *grad_weight,
+                          float *workspace, bool noalloc, hipStream_t stream)
 {
-    if (!plan) return fail(HS_ERR_INVALID_ARG, "hs_pose_sample_backward: plan is NULL");
+    if (!plan) return fail(HS_ERR_INVALID_ARG, "%s: plan is NULL", name);
+    if (noalloc) {
+        if (plan->N > hs::kNoAllocMaxJoints)
+            return fail(HS_ERR_INVALID_ARG,
+                        "%s: %lld joints exceed the static workspace of %lld joints (HS_NOALLOC_MAX_JOINTS); "
+                        "use hs_pose_sample_backward with a caller workspace",
+                        name, (long long)plan->N, (long long)hs::kNoAllocMaxJoints);
+        if (!plan->ctx->noalloc_ws) return fail(HS_ERR_DEVICE, "%s: no static workspace on this device", name);
+        workspace = reinterpret_cast<float *>(plan->ctx->noalloc_ws);
+    }
     hs_pose_src src{};
     src.kind = HS_POSE_CLIPS;
     src.clips = lib;
@@ -1419,12 +1442,11 @@ hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, c
     if (rc != HS_OK) return rc;
     const size_t N = (size_t)plan->N, C = (size_t)plan->C;
     if (N > 0 && (!grad_quat || !grad_trans))
-        return fail(HS_ERR_INVALID_ARG, "hs_pose_sample_backward: grad_quat and grad_trans must be non-NULL");
+        return fail(HS_ERR_INVALID_ARG, "%s: grad_quat and grad_trans must be non-NULL", name);
     if (!aligned(grad_quat, 16) || !aligned(grad_trans, 4) || !aligned(grad_key_quat, 4) ||
         !aligned(grad_key_trans, 4) || !aligned(grad_time, 4) || !aligned(grad_weight, 4) ||
         !aligned(workspace, 16))
-        return fail(HS_ERR_INVALID_ARG,
-                    "hs_pose_sample_backward: grad_quat and workspace must be 16-byte aligned, the rest 4");
+        return fail(HS_ERR_INVALID_ARG, "%s: grad_quat and workspace must be 16-byte aligned, the rest 4", name);
     ins.push_back({grad_quat, N * 16, "grad_quat"});
     ins.push_back({grad_trans, N * 12, "grad_trans"});
     const size_t keys = (size_t)lib->num_clips * lib->num_keys * lib->joints_per_clip;
@@ -1435,12 +1457,34 @@ hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, c
                                {workspace, workspace ? N * 32 : 0, "workspace"}};
     if ((rc = check_aliasing(outs, ins)) != HS_OK) return rc;
     DeviceGuard dg(plan->ctx->device);
-    if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_pose_sample_backward: cannot select device");
+    if (!dg.ok) return fail(HS_ERR_DEVICE, "%s: cannot select device", name);
     hs::SampleBwdArgs A{grad_quat, grad_trans, grad_key_quat, grad_key_trans, grad_time, grad_weight,
                         (int32_t)plan->C, reinterpret_cast<float4 *>(workspace)};
     hipError_t err = hs::launch_pose_sample_backward(pa, A, stream);
-    if (err != hipSuccess) return fail_hip(err, "hs_pose_sample_backward");
+    if (err != hipSuccess) return fail_hip(err, name);
     return HS_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+hs_status hs_pose_sample_backward(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
+                                  const float *grad_quat, const float *grad_trans, float *grad_key_quat,
+                                  float *grad_key_trans, float *grad_time, float *grad_weight, float *workspace,
+                                  hipStream_t stream)
+{
+    return sample_backward("hs_pose_sample_backward", plan, lib, params, grad_quat, grad_trans, grad_key_quat,
+                           grad_key_trans, grad_time, grad_weight, workspace, false, stream);
+}
+
+hs_status hs_pose_sample_backward_noalloc(const hs_plan *plan, const hs_clip_lib *lib,
+                                          const hs_clip_params *params, const float *grad_quat,
+                                          const float *grad_trans, float *grad_key_quat, float *grad_key_trans,
+                                          float *grad_time, float *grad_weight, hipStream_t stream)
+{
+    return sample_backward("hs_pose_sample_backward_noalloc", plan, lib, params, grad_quat, grad_trans,
+                           grad_key_quat, grad_key_trans, grad_time, grad_weight, nullptr, true, stream);
 }
 
 hs_status hs_effector_loss_grad(int64_t num_joints, int64_t num_effectors, const int64_t *effectors,

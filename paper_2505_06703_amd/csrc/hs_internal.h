@@ -211,6 +211,15 @@ struct SampleBwdArgs {
 };
 hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs &A, hipStream_t stream);
 
+// The allocation-free route of the sampler's reverse mode keeps its
+// workspace ([N][2] float4) in a static device array of this many joints.
+constexpr int64_t kNoAllocMaxJoints = 1 << 19;  // HS_NOALLOC_MAX_JOINTS
+constexpr int kMaxDevices = 64;
+// Device address of the calling thread's current device's copy of that
+// array (looked up once per device, then cached); call with `device`
+// current.
+hipError_t noalloc_workspace(int device, float4 **out);
+
 // Vertex skinning (after the Bind MeshPose step): character c's vertices
 // are output rows voff[c] .. voff[c+1]-1; its k-th vertex reads mesh row
 // mfirst[c] + k; joint ids are character-local (checked when the mesh is

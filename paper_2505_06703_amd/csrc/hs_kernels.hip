@@ -40,6 +40,7 @@
 #include "hs_internal.h"
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 
 namespace hs {
@@ -2752,6 +2753,31 @@ hipError_t set_lds_limits()
 }
 
 } // namespace
+
+// Workspace of the allocation-free reverse mode of the sampler
+// (hs_pose_sample_backward_noalloc): 2 float4 per joint for at most
+// kNoAllocMaxJoints joints.  Each device that loads the library holds its
+// own copy until the process ends; host code reaches it only through the
+// device address that noalloc_workspace() looks up (the symbol itself is
+// a host-side stand-in, not a device address).
+static __device__ __align__(256) float4 scratch[2 * (size_t)kNoAllocMaxJoints];
+
+hipError_t noalloc_workspace(int device, float4 **out)
+{
+    static std::mutex mu;
+    static float4 *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+        if (err != hipSuccess) return err;
+        addr[device] = static_cast<float4 *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
 
 hipError_t prepare_kernels()
 {

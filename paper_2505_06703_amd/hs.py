@@ -38,6 +38,7 @@ HS_POSE_CLIPS = 1
 HS_DEV_WAIT_TIMEOUT = 1
 HS_DEV_TOPOLOGY = 2
 HS_FLAG_VALIDATE = 1
+HS_NOALLOC_MAX_JOINTS = 1 << 19  # joints the static workspace of hs_pose_sample_backward_noalloc holds
 
 SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destroy",
            "hs_plan_create", "hs_plan_create_instanced", "hs_plan_destroy", "hs_plan_get_info", "hs_pose_sample",
@@ -46,7 +47,7 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices",
            "hs_effector_loss_grad", "hs_effectors_create", "hs_effectors_destroy", "hs_effectors_sparse",
            "hs_effector_backward", "hs_effector_step", "hs_plan_status", "hs_plan_set_wait_limit",
-           "hs_plan_debug_break_parent")
+           "hs_plan_debug_break_parent", "hs_pose_sample_backward_noalloc")
 
 
 class HSError(RuntimeError):
@@ -145,6 +146,8 @@ def load_library():
     lib.hs_scan_skin_vertices.argtypes = [vp, ctypes.POINTER(hs_pose_src), vp, vp, i32, vp, vp, vp]
     lib.hs_pose_sample_backward.argtypes = [vp, ctypes.POINTER(hs_clip_lib), ctypes.POINTER(hs_clip_params),
                                             vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hs_pose_sample_backward_noalloc.argtypes = [vp, ctypes.POINTER(hs_clip_lib),
+                                                    ctypes.POINTER(hs_clip_params), vp, vp, vp, vp, vp, vp, vp]
     lib.hs_plan_destroy.argtypes = [vp]
     lib.hs_plan_destroy.restype = None
     lib.hs_plan_get_info.argtypes = [vp, ctypes.POINTER(hs_plan_info)]
@@ -382,6 +385,37 @@ def hs_pose_sample_backward(plan, clips, clip_a, clip_b, time, weight, grad_quat
     _check(load_library().hs_pose_sample_backward(plan.handle, ctypes.byref(clips.c), ctypes.byref(params),
                                                   _ptr(grad_quat), _ptr(grad_trans), _ptr(gkq), _ptr(gkt),
                                                   _ptr(gtime), _ptr(gw), _ptr(workspace), _stream(stream)))
+    return gkq, gkt, gtime, gw
+
+
+def hs_pose_sample_backward_noalloc(plan, clips, clip_a, clip_b, time, weight, grad_quat, grad_trans,
+                                    want_keys=True, out=None, stream=None):
+    """``hs_pose_sample_backward`` on the library's static device workspace
+    (the C call allocates nothing; plans of at most
+    ``HS_NOALLOC_MAX_JOINTS`` joints).  ``out``: None, or preallocated
+    (grad_key_quat, grad_key_trans, grad_time, grad_weight) tensors, the key
+    gradients None when ``want_keys`` is false."""
+    N, C = plan.num_joints, plan.num_characters
+    _need(grad_quat, "grad_quat", (N, 4))
+    _need(grad_trans, "grad_trans", (N, 3))
+    if out is None:
+        dev = clips.key_quat.device
+        out = (torch.empty_like(clips.key_quat) if want_keys else None,
+               torch.empty_like(clips.key_trans) if want_keys else None,
+               torch.empty((C,), device=dev, dtype=torch.float32),
+               torch.empty((C,), device=dev, dtype=torch.float32))
+    gkq, gkt, gtime, gw = out
+    if gkq is not None:
+        _need(gkq, "grad_key_quat", tuple(clips.key_quat.shape))
+    if gkt is not None:
+        _need(gkt, "grad_key_trans", tuple(clips.key_trans.shape))
+    _need(gtime, "grad_time", (C,))
+    _need(gw, "grad_weight", (C,))
+    params = _clip_params(plan, clip_a, clip_b, time, weight)
+    _check(load_library().hs_pose_sample_backward_noalloc(plan.handle, ctypes.byref(clips.c),
+                                                          ctypes.byref(params), _ptr(grad_quat),
+                                                          _ptr(grad_trans), _ptr(gkq), _ptr(gkt),
+                                                          _ptr(gtime), _ptr(gw), _stream(stream)))
     return gkq, gkt, gtime, gw
 
 
