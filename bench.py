@@ -144,7 +144,12 @@ def summarize_pmc(workload, fetch_csv, write_csv):
     kernel, scaled by what the same counters read for the plain copy of
     COPY_BYTES in the same run."""
     import csv
-    kname = DOMINANT.get(workload, "fwd_tile_kernel")
+    kname = DOMINANT.get(workload)
+    if kname is None:
+        # the forward's kernel: the work-queue launch if the run made one
+        with open(fetch_csv) as f:
+            queued = any("fwd_queue_kernel" in r.get("Kernel_Name", "") for r in csv.DictReader(f))
+        kname = "fwd_queue_kernel" if queued else "fwd_tile_kernel"
     match = PMC_MATCH.get(workload, (kname,))
 
     def per_kernel(path, counter):
@@ -508,7 +513,8 @@ def measure(args, name):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    dominant = DOMINANT.get(name, "fwd_tile_kernel")
+    dominant = DOMINANT.get(name, "fwd_queue_kernel" if info["schedule"] == w.hs.HS_SCHED_QUEUE
+                            else "fwd_tile_kernel")
     if diff:
         # the adjoint and the forward timed on their own, back to back
         kernel_ms = w.backward_ms()
@@ -543,6 +549,7 @@ def measure(args, name):
         "config": {"workload": name, "characters": C, "joints": N, "max_depth": info["max_depth"],
                    "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
                    "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
+                   "schedule": "queue" if info["schedule"] == w.hs.HS_SCHED_QUEUE else "size classes",
                    "autotuned": not args.no_autotune, "hip_graph": mode == "graph",
                    "input_sets": len(w.sets),
                    **({"adjoint": args.adjoint} if diff else {})},

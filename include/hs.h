@@ -115,8 +115,25 @@ typedef struct hs_plan_opts {
     int32_t algorithm;      /* HS_ALG_*: the scan that tiles run (forward, stored TRS poses) */
     int32_t adjoint;        /* HS_ADJ_*: the kernel that runs the adjoint of characters of up to
                                1024 joints */
-    int32_t reserved[1];    /* must be zero */
+    int32_t schedule;       /* HS_SCHED_*: how hs_scan_forward launches the tiles */
 } hs_plan_opts;
+
+/* Forward schedules (hs_scan_forward; the other tiled calls keep the size
+ * classes).  HS_SCHED_QUEUE: every tile of the plan in one persistent
+ * launch (as many workgroups as fit the CUs at once) that walks the plan's
+ * heaviest-first tile list with a static stride; LDS holds only the
+ * transforms of each tile's anchors (joints whose children lie in another
+ * 64-joint block) and one staging slice per wave, so large tiles do not
+ * cost occupancy.  HS_SCHED_CLASSES:
+ * one launch per size class (characters of up to 1024 joints, up to 1664,
+ * the rest) with all of a tile's transforms in LDS.  HS_SCHED_AUTO takes the
+ * queue where it applies (the library's scan, no chain units, not
+ * instanced, a tile strategy, and each tile's anchors within the LDS) and
+ * the classes elsewhere; HS_SCHED_QUEUE where it does not apply is
+ * HS_ERR_UNSUPPORTED. */
+#define HS_SCHED_AUTO 0
+#define HS_SCHED_QUEUE 1
+#define HS_SCHED_CLASSES 2
 
 /* Adjoint kernels for characters of up to 1024 joints in recompute mode
  * (hs_scan_backward without checkpoints; larger characters always take the
@@ -161,6 +178,8 @@ typedef struct hs_plan_info {
     int32_t grid;              /* workgroups per tiled launch */
     int32_t multipass_rounds;  /* global jump rounds of the multipass path */
     int32_t max_block_chain;   /* longest chain of 64-joint blocks on any path */
+    int32_t schedule;          /* HS_SCHED_QUEUE or HS_SCHED_CLASSES: the forward's launches */
+    int32_t max_anchors;       /* queue: most anchors of one tile (LDS slots), else 0 */
 } hs_plan_info;
 
 /* Analyse a batch: validates the CSR topology (HS_ERR_TOPOLOGY if some

@@ -118,6 +118,7 @@ struct Shape {
     bool chain_units = false;
     int algorithm = HS_ALG_SCAN;
     int adjoint = HS_ADJ_ROUNDS;
+    int queue_waves = 0;  // > 0: the forward runs as one work-queue launch with this many waves
 };
 
 } // namespace
@@ -215,6 +216,15 @@ struct hs_plan {
     // kernels' bounded waits
     uint32_t *d_status = nullptr;
     int32_t spin_limit = hs::kDefaultSpinLimit;
+    // the forward's work queue (schedule HS_SCHED_QUEUE): tiles heaviest
+    // first and per-joint codes; num_tiles = 0 when the forward launches the
+    // size classes instead
+    struct QueueSet {
+        hs::QTile *d_tiles = nullptr;
+        int32_t num_tiles = 0, grid = 0, grid_sample = 0, waves = 0, max_anchors = 0, cap = 0;
+        int32_t *d_code = nullptr;
+    } q;
+    int sched_opt = HS_SCHED_AUTO;
 };
 
 namespace {
@@ -234,6 +244,8 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_skel_parent);
     (void)hipFree(p->d_char_skel);
     (void)hipFree(p->d_status);
+    (void)hipFree(p->q.d_tiles);
+    (void)hipFree(p->q.d_code);
     delete p;
 }
 
@@ -526,6 +538,82 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
     return HS_OK;
 }
 
+// The forward's work queue: every character of at most `cap` joints, in
+// id order, on tiles of at most `cap` joints, heaviest first.  A tile's
+// anchors are the parents of its joints that lie in another 64-joint
+// block; they get LDS slots in joint order, and every joint a code naming
+// its in-block parent lane or its parent's slot, and its own slot.
+// Returns false (nothing built) when the anchors of some tile would not
+// fit the LDS.
+hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *built)
+{
+    *built = false;
+    auto &Q = plan->q;
+    (void)hipFree(Q.d_tiles);
+    (void)hipFree(Q.d_code);
+    Q.d_tiles = nullptr;
+    Q.d_code = nullptr;
+    Q.num_tiles = Q.grid = Q.max_anchors = 0;
+    const int cap = shape.tile_cap;
+    const Packing pk = pack_tiles(plan, cap, strategy, false, 0, cap);
+    const auto &gpar = plan->h_gparent;
+    std::vector<hs::QTile> qt(pk.tiles.size());
+    std::vector<int32_t> code((size_t)plan->N, 0), slot;
+    int max_anchors = 0;
+    for (size_t i = 0; i < pk.tiles.size(); ++i) {
+        const TileDesc &t = pk.tiles[i];
+        slot.assign((size_t)t.count, 0);
+        for (int jl = 0; jl < t.count; ++jl) {
+            const int32_t pg = gpar[t.begin + jl];
+            if (pg >= 0 && (pg - t.begin) / 64 != jl / 64) slot[pg - t.begin] = 1;
+        }
+        int na = 0;
+        for (int jl = 0; jl < t.count; ++jl) slot[jl] = slot[jl] ? ++na : 0;  // 1 + slot, or 0
+        for (int jl = 0; jl < t.count; ++jl) {
+            const int32_t pg = gpar[t.begin + jl];
+            const int base = jl & ~63;
+            int c = 0;
+            if (pg >= 0) {
+                const int pl = (int)(pg - t.begin);
+                c = pl >= base ? (hs::kQInBlock | (pl - base)) : slot[pl];
+            }
+            code[t.begin + jl] = c | (slot[jl] << hs::kQOwnShift);
+        }
+        hs::QTile &q = qt[i];
+        q = hs::QTile{};
+        q.begin = t.begin;
+        q.count = t.count;
+        q.first_char = t.first_char;
+        q.num_chars = t.num_chars;
+        q.num_anchors = na;
+        max_anchors = std::max(max_anchors, na);
+    }
+    const int waves = shape.queue_waves;
+    const size_t lds = hs::forward_queue_lds_bytes(waves, max_anchors, cap, false);
+    const size_t lds_s = hs::forward_queue_lds_bytes(waves, max_anchors, cap, true);
+    if (max_anchors > hs::kQMaxAnchors || cap > hs::kQMaxTileJoints || lds_s > plan->ctx->max_lds) return HS_OK;
+    hipError_t err = upload(&Q.d_tiles, qt);
+    if (err == hipSuccess) err = upload(&Q.d_code, code);
+    if (err != hipSuccess) return fail_hip(err, "hs_plan_create (work queue)");
+    Q.num_tiles = (int32_t)qt.size();
+    Q.max_anchors = max_anchors;
+    Q.cap = cap;
+    Q.waves = waves;
+    // as many workgroups as fit the CUs at once (each pose source has its
+    // own instance, registers and LDS)
+    for (int smp = 0; smp < 2; ++smp) {
+        int per_cu = 1;
+        if ((err = hs::queue_blocks_per_cu(waves, smp != 0, smp ? lds_s : lds, &per_cu)) != hipSuccess)
+            return fail_hip(err, "hs_plan_create (work-queue occupancy)");
+        per_cu = std::max(1, shape.grid_per_cu > 0 ? std::min(per_cu, shape.grid_per_cu) : per_cu);
+        const int32_t g =
+            (int32_t)std::max<int64_t>(1, std::min<int64_t>(Q.num_tiles, (int64_t)per_cu * plan->ctx->num_cu));
+        (smp ? Q.grid_sample : Q.grid) = g;
+    }
+    *built = true;
+    return HS_OK;
+}
+
 hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
 {
     const int cap = shape.tile_cap;
@@ -623,6 +711,27 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     I.grid = plan->main_grid + small_grid;
     I.multipass_rounds = plan->mp.rounds;
     I.max_block_chain = std::max(max_chain_tiles, max_chain_mp);
+    I.schedule = HS_SCHED_CLASSES;
+    I.max_anchors = 0;
+    bool queued = false;
+    if (shape.queue_waves > 0 && strategy != HS_STRATEGY_MULTIPASS) {
+        if ((rc = build_queue(plan, shape, strategy, &queued)) != HS_OK) return rc;
+    } else {
+        (void)hipFree(plan->q.d_tiles);
+        (void)hipFree(plan->q.d_code);
+        plan->q.d_tiles = nullptr;
+        plan->q.d_code = nullptr;
+        plan->q.num_tiles = 0;
+    }
+    if (queued) {
+        I.schedule = HS_SCHED_QUEUE;
+        I.max_anchors = plan->q.max_anchors;
+        I.num_tiles = plan->q.num_tiles;
+        I.waves_per_tile = plan->q.waves;
+        I.grid = plan->q.grid;
+    } else if (plan->sched_opt == HS_SCHED_QUEUE) {
+        return fail(HS_ERR_UNSUPPORTED, "the work-queue schedule does not fit this plan (tile anchors beyond the LDS)");
+    }
     return HS_OK;
 }
 
@@ -758,9 +867,25 @@ hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Out
         if (rc != HS_OK) return rc;
     }
     hipError_t err = hipSuccess;
-    for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
-        err = hs::launch_forward_tiles(tile_launch(plan, k, validate), pa, oa, stream);
-    if (err == hipSuccess) err = hs::launch_forward_tiles(tile_launch(plan, -1, validate), pa, oa, stream);
+    if (plan->q.num_tiles > 0) {
+        hs::QueueLaunch ql{};
+        ql.tiles = plan->q.d_tiles;
+        ql.num_tiles = plan->q.num_tiles;
+        ql.waves = plan->q.waves;
+        ql.grid = plan->q.grid;
+        ql.grid_sample = plan->q.grid_sample;
+        ql.max_anchors = plan->q.max_anchors;
+        ql.tile_cap = plan->q.cap;
+        ql.code = plan->q.d_code;
+        ql.status = plan->d_status;
+        ql.spin_limit = plan->spin_limit;
+        ql.gate = validate ? plan->d_status : nullptr;
+        err = hs::launch_forward_queue(ql, pa, oa, stream);
+    } else {
+        for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
+            err = hs::launch_forward_tiles(tile_launch(plan, k, validate), pa, oa, stream);
+        if (err == hipSuccess) err = hs::launch_forward_tiles(tile_launch(plan, -1, validate), pa, oa, stream);
+    }
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (tiles)");
     err = hs::launch_forward_multipass(mp_launch(plan, plan->mp, validate), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (multipass)");
@@ -777,10 +902,10 @@ std::string tune_key(const hs_plan *p, int strategy)
     // block chain, rounded so that similar batches share an entry; the
     // strategy and the instancing decide which candidates are allowed
     char buf[160];
-    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d|inst%d|strat%d", p->ctx->arch.c_str(),
+    snprintf(buf, sizeof buf, "%s|N%d|maxc%d|chain%d|chars%d|inst%d|strat%d|sched%d", p->ctx->arch.c_str(),
              ceil_log2(std::max<int64_t>(1, p->N)), round_up(std::max(1, p->info.max_character), 64),
              ceil_log2(std::max(1, p->info.max_block_chain)), ceil_log2(std::max<int64_t>(1, p->C)),
-             p->inst ? 1 : 0, strategy);
+             p->inst ? 1 : 0, strategy, p->sched_opt);
     return buf;
 }
 
@@ -800,7 +925,23 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     const size_t N = (size_t)plan->N;
     std::vector<Shape> cands;
     const int min_cap = round_up(std::max(1, plan->info.max_character), 64);
+    if (base.queue_waves > 0) {
+        // the work queue: tile size and waves (as many workgroups per CU as fit)
+        for (int cap : {256, 512, 1024, 2048, 3072}) {
+            if (cap < min_cap && strategy == HS_STRATEGY_TILE) continue;
+            for (int w : {2, 4, 8, 16}) {
+                if (w * 64 > cap) continue;
+                Shape c = base;
+                c.tile_cap = cap;
+                c.queue_waves = w;
+                c.grid_per_cu = 0;
+                while (c.waves > 1 && c.waves * 64 > cap) c.waves >>= 1;  // the size-class tiles' waves
+                cands.push_back(c);
+            }
+        }
+    }
     for (int cap : {64, 128, 256, 512, 1024, 2048}) {
+        if (plan->sched_opt == HS_SCHED_QUEUE) break;  // the size classes are not candidates then
         // every character must stay on a tile for the tile strategy and for
         // instanced plans (which have no multipass path)
         if (cap < min_cap && (strategy == HS_STRATEGY_TILE || plan->inst)) continue;
@@ -816,6 +957,7 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
                     c.waves = w;
                     c.grid_per_cu = g;
                     c.chain_units = cu;
+                    c.queue_waves = 0;
                     cands.push_back(c);
                 }
         }
@@ -1056,8 +1198,8 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
     if (N > 0 && !batch->parents) return fail(HS_ERR_INVALID_ARG, "parents is NULL");
     hs_plan_opts o{};
     if (opts) o = *opts;
-    for (int r : o.reserved)
-        if (r != 0) return fail(HS_ERR_INVALID_ARG, "hs_plan_opts.reserved must be zero");
+    if (o.schedule < HS_SCHED_AUTO || o.schedule > HS_SCHED_CLASSES)
+        return fail(HS_ERR_INVALID_ARG, "unknown schedule %d", o.schedule);
     if (o.strategy < HS_STRATEGY_AUTO || o.strategy > HS_STRATEGY_MULTIPASS)
         return fail(HS_ERR_INVALID_ARG, "unknown strategy %d", o.strategy);
     if (o.tile_joints < 0 || o.tile_joints % 64 != 0)
@@ -1072,6 +1214,9 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
         return fail(HS_ERR_INVALID_ARG, "unknown adjoint kernel %d", o.adjoint);
     if (o.algorithm != HS_ALG_SCAN && o.chain_units)
         return fail(HS_ERR_INVALID_ARG, "chain units belong to the library's own scan (algorithm 0)");
+    if (o.schedule == HS_SCHED_QUEUE &&
+        (o.algorithm != HS_ALG_SCAN || o.chain_units || o.strategy == HS_STRATEGY_MULTIPASS))
+        return fail(HS_ERR_UNSUPPORTED, "the work-queue schedule runs the library's scan on tiles, without chain units");
 
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_plan_create: cannot select device %d", ctx->device);
@@ -1176,6 +1321,20 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
     sh.chain_units = o.chain_units != 0;
     sh.algorithm = o.algorithm;
     sh.adjoint = o.adjoint == HS_ADJ_AUTO ? HS_ADJ_ROUNDS : o.adjoint;
+    plan->sched_opt = o.schedule;
+    if (inst && o.schedule == HS_SCHED_QUEUE) {
+        free_plan(plan);
+        return fail(HS_ERR_UNSUPPORTED, "the work-queue schedule does not take instanced plans");
+    }
+    if (o.schedule != HS_SCHED_CLASSES && sh.algorithm == HS_ALG_SCAN && !sh.chain_units && !inst &&
+        o.strategy != HS_STRATEGY_MULTIPASS) {
+        // four waves (measured against eight and sixteen on the deep,
+        // heterogeneous and fused workloads: more workgroups per CU), fewer
+        // on tiles of fewer blocks
+        int w = o.waves_per_tile > 0 ? o.waves_per_tile : 4;
+        while (w > 1 && w * 64 > sh.tile_cap) w >>= 1;
+        sh.queue_waves = w;
+    }
     if (sh.algorithm != HS_ALG_SCAN) {
         // the paper's algorithms: one joint per thread, 1024-thread workgroups
         if (o.strategy == HS_STRATEGY_TILE && min_cap > hs::kPaperAlgTileJoints) {

@@ -51,6 +51,46 @@ struct TileDesc {
 };
 static_assert(sizeof(TileDesc) == 32, "TileDesc layout");
 
+// A tile of the work-queue forward kernel: a contiguous range of global
+// joint ids holding whole characters, whose joints find their parent
+// through the plan's per-joint codes (QueueLaunch::code).
+struct QTile {
+    int64_t begin;       // global id of the tile's first joint
+    int32_t count;       // joints in the tile
+    int32_t first_char;  // index of the tile's first character
+    int32_t num_chars;   // characters in the tile
+    int32_t num_anchors; // anchors of the tile (their transforms stay in LDS)
+    int32_t pad[2];
+};
+static_assert(sizeof(QTile) == 32, "QTile layout");
+
+// Per-joint code of a queue tile (int32):
+//   bits 0-11   parent reference: the in-block lane of the parent when bit
+//               12 is set, else 1 + the anchor slot of the parent (0: root)
+//   bit 12      the parent lies in the joint's own 64-joint block
+//   bits 13-24  1 + the joint's own anchor slot (0: not an anchor)
+// An anchor is a joint whose transform a later block of the tile needs:
+// the parent of some joint of another block.
+constexpr int kQRefBits = 12;
+constexpr int kQInBlock = 1 << kQRefBits;
+constexpr int kQOwnShift = kQRefBits + 1;
+constexpr int kQMaxAnchors = (1 << kQRefBits) - 1;
+constexpr int kQMaxTileJoints = 4096;
+
+struct QueueLaunch {
+    const QTile *tiles;       // heaviest first
+    int32_t num_tiles;
+    int32_t waves;            // 4, 8 or 16
+    int32_t grid;             // persistent workgroups (<= num_tiles), stored poses
+    int32_t grid_sample;      // the same for poses sampled in the kernel
+    int32_t max_anchors;      // LDS anchor slots (largest num_anchors)
+    int32_t tile_cap;         // largest tile (the fused sampler's character table)
+    const int32_t *code;      // [N] per-joint codes
+    uint32_t *status;
+    int32_t spin_limit;
+    const uint32_t *gate;
+};
+
 // A 64-joint block of a character on the multipass path.  Blocks start at
 // the character's first joint, so a block never spans two characters.
 struct MPBlock {
@@ -169,6 +209,12 @@ struct BwdArgs {
 // launch; none synchronises or allocates.
 hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, const OutArgs &out,
                                 hipStream_t stream);
+hipError_t launch_forward_queue(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
+                                hipStream_t stream);
+size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample);
+// Workgroups of the queue kernel (stored or sampled poses) that fit one CU
+// with `lds` bytes of LDS.
+hipError_t queue_blocks_per_cu(int waves, bool sample, size_t lds, int *out);
 hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
                                     hipStream_t stream);
 hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,

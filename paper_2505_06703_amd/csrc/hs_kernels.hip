@@ -785,6 +785,121 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 }
 
 // ---------------------------------------------------------------------------
+// Work-queue forward kernel: every tile of the plan in one persistent
+// launch.  The plan lists the tiles heaviest first; round r of the
+// workgroups takes the next gridDim.x of them, in alternating directions
+// (a static stride: a shared ticket counter serialised the workgroups on
+// its atomics), so tiles of every size share the launch and no size class
+// waits for another to drain.
+//
+// LDS holds only what other blocks read: the final transforms of the
+// tile's anchors (the parents of joints in other blocks; the plan numbers
+// them into slots) and a ready flag per slot, plus one staging slice per
+// wave for the coalesced row stores.  A block scans its 64 joints across
+// the wave as in the tiled kernel, carrying the slot of its nearest
+// out-of-block ancestor instead of a joint id; it waits for that slot's
+// flag, composes once, stores its anchors' transforms and raises their
+// flags.  The LDS footprint therefore follows the anchor count, not the
+// tile size, and large tiles keep several workgroups per CU.
+// LDS: staging [WAVES][64][3] float4 | anchors [max_anchors][3] float4 |
+// flags [max_anchors] int | (SAMPLE) char starts [tile_cap + 1]
+// ---------------------------------------------------------------------------
+// Bounded wait (as wait_block_of) until anchor slot e (if e >= 0) is ready.
+__device__ __forceinline__ void wait_slot(const int *flags, int e, uint32_t *status, int limit)
+{
+    const bool need = e >= 0;
+    bool done = !__any(need);
+    for (int spin = 0; !done && spin < limit; ++spin) {
+        const int ok = need ? __hip_atomic_load(flags + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 1;
+        done = __all(ok);
+        if (!done) __builtin_amdgcn_s_sleep(1);
+    }
+    if (!done) note_status(status, kStatusWaitTimeout);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool SAMPLE>
+__device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
+                                            const QTile &td, int b, float4 *stage, float4 *anc, int *flags,
+                                            const int *cstart, int lane)
+{
+    const int base = b * kWave;
+    const int jl = base + lane;
+    const bool valid = jl < td.count;
+    const int64_t gid = td.begin + jl;
+    float m[12];
+    int a = -1, e = -1, own = -1;
+    if (valid) {
+        const int code = ql.code[gid];
+        const int ref = code & (kQInBlock - 1);
+        if (code & kQInBlock) a = ref; else e = ref - 1;
+        own = (code >> kQOwnShift) - 1;
+        int chr = 0, lj = 0;
+        if constexpr (SAMPLE) {
+            const int c = tile_char_of(cstart, td.num_chars, jl);
+            chr = td.first_char + c;
+            lj = jl - cstart[c];
+        }
+        load_local<SAMPLE>(pose, gid, chr, lj, m);
+    } else {
+        aff_identity(m);
+    }
+    wave_inblock_scan(m, a, e, lane);
+    wait_slot(flags, valid ? e : -1, ql.status, ql.spin_limit);
+    if (valid && e >= 0) {
+        float g[12];
+        aff_load(anc + 3 * e, g);
+        aff_mul_left(g, m);
+    }
+    if (own >= 0) aff_store(anc + 3 * own, m);
+    aff_store(stage + 3 * lane, m);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (own >= 0) __hip_atomic_store(flags + own, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (out.global_out) store_rows<1>(out, stage, td.begin + base, 0, 1, td.count - base, lane);
+    if (valid) write_skin_and_ckpt(out, gid, gid, m);
+    // the slice is written again by this wave's next block only after
+    // every lane's reads above
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int WAVES, bool SAMPLE>
+__global__ void __launch_bounds__(WAVES * kWave)
+fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
+{
+    extern __shared__ float4 lds[];
+    if (gated(ql.gate)) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    float4 *stage = lds + wave * kWave * 3;
+    float4 *anc = lds + WAVES * kWave * 3;
+    int *flags = reinterpret_cast<int *>(anc + 3 * ql.max_anchors);
+    int *cstart = flags + ql.max_anchors;
+
+    for (int r = 0;; ++r) {
+        // round r takes tiles [r G, (r + 1) G) of the heaviest-first list,
+        // in alternating directions, so that each workgroup's total stays
+        // close to the others'
+        const int G = (int)gridDim.x;
+        const int tile = r * G + ((r & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (tile >= ql.num_tiles) break;  // uniform: every wave leaves together
+        const QTile td = ql.tiles[tile];
+        for (int i = threadIdx.x; i < td.num_anchors; i += WAVES * kWave) flags[i] = 0;
+        if constexpr (SAMPLE) {
+            for (int i = threadIdx.x; i <= td.num_chars; i += WAVES * kWave)
+                cstart[i] = (int)(pose.offsets[td.first_char + i] - td.begin);
+        }
+        __syncthreads();
+        const int nblk = (td.count + kWave - 1) / kWave;
+        for (int b = wave; b < nblk; b += WAVES)
+            queue_block<SAMPLE>(ql, pose, out, td, b, stage, anc, flags, cstart, lane);
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The paper's Algorithms 1-4 as tile kernels (plan option `algorithm`), for
 // comparison with the scan above on this hardware.  One workgroup of 1024
 // threads per tile, one joint per thread, the tile's local transforms in
@@ -2782,6 +2897,27 @@ hipError_t noalloc_workspace(int device, float4 **out)
 hipError_t prepare_kernels()
 {
     hipError_t err;
+    {
+        // the queue kernels: up to the whole LDS of a CU (the plan checks
+        // its own need against the device's limit)
+        int dev = 0, lds_max = 0;
+        if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+        if ((err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+            return err;
+        const void *qk[10] = {reinterpret_cast<const void *>(fwd_queue_kernel<1, false>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<1, true>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<2, false>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<2, true>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<4, false>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<4, true>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<8, false>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<8, true>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<16, false>),
+                             reinterpret_cast<const void *>(fwd_queue_kernel<16, true>)};
+        for (const void *k : qk)
+            if ((err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max)) != hipSuccess)
+                return err;
+    }
     if ((err = set_vertex_lds_limits_all<4>()) != hipSuccess || (err = set_vertex_lds_limits_all<8>()) != hipSuccess ||
         (err = set_vertex_lds_limits_all<16>()) != hipSuccess)
         return err;
@@ -2798,6 +2934,13 @@ hipError_t prepare_kernels()
     if ((err = set_lds_limits<4>()) != hipSuccess) return err;
     if ((err = set_lds_limits<8>()) != hipSuccess) return err;
     return set_lds_limits<16>();
+}
+
+size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample)
+{
+    size_t bytes = (size_t)waves * kWave * 48 + (size_t)max_anchors * 52;
+    if (sample) bytes += (size_t)(tile_cap + 1) * 4;
+    return bytes;
 }
 
 size_t forward_tile_lds_bytes(int tile_cap, bool char_map)
@@ -2992,6 +3135,57 @@ hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, fl
 size_t forward_vertex_lds_bytes(int tile_cap)
 {
     return forward_tile_lds_bytes(tile_cap, true) + (size_t)(tile_cap + 1) * 4;
+}
+
+template <int WAVES, bool SAMPLE>
+hipError_t launch_queue_t(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out, hipStream_t stream)
+{
+    const size_t lds = forward_queue_lds_bytes(WAVES, ql.max_anchors, ql.tile_cap, SAMPLE);
+    hipLaunchKernelGGL((fwd_queue_kernel<WAVES, SAMPLE>), dim3(ql.grid), dim3(WAVES * kWave), lds, stream, ql, pose,
+                       out);
+    return hipGetLastError();
+}
+
+template <int WAVES>
+hipError_t queue_occupancy_t(bool sample, size_t lds, int *out)
+{
+    return sample ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fwd_queue_kernel<WAVES, true>, WAVES * kWave, lds)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fwd_queue_kernel<WAVES, false>, WAVES * kWave, lds);
+}
+
+hipError_t queue_blocks_per_cu(int waves, bool sample, size_t lds, int *out)
+{
+    *out = 1;
+    switch (waves) {
+    case 1: return queue_occupancy_t<1>(sample, lds, out);
+    case 2: return queue_occupancy_t<2>(sample, lds, out);
+    case 4: return queue_occupancy_t<4>(sample, lds, out);
+    case 8: return queue_occupancy_t<8>(sample, lds, out);
+    case 16: return queue_occupancy_t<16>(sample, lds, out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_forward_queue(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
+                                hipStream_t stream)
+{
+    if (ql.num_tiles == 0) return hipSuccess;
+    if (ql.max_anchors > kQMaxAnchors || ql.tile_cap > kQMaxTileJoints)
+        return hipErrorInvalidValue;
+    const bool sample = pose.kind == 1;
+    if (sample && !pose.offsets) return hipErrorInvalidValue;
+    QueueLaunch q = ql;
+    q.grid = sample ? ql.grid_sample : ql.grid;
+    if (q.grid < 1) return hipErrorInvalidValue;
+    switch (ql.waves) {
+    case 1: return sample ? launch_queue_t<1, true>(q, pose, out, stream) : launch_queue_t<1, false>(q, pose, out, stream);
+    case 2: return sample ? launch_queue_t<2, true>(q, pose, out, stream) : launch_queue_t<2, false>(q, pose, out, stream);
+    case 4: return sample ? launch_queue_t<4, true>(q, pose, out, stream) : launch_queue_t<4, false>(q, pose, out, stream);
+    case 8: return sample ? launch_queue_t<8, true>(q, pose, out, stream) : launch_queue_t<8, false>(q, pose, out, stream);
+    case 16:
+        return sample ? launch_queue_t<16, true>(q, pose, out, stream) : launch_queue_t<16, false>(q, pose, out, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int WAVES, bool SAMPLE, bool INST>

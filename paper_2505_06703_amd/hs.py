@@ -30,6 +30,7 @@ HS_STRATEGY_TILE = 1
 HS_STRATEGY_MULTIPASS = 2
 HS_ALG_SCAN, HS_ALG_WALK, HS_ALG_JUMP, HS_ALG_BLOCKS, HS_ALG_COMPRESSED = 0, 1, 2, 3, 4
 HS_ADJ_AUTO, HS_ADJ_ROUNDS, HS_ADJ_DATAFLOW = 0, 1, 2
+HS_SCHED_AUTO, HS_SCHED_QUEUE, HS_SCHED_CLASSES = 0, 1, 2
 HS_SKIN_LINEAR, HS_SKIN_DUAL_QUAT = 0, 1
 
 HS_POSE_TRS = 0
@@ -76,7 +77,7 @@ class hs_plan_opts(ctypes.Structure):
                 ("waves_per_tile", ctypes.c_int32), ("grid_tiles", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("chain_units", ctypes.c_int32),
                 ("algorithm", ctypes.c_int32), ("adjoint", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("schedule", ctypes.c_int32)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -85,7 +86,8 @@ class hs_plan_info(ctypes.Structure):
                 ("max_depth", ctypes.c_int32), ("max_character", ctypes.c_int32),
                 ("num_tiles", ctypes.c_int32), ("tile_joints", ctypes.c_int32),
                 ("waves_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("multipass_rounds", ctypes.c_int32), ("max_block_chain", ctypes.c_int32)]
+                ("multipass_rounds", ctypes.c_int32), ("max_block_chain", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("max_anchors", ctypes.c_int32)]
 
 
 class hs_clip_lib(ctypes.Structure):
@@ -242,7 +244,7 @@ class Plan:
 
     def __init__(self, offsets, parents, ctx=None, strategy=HS_STRATEGY_AUTO, tile_joints=0,
                  waves_per_tile=0, grid_tiles=0, autotune=False, chain_units=False, algorithm=HS_ALG_SCAN,
-                 adjoint=HS_ADJ_AUTO, skeletons=None):
+                 adjoint=HS_ADJ_AUTO, schedule=HS_SCHED_AUTO, skeletons=None):
         self.ctx = ctx or default_context()
         off = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
                                               dtype=np.int64))
@@ -254,7 +256,7 @@ class Plan:
         self.num_joints = par.size
         batch = hs_batch(self.num_characters, self.num_joints, off.ctypes.data, par.ctypes.data)
         opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)),
-                            int(bool(chain_units)), int(algorithm), int(adjoint))
+                            int(bool(chain_units)), int(algorithm), int(adjoint), int(schedule))
         h = ctypes.c_void_p()
         if skeletons is None:
             _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),

@@ -74,7 +74,7 @@ def test_mixed_skeletons_match_oracle_and_expanded_plan():
     plan = hs.Plan.instanced(soff, spar, sid)
     assert plan.num_joints == N and plan.bind_rows == spar.size
     G, S = hs.hs_scan_forward(plan, dev(q), dev(t), dev(s), inv_bind=dev(inv_s))
-    ref_plan = hs.Plan(off, par)
+    ref_plan = hs.Plan(off, par, schedule=hs.HS_SCHED_CLASSES)  # the same tiles as the instanced plan
     G2, S2 = hs.hs_scan_forward(ref_plan, dev(q), dev(t), dev(s), inv_bind=dev(inv_s[rows]))
     torch.cuda.synchronize()
     G, S, G2, S2 = (x.cpu().numpy() for x in (G, S, G2, S2))
@@ -115,7 +115,7 @@ def test_fused_sampling_and_skin_of_one_shared_skeleton():
     cp = dict(clip_a=dev(x["clip_a"]), clip_b=dev(x["clip_b"]), time=dev(x["time"]), weight=dev(x["weight"]))
     plan = hs.Plan.instanced(soff, spar, sid)
     _, S = hs.hs_scan_forward(plan, clips=lib, **cp, want_global=False, inv_bind=dev(inv_s))
-    ref_plan = hs.Plan(b.offsets, b.parents)
+    ref_plan = hs.Plan(b.offsets, b.parents, schedule=hs.HS_SCHED_CLASSES)  # the same tiles as the instanced plan
     rows = np.tile(np.arange(spar.size), b.num_characters)
     _, S2 = hs.hs_scan_forward(ref_plan, clips=lib, **cp, want_global=False, inv_bind=dev(inv_s[rows]))
     torch.cuda.synchronize()
