@@ -82,12 +82,12 @@ BYTES_PER_JOINT = {
     # (+ 12 B of targets per effector)
     "differentiable": 136,
 }
-DOMINANT = {"differentiable": "bwd_sync_kernel",
+DOMINANT = {"differentiable": "bwd_anchor_kernel",
             "long_chains": "multipass step (mp_local, anchor rounds, mp_out)"}
 # what a --pmc dispatch's kernel name must contain to be the dominant
 # kernel: the differentiable run also times the dense route, whose adjoint
 # is the other instance of the same template
-PMC_MATCH = {"differentiable": ("bwd_sync_kernel<", ", 2>")}
+PMC_MATCH = {"differentiable": ("bwd_anchor_kernel<", ", 2>")}
 CHUNK = 8  # at least this many forward passes per captured graph replay
 CKPT_K = 8  # levels between checkpoints in the differentiable form's checkpoint mode
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
@@ -126,7 +126,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the plan's default launch shape instead of timing candidates at plan time")
-    ap.add_argument("--adjoint", default="auto", choices=("auto", "rounds", "dataflow"),
+    ap.add_argument("--adjoint", default="auto", choices=("auto", "rounds", "dataflow", "anchors"),
                     help="adjoint kernel for characters of up to 1024 joints (differentiable workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
@@ -202,7 +202,8 @@ class Workload:
         up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         self.b = b = wl.make(name)
         N = b.num_joints
-        adj = {"auto": hs.HS_ADJ_AUTO, "rounds": hs.HS_ADJ_ROUNDS, "dataflow": hs.HS_ADJ_DATAFLOW}[adjoint]
+        adj = {"auto": hs.HS_ADJ_AUTO, "rounds": hs.HS_ADJ_ROUNDS, "dataflow": hs.HS_ADJ_DATAFLOW,
+               "anchors": hs.HS_ADJ_ANCHORS}[adjoint]
         self.inv = None
         self.clips = None
         if name == "fused_sample_instanced":
@@ -515,6 +516,8 @@ def measure(args, name):
 
     dominant = DOMINANT.get(name, "fwd_queue_kernel" if info["schedule"] == w.hs.HS_SCHED_QUEUE
                             else "fwd_tile_kernel")
+    if diff and args.adjoint in ("rounds", "dataflow"):
+        dominant = "bwd_sync_kernel"  # the effector step's kernel under these options
     if diff:
         # the adjoint and the forward timed on their own, back to back
         kernel_ms = w.backward_ms()

@@ -136,19 +136,27 @@ typedef struct hs_plan_opts {
 #define HS_SCHED_CLASSES 2
 
 /* Adjoint kernels for characters of up to 1024 joints in recompute mode
- * (hs_scan_backward without checkpoints; larger characters always take the
- * dataflow kernel up to 1664 joints, then the multipass adjoint).
- * HS_ADJ_ROUNDS: tile-wide synchronous reverse pointer-jumping rounds, one
- * joint per thread, workgroup barriers between rounds; recomputes every G_j
- * on chip.  HS_ADJ_DATAFLOW: wave-level rounds per 64-joint block, blocks
- * ordered by LDS flags (no workgroup barriers between rounds).  HS_ADJ_AUTO
- * picks HS_ADJ_ROUNDS (measured faster: blocks of long chains wait for each
- * other in turn under HS_ADJ_DATAFLOW).  Given checkpoints, characters of
- * up to 1664 joints always run the dataflow kernel, which rebuilds each G_j
+ * (hs_scan_backward without checkpoints, hs_effector_backward,
+ * hs_effector_step; larger characters always take the dataflow kernel up to
+ * 1664 joints, then the multipass adjoint).  HS_ADJ_ROUNDS: tile-wide
+ * synchronous reverse pointer-jumping rounds, one joint per thread,
+ * workgroup barriers between rounds; recomputes every G_j on chip.
+ * HS_ADJ_DATAFLOW: wave-level rounds per 64-joint block, blocks ordered by
+ * LDS flags (no workgroup barriers between rounds).  HS_ADJ_ANCHORS: two
+ * levels: every joint's seed goes straight to the nearest out-of-block
+ * ancestor of its block path, those anchors pass their totals on to theirs
+ * in decreasing order, then one wave-level reverse pointer jumping per
+ * block over the seeds and the anchors' inflows (tiles whose anchors do not
+ * fit the LDS fall back to HS_ADJ_ROUNDS).  HS_ADJ_AUTO resolves per call:
+ * HS_ADJ_ANCHORS for end-effector seeds, HS_ADJ_ROUNDS for a dense
+ * dLoss/dG (measured fastest for each: on a dense seed every joint of a
+ * chain block sends to one anchor).  Given checkpoints, characters of up
+ * to 1664 joints always run the dataflow kernel, which rebuilds each G_j
  * from them. */
 #define HS_ADJ_AUTO 0
 #define HS_ADJ_ROUNDS 1
 #define HS_ADJ_DATAFLOW 2
+#define HS_ADJ_ANCHORS 3
 
 /* Tile algorithms.  HS_ALG_SCAN is this library's scan (wave-level pointer
  * jumping per 64-joint block, dataflow between blocks).  HS_ALG_WALK ..

@@ -108,7 +108,9 @@ int ceil_log2(int64_t v)
     return r;
 }
 
-static_assert(hs::kAdjRounds == HS_ADJ_ROUNDS && hs::kAdjDataflow == HS_ADJ_DATAFLOW, "adjoint kinds");
+static_assert(hs::kAdjRounds == HS_ADJ_ROUNDS && hs::kAdjDataflow == HS_ADJ_DATAFLOW &&
+                  hs::kAdjAnchors == HS_ADJ_ANCHORS,
+              "adjoint kinds");
 static_assert(hs::kStatusWaitTimeout == HS_DEV_WAIT_TIMEOUT && hs::kStatusTopology == HS_DEV_TOPOLOGY, "status bits");
 
 struct Shape {
@@ -200,6 +202,9 @@ struct hs_plan {
     int32_t bwd_cap = 0;
     TileDesc *d_bbig = nullptr;
     int32_t num_bbig = 0;
+    int32_t *d_bcode = nullptr;  // anchor codes of the adjoint tiles' joints
+    int32_t b_max_anchors = 0;
+    bool b_anchor_ok = false;    // the two-level adjoint fits the LDS
     int64_t bwd_untiled = 0;  // joints the adjoint's tiles do not cover
     int32_t max_units = 0;
     // multipass: characters larger than the forward tile (mp) and than the
@@ -246,6 +251,7 @@ void free_plan(hs_plan *p)
     (void)hipFree(p->d_status);
     (void)hipFree(p->q.d_tiles);
     (void)hipFree(p->q.d_code);
+    (void)hipFree(p->d_bcode);
     delete p;
 }
 
@@ -545,6 +551,34 @@ hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjo
 // its in-block parent lane or its parent's slot, and its own slot.
 // Returns false (nothing built) when the anchors of some tile would not
 // fit the LDS.
+// Anchor slots and per-joint codes (the layout of hs::QueueLaunch::code) of
+// a tile: the anchors are the parents of the tile's joints that lie in
+// another 64-joint block (blocks counted from the tile's first joint),
+// numbered in joint order.  Writes the codes of the tile's joints into
+// `code` and returns the tile's anchor count.
+int tile_codes(const hs_plan *plan, const TileDesc &t, std::vector<int32_t> &code, std::vector<int32_t> &slot)
+{
+    const auto &gpar = plan->h_gparent;
+    slot.assign((size_t)t.count, 0);
+    for (int jl = 0; jl < t.count; ++jl) {
+        const int32_t pg = gpar[t.begin + jl];
+        if (pg >= 0 && (pg - t.begin) / 64 != jl / 64) slot[pg - t.begin] = 1;
+    }
+    int na = 0;
+    for (int jl = 0; jl < t.count; ++jl) slot[jl] = slot[jl] ? ++na : 0;  // 1 + slot, or 0
+    for (int jl = 0; jl < t.count; ++jl) {
+        const int32_t pg = gpar[t.begin + jl];
+        const int base = jl & ~63;
+        int c = 0;
+        if (pg >= 0) {
+            const int pl = (int)(pg - t.begin);
+            c = pl >= base ? (hs::kQInBlock | (pl - base)) : slot[pl];
+        }
+        code[t.begin + jl] = c | (slot[jl] << hs::kQOwnShift);
+    }
+    return na;
+}
+
 hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *built)
 {
     *built = false;
@@ -556,29 +590,12 @@ hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *bui
     Q.num_tiles = Q.grid = Q.max_anchors = 0;
     const int cap = shape.tile_cap;
     const Packing pk = pack_tiles(plan, cap, strategy, false, 0, cap);
-    const auto &gpar = plan->h_gparent;
     std::vector<hs::QTile> qt(pk.tiles.size());
     std::vector<int32_t> code((size_t)plan->N, 0), slot;
     int max_anchors = 0;
     for (size_t i = 0; i < pk.tiles.size(); ++i) {
         const TileDesc &t = pk.tiles[i];
-        slot.assign((size_t)t.count, 0);
-        for (int jl = 0; jl < t.count; ++jl) {
-            const int32_t pg = gpar[t.begin + jl];
-            if (pg >= 0 && (pg - t.begin) / 64 != jl / 64) slot[pg - t.begin] = 1;
-        }
-        int na = 0;
-        for (int jl = 0; jl < t.count; ++jl) slot[jl] = slot[jl] ? ++na : 0;  // 1 + slot, or 0
-        for (int jl = 0; jl < t.count; ++jl) {
-            const int32_t pg = gpar[t.begin + jl];
-            const int base = jl & ~63;
-            int c = 0;
-            if (pg >= 0) {
-                const int pl = (int)(pg - t.begin);
-                c = pl >= base ? (hs::kQInBlock | (pl - base)) : slot[pl];
-            }
-            code[t.begin + jl] = c | (slot[jl] << hs::kQOwnShift);
-        }
+        const int na = tile_codes(plan, t, code, slot);
         hs::QTile &q = qt[i];
         q = hs::QTile{};
         q.begin = t.begin;
@@ -681,6 +698,22 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         pb = pack_tiles(plan, hs::kMaxBwdTileJoints, strategy, false, mp_all ? 0 : hs::kMaxSyncTileJoints + 1);
         plan->num_btiles = (int32_t)ps.tiles.size();
         plan->h_btiles = ps.tiles;
+        // anchor codes of the adjoint tiles (the two-level adjoint)
+        (void)hipFree(plan->d_bcode);
+        plan->d_bcode = nullptr;
+        plan->b_max_anchors = 0;
+        plan->b_anchor_ok = false;
+        if (!ps.tiles.empty()) {
+            std::vector<int32_t> code((size_t)plan->N, 0), slot;
+            for (const TileDesc &t : ps.tiles)
+                plan->b_max_anchors = std::max(plan->b_max_anchors, tile_codes(plan, t, code, slot));
+            int w = 1;
+            while (w * 64 < plan->bwd_cap) w *= 2;
+            plan->b_anchor_ok = plan->b_max_anchors <= hs::kQMaxAnchors &&
+                                hs::backward_anchor_lds_bytes(w, plan->b_max_anchors) <= plan->ctx->max_lds;
+            hipError_t e3 = upload(&plan->d_bcode, code);
+            if (e3 != hipSuccess) return fail_hip(e3, "hs_plan_create (adjoint codes)");
+        }
         plan->num_bbig = (int32_t)pb.tiles.size();
         hipError_t e2 = upload(&plan->d_btiles, ps.tiles);
         if (e2 == hipSuccess) e2 = upload(&plan->d_bbig, pb.tiles);
@@ -1210,7 +1243,7 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
     if (o.grid_tiles < 0 || o.grid_tiles > 64) return fail(HS_ERR_INVALID_ARG, "grid_tiles must be in [0, 64]");
     if (o.algorithm < HS_ALG_SCAN || o.algorithm > HS_ALG_COMPRESSED)
         return fail(HS_ERR_INVALID_ARG, "unknown algorithm %d", o.algorithm);
-    if (o.adjoint < HS_ADJ_AUTO || o.adjoint > HS_ADJ_DATAFLOW)
+    if (o.adjoint < HS_ADJ_AUTO || o.adjoint > HS_ADJ_ANCHORS)
         return fail(HS_ERR_INVALID_ARG, "unknown adjoint kernel %d", o.adjoint);
     if (o.algorithm != HS_ALG_SCAN && o.chain_units)
         return fail(HS_ERR_INVALID_ARG, "chain units belong to the library's own scan (algorithm 0)");
@@ -1320,7 +1353,7 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
     sh.grid_per_cu = o.grid_tiles;
     sh.chain_units = o.chain_units != 0;
     sh.algorithm = o.algorithm;
-    sh.adjoint = o.adjoint == HS_ADJ_AUTO ? HS_ADJ_ROUNDS : o.adjoint;
+    sh.adjoint = o.adjoint;  // AUTO is resolved per call (the seeds decide)
     plan->sched_opt = o.schedule;
     if (inst && o.schedule == HS_SCHED_QUEUE) {
         free_plan(plan);
@@ -1731,6 +1764,14 @@ hs_status run_backward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Bw
         // nearest checkpointed ancestor; without, the plan's kernel
         // recomputes them (the synchronous rounds: as their jump products)
         tl.adjoint = ba.ckpt ? hs::kAdjDataflow : plan->shape.adjoint;
+        // AUTO: the two-level kernel for end-effector seeds (measured on
+        // the differentiable workload: 40 against 49 us per step), the
+        // synchronous rounds for dense seeds (37 against 73 us: every joint
+        // of a chain block sends to the same anchor)
+        if (tl.adjoint == 0) tl.adjoint = ba.eff_ids ? hs::kAdjAnchors : hs::kAdjRounds;
+        if (tl.adjoint == hs::kAdjAnchors && !plan->b_anchor_ok) tl.adjoint = hs::kAdjRounds;
+        tl.code = plan->d_bcode;
+        tl.max_anchors = plan->b_max_anchors;
         tl.grid = plan->num_btiles;
         tl.waves = 1;  // dataflow: a power of two, at most one wave per block
         while (tl.waves < 16 && tl.waves * 2 * 64 <= plan->bwd_cap) tl.waves *= 2;

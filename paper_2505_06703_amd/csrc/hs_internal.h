@@ -132,6 +132,7 @@ struct OutArgs {
 // of HS_ADJ_ROUNDS and HS_ADJ_DATAFLOW)
 constexpr int32_t kAdjRounds = 1;
 constexpr int32_t kAdjDataflow = 2;
+constexpr int32_t kAdjAnchors = 3;
 
 struct TileLaunch {
     const TileDesc *tiles;
@@ -153,6 +154,11 @@ struct TileLaunch {
     uint32_t *status;
     int32_t spin_limit;
     const uint32_t *gate;
+    // the two-level adjoint (kAdjAnchors): per-joint anchor codes of the
+    // adjoint tiles (the layout of QueueLaunch::code) and the most anchors
+    // of one tile
+    const int32_t *code;
+    int32_t max_anchors;
 };
 
 struct MPLaunch {
@@ -212,6 +218,7 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
 hipError_t launch_forward_queue(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
                                 hipStream_t stream);
 size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample);
+size_t backward_anchor_lds_bytes(int waves, int max_anchors);
 // Workgroups of the queue kernel (stored or sampled poses) that fit one CU
 // with `lds` bytes of LDS.
 hipError_t queue_blocks_per_cu(int waves, bool sample, size_t lds, int *out);

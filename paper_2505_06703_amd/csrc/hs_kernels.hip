@@ -1630,6 +1630,293 @@ bwd_sync_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 }
 
 // ---------------------------------------------------------------------------
+// Two-level adjoint (tiles of up to 1024 joints, one 64-joint block per
+// wave, the anchor codes of the work-queue forward).
+//
+// With Y_j the sum over j's in-block descendants d of D_d pulled back
+// through the in-block path products, and P_k the forward's in-block
+// product of joint k (from the top of its in-block path), the inflow I_k
+// of an anchor k (what its children in other blocks send) satisfies
+//     I_k = sum over heads h with parent k of  Y_h (.) L_h
+//         + sum over anchors k' whose nearest out-of-block ancestor is k
+//           of  I_k' (.) P_k',
+// and the total adjoint is the in-block reverse sum of the seeds D_j + I_j
+// (I_j = 0 off the anchors).  Summed over a head's in-block subtree, the
+// first term is sum_d D_d (.) P_d, so every seeded joint that is not an
+// anchor sends D_d (.) P_d to its anchor at once, and every anchor, once
+// its own inflow is complete, sends (D_k + I_k) (.) P_k: one composition
+// per sender, anchors in decreasing order through LDS counters, no block
+// waiting for another block's rounds.  Each block then runs one in-block
+// reverse pointer jumping over D + I inside its wave (no workgroup
+// barriers: pushes to in-block ancestors travel over per-wave lists built
+// with LDS exchanges, values through the wave's own LDS slices).
+// LDS per wave: stage [64][3] f4 (the block's G, then the scan's jump
+// products), seeds [64][3] f4 (then the scan's contributions), jump
+// targets, list heads and links [64] int each; per anchor slot: G, P, I [3]
+// f4 each, flag, expected and received sends (int).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool any_nonzero12(const float v[12])
+{
+    bool nz = false;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) nz |= v[k] != 0.0f;
+    return nz;
+}
+
+// In-wave reverse pointer jumping over the block's in-block parents: S holds
+// the seeds on entry and, on return, the sum over the lane's in-block
+// descendants d of seed_d (.) (the local transforms on the path below the
+// lane down to d).  L: the lane's local transform; a: in-block parent lane
+// or -1.  Values move through the wave's own LDS slices with 16-byte
+// accesses (cheaper than 4-byte cross-lane permutes for 12-float rows):
+// Cx [64][3] the round's contributions, Mx [64][3] the jump products, and
+// ints ax (jump targets), head and nxt (the list of the lanes that send to
+// each lane in the round, built with LDS exchanges).
+__device__ __forceinline__ void wave_reverse_scan(float S[12], const float L[12], int a, int lane, float4 *Cx,
+                                                  float4 *Mx, int *ax, int *head, int *nxt)
+{
+    float M[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) M[k] = L[k];
+    wave_sync();  // the caller's reads of these slices are done
+    aff_store(Mx + 3 * lane, M);
+    ax[lane] = a;
+#pragma unroll 1
+    for (int r = 0; r < 6; ++r) {  // an in-block path has at most 64 joints
+        if (!__any(a >= 0)) break;
+        const bool act = a >= 0;
+        wave_sync();  // the previous round's reads are done
+        if (act) {
+            float c[12];
+            adj_pull(S, M, c);  // what this lane sends to its 2^r-th in-block ancestor
+            aff_store(Cx + 3 * lane, c);
+        }
+        head[lane] = -1;
+        wave_sync();
+        float ma[12];
+        int aa = -1;
+        if (act) {
+            nxt[lane] = atomicExch(head + a, lane);  // the senders to a form a list
+            aff_load(Mx + 3 * a, ma);
+            aa = ax[a];
+        }
+        wave_sync();
+        int h = head[lane];
+        while (__any(h >= 0)) {
+            if (h >= 0) {
+                float cin[12];
+                aff_load(Cx + 3 * h, cin);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) S[k] += cin[k];
+                h = nxt[h];
+            }
+        }
+        // forward doubling: M_{r+1} = M_r(a) M_r, a <- a's ancestor; every
+        // lane read round r's values before this point
+        if (act) {
+            aff_mul_left(ma, M);
+            a = aa;
+            aff_store(Mx + 3 * lane, M);
+            ax[lane] = a;
+        }
+    }
+}
+
+template <int WAVES, int SEED>
+__global__ void __launch_bounds__(WAVES * kWave)
+bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
+{
+    extern __shared__ float4 lds[];
+    if (gated(tl.gate)) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int na = tl.max_anchors;
+    float4 *stage_all = lds;                      // [WAVES][64][3]
+    float4 *seed_all = lds + WAVES * kWave * 3;   // [WAVES][64][3]
+    float4 *stage = stage_all + wave * kWave * 3;
+    float4 *seed = seed_all + wave * kWave * 3;
+    float4 *AG = lds + WAVES * kWave * 6;
+    float4 *AP = AG + 3 * na;
+    float4 *AI = AP + 3 * na;
+    int *aflag = reinterpret_cast<int *>(AI + 3 * na);
+    int *expect = aflag + na;
+    int *recv = expect + na;
+    int *ax = recv + na + wave * kWave * 3;  // [WAVES][3][64]: jump targets, list heads, next
+    int *head = ax + kWave;
+    int *nxt = head + kWave;
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+
+    for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
+        const TileDesc td = tl.tiles[tile];
+        const int n = td.count;
+        for (int i = threadIdx.x; i < na; i += WAVES * kWave) {
+            aflag[i] = 0;
+            expect[i] = 0;
+            recv[i] = 0;
+        }
+        for (int i = threadIdx.x; i < 3 * na; i += WAVES * kWave) AI[i] = zero4;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) seed[3 * lane + r] = zero4;
+        __syncthreads();
+
+        // ---- the forward scan of the block (the queue kernel's scheme) ----
+        const int base = wave * kWave;
+        const int jl = base + lane;
+        const bool valid = jl < n;
+        const int64_t gid = td.begin + jl;
+        int a = -1, e = -1, own = -1, ps = -1;
+        float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f, sx = 1.0f, sy = 1.0f, sz = 1.0f;
+        float m[12];
+        if (valid) {
+            const int code = tl.code[gid];
+            const int ref = code & (kQInBlock - 1);
+            if (code & kQInBlock) a = ref; else e = ps = ref - 1;
+            own = (code >> kQOwnShift) - 1;
+            const native_float4 qn =
+                __builtin_nontemporal_load(reinterpret_cast<const native_float4 *>(pose.quat) + gid);
+            q = make_float4(qn.x, qn.y, qn.z, qn.w);
+            const float *t = pose.trans + 3 * gid;
+            tx = __builtin_nontemporal_load(t);
+            ty = __builtin_nontemporal_load(t + 1);
+            tz = __builtin_nontemporal_load(t + 2);
+            if (pose.scale) {
+                const float *sp = pose.scale + 3 * gid;
+                sx = __builtin_nontemporal_load(sp);
+                sy = __builtin_nontemporal_load(sp + 1);
+                sz = __builtin_nontemporal_load(sp + 2);
+            }
+            aff_from_trs(q, tx, ty, tz, sx, sy, sz, m);
+        } else {
+            aff_identity(m);
+        }
+        const int pa = a;  // in-block parent lane, for the reverse sums
+        wave_inblock_scan(m, a, e, lane);
+        float P[12];  // the in-block product from the top of the joint's in-block path
+#pragma unroll
+        for (int k = 0; k < 12; ++k) P[k] = m[k];
+        if (own >= 0 && e >= 0) atomicAdd(expect + e, 1);  // k will send to its own anchor
+        wait_slot(aflag, valid ? e : -1, tl.status, tl.spin_limit);
+        if (valid && e >= 0) {
+            float g[12];
+            aff_load(AG + 3 * e, g);
+            aff_mul_left(g, m);
+        }
+        if (own >= 0) aff_store(AG + 3 * own, m);
+        aff_store(stage + 3 * lane, m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (own >= 0) __hip_atomic_store(aflag + own, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if constexpr (SEED == kSeedForward) {
+            if (bwd.eff_global_out) {
+                wave_sync();
+                OutArgs out{};
+                out.global_out = bwd.eff_global_out;
+                store_rows<1>(out, stage, td.begin + base, 0, 1, n - base, lane);
+            }
+        }
+        __syncthreads();  // expected pushes counted; every block's G staged
+
+        // ---- seeds ----
+        if constexpr (SEED == kSeedDense) {
+            if (valid) {
+                const float4 *gg = reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) seed[3 * lane + r] = gg[r];
+            }
+            wave_sync();
+        } else {
+            const int e1 = bwd.eff_tile[2 * tile + 1];
+            for (int k = bwd.eff_tile[2 * tile] + (int)threadIdx.x; k < e1; k += WAVES * kWave) {
+                const int64_t eg = bwd.eff_ids[k];
+                const int le = (int)(eg - td.begin);
+                const float *y = bwd.eff_target + 3 * (int64_t)bwd.eff_row[k];
+                float4 *dst = seed_all + 3 * le;  // [wave][lane] = tile-local id
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    float b;
+                    if constexpr (SEED == kSeedForward) b = stage_all[3 * le + r].w;
+                    else b = bwd.eff_global[16 * eg + 4 * r + 3];
+                    dst[r] = make_float4(0.0f, 0.0f, 0.0f, 2.0f * (b - y[r]));
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- seeds of joints that are not anchors go straight to their
+        // anchor: D_d (.) P_d (the sum over a head's in-block subtree of
+        // these is the head's in-block reverse sum pulled through its local
+        // transform) ----
+        {
+            float D[12];
+            aff_load(seed + 3 * lane, D);
+            if (own < 0 && e >= 0 && any_nonzero12(D)) {
+                float c[12];
+                adj_pull(D, P, c);
+                lds_atomic_add12(AI + 3 * e, c);
+            }
+            if (own >= 0) aff_store(AP + 3 * own, P);
+        }
+        __syncthreads();  // every direct send is in
+
+        // ---- anchors: once all its children anchors have sent, an anchor
+        // sends (D_k + I_k) (.) P_k to its own anchor ----
+        {
+            const bool need = own >= 0;
+            const int want = need ? expect[own] : 0;
+            bool done = !__any(need && want > 0);
+            for (int spin = 0; !done && spin < tl.spin_limit; ++spin) {
+                const int got =
+                    need ? __hip_atomic_load(recv + own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+                done = __all(got >= want);
+                if (!done) __builtin_amdgcn_s_sleep(1);
+            }
+            if (!done) note_status(tl.status, kStatusWaitTimeout);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            if (need && e >= 0) {
+                float I[12], D[12], Pk[12], c[12];
+                aff_load(AI + 3 * own, I);
+                aff_load(seed + 3 * lane, D);
+                aff_load(AP + 3 * own, Pk);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) I[k] += D[k];
+                adj_pull(I, Pk, c);
+                lds_atomic_add12(AI + 3 * e, c);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                atomicAdd(recv + e, 1);
+            }
+        }
+
+        // ---- in-block reverse sums over seeds + inflows: X ----
+        float L[12];
+        if (valid) aff_from_trs(q, tx, ty, tz, sx, sy, sz, L); else aff_identity(L);
+        float X[12];
+        aff_load(seed + 3 * lane, X);
+        if (own >= 0) {
+            float I[12];
+            aff_load(AI + 3 * own, I);  // final: this lane's own wait is over
+#pragma unroll
+            for (int k = 0; k < 12; ++k) X[k] += I[k];
+        }
+        // the parent's global rotation-scale block, for the gradients
+        float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
+        if (valid && (pa >= 0 || ps >= 0)) {
+            float g[12];
+            aff_load(pa >= 0 ? stage + 3 * pa : AG + 3 * ps, g);
+            Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
+            Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
+            Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
+        }
+        // the stage and seed slices are free now: they carry the scan's jump
+        // products and contributions
+        if (__any(any_nonzero12(X))) wave_reverse_scan(X, L, pa, lane, seed, stage, ax, head, nxt);
+
+        // ---- gradients ----
+        if (valid) write_grads(bwd, gid, X, Ap, q, sx, sy, sz);
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Reverse mode of the Simulation step.  One workgroup per character; each
 // thread takes joints, recomputes the two clips' key interpolations and the
 // blend, and applies the reverse rules
@@ -2854,6 +3141,19 @@ hipError_t set_lds_limits()
     hipError_t err = hipSuccess;
     for (const void *k : sk)
         if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bs);
+    if (err != hipSuccess) return err;
+    {
+        // the two-level adjoint: up to the whole LDS (the plan checks its need)
+        int dev = 0, lds_max = 0;
+        if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
+        if ((err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
+            return err;
+        const void *ak[3] = {reinterpret_cast<const void *>(bwd_anchor_kernel<WAVES, kSeedDense>),
+                             reinterpret_cast<const void *>(bwd_anchor_kernel<WAVES, kSeedEffectors>),
+                             reinterpret_cast<const void *>(bwd_anchor_kernel<WAVES, kSeedForward>)};
+        for (const void *k : ak)
+            if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    }
     if (err != hipSuccess || WAVES != 16) return err;
     const void *pk[4] = {reinterpret_cast<const void *>(paper_alg_kernel<1>),
                          reinterpret_cast<const void *>(paper_alg_kernel<2>),
@@ -3245,6 +3545,11 @@ hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *s
     return hipGetLastError();
 }
 
+size_t backward_anchor_lds_bytes(int waves, int max_anchors)
+{
+    return (size_t)waves * kWave * (2 * 48 + 3 * 4) + (size_t)max_anchors * (3 * 48 + 12);
+}
+
 size_t backward_sync_lds_bytes(int tile_cap)
 {
     return (size_t)tile_cap * 104 + (size_t)(tile_cap / kWave + 1) * 4;
@@ -3280,9 +3585,25 @@ hipError_t launch_bwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const 
 }
 
 template <int WAVES>
+hipError_t launch_bwd_anchor_w(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd, hipStream_t stream)
+{
+    if (tl.tile_cap > WAVES * kWave || !tl.code) return hipErrorInvalidValue;
+    const size_t lds = backward_anchor_lds_bytes(WAVES, tl.max_anchors);
+    const dim3 grid(tl.grid), blk(WAVES * kWave);
+    if (bwd.eff_ids && bwd.eff_forward)
+        hipLaunchKernelGGL((bwd_anchor_kernel<WAVES, kSeedForward>), grid, blk, lds, stream, tl, pose, bwd);
+    else if (bwd.eff_ids)
+        hipLaunchKernelGGL((bwd_anchor_kernel<WAVES, kSeedEffectors>), grid, blk, lds, stream, tl, pose, bwd);
+    else
+        hipLaunchKernelGGL((bwd_anchor_kernel<WAVES, kSeedDense>), grid, blk, lds, stream, tl, pose, bwd);
+    return hipGetLastError();
+}
+
+template <int WAVES>
 hipError_t launch_bwd_sync_w(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd, hipStream_t stream)
 {
     if (tl.tile_cap > WAVES * kWave) return hipErrorInvalidValue;
+    if (tl.adjoint == kAdjAnchors) return launch_bwd_anchor_w<WAVES>(tl, pose, bwd, stream);
     const size_t lds = backward_sync_lds_bytes(tl.tile_cap);
     if (bwd.eff_ids && bwd.eff_forward)
         hipLaunchKernelGGL((bwd_sync_kernel<WAVES, kSeedForward>), dim3(tl.grid), dim3(WAVES * kWave), lds, stream,

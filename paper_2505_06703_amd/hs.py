@@ -29,7 +29,7 @@ HS_STRATEGY_AUTO = 0
 HS_STRATEGY_TILE = 1
 HS_STRATEGY_MULTIPASS = 2
 HS_ALG_SCAN, HS_ALG_WALK, HS_ALG_JUMP, HS_ALG_BLOCKS, HS_ALG_COMPRESSED = 0, 1, 2, 3, 4
-HS_ADJ_AUTO, HS_ADJ_ROUNDS, HS_ADJ_DATAFLOW = 0, 1, 2
+HS_ADJ_AUTO, HS_ADJ_ROUNDS, HS_ADJ_DATAFLOW, HS_ADJ_ANCHORS = 0, 1, 2, 3
 HS_SCHED_AUTO, HS_SCHED_QUEUE, HS_SCHED_CLASSES = 0, 1, 2
 HS_SKIN_LINEAR, HS_SKIN_DUAL_QUAT = 0, 1
 

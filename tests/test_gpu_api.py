@@ -83,7 +83,7 @@ def test_forward_argument_errors_launch_nothing():
 def test_unknown_adjoint_kernel_is_rejected():
     b = wl.plain_scan(num_characters=2)
     with pytest.raises(hs.HSError) as ei:
-        hs.Plan(b.offsets, b.parents, adjoint=3)
+        hs.Plan(b.offsets, b.parents, adjoint=4)  # 0-3 are the kernels of HS_ADJ_*
     assert ei.value.status == hs.HS_ERR_INVALID_ARG
 
 

@@ -64,7 +64,7 @@ def oracle_grads(batch, W):
     return oracle.backward(batch.offsets, batch.parents, batch.quat, batch.trans, batch.scale, W)
 
 
-ADJ = [hs.HS_ADJ_ROUNDS, hs.HS_ADJ_DATAFLOW]
+ADJ = [hs.HS_ADJ_ROUNDS, hs.HS_ADJ_DATAFLOW, hs.HS_ADJ_ANCHORS]
 
 
 @pytest.mark.parametrize("adj", ADJ)

@@ -74,16 +74,21 @@ def targets(b, eff, rng, radius=0.5):
     return (Grest[eff, :3, 3] + wl.ball_offsets(rng, len(eff), radius)).astype(np.float32)
 
 
+ADJ = [hs.HS_ADJ_ROUNDS, hs.HS_ADJ_ANCHORS]
+
+
+@pytest.mark.parametrize("adj", ADJ)
 @pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4), dict(tile_joints=512)])
-def test_effector_loss_matches_oracle(shape):
+def test_effector_loss_matches_oracle(shape, adj):
     b = wl.differentiable(num_characters=12)
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(20))
-    G, got, _ = run(b, eff, y, expect_sparse=True, **shape)
+    G, got, _ = run(b, eff, y, expect_sparse=True, adjoint=adj, **shape)
     check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector adjoint {shape}")
 
 
-def test_ids_in_any_order_with_their_targets():
+@pytest.mark.parametrize("adj", ADJ)
+def test_ids_in_any_order_with_their_targets(adj):
     """Ids given unsorted, targets in the same order: each target stays with
     its joint.  Roots, the first and last joint of a character and a joint
     of every character, in a batch of mixed small characters."""
@@ -97,8 +102,8 @@ def test_ids_in_any_order_with_their_targets():
     eff = np.array(sorted(eff), np.int64)
     rng.shuffle(eff)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
-    G, got, _ = run(b, eff, y, expect_sparse=True)
-    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), "unsorted ids")
+    G, got, _ = run(b, eff, y, expect_sparse=True, adjoint=adj)
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"unsorted ids adj {adj}")
 
 
 def test_no_effectors_gives_zero_gradients():
@@ -244,16 +249,18 @@ def run_step(b, eff, y, want_global=True, **plan_kw):
     return None, got
 
 
+@pytest.mark.parametrize("adj", ADJ)
 @pytest.mark.parametrize("shape", [dict(), dict(tile_joints=1024, waves_per_tile=4), dict(tile_joints=512)])
-def test_fused_step_matches_oracle(shape):
+def test_fused_step_matches_oracle(shape, adj):
     b = wl.differentiable(num_characters=12)
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(30))
-    G, got = run_step(b, eff, y, **shape)
+    G, got = run_step(b, eff, y, adjoint=adj, **shape)
     check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector step {shape}")
 
 
-def test_fused_step_mixed_small_characters_and_unsorted_ids():
+@pytest.mark.parametrize("adj", ADJ)
+def test_fused_step_mixed_small_characters_and_unsorted_ids(adj):
     b = wl.heterogeneous(num_characters=40, lo=32, hi=1000)
     rng = np.random.default_rng(31)
     off = b.offsets
@@ -264,8 +271,8 @@ def test_fused_step_mixed_small_characters_and_unsorted_ids():
     eff = np.array(sorted(eff), np.int64)
     rng.shuffle(eff)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
-    G, got = run_step(b, eff, y)
-    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), "effector step, mixed characters")
+    G, got = run_step(b, eff, y, adjoint=adj)
+    check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector step, mixed characters adj {adj}")
 
 
 def test_fused_step_without_global_agrees_with_two_calls():
