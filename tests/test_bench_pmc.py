@@ -51,12 +51,13 @@ def test_calibration_copy_and_scales(tmp_path, monkeypatch):
 def test_only_the_dominant_instance_is_averaged(tmp_path, monkeypatch):
     copy = "__amd_rocclr_copyBuffer"
     # the step's instance (seeds from the tile's own forward) next to the
-    # comparison routes' instances of the same template
-    fetch = [(2, copy, 128.0 * MIB), (4, "void hs::bwd_sync_kernel<8, 2>(hs::TileLaunch)", 13.0 * MIB),
+    # comparison routes' kernels and other instances of the same template
+    fetch = [(2, copy, 128.0 * MIB), (4, "void hs::bwd_anchor_kernel<8, 2>(hs::TileLaunch)", 13.0 * MIB),
              (5, "void hs::bwd_sync_kernel<8, 0>(hs::TileLaunch)", 28.0 * MIB),
-             (6, "void hs::bwd_sync_kernel<8, 1>(hs::TileLaunch)", 20.0 * MIB),
-             (7, "void hs::bwd_sync_kernel<8, 2>(hs::TileLaunch)", 13.0 * MIB)]
-    write = [(2, copy, 256.0 * MIB), (4, "void hs::bwd_sync_kernel<8, 2>(hs::TileLaunch)", 14.0 * MIB),
+             (6, "void hs::bwd_anchor_kernel<8, 1>(hs::TileLaunch)", 20.0 * MIB),
+             (8, "void hs::bwd_sync_kernel<8, 2>(hs::TileLaunch)", 11.0 * MIB),
+             (7, "void hs::bwd_anchor_kernel<8, 2>(hs::TileLaunch)", 13.0 * MIB)]
+    write = [(2, copy, 256.0 * MIB), (4, "void hs::bwd_anchor_kernel<8, 2>(hs::TileLaunch)", 14.0 * MIB),
              (5, "void hs::bwd_sync_kernel<8, 0>(hs::TileLaunch)", 50.0 * MIB)]
     rec = run(tmp_path, monkeypatch, "differentiable", fetch, write)
     assert rec["fetch_bytes_per_launch"] == 13.0 * MIB * 1024.0 * 2.0
@@ -70,3 +71,14 @@ def test_records_of_other_workloads_are_kept(tmp_path, monkeypatch):
     run(tmp_path, monkeypatch, "deep_forward", rows, rows)
     data = json.load(open(tmp_path / "traffic.json"))
     assert set(data) == {"long_chains", "deep_forward"}
+
+
+def test_the_work_queue_launch_is_the_forward_kernel_when_present(tmp_path, monkeypatch):
+    copy = "__amd_rocclr_copyBuffer"
+    fetch = [(1, copy, 128.0 * MIB), (2, "void hs::fwd_queue_kernel<4, false>(hs::QueueLaunch)", 30.0 * MIB),
+             (3, "void hs::fwd_tile_kernel<8, false, 0>(hs::TileLaunch)", 99.0 * MIB)]
+    write = [(1, copy, 256.0 * MIB), (2, "void hs::fwd_queue_kernel<4, false>(hs::QueueLaunch)", 64.0 * MIB)]
+    rec = run(tmp_path, monkeypatch, "heterogeneous", fetch, write)
+    assert rec["kernel"] == "fwd_queue_kernel"
+    assert rec["fetch_bytes_per_launch"] == 30.0 * MIB * 1024.0 * 2.0
+    assert rec["write_bytes_per_launch"] == 64.0 * MIB * 1024.0
