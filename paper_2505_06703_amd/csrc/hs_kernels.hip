@@ -144,6 +144,15 @@ __device__ __forceinline__ void aff_store(float4 *p, const float m[12])
     p[2] = make_float4(m[8], m[9], m[10], m[11]);
 }
 
+// Orders a wave's LDS accesses: every lane's earlier accesses complete
+// before any lane's later ones.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float lane_read(float v, int byte_addr)
 {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
@@ -291,6 +300,34 @@ __device__ __forceinline__ void wave_inblock_scan(float m[12], int &a, int &e, i
         e = (act && aa < 0) ? ea : e;
         a = act ? aa : a;
     }
+}
+
+// The same scan with the rows moving through the wave's own LDS slice (X:
+// [64][3] float4, xi: [64] int) with 16-byte accesses instead of 4-byte
+// cross-lane permutes (measured faster on deep chains); the products and
+// their order are those of wave_inblock_scan, so the results are bitwise
+// equal.  e must fit 24 bits.
+__device__ __forceinline__ void wave_inblock_scan_lds(float m[12], int &a, int &e, int lane, float4 *X, int *xi)
+{
+#pragma unroll 1
+    for (int r = 0; r < 6; ++r) {
+        if (!__any(a >= 0)) break;
+        const bool act = a >= 0;
+        wave_sync();  // the previous round's reads are done
+        aff_store(X + 3 * lane, m);
+        xi[lane] = (a + 1) | ((e + 1) << 7);
+        wave_sync();
+        if (act) {
+            float ma[12];
+            aff_load(X + 3 * a, ma);
+            const int pk = xi[a];
+            aff_mul_left(ma, m);
+            const int aa = (pk & 127) - 1;
+            if (aa < 0) e = (pk >> 7) - 1;
+            a = aa;
+        }
+    }
+    wave_sync();  // the slice is free for the caller
 }
 
 // Find the character of tile-local joint jl: the largest i with cstart[i] <= jl.
@@ -801,8 +838,9 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 // flag, composes once, stores its anchors' transforms and raises their
 // flags.  The LDS footprint therefore follows the anchor count, not the
 // tile size, and large tiles keep several workgroups per CU.
-// LDS: staging [WAVES][64][3] float4 | anchors [max_anchors][3] float4 |
-// flags [max_anchors] int | (SAMPLE) char starts [tile_cap + 1]
+// LDS: staging [WAVES][64][3] float4 (also the in-block scan's slices) |
+// scan ints [WAVES][64] | anchors [max_anchors][3] float4 | flags
+// [max_anchors] int | (SAMPLE) char starts [tile_cap + 1]
 // ---------------------------------------------------------------------------
 // Bounded wait (as wait_block_of) until anchor slot e (if e >= 0) is ready.
 __device__ __forceinline__ void wait_slot(const int *flags, int e, uint32_t *status, int limit)
@@ -820,8 +858,8 @@ __device__ __forceinline__ void wait_slot(const int *flags, int e, uint32_t *sta
 
 template <bool SAMPLE>
 __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
-                                            const QTile &td, int b, float4 *stage, float4 *anc, int *flags,
-                                            const int *cstart, int lane)
+                                            const QTile &td, int b, float4 *stage, int *xi, float4 *anc,
+                                            int *flags, const int *cstart, int lane)
 {
     const int base = b * kWave;
     const int jl = base + lane;
@@ -844,7 +882,7 @@ __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArg
     } else {
         aff_identity(m);
     }
-    wave_inblock_scan(m, a, e, lane);
+    wave_inblock_scan_lds(m, a, e, lane, stage, xi);
     wait_slot(flags, valid ? e : -1, ql.status, ql.spin_limit);
     if (valid && e >= 0) {
         float g[12];
@@ -874,7 +912,8 @@ fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     float4 *stage = lds + wave * kWave * 3;
-    float4 *anc = lds + WAVES * kWave * 3;
+    int *xi = reinterpret_cast<int *>(lds + WAVES * kWave * 3) + wave * kWave;
+    float4 *anc = lds + WAVES * kWave * 3 + WAVES * kWave / 4;
     int *flags = reinterpret_cast<int *>(anc + 3 * ql.max_anchors);
     int *cstart = flags + ql.max_anchors;
 
@@ -894,7 +933,7 @@ fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
         __syncthreads();
         const int nblk = (td.count + kWave - 1) / kWave;
         for (int b = wave; b < nblk; b += WAVES)
-            queue_block<SAMPLE>(ql, pose, out, td, b, stage, anc, flags, cstart, lane);
+            queue_block<SAMPLE>(ql, pose, out, td, b, stage, xi, anc, flags, cstart, lane);
         __syncthreads();  // LDS is reused by the next tile
     }
 }
@@ -1175,13 +1214,6 @@ __device__ __forceinline__ void own16_claim(uint16_t *w, uint16_t v)
 __device__ __forceinline__ int own16_read(const uint16_t *w)
 {
     return (int)__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int WAVES, bool CKPT>
@@ -1791,7 +1823,7 @@ bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             aff_identity(m);
         }
         const int pa = a;  // in-block parent lane, for the reverse sums
-        wave_inblock_scan(m, a, e, lane);
+        wave_inblock_scan_lds(m, a, e, lane, stage, ax);
         float P[12];  // the in-block product from the top of the joint's in-block path
 #pragma unroll
         for (int k = 0; k < 12; ++k) P[k] = m[k];
@@ -3238,7 +3270,7 @@ hipError_t prepare_kernels()
 
 size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample)
 {
-    size_t bytes = (size_t)waves * kWave * 48 + (size_t)max_anchors * 52;
+    size_t bytes = (size_t)waves * kWave * 52 + (size_t)max_anchors * 52;
     if (sample) bytes += (size_t)(tile_cap + 1) * 4;
     return bytes;
 }
