@@ -76,11 +76,30 @@ const char *hs_version(void);
 const char *hs_last_error(void);
 
 /* Create a context bound to HIP device `device`.  The context owns the
- * device properties and the in-memory autotuning cache.  *out receives the
+ * device properties and the autotuning cache (in memory; see
+ * hs_context_load_tuning for the file form).  *out receives the
  * context; destroy it with hs_context_destroy after every plan made from it
  * has been destroyed. */
 hs_status hs_context_create(int device, hs_context **out);
 void hs_context_destroy(hs_context *ctx);
+
+/* The autotuner's results on disk, as JSON: one entry per tuning key (the
+ * device's gfx architecture, the size class of the batch -- log2 of its
+ * joints and characters, its largest character, its longest chain of
+ * 64-joint blocks -- instancing, strategy and schedule options) holding
+ * the chosen launch shape:
+ *   {"version": 1, "entries": {"<key>": {"tile_cap": 2048, "waves": 16,
+ *    "grid_per_cu": 0, "chain_units": 0, "queue_waves": 4}, ...}}
+ * hs_context_load_tuning merges a file's entries into the context's cache
+ * (a missing file is HS_OK with nothing loaded; a malformed one is
+ * HS_ERR_INVALID_ARG with the cache unchanged); plans created with
+ * autotune then take a cached shape without timing candidates.
+ * hs_context_save_tuning writes the context's whole cache (to a temporary
+ * file renamed into place).  If the environment variable HS_TUNE_CACHE
+ * names a file, hs_context_create loads it and every plan that tunes saves
+ * the cache there.  Host calls; they touch no device memory. */
+hs_status hs_context_load_tuning(hs_context *ctx, const char *path);
+hs_status hs_context_save_tuning(const hs_context *ctx, const char *path);
 
 /* ------------------------------------------------------------------------
  * Plans: topology analysis, done once per skeleton batch.

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -132,8 +133,207 @@ struct hs_context {
     std::string arch;
     std::mutex mu;
     std::map<std::string, Shape> tuned;  // autotuning cache keyed by arch + size class
+    std::string tune_file;               // HS_TUNE_CACHE: where tuning results persist
     float4 *noalloc_ws = nullptr;        // this device's static workspace (hs_pose_sample_backward_noalloc)
 };
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// The autotuning cache as JSON (hs_context_load_tuning / _save_tuning).  A
+// small reader for the one shape the file has: an object whose "entries"
+// member maps keys to objects of integer fields; unknown members are
+// skipped.
+// ---------------------------------------------------------------------------
+struct JsonReader {
+    const std::string &t;
+    size_t i = 0;
+    explicit JsonReader(const std::string &text) : t(text) {}
+    void ws()
+    {
+        while (i < t.size() && (t[i] == ' ' || t[i] == '\n' || t[i] == '\r' || t[i] == '\t')) ++i;
+    }
+    bool eat(char c)
+    {
+        ws();
+        if (i < t.size() && t[i] == c) {
+            ++i;
+            return true;
+        }
+        return false;
+    }
+    bool str(std::string &out)
+    {
+        ws();
+        if (i >= t.size() || t[i] != '"') return false;
+        out.clear();
+        for (++i; i < t.size() && t[i] != '"'; ++i) {
+            if (t[i] == '\\') {
+                if (++i >= t.size()) return false;
+            }
+            out.push_back(t[i]);
+        }
+        return i++ < t.size();
+    }
+    bool integer(long long &v)
+    {
+        ws();
+        const char *b = t.c_str() + i;
+        char *e = nullptr;
+        v = std::strtoll(b, &e, 10);
+        if (e == b) return false;
+        i += (size_t)(e - b);
+        return true;
+    }
+    // skips one value of any kind
+    bool skip()
+    {
+        ws();
+        if (i >= t.size()) return false;
+        if (t[i] == '"') {
+            std::string d;
+            return str(d);
+        }
+        if (t[i] == '{' || t[i] == '[') {
+            const char close = t[i] == '{' ? '}' : ']';
+            ++i;
+            if (eat(close)) return true;
+            do {
+                if (close == '}') {
+                    std::string k;
+                    if (!str(k) || !eat(':')) return false;
+                }
+                if (!skip()) return false;
+            } while (eat(','));
+            return eat(close);
+        }
+        while (i < t.size() && std::strchr(",}] \n\r\t", t[i]) == nullptr) ++i;
+        return true;
+    }
+};
+
+bool parse_shape(JsonReader &r, Shape &sh)
+{
+    if (!r.eat('{')) return false;
+    if (r.eat('}')) return false;
+    bool cap = false;
+    do {
+        std::string k;
+        long long v = 0;
+        if (!r.str(k) || !r.eat(':')) return false;
+        if (k == "tile_cap" || k == "waves" || k == "grid_per_cu" || k == "chain_units" || k == "queue_waves") {
+            if (!r.integer(v)) return false;
+            if (k == "tile_cap") {
+                if (v < 64 || v > hs::kMaxTileJoints || v % 64) return false;
+                sh.tile_cap = (int)v;
+                cap = true;
+            } else if (k == "waves" || k == "queue_waves") {
+                if (v < (k == "waves" ? 1 : 0) || v > 16 || (v & (v - 1))) return false;
+                (k == "waves" ? sh.waves : sh.queue_waves) = (int)v;
+            } else if (k == "grid_per_cu") {
+                if (v < 0 || v > 64) return false;
+                sh.grid_per_cu = (int)v;
+            } else {
+                if (v != 0 && v != 1) return false;
+                sh.chain_units = v != 0;
+            }
+        } else if (!r.skip()) {
+            return false;
+        }
+    } while (r.eat(','));
+    return r.eat('}') && cap && sh.waves >= 1 && !(sh.chain_units && sh.queue_waves);
+}
+
+// Parses a cache file's text; false (and nothing in `out`) if malformed.
+bool parse_tuning(const std::string &text, std::map<std::string, Shape> &out)
+{
+    JsonReader r(text);
+    std::map<std::string, Shape> got;
+    if (!r.eat('{')) return false;
+    if (!r.eat('}')) {
+        do {
+            std::string k;
+            if (!r.str(k) || !r.eat(':')) return false;
+            if (k == "entries") {
+                if (!r.eat('{')) return false;
+                if (!r.eat('}')) {
+                    do {
+                        std::string key;
+                        Shape sh;
+                        if (!r.str(key) || !r.eat(':') || !parse_shape(r, sh)) return false;
+                        got[key] = sh;
+                    } while (r.eat(','));
+                    if (!r.eat('}')) return false;
+                }
+            } else if (!r.skip()) {
+                return false;
+            }
+        } while (r.eat(','));
+        if (!r.eat('}')) return false;
+    }
+    r.ws();
+    if (r.i != text.size()) return false;
+    out = got;
+    return true;
+}
+
+std::string format_tuning(const std::map<std::string, Shape> &tuned)
+{
+    std::string o = "{\"version\": 1, \"entries\": {";
+    bool first = true;
+    char buf[256];
+    for (const auto &kv : tuned) {
+        std::string key;
+        for (char c : kv.first) {
+            if (c == '"' || c == '\\') key.push_back('\\');
+            key.push_back(c);
+        }
+        const Shape &sh = kv.second;
+        snprintf(buf, sizeof buf,
+                 "\"tile_cap\": %d, \"waves\": %d, \"grid_per_cu\": %d, \"chain_units\": %d, \"queue_waves\": %d",
+                 sh.tile_cap, sh.waves, sh.grid_per_cu, sh.chain_units ? 1 : 0, sh.queue_waves);
+        o += (first ? "\n  \"" : ",\n  \"") + key + "\": {" + buf + "}";
+        first = false;
+    }
+    o += first ? "}}\n" : "\n}}\n";
+    return o;
+}
+
+hs_status load_tuning_file(hs_context *ctx, const char *path)
+{
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return HS_OK;  // nothing tuned yet
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    std::map<std::string, Shape> got;
+    if (!parse_tuning(text, got)) return fail(HS_ERR_INVALID_ARG, "tuning cache %s is malformed", path);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const auto &kv : got) ctx->tuned[kv.first] = kv.second;
+    return HS_OK;
+}
+
+hs_status save_tuning_file(const hs_context *ctx, const char *path)
+{
+    std::string text;
+    {
+        std::lock_guard<std::mutex> lk(const_cast<hs_context *>(ctx)->mu);
+        text = format_tuning(ctx->tuned);
+    }
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(HS_ERR_INVALID_ARG, "cannot write tuning cache %s", tmp.c_str());
+    const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(HS_ERR_INVALID_ARG, "cannot write tuning cache %s", path);
+    }
+    return HS_OK;
+}
+
+} // namespace
 
 // Device tables and workspace of the multipass path.
 struct MPSet {
@@ -747,7 +947,8 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     I.schedule = HS_SCHED_CLASSES;
     I.max_anchors = 0;
     bool queued = false;
-    if (shape.queue_waves > 0 && strategy != HS_STRATEGY_MULTIPASS) {
+    if (shape.queue_waves > 0 && strategy != HS_STRATEGY_MULTIPASS && !plan->inst && !shape.chain_units &&
+        shape.algorithm == HS_ALG_SCAN) {
         if ((rc = build_queue(plan, shape, strategy, &queued)) != HS_OK) return rc;
     } else {
         (void)hipFree(plan->q.d_tiles);
@@ -951,7 +1152,9 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
         if (it != plan->ctx->tuned.end()) {
             Shape sh = it->second;  // the forward's launch shape; the adjoint kind is this plan's
             sh.adjoint = base.adjoint;
+            sh.algorithm = base.algorithm;
             if (plan->inst) sh.chain_units = false;
+            if (plan->inst || plan->sched_opt == HS_SCHED_CLASSES || sh.chain_units) sh.queue_waves = 0;
             return build_tables(plan, sh, strategy);
         }
     }
@@ -1064,6 +1267,10 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
         std::lock_guard<std::mutex> lk(plan->ctx->mu);
         plan->ctx->tuned[key] = best;
     }
+    if (!plan->ctx->tune_file.empty()) {
+        hs_status rc2 = save_tuning_file(plan->ctx, plan->ctx->tune_file.c_str());
+        if (rc2 != HS_OK) return rc2;
+    }
     return build_tables(plan, best, strategy);
 }
 
@@ -1140,6 +1347,18 @@ hs_status hs_context_create(int device, hs_context **out)
     }
     hs_context *ctx = new hs_context();
     ctx->noalloc_ws = noalloc_ws;
+    if (const char *tf = std::getenv("HS_TUNE_CACHE")) {
+        if (*tf) {
+            ctx->tune_file = tf;
+            ctx->device = device;
+            ctx->arch = arch.substr(0, arch.find(':'));
+            hs_status rc = load_tuning_file(ctx, tf);
+            if (rc != HS_OK) {
+                delete ctx;
+                return rc;
+            }
+        }
+    }
     ctx->device = device;
     ctx->num_cu = prop.multiProcessorCount;
     ctx->max_lds = prop.sharedMemPerBlock;
@@ -1149,6 +1368,18 @@ hs_status hs_context_create(int device, hs_context **out)
 }
 
 void hs_context_destroy(hs_context *ctx) { delete ctx; }
+
+hs_status hs_context_load_tuning(hs_context *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(HS_ERR_INVALID_ARG, "hs_context_load_tuning: NULL argument");
+    return load_tuning_file(ctx, path);
+}
+
+hs_status hs_context_save_tuning(const hs_context *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(HS_ERR_INVALID_ARG, "hs_context_save_tuning: NULL argument");
+    return save_tuning_file(ctx, path);
+}
 
 } // extern "C"
 

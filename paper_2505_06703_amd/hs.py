@@ -48,7 +48,8 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_mesh_destroy", "hs_skin_vertices", "hs_pose_sample_backward", "hs_scan_skin_vertices",
            "hs_effector_loss_grad", "hs_effectors_create", "hs_effectors_destroy", "hs_effectors_sparse",
            "hs_effector_backward", "hs_effector_step", "hs_plan_status", "hs_plan_set_wait_limit",
-           "hs_plan_debug_break_parent", "hs_pose_sample_backward_noalloc")
+           "hs_plan_debug_break_parent", "hs_pose_sample_backward_noalloc", "hs_context_load_tuning",
+           "hs_context_save_tuning")
 
 
 class HSError(RuntimeError):
@@ -129,6 +130,8 @@ def load_library():
     lib.hs_context_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
     lib.hs_context_destroy.argtypes = [vp]
     lib.hs_context_destroy.restype = None
+    lib.hs_context_load_tuning.argtypes = [vp, ctypes.c_char_p]
+    lib.hs_context_save_tuning.argtypes = [vp, ctypes.c_char_p]
     lib.hs_plan_create.argtypes = [vp, ctypes.POINTER(hs_batch), ctypes.POINTER(hs_plan_opts),
                                    ctypes.POINTER(vp)]
     lib.hs_plan_create_instanced.argtypes = [vp, ctypes.POINTER(hs_skeleton_set), i32, vp,
@@ -216,6 +219,14 @@ class Context:
         _check(lib.hs_context_create(int(device), ctypes.byref(h)))
         self.handle = h
         self.device = int(device)
+
+    def load_tuning(self, path):
+        """Merge a JSON tuning cache file into this context (``hs_context_load_tuning``)."""
+        _check(load_library().hs_context_load_tuning(self.handle, os.fsencode(path)))
+
+    def save_tuning(self, path):
+        """Write this context's tuning cache as JSON (``hs_context_save_tuning``)."""
+        _check(load_library().hs_context_save_tuning(self.handle, os.fsencode(path)))
 
     def close(self):
         if self.handle:
