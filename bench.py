@@ -538,6 +538,11 @@ def measure(args, name):
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
             "kernel": dominant, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
             "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
+    if BYTES_PER_JOINT[name] == 108 and name != "long_chains":
+        # the achievable rate of this access pattern, measured beside it
+        probe = stream_probe_gbs(torch, w.hs, N)
+        roof["stream_probe_GBs"] = probe
+        roof["frac_of_stream_probe"] = achieved / probe
     if diff:
         roof["forward_kernel_ms"] = fwd_ms
         roof["two_call_ms_per_step"] = w.graph_step_ms(w.two_call_graph)
@@ -865,6 +870,30 @@ def device_copy_gbs(torch, nbytes=1 << 30, reps=10):
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def stream_probe_gbs(torch, hs, n, reps=20):
+    """Rate of hs_stream_probe over n joints: the forward's 108 bytes per
+    joint (44 read, 64 written, the same access pattern) with no
+    arithmetic, the HBM rate this kernel shape can reach."""
+    dev = "cuda:0"
+    q = torch.zeros((n, 4), device=dev)
+    t = torch.zeros((n, 3), device=dev)
+    s = torch.zeros((n, 3), device=dev)
+    tab = torch.zeros((n,), device=dev, dtype=torch.int32)
+    out = torch.empty((n, 4, 4), device=dev)
+    for _ in range(3):
+        hs.hs_stream_probe(q, t, s, tab, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        hs.hs_stream_probe(q, t, s, tab, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del q, t, s, tab, out
+    return 108.0 * n / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(w):

@@ -329,6 +329,19 @@ typedef struct hs_clip_params {
 hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_clip_params *params,
                          float *quat_out, float *trans_out, hipStream_t stream);
 
+/* Measurement reference, not part of the method: moves the bytes of a
+ * forward scan of n joints and no arithmetic.  Reads quat [n,4] (16-byte
+ * aligned), trans [n,3], scale [n,3] and table [n] (any 4-byte values, as
+ * the scan reads one parent or code per joint) once each with streaming
+ * loads, one joint per lane, and writes out [n,4,4] (16-byte aligned) as
+ * the scan writes G: coalesced 16-byte rows through a per-wave LDS slice.
+ * The rows hold the inputs (row 0: q.x q.y q.z t.x; row 1: q.w s.x s.y
+ * t.y; row 2: s.z table-bits 0 t.z; row 3: 0 0 0 1).  Its speed is the
+ * HBM rate this access pattern can reach on the device.  Asynchronous on
+ * stream; allocates nothing; out must not overlap the inputs. */
+hs_status hs_stream_probe(int64_t n, const float *quat, const float *trans, const float *scale,
+                          const int32_t *table, float *out, hipStream_t stream);
+
 /* Reverse mode of hs_pose_sample: given dLoss/dquat [N,4] (raw components,
  * 16-byte aligned) and dLoss/dtrans [N,3] of the sampled local poses,
  * writes dLoss/dkey_quat [num_clips, num_keys, joints_per_clip, 4] and

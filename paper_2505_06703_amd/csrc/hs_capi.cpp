@@ -1910,6 +1910,25 @@ hs_status hs_pose_sample_backward_noalloc(const hs_plan *plan, const hs_clip_lib
                            grad_key_quat, grad_key_trans, grad_time, grad_weight, nullptr, true, stream);
 }
 
+hs_status hs_stream_probe(int64_t n, const float *quat, const float *trans, const float *scale,
+                          const int32_t *table, float *out, hipStream_t stream)
+{
+    if (n < 0) return fail(HS_ERR_INVALID_ARG, "hs_stream_probe: n must be >= 0");
+    if (n == 0) return HS_OK;
+    if (!quat || !trans || !scale || !table || !out)
+        return fail(HS_ERR_INVALID_ARG, "hs_stream_probe: arrays must be non-NULL");
+    if (!aligned(quat, 16) || !aligned(out, 16) || !aligned(trans, 4) || !aligned(scale, 4) || !aligned(table, 4))
+        return fail(HS_ERR_INVALID_ARG, "hs_stream_probe: quat and out must be 16-byte aligned, the rest 4");
+    const size_t N = (size_t)n;
+    std::vector<Range> ins = {{quat, N * 16, "quat"}, {trans, N * 12, "trans"}, {scale, N * 12, "scale"},
+                              {table, N * 4, "table"}};
+    hs_status rc = check_aliasing({{out, N * 64, "out"}}, ins);
+    if (rc != HS_OK) return rc;
+    hipError_t err = hs::launch_stream_probe(n, quat, trans, scale, table, out, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_stream_probe");
+    return HS_OK;
+}
+
 hs_status hs_effector_loss_grad(int64_t num_joints, int64_t num_effectors, const int64_t *effectors,
                                 const float *global, const float *targets, float *grad_global, hipStream_t stream)
 {

@@ -245,6 +245,8 @@ hipError_t prepare_kernels();
 hipError_t launch_validate(const int64_t *offsets, int64_t num_chars, const int32_t *parent, const int32_t *level,
                            uint32_t *status, hipStream_t stream);
 
+hipError_t launch_stream_probe(int64_t n, const float *quat, const float *trans, const float *scale,
+                               const int32_t *table, float *out, hipStream_t stream);
 hipError_t launch_effector_grad(int64_t n, int64_t ne, const int64_t *eff, const float *G, const float *target,
                                 float *grad, hipStream_t stream);
 

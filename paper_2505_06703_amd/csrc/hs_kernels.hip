@@ -3408,6 +3408,54 @@ hipError_t launch_pose_sample_backward(const PoseArgs &pose, const SampleBwdArgs
     return err;
 }
 
+// The forward's memory traffic without its arithmetic: per joint the same
+// reads (quat 16, trans 12, scale 12, a 4-byte table entry: streaming
+// loads, one joint per lane) and the same 64-byte output rows (coalesced
+// 16-byte stores, four per joint, through a per-wave LDS slice as the
+// scan's blocks store them), the rows holding the inputs so that nothing
+// can be dropped.
+__global__ void __launch_bounds__(256)
+stream_probe_kernel(int64_t n, const float *quat, const float *trans, const float *scale, const int32_t *table,
+                    float *out)
+{
+    __shared__ float4 slice[4][kWave * 3];
+    const int lane = threadIdx.x & (kWave - 1);
+    float4 *X = slice[threadIdx.x / kWave];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~(int64_t)(kWave - 1); base < n;
+         base += stride) {
+        const int64_t g = base + lane;
+        float m[12];
+        if (g < n) {
+            const native_float4 q = __builtin_nontemporal_load(reinterpret_cast<const native_float4 *>(quat) + g);
+            const float *t = trans + 3 * g, *sc = scale + 3 * g;
+            m[0] = q.x; m[1] = q.y; m[2] = q.z; m[3] = __builtin_nontemporal_load(t);
+            m[4] = q.w; m[5] = __builtin_nontemporal_load(sc); m[6] = __builtin_nontemporal_load(sc + 1);
+            m[7] = __builtin_nontemporal_load(t + 1);
+            m[8] = __builtin_nontemporal_load(sc + 2); m[9] = __int_as_float(__builtin_nontemporal_load(table + g));
+            m[10] = 0.0f; m[11] = __builtin_nontemporal_load(t + 2);
+        } else {
+            aff_identity(m);
+        }
+        wave_sync();
+        aff_store(X + 3 * lane, m);
+        wave_sync();
+        OutArgs o{};
+        o.global_out = out;
+        store_rows<1>(o, X, base, 0, 1, (int)std::min<int64_t>(kWave, n - base), lane);
+    }
+}
+
+hipError_t launch_stream_probe(int64_t n, const float *quat, const float *trans, const float *scale,
+                               const int32_t *table, float *out, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t waves = (n + kWave - 1) / kWave;
+    const dim3 grid((unsigned)std::min<int64_t>((waves + 3) / 4, 1 << 20));
+    hipLaunchKernelGGL(stream_probe_kernel, grid, dim3(256), 0, stream, n, quat, trans, scale, table, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_effector_grad(int64_t n, int64_t ne, const int64_t *eff, const float *G, const float *target,
                                 float *grad, hipStream_t stream)
 {

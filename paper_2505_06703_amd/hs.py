@@ -49,7 +49,7 @@ SYMBOLS = ("hs_version", "hs_last_error", "hs_context_create", "hs_context_destr
            "hs_effector_loss_grad", "hs_effectors_create", "hs_effectors_destroy", "hs_effectors_sparse",
            "hs_effector_backward", "hs_effector_step", "hs_plan_status", "hs_plan_set_wait_limit",
            "hs_plan_debug_break_parent", "hs_pose_sample_backward_noalloc", "hs_context_load_tuning",
-           "hs_context_save_tuning")
+           "hs_context_save_tuning", "hs_stream_probe")
 
 
 class HSError(RuntimeError):
@@ -130,6 +130,7 @@ def load_library():
     lib.hs_context_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
     lib.hs_context_destroy.argtypes = [vp]
     lib.hs_context_destroy.restype = None
+    lib.hs_stream_probe.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     lib.hs_context_load_tuning.argtypes = [vp, ctypes.c_char_p]
     lib.hs_context_save_tuning.argtypes = [vp, ctypes.c_char_p]
     lib.hs_plan_create.argtypes = [vp, ctypes.POINTER(hs_batch), ctypes.POINTER(hs_plan_opts),
@@ -430,6 +431,22 @@ def hs_pose_sample_backward_noalloc(plan, clips, clip_a, clip_b, time, weight, g
                                                           _ptr(grad_trans), _ptr(gkq), _ptr(gkt),
                                                           _ptr(gtime), _ptr(gw), _stream(stream)))
     return gkq, gkt, gtime, gw
+
+
+def hs_stream_probe(quat, trans, scale, table, out=None, stream=None):
+    """The forward's HBM traffic without its arithmetic (``hs_stream_probe``):
+    returns out [n,4,4]."""
+    n = quat.shape[0]
+    _need(quat, "quat", (n, 4))
+    _need(trans, "trans", (n, 3))
+    _need(scale, "scale", (n, 3))
+    _need(table, "table", (n,), torch.int32)
+    if out is None:
+        out = torch.empty((n, 4, 4), device=quat.device, dtype=torch.float32)
+    _need(out, "out", (n, 4, 4))
+    _check(load_library().hs_stream_probe(n, _ptr(quat), _ptr(trans), _ptr(scale), _ptr(table), _ptr(out),
+                                          _stream(stream)))
+    return out
 
 
 def _trs_src(plan, quat, trans, scale):

@@ -179,3 +179,30 @@ def test_plan_info_reports_tiles_and_multipass():
     assert inf["tiled_joints"] + inf["multipass_joints"] == b.num_joints
     assert inf["multipass_joints"] == int(np.sum(np.diff(b.offsets)[np.diff(b.offsets) > 512]))
     assert inf["tile_joints"] == 512 and inf["num_tiles"] > 0
+
+
+def test_stream_probe_moves_the_forward_bytes_verbatim():
+    """hs_stream_probe (the bandwidth reference): every input value lands in
+    its row of the output, for a ragged size and an exact multiple of 64."""
+    rng = np.random.default_rng(9)
+    for n in (1, 64, 1000, 4096 + 37):
+        q = rng.standard_normal((n, 4)).astype(np.float32)
+        t = rng.standard_normal((n, 3)).astype(np.float32)
+        s = rng.standard_normal((n, 3)).astype(np.float32)
+        tab = rng.integers(-1, 1 << 20, n).astype(np.int32)
+        out = hs.hs_stream_probe(dev(q), dev(t), dev(s), dev(tab))
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        ref = np.zeros((n, 4, 4), np.float32)
+        ref[:, 0, :3], ref[:, 0, 3] = q[:, :3], t[:, 0]
+        ref[:, 1, 0], ref[:, 1, 1:3], ref[:, 1, 3] = q[:, 3], s[:, :2], t[:, 1]
+        ref[:, 2, 0], ref[:, 2, 3] = s[:, 2], t[:, 2]
+        ref[:, 3, 3] = 1.0
+        bits = o[:, 2, 1].view(np.int32).copy()
+        o[:, 2, 1] = 0.0
+        assert np.array_equal(o, ref), n
+        assert np.array_equal(bits, tab), n
+    qd = dev(q)  # output overlapping an input: refused, nothing launched
+    rc = hs.load_library().hs_stream_probe(n, qd.data_ptr(), dev(t).data_ptr(), dev(s).data_ptr(),
+                                           dev(tab).data_ptr(), qd.data_ptr(), None)
+    assert rc == hs.HS_ERR_INVALID_ARG
