@@ -88,6 +88,8 @@ DOMINANT = {"differentiable": "bwd_anchor_kernel",
 # kernel: the differentiable run also times the dense route, whose adjoint
 # is the other instance of the same template
 PMC_MATCH = {"differentiable": ("bwd_anchor_kernel<", ", 2>")}
+# fused workloads: the instance that samples poses in the kernel
+SAMPLE_INSTANCE = ", true"
 CHUNK = 8  # at least this many forward passes per captured graph replay
 CKPT_K = 8  # levels between checkpoints in the differentiable form's checkpoint mode
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
@@ -128,6 +130,11 @@ def parse():
                     help="use the plan's default launch shape instead of timing candidates at plan time")
     ap.add_argument("--adjoint", default="auto", choices=("auto", "rounds", "dataflow", "anchors"),
                     help="adjoint kernel for characters of up to 1024 joints (differentiable workload)")
+    ap.add_argument("--schedule", choices=("auto", "queue", "classes"),
+                    help="forward schedule of the plan (with --tile-joints/--waves: a fixed launch shape, "
+                         "no autotuning; for profiling the shape an autotuned run picked)")
+    ap.add_argument("--tile-joints", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--depth-sweep", action="store_true",
@@ -137,6 +144,16 @@ def parse():
                     help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE run, WRITE_SIZE run) "
                          "into profiles/traffic.json for --workload and exit")
     return ap.parse_args()
+
+
+def fixed_shape(args):
+    """Plan options of a fixed launch shape from the command line, or None."""
+    if not (args.schedule or args.tile_joints or args.waves):
+        return None
+    from paper_2505_06703_amd import hs
+    sched = {None: hs.HS_SCHED_AUTO, "auto": hs.HS_SCHED_AUTO, "queue": hs.HS_SCHED_QUEUE,
+             "classes": hs.HS_SCHED_CLASSES}[args.schedule]
+    return {"schedule": sched, "tile_joints": args.tile_joints, "waves_per_tile": args.waves}
 
 
 def summarize_pmc(workload, fetch_csv, write_csv):
@@ -150,7 +167,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
         with open(fetch_csv) as f:
             queued = any("fwd_queue_kernel" in r.get("Kernel_Name", "") for r in csv.DictReader(f))
         kname = "fwd_queue_kernel" if queued else "fwd_tile_kernel"
-    match = PMC_MATCH.get(workload, (kname,))
+    match = PMC_MATCH.get(workload, (kname,) + ((SAMPLE_INSTANCE,) if workload in FUSED else ()))
 
     def per_kernel(path, counter):
         scan, copy = [], None
@@ -193,7 +210,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
 class Workload:
     """Device-resident inputs/outputs of one preset and its step."""
 
-    def __init__(self, name, autotune, adjoint="auto"):
+    def __init__(self, name, autotune, adjoint="auto", shape=None):
         import torch
         from paper_2505_06703_amd import hs
         from paper_2505_06703_amd import workloads as wl
@@ -215,7 +232,7 @@ class Workload:
             self.inv = up(np.linalg.inv(Grest.cpu().numpy().astype(np.float64)).astype(np.float32))
             del Grest, one
         else:
-            self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune, adjoint=adj)
+            self.plan = hs.Plan(b.offsets, b.parents, autotune=autotune and not shape, adjoint=adj, **(shape or {}))
         if name in ("plain_scan", "fused_sample"):
             # inverse binds from the rest pose: scan it on the GPU, invert on the host
             Grest, _ = hs.hs_scan_forward(self.plan, up(b.rest_quat), up(b.rest_trans), up(b.rest_scale))
@@ -484,7 +501,7 @@ def measure(args, name):
     """Time one workload's steps and return its JSON record (without the
     keys of the line's frame: metric, n_gpus, ...)."""
     import torch
-    w = Workload(name, autotune=not args.no_autotune, adjoint=args.adjoint)
+    w = Workload(name, autotune=not args.no_autotune, adjoint=args.adjoint, shape=fixed_shape(args))
     b, info = w.b, w.plan.info
     N, C = b.num_joints, b.num_characters
 
@@ -558,7 +575,7 @@ def measure(args, name):
                    "tile_joints": info["tile_joints"], "waves_per_tile": info["waves_per_tile"],
                    "grid": info["grid"], "tiles": info["num_tiles"], "multipass_joints": info["multipass_joints"],
                    "schedule": "queue" if info["schedule"] == w.hs.HS_SCHED_QUEUE else "size classes",
-                   "autotuned": not args.no_autotune, "hip_graph": mode == "graph",
+                   "autotuned": not args.no_autotune and not fixed_shape(args), "hip_graph": mode == "graph",
                    "input_sets": len(w.sets),
                    **({"adjoint": args.adjoint} if diff else {})},
         "roofline": roof,

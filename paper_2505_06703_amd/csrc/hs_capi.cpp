@@ -426,7 +426,8 @@ struct hs_plan {
     // size classes instead
     struct QueueSet {
         hs::QTile *d_tiles = nullptr;
-        int32_t num_tiles = 0, grid = 0, grid_sample = 0, waves = 0, max_anchors = 0, cap = 0;
+        int32_t num_tiles = 0, grid = 0, waves = 0, max_anchors = 0, cap = 0;
+        int32_t grids[2][2] = {{0, 0}, {0, 0}};  // by [sampled poses][skin rows]
         int32_t *d_code = nullptr;
     } q;
     int sched_opt = HS_SCHED_AUTO;
@@ -806,9 +807,8 @@ hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *bui
         max_anchors = std::max(max_anchors, na);
     }
     const int waves = shape.queue_waves;
-    const size_t lds = hs::forward_queue_lds_bytes(waves, max_anchors, cap, false);
-    const size_t lds_s = hs::forward_queue_lds_bytes(waves, max_anchors, cap, true);
-    if (max_anchors > hs::kQMaxAnchors || cap > hs::kQMaxTileJoints || lds_s > plan->ctx->max_lds) return HS_OK;
+    const size_t lds_max = hs::forward_queue_lds_bytes(waves, max_anchors, cap, true, true);
+    if (max_anchors > hs::kQMaxAnchors || cap > hs::kQMaxTileJoints || lds_max > plan->ctx->max_lds) return HS_OK;
     hipError_t err = upload(&Q.d_tiles, qt);
     if (err == hipSuccess) err = upload(&Q.d_code, code);
     if (err != hipSuccess) return fail_hip(err, "hs_plan_create (work queue)");
@@ -818,15 +818,17 @@ hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *bui
     Q.waves = waves;
     // as many workgroups as fit the CUs at once (each pose source has its
     // own instance, registers and LDS)
-    for (int smp = 0; smp < 2; ++smp) {
-        int per_cu = 1;
-        if ((err = hs::queue_blocks_per_cu(waves, smp != 0, smp ? lds_s : lds, &per_cu)) != hipSuccess)
-            return fail_hip(err, "hs_plan_create (work-queue occupancy)");
-        per_cu = std::max(1, shape.grid_per_cu > 0 ? std::min(per_cu, shape.grid_per_cu) : per_cu);
-        const int32_t g =
-            (int32_t)std::max<int64_t>(1, std::min<int64_t>(Q.num_tiles, (int64_t)per_cu * plan->ctx->num_cu));
-        (smp ? Q.grid_sample : Q.grid) = g;
-    }
+    for (int smp = 0; smp < 2; ++smp)
+        for (int skin = 0; skin < 2; ++skin) {
+            int per_cu = 1;
+            const size_t lds = hs::forward_queue_lds_bytes(waves, max_anchors, cap, smp != 0, skin != 0);
+            if ((err = hs::queue_blocks_per_cu(waves, smp != 0, lds, &per_cu)) != hipSuccess)
+                return fail_hip(err, "hs_plan_create (work-queue occupancy)");
+            per_cu = std::max(1, shape.grid_per_cu > 0 ? std::min(per_cu, shape.grid_per_cu) : per_cu);
+            Q.grids[smp][skin] =
+                (int32_t)std::max<int64_t>(1, std::min<int64_t>(Q.num_tiles, (int64_t)per_cu * plan->ctx->num_cu));
+        }
+    Q.grid = Q.grids[0][0];
     *built = true;
     return HS_OK;
 }
@@ -1107,7 +1109,7 @@ hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Out
         ql.num_tiles = plan->q.num_tiles;
         ql.waves = plan->q.waves;
         ql.grid = plan->q.grid;
-        ql.grid_sample = plan->q.grid_sample;
+        std::memcpy(ql.grids, plan->q.grids, sizeof ql.grids);
         ql.max_anchors = plan->q.max_anchors;
         ql.tile_cap = plan->q.cap;
         ql.code = plan->q.d_code;

@@ -81,8 +81,11 @@ struct QueueLaunch {
     const QTile *tiles;       // heaviest first
     int32_t num_tiles;
     int32_t waves;            // 4, 8 or 16
-    int32_t grid;             // persistent workgroups (<= num_tiles), stored poses
-    int32_t grid_sample;      // the same for poses sampled in the kernel
+    // persistent workgroups (<= num_tiles) by [poses sampled in the kernel]
+    // [skin rows staged]: each instance and LDS layout has its own occupancy;
+    // grid: the one launched (set by launch_forward_queue)
+    int32_t grids[2][2];
+    int32_t grid;
     int32_t max_anchors;      // LDS anchor slots (largest num_anchors)
     int32_t tile_cap;         // largest tile (the fused sampler's character table)
     const int32_t *code;      // [N] per-joint codes
@@ -217,7 +220,7 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
                                 hipStream_t stream);
 hipError_t launch_forward_queue(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
                                 hipStream_t stream);
-size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample);
+size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample, bool skin);
 size_t backward_anchor_lds_bytes(int waves, int max_anchors);
 // Workgroups of the queue kernel (stored or sampled poses) that fit one CU
 // with `lds` bytes of LDS.

@@ -303,23 +303,24 @@ __device__ __forceinline__ void wave_inblock_scan(float m[12], int &a, int &e, i
 }
 
 // The same scan with the rows moving through the wave's own LDS slice (X:
-// [64][3] float4, xi: [64] int) with 16-byte accesses instead of 4-byte
+// [64][S] float4, S >= 3, xi: [64] int) with 16-byte accesses instead of 4-byte
 // cross-lane permutes (measured faster on deep chains); the products and
 // their order are those of wave_inblock_scan, so the results are bitwise
 // equal.  e must fit 24 bits.
-__device__ __forceinline__ void wave_inblock_scan_lds(float m[12], int &a, int &e, int lane, float4 *X, int *xi)
+__device__ __forceinline__ void wave_inblock_scan_lds(float m[12], int &a, int &e, int lane, float4 *X, int *xi,
+                                                      int S = 3)
 {
 #pragma unroll 1
     for (int r = 0; r < 6; ++r) {
         if (!__any(a >= 0)) break;
         const bool act = a >= 0;
         wave_sync();  // the previous round's reads are done
-        aff_store(X + 3 * lane, m);
+        aff_store(X + S * lane, m);
         xi[lane] = (a + 1) | ((e + 1) << 7);
         wave_sync();
         if (act) {
             float ma[12];
-            aff_load(X + 3 * a, ma);
+            aff_load(X + S * a, ma);
             const int pk = xi[a];
             aff_mul_left(ma, m);
             const int aa = (pk & 127) - 1;
@@ -838,7 +839,8 @@ fwd_tile_kernel(TileLaunch tl, PoseArgs pose, OutArgs out)
 // flag, composes once, stores its anchors' transforms and raises their
 // flags.  The LDS footprint therefore follows the anchor count, not the
 // tile size, and large tiles keep several workgroups per CU.
-// LDS: staging [WAVES][64][3] float4 (also the in-block scan's slices) |
+// LDS: staging [WAVES][64][3 or 4] float4 (also the in-block scan's slices;
+// 4 rows when skin rows are staged) |
 // scan ints [WAVES][64] | anchors [max_anchors][3] float4 | flags
 // [max_anchors] int | (SAMPLE) char starts [tile_cap + 1]
 // ---------------------------------------------------------------------------
@@ -856,9 +858,26 @@ __device__ __forceinline__ void wait_slot(const int *flags, int e, uint32_t *sta
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Rows of the block's 64 joints from the wave's slice X (stride S float4
+// per joint; `rows` of them hold data: with 3 the fourth row is the
+// constant (0, 0, 0, 1)) to dst (four 16-byte rows per joint, n joints at
+// most): each store instruction covers 1 KiB of contiguous output, written
+// with the streaming hint.
+__device__ __forceinline__ void store_slice_rows(float4 *dst, const float4 *X, int S, int rows, int n, int lane)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = lane + kWave * k;
+        const int jj = c >> 2, r = c & 3;
+        if (jj < n) store_stream(dst + c, r < rows ? X[S * jj + r] : make_float4(0.0f, 0.0f, 0.0f, 1.0f));
+    }
+}
+
+// SS: float4 rows per joint in the staging slice (3, or 4 when skin rows
+// are staged too)
 template <bool SAMPLE>
 __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
-                                            const QTile &td, int b, float4 *stage, int *xi, float4 *anc,
+                                            const QTile &td, int b, float4 *stage, int SS, int *xi, float4 *anc,
                                             int *flags, const int *cstart, int lane)
 {
     const int base = b * kWave;
@@ -882,7 +901,7 @@ __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArg
     } else {
         aff_identity(m);
     }
-    wave_inblock_scan_lds(m, a, e, lane, stage, xi);
+    wave_inblock_scan_lds(m, a, e, lane, stage, xi, SS);
     wait_slot(flags, valid ? e : -1, ql.status, ql.spin_limit);
     if (valid && e >= 0) {
         float g[12];
@@ -890,13 +909,41 @@ __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArg
         aff_mul_left(g, m);
     }
     if (own >= 0) aff_store(anc + 3 * own, m);
-    aff_store(stage + 3 * lane, m);
+    aff_store(stage + SS * lane, m);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (own >= 0) __hip_atomic_store(flags + own, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (out.global_out) store_rows<1>(out, stage, td.begin + base, 0, 1, td.count - base, lane);
-    if (valid) write_skin_and_ckpt(out, gid, gid, m);
+    const int nb = td.count - base;  // joints of this block (may exceed 64: clipped by the row stores)
+    if (out.global_out)
+        store_slice_rows(reinterpret_cast<float4 *>(out.global_out) + 4 * (td.begin + base), stage, SS, 3, nb, lane);
+    if (out.skin_out) {
+        // S = G B^-1 (the bottom row of S is B^-1's), staged like G so that
+        // the rows leave as whole lines
+        float4 srow[4];
+        if (valid) {
+            const float4 *B = reinterpret_cast<const float4 *>(out.inv_bind) + 4 * gid;
+            const float4 b0 = B[0], b1 = B[1], b2 = B[2], b3 = B[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const float g0 = m[4 * r], g1 = m[4 * r + 1], g2 = m[4 * r + 2], g3 = m[4 * r + 3];
+                srow[r] = make_float4(fmaf(g0, b0.x, fmaf(g1, b1.x, fmaf(g2, b2.x, g3 * b3.x))),
+                                      fmaf(g0, b0.y, fmaf(g1, b1.y, fmaf(g2, b2.y, g3 * b3.y))),
+                                      fmaf(g0, b0.z, fmaf(g1, b1.z, fmaf(g2, b2.z, g3 * b3.z))),
+                                      fmaf(g0, b0.w, fmaf(g1, b1.w, fmaf(g2, b2.w, g3 * b3.w))));
+            }
+            srow[3] = b3;
+        } else {
+            srow[0] = srow[1] = srow[2] = srow[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        wave_sync();  // the G rows have left the slice
+#pragma unroll
+        for (int r = 0; r < 4; ++r) stage[4 * lane + r] = srow[r];
+        wave_sync();
+        store_slice_rows(reinterpret_cast<float4 *>(out.skin_out) + 4 * (td.begin + base), stage, 4, 4, nb, lane);
+    }
+    if (valid && out.ckpt && out.level[gid] % out.ckpt_k == 0)
+        aff_store(reinterpret_cast<float4 *>(out.ckpt) + 3 * gid, m);
     // the slice is written again by this wave's next block only after
     // every lane's reads above
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -911,9 +958,10 @@ fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
     if (gated(ql.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    float4 *stage = lds + wave * kWave * 3;
-    int *xi = reinterpret_cast<int *>(lds + WAVES * kWave * 3) + wave * kWave;
-    float4 *anc = lds + WAVES * kWave * 3 + WAVES * kWave / 4;
+    const int SS = out.skin_out ? 4 : 3;  // staged rows per joint
+    float4 *stage = lds + wave * kWave * SS;
+    int *xi = reinterpret_cast<int *>(lds + WAVES * kWave * SS) + wave * kWave;
+    float4 *anc = lds + WAVES * kWave * SS + WAVES * kWave / 4;
     int *flags = reinterpret_cast<int *>(anc + 3 * ql.max_anchors);
     int *cstart = flags + ql.max_anchors;
 
@@ -933,7 +981,7 @@ fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
         __syncthreads();
         const int nblk = (td.count + kWave - 1) / kWave;
         for (int b = wave; b < nblk; b += WAVES)
-            queue_block<SAMPLE>(ql, pose, out, td, b, stage, xi, anc, flags, cstart, lane);
+            queue_block<SAMPLE>(ql, pose, out, td, b, stage, SS, xi, anc, flags, cstart, lane);
         __syncthreads();  // LDS is reused by the next tile
     }
 }
@@ -3268,9 +3316,9 @@ hipError_t prepare_kernels()
     return set_lds_limits<16>();
 }
 
-size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample)
+size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample, bool skin)
 {
-    size_t bytes = (size_t)waves * kWave * 52 + (size_t)max_anchors * 52;
+    size_t bytes = (size_t)waves * kWave * (skin ? 68 : 52) + (size_t)max_anchors * 52;
     if (sample) bytes += (size_t)(tile_cap + 1) * 4;
     return bytes;
 }
@@ -3520,7 +3568,7 @@ size_t forward_vertex_lds_bytes(int tile_cap)
 template <int WAVES, bool SAMPLE>
 hipError_t launch_queue_t(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out, hipStream_t stream)
 {
-    const size_t lds = forward_queue_lds_bytes(WAVES, ql.max_anchors, ql.tile_cap, SAMPLE);
+    const size_t lds = forward_queue_lds_bytes(WAVES, ql.max_anchors, ql.tile_cap, SAMPLE, out.skin_out != nullptr);
     hipLaunchKernelGGL((fwd_queue_kernel<WAVES, SAMPLE>), dim3(ql.grid), dim3(WAVES * kWave), lds, stream, ql, pose,
                        out);
     return hipGetLastError();
@@ -3555,7 +3603,7 @@ hipError_t launch_forward_queue(const QueueLaunch &ql, const PoseArgs &pose, con
     const bool sample = pose.kind == 1;
     if (sample && !pose.offsets) return hipErrorInvalidValue;
     QueueLaunch q = ql;
-    q.grid = sample ? ql.grid_sample : ql.grid;
+    q.grid = ql.grids[sample ? 1 : 0][out.skin_out ? 1 : 0];
     if (q.grid < 1) return hipErrorInvalidValue;
     switch (ql.waves) {
     case 1: return sample ? launch_queue_t<1, true>(q, pose, out, stream) : launch_queue_t<1, false>(q, pose, out, stream);
