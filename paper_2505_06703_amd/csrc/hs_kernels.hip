@@ -303,12 +303,13 @@ __device__ __forceinline__ void wave_inblock_scan(float m[12], int &a, int &e, i
 }
 
 // The same scan with the rows moving through the wave's own LDS slice (X:
-// [64][S] float4, S >= 3, xi: [64] int) with 16-byte accesses instead of 4-byte
+// [64][S] float4, S >= 3) with 16-byte accesses instead of 4-byte
 // cross-lane permutes (measured faster on deep chains); the products and
 // their order are those of wave_inblock_scan, so the results are bitwise
-// equal.  e must fit 24 bits.
+// equal.  xi: [64] int holding a and e packed (e < 2^24), or with xe
+// non-null a in xi and e in xe ([64] int each).
 __device__ __forceinline__ void wave_inblock_scan_lds(float m[12], int &a, int &e, int lane, float4 *X, int *xi,
-                                                      int S = 3)
+                                                      int S = 3, int *xe = nullptr)
 {
 #pragma unroll 1
     for (int r = 0; r < 6; ++r) {
@@ -316,15 +317,27 @@ __device__ __forceinline__ void wave_inblock_scan_lds(float m[12], int &a, int &
         const bool act = a >= 0;
         wave_sync();  // the previous round's reads are done
         aff_store(X + S * lane, m);
-        xi[lane] = (a + 1) | ((e + 1) << 7);
+        if (xe) {
+            xi[lane] = a;
+            xe[lane] = e;
+        } else {
+            xi[lane] = (a + 1) | ((e + 1) << 7);
+        }
         wave_sync();
         if (act) {
             float ma[12];
             aff_load(X + S * a, ma);
-            const int pk = xi[a];
+            int aa, ea;
+            if (xe) {
+                aa = xi[a];
+                ea = xe[a];
+            } else {
+                const int pk = xi[a];
+                aa = (pk & 127) - 1;
+                ea = (pk >> 7) - 1;
+            }
             aff_mul_left(ma, m);
-            const int aa = (pk & 127) - 1;
-            if (aa < 0) e = (pk >> 7) - 1;
+            if (aa < 0) e = ea;
             a = aa;
         }
     }
@@ -2666,9 +2679,12 @@ template <bool SAMPLE>
 __global__ void __launch_bounds__(kMPWaves * kWave)
 mp_local_kernel(MPLaunch ml, PoseArgs pose)
 {
+    __shared__ float4 slice[kMPWaves * kWave * 3];
+    __shared__ int xs[2 * kMPWaves * kWave];
     if (gated(ml.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
+    const int wv = threadIdx.x / kWave;
+    const int w = blockIdx.x * kMPWaves + wv;
     if (w >= ml.num_blocks) return;  // whole waves leave together
     const MPBlock bd = ml.blocks[w];
     const bool valid = lane < bd.count;
@@ -2688,7 +2704,8 @@ mp_local_kernel(MPLaunch ml, PoseArgs pose)
     } else {
         aff_identity(m);
     }
-    wave_inblock_scan(m, a, e, lane);
+    wave_inblock_scan_lds(m, a, e, lane, slice + wv * kWave * 3, xs + 2 * wv * kWave, 3,
+                          xs + (2 * wv + 1) * kWave);
     // only the anchors' in-block products leave the kernel (the output pass
     // recomputes the others from the poses): anchor i starts the rounds from
     // its phase-1 product and the anchor index of its own anchor
@@ -2775,6 +2792,7 @@ __global__ void __launch_bounds__(kMPWaves * kWave)
 mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 *Gc)
 {
     __shared__ float4 stage[kMPWaves * kWave * 3];
+    __shared__ int xs[2 * kMPWaves * kWave];
     if (gated(ml.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -2798,7 +2816,7 @@ mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 
     } else {
         aff_identity(m);
     }
-    wave_inblock_scan(m, a, e, lane);
+    wave_inblock_scan_lds(m, a, e, lane, stage + wv * kWave * 3, xs + 2 * wv * kWave, 3, xs + (2 * wv + 1) * kWave);
     const int an = valid ? ml.janc[cid] : -1;
     if (an >= 0) {
         float g[12];
