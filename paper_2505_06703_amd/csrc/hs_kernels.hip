@@ -76,21 +76,23 @@ __device__ __forceinline__ void aff_identity(float m[12])
 __device__ __forceinline__ void aff_from_trs(float4 q, float tx, float ty, float tz, float sx,
                                              float sy, float sz, float m[12])
 {
+    // every sum is written as an explicit fma so that the rounding does not
+    // depend on how the compiler contracts the surrounding code: every
+    // kernel forms bitwise the same local transform from the same pose
     const float x = q.x, y = q.y, z = q.z, w = q.w;
-    const float xx = x * x, yy = y * y, zz = z * z;
-    const float xy = x * y, xz = x * z, yz = y * z;
+    const float yy = y * y, zz = z * z;
     const float wx = w * x, wy = w * y, wz = w * z;
-    m[0] = (1.0f - 2.0f * (yy + zz)) * sx;
-    m[1] = 2.0f * (xy - wz) * sy;
-    m[2] = 2.0f * (xz + wy) * sz;
+    m[0] = fmaf(-2.0f, fmaf(y, y, zz), 1.0f) * sx;
+    m[1] = 2.0f * fmaf(x, y, -wz) * sy;
+    m[2] = 2.0f * fmaf(x, z, wy) * sz;
     m[3] = tx;
-    m[4] = 2.0f * (xy + wz) * sx;
-    m[5] = (1.0f - 2.0f * (xx + zz)) * sy;
-    m[6] = 2.0f * (yz - wx) * sz;
+    m[4] = 2.0f * fmaf(x, y, wz) * sx;
+    m[5] = fmaf(-2.0f, fmaf(x, x, zz), 1.0f) * sy;
+    m[6] = 2.0f * fmaf(y, z, -wx) * sz;
     m[7] = ty;
-    m[8] = 2.0f * (xz - wy) * sx;
-    m[9] = 2.0f * (yz + wx) * sy;
-    m[10] = (1.0f - 2.0f * (xx + yy)) * sz;
+    m[8] = 2.0f * fmaf(x, z, -wy) * sx;
+    m[9] = 2.0f * fmaf(y, z, wx) * sy;
+    m[10] = fmaf(-2.0f, fmaf(x, x, yy), 1.0f) * sz;
     m[11] = tz;
 }
 
