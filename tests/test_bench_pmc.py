@@ -1,8 +1,8 @@
 """Host logic of bench.py's HBM-traffic summary (--summarize-pmc) on
 synthetic rocprofv3 counter files: the calibration copy is the first copy
-of at least 1/16 of its size (not the small setup copies before it, nor the
-larger bandwidth probe after it), and only the dominant kernel's instance
-is averaged; no GPU."""
+that writes its size (not the input uploads or small setup copies before
+it, nor the larger bandwidth probe after it), and only the dominant
+kernel's instance is averaged; no GPU."""
 import csv
 import json
 
@@ -68,7 +68,8 @@ def test_records_of_other_workloads_are_kept(tmp_path, monkeypatch):
     (tmp_path / "traffic.json").write_text(json.dumps({"long_chains": {"kernel": "x"}}))
     copy = "__amd_rocclr_copyBuffer"
     rows = [(1, copy, 128.0 * MIB), (2, "fwd_tile_kernel<8, false, 0>", 1.0)]
-    run(tmp_path, monkeypatch, "deep_forward", rows, rows)
+    wrows = [(1, copy, 256.0 * MIB), (2, "fwd_tile_kernel<8, false, 0>", 1.0)]
+    run(tmp_path, monkeypatch, "deep_forward", rows, wrows)
     data = json.load(open(tmp_path / "traffic.json"))
     assert set(data) == {"long_chains", "deep_forward"}
 
@@ -82,3 +83,16 @@ def test_the_work_queue_launch_is_the_forward_kernel_when_present(tmp_path, monk
     assert rec["kernel"] == "fwd_queue_kernel"
     assert rec["fetch_bytes_per_launch"] == 30.0 * MIB * 1024.0 * 2.0
     assert rec["write_bytes_per_launch"] == 64.0 * MIB * 1024.0
+
+
+def test_input_uploads_before_the_calibration_copy_are_skipped(tmp_path, monkeypatch):
+    copy = "__amd_rocclr_copyBuffer"
+    kern = "void hs::fwd_queue_kernel<4, true>(hs::QueueLaunch)"
+    # 156.25 MiB uploads of the inputs come first; the calibration copy
+    # (256 MiB written, half of it counted by FETCH_SIZE) follows
+    fetch = [(3, copy, 156.25 * MIB), (4, copy, 156.25 * MIB), (7, copy, 128.0 * MIB), (8, kern, 200.0 * MIB)]
+    write = [(3, copy, 156.25 * MIB), (4, copy, 156.25 * MIB), (7, copy, 256.0 * MIB), (8, kern, 156.25 * MIB)]
+    rec = run(tmp_path, monkeypatch, "fused_sample", fetch, write)
+    assert rec["copy_dispatch"] == [7, 7]
+    assert rec["copy_fetch_scale"] == 2.0 and rec["copy_write_scale"] == 1.0
+    assert rec["write_bytes_per_launch"] == 156.25 * MIB * 1024.0
