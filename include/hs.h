@@ -135,6 +135,10 @@ typedef struct hs_plan_opts {
     int32_t adjoint;        /* HS_ADJ_*: the kernel that runs the adjoint of characters of up to
                                1024 joints */
     int32_t schedule;       /* HS_SCHED_*: how hs_scan_forward launches the tiles */
+    int32_t adjoint_blocks_per_wave; /* HS_ADJ_ANCHORS: 64-joint blocks that each wave of the
+                               two-level adjoint takes (1 or 2); 0 = choose: 2 when it lets
+                               the batch's adjoint tiles run in fewer rounds of resident
+                               workgroups, else 1 */
 } hs_plan_opts;
 
 /* Forward schedules (hs_scan_forward; the other tiled calls keep the size
@@ -207,6 +211,8 @@ typedef struct hs_plan_info {
     int32_t max_block_chain;   /* longest chain of 64-joint blocks on any path */
     int32_t schedule;          /* HS_SCHED_QUEUE or HS_SCHED_CLASSES: the forward's launches */
     int32_t max_anchors;       /* queue: most anchors of one tile (LDS slots), else 0 */
+    int32_t adjoint_blocks_per_wave; /* two-level adjoint of hs_effector_step: 64-joint blocks
+                                  per wave (0: the plan has no such tiles) */
 } hs_plan_info;
 
 /* Analyse a batch: validates the CSR topology (HS_ERR_TOPOLOGY if some

@@ -405,6 +405,8 @@ struct hs_plan {
     int32_t *d_bcode = nullptr;  // anchor codes of the adjoint tiles' joints
     int32_t b_max_anchors = 0;
     bool b_anchor_ok = false;    // the two-level adjoint fits the LDS
+    int b_bpw_opt = 0;           // the two-level adjoint's blocks per wave as asked (0 = choose)
+    int b_bpw[3] = {1, 1, 1};    // ... as chosen, per seed kind (dense, effectors, forward in the tile)
     int64_t bwd_untiled = 0;  // joints the adjoint's tiles do not cover
     int32_t max_units = 0;
     // multipass: characters larger than the forward tile (mp) and than the
@@ -911,8 +913,27 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
                 plan->b_max_anchors = std::max(plan->b_max_anchors, tile_codes(plan, t, code, slot));
             int w = 1;
             while (w * 64 < plan->bwd_cap) w *= 2;
-            plan->b_anchor_ok = plan->b_max_anchors <= hs::kQMaxAnchors &&
-                                hs::backward_anchor_lds_bytes(w, plan->b_max_anchors) <= plan->ctx->max_lds;
+            const size_t lds1 = hs::backward_anchor_lds_bytes(w, plan->b_max_anchors, plan->bwd_cap);
+            const size_t lds2 = hs::backward_anchor_lds_bytes(std::max(1, w / 2), plan->b_max_anchors, plan->bwd_cap);
+            const int64_t tiles = (int64_t)ps.tiles.size();
+            const int nc = std::max(1, plan->ctx->num_cu);
+            plan->b_anchor_ok = plan->b_max_anchors <= hs::kQMaxAnchors && lds1 <= plan->ctx->max_lds;
+            // blocks per wave, per seed kind: two when the resident
+            // workgroups then cover the tiles in fewer rounds (the adjoint
+            // is latency-bound, so a round costs about one tile's time)
+            for (int kind = 0; kind < 3 && plan->b_anchor_ok; ++kind) {
+                int occ1 = 0, occ2 = 0;
+                hipError_t e4 = hs::anchor_blocks_per_cu(w, 1, kind, lds1, &occ1);
+                if (e4 == hipSuccess && w >= 2) e4 = hs::anchor_blocks_per_cu(w / 2, 2, kind, lds2, &occ2);
+                if (e4 != hipSuccess) return fail_hip(e4, "hs_plan_create (adjoint occupancy)");
+                const int64_t r1 = occ1 > 0 ? (tiles + (int64_t)occ1 * nc - 1) / ((int64_t)occ1 * nc) : INT64_MAX;
+                const int64_t r2 = occ2 > 0 ? (tiles + (int64_t)occ2 * nc - 1) / ((int64_t)occ2 * nc) : INT64_MAX;
+                int bpw = r2 < r1 ? 2 : 1;
+                if (plan->b_bpw_opt == 2 && w >= 2 && occ2 > 0) bpw = 2;
+                if (plan->b_bpw_opt == 1 && occ1 > 0) bpw = 1;
+                if (bpw == 1 && occ1 == 0) plan->b_anchor_ok = false;
+                plan->b_bpw[kind] = bpw;
+            }
             hipError_t e3 = upload(&plan->d_bcode, code);
             if (e3 != hipSuccess) return fail_hip(e3, "hs_plan_create (adjoint codes)");
         }
@@ -948,6 +969,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
     I.max_block_chain = std::max(max_chain_tiles, max_chain_mp);
     I.schedule = HS_SCHED_CLASSES;
     I.max_anchors = 0;
+    I.adjoint_blocks_per_wave = plan->num_btiles > 0 && plan->b_anchor_ok ? plan->b_bpw[2] : 0;
     bool queued = false;
     if (shape.queue_waves > 0 && strategy != HS_STRATEGY_MULTIPASS && !plan->inst && !shape.chain_units &&
         shape.algorithm == HS_ALG_SCAN) {
@@ -1478,6 +1500,8 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
         return fail(HS_ERR_INVALID_ARG, "unknown algorithm %d", o.algorithm);
     if (o.adjoint < HS_ADJ_AUTO || o.adjoint > HS_ADJ_ANCHORS)
         return fail(HS_ERR_INVALID_ARG, "unknown adjoint kernel %d", o.adjoint);
+    if (o.adjoint_blocks_per_wave < 0 || o.adjoint_blocks_per_wave > 2)
+        return fail(HS_ERR_INVALID_ARG, "adjoint_blocks_per_wave must be 0, 1 or 2");
     if (o.algorithm != HS_ALG_SCAN && o.chain_units)
         return fail(HS_ERR_INVALID_ARG, "chain units belong to the library's own scan (algorithm 0)");
     if (o.schedule == HS_SCHED_QUEUE &&
@@ -1588,6 +1612,7 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
     sh.algorithm = o.algorithm;
     sh.adjoint = o.adjoint;  // AUTO is resolved per call (the seeds decide)
     plan->sched_opt = o.schedule;
+    plan->b_bpw_opt = o.adjoint_blocks_per_wave;
     if (inst && o.schedule == HS_SCHED_QUEUE) {
         free_plan(plan);
         return fail(HS_ERR_UNSUPPORTED, "the work-queue schedule does not take instanced plans");
@@ -2024,6 +2049,7 @@ hs_status run_backward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Bw
         if (tl.adjoint == hs::kAdjAnchors && !plan->b_anchor_ok) tl.adjoint = hs::kAdjRounds;
         tl.code = plan->d_bcode;
         tl.max_anchors = plan->b_max_anchors;
+        tl.blocks_per_wave = plan->b_bpw[ba.eff_ids ? (ba.eff_forward ? 2 : 1) : 0];
         tl.grid = plan->num_btiles;
         tl.waves = 1;  // dataflow: a power of two, at most one wave per block
         while (tl.waves < 16 && tl.waves * 2 * 64 <= plan->bwd_cap) tl.waves *= 2;

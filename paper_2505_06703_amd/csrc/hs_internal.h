@@ -162,6 +162,7 @@ struct TileLaunch {
     // of one tile
     const int32_t *code;
     int32_t max_anchors;
+    int32_t blocks_per_wave;  // the two-level adjoint: 64-joint blocks per wave (1 or 2)
 };
 
 struct MPLaunch {
@@ -221,7 +222,11 @@ hipError_t launch_forward_tiles(const TileLaunch &tl, const PoseArgs &pose, cons
 hipError_t launch_forward_queue(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
                                 hipStream_t stream);
 size_t forward_queue_lds_bytes(int waves, int max_anchors, int tile_cap, bool sample, bool skin);
-size_t backward_anchor_lds_bytes(int waves, int max_anchors);
+size_t backward_anchor_lds_bytes(int waves, int max_anchors, int tile_cap);
+// Workgroups of the two-level adjoint (waves per workgroup, blocks per
+// wave, seed kind 0 dense / 1 effectors / 2 forward in the tile) that fit
+// one CU with `lds` bytes of LDS.
+hipError_t anchor_blocks_per_cu(int waves, int bpw, int seed, size_t lds, int *out);
 // Workgroups of the queue kernel (stored or sampled poses) that fit one CU
 // with `lds` bytes of LDS.
 hipError_t queue_blocks_per_cu(int waves, bool sample, size_t lds, int *out);

@@ -1817,19 +1817,43 @@ __device__ __forceinline__ void wave_reverse_scan(float S[12], const float L[12]
     }
 }
 
-template <int WAVES, int SEED>
-__global__ void __launch_bounds__(WAVES * kWave)
+// The stored TRS pose of joint gid (unit scale when the batch has none).
+__device__ __forceinline__ void load_trs(const PoseArgs &pose, int64_t gid, float4 &q, float t[3], float s[3])
+{
+    const native_float4 qn = reinterpret_cast<const native_float4 *>(pose.quat)[gid];
+    q = make_float4(qn.x, qn.y, qn.z, qn.w);
+    const float *tp = pose.trans + 3 * gid;
+    t[0] = tp[0];
+    t[1] = tp[1];
+    t[2] = tp[2];
+    s[0] = s[1] = s[2] = 1.0f;
+    if (pose.scale) {
+        const float *sp = pose.scale + 3 * gid;
+        s[0] = sp[0];
+        s[1] = sp[1];
+        s[2] = sp[2];
+    }
+}
+
+// A wave takes BPW of the tile's blocks (wave, wave + WAVES, ...): with
+// fewer, fuller waves a CU holds more tiles at once, so a batch of many
+// tiles runs in fewer rounds of resident workgroups.  The forward handles
+// the wave's blocks in increasing order and the anchor sends and reverse
+// sums in decreasing order; forward waits only point to lower blocks and
+// anchor waits only to higher ones, so the wave holding the lowest (resp.
+// highest) unfinished block can always proceed.
+template <int WAVES, int BPW, int SEED>
+__global__ void __launch_bounds__(WAVES * kWave, 4)  // at most 128 VGPRs: four waves per SIMD
 bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
 {
     extern __shared__ float4 lds[];
     if (gated(tl.gate)) return;
+    constexpr int T = WAVES * kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int na = tl.max_anchors;
-    float4 *stage_all = lds;                      // [WAVES][64][3]
-    float4 *seed_all = lds + WAVES * kWave * 3;   // [WAVES][64][3]
-    float4 *stage = stage_all + wave * kWave * 3;
-    float4 *seed = seed_all + wave * kWave * 3;
+    float4 *stage = lds + wave * kWave * 3;                    // [WAVES][64][3]: a block's G, then jump products
+    float4 *contrib = lds + (WAVES + wave) * kWave * 3;        // [WAVES][64][3]: the reverse scan's contributions
     float4 *AG = lds + WAVES * kWave * 6;
     float4 *AP = AG + 3 * na;
     float4 *AI = AP + 3 * na;
@@ -1839,176 +1863,230 @@ bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
     int *ax = recv + na + wave * kWave * 3;  // [WAVES][3][64]: jump targets, list heads, next
     int *head = ax + kWave;
     int *nxt = head + kWave;
+    int *effk = recv + na + WAVES * kWave * 3;  // [tile_cap]: each joint's effector entry, or -1
     const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 
     for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
         const TileDesc td = tl.tiles[tile];
         const int n = td.count;
-        for (int i = threadIdx.x; i < na; i += WAVES * kWave) {
+        for (int i = threadIdx.x; i < na; i += T) {
             aflag[i] = 0;
             expect[i] = 0;
             recv[i] = 0;
         }
-        for (int i = threadIdx.x; i < 3 * na; i += WAVES * kWave) AI[i] = zero4;
-#pragma unroll
-        for (int r = 0; r < 3; ++r) seed[3 * lane + r] = zero4;
+        for (int i = threadIdx.x; i < 3 * na; i += T) AI[i] = zero4;
+        if constexpr (SEED != kSeedDense) {
+            for (int i = threadIdx.x; i < n; i += T) effk[i] = -1;
+            __syncthreads();
+            const int e1 = bwd.eff_tile[2 * tile + 1];
+            for (int k = bwd.eff_tile[2 * tile] + (int)threadIdx.x; k < e1; k += T)
+                effk[(int)(bwd.eff_ids[k] - td.begin)] = k;
+        }
         __syncthreads();
 
-        // ---- the forward scan of the block (the queue kernel's scheme) ----
-        const int base = wave * kWave;
-        const int jl = base + lane;
-        const bool valid = jl < n;
-        const int64_t gid = td.begin + jl;
-        int a = -1, e = -1, own = -1, ps = -1;
-        float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-        float tx = 0.0f, ty = 0.0f, tz = 0.0f, sx = 1.0f, sy = 1.0f, sz = 1.0f;
-        float m[12];
-        if (valid) {
-            const int code = tl.code[gid];
-            const int ref = code & (kQInBlock - 1);
-            if (code & kQInBlock) a = ref; else e = ps = ref - 1;
-            own = (code >> kQOwnShift) - 1;
-            const native_float4 qn =
-                __builtin_nontemporal_load(reinterpret_cast<const native_float4 *>(pose.quat) + gid);
-            q = make_float4(qn.x, qn.y, qn.z, qn.w);
-            const float *t = pose.trans + 3 * gid;
-            tx = __builtin_nontemporal_load(t);
-            ty = __builtin_nontemporal_load(t + 1);
-            tz = __builtin_nontemporal_load(t + 2);
-            if (pose.scale) {
-                const float *sp = pose.scale + 3 * gid;
-                sx = __builtin_nontemporal_load(sp);
-                sy = __builtin_nontemporal_load(sp + 1);
-                sz = __builtin_nontemporal_load(sp + 2);
-            }
-            aff_from_trs(q, tx, ty, tz, sx, sy, sz, m);
-        } else {
-            aff_identity(m);
-        }
-        const int pa = a;  // in-block parent lane, for the reverse sums
-        wave_inblock_scan_lds(m, a, e, lane, stage, ax);
-        float P[12];  // the in-block product from the top of the joint's in-block path
-#pragma unroll
-        for (int k = 0; k < 12; ++k) P[k] = m[k];
-        if (own >= 0 && e >= 0) atomicAdd(expect + e, 1);  // k will send to its own anchor
-        wait_slot(aflag, valid ? e : -1, tl.status, tl.spin_limit);
-        if (valid && e >= 0) {
-            float g[12];
-            aff_load(AG + 3 * e, g);
-            aff_mul_left(g, m);
-        }
-        if (own >= 0) aff_store(AG + 3 * own, m);
-        aff_store(stage + 3 * lane, m);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        if (own >= 0) __hip_atomic_store(aflag + own, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if constexpr (SEED == kSeedForward) {
-            if (bwd.eff_global_out) {
-                wave_sync();
-                OutArgs out{};
-                out.global_out = bwd.eff_global_out;
-                store_rows<1>(out, stage, td.begin + base, 0, 1, n - base, lane);
-            }
-        }
-        __syncthreads();  // expected pushes counted; every block's G staged
+        // what each of the wave's blocks keeps from the forward for the
+        // reverse: codes, the parent's rotation-scale block, the seed
+        // (effector forms: its translation column); the reverse reads the
+        // pose again (from the caches: the tile's poses were read just before)
+        float Apb[BPW][9], Db[BPW][3];
+        int ownb[BPW], eb[BPW], pab[BPW];
 
-        // ---- seeds ----
-        if constexpr (SEED == kSeedDense) {
+        // ---- forward: the wave's blocks in increasing order (the queue
+        // kernel's scheme); non-anchor seeded joints send D (.) P to their
+        // anchor at once ----
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            const int base = (wave + b * WAVES) * kWave;
+            ownb[b] = eb[b] = pab[b] = -1;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) Db[b][k] = 0.0f;
+            if (base >= n) continue;  // uniform across the wave
+            const int jl = base + lane;
+            const bool valid = jl < n;
+            const int64_t gid = td.begin + jl;
+            int a = -1, e = -1, own = -1, ps = -1;
+            float m[12];
             if (valid) {
-                const float4 *gg = reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid;
-#pragma unroll
-                for (int r = 0; r < 3; ++r) seed[3 * lane + r] = gg[r];
+                const int code = tl.code[gid];
+                const int ref = code & (kQInBlock - 1);
+                if (code & kQInBlock) a = ref; else e = ps = ref - 1;
+                own = (code >> kQOwnShift) - 1;
+                float4 q;
+                float t[3], sc[3];
+                load_trs(pose, gid, q, t, sc);
+                aff_from_trs(q, t[0], t[1], t[2], sc[0], sc[1], sc[2], m);
+            } else {
+                aff_identity(m);
             }
-            wave_sync();
-        } else {
-            const int e1 = bwd.eff_tile[2 * tile + 1];
-            for (int k = bwd.eff_tile[2 * tile] + (int)threadIdx.x; k < e1; k += WAVES * kWave) {
-                const int64_t eg = bwd.eff_ids[k];
-                const int le = (int)(eg - td.begin);
-                const float *y = bwd.eff_target + 3 * (int64_t)bwd.eff_row[k];
-                float4 *dst = seed_all + 3 * le;  // [wave][lane] = tile-local id
+            pab[b] = a;  // in-block parent lane, for the reverse sums
+            wave_inblock_scan_lds(m, a, e, lane, stage, ax);
+            float P[12];  // the in-block product from the top of the joint's in-block path
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    float b;
-                    if constexpr (SEED == kSeedForward) b = stage_all[3 * le + r].w;
-                    else b = bwd.eff_global[16 * eg + 4 * r + 3];
-                    dst[r] = make_float4(0.0f, 0.0f, 0.0f, 2.0f * (b - y[r]));
+            for (int k = 0; k < 12; ++k) P[k] = m[k];
+            if (own >= 0 && e >= 0) atomicAdd(expect + e, 1);  // k will send to its own anchor
+            wait_slot(aflag, valid ? e : -1, tl.status, tl.spin_limit);
+            if (valid && e >= 0) {
+                float g[12];
+                aff_load(AG + 3 * e, g);
+                aff_mul_left(g, m);
+            }
+            if (own >= 0) {
+                aff_store(AG + 3 * own, m);
+                aff_store(AP + 3 * own, P);
+            }
+            aff_store(stage + 3 * lane, m);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (own >= 0) __hip_atomic_store(aflag + own, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            wave_sync();  // the block's G is staged
+            if constexpr (SEED == kSeedForward) {
+                if (bwd.eff_global_out) {
+                    OutArgs out{};
+                    out.global_out = bwd.eff_global_out;
+                    store_rows<1>(out, stage, td.begin + base, 0, 1, n - base, lane);
                 }
             }
-            __syncthreads();
-        }
-
-        // ---- seeds of joints that are not anchors go straight to their
-        // anchor: D_d (.) P_d (the sum over a head's in-block subtree of
-        // these is the head's in-block reverse sum pulled through its local
-        // transform) ----
-        {
+            // the parent's global rotation-scale block, for the gradients (an
+            // out-of-block parent is the anchor waited for above)
+            float *Ap = Apb[b];
+            Ap[0] = 1.0f; Ap[1] = 0.0f; Ap[2] = 0.0f;
+            Ap[3] = 0.0f; Ap[4] = 1.0f; Ap[5] = 0.0f;
+            Ap[6] = 0.0f; Ap[7] = 0.0f; Ap[8] = 1.0f;
+            if (valid && (pab[b] >= 0 || ps >= 0)) {
+                float g[12];
+                aff_load(pab[b] >= 0 ? stage + 3 * pab[b] : AG + 3 * ps, g);
+                Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
+                Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
+                Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
+            }
+            // the seed
             float D[12];
-            aff_load(seed + 3 * lane, D);
+            if constexpr (SEED == kSeedDense) {
+                if (valid) {
+                    const float4 *gg = reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid;
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const float4 v = gg[r];
+                        D[4 * r] = v.x;
+                        D[4 * r + 1] = v.y;
+                        D[4 * r + 2] = v.z;
+                        D[4 * r + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) D[k] = 0.0f;
+                }
+            } else {
+                const int k = valid ? effk[jl] : -1;
+                if (k >= 0) {
+                    const float *y = bwd.eff_target + 3 * (int64_t)bwd.eff_row[k];
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        float bt;
+                        if constexpr (SEED == kSeedForward) bt = m[4 * r + 3];
+                        else bt = bwd.eff_global[16 * gid + 4 * r + 3];
+                        Db[b][r] = 2.0f * (bt - y[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    D[4 * r] = D[4 * r + 1] = D[4 * r + 2] = 0.0f;
+                    D[4 * r + 3] = Db[b][r];
+                }
+            }
             if (own < 0 && e >= 0 && any_nonzero12(D)) {
                 float c[12];
                 adj_pull(D, P, c);
                 lds_atomic_add12(AI + 3 * e, c);
             }
-            if (own >= 0) aff_store(AP + 3 * own, P);
+            ownb[b] = own;
+            eb[b] = e;
         }
-        __syncthreads();  // every direct send is in
+        __syncthreads();  // every direct send is in, every expected send counted
 
-        // ---- anchors: once all its children anchors have sent, an anchor
-        // sends (D_k + I_k) (.) P_k to its own anchor ----
-        {
-            const bool need = own >= 0;
-            const int want = need ? expect[own] : 0;
-            bool done = !__any(need && want > 0);
-            for (int spin = 0; !done && spin < tl.spin_limit; ++spin) {
-                const int got =
-                    need ? __hip_atomic_load(recv + own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
-                done = __all(got >= want);
-                if (!done) __builtin_amdgcn_s_sleep(1);
-            }
-            if (!done) note_status(tl.status, kStatusWaitTimeout);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-            if (need && e >= 0) {
-                float I[12], D[12], Pk[12], c[12];
-                aff_load(AI + 3 * own, I);
-                aff_load(seed + 3 * lane, D);
-                aff_load(AP + 3 * own, Pk);
+        // ---- the wave's blocks in decreasing order: once all its children
+        // anchors have sent, an anchor sends (D_k + I_k) (.) P_k to its own
+        // anchor; then the block's in-block reverse sums over D + I and its
+        // gradients ----
 #pragma unroll
-                for (int k = 0; k < 12; ++k) I[k] += D[k];
-                adj_pull(I, Pk, c);
-                lds_atomic_add12(AI + 3 * e, c);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                atomicAdd(recv + e, 1);
-            }
-        }
-
-        // ---- in-block reverse sums over seeds + inflows: X ----
-        float L[12];
-        if (valid) aff_from_trs(q, tx, ty, tz, sx, sy, sz, L); else aff_identity(L);
-        float X[12];
-        aff_load(seed + 3 * lane, X);
-        if (own >= 0) {
-            float I[12];
-            aff_load(AI + 3 * own, I);  // final: this lane's own wait is over
+        for (int b = BPW - 1; b >= 0; --b) {
+            const int base = (wave + b * WAVES) * kWave;
+            if (base >= n) continue;  // uniform across the wave
+            const int jl = base + lane;
+            const bool valid = jl < n;
+            const int64_t gid = td.begin + jl;
+            const int own = ownb[b], e = eb[b];
+            // the pose again, issued before the wait for the anchor inflows
+            float4 q = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+            float t[3] = {0.0f, 0.0f, 0.0f}, sc[3] = {1.0f, 1.0f, 1.0f};
+            if (valid) load_trs(pose, gid, q, t, sc);
+            float X[12];
+            if constexpr (SEED == kSeedDense) {
+                if (valid) {
+                    const float4 *gg = reinterpret_cast<const float4 *>(bwd.grad_global) + 4 * gid;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) X[k] += I[k];
+                    for (int r = 0; r < 3; ++r) {
+                        const float4 v = gg[r];
+                        X[4 * r] = v.x;
+                        X[4 * r + 1] = v.y;
+                        X[4 * r + 2] = v.z;
+                        X[4 * r + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) X[k] = 0.0f;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    X[4 * r] = X[4 * r + 1] = X[4 * r + 2] = 0.0f;
+                    X[4 * r + 3] = Db[b][r];
+                }
+            }
+            {
+                const bool need = own >= 0;
+                const int want = need ? expect[own] : 0;
+                bool done = !__any(need && want > 0);
+                for (int spin = 0; !done && spin < tl.spin_limit; ++spin) {
+                    const int got =
+                        need ? __hip_atomic_load(recv + own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : 0;
+                    done = __all(got >= want);
+                    if (!done) __builtin_amdgcn_s_sleep(1);
+                }
+                if (!done) note_status(tl.status, kStatusWaitTimeout);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (need) {
+                    float I[12];
+                    aff_load(AI + 3 * own, I);  // complete: every sender has arrived
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) X[k] += I[k];
+                    if (e >= 0) {
+                        float Pk[12], c[12];
+                        aff_load(AP + 3 * own, Pk);
+                        adj_pull(X, Pk, c);
+                        lds_atomic_add12(AI + 3 * e, c);
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                        atomicAdd(recv + e, 1);
+                    }
+                }
+            }
+            // X = D + I; the in-block reverse sums over it (the stage and
+            // contribution slices carry the scan's jump products and sends)
+            float L[12];
+            if (valid) aff_from_trs(q, t[0], t[1], t[2], sc[0], sc[1], sc[2], L);
+            else aff_identity(L);
+            if (__any(any_nonzero12(X))) wave_reverse_scan(X, L, pab[b], lane, contrib, stage, ax, head, nxt);
+            if (valid) write_grads(bwd, gid, X, Apb[b], q, sc[0], sc[1], sc[2]);
         }
-        // the parent's global rotation-scale block, for the gradients
-        float Ap[9] = {1.0f, 0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f, 0.0f, 1.0f};
-        if (valid && (pa >= 0 || ps >= 0)) {
-            float g[12];
-            aff_load(pa >= 0 ? stage + 3 * pa : AG + 3 * ps, g);
-            Ap[0] = g[0]; Ap[1] = g[1]; Ap[2] = g[2];
-            Ap[3] = g[4]; Ap[4] = g[5]; Ap[5] = g[6];
-            Ap[6] = g[8]; Ap[7] = g[9]; Ap[8] = g[10];
-        }
-        // the stage and seed slices are free now: they carry the scan's jump
-        // products and contributions
-        if (__any(any_nonzero12(X))) wave_reverse_scan(X, L, pa, lane, seed, stage, ax, head, nxt);
-
-        // ---- gradients ----
-        if (valid) write_grads(bwd, gid, X, Ap, q, sx, sy, sz);
         __syncthreads();  // LDS is reused by the next tile
     }
+}
+
+template <int W, int BPW>
+const void *anchor_kernel_of(int seed)
+{
+    if (seed == kSeedForward) return reinterpret_cast<const void *>(bwd_anchor_kernel<W, BPW, kSeedForward>);
+    if (seed == kSeedEffectors) return reinterpret_cast<const void *>(bwd_anchor_kernel<W, BPW, kSeedEffectors>);
+    return reinterpret_cast<const void *>(bwd_anchor_kernel<W, BPW, kSeedDense>);
 }
 
 // ---------------------------------------------------------------------------
@@ -3248,11 +3326,16 @@ hipError_t set_lds_limits()
         if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
         if ((err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
             return err;
-        const void *ak[3] = {reinterpret_cast<const void *>(bwd_anchor_kernel<WAVES, kSeedDense>),
-                             reinterpret_cast<const void *>(bwd_anchor_kernel<WAVES, kSeedEffectors>),
-                             reinterpret_cast<const void *>(bwd_anchor_kernel<WAVES, kSeedForward>)};
-        for (const void *k : ak)
-            if (err == hipSuccess) err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        for (int seed = 0; seed < 3; ++seed) {
+            if (err == hipSuccess)
+                err = hipFuncSetAttribute(anchor_kernel_of<WAVES, 1>(seed), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          lds_max);
+            if constexpr (WAVES <= 8) {
+                if (err == hipSuccess)
+                    err = hipFuncSetAttribute(anchor_kernel_of<WAVES, 2>(seed),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+            }
+        }
     }
     if (err != hipSuccess || WAVES != 16) return err;
     const void *pk[4] = {reinterpret_cast<const void *>(paper_alg_kernel<1>),
@@ -3693,9 +3776,9 @@ hipError_t launch_vertex_skin(const VertexLaunch &vl, int method, const float *s
     return hipGetLastError();
 }
 
-size_t backward_anchor_lds_bytes(int waves, int max_anchors)
+size_t backward_anchor_lds_bytes(int waves, int max_anchors, int tile_cap)
 {
-    return (size_t)waves * kWave * (2 * 48 + 3 * 4) + (size_t)max_anchors * (3 * 48 + 12);
+    return (size_t)waves * kWave * (2 * 48 + 3 * 4) + (size_t)max_anchors * (3 * 48 + 12) + (size_t)tile_cap * 4;
 }
 
 size_t backward_sync_lds_bytes(int tile_cap)
@@ -3732,19 +3815,61 @@ hipError_t launch_bwd_tiles_w(const TileLaunch &tl, const PoseArgs &pose, const 
     }
 }
 
+// The two-level adjoint with W waves of BPW blocks each (W * BPW blocks
+// cover the tile).
+template <int W, int BPW>
+hipError_t launch_bwd_anchor_t(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd, hipStream_t stream)
+{
+    if (tl.tile_cap > W * BPW * kWave || !tl.code) return hipErrorInvalidValue;
+    const size_t lds = backward_anchor_lds_bytes(W, tl.max_anchors, tl.tile_cap);
+    const dim3 grid(tl.grid), blk(W * kWave);
+    if (bwd.eff_ids && bwd.eff_forward)
+        hipLaunchKernelGGL((bwd_anchor_kernel<W, BPW, kSeedForward>), grid, blk, lds, stream, tl, pose, bwd);
+    else if (bwd.eff_ids)
+        hipLaunchKernelGGL((bwd_anchor_kernel<W, BPW, kSeedEffectors>), grid, blk, lds, stream, tl, pose, bwd);
+    else
+        hipLaunchKernelGGL((bwd_anchor_kernel<W, BPW, kSeedDense>), grid, blk, lds, stream, tl, pose, bwd);
+    return hipGetLastError();
+}
+
+// WAVES: the tile's blocks (a power of two); tl.blocks_per_wave 2 halves
+// the waves.
 template <int WAVES>
 hipError_t launch_bwd_anchor_w(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd, hipStream_t stream)
 {
-    if (tl.tile_cap > WAVES * kWave || !tl.code) return hipErrorInvalidValue;
-    const size_t lds = backward_anchor_lds_bytes(WAVES, tl.max_anchors);
-    const dim3 grid(tl.grid), blk(WAVES * kWave);
-    if (bwd.eff_ids && bwd.eff_forward)
-        hipLaunchKernelGGL((bwd_anchor_kernel<WAVES, kSeedForward>), grid, blk, lds, stream, tl, pose, bwd);
-    else if (bwd.eff_ids)
-        hipLaunchKernelGGL((bwd_anchor_kernel<WAVES, kSeedEffectors>), grid, blk, lds, stream, tl, pose, bwd);
-    else
-        hipLaunchKernelGGL((bwd_anchor_kernel<WAVES, kSeedDense>), grid, blk, lds, stream, tl, pose, bwd);
-    return hipGetLastError();
+    if constexpr (WAVES >= 2) {
+        if (tl.blocks_per_wave == 2) return launch_bwd_anchor_t<WAVES / 2, 2>(tl, pose, bwd, stream);
+    }
+    return launch_bwd_anchor_t<WAVES, 1>(tl, pose, bwd, stream);
+}
+
+
+template <int W, int BPW>
+hipError_t anchor_occupancy_t(int seed, size_t lds, int *out)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, anchor_kernel_of<W, BPW>(seed), W * kWave, lds);
+}
+
+hipError_t anchor_blocks_per_cu(int waves, int bpw, int seed, size_t lds, int *out)
+{
+    *out = 0;
+    if (bpw == 2) {
+        switch (waves) {
+        case 1: return anchor_occupancy_t<1, 2>(seed, lds, out);
+        case 2: return anchor_occupancy_t<2, 2>(seed, lds, out);
+        case 4: return anchor_occupancy_t<4, 2>(seed, lds, out);
+        case 8: return anchor_occupancy_t<8, 2>(seed, lds, out);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (waves) {
+    case 1: return anchor_occupancy_t<1, 1>(seed, lds, out);
+    case 2: return anchor_occupancy_t<2, 1>(seed, lds, out);
+    case 4: return anchor_occupancy_t<4, 1>(seed, lds, out);
+    case 8: return anchor_occupancy_t<8, 1>(seed, lds, out);
+    case 16: return anchor_occupancy_t<16, 1>(seed, lds, out);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int WAVES>

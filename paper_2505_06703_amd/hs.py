@@ -78,7 +78,7 @@ class hs_plan_opts(ctypes.Structure):
                 ("waves_per_tile", ctypes.c_int32), ("grid_tiles", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("chain_units", ctypes.c_int32),
                 ("algorithm", ctypes.c_int32), ("adjoint", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("adjoint_blocks_per_wave", ctypes.c_int32)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -88,7 +88,8 @@ class hs_plan_info(ctypes.Structure):
                 ("num_tiles", ctypes.c_int32), ("tile_joints", ctypes.c_int32),
                 ("waves_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("multipass_rounds", ctypes.c_int32), ("max_block_chain", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("max_anchors", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("max_anchors", ctypes.c_int32),
+                ("adjoint_blocks_per_wave", ctypes.c_int32)]
 
 
 class hs_clip_lib(ctypes.Structure):
@@ -256,7 +257,8 @@ class Plan:
 
     def __init__(self, offsets, parents, ctx=None, strategy=HS_STRATEGY_AUTO, tile_joints=0,
                  waves_per_tile=0, grid_tiles=0, autotune=False, chain_units=False, algorithm=HS_ALG_SCAN,
-                 adjoint=HS_ADJ_AUTO, schedule=HS_SCHED_AUTO, skeletons=None):
+                 adjoint=HS_ADJ_AUTO, schedule=HS_SCHED_AUTO, adjoint_blocks_per_wave=0,
+                 skeletons=None):
         self.ctx = ctx or default_context()
         off = np.ascontiguousarray(np.asarray(offsets.cpu() if isinstance(offsets, torch.Tensor) else offsets,
                                               dtype=np.int64))
@@ -268,7 +270,8 @@ class Plan:
         self.num_joints = par.size
         batch = hs_batch(self.num_characters, self.num_joints, off.ctypes.data, par.ctypes.data)
         opts = hs_plan_opts(strategy, tile_joints, waves_per_tile, grid_tiles, int(bool(autotune)),
-                            int(bool(chain_units)), int(algorithm), int(adjoint), int(schedule))
+                            int(bool(chain_units)), int(algorithm), int(adjoint), int(schedule),
+                            int(adjoint_blocks_per_wave))
         h = ctypes.c_void_p()
         if skeletons is None:
             _check(load_library().hs_plan_create(self.ctx.handle, ctypes.byref(batch), ctypes.byref(opts),

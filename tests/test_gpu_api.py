@@ -85,6 +85,12 @@ def test_unknown_adjoint_kernel_is_rejected():
     with pytest.raises(hs.HSError) as ei:
         hs.Plan(b.offsets, b.parents, adjoint=4)  # 0-3 are the kernels of HS_ADJ_*
     assert ei.value.status == hs.HS_ERR_INVALID_ARG
+    with pytest.raises(hs.HSError) as ei:
+        hs.Plan(b.offsets, b.parents, adjoint=hs.HS_ADJ_ANCHORS, adjoint_blocks_per_wave=3)
+    assert ei.value.status == hs.HS_ERR_INVALID_ARG
+    for bpw in (1, 2):  # asked for: reported
+        p = hs.Plan(b.offsets, b.parents, adjoint=hs.HS_ADJ_ANCHORS, adjoint_blocks_per_wave=bpw)
+        assert p.info["adjoint_blocks_per_wave"] == bpw
 
 
 def test_backward_and_sampler_argument_errors():

@@ -64,7 +64,11 @@ def oracle_grads(batch, W):
     return oracle.backward(batch.offsets, batch.parents, batch.quat, batch.trans, batch.scale, W)
 
 
-ADJ = [hs.HS_ADJ_ROUNDS, hs.HS_ADJ_DATAFLOW, hs.HS_ADJ_ANCHORS]
+# the adjoint kernels; the two-level one with one and with two 64-joint
+# blocks per wave
+ADJ = [dict(adjoint=hs.HS_ADJ_ROUNDS), dict(adjoint=hs.HS_ADJ_DATAFLOW),
+       dict(adjoint=hs.HS_ADJ_ANCHORS, adjoint_blocks_per_wave=1),
+       dict(adjoint=hs.HS_ADJ_ANCHORS, adjoint_blocks_per_wave=2)]
 
 
 @pytest.mark.parametrize("adj", ADJ)
@@ -73,7 +77,7 @@ def test_differentiable_effector_loss(shape, adj):
     b = wl.differentiable(num_characters=12)
     G = oracle.forward(b.offsets, b.parents, b.quat, b.trans, b.scale)
     W = effector_grad(b, G)
-    check_grads(b.offsets, run(b, W, adjoint=adj, **shape), oracle_grads(b, W), f"differentiable {shape} adj {adj}")
+    check_grads(b.offsets, run(b, W, **adj, **shape), oracle_grads(b, W), f"differentiable {shape} adj {adj}")
 
 
 @pytest.mark.parametrize("k", [1, 3, 8])
@@ -90,8 +94,8 @@ def test_dense_random_gradient_with_scale_and_forests(adj):
     b = wl.heterogeneous(num_characters=40, hi=1500, chain_fraction=0.05)
     b.scale = rng.uniform(0.8, 1.25, b.scale.shape).astype(np.float32)
     W = rng.standard_normal((b.num_joints, 4, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), "dense random")
-    check_grads(b.offsets, run(b, W, ckpt_k=5, adjoint=adj), oracle_grads(b, W), "dense random ckpt")
+    check_grads(b.offsets, run(b, W, **adj), oracle_grads(b, W), "dense random")
+    check_grads(b.offsets, run(b, W, ckpt_k=5, **adj), oracle_grads(b, W), "dense random ckpt")
 
 
 @pytest.mark.parametrize("adj", ADJ)
@@ -105,8 +109,8 @@ def test_plain_scan_trees_and_star(adj):
     q, t, s = wl.random_pose(rng, par.size)
     b = wl.Batch("mix", off.astype(np.int64), par, q, t, s, q, t, s)
     W = rng.standard_normal((par.size, 4, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), "trees+star")
-    got = run(b, W, want_scale=False, adjoint=adj)
+    check_grads(b.offsets, run(b, W, **adj), oracle_grads(b, W), "trees+star")
+    got = run(b, W, want_scale=False, **adj)
     assert got[2] is None
 
 
@@ -123,8 +127,8 @@ def test_chains(n, adj):
     W[-1, :3, 3] = rng.standard_normal(3)
     W[n // 2, :3, :3] = rng.standard_normal((3, 3))
     ref = oracle_grads(b, W)
-    check_grads(b.offsets, run(b, W, adjoint=adj), ref, f"chain {n}")
-    check_grads(b.offsets, run(b, W, ckpt_k=4, adjoint=adj), ref, f"chain {n} ckpt 4")
+    check_grads(b.offsets, run(b, W, **adj), ref, f"chain {n}")
+    check_grads(b.offsets, run(b, W, ckpt_k=4, **adj), ref, f"chain {n} ckpt 4")
 
 
 @pytest.mark.parametrize("adj", ADJ)
@@ -144,7 +148,7 @@ def test_stars_and_brooms_collide_on_one_target(n, adj):
     q, t, s = wl.random_pose(rng, par.size, max_angle=0.2)
     b = wl.Batch("star", off, par, q, t, s, q, t, s)
     W = rng.standard_normal((par.size, 4, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), f"star/broom {n}")
+    check_grads(b.offsets, run(b, W, **adj), oracle_grads(b, W), f"star/broom {n}")
 
 
 def test_large_forward_tiles_use_smaller_adjoint_tiles():
@@ -267,7 +271,7 @@ def test_more_tiles_than_resident_workgroups(adj):
     W = effector_grad(b, G)
     rng = np.random.default_rng(13)
     W[:, :3, :] += 0.01 * rng.standard_normal((b.num_joints, 3, 4)).astype(np.float32)
-    check_grads(b.offsets, run(b, W, adjoint=adj), oracle_grads(b, W), f"1300 characters adj {adj}")
+    check_grads(b.offsets, run(b, W, **adj), oracle_grads(b, W), f"1300 characters adj {adj}")
 
 
 def test_effector_loss_gradient_kernel():

@@ -109,6 +109,7 @@ def test_differentiable_step_autotuned():
     oracle's forward and reverse mode of the same loss."""
     b = wl.differentiable()
     plan = hs.Plan(b.offsets, b.parents, autotune=True)
+    assert plan.info["adjoint_blocks_per_wave"] in (1, 2)
     eff = b.extra["effectors"]
     Grest = oracle.forward(b.offsets, b.parents, b.rest_quat, b.rest_trans, b.rest_scale)
     y = (Grest[eff, :3, 3] + b.extra["target_offsets"]).astype(np.float32)

@@ -74,7 +74,11 @@ def targets(b, eff, rng, radius=0.5):
     return (Grest[eff, :3, 3] + wl.ball_offsets(rng, len(eff), radius)).astype(np.float32)
 
 
-ADJ = [hs.HS_ADJ_ROUNDS, hs.HS_ADJ_ANCHORS]
+# the adjoint kernels; the two-level one with one and with two 64-joint
+# blocks per wave
+ADJ = [dict(adjoint=hs.HS_ADJ_ROUNDS),
+       dict(adjoint=hs.HS_ADJ_ANCHORS, adjoint_blocks_per_wave=1),
+       dict(adjoint=hs.HS_ADJ_ANCHORS, adjoint_blocks_per_wave=2)]
 
 
 @pytest.mark.parametrize("adj", ADJ)
@@ -83,7 +87,7 @@ def test_effector_loss_matches_oracle(shape, adj):
     b = wl.differentiable(num_characters=12)
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(20))
-    G, got, _ = run(b, eff, y, expect_sparse=True, adjoint=adj, **shape)
+    G, got, _ = run(b, eff, y, expect_sparse=True, **adj, **shape)
     check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector adjoint {shape}")
 
 
@@ -102,7 +106,7 @@ def test_ids_in_any_order_with_their_targets(adj):
     eff = np.array(sorted(eff), np.int64)
     rng.shuffle(eff)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
-    G, got, _ = run(b, eff, y, expect_sparse=True, adjoint=adj)
+    G, got, _ = run(b, eff, y, expect_sparse=True, **adj)
     check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"unsorted ids adj {adj}")
 
 
@@ -255,7 +259,7 @@ def test_fused_step_matches_oracle(shape, adj):
     b = wl.differentiable(num_characters=12)
     eff = b.extra["effectors"]
     y = targets(b, eff, np.random.default_rng(30))
-    G, got = run_step(b, eff, y, adjoint=adj, **shape)
+    G, got = run_step(b, eff, y, **adj, **shape)
     check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector step {shape}")
 
 
@@ -271,7 +275,7 @@ def test_fused_step_mixed_small_characters_and_unsorted_ids(adj):
     eff = np.array(sorted(eff), np.int64)
     rng.shuffle(eff)
     y = rng.standard_normal((eff.size, 3)).astype(np.float32)
-    G, got = run_step(b, eff, y, adjoint=adj)
+    G, got = run_step(b, eff, y, **adj)
     check(b.offsets, got, oracle_grads(b, seed(b, eff, y)), f"effector step, mixed characters adj {adj}")
 
 
