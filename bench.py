@@ -17,7 +17,8 @@ Default run: the batched form and the differentiable form in one JSON line.
   the adjoint rebuilds G from them), each with its time, roofline and
   error against FP64.
 
-The steps are issued either as direct calls or as replays of a HIP graph
+The steps are issued either as direct library calls (each marshalled once,
+before the timed region, with hs.prepare) or as replays of a HIP graph
 that holds eight such passes (one light host call per eight steps),
 whichever runs faster on the box (both are timed on a few steps after the
 warmup; the line reports both).  The steps cycle through as many
@@ -126,7 +127,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="heterogeneous", choices=WORKLOADS)
     ap.add_argument("--no-fwd-bwd", action="store_true",
-                    help="heterogeneous workload: leave out the differentiable form (fwd_bwd)")
+                    help="heterogeneous workload: leave out the differentiable form (fwd_bwd; always left out "
+                         "with --calibrate-copy)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the plan's default launch shape instead of timing candidates at plan time")
@@ -347,6 +349,9 @@ class Workload:
             with torch.cuda.graph(self.ckpt_graph):
                 for k in range(self.chunk):
                     self.ckpt_step(self.sets[k % S])
+        # plain mode: each set's step as one prepared library call (the
+        # binding's checks and argument marshalling done once, here)
+        self.plain_calls = [self.prepare_plain(st) for st in self.sets]
 
     def close(self):
         """Release the graphs, the effector set, the plan and the buffers."""
@@ -388,19 +393,24 @@ class Workload:
             self.graphs[k % S].launch()
 
     def plain_step(self, k):
-        """One step on set k (cycled) as direct library calls."""
-        s = self.sets[k % len(self.sets)]
+        """One step on set k (cycled) as a direct library call."""
+        self.plain_calls[k % len(self.sets)]()
+
+    def prepare_plain(self, s):
+        """The library call of one step on set s, marshalled once."""
         hs = self.hs
         if self.graphs is None:
-            self.diff_step(s)
+            call, _ = hs.prepare(hs.hs_effector_step, self.plan, self.effset, s["q"], s["t"], s["s"], self.target,
+                                 global_out=s["G"], want_scale=False, grad_quat=s["gq"], grad_trans=s["gt"])
         elif self.name in FUSED:
-            hs.hs_scan_forward(self.plan, clips=self.clips, **self.cp, want_global=False, inv_bind=s["inv"],
-                               skin_out=s["S"])
+            call, _ = hs.prepare(hs.hs_scan_forward, self.plan, clips=self.clips, **self.cp, want_global=False,
+                                 inv_bind=s["inv"], skin_out=s["S"])
         elif self.name == "plain_scan":
-            hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], want_global=False, inv_bind=s["inv"],
-                               skin_out=s["S"])
+            call, _ = hs.prepare(hs.hs_scan_forward, self.plan, s["q"], s["t"], s["s"], want_global=False,
+                                 inv_bind=s["inv"], skin_out=s["S"])
         else:
-            hs.hs_scan_forward(self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+            call, _ = hs.prepare(hs.hs_scan_forward, self.plan, s["q"], s["t"], s["s"], global_out=s["G"])
+        return call
 
     def mode_ms(self, mode, steps):
         """Mean time per step of `steps` steps in the given launch mode."""
@@ -486,18 +496,6 @@ class Workload:
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / (reps * self.chunk)
 
-    def backward_ms(self, reps=50):
-        """Mean duration of the step's one launch, back to back."""
-        torch, s = self.torch, self.sets[0]
-        self.diff_step(s)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            self.diff_step(s)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
-
     def forward_ms(self, reps=50):
         """Mean duration of the forward launch alone, back to back (the
         two-call route's first launch)."""
@@ -550,15 +548,14 @@ def measure(args, name):
                             else "fwd_tile_kernel")
     if diff and args.adjoint in ("rounds", "dataflow"):
         dominant = "bwd_sync_kernel"  # the effector step's kernel under these options
+    # one launch per step (the forward's work queue or classes launched back
+    # to back; the differentiable step's one kernel): HIP events around the
+    # timed region give the step's mean kernel time, on the cycled sets
+    kernel_ms = region[0].elapsed_time(region[1]) / args.steps
     if diff:
-        # the adjoint and the forward timed on their own, back to back
-        kernel_ms = w.backward_ms()
+        # the forward launch alone, back to back on one set (the two-call
+        # route's first launch), for the split of the step
         fwd_ms = w.forward_ms()
-    else:
-        # forward-only step = one kernel per size class, launched back to
-        # back: HIP events around the timed region give the step's mean
-        # kernel time
-        kernel_ms = region[0].elapsed_time(region[1]) / args.steps
     bytes_per_launch = N * BYTES_PER_JOINT[name]
     if diff:
         bytes_per_launch += 12 * w.effset.num_effectors
@@ -593,7 +590,8 @@ def measure(args, name):
                    "autotuned": not args.no_autotune and not fixed_shape(args) and name != "fused_sample",
                    "hip_graph": mode == "graph",
                    "input_sets": len(w.sets),
-                   **({"adjoint": args.adjoint} if diff else {})},
+                   **({"adjoint": args.adjoint,
+                       "adjoint_blocks_per_wave": info["adjoint_blocks_per_wave"]} if diff else {})},
         "roofline": roof,
         "launch_modes": launch,
     }
@@ -683,7 +681,9 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic"}
     out.update(rec)
-    if args.workload == "heterogeneous" and not args.no_fwd_bwd:
+    # a counter run (--calibrate-copy) covers the named workload's kernel
+    # only: the differentiable form launches the same forward kernel
+    if args.workload == "heterogeneous" and not args.no_fwd_bwd and not args.calibrate_copy:
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         out["fwd_bwd"] = measure(args, "differentiable")

@@ -117,8 +117,11 @@ def library_path():
 
 
 def load_library():
-    """Load ``libhs.so``; raises if it has not been built."""
+    """Load ``libhs.so``; raises if it has not been built.  (Inside
+    ``prepare`` the binding's calls are recorded instead of issued.)"""
     global _lib
+    if _recorder is not None:
+        return _recorder
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB):
@@ -183,6 +186,65 @@ def load_library():
 def _check(status):
     if status != HS_OK:
         raise HSError(status, load_library().hs_last_error().decode())
+
+
+_recorder = None
+
+
+class _Recorder:
+    """Stands in for the library inside ``prepare``: keeps each C call and
+    its marshalled arguments and reports success."""
+
+    def __init__(self, lib):
+        self.lib = lib
+        self.calls = []
+
+    def __getattr__(self, name):
+        fn = getattr(self.lib, name)
+
+        def record(*args):
+            self.calls.append((fn, args))
+            return HS_OK
+        return record
+
+
+class PreparedCall:
+    """One library call with its arguments marshalled once: calling the
+    object issues the same C call again (the same buffers, the same stream)
+    and raises HSError if it fails.  For loops that repeat a call on fixed
+    buffers, where the binding's per-call checks cost more host time than
+    the call itself."""
+
+    def __init__(self, fn, args, keep):
+        self._fn = fn
+        self._args = args
+        self._keep = keep  # the tensors and structures the arguments point into
+
+    def __call__(self):
+        status = self._fn(*self._args)
+        if status != HS_OK:
+            _check(status)
+
+
+def prepare(binding, *args, **kwargs):
+    """Check and marshal one call of a binding function (``hs_scan_forward``,
+    ``hs_effector_step``, ...) without issuing it.  Returns ``(call, result)``:
+    ``call()`` issues the C call with exactly these arguments, ``result`` is
+    what the binding function returns (the output tensors it was given or
+    allocated).  The stream is the one current now unless ``stream`` is
+    given.  Not thread-safe: no other thread may call the binding meanwhile."""
+    global _recorder
+    lib = load_library()
+    rec = _Recorder(lib)
+    _recorder = rec
+    try:
+        result = binding(*args, **kwargs)
+    finally:
+        _recorder = None
+    if len(rec.calls) != 1:
+        raise ValueError(f"{getattr(binding, '__name__', binding)} makes {len(rec.calls)} library calls, not one")
+    fn, cargs = rec.calls[0]
+    return PreparedCall(fn, cargs, (args, kwargs, result)), result
 
 
 def hs_version():

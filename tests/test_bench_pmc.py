@@ -50,14 +50,15 @@ def test_calibration_copy_and_scales(tmp_path, monkeypatch):
 
 def test_only_the_dominant_instance_is_averaged(tmp_path, monkeypatch):
     copy = "__amd_rocclr_copyBuffer"
-    # the step's instance (seeds from the tile's own forward) next to the
-    # comparison routes' kernels and other instances of the same template
-    fetch = [(2, copy, 128.0 * MIB), (4, "void hs::bwd_anchor_kernel<8, 2>(hs::TileLaunch)", 13.0 * MIB),
+    # the step's instance (seeds from the tile's own forward; waves, blocks
+    # per wave, seed kind) next to the comparison routes' kernels and other
+    # instances of the same template
+    fetch = [(2, copy, 128.0 * MIB), (4, "void hs::bwd_anchor_kernel<4, 2, 2>(hs::TileLaunch)", 13.0 * MIB),
              (5, "void hs::bwd_sync_kernel<8, 0>(hs::TileLaunch)", 28.0 * MIB),
-             (6, "void hs::bwd_anchor_kernel<8, 1>(hs::TileLaunch)", 20.0 * MIB),
+             (6, "void hs::bwd_anchor_kernel<4, 2, 1>(hs::TileLaunch)", 20.0 * MIB),
              (8, "void hs::bwd_sync_kernel<8, 2>(hs::TileLaunch)", 11.0 * MIB),
-             (7, "void hs::bwd_anchor_kernel<8, 2>(hs::TileLaunch)", 13.0 * MIB)]
-    write = [(2, copy, 256.0 * MIB), (4, "void hs::bwd_anchor_kernel<8, 2>(hs::TileLaunch)", 14.0 * MIB),
+             (7, "void hs::bwd_anchor_kernel<4, 2, 2>(hs::TileLaunch)", 13.0 * MIB)]
+    write = [(2, copy, 256.0 * MIB), (4, "void hs::bwd_anchor_kernel<4, 2, 2>(hs::TileLaunch)", 14.0 * MIB),
              (5, "void hs::bwd_sync_kernel<8, 0>(hs::TileLaunch)", 50.0 * MIB)]
     rec = run(tmp_path, monkeypatch, "differentiable", fetch, write)
     assert rec["fetch_bytes_per_launch"] == 13.0 * MIB * 1024.0 * 2.0

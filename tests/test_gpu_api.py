@@ -212,3 +212,38 @@ def test_stream_probe_moves_the_forward_bytes_verbatim():
     rc = hs.load_library().hs_stream_probe(n, qd.data_ptr(), dev(t).data_ptr(), dev(s).data_ptr(),
                                            dev(tab).data_ptr(), qd.data_ptr(), None)
     assert rc == hs.HS_ERR_INVALID_ARG
+
+
+def test_prepared_calls_repeat_the_direct_call():
+    """hs.prepare marshals a binding call once; each call() of the result
+    issues the same C call: outputs equal the direct call's, and the inputs
+    are read at call time (changed in place between calls)."""
+    b = wl.differentiable(num_characters=4)
+    plan = hs.Plan(b.offsets, b.parents)
+    N = b.num_joints
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    G = torch.full((N, 4, 4), float("nan"), device=DEV)
+    call, (Gout, Sout) = hs.prepare(hs.hs_scan_forward, plan, q, t, s, global_out=G)
+    assert Gout is G and Sout is None
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(G).all())  # preparing issues nothing
+    rng = np.random.default_rng(5)
+    for it in range(3):
+        call()
+        ref, _ = hs.hs_scan_forward(plan, q, t, s)
+        torch.cuda.synchronize()
+        assert torch.equal(G, ref), f"forward call {it}"
+        q.copy_(dev(wl.random_quats(rng, N, 0.3)))
+    eff = b.extra["effectors"]
+    E = hs.Effectors(plan, eff)
+    y = dev(rng.standard_normal((eff.size, 3)).astype(np.float32))
+    gq, gt = torch.empty((N, 4), device=DEV), torch.empty((N, 3), device=DEV)
+    step, _ = hs.prepare(hs.hs_effector_step, plan, E, q, t, s, y, global_out=G, want_scale=False,
+                         grad_quat=gq, grad_trans=gt)
+    step()
+    rq, rt, _ = hs.hs_effector_step(plan, E, q, t, s, y, want_scale=False)
+    torch.cuda.synchronize()
+    # anchors sum their inflows in arrival order: equal up to rounding
+    assert torch.allclose(gq, rq, rtol=1e-5, atol=1e-6) and torch.allclose(gt, rt, rtol=1e-5, atol=1e-6)
+    with pytest.raises(ValueError):  # the binding's checks run when preparing
+        hs.prepare(hs.hs_scan_forward, plan, q[:-1], t, s)

@@ -116,9 +116,42 @@ def test_chain_of_100k_joints_multipass_stress():
     n = 100_000
     b = _single(np.arange(-1, n - 1), seed=5, angle=0.02)
     plan, G, _ = run_forward(b)
+    # 1562 anchors (the last joints of all 64-joint blocks but the final
+    # one) in one chain: ceil(log2 1562) = 11 anchor rounds
     assert plan.info["multipass_joints"] == n and plan.info["multipass_rounds"] == 11
     Gr, lam, _ = reference(b)
     check_global(G, Gr, lam, "chain 1e5", scale=depth_scale(n))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_multipass_long_runs_with_branches(seed):
+    """Characters beyond a tile made of long runs where each parent is the
+    previous joint, broken by joints hanging off earlier joints (anchors
+    inside blocks, anchors of anchors in earlier blocks), with lengths just
+    past the tile and around block boundaries; the fused skin on one."""
+    rng = np.random.default_rng(40 + seed)
+    parts = []
+    for n in (2049, 2304, 2305, 3000 + int(rng.integers(0, 200)), 4999):
+        p = np.arange(-1, n - 1, dtype=np.int32)
+        for j in range(1, n):
+            r = rng.uniform()
+            if r < 0.02:
+                p[j] = rng.integers(0, j)  # a branch off any earlier joint
+            elif r < 0.025:
+                p[j] = max(0, j - 2)  # a short fork
+        parts.append(p)
+    off = np.concatenate([[0], np.cumsum([p.size for p in parts])]).astype(np.int64)
+    par = np.concatenate(parts)
+    q, t, s = wl.random_pose(rng, par.size, max_angle=0.1)
+    s = rng.uniform(0.9, 1.1, s.shape).astype(np.float32)
+    b = wl.Batch("units", off, par, q, t, s, q, t, s)
+    inv = inverse_binds(b) if seed == 1 else None  # the fused skin epilogue too
+    plan, G, S = run_forward(b, inv, tile_joints=2048)
+    assert plan.info["multipass_joints"] == par.size
+    Gr, lam, _ = reference(b)
+    check_global(G, Gr, lam, f"multipass runs with branches seed {seed}")
+    if inv is not None:
+        check_skin(S, Gr, inv, lam, "multipass runs with branches skin")
 
 
 def test_star_forest_and_empty_characters():
