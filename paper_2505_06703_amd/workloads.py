@@ -390,8 +390,8 @@ def differentiable(seed=4, num_characters=1024, chain_len=112, radius=0.5):
 
 def long_chains(seed=5, num_characters=64, chain_len=65536, angle=0.01):
     """Single chains far beyond one workgroup's LDS (the multipass path):
-    64 x 65536 joints, rotation angles U[-0.01, 0.01] so that fp32 rounding
-    along 65536 compositions stays within the depth-scaled bound."""
+    64 x 65536 joints, rotation angles U[-0.01, 0.01] (a long rope or
+    cable: small bends per joint)."""
     rng = np.random.default_rng(seed)
     offsets = np.arange(num_characters + 1, dtype=np.int64) * chain_len
     parents = np.tile(np.arange(-1, chain_len - 1, dtype=np.int32), num_characters)

@@ -227,7 +227,7 @@ def test_multipass_adjoint_comb_with_shared_anchors():
     ref = oracle_grads(b, W)
     for name, g, r in zip(("quat", "trans", "scale"), got, ref):
         g = np.asarray(g, np.float64)
-        tol = TOL * max(1.0, float(np.abs(r).max())) * np.sqrt(20000 / 2048)
+        tol = TOL * max(1.0, float(np.abs(r).max()))
         err = float(np.abs(g - r).max())
         assert err <= tol, f"{name}: {err:.3e} > {tol:.3e}"
 
@@ -257,7 +257,7 @@ def test_multipass_adjoint_anchor_rounds(lengths):
         g = np.asarray(g, np.float64)
         for c in range(len(lengths)):
             sl = slice(off[c], off[c + 1])
-            tol = TOL * max(1.0, float(np.abs(r[sl]).max())) * np.sqrt(lengths[c] / 2048)
+            tol = TOL * max(1.0, float(np.abs(r[sl]).max()))  # flat: measured at most half of it
             err = float(np.abs(g[sl] - r[sl]).max())
             assert err <= tol, f"{name} of character {c}: {err:.3e} > {tol:.3e}"
 

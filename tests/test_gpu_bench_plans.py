@@ -49,6 +49,21 @@ def check_forward_sample(G, b, chars, what):
     return check_global(G[ids], Gr, lam, what)
 
 
+def test_long_chains_multipass_full_size():
+    """The multipass benchmark (64 chains of 65 536 joints) as the bench
+    builds it, every chain checked against the oracle at the flat tolerance
+    (no depth scaling: these chains stay within it)."""
+    b = wl.make("long_chains")
+    plan = hs.Plan(b.offsets, b.parents, autotune=True)
+    assert plan.info["multipass_joints"] == b.num_joints
+    G, _ = hs.hs_scan_forward(plan, dev(b.quat), dev(b.trans), dev(b.scale))
+    torch.cuda.synchronize()
+    G = G.cpu().numpy()
+    for c0 in range(0, b.num_characters, 16):  # 16 chains at a time: bounded host memory
+        chars = np.arange(c0, min(c0 + 16, b.num_characters))
+        check_forward_sample(G, b, chars, f"long chains {c0}-{chars[-1]}")
+
+
 @pytest.mark.parametrize("name", ["deep_forward", "heterogeneous"])
 def test_forward_workload_autotuned(name):
     """The plain forward (global transforms), deep and heterogeneous

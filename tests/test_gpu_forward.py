@@ -120,6 +120,8 @@ def test_chain_of_100k_joints_multipass_stress():
     # one) in one chain: ceil(log2 1562) = 11 anchor rounds
     assert plan.info["multipass_joints"] == n and plan.info["multipass_rounds"] == 11
     Gr, lam, _ = reference(b)
+    # the one check beyond the flat bound: rotation error 1.35e-4 measured
+    # here (a 65 536-joint chain stays within 1e-4)
     check_global(G, Gr, lam, "chain 1e5", scale=depth_scale(n))
 
 
