@@ -824,7 +824,7 @@ hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *bui
         for (int skin = 0; skin < 2; ++skin) {
             int per_cu = 1;
             const size_t lds = hs::forward_queue_lds_bytes(waves, max_anchors, cap, smp != 0, skin != 0);
-            if ((err = hs::queue_blocks_per_cu(waves, smp != 0, lds, &per_cu)) != hipSuccess)
+            if ((err = hs::queue_blocks_per_cu(waves, smp != 0, skin != 0, lds, &per_cu)) != hipSuccess)
                 return fail_hip(err, "hs_plan_create (work-queue occupancy)");
             per_cu = std::max(1, shape.grid_per_cu > 0 ? std::min(per_cu, shape.grid_per_cu) : per_cu);
             Q.grids[smp][skin] =

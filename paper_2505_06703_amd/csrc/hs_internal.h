@@ -227,9 +227,9 @@ size_t backward_anchor_lds_bytes(int waves, int max_anchors, int tile_cap);
 // wave, seed kind 0 dense / 1 effectors / 2 forward in the tile) that fit
 // one CU with `lds` bytes of LDS.
 hipError_t anchor_blocks_per_cu(int waves, int bpw, int seed, size_t lds, int *out);
-// Workgroups of the queue kernel (stored or sampled poses) that fit one CU
-// with `lds` bytes of LDS.
-hipError_t queue_blocks_per_cu(int waves, bool sample, size_t lds, int *out);
+// Workgroups of the queue kernel (stored or sampled poses; G or skin
+// output) that fit one CU with `lds` bytes of LDS.
+hipError_t queue_blocks_per_cu(int waves, bool sample, bool skin, size_t lds, int *out);
 hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
                                     hipStream_t stream);
 hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,

@@ -890,7 +890,7 @@ __device__ __forceinline__ void store_slice_rows(float4 *dst, const float4 *X, i
 
 // SS: float4 rows per joint in the staging slice (3, or 4 when skin rows
 // are staged too)
-template <bool SAMPLE>
+template <bool SAMPLE, bool SKIN>
 __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out,
                                             const QTile &td, int b, float4 *stage, int SS, int *xi, float4 *anc,
                                             int *flags, const int *cstart, int lane)
@@ -932,7 +932,7 @@ __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArg
     const int nb = td.count - base;  // joints of this block (may exceed 64: clipped by the row stores)
     if (out.global_out)
         store_slice_rows(reinterpret_cast<float4 *>(out.global_out) + 4 * (td.begin + base), stage, SS, 3, nb, lane);
-    if (out.skin_out) {
+    if constexpr (SKIN) {
         // S = G B^-1 (the bottom row of S is B^-1's), staged like G so that
         // the rows leave as whole lines
         float4 srow[4];
@@ -965,7 +965,7 @@ __device__ __forceinline__ void queue_block(const QueueLaunch &ql, const PoseArg
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int WAVES, bool SAMPLE>
+template <int WAVES, bool SAMPLE, bool SKIN>
 __global__ void __launch_bounds__(WAVES * kWave)
 fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
 {
@@ -973,7 +973,7 @@ fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
     if (gated(ql.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    const int SS = out.skin_out ? 4 : 3;  // staged rows per joint
+    constexpr int SS = SKIN ? 4 : 3;  // staged rows per joint
     float4 *stage = lds + wave * kWave * SS;
     int *xi = reinterpret_cast<int *>(lds + WAVES * kWave * SS) + wave * kWave;
     float4 *anc = lds + WAVES * kWave * SS + WAVES * kWave / 4;
@@ -996,7 +996,7 @@ fwd_queue_kernel(QueueLaunch ql, PoseArgs pose, OutArgs out)
         __syncthreads();
         const int nblk = (td.count + kWave - 1) / kWave;
         for (int b = wave; b < nblk; b += WAVES)
-            queue_block<SAMPLE>(ql, pose, out, td, b, stage, SS, xi, anc, flags, cstart, lane);
+            queue_block<SAMPLE, SKIN>(ql, pose, out, td, b, stage, SS, xi, anc, flags, cstart, lane);
         __syncthreads();  // LDS is reused by the next tile
     }
 }
@@ -3377,6 +3377,15 @@ hipError_t noalloc_workspace(int device, float4 **out)
     return hipSuccess;
 }
 
+template <int WAVES>
+void queue_kernels(const void **k, int &n)
+{
+    k[n++] = reinterpret_cast<const void *>(fwd_queue_kernel<WAVES, false, false>);
+    k[n++] = reinterpret_cast<const void *>(fwd_queue_kernel<WAVES, false, true>);
+    k[n++] = reinterpret_cast<const void *>(fwd_queue_kernel<WAVES, true, false>);
+    k[n++] = reinterpret_cast<const void *>(fwd_queue_kernel<WAVES, true, true>);
+}
+
 hipError_t prepare_kernels()
 {
     hipError_t err;
@@ -3387,18 +3396,15 @@ hipError_t prepare_kernels()
         if ((err = hipGetDevice(&dev)) != hipSuccess) return err;
         if ((err = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess)
             return err;
-        const void *qk[10] = {reinterpret_cast<const void *>(fwd_queue_kernel<1, false>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<1, true>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<2, false>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<2, true>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<4, false>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<4, true>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<8, false>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<8, true>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<16, false>),
-                             reinterpret_cast<const void *>(fwd_queue_kernel<16, true>)};
-        for (const void *k : qk)
-            if ((err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max)) != hipSuccess)
+        const void *qk[20];
+        int nq = 0;
+        queue_kernels<1>(qk, nq);
+        queue_kernels<2>(qk, nq);
+        queue_kernels<4>(qk, nq);
+        queue_kernels<8>(qk, nq);
+        queue_kernels<16>(qk, nq);
+        for (int i = 0; i < nq; ++i)
+            if ((err = hipFuncSetAttribute(qk[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds_max)) != hipSuccess)
                 return err;
     }
     if ((err = set_vertex_lds_limits_all<4>()) != hipSuccess || (err = set_vertex_lds_limits_all<8>()) != hipSuccess ||
@@ -3671,28 +3677,36 @@ size_t forward_vertex_lds_bytes(int tile_cap)
 template <int WAVES, bool SAMPLE>
 hipError_t launch_queue_t(const QueueLaunch &ql, const PoseArgs &pose, const OutArgs &out, hipStream_t stream)
 {
-    const size_t lds = forward_queue_lds_bytes(WAVES, ql.max_anchors, ql.tile_cap, SAMPLE, out.skin_out != nullptr);
-    hipLaunchKernelGGL((fwd_queue_kernel<WAVES, SAMPLE>), dim3(ql.grid), dim3(WAVES * kWave), lds, stream, ql, pose,
-                       out);
+    const bool skin = out.skin_out != nullptr;
+    const size_t lds = forward_queue_lds_bytes(WAVES, ql.max_anchors, ql.tile_cap, SAMPLE, skin);
+    if (skin)
+        hipLaunchKernelGGL((fwd_queue_kernel<WAVES, SAMPLE, true>), dim3(ql.grid), dim3(WAVES * kWave), lds, stream,
+                           ql, pose, out);
+    else
+        hipLaunchKernelGGL((fwd_queue_kernel<WAVES, SAMPLE, false>), dim3(ql.grid), dim3(WAVES * kWave), lds, stream,
+                           ql, pose, out);
     return hipGetLastError();
 }
 
 template <int WAVES>
-hipError_t queue_occupancy_t(bool sample, size_t lds, int *out)
+hipError_t queue_occupancy_t(bool sample, bool skin, size_t lds, int *out)
 {
-    return sample ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fwd_queue_kernel<WAVES, true>, WAVES * kWave, lds)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, fwd_queue_kernel<WAVES, false>, WAVES * kWave, lds);
+    const void *k[4];
+    int n = 0;
+    queue_kernels<WAVES>(k, n);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, k[2 * (sample ? 1 : 0) + (skin ? 1 : 0)], WAVES * kWave,
+                                                        lds);
 }
 
-hipError_t queue_blocks_per_cu(int waves, bool sample, size_t lds, int *out)
+hipError_t queue_blocks_per_cu(int waves, bool sample, bool skin, size_t lds, int *out)
 {
     *out = 1;
     switch (waves) {
-    case 1: return queue_occupancy_t<1>(sample, lds, out);
-    case 2: return queue_occupancy_t<2>(sample, lds, out);
-    case 4: return queue_occupancy_t<4>(sample, lds, out);
-    case 8: return queue_occupancy_t<8>(sample, lds, out);
-    case 16: return queue_occupancy_t<16>(sample, lds, out);
+    case 1: return queue_occupancy_t<1>(sample, skin, lds, out);
+    case 2: return queue_occupancy_t<2>(sample, skin, lds, out);
+    case 4: return queue_occupancy_t<4>(sample, skin, lds, out);
+    case 8: return queue_occupancy_t<8>(sample, skin, lds, out);
+    case 16: return queue_occupancy_t<16>(sample, skin, lds, out);
     default: return hipErrorInvalidValue;
     }
 }
