@@ -213,6 +213,8 @@ typedef struct hs_plan_info {
     int32_t max_anchors;       /* queue: most anchors of one tile (LDS slots), else 0 */
     int32_t adjoint_blocks_per_wave; /* two-level adjoint of hs_effector_step: 64-joint blocks
                                   per wave (0: the plan has no such tiles) */
+    int64_t chain_joints;      /* multipass joints of chain characters (every parent the previous
+                                  joint), scanned in one pass over their poses */
 } hs_plan_info;
 
 /* Analyse a batch: validates the CSR topology (HS_ERR_TOPOLOGY if some

@@ -353,6 +353,16 @@ struct MPSet {
     // adjoint: anchor adjoints, compact G
     float4 *S[2] = {nullptr, nullptr};
     float4 *G = nullptr;
+    // the one-pass chain path (forward set only): chain characters' blocks
+    // and superblocks, their workspace, and the resident grid per pose kind
+    hs::ChainBlock *d_cblocks = nullptr;
+    int32_t num_cblocks = 0;
+    hs::ChainSB *d_csb = nullptr;
+    int32_t num_csb = 0;
+    int64_t chain_joints = 0;
+    float4 *c_sbagg = nullptr, *c_sbinc = nullptr;
+    int32_t *c_words = nullptr;
+    int32_t c_grid[2] = {0, 0};
 };
 
 void free_mpset(MPSet &m)
@@ -369,6 +379,11 @@ void free_mpset(MPSet &m)
         (void)hipFree(m.S[i]);
     }
     (void)hipFree(m.G);
+    (void)hipFree(m.d_cblocks);
+    (void)hipFree(m.d_csb);
+    (void)hipFree(m.c_sbagg);
+    (void)hipFree(m.c_sbinc);
+    (void)hipFree(m.c_words);
     m = MPSet{};
 }
 
@@ -539,6 +554,7 @@ int mark_chain_units(const std::vector<int32_t> &gparent, TileDesc &t)
 struct Packing {
     std::vector<TileDesc> tiles;  // sorted, heaviest first
     std::vector<MPBlock> mpb;
+    std::vector<int64_t> chains;  // one-pass chain characters (when asked for)
     int64_t nmp = 0, tiled = 0;
     int max_chain_tiles = 0, max_chain_mp = 0;
     int max_units = 0;  // most work units (blocks or chain units) in one tile
@@ -549,7 +565,7 @@ struct Packing {
 // lo..hi joints are taken; the others are left out (another packing covers
 // them).
 Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units, int64_t lo = 0,
-                   int64_t hi = INT64_MAX)
+                   int64_t hi = INT64_MAX, bool chain_pass = false)
 {
     const int64_t C = plan->C;
     const auto &off = plan->h_offsets;
@@ -584,6 +600,16 @@ Packing pack_tiles(const hs_plan *plan, int cap, int strategy, bool chain_units,
         if (to_mp) {
             flush();
             if (n == 0) continue;
+            if (chain_pass) {
+                // every parent the previous joint: the one-pass chain path
+                const int32_t *pc = par.data() + off[c];
+                bool chain = pc[0] == -1;
+                for (int64_t j = 1; j < n && chain; ++j) chain = pc[j] == j - 1;
+                if (chain) {
+                    pk.chains.push_back(c);
+                    continue;
+                }
+            }
             const int L = block_chain_length(par.data() + off[c], n, 0, top, chain);
             pk.max_chain_mp = std::max(pk.max_chain_mp, L);
             for (int64_t k = 0; k < n; k += 64) {
@@ -683,11 +709,62 @@ void build_anchors(const hs_plan *plan, const Packing &pk, std::vector<int32_t> 
 
 // Upload a packing's multipass blocks and anchors and allocate the path's
 // workspace (and the adjoint's, if asked).
+// The one-pass chain path's tables and workspace: each chain character in
+// 64-joint blocks, up to 64 consecutive blocks of one chain per
+// superblock; the grid is the workgroups resident at once.
+hs_status make_chains(MPSet &m, const hs_plan *plan, const Packing &pk)
+{
+    if (pk.chains.empty()) return HS_OK;
+    std::vector<hs::ChainBlock> cb;
+    std::vector<hs::ChainSB> sbs;
+    for (int64_t c : pk.chains) {
+        const int64_t b0 = plan->h_offsets[c], n = plan->h_offsets[c + 1] - b0;
+        const int32_t first_sb = (int32_t)sbs.size();
+        for (int64_t k = 0; k < n; k += 64) {
+            const int64_t blk = k / 64;
+            if (blk % 64 == 0) sbs.push_back(hs::ChainSB{(int32_t)cb.size(), 0, first_sb, 0});
+            hs::ChainBlock b{};
+            b.gbegin = b0 + k;
+            b.count = (int32_t)std::min<int64_t>(64, n - k);
+            b.sb = (int32_t)sbs.size() - 1;
+            b.k = sbs.back().nblk++;
+            b.chr = (int32_t)c;
+            cb.push_back(b);
+        }
+        m.chain_joints += n;
+    }
+    if (cb.size() > (size_t)INT32_MAX / 4) return fail(HS_ERR_UNSUPPORTED, "too many chain blocks");
+    m.num_cblocks = (int32_t)cb.size();
+    m.num_csb = (int32_t)sbs.size();
+    for (int smp = 0; smp < 2; ++smp) {
+        int per_cu = 0;
+        hipError_t e = hs::chain_blocks_per_cu(smp != 0, &per_cu);
+        if (e != hipSuccess) return fail_hip(e, "hs_plan_create (chain occupancy)");
+        if (per_cu < 1) return fail(HS_ERR_UNSUPPORTED, "the chain kernel does not fit a CU");
+        m.c_grid[smp] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(m.num_csb, (int64_t)per_cu * plan->ctx->num_cu));
+    }
+    const size_t nb = (size_t)m.num_cblocks, ns = (size_t)m.num_csb;
+    hipError_t err = upload(&m.d_cblocks, cb);
+    if (err == hipSuccess) err = upload(&m.d_csb, sbs);
+    if (err == hipSuccess) err = hipMalloc(&m.c_sbagg, ns * 3 * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&m.c_sbinc, ns * 3 * sizeof(float4));
+    if (err == hipSuccess) err = hipMalloc(&m.c_words, ns * sizeof(int32_t));
+    if (err != hipSuccess) return fail_hip(err, "hs_plan_create (chain workspace)");
+    return HS_OK;
+}
+
 hs_status make_mpset(MPSet &m, const hs_plan *plan, const Packing &pk, bool adjoint)
 {
     free_mpset(m);
     m.num_blocks = (int32_t)pk.mpb.size();
     m.nmp = pk.nmp;
+    if (!adjoint) {
+        hs_status rc = make_chains(m, plan, pk);
+        if (rc != HS_OK) {
+            free_mpset(m);
+            return rc;
+        }
+    }
     if (pk.nmp == 0) return HS_OK;
     std::vector<int32_t> janc, anchors;
     build_anchors(plan, pk, janc, anchors, m.rounds);
@@ -874,7 +951,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
             small_grid += cs.grid;
         }
     }
-    Packing pk = pack_tiles(plan, cap, strategy, shape.chain_units, main_lo);
+    Packing pk = pack_tiles(plan, cap, strategy, shape.chain_units, main_lo, INT64_MAX, true);
     std::vector<TileDesc> &sorted = pk.tiles;
     const int64_t nmp = pk.nmp, tiled = pk.tiled + small_tiled;
     const int max_chain_tiles = pk.max_chain_tiles, max_chain_mp = pk.max_chain_mp;
@@ -960,7 +1037,8 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
 
     hs_plan_info &I = plan->info;
     I.tiled_joints = tiled;
-    I.multipass_joints = nmp;
+    I.multipass_joints = nmp + plan->mp.chain_joints;
+    I.chain_joints = plan->mp.chain_joints;
     I.num_tiles = (int32_t)sorted.size() + small_tiles;
     I.tile_joints = cap;
     I.waves_per_tile = shape.waves;
@@ -1049,6 +1127,24 @@ hs::MPLaunch mp_launch(const hs_plan *p, const MPSet &m, bool validate = false)
     }
     ml.gate = validate ? p->d_status : nullptr;
     return ml;
+}
+
+hs::ChainLaunch chain_launch(const hs_plan *p, bool sample, bool validate = false)
+{
+    const MPSet &m = p->mp;
+    hs::ChainLaunch cl{};
+    cl.blocks = m.d_cblocks;
+    cl.num_blocks = m.num_cblocks;
+    cl.sbs = m.d_csb;
+    cl.num_sb = m.num_csb;
+    cl.grid = m.c_grid[sample ? 1 : 0];
+    cl.sbagg = m.c_sbagg;
+    cl.sbinc = m.c_sbinc;
+    cl.words = m.c_words;
+    cl.status = p->d_status;
+    cl.spin_limit = p->spin_limit;
+    cl.gate = validate ? p->d_status : nullptr;
+    return cl;
 }
 
 // HS_FLAG_VALIDATE: the topology check of the plan's device tables, on the
@@ -1147,6 +1243,8 @@ hs_status run_forward(const hs_plan *plan, const hs::PoseArgs &pa, const hs::Out
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (tiles)");
     err = hs::launch_forward_multipass(mp_launch(plan, plan->mp, validate), pa, oa, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (multipass)");
+    err = hs::launch_forward_chains(chain_launch(plan, pa.kind == 1, validate), pa, oa, stream);
+    if (err != hipSuccess) return fail_hip(err, "hs_scan_forward (chains)");
     return HS_OK;
 }
 
@@ -1651,7 +1749,7 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
         }
     }
     if (rc == HS_OK && o.autotune && N > 0 && sh.algorithm == HS_ALG_SCAN) rc = autotune(plan, sh, o.strategy);
-    if (rc == HS_OK && plan->inst && plan->mp.nmp > 0)
+    if (rc == HS_OK && plan->inst && (plan->mp.nmp > 0 || plan->mp.chain_joints > 0))
         rc = fail(HS_ERR_UNSUPPORTED, "instanced plans need every character on a tile (%d joints at most here)",
                   plan->shape.tile_cap);
     if (rc != HS_OK) {
@@ -1852,9 +1950,11 @@ hs_status hs_pose_sample(const hs_plan *plan, const hs_clip_lib *lib, const hs_c
     if (!dg.ok) return fail(HS_ERR_DEVICE, "hs_pose_sample: cannot select device");
     hipError_t err = hipSuccess;
     for (int k = 0; k < (int)plan->small.size() && err == hipSuccess; ++k)
-        err = hs::launch_pose_sample(tile_launch(plan, k), hs::MPLaunch{}, pa, quat_out, trans_out, stream);
+        err = hs::launch_pose_sample(tile_launch(plan, k), hs::MPLaunch{}, hs::ChainLaunch{}, pa, quat_out,
+                                     trans_out, stream);
     if (err == hipSuccess)
-        err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan, plan->mp), pa, quat_out, trans_out, stream);
+        err = hs::launch_pose_sample(tile_launch(plan), mp_launch(plan, plan->mp), chain_launch(plan, true), pa,
+                                     quat_out, trans_out, stream);
     if (err != hipSuccess) return fail_hip(err, "hs_pose_sample");
     return HS_OK;
 }
@@ -2180,7 +2280,7 @@ hs_status hs_scan_skin_vertices(const hs_plan *plan, const hs_pose_src *src, con
     if (mesh->plan != plan) return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: the mesh was made for another plan");
     if (method != HS_SKIN_LINEAR && method != HS_SKIN_DUAL_QUAT)
         return fail(HS_ERR_INVALID_ARG, "hs_scan_skin_vertices: unknown method %d", method);
-    if (plan->mp.nmp > 0)
+    if (plan->mp.nmp > 0 || plan->mp.chain_joints > 0)
         return fail(HS_ERR_UNSUPPORTED, "hs_scan_skin_vertices: every character must be on a tile (no multipass)");
     if (plan->shape.tile_cap > hs::kMaxVertexTileJoints)
         return fail(HS_ERR_UNSUPPORTED, "hs_scan_skin_vertices: tiles of at most %d joints (plan has %d)",

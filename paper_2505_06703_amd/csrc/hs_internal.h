@@ -165,6 +165,40 @@ struct TileLaunch {
     int32_t blocks_per_wave;  // the two-level adjoint: 64-joint blocks per wave (1 or 2)
 };
 
+// The one-pass path for chain characters on the multipass path (every
+// joint's parent the previous joint): 64-joint blocks in chain order,
+// grouped into superblocks of up to 64 consecutive blocks of one chain.
+struct ChainBlock {
+    int64_t gbegin;  // global id of the block's first joint
+    int32_t count;   // joints in the block (1..64)
+    int32_t sb;      // superblock
+    int32_t k;       // index of the block in its superblock
+    int32_t chr;     // character
+    int64_t pad;
+};
+static_assert(sizeof(ChainBlock) == 32, "ChainBlock layout");
+
+struct ChainSB {
+    int32_t first;        // first block
+    int32_t nblk;         // blocks (1..64)
+    int32_t chain_first;  // the chain's first superblock
+    int32_t pad;
+};
+
+struct ChainLaunch {
+    const ChainBlock *blocks;
+    int32_t num_blocks;
+    const ChainSB *sbs;
+    int32_t num_sb;
+    int32_t grid;      // workgroups, all resident at once
+    float4 *sbagg;     // [superblocks][3] each superblock's product of its local transforms
+    float4 *sbinc;     // [superblocks][3] G of each superblock's last joint
+    int32_t *words;    // [superblocks] published: 1 the product, 2 the final transform; zeroed per call
+    uint32_t *status;
+    int32_t spin_limit;
+    const uint32_t *gate;
+};
+
 struct MPLaunch {
     const MPBlock *blocks;
     int32_t num_blocks;
@@ -232,11 +266,17 @@ hipError_t anchor_blocks_per_cu(int waves, int bpw, int seed, size_t lds, int *o
 hipError_t queue_blocks_per_cu(int waves, bool sample, bool skin, size_t lds, int *out);
 hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
                                     hipStream_t stream);
+// The one-pass chain path (clears its words, then one persistent launch).
+hipError_t launch_forward_chains(const ChainLaunch &cl, const PoseArgs &pose, const OutArgs &out,
+                                 hipStream_t stream);
+// Workgroups of the chain kernel (stored or sampled poses) that fit one CU.
+hipError_t chain_blocks_per_cu(bool sample, int *out);
+constexpr int kChainWaves = 16;  // waves per workgroup of the chain kernel
 hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
                                  hipStream_t stream);
 hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, const BwdArgs &bwd,
                                      hipStream_t stream);
-hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const PoseArgs &pose,
+hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const ChainLaunch &cl, const PoseArgs &pose,
                               float *quat_out, float *trans_out, hipStream_t stream);
 hipError_t launch_skin(int64_t n, const float *global, const float *inv_bind, float *skin_out,
                        hipStream_t stream);

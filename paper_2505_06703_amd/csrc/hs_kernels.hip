@@ -2926,6 +2926,218 @@ mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 
 }
 
 // ---------------------------------------------------------------------------
+// One pass for chain characters beyond a tile (every joint's parent the
+// previous joint): a reduce-then-scan over superblocks of up to 64
+// consecutive 64-joint blocks of one chain, one superblock per workgroup
+// at a time (16 waves, four blocks each).  Each wave scans its blocks (the
+// in-block rounds, lane = joint) and keeps every joint's product P_j from
+// its block's first joint in registers; the blocks' totals meet in LDS,
+// where one wave scans them (lane = block), publishes the superblock's
+// total, looks back over the chain's earlier superblocks (lane =
+// superblock: the nearest final transform and the totals after it,
+// composed by the same scan) for the transform entering the superblock,
+// publishes its final transform, and leaves in LDS the transform entering
+// each block; then G_j = (transform entering its block) P_j leaves as
+// coalesced rows.  Each pose is read once.  Workgroups take superblocks in
+// increasing order (a static stride; the launch holds no more workgroups
+// than are resident at once), and a superblock publishes its total before
+// it looks back, so the look-backs only wait for publications that need
+// no waiting.  Values cross workgroups as agent-scope atomic stores and
+// loads (coherent across the XCDs' L2s), each publication's stores
+// complete before its flag is stored.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_agent12(float4 *dst, const float m[12])
+{
+    unsigned *d = reinterpret_cast<unsigned *>(dst);
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        __hip_atomic_store(d + k, __float_as_uint(m[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void load_agent12(const float4 *src, float m[12])
+{
+    unsigned *s = reinterpret_cast<unsigned *>(const_cast<float4 *>(src));
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        m[k] = __uint_as_float(__hip_atomic_load(s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Every store the wave has issued is complete (at agent scope) before what
+// follows: the memory counter of gfx9 waves counts stores too.
+__device__ __forceinline__ void stores_done()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt not waited for
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+constexpr int kChainBlocksPerWave = 4;  // 16 waves x 4 blocks = a superblock of 64 blocks
+
+// Wave 0 of the workgroup resolving superblock s: T [64][3] the blocks'
+// totals (in), E [64][3] the transforms entering the blocks (out); X, xi
+// the wave's scan slice.
+__device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s, const ChainSB &sb, int lane,
+                                                   const float4 *T, float4 *E, float4 *X, int *xi)
+{
+    int *pub = cl.words;
+    // inclusive products of the blocks' totals, in chain order (lane = block)
+    const bool in = lane < sb.nblk;
+    float x[12];
+    if (in) aff_load(T + 3 * lane, x);
+    else aff_identity(x);
+    int a = in && lane > 0 ? lane - 1 : -1, e = -1;
+    wave_inblock_scan_lds(x, a, e, lane, X, xi);
+    aff_store(X + 3 * lane, x);
+    wave_sync();
+    float tot[12], xex[12];
+    aff_load(X + 3 * (sb.nblk - 1), tot);  // the superblock's total
+    if (lane > 0) aff_load(X + 3 * (lane - 1), xex);
+    else aff_identity(xex);
+    wave_sync();  // the slice is free
+    float acc[12];  // the transform entering the superblock
+    aff_identity(acc);
+    if (s == sb.chain_first) {
+        if (lane == 0) {
+            store_agent12(cl.sbinc + 3 * s, tot);
+            stores_done();
+            __hip_atomic_store(pub + s, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        if (lane == 0) {
+            store_agent12(cl.sbagg + 3 * s, tot);
+            stores_done();
+            __hip_atomic_store(pub + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // look back, 64 superblocks at a time (lane k: superblock base - k)
+        for (int base = s - 1;; base -= kWave) {
+            const int q = base - lane;
+            const bool lv = q >= sb.chain_first;
+            int st = 2;
+            for (int spin = 0;; ++spin) {
+                st = lv ? __hip_atomic_load(pub + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 2;
+                if (__all(st > 0)) break;
+                if (spin >= cl.spin_limit) {
+                    note_status(cl.status, kStatusWaitTimeout);
+                    st = 2;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            // the nearest final transform (the chain's first superblock always is one)
+            const unsigned long long fin = __ballot(lv && st == 2);
+            const int kf = fin ? __ffsll((long long)fin) - 1 : -1;
+            const int nv = min(kWave, base - sb.chain_first + 1);  // lanes inside the chain
+            float v[12];
+            if (lane < nv && (kf < 0 || lane <= kf)) load_agent12((lane == kf ? cl.sbinc : cl.sbagg) + 3 * q, v);
+            else aff_identity(v);
+            const int top = kf >= 0 ? kf : nv - 1;  // the window's earliest superblock taken
+            int pa = lane < top ? lane + 1 : -1, pe = -1;
+            wave_inblock_scan_lds(v, pa, pe, lane, X, xi);  // lane 0: v(top) ... v(0)
+            if (lane == 0) aff_store(X, v);
+            wave_sync();
+            float w[12];
+            aff_load(X, w);
+            wave_sync();
+            aff_mul_left(w, acc);  // acc = w acc
+            if (kf >= 0) break;    // uniform
+        }
+        if (lane == 0) {
+            float inc[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) inc[k] = tot[k];
+            aff_mul_left(acc, inc);
+            store_agent12(cl.sbinc + 3 * s, inc);
+            stores_done();
+            __hip_atomic_store(pub + s, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    aff_mul_left(acc, xex);  // the transform entering block `lane`
+    if (in) aff_store(E + 3 * lane, xex);
+}
+
+template <bool SAMPLE>
+__global__ void __launch_bounds__(kChainWaves * kWave)
+mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
+{
+    __shared__ float4 slice[kChainWaves * kWave * 3];
+    __shared__ float4 T[kWave * 3], E[kWave * 3];
+    __shared__ float4 PS[kChainBlocksPerWave * kWave * 3];  // wave 0's products while it resolves
+    __shared__ int xs[kChainWaves * kWave];
+    if (gated(cl.gate)) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    float4 *X = slice + wv * kWave * 3;
+    int *xi = xs + wv * kWave;
+    const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    for (int s = blockIdx.x; s < cl.num_sb; s += gridDim.x) {  // uniform per workgroup
+        const ChainSB sb = cl.sbs[s];
+        // the wave's blocks: k = wave + 16 i
+        float P[kChainBlocksPerWave][12];
+#pragma unroll
+        for (int i = 0; i < kChainBlocksPerWave; ++i) {
+            const int k = wv + kChainWaves * i;
+            if (k >= sb.nblk) break;  // uniform per wave
+            const ChainBlock cb = cl.blocks[sb.first + k];
+            const bool valid = lane < cb.count;
+            const int64_t gid = cb.gbegin + lane;
+            if (valid) {
+                int lj = 0;
+                if constexpr (SAMPLE) lj = (int)(gid - pose.offsets[cb.chr]);
+                load_local<SAMPLE>(pose, gid, cb.chr, lj, P[i]);
+            } else {
+                aff_identity(P[i]);
+            }
+            int a = valid && lane > 0 ? lane - 1 : -1, e = -1;
+            wave_inblock_scan_lds(P[i], a, e, lane, X, xi);
+            if (lane == cb.count - 1) aff_store(T + 3 * k, P[i]);  // the block's total
+        }
+        __syncthreads();  // every block's total
+        if (wv == 0) {
+            // the products wait in LDS (registers for the resolution)
+#pragma unroll
+            for (int i = 0; i < kChainBlocksPerWave; ++i) aff_store(PS + 3 * (kWave * i + lane), P[i]);
+            resolve_superblock(cl, s, sb, lane, T, E, X, xi);
+#pragma unroll
+            for (int i = 0; i < kChainBlocksPerWave; ++i) aff_load(PS + 3 * (kWave * i + lane), P[i]);
+        }
+        __syncthreads();  // the transforms entering the blocks
+#pragma unroll
+        for (int i = 0; i < kChainBlocksPerWave; ++i) {
+            const int k = wv + kChainWaves * i;
+            if (k >= sb.nblk) break;
+            const ChainBlock cb = cl.blocks[sb.first + k];
+            const int64_t gid = cb.gbegin + lane;
+            float g[12];
+            aff_load(E + 3 * k, g);
+            aff_mul_left(g, P[i]);
+            if (out.global_out) {
+                wave_sync();  // the slice's last readers are done
+                aff_store(X + 3 * lane, P[i]);
+                wave_sync();
+                float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * cb.gbegin;
+#pragma unroll
+                for (int c4 = 0; c4 < 4; ++c4) {
+                    const int c = lane + kWave * c4;
+                    if ((c >> 2) < cb.count) {
+                        const int r = c & 3;
+                        store_stream(dst + c, r == 3 ? bottom : X[3 * (c >> 2) + r]);
+                    }
+                }
+            }
+            if (lane < cb.count) write_skin_and_ckpt(out, gid, gid, P[i]);
+        }
+        __syncthreads();  // T and E are rewritten by the next superblock
+    }
+}
+
+__global__ void __launch_bounds__(256) zero_words_kernel(int32_t *w, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint on the multipass path (characters larger than an adjoint tile).
 //
 // With D the incoming dLoss/dG, the in-block adjoint Z = R_B(Y) of a block
@@ -3212,13 +3424,14 @@ sample_tile_kernel(TileLaunch tl, PoseArgs pose, float *quat_out, float *trans_o
     }
 }
 
+template <class BLOCK>
 __global__ void __launch_bounds__(256)
-sample_mp_kernel(MPLaunch ml, PoseArgs pose, float *quat_out, float *trans_out)
+sample_mp_kernel(const BLOCK *blocks, int32_t num_blocks, PoseArgs pose, float *quat_out, float *trans_out)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const int w = blockIdx.x * kMPWaves + threadIdx.x / kWave;
-    if (w >= ml.num_blocks) return;
-    const MPBlock bd = ml.blocks[w];
+    if (w >= num_blocks) return;
+    const BLOCK bd = blocks[w];
     if (lane >= bd.count) return;
     const int64_t gid = bd.gbegin + lane;
     float4 q;
@@ -3518,6 +3731,29 @@ hipError_t run_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs
     return hipGetLastError();
 }
 
+hipError_t chain_blocks_per_cu(bool sample, int *out)
+{
+    *out = 0;
+    return sample ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, mp_chain_kernel<true>, kChainWaves * kWave, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, mp_chain_kernel<false>, kChainWaves * kWave, 0);
+}
+
+hipError_t launch_forward_chains(const ChainLaunch &cl, const PoseArgs &pose, const OutArgs &out,
+                                 hipStream_t stream)
+{
+    if (cl.num_blocks == 0) return hipSuccess;
+    if (cl.grid < 1 || cl.num_sb < 1) return hipErrorInvalidValue;
+    const int nw = cl.num_sb;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((nw + 255) / 256), dim3(256), 0, stream, cl.words, nw);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (pose.kind == 1)
+        hipLaunchKernelGGL(mp_chain_kernel<true>, dim3(cl.grid), dim3(kChainWaves * kWave), 0, stream, cl, pose, out);
+    else
+        hipLaunchKernelGGL(mp_chain_kernel<false>, dim3(cl.grid), dim3(kChainWaves * kWave), 0, stream, cl, pose, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs &out,
                                     hipStream_t stream)
 {
@@ -3525,7 +3761,7 @@ hipError_t launch_forward_multipass(const MPLaunch &ml, const PoseArgs &pose, co
     return run_multipass(ml, pose, out, nullptr, stream);
 }
 
-hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const PoseArgs &pose,
+hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const ChainLaunch &cl, const PoseArgs &pose,
                               float *quat_out, float *trans_out, hipStream_t stream)
 {
     if (tl.num_tiles > 0) {
@@ -3536,8 +3772,14 @@ hipError_t launch_pose_sample(const TileLaunch &tl, const MPLaunch &ml, const Po
         if (err != hipSuccess) return err;
     }
     if (ml.num_blocks > 0) {
-        hipLaunchKernelGGL(sample_mp_kernel, dim3((ml.num_blocks + kMPWaves - 1) / kMPWaves),
-                           dim3(kMPWaves * kWave), 0, stream, ml, pose, quat_out, trans_out);
+        hipLaunchKernelGGL(sample_mp_kernel<MPBlock>, dim3((ml.num_blocks + kMPWaves - 1) / kMPWaves),
+                           dim3(kMPWaves * kWave), 0, stream, ml.blocks, ml.num_blocks, pose, quat_out, trans_out);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    if (cl.num_blocks > 0) {
+        hipLaunchKernelGGL(sample_mp_kernel<ChainBlock>, dim3((cl.num_blocks + kMPWaves - 1) / kMPWaves),
+                           dim3(kMPWaves * kWave), 0, stream, cl.blocks, cl.num_blocks, pose, quat_out, trans_out);
         return hipGetLastError();
     }
     return hipSuccess;

@@ -89,7 +89,7 @@ class hs_plan_info(ctypes.Structure):
                 ("waves_per_tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("multipass_rounds", ctypes.c_int32), ("max_block_chain", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("max_anchors", ctypes.c_int32),
-                ("adjoint_blocks_per_wave", ctypes.c_int32)]
+                ("adjoint_blocks_per_wave", ctypes.c_int32), ("chain_joints", ctypes.c_int64)]
 
 
 class hs_clip_lib(ctypes.Structure):

@@ -116,9 +116,9 @@ def test_chain_of_100k_joints_multipass_stress():
     n = 100_000
     b = _single(np.arange(-1, n - 1), seed=5, angle=0.02)
     plan, G, _ = run_forward(b)
-    # 1562 anchors (the last joints of all 64-joint blocks but the final
-    # one) in one chain: ceil(log2 1562) = 11 anchor rounds
-    assert plan.info["multipass_joints"] == n and plan.info["multipass_rounds"] == 11
+    # a chain: the one-pass path (25 superblocks), no anchor rounds
+    assert plan.info["multipass_joints"] == n == plan.info["chain_joints"]
+    assert plan.info["multipass_rounds"] == 0
     Gr, lam, _ = reference(b)
     # the one check beyond the flat bound: rotation error 1.35e-4 measured
     # here (a 65 536-joint chain stays within 1e-4)
