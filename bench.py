@@ -84,7 +84,7 @@ BYTES_PER_JOINT = {
     "differentiable": 136,
 }
 DOMINANT = {"differentiable": "bwd_anchor_kernel",
-            "long_chains": "multipass step (mp_local, anchor rounds, mp_out)"}
+            "long_chains": "mp_chain_kernel (one-pass multipass for chains)"}
 # what a --pmc dispatch's kernel name must contain to be the dominant
 # kernel: the differentiable run also times the dense route, whose adjoint
 # is the other instance of the same template
@@ -92,7 +92,9 @@ PMC_MATCH = {"differentiable": ("bwd_anchor_kernel<", ", 2>")}
 # fused workloads: the instance that samples poses in the kernel
 SAMPLE_INSTANCE = ", true"
 # steps of several kernels: HBM traffic per step is the sum over them
-STEP_KERNELS = {"long_chains": [("mp_local_kernel",), ("mp_anchor",), ("mp_out_kernel",)]}
+# (the kernels a step launches; those absent from a run count nothing)
+STEP_KERNELS = {"long_chains": [("mp_chain_kernel",), ("zero_words_kernel",), ("mp_local_kernel",), ("mp_anchor",),
+                                ("mp_out_kernel",)]}
 CHUNK = 8  # at least this many forward passes per captured graph replay
 CKPT_K = 8  # levels between checkpoints in the differentiable form's checkpoint mode
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches
@@ -187,7 +189,7 @@ def summarize_pmc(workload, fetch_csv, write_csv):
                 scan[hit[0]].append(kib)
             elif "copy" in name.lower() and int(row["Dispatch_Id"]) == copy_id:
                 copy = (kib, copy_id)
-        return {"scan": sum(sum(x) / len(x) for x in scan), "copy": copy[0], "copy_dispatch": copy[1]}
+        return {"scan": sum(sum(x) / len(x) for x in scan if x), "copy": copy[0], "copy_dispatch": copy[1]}
 
     # the calibration copy (--calibrate-copy): the first device copy that
     # writes COPY_BYTES (uploads of the workload's inputs come before it,
@@ -567,7 +569,7 @@ def measure(args, name):
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(name),
             "kernel": dominant, "kernel_ms": kernel_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
             "device_copy_GBs": copy_gbs, "frac_of_device_copy": achieved / copy_gbs}
-    if BYTES_PER_JOINT[name] == 108 and name != "long_chains":
+    if BYTES_PER_JOINT[name] == 108:
         # the achievable rate of this access pattern, measured beside it
         probe = stream_probe_gbs(torch, w.hs, N)
         roof["stream_probe_GBs"] = probe

@@ -97,3 +97,19 @@ def test_input_uploads_before_the_calibration_copy_are_skipped(tmp_path, monkeyp
     assert rec["copy_dispatch"] == [7, 7]
     assert rec["copy_fetch_scale"] == 2.0 and rec["copy_write_scale"] == 1.0
     assert rec["write_bytes_per_launch"] == 156.25 * MIB * 1024.0
+
+
+def test_a_multipass_step_sums_its_kernels(tmp_path, monkeypatch):
+    """long_chains: the chain kernel and its word-clearing launch are one
+    step (their averages add); multipass kernels absent from the run count
+    nothing."""
+    copy = "__amd_rocclr_copyBuffer"
+    chain = "void hs::mp_chain_kernel<false>(hs::ChainLaunch, hs::PoseArgs, hs::OutArgs)"
+    zero = "hs::zero_words_kernel(int*, int)"
+    fetch = [(1, copy, 128.0 * MIB), (2, zero, 0.0), (3, chain, 100.0 * MIB), (4, zero, 2.0),
+             (5, chain, 102.0 * MIB)]
+    write = [(1, copy, 256.0 * MIB), (2, zero, 4.0), (3, chain, 300.0 * MIB), (4, zero, 4.0),
+             (5, chain, 300.0 * MIB)]
+    rec = run(tmp_path, monkeypatch, "long_chains", fetch, write)
+    assert rec["fetch_bytes_per_launch"] == (101.0 * MIB + 1.0) * 1024.0 * 2.0
+    assert rec["write_bytes_per_launch"] == (300.0 * MIB + 4.0) * 1024.0
