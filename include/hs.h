@@ -89,7 +89,9 @@ void hs_context_destroy(hs_context *ctx);
  * 64-joint blocks -- instancing, strategy and schedule options) holding
  * the chosen launch shape:
  *   {"version": 1, "entries": {"<key>": {"tile_cap": 2048, "waves": 16,
- *    "grid_per_cu": 0, "chain_units": 0, "queue_waves": 4}, ...}}
+ *    "grid_per_cu": 0, "chain_units": 0, "queue_waves": 4, "queue_per_tile": 0}, ...}}
+ * (queue_per_tile 1: the work queue with one workgroup per tile instead of
+ * the resident workgroups looping over the tiles; absent means 0)
  * hs_context_load_tuning merges a file's entries into the context's cache
  * (a missing file is HS_OK with nothing loaded; a malformed one is
  * HS_ERR_INVALID_ARG with the cache unchanged); plans created with

@@ -8,6 +8,7 @@ import os
 
 import numpy as np
 import pytest
+import torch
 
 from paper_2505_06703_amd import hs
 from paper_2505_06703_amd import workloads as wl
@@ -29,7 +30,7 @@ def test_save_then_load_gives_the_stored_shape(tmp_path):
     assert data["version"] == 1 and len(data["entries"]) == 1
     (key, shape), = data["entries"].items()
     assert key.startswith("gfx950|")
-    assert set(shape) == {"tile_cap", "waves", "grid_per_cu", "chain_units", "queue_waves"}
+    assert set(shape) == {"tile_cap", "waves", "grid_per_cu", "chain_units", "queue_waves", "queue_per_tile"}
     assert tuned.info["tile_joints"] == shape["tile_cap"]
     # an unusual but valid shape under the same key: a fresh context that
     # loads it must build exactly that shape instead of timing candidates
@@ -40,8 +41,21 @@ def test_save_then_load_gives_the_stored_shape(tmp_path):
     p = hs.Plan(b.offsets, b.parents, ctx=c, autotune=True)
     assert p.info["tile_joints"] == 2048 and p.info["waves_per_tile"] == 2
     assert p.info["schedule"] == hs.HS_SCHED_QUEUE
-    tuned.close(), p.close()
-    a.close(), c.close()
+    # one workgroup per tile (entries without queue_per_tile read as 0: the
+    # resident workgroups loop over the tiles)
+    data["entries"][key]["queue_per_tile"] = 1
+    path.write_text(json.dumps(data))
+    d = hs.Context(0)
+    d.load_tuning(path)
+    p2 = hs.Plan(b.offsets, b.parents, ctx=d, autotune=True)
+    assert p2.info["grid"] == p2.info["num_tiles"]
+    q, t, s = (torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0") for x in (b.quat, b.trans, b.scale))
+    G1, _ = hs.hs_scan_forward(p, q, t, s)
+    G2, _ = hs.hs_scan_forward(p2, q, t, s)
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2)  # the same tiles, whichever workgroup takes them
+    tuned.close(), p.close(), p2.close()
+    a.close(), c.close(), d.close()
 
 
 def test_missing_and_malformed_files(tmp_path):
@@ -65,7 +79,8 @@ def test_missing_and_malformed_files(tmp_path):
     c.load_tuning(ok)
     c.save_tuning(out)
     assert json.loads(out.read_text())["entries"] == {
-        "gfx950|x": {"tile_cap": 1024, "waves": 8, "grid_per_cu": 0, "chain_units": 0, "queue_waves": 0}}
+        "gfx950|x": {"tile_cap": 1024, "waves": 8, "grid_per_cu": 0, "chain_units": 0, "queue_waves": 0,
+                     "queue_per_tile": 0}}
     c.close()
 
 
