@@ -89,9 +89,7 @@ void hs_context_destroy(hs_context *ctx);
  * 64-joint blocks -- instancing, strategy and schedule options) holding
  * the chosen launch shape:
  *   {"version": 1, "entries": {"<key>": {"tile_cap": 2048, "waves": 16,
- *    "grid_per_cu": 0, "chain_units": 0, "queue_waves": 4, "queue_per_tile": 0}, ...}}
- * (queue_per_tile 1: the work queue with one workgroup per tile instead of
- * the resident workgroups looping over the tiles; absent means 0)
+ *    "grid_per_cu": 0, "chain_units": 0, "queue_waves": 4}, ...}}
  * hs_context_load_tuning merges a file's entries into the context's cache
  * (a missing file is HS_OK with nothing loaded; a malformed one is
  * HS_ERR_INVALID_ARG with the cache unchanged); plans created with
@@ -144,12 +142,14 @@ typedef struct hs_plan_opts {
 } hs_plan_opts;
 
 /* Forward schedules (hs_scan_forward; the other tiled calls keep the size
- * classes).  HS_SCHED_QUEUE: every tile of the plan in one persistent
- * launch (as many workgroups as fit the CUs at once) that walks the plan's
- * heaviest-first tile list with a static stride; LDS holds only the
- * transforms of each tile's anchors (joints whose children lie in another
- * 64-joint block) and one staging slice per wave, so large tiles do not
- * cost occupancy.  HS_SCHED_CLASSES:
+ * classes).  HS_SCHED_QUEUE: every tile of the plan in one launch over the
+ * plan's heaviest-first tile list: one workgroup per tile (grid_tiles 0,
+ * the hardware dispatching them as CUs free up), or at most grid_tiles
+ * resident workgroups per CU, each walking the list with a static stride;
+ * LDS holds only the transforms of each tile's anchors (joints whose
+ * children lie in another 64-joint block) and one staging slice per wave,
+ * so large tiles do not cost occupancy.  Without tile_joints the queue's
+ * tiles hold the largest character, at least 256 joints.  HS_SCHED_CLASSES:
  * one launch per size class (characters of up to 1024 joints, up to 1664,
  * the rest) with all of a tile's transforms in LDS.  HS_SCHED_AUTO takes the
  * queue where it applies (the library's scan, no chain units, not

@@ -122,8 +122,7 @@ struct Shape {
     int algorithm = HS_ALG_SCAN;
     int adjoint = HS_ADJ_ROUNDS;
     int queue_waves = 0;  // > 0: the forward runs as one work-queue launch with this many waves
-    bool queue_per_tile = false;  // work queue: one workgroup per tile (the hardware dispatches them as
-                                  // CUs free up) instead of the resident workgroups looping
+    int queue_cap = 0;    // work queue: tile capacity when it differs from tile_cap (0: tile_cap)
 };
 
 } // namespace
@@ -223,8 +222,7 @@ bool parse_shape(JsonReader &r, Shape &sh)
         std::string k;
         long long v = 0;
         if (!r.str(k) || !r.eat(':')) return false;
-        if (k == "tile_cap" || k == "waves" || k == "grid_per_cu" || k == "chain_units" || k == "queue_waves" ||
-            k == "queue_per_tile") {
+        if (k == "tile_cap" || k == "waves" || k == "grid_per_cu" || k == "chain_units" || k == "queue_waves") {
             if (!r.integer(v)) return false;
             if (k == "tile_cap") {
                 if (v < 64 || v > hs::kMaxTileJoints || v % 64) return false;
@@ -238,7 +236,7 @@ bool parse_shape(JsonReader &r, Shape &sh)
                 sh.grid_per_cu = (int)v;
             } else {
                 if (v != 0 && v != 1) return false;
-                (k == "chain_units" ? sh.chain_units : sh.queue_per_tile) = v != 0;
+                sh.chain_units = v != 0;
             }
         } else if (!r.skip()) {
             return false;
@@ -293,10 +291,8 @@ std::string format_tuning(const std::map<std::string, Shape> &tuned)
         }
         const Shape &sh = kv.second;
         snprintf(buf, sizeof buf,
-                 "\"tile_cap\": %d, \"waves\": %d, \"grid_per_cu\": %d, \"chain_units\": %d, \"queue_waves\": %d, "
-                 "\"queue_per_tile\": %d",
-                 sh.tile_cap, sh.waves, sh.grid_per_cu, sh.chain_units ? 1 : 0, sh.queue_waves,
-                 sh.queue_per_tile ? 1 : 0);
+                 "\"tile_cap\": %d, \"waves\": %d, \"grid_per_cu\": %d, \"chain_units\": %d, \"queue_waves\": %d",
+                 sh.tile_cap, sh.waves, sh.grid_per_cu, sh.chain_units ? 1 : 0, sh.queue_waves);
         o += (first ? "\n  \"" : ",\n  \"") + key + "\": {" + buf + "}";
         first = false;
     }
@@ -873,7 +869,7 @@ hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *bui
     Q.d_tiles = nullptr;
     Q.d_code = nullptr;
     Q.num_tiles = Q.grid = Q.max_anchors = 0;
-    const int cap = shape.tile_cap;
+    const int cap = shape.queue_cap > 0 ? shape.queue_cap : shape.tile_cap;
     const Packing pk = pack_tiles(plan, cap, strategy, false, 0, cap);
     std::vector<hs::QTile> qt(pk.tiles.size());
     std::vector<int32_t> code((size_t)plan->N, 0), slot;
@@ -908,10 +904,14 @@ hs_status build_queue(hs_plan *plan, const Shape &shape, int strategy, bool *bui
             const size_t lds = hs::forward_queue_lds_bytes(waves, max_anchors, cap, smp != 0, skin != 0);
             if ((err = hs::queue_blocks_per_cu(waves, smp != 0, skin != 0, lds, &per_cu)) != hipSuccess)
                 return fail_hip(err, "hs_plan_create (work-queue occupancy)");
-            per_cu = std::max(1, shape.grid_per_cu > 0 ? std::min(per_cu, shape.grid_per_cu) : per_cu);
+            // grid_per_cu 0: one workgroup per tile, dispatched by the
+            // hardware as CUs free up; k > 0: at most k resident workgroups
+            // per CU, each walking the list
+            per_cu = std::max(1, std::min(per_cu, std::max(1, shape.grid_per_cu)));
             Q.grids[smp][skin] =
-                (int32_t)std::max<int64_t>(1, std::min<int64_t>(Q.num_tiles, (int64_t)per_cu * plan->ctx->num_cu));
-            if (shape.queue_per_tile) Q.grids[smp][skin] = std::max<int32_t>(1, Q.num_tiles);
+                shape.grid_per_cu > 0
+                    ? (int32_t)std::max<int64_t>(1, std::min<int64_t>(Q.num_tiles, (int64_t)per_cu * plan->ctx->num_cu))
+                    : std::max<int32_t>(1, Q.num_tiles);
         }
     Q.grid = Q.grids[0][0];
     *built = true;
@@ -1069,6 +1069,7 @@ hs_status build_tables(hs_plan *plan, const Shape &shape, int strategy)
         I.schedule = HS_SCHED_QUEUE;
         I.max_anchors = plan->q.max_anchors;
         I.num_tiles = plan->q.num_tiles;
+        I.tile_joints = plan->q.cap;
         I.waves_per_tile = plan->q.waves;
         I.grid = plan->q.grid;
     } else if (plan->sched_opt == HS_SCHED_QUEUE) {
@@ -1290,19 +1291,19 @@ hs_status autotune(hs_plan *plan, const Shape &base, int strategy)
     std::vector<Shape> cands;
     const int min_cap = round_up(std::max(1, plan->info.max_character), 64);
     if (base.queue_waves > 0) {
-        // the work queue: tile size and waves; the resident workgroups
-        // looping over the tiles, or one workgroup per tile (measured on
-        // the heterogeneous batch: 180.5 against 175.7 us)
+        // the work queue: tile size and waves; one workgroup per tile, or
+        // the resident workgroups looping over the tiles (measured on the
+        // heterogeneous batch: 175.7 against 180.5 us)
         for (int cap : {256, 512, 1024, 2048, 3072}) {
             if (cap < min_cap && strategy == HS_STRATEGY_TILE) continue;
             for (int w : {2, 4, 8, 16}) {
                 if (w * 64 > cap) continue;
-                for (bool per_tile : {false, true}) {
+                for (int g : {0, 64}) {
                     Shape c = base;
                     c.tile_cap = cap;
+                    c.queue_cap = 0;
                     c.queue_waves = w;
-                    c.queue_per_tile = per_tile;
-                    c.grid_per_cu = 0;
+                    c.grid_per_cu = g;
                     while (c.waves > 1 && c.waves * 64 > cap) c.waves >>= 1;  // the size-class tiles' waves
                     cands.push_back(c);
                 }
@@ -1731,8 +1732,14 @@ hs_status create_plan(hs_context *ctx, const hs_batch *batch, const hs_plan_opts
         // four waves (measured against eight and sixteen on the deep,
         // heterogeneous and fused workloads: more workgroups per CU), fewer
         // on tiles of fewer blocks
+        // default tiles: the largest character's size, at least 256 joints
+        // (one workgroup per tile; measured on 10 000 x 256 joints with
+        // sampled poses: 88.4 us on 256-joint tiles against 93.9 us on
+        // 1024-joint ones)
+        if (o.tile_joints == 0 && sh.tile_cap > 256) sh.queue_cap = std::max(256, std::min(min_cap, sh.tile_cap));
+        const int qcap = sh.queue_cap > 0 ? sh.queue_cap : sh.tile_cap;
         int w = o.waves_per_tile > 0 ? o.waves_per_tile : 4;
-        while (w > 1 && w * 64 > sh.tile_cap) w >>= 1;
+        while (w > 1 && w * 64 > qcap) w >>= 1;
         sh.queue_waves = w;
     }
     if (sh.algorithm != HS_ALG_SCAN) {

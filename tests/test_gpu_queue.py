@@ -46,19 +46,25 @@ def test_heterogeneous_reduced_queue(shape):
     check_global(G, Gr, lam, f"heterogeneous queue {shape}")
 
 
-def test_heterogeneous_full_size_one_launch():
+@pytest.mark.parametrize("grid_tiles", [0, 64])
+def test_heterogeneous_full_size_one_launch(grid_tiles):
+    """One workgroup per tile (the default), and the resident workgroups
+    (at most grid_tiles per CU) looping over the heaviest-first list."""
     b = wl.heterogeneous()
-    plan, G, _ = forward(b)
+    plan, G, _ = forward(b, grid_tiles=grid_tiles)
     info = plan.info
     assert info["schedule"] == hs.HS_SCHED_QUEUE and info["multipass_joints"] == 0
-    assert info["grid"] < info["num_tiles"]  # persistent workgroups loop over the queue
+    if grid_tiles == 0:
+        assert info["grid"] == info["num_tiles"]
+    else:
+        assert info["grid"] < info["num_tiles"]  # persistent workgroups loop over the queue
     rng = np.random.default_rng(11)
     n = np.diff(b.offsets)
     chains = np.nonzero(b.extra["is_chain"])[0]
     chars = np.unique(np.concatenate([rng.choice(b.num_characters, 40, replace=False), chains[:8],
                                       [int(np.argmax(n)), int(np.argmin(n)), 0, b.num_characters - 1]]))
     Gr, lam, ids = reference(b, chars=chars)
-    check_global(G[ids], Gr, lam, "heterogeneous full, one launch (sampled)")
+    check_global(G[ids], Gr, lam, f"heterogeneous full, one launch, grid_tiles {grid_tiles} (sampled)")
 
 
 def test_deep_forward_queue_bitwise_equals_size_classes():
@@ -141,7 +147,7 @@ def test_fused_sample_and_checkpoints_queue():
 
 def test_repeated_launches_and_graph_replays_cover_every_tile():
     b = wl.heterogeneous(num_characters=400, seed=9)
-    plan = hs.Plan(b.offsets, b.parents, schedule=hs.HS_SCHED_QUEUE, tile_joints=1024)
+    plan = hs.Plan(b.offsets, b.parents, schedule=hs.HS_SCHED_QUEUE, tile_joints=1024, grid_tiles=1)
     assert plan.info["grid"] <= plan.info["num_tiles"]
     q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
     G0, _ = hs.hs_scan_forward(plan, q, t, s)

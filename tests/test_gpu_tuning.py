@@ -30,7 +30,7 @@ def test_save_then_load_gives_the_stored_shape(tmp_path):
     assert data["version"] == 1 and len(data["entries"]) == 1
     (key, shape), = data["entries"].items()
     assert key.startswith("gfx950|")
-    assert set(shape) == {"tile_cap", "waves", "grid_per_cu", "chain_units", "queue_waves", "queue_per_tile"}
+    assert set(shape) == {"tile_cap", "waves", "grid_per_cu", "chain_units", "queue_waves"}
     assert tuned.info["tile_joints"] == shape["tile_cap"]
     # an unusual but valid shape under the same key: a fresh context that
     # loads it must build exactly that shape instead of timing candidates
@@ -41,14 +41,14 @@ def test_save_then_load_gives_the_stored_shape(tmp_path):
     p = hs.Plan(b.offsets, b.parents, ctx=c, autotune=True)
     assert p.info["tile_joints"] == 2048 and p.info["waves_per_tile"] == 2
     assert p.info["schedule"] == hs.HS_SCHED_QUEUE
-    # one workgroup per tile (entries without queue_per_tile read as 0: the
-    # resident workgroups loop over the tiles)
-    data["entries"][key]["queue_per_tile"] = 1
+    # the resident workgroups looping over the tiles (grid_per_cu > 0)
+    data["entries"][key]["grid_per_cu"] = 1
     path.write_text(json.dumps(data))
     d = hs.Context(0)
     d.load_tuning(path)
     p2 = hs.Plan(b.offsets, b.parents, ctx=d, autotune=True)
-    assert p2.info["grid"] == p2.info["num_tiles"]
+    assert p.info["grid"] == p.info["num_tiles"]  # grid_per_cu 0: one workgroup per tile
+    assert p2.info["grid"] == min(p2.info["num_tiles"], torch.cuda.get_device_properties(0).multi_processor_count)
     q, t, s = (torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0") for x in (b.quat, b.trans, b.scale))
     G1, _ = hs.hs_scan_forward(p, q, t, s)
     G2, _ = hs.hs_scan_forward(p2, q, t, s)
@@ -79,8 +79,7 @@ def test_missing_and_malformed_files(tmp_path):
     c.load_tuning(ok)
     c.save_tuning(out)
     assert json.loads(out.read_text())["entries"] == {
-        "gfx950|x": {"tile_cap": 1024, "waves": 8, "grid_per_cu": 0, "chain_units": 0, "queue_waves": 0,
-                     "queue_per_tile": 0}}
+        "gfx950|x": {"tile_cap": 1024, "waves": 8, "grid_per_cu": 0, "chain_units": 0, "queue_waves": 0}}
     c.close()
 
 
