@@ -361,8 +361,7 @@ struct MPSet {
     hs::ChainSB *d_csb = nullptr;
     int32_t num_csb = 0;
     int64_t chain_joints = 0;
-    float4 *c_sbagg = nullptr, *c_sbinc = nullptr;
-    int32_t *c_words = nullptr;
+    uint64_t *c_recs = nullptr;
     int32_t c_grid[2] = {0, 0};
 };
 
@@ -382,9 +381,7 @@ void free_mpset(MPSet &m)
     (void)hipFree(m.G);
     (void)hipFree(m.d_cblocks);
     (void)hipFree(m.d_csb);
-    (void)hipFree(m.c_sbagg);
-    (void)hipFree(m.c_sbinc);
-    (void)hipFree(m.c_words);
+    (void)hipFree(m.c_recs);
     m = MPSet{};
 }
 
@@ -747,9 +744,7 @@ hs_status make_chains(MPSet &m, const hs_plan *plan, const Packing &pk)
     const size_t ns = (size_t)m.num_csb;
     hipError_t err = upload(&m.d_cblocks, cb);
     if (err == hipSuccess) err = upload(&m.d_csb, sbs);
-    if (err == hipSuccess) err = hipMalloc(&m.c_sbagg, ns * 3 * sizeof(float4));
-    if (err == hipSuccess) err = hipMalloc(&m.c_sbinc, ns * 3 * sizeof(float4));
-    if (err == hipSuccess) err = hipMalloc(&m.c_words, ns * sizeof(int32_t));
+    if (err == hipSuccess) err = hipMalloc(&m.c_recs, ns * 12 * sizeof(uint64_t));
     if (err != hipSuccess) return fail_hip(err, "hs_plan_create (chain workspace)");
     return HS_OK;
 }
@@ -1145,9 +1140,7 @@ hs::ChainLaunch chain_launch(const hs_plan *p, bool sample, bool validate = fals
     cl.sbs = m.d_csb;
     cl.num_sb = m.num_csb;
     cl.grid = m.c_grid[sample ? 1 : 0];
-    cl.sbagg = m.c_sbagg;
-    cl.sbinc = m.c_sbinc;
-    cl.words = m.c_words;
+    cl.recs = m.c_recs;
     cl.status = p->d_status;
     cl.spin_limit = p->spin_limit;
     cl.gate = validate ? p->d_status : nullptr;

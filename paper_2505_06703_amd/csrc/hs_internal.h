@@ -191,9 +191,8 @@ struct ChainLaunch {
     const ChainSB *sbs;
     int32_t num_sb;
     int32_t grid;      // workgroups, all resident at once
-    float4 *sbagg;     // [superblocks][3] each superblock's product of its local transforms
-    float4 *sbinc;     // [superblocks][3] G of each superblock's last joint
-    int32_t *words;    // [superblocks] published: 1 the product, 2 the final transform; zeroed per call
+    uint64_t *recs;    // [superblocks][12] tagged words: the product of the superblock's local
+                       // transforms (tag 1), then G of its last joint (tag 2); zeroed per call
     uint32_t *status;
     int32_t spin_limit;
     const uint32_t *gate;

@@ -2927,94 +2927,102 @@ mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 
 
 // ---------------------------------------------------------------------------
 // One pass for chain characters beyond a tile (every joint's parent the
-// previous joint): a reduce-then-scan over superblocks of up to 64
-// consecutive 64-joint blocks of one chain, one superblock per workgroup
-// at a time (16 waves, four blocks each).  Each wave scans its blocks (the
-// in-block rounds, lane = joint) and keeps every joint's product P_j from
-// its block's first joint in registers; the blocks' totals meet in LDS,
-// where one wave scans them (lane = block), publishes the superblock's
-// total, looks back over the chain's earlier superblocks (lane =
-// superblock: the nearest final transform and the totals after it,
-// composed by the same scan) for the transform entering the superblock,
-// publishes its final transform, and leaves in LDS the transform entering
-// each block; then G_j = (transform entering its block) P_j leaves as
-// coalesced rows.  Each pose is read once.  Workgroups take superblocks in
-// increasing order (a static stride; the launch holds no more workgroups
-// than are resident at once), and a superblock publishes its total before
-// it looks back, so the look-backs only wait for publications that need
-// no waiting.  Values cross workgroups as agent-scope atomic stores and
-// loads (coherent across the XCDs' L2s), each publication's stores
-// complete before its flag is stored.
+// previous joint): a reduce-then-scan over superblocks of up to 4096
+// consecutive joints of one chain (64 blocks of the plan's 64-joint
+// blocks), one superblock per workgroup at a time.  Each of the 16 waves
+// takes a segment of 256 consecutive joints, four per lane: the lane
+// multiplies its four local transforms in order (Q_i = L_0 ... L_i), the
+// wave scans the lanes' products (pointer jumping over lane - 1, six rounds
+// for 256 joints) and keeps each lane's exclusive prefix W.  The segments'
+// totals meet in LDS, where one wave scans them (lane = segment),
+// publishes the superblock's total, looks back over the chain's earlier
+// superblocks (lane = superblock: the nearest final transform and the
+// totals after it, composed by the same scan) for the transform entering
+// the superblock, publishes its final transform, and leaves in LDS the
+// transform entering each segment E; then G = (E W) Q_i, staged in LDS a
+// 64-joint row group at a time and stored as coalesced rows.  Each pose is
+// read once.  Workgroups take superblocks in increasing order (a static
+// stride; the launch holds no more workgroups than are resident at once),
+// and a superblock publishes its total before it looks back, so the
+// look-backs only wait for publications that need no waiting.  Values
+// cross workgroups as agent-scope atomic stores and loads (coherent across
+// the XCDs' L2s), each publication's stores complete before its flag is
+// stored.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void store_agent12(float4 *dst, const float m[12])
+// A superblock's record: 12 words, each a 32-bit value with its tag in the
+// high half (0 not published, 1 the superblock's total, 2 the final
+// transform), written as single 8-byte agent-scope stores (coherent across
+// the XCDs' L2s).  A word read is then both the value and its own flag: a
+// reader takes the record when all 12 tags agree, and reads again while
+// they do not (not yet published, or a total being overwritten by the
+// final transform), so no store has to complete before another.
+// m: the 12 values in LDS (an affine row block); lane k < 12 stores word k.
+__device__ __forceinline__ void publish12(uint64_t *rec, const float4 *m, unsigned tag, int lane)
 {
-    unsigned *d = reinterpret_cast<unsigned *>(dst);
+    if (lane < 12) {
+        const float v = reinterpret_cast<const float *>(m)[lane];
+        __hip_atomic_store(rec + lane, ((uint64_t)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The record's tag when its 12 tags agree, else 0; the values in m.
+__device__ __forceinline__ unsigned read12(uint64_t *rec, float m[12])
+{
+    uint64_t w[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k)
-        __hip_atomic_store(d + k, __float_as_uint(m[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void load_agent12(const float4 *src, float m[12])
-{
-    unsigned *s = reinterpret_cast<unsigned *>(const_cast<float4 *>(src));
+    for (int k = 0; k < 12; ++k) w[k] = __hip_atomic_load(rec + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned tag = (unsigned)(w[0] >> 32);
+    bool same = true;
 #pragma unroll
-    for (int k = 0; k < 12; ++k)
-        m[k] = __uint_as_float(__hip_atomic_load(s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    for (int k = 0; k < 12; ++k) {
+        same &= (unsigned)(w[k] >> 32) == tag;
+        m[k] = __uint_as_float((unsigned)w[k]);
+    }
+    return same ? tag : 0u;
 }
 
-// Every store the wave has issued is complete (at agent scope) before what
-// follows: the memory counter of gfx9 waves counts stores too.
-__device__ __forceinline__ void stores_done()
+// Wave 0 of the workgroup resolving superblock s: T [nt][3] the segments'
+// totals (in; T[nt - 1] then holds the superblock's total), E [nt][3] the
+// transforms entering the segments (out; first the products of the earlier
+// segments' totals); X, xi the wave's scan slice.
+__device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s, const ChainSB &sb, int nt, int lane,
+                                                   float4 *T, float4 *E, float4 *X, int *xi)
 {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt not waited for
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-constexpr int kChainBlocksPerWave = 4;  // 16 waves x 4 blocks = a superblock of 64 blocks
-
-// Wave 0 of the workgroup resolving superblock s: T [64][3] the blocks'
-// totals (in), E [64][3] the transforms entering the blocks (out); X, xi
-// the wave's scan slice.
-__device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s, const ChainSB &sb, int lane,
-                                                   const float4 *T, float4 *E, float4 *X, int *xi)
-{
-    int *pub = cl.words;
-    // inclusive products of the blocks' totals, in chain order (lane = block)
-    const bool in = lane < sb.nblk;
-    float x[12];
-    if (in) aff_load(T + 3 * lane, x);
-    else aff_identity(x);
-    int a = in && lane > 0 ? lane - 1 : -1, e = -1;
-    wave_inblock_scan_lds(x, a, e, lane, X, xi);
-    aff_store(X + 3 * lane, x);
-    wave_sync();
-    float tot[12], xex[12];
-    aff_load(X + 3 * (sb.nblk - 1), tot);  // the superblock's total
-    if (lane > 0) aff_load(X + 3 * (lane - 1), xex);
-    else aff_identity(xex);
-    wave_sync();  // the slice is free
+    // inclusive products of the segments' totals, in chain order (lane = segment)
+    const bool in = lane < nt;
+    {
+        float x[12];
+        if (in) aff_load(T + 3 * lane, x);
+        else aff_identity(x);
+        int a = in && lane > 0 ? lane - 1 : -1, e = -1;
+        wave_inblock_scan_lds(x, a, e, lane, X, xi);
+        aff_store(X + 3 * lane, x);
+        wave_sync();
+        if (lane == nt - 1) aff_store(T + 3 * lane, x);  // the superblock's total
+        if (in) {
+            if (lane > 0) aff_load(X + 3 * (lane - 1), x);
+            else aff_identity(x);
+            aff_store(E + 3 * lane, x);
+        }
+        wave_sync();  // the slice is free; T and E written
+    }
     float acc[12];  // the transform entering the superblock
     aff_identity(acc);
+    uint64_t *rec = cl.recs + 12 * (int64_t)s;
+    float4 *tot = T + 3 * (nt - 1);
     if (s == sb.chain_first) {
-        if (lane == 0) {
-            store_agent12(cl.sbinc + 3 * s, tot);
-            stores_done();
-            __hip_atomic_store(pub + s, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        publish12(rec, tot, 2, lane);
     } else {
-        if (lane == 0) {
-            store_agent12(cl.sbagg + 3 * s, tot);
-            stores_done();
-            __hip_atomic_store(pub + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        publish12(rec, tot, 1, lane);
         // look back, 64 superblocks at a time (lane k: superblock base - k)
         for (int base = s - 1;; base -= kWave) {
             const int q = base - lane;
             const bool lv = q >= sb.chain_first;
-            int st = 2;
+            unsigned st = 2;
+            float v[12];
             for (int spin = 0;; ++spin) {
-                st = lv ? __hip_atomic_load(pub + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 2;
+                if (lv) st = read12(cl.recs + 12 * (int64_t)q, v);
                 if (__all(st > 0)) break;
                 if (spin >= cl.spin_limit) {
                     note_status(cl.status, kStatusWaitTimeout);
@@ -3023,14 +3031,11 @@ __device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s,
                 }
                 __builtin_amdgcn_s_sleep(2);
             }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             // the nearest final transform (the chain's first superblock always is one)
             const unsigned long long fin = __ballot(lv && st == 2);
             const int kf = fin ? __ffsll((long long)fin) - 1 : -1;
             const int nv = min(kWave, base - sb.chain_first + 1);  // lanes inside the chain
-            float v[12];
-            if (lane < nv && (kf < 0 || lane <= kf)) load_agent12((lane == kf ? cl.sbinc : cl.sbagg) + 3 * q, v);
-            else aff_identity(v);
+            if (!(lane < nv && (kf < 0 || lane <= kf))) aff_identity(v);
             const int top = kf >= 0 ? kf : nv - 1;  // the window's earliest superblock taken
             int pa = lane < top ? lane + 1 : -1, pe = -1;
             wave_inblock_scan_lds(v, pa, pe, lane, X, xi);  // lane 0: v(top) ... v(0)
@@ -3042,92 +3047,166 @@ __device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s,
             aff_mul_left(w, acc);  // acc = w acc
             if (kf >= 0) break;    // uniform
         }
-        if (lane == 0) {
-            float inc[12];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) inc[k] = tot[k];
-            aff_mul_left(acc, inc);
-            store_agent12(cl.sbinc + 3 * s, inc);
-            stores_done();
-            __hip_atomic_store(pub + s, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        float inc[12];
+        aff_load(tot, inc);
+        aff_mul_left(acc, inc);
+        wave_sync();  // every lane has read the total
+        if (lane == 0) aff_store(tot, inc);
+        wave_sync();
+        publish12(rec, tot, 2, lane);
     }
-    aff_mul_left(acc, xex);  // the transform entering block `lane`
-    if (in) aff_store(E + 3 * lane, xex);
+    if (in) {
+        float x[12];
+        aff_load(E + 3 * lane, x);
+        aff_mul_left(acc, x);  // the transform entering segment `lane`
+        aff_store(E + 3 * lane, x);
+    }
+}
+
+constexpr int kChainPerLane = 2;                          // consecutive joints per lane
+constexpr int kChainSeg = kChainPerLane * kWave;          // joints per segment
+constexpr int kChainSegPerWave = 2;                       // a wave's segments: wave, wave + 16
+constexpr int kChainSegs = kChainWaves * kChainSegPerWave;  // segments per superblock
+static_assert(kChainSegs * kChainSeg == 64 * 64, "a superblock is 64 blocks of 64 joints");
+static_assert(kChainSegs <= kWave, "the segments' totals are scanned by one wave");
+
+// LDS of the chain kernel, in float4: per wave a slice of one segment's
+// rows (the two segments' lane products after the forward half, then the
+// staging of the rows), wave 0's parked products, the resolving wave's
+// scan slice, the segments' totals and entering transforms, and the scans'
+// int words (16 waves and the resolving wave).
+constexpr int kChainSlice = kChainSeg * 3;
+constexpr size_t kChainLdsF4 = (size_t)kChainWaves * kChainSlice + kChainSegPerWave * kChainPerLane * kWave * 3 +
+                               kWave * 3 + 2 * kChainSegs * 3 + (kChainWaves + 1) * kWave / 4;
+constexpr size_t kChainLdsBytes = kChainLdsF4 * sizeof(float4);
+
+// The local transform of joint gid, the pose read with plain loads (a
+// lane's joints share cache lines with its neighbours').
+template <bool SAMPLE>
+__device__ __forceinline__ void load_local_lane(const PoseArgs &P, int64_t gid, int chr, int lj, float m[12])
+{
+    if constexpr (SAMPLE) {
+        float4 q;
+        float tx, ty, tz;
+        sample_pose(P, chr, lj, q, tx, ty, tz);
+        aff_from_trs(q, tx, ty, tz, 1.0f, 1.0f, 1.0f, m);
+    } else {
+        const float4 q = reinterpret_cast<const float4 *>(P.quat)[gid];
+        const float *t = P.trans + 3 * gid;
+        float sx = 1.0f, sy = 1.0f, sz = 1.0f;
+        if (P.scale) {
+            const float *sp = P.scale + 3 * gid;
+            sx = sp[0];
+            sy = sp[1];
+            sz = sp[2];
+        }
+        aff_from_trs(q, t[0], t[1], t[2], sx, sy, sz, m);
+    }
 }
 
 template <bool SAMPLE>
 __global__ void __launch_bounds__(kChainWaves * kWave)
 mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
 {
-    __shared__ float4 slice[kChainWaves * kWave * 3];
-    __shared__ float4 T[kWave * 3], E[kWave * 3];
-    __shared__ float4 PS[kChainBlocksPerWave * kWave * 3];  // wave 0's products while it resolves
-    __shared__ int xs[kChainWaves * kWave];
+    extern __shared__ float4 lds[];
     if (gated(cl.gate)) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    float4 *X = slice + wv * kWave * 3;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform: branches on it stay scalar
+    float4 *X = lds + wv * kChainSlice;                     // the wave's slice
+    float4 *PS = lds + kChainWaves * kChainSlice;           // wave 0's products while it resolves
+    float4 *R = PS + kChainSegPerWave * kChainPerLane * kWave * 3;  // the resolving wave's scan slice
+    float4 *T = R + kWave * 3;                              // [segments][3] totals
+    float4 *E = T + kChainSegs * 3;                         // [segments][3] entering transforms
+    int *xs = reinterpret_cast<int *>(E + kChainSegs * 3);  // [17][64]
     int *xi = xs + wv * kWave;
     const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    const int j0 = kChainPerLane * lane;  // the lane's first joint in a segment
     for (int s = blockIdx.x; s < cl.num_sb; s += gridDim.x) {  // uniform per workgroup
         const ChainSB sb = cl.sbs[s];
-        // the wave's blocks: k = wave + 16 i
-        float P[kChainBlocksPerWave][12];
+        const ChainBlock b0 = cl.blocks[sb.first];
+        const int cnt = kWave * (sb.nblk - 1) + cl.blocks[sb.first + sb.nblk - 1].count;
+        const int nt = (cnt + kChainSeg - 1) / kChainSeg;  // segments holding joints
+        int lj0 = 0;
+        if constexpr (SAMPLE) lj0 = (int)(b0.gbegin - pose.offsets[b0.chr]);
+        float Q[kChainSegPerWave][kChainPerLane][12];
 #pragma unroll
-        for (int i = 0; i < kChainBlocksPerWave; ++i) {
-            const int k = wv + kChainWaves * i;
-            if (k >= sb.nblk) break;  // uniform per wave
-            const ChainBlock cb = cl.blocks[sb.first + k];
-            const bool valid = lane < cb.count;
-            const int64_t gid = cb.gbegin + lane;
-            if (valid) {
-                int lj = 0;
-                if constexpr (SAMPLE) lj = (int)(gid - pose.offsets[cb.chr]);
-                load_local<SAMPLE>(pose, gid, cb.chr, lj, P[i]);
-            } else {
-                aff_identity(P[i]);
+        for (int h = 0; h < kChainSegPerWave; ++h) {
+            const int gs = wv + kChainWaves * h;               // the segment
+            const int n = min(kChainSeg, cnt - gs * kChainSeg);  // its joints (<= 0: none)
+            if (n <= 0) break;                                 // uniform per wave
+            const int sj = gs * kChainSeg + j0;                // the lane's first joint in the superblock
+#pragma unroll
+            for (int i = 0; i < kChainPerLane; ++i) {
+                if (j0 + i < n) load_local_lane<SAMPLE>(pose, b0.gbegin + sj + i, b0.chr, lj0 + sj + i, Q[h][i]);
+                else aff_identity(Q[h][i]);
+                if (i > 0) aff_mul_left(Q[h][i - 1], Q[h][i]);  // Q_i = L_0 ... L_i
             }
-            int a = valid && lane > 0 ? lane - 1 : -1, e = -1;
-            wave_inblock_scan_lds(P[i], a, e, lane, X, xi);
-            if (lane == cb.count - 1) aff_store(T + 3 * k, P[i]);  // the block's total
+            float x[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) x[k] = Q[h][kChainPerLane - 1][k];
+            int a = lane > 0 && j0 < n ? lane - 1 : -1, e = -1;
+            float4 *Xh = X + h * (kWave * 3);
+            wave_inblock_scan_lds(x, a, e, lane, Xh, xi);  // x: the product over lanes 0..lane
+            aff_store(Xh + 3 * lane, x);                   // read back once E is known
+            if (lane == (n - 1) / kChainPerLane) aff_store(T + 3 * gs, x);  // the segment's total
         }
-        __syncthreads();  // every block's total
+        __syncthreads();  // every segment's total
         if (wv == 0) {
             // the products wait in LDS (registers for the resolution)
 #pragma unroll
-            for (int i = 0; i < kChainBlocksPerWave; ++i) aff_store(PS + 3 * (kWave * i + lane), P[i]);
-            resolve_superblock(cl, s, sb, lane, T, E, X, xi);
+            for (int h = 0; h < kChainSegPerWave; ++h)
 #pragma unroll
-            for (int i = 0; i < kChainBlocksPerWave; ++i) aff_load(PS + 3 * (kWave * i + lane), P[i]);
+                for (int i = 0; i < kChainPerLane; ++i)
+                    aff_store(PS + 3 * (kWave * (kChainPerLane * h + i) + lane), Q[h][i]);
+            resolve_superblock(cl, s, sb, nt, lane, T, E, R, xs + kChainWaves * kWave);
+#pragma unroll
+            for (int h = 0; h < kChainSegPerWave; ++h)
+#pragma unroll
+                for (int i = 0; i < kChainPerLane; ++i)
+                    aff_load(PS + 3 * (kWave * (kChainPerLane * h + i) + lane), Q[h][i]);
         }
-        __syncthreads();  // the transforms entering the blocks
+        __syncthreads();  // the transforms entering the segments
+        // G = (E W) Q_i, W the product over the segment's earlier lanes
 #pragma unroll
-        for (int i = 0; i < kChainBlocksPerWave; ++i) {
-            const int k = wv + kChainWaves * i;
-            if (k >= sb.nblk) break;
-            const ChainBlock cb = cl.blocks[sb.first + k];
-            const int64_t gid = cb.gbegin + lane;
-            float g[12];
-            aff_load(E + 3 * k, g);
-            aff_mul_left(g, P[i]);
+        for (int h = 0; h < kChainSegPerWave; ++h) {
+            const int gs = wv + kChainWaves * h;
+            if (gs * kChainSeg >= cnt) break;
+            float W[12], F[12];
+            if (lane > 0) aff_load(X + h * (kWave * 3) + 3 * (lane - 1), W);
+            else aff_identity(W);
+            aff_load(E + 3 * gs, F);
+            aff_mul_left(F, W);
+#pragma unroll
+            for (int i = 0; i < kChainPerLane; ++i) aff_mul_left(W, Q[h][i]);
+        }
+#pragma unroll
+        for (int h = 0; h < kChainSegPerWave; ++h) {
+            const int gs = wv + kChainWaves * h;
+            const int n = min(kChainSeg, cnt - gs * kChainSeg);
+            if (n <= 0) break;
+            const int64_t gb = b0.gbegin + gs * kChainSeg;  // the segment's first joint
             if (out.global_out) {
                 wave_sync();  // the slice's last readers are done
-                aff_store(X + 3 * lane, P[i]);
-                wave_sync();
-                float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * cb.gbegin;
 #pragma unroll
-                for (int c4 = 0; c4 < 4; ++c4) {
-                    const int c = lane + kWave * c4;
-                    if ((c >> 2) < cb.count) {
-                        const int r = c & 3;
-                        store_stream(dst + c, r == 3 ? bottom : X[3 * (c >> 2) + r]);
-                    }
+                for (int i = 0; i < kChainPerLane; ++i) aff_store(X + 3 * (j0 + i), Q[h][i]);
+                wave_sync();
+                // lane: row r of joints lane / 4 + 16 k
+                const int r = lane & 3;
+                float4 *dst = reinterpret_cast<float4 *>(out.global_out) + 4 * gb + lane;
+                const float4 *src = X + 3 * (lane >> 2) + min(r, 2);
+#pragma unroll 1
+                for (int jr = lane >> 2; jr < n; jr += kWave / 4) {
+                    const float4 v = *src;
+                    store_stream(dst, r == 3 ? bottom : v);
+                    dst += kWave;
+                    src += 3 * (kWave / 4);
                 }
             }
-            if (lane < cb.count) write_skin_and_ckpt(out, gid, gid, P[i]);
+#pragma unroll
+            for (int i = 0; i < kChainPerLane; ++i)
+                if (j0 + i < n) write_skin_and_ckpt(out, gb + j0 + i, gb + j0 + i, Q[h][i]);
         }
-        __syncthreads();  // T and E are rewritten by the next superblock
+        __syncthreads();  // the LDS is rewritten by the next superblock
     }
 }
 
@@ -3631,6 +3710,11 @@ hipError_t prepare_kernels()
     if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(mpr_anchor_seg_kernel),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)mpr_seg_lds_bytes())) != hipSuccess)
         return err;
+    if ((err = hipFuncSetAttribute(reinterpret_cast<const void *>(mp_chain_kernel<false>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLdsBytes)) != hipSuccess ||
+        (err = hipFuncSetAttribute(reinterpret_cast<const void *>(mp_chain_kernel<true>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLdsBytes)) != hipSuccess)
+        return err;
     if ((err = set_lds_limits<1>()) != hipSuccess) return err;
     if ((err = set_lds_limits<2>()) != hipSuccess) return err;
     if ((err = set_lds_limits<4>()) != hipSuccess) return err;
@@ -3734,8 +3818,10 @@ hipError_t run_multipass(const MPLaunch &ml, const PoseArgs &pose, const OutArgs
 hipError_t chain_blocks_per_cu(bool sample, int *out)
 {
     *out = 0;
-    return sample ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, mp_chain_kernel<true>, kChainWaves * kWave, 0)
-                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, mp_chain_kernel<false>, kChainWaves * kWave, 0);
+    return sample ? hipOccupancyMaxActiveBlocksPerMultiprocessor(out, mp_chain_kernel<true>, kChainWaves * kWave,
+                                                                 kChainLdsBytes)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(out, mp_chain_kernel<false>, kChainWaves * kWave,
+                                                                 kChainLdsBytes);
 }
 
 hipError_t launch_forward_chains(const ChainLaunch &cl, const PoseArgs &pose, const OutArgs &out,
@@ -3743,14 +3829,17 @@ hipError_t launch_forward_chains(const ChainLaunch &cl, const PoseArgs &pose, co
 {
     if (cl.num_blocks == 0) return hipSuccess;
     if (cl.grid < 1 || cl.num_sb < 1) return hipErrorInvalidValue;
-    const int nw = cl.num_sb;
-    hipLaunchKernelGGL(zero_words_kernel, dim3((nw + 255) / 256), dim3(256), 0, stream, cl.words, nw);
+    const int nw = 24 * cl.num_sb;  // the records as 32-bit words
+    hipLaunchKernelGGL(zero_words_kernel, dim3((nw + 255) / 256), dim3(256), 0, stream,
+                       reinterpret_cast<int32_t *>(cl.recs), nw);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (pose.kind == 1)
-        hipLaunchKernelGGL(mp_chain_kernel<true>, dim3(cl.grid), dim3(kChainWaves * kWave), 0, stream, cl, pose, out);
+        hipLaunchKernelGGL(mp_chain_kernel<true>, dim3(cl.grid), dim3(kChainWaves * kWave), kChainLdsBytes, stream,
+                           cl, pose, out);
     else
-        hipLaunchKernelGGL(mp_chain_kernel<false>, dim3(cl.grid), dim3(kChainWaves * kWave), 0, stream, cl, pose, out);
+        hipLaunchKernelGGL(mp_chain_kernel<false>, dim3(cl.grid), dim3(kChainWaves * kWave), kChainLdsBytes, stream,
+                           cl, pose, out);
     return hipGetLastError();
 }
 
