@@ -3129,6 +3129,7 @@ mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
         int lj0 = 0;
         if constexpr (SAMPLE) lj0 = (int)(b0.gbegin - pose.offsets[b0.chr]);
         float Q[kChainSegPerWave][kChainPerLane][12];
+        wave_sync();  // the previous superblock's reads of the slice are done
 #pragma unroll
         for (int h = 0; h < kChainSegPerWave; ++h) {
             const int gs = wv + kChainWaves * h;               // the segment
@@ -3206,7 +3207,11 @@ mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
             for (int i = 0; i < kChainPerLane; ++i)
                 if (j0 + i < n) write_skin_and_ckpt(out, gb + j0 + i, gb + j0 + i, Q[h][i]);
         }
-        __syncthreads();  // the LDS is rewritten by the next superblock
+        // no barrier here: a wave's next writes are to its own slice, to T
+        // (read by the resolution before the second barrier) and, for wave
+        // 0, to PS, R and its words; E is rewritten only after every wave
+        // has reached the next superblock's first barrier.  A wave that is
+        // done storing starts the next superblock's loads.
     }
 }
 
