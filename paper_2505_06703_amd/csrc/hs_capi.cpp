@@ -720,7 +720,7 @@ hs_status make_chains(MPSet &m, const hs_plan *plan, const Packing &pk)
         const int32_t first_sb = (int32_t)sbs.size();
         for (int64_t k = 0; k < n; k += 64) {
             const int64_t blk = k / 64;
-            if (blk % 64 == 0) sbs.push_back(hs::ChainSB{(int32_t)cb.size(), 0, first_sb, 0});
+            if (blk % hs::kChainSBBlocks == 0) sbs.push_back(hs::ChainSB{(int32_t)cb.size(), 0, first_sb, 0});
             hs::ChainBlock b{};
             b.gbegin = b0 + k;
             b.count = (int32_t)std::min<int64_t>(64, n - k);

@@ -270,7 +270,8 @@ hipError_t launch_forward_chains(const ChainLaunch &cl, const PoseArgs &pose, co
                                  hipStream_t stream);
 // Workgroups of the chain kernel (stored or sampled poses) that fit one CU.
 hipError_t chain_blocks_per_cu(bool sample, int *out);
-constexpr int kChainWaves = 16;  // waves per workgroup of the chain kernel
+constexpr int kChainWaves = 16;     // waves per workgroup of the chain kernel
+constexpr int kChainSBBlocks = 64;  // 64-joint blocks per superblock of the chain kernel
 hipError_t launch_backward_tiles(const TileLaunch &tl, const PoseArgs &pose, const BwdArgs &bwd,
                                  hipStream_t stream);
 hipError_t launch_backward_multipass(const MPLaunch &ml, const PoseArgs &pose, const BwdArgs &bwd,

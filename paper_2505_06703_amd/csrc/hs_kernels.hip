@@ -3067,7 +3067,7 @@ constexpr int kChainPerLane = 2;                          // consecutive joints 
 constexpr int kChainSeg = kChainPerLane * kWave;          // joints per segment
 constexpr int kChainSegPerWave = 2;                       // a wave's segments: wave, wave + 16
 constexpr int kChainSegs = kChainWaves * kChainSegPerWave;  // segments per superblock
-static_assert(kChainSegs * kChainSeg == 64 * 64, "a superblock is 64 blocks of 64 joints");
+static_assert(kChainSegs * kChainSeg == kChainSBBlocks * 64, "the segments cover a superblock");
 static_assert(kChainSegs <= kWave, "the segments' totals are scanned by one wave");
 
 // LDS of the chain kernel, in float4: per wave a slice of one segment's
@@ -3105,7 +3105,7 @@ __device__ __forceinline__ void load_local_lane(const PoseArgs &P, int64_t gid, 
 }
 
 template <bool SAMPLE>
-__global__ void __launch_bounds__(kChainWaves * kWave)
+__global__ void __launch_bounds__(kChainWaves * kWave, 4)  // at most 128 VGPRs: four waves per SIMD
 mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
 {
     extern __shared__ float4 lds[];
