@@ -3176,6 +3176,9 @@ mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
             if (lane > 0) aff_load(X + h * (kWave * 3) + 3 * (lane - 1), W);
             else aff_identity(W);
             aff_load(E + 3 * gs, F);
+#pragma unroll
+            for (int k = 0; k < 12; ++k)  // the same for every lane: scalar registers
+                F[k] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(F[k])));
             aff_mul_left(F, W);
 #pragma unroll
             for (int i = 0; i < kChainPerLane; ++i) aff_mul_left(W, Q[h][i]);
