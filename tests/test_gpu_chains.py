@@ -1,14 +1,16 @@
 """The one-pass path for chain characters beyond a tile (every joint's
-parent the previous joint): 64-joint blocks, superblocks of up to 64
-blocks resolved by the last block to arrive, a look-back over the chain's
-earlier superblocks.
+parent the previous joint): superblocks of 4096 joints, 16 waves of two
+128-joint segments each, two consecutive joints per lane; the segments'
+totals scanned in LDS and a look-back over the chain's earlier
+superblocks through tagged publication words.
 
 Parity against the FP64 oracle at the flat tolerance for chains that end
-inside a block, at block and superblock boundaries and with one to many
-superblocks; next to characters on the block path and on tiles; with clip
-sampling, skin and checkpoints; repeated launches and graph replays (the
-arrival and publication words start from zero every call); the sampler
-over chain characters; and the plan's bookkeeping."""
+inside a segment (odd lengths: a lane holding one joint), at segment and
+superblock boundaries and with one to many superblocks; next to characters
+on the block path and on tiles; with clip sampling, skin and checkpoints;
+repeated launches and graph replays (the publication records are cleared
+every call); the sampler over chain characters; and the plan's
+bookkeeping."""
 import numpy as np
 import pytest
 import torch
@@ -47,8 +49,9 @@ def chains_batch(lengths, seed, angle=0.1, extra=()):
     return wl.Batch("chains", off, par, q, t, s, rq, rt, rs)
 
 
-# block (64) and superblock (4096) boundaries, and several superblocks
-LENGTHS = [2049, 2112, 4096, 4097, 4160, 8191, 12345, 20000]
+# segment (128) and superblock (4096) boundaries, odd lengths, and several
+# superblocks
+LENGTHS = [2049, 2112, 2175, 2176, 4096, 4097, 4160, 4223, 8191, 12345, 20000]
 
 
 def test_chains_of_many_lengths_one_pass():
