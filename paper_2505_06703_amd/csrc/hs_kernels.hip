@@ -1869,6 +1869,7 @@ bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
     for (int tile = blockIdx.x; tile < tl.num_tiles; tile += gridDim.x) {
         const TileDesc td = tl.tiles[tile];
         const int n = td.count;
+        if (n == 0) continue;  // uniform: nothing to do, and no joint to read
         for (int i = threadIdx.x; i < na; i += T) {
             aflag[i] = 0;
             expect[i] = 0;
@@ -1891,6 +1892,18 @@ bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
         float Apb[BPW][9], Db[BPW][3];
         int ownb[BPW], eb[BPW], pab[BPW];
 
+        // every block's codes and poses are loaded before the first scan
+        int codeb[BPW];
+        float4 qb[BPW];
+        float tb[BPW][3], sb[BPW][3];
+#pragma unroll
+        for (int b = 0; b < BPW; ++b) {
+            const int jl = (wave + b * WAVES) * kWave + lane;
+            const int64_t gid = td.begin + min(jl, n - 1);  // past the tile: its last joint, not used
+            codeb[b] = tl.code[gid];
+            load_trs(pose, gid, qb[b], tb[b], sb[b]);
+        }
+
         // ---- forward: the wave's blocks in increasing order (the queue
         // kernel's scheme); non-anchor seeded joints send D (.) P to their
         // anchor at once ----
@@ -1907,14 +1920,11 @@ bwd_anchor_kernel(TileLaunch tl, PoseArgs pose, BwdArgs bwd)
             int a = -1, e = -1, own = -1, ps = -1;
             float m[12];
             if (valid) {
-                const int code = tl.code[gid];
+                const int code = codeb[b];
                 const int ref = code & (kQInBlock - 1);
                 if (code & kQInBlock) a = ref; else e = ps = ref - 1;
                 own = (code >> kQOwnShift) - 1;
-                float4 q;
-                float t[3], sc[3];
-                load_trs(pose, gid, q, t, sc);
-                aff_from_trs(q, t[0], t[1], t[2], sc[0], sc[1], sc[2], m);
+                aff_from_trs(qb[b], tb[b][0], tb[b][1], tb[b][2], sb[b][0], sb[b][1], sb[b][2], m);
             } else {
                 aff_identity(m);
             }
