@@ -31,7 +31,11 @@ bytes / mean kernel duration from HIP events on the launch stream, against
 error of one GPU step against FP64.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
-                    [--no-autotune] [--no-fwd-bwd]
+                    [--no-autotune] [--no-fwd-bwd] [--no-schedules]
+
+The heterogeneous line also carries `schedules`: the same forward through
+the work queue as a resident loop (four workgroups per CU, grid < tiles)
+and through the size classes (one launch per class), as plain calls.
 
 Other workloads (--workload): deep_forward (4096 x 1024 joints, depth
 246), plain_scan, fused_sample and fused_sample_instanced (clip sampling +
@@ -128,6 +132,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="heterogeneous", choices=WORKLOADS)
+    ap.add_argument("--no-schedules", action="store_true",
+                    help="heterogeneous: skip timing the other launch schedules beside the line "
+                         "(profiling runs; --calibrate-copy skips them too)")
     ap.add_argument("--no-fwd-bwd", action="store_true",
                     help="heterogeneous workload: leave out the differentiable form (fwd_bwd; always left out "
                          "with --calibrate-copy)")
@@ -599,6 +606,8 @@ def measure(args, name):
     }
     if diff:
         out["memory_modes"] = memory_modes(w)
+    if name == "heterogeneous" and not args.no_schedules and not args.calibrate_copy:
+        out["schedules"] = schedule_alternatives(w, info)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["err_vs_fp64"], ref_grads = cpu_baseline(w)
         if diff:
@@ -607,6 +616,44 @@ def measure(args, name):
                 out["memory_modes"][key]["err_vs_fp64"] = grad_errors(w, ck, ref_grads)
     w.close()
     return out
+
+
+def schedule_alternatives(w, info, steps=60, warmup=10):
+    """The same forward through the other launch schedules, as plain calls
+    over the cycled sets: the work queue as a resident loop (four
+    workgroups per CU walking the heaviest-first tile list, grid < tiles)
+    at the line's tile and wave shape, and the size classes (one launch per
+    class) at the plan's default shape.  The line's own schedule is the
+    timed region above."""
+    torch, hs, b = w.torch, w.hs, w.b
+    plans = {
+        "queue_resident_loop": hs.Plan(b.offsets, b.parents, schedule=hs.HS_SCHED_QUEUE,
+                                       tile_joints=info["tile_joints"], waves_per_tile=info["waves_per_tile"],
+                                       grid_tiles=4),  # workgroups per CU
+        "size_classes": hs.Plan(b.offsets, b.parents, schedule=hs.HS_SCHED_CLASSES),
+    }
+    res = {}
+    for key, plan in plans.items():
+        pi = plan.info
+
+        def step(k):
+            st = w.sets[k % len(w.sets)]
+            hs.hs_scan_forward(plan, st["q"], st["t"], st["s"], global_out=st["G"])
+
+        for k in range(warmup):
+            step(k)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(steps):
+            step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        res[key] = {"ms_per_step": e0.elapsed_time(e1) / steps, "grid": pi["grid"], "tiles": pi["num_tiles"],
+                    "tile_joints": pi["tile_joints"], "waves_per_tile": pi["waves_per_tile"],
+                    "launches": 1 if pi["schedule"] == hs.HS_SCHED_QUEUE else "one per size class"}
+        plan.close()
+    return res
 
 
 def memory_modes(w):
