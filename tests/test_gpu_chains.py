@@ -158,3 +158,28 @@ def test_chain_with_sampled_poses():
     Gr = oracle.forward(off, par, qr, tr, None)
     lam = oracle.path_length(off, par, Gr, tr)
     check_global(G.cpu().numpy(), Gr, lam, "sampled chains")
+
+
+def test_chain_wait_limit_zero_is_never_silently_wrong():
+    """With a zero wait limit a look-back gives up at once when an earlier
+    superblock has not published yet (whether one has depends on timing):
+    the call then reports the timeout in the plan's status word; when it
+    reports nothing, every look-back found what it needed and the result
+    is right.  Restoring the limit restores clean calls."""
+    b = chains_batch([20000, 12345, 9000], seed=5)
+    plan = hs.Plan(b.offsets, b.parents, tile_joints=2048)
+    assert plan.info["chain_joints"] == b.num_joints
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    Gr, lam, _ = reference(b)
+    plan.set_wait_limit(0)
+    for _ in range(3):
+        G, _ = hs.hs_scan_forward(plan, q, t, s)
+        rc, bits, _ = plan.status(clear=True)
+        if rc == hs.HS_OK:
+            check_global(G.cpu().numpy(), Gr, lam, "chains, zero wait limit, no timeout reported")
+        else:
+            assert rc == hs.HS_ERR_DEVICE and bits & hs.HS_DEV_WAIT_TIMEOUT
+    plan.set_wait_limit(1 << 22)
+    G, _ = hs.hs_scan_forward(plan, q, t, s)
+    assert plan.status() == (hs.HS_OK, 0, -1)
+    check_global(G.cpu().numpy(), Gr, lam, "chains after the wait limit is restored")
