@@ -2938,26 +2938,26 @@ mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 
 // ---------------------------------------------------------------------------
 // One pass for chain characters beyond a tile (every joint's parent the
 // previous joint): a reduce-then-scan over superblocks of up to 4096
-// consecutive joints of one chain (64 blocks of the plan's 64-joint
-// blocks), one superblock per workgroup at a time.  Each of the 16 waves
-// takes a segment of 256 consecutive joints, four per lane: the lane
-// multiplies its four local transforms in order (Q_i = L_0 ... L_i), the
-// wave scans the lanes' products (pointer jumping over lane - 1, six rounds
-// for 256 joints) and keeps each lane's exclusive prefix W.  The segments'
-// totals meet in LDS, where one wave scans them (lane = segment),
-// publishes the superblock's total, looks back over the chain's earlier
-// superblocks (lane = superblock: the nearest final transform and the
-// totals after it, composed by the same scan) for the transform entering
-// the superblock, publishes its final transform, and leaves in LDS the
-// transform entering each segment E; then G = (E W) Q_i, staged in LDS a
-// 64-joint row group at a time and stored as coalesced rows.  Each pose is
-// read once.  Workgroups take superblocks in increasing order (a static
-// stride; the launch holds no more workgroups than are resident at once),
-// and a superblock publishes its total before it looks back, so the
-// look-backs only wait for publications that need no waiting.  Values
-// cross workgroups as agent-scope atomic stores and loads (coherent across
-// the XCDs' L2s), each publication's stores complete before its flag is
-// stored.
+// consecutive joints of one chain (64 of the plan's 64-joint blocks), one
+// superblock per workgroup at a time.  Each of the 16 waves takes two
+// segments of 128 consecutive joints (wave w: segments w and w + 16), two
+// per lane: the lane multiplies its two local transforms in order
+// (Q_0 = L_0, Q_1 = L_0 L_1), the wave scans the lanes' products (pointer
+// jumping over lane - 1, six rounds for 128 joints) and keeps the
+// inclusive products in its LDS slice.  The segments' totals meet in LDS,
+// where one wave scans them (lane = segment), publishes the superblock's
+// total, looks back over the chain's earlier superblocks (lane =
+// superblock: the nearest final transform and the totals after it,
+// composed by the same scan) for the transform entering the superblock,
+// publishes its final transform, and leaves in LDS the transform entering
+// each segment E; then G = (E W) Q_i, W the product of the segment's
+// earlier lanes, staged in the slice a segment at a time and stored as
+// coalesced rows.  Each pose is read once.  Workgroups take superblocks in
+// increasing order (a static stride; the launch holds no more workgroups
+// than are resident at once), and a superblock publishes its total before
+// it looks back, so the look-backs only wait for publications that need no
+// waiting.  Values cross workgroups as tagged agent-scope words (coherent
+// across the XCDs' L2s).
 // ---------------------------------------------------------------------------
 // A superblock's record: 12 words, each a 32-bit value with its tag in the
 // high half (0 not published, 1 the superblock's total, 2 the final
