@@ -362,6 +362,7 @@ struct MPSet {
     int32_t num_csb = 0;
     int64_t chain_joints = 0;
     uint64_t *c_recs = nullptr;
+    uint32_t *c_epoch = nullptr;
     int32_t c_grid[2] = {0, 0};
 };
 
@@ -382,6 +383,7 @@ void free_mpset(MPSet &m)
     (void)hipFree(m.d_cblocks);
     (void)hipFree(m.d_csb);
     (void)hipFree(m.c_recs);
+    (void)hipFree(m.c_epoch);
     m = MPSet{};
 }
 
@@ -745,6 +747,12 @@ hs_status make_chains(MPSet &m, const hs_plan *plan, const Packing &pk)
     hipError_t err = upload(&m.d_cblocks, cb);
     if (err == hipSuccess) err = upload(&m.d_csb, sbs);
     if (err == hipSuccess) err = hipMalloc(&m.c_recs, ns * 12 * sizeof(uint64_t));
+    if (err == hipSuccess) err = hipMalloc(&m.c_epoch, 2 * sizeof(uint32_t));
+    // records and epoch start at zero once; each call then tags its
+    // publications with the next epoch (no clearing per call)
+    if (err == hipSuccess) err = hipMemset(m.c_recs, 0, ns * 12 * sizeof(uint64_t));
+    if (err == hipSuccess) err = hipMemset(m.c_epoch, 0, 2 * sizeof(uint32_t));
+    if (err == hipSuccess) err = hipDeviceSynchronize();
     if (err != hipSuccess) return fail_hip(err, "hs_plan_create (chain workspace)");
     return HS_OK;
 }
@@ -1141,6 +1149,7 @@ hs::ChainLaunch chain_launch(const hs_plan *p, bool sample, bool validate = fals
     cl.num_sb = m.num_csb;
     cl.grid = m.c_grid[sample ? 1 : 0];
     cl.recs = m.c_recs;
+    cl.epoch = m.c_epoch;
     cl.status = p->d_status;
     cl.spin_limit = p->spin_limit;
     cl.gate = validate ? p->d_status : nullptr;

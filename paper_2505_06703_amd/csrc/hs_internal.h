@@ -192,7 +192,9 @@ struct ChainLaunch {
     int32_t num_sb;
     int32_t grid;      // workgroups, all resident at once
     uint64_t *recs;    // [superblocks][12] tagged words: the product of the superblock's local
-                       // transforms (tag 1), then G of its last joint (tag 2); zeroed per call
+                       // transforms (kind 1), then G of its last joint (kind 2), tagged with
+                       // the call's epoch; zeroed once when allocated
+    uint32_t *epoch;   // [2]: the last call's epoch, and the count of its finished workgroups
     uint32_t *status;
     int32_t spin_limit;
     const uint32_t *gate;

@@ -2960,44 +2960,47 @@ mp_out_kernel(MPLaunch ml, PoseArgs pose, const float4 *AP, OutArgs out, float4 
 // across the XCDs' L2s).
 // ---------------------------------------------------------------------------
 // A superblock's record: 12 words, each a 32-bit value with its tag in the
-// high half (0 not published, 1 the superblock's total, 2 the final
-// transform), written as single 8-byte agent-scope stores (coherent across
-// the XCDs' L2s).  A word read is then both the value and its own flag: a
-// reader takes the record when all 12 tags agree, and reads again while
-// they do not (not yet published, or a total being overwritten by the
-// final transform), so no store has to complete before another.
+// high half, (epoch << 2) | kind (kind 1 the superblock's total, 2 the
+// final transform; the epoch numbers the calls, so that a word of an
+// earlier call never reads as published), written as single 8-byte
+// agent-scope stores (coherent across the XCDs' L2s).  A word read is then
+// both the value and its own flag: a reader takes the record when all 12
+// tags agree and carry this call's epoch, and reads again while they do
+// not (not yet published, or a total being overwritten by the final
+// transform), so no store has to complete before another.
 // m: the 12 values in LDS (an affine row block); lane k < 12 stores word k.
-__device__ __forceinline__ void publish12(uint64_t *rec, const float4 *m, unsigned tag, int lane)
+__device__ __forceinline__ void publish12(uint64_t *rec, const float4 *m, unsigned epoch, unsigned kind, int lane)
 {
     if (lane < 12) {
         const float v = reinterpret_cast<const float *>(m)[lane];
-        __hip_atomic_store(rec + lane, ((uint64_t)tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t tag = ((uint64_t)(epoch & 0x3fffffffu) << 2) | kind;
+        __hip_atomic_store(rec + lane, (tag << 32) | __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// The record's tag when its 12 tags agree, else 0; the values in m.
-__device__ __forceinline__ unsigned read12(uint64_t *rec, float m[12])
+// The record's kind when its 12 tags agree and carry this call's epoch,
+// else 0; the values in m.
+__device__ __forceinline__ unsigned read12(uint64_t *rec, unsigned epoch, float m[12])
 {
     uint64_t w[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) w[k] = __hip_atomic_load(rec + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned tag = (unsigned)(w[0] >> 32);
-    bool same = true;
+    bool same = (tag >> 2) == (epoch & 0x3fffffffu);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         same &= (unsigned)(w[k] >> 32) == tag;
         m[k] = __uint_as_float((unsigned)w[k]);
     }
-    return same ? tag : 0u;
+    return same ? (tag & 3u) : 0u;
 }
 
 // Wave 0 of the workgroup resolving superblock s: T [nt][3] the segments'
 // totals (in; T[nt - 1] then holds the superblock's total), E [nt][3] the
 // transforms entering the segments (out; first the products of the earlier
 // segments' totals); X, xi the wave's scan slice.
-__device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s, const ChainSB &sb, int nt, int lane,
-                                                   float4 *T, float4 *E, float4 *X, int *xi)
+__device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, unsigned epoch, int s, const ChainSB &sb,
+                                                   int nt, int lane, float4 *T, float4 *E, float4 *X, int *xi)
 {
     // inclusive products of the segments' totals, in chain order (lane = segment)
     const bool in = lane < nt;
@@ -3022,9 +3025,9 @@ __device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s,
     uint64_t *rec = cl.recs + 12 * (int64_t)s;
     float4 *tot = T + 3 * (nt - 1);
     if (s == sb.chain_first) {
-        publish12(rec, tot, 2, lane);
+        publish12(rec, tot, epoch, 2, lane);
     } else {
-        publish12(rec, tot, 1, lane);
+        publish12(rec, tot, epoch, 1, lane);
         // look back, 64 superblocks at a time (lane k: superblock base - k)
         for (int base = s - 1;; base -= kWave) {
             const int q = base - lane;
@@ -3032,7 +3035,7 @@ __device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s,
             unsigned st = 2;
             float v[12];
             for (int spin = 0;; ++spin) {
-                if (lv) st = read12(cl.recs + 12 * (int64_t)q, v);
+                if (lv) st = read12(cl.recs + 12 * (int64_t)q, epoch, v);
                 if (__all(st > 0)) break;
                 if (spin >= cl.spin_limit) {
                     note_status(cl.status, kStatusWaitTimeout);
@@ -3063,7 +3066,7 @@ __device__ __forceinline__ void resolve_superblock(const ChainLaunch &cl, int s,
         wave_sync();  // every lane has read the total
         if (lane == 0) aff_store(tot, inc);
         wave_sync();
-        publish12(rec, tot, 2, lane);
+        publish12(rec, tot, epoch, 2, lane);
     }
     if (in) {
         float x[12];
@@ -3131,6 +3134,10 @@ mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
     int *xi = xs + wv * kWave;
     const float4 bottom = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     const int j0 = kChainPerLane * lane;  // the lane's first joint in a segment
+    // this call's epoch: the last call's plus one (the last workgroup of a
+    // call stores it, after every workgroup has read it)
+    const unsigned epoch = (unsigned)__builtin_amdgcn_readfirstlane(
+        (int)(__hip_atomic_load(cl.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u));  // uniform
     for (int s = blockIdx.x; s < cl.num_sb; s += gridDim.x) {  // uniform per workgroup
         const ChainSB sb = cl.sbs[s];
         const ChainBlock b0 = cl.blocks[sb.first];
@@ -3169,7 +3176,7 @@ mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
 #pragma unroll
                 for (int i = 0; i < kChainPerLane; ++i)
                     aff_store(PS + 3 * (kWave * (kChainPerLane * h + i) + lane), Q[h][i]);
-            resolve_superblock(cl, s, sb, nt, lane, T, E, R, xs + kChainWaves * kWave);
+            resolve_superblock(cl, epoch, s, sb, nt, lane, T, E, R, xs + kChainWaves * kWave);
 #pragma unroll
             for (int h = 0; h < kChainSegPerWave; ++h)
 #pragma unroll
@@ -3226,12 +3233,16 @@ mp_chain_kernel(ChainLaunch cl, PoseArgs pose, OutArgs out)
         // has reached the next superblock's first barrier.  A wave that is
         // done storing starts the next superblock's loads.
     }
-}
-
-__global__ void __launch_bounds__(256) zero_words_kernel(int32_t *w, int32_t n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) w[i] = 0;
+    // the last workgroup to finish (every workgroup has read the epoch)
+    // stores it for the next call and resets the count
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = __hip_atomic_fetch_add(cl.epoch + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(cl.epoch + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(cl.epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -3847,11 +3858,6 @@ hipError_t launch_forward_chains(const ChainLaunch &cl, const PoseArgs &pose, co
 {
     if (cl.num_blocks == 0) return hipSuccess;
     if (cl.grid < 1 || cl.num_sb < 1) return hipErrorInvalidValue;
-    const int nw = 24 * cl.num_sb;  // the records as 32-bit words
-    hipLaunchKernelGGL(zero_words_kernel, dim3((nw + 255) / 256), dim3(256), 0, stream,
-                       reinterpret_cast<int32_t *>(cl.recs), nw);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
     if (pose.kind == 1)
         hipLaunchKernelGGL(mp_chain_kernel<true>, dim3(cl.grid), dim3(kChainWaves * kWave), kChainLdsBytes, stream,
                            cl, pose, out);
