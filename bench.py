@@ -97,8 +97,7 @@ PMC_MATCH = {"differentiable": ("bwd_anchor_kernel<", ", 2>")}
 SAMPLE_INSTANCE = ", true"
 # steps of several kernels: HBM traffic per step is the sum over them
 # (the kernels a step launches; those absent from a run count nothing)
-STEP_KERNELS = {"long_chains": [("mp_chain_kernel",), ("zero_words_kernel",), ("mp_local_kernel",), ("mp_anchor",),
-                                ("mp_out_kernel",)]}
+STEP_KERNELS = {"long_chains": [("mp_chain_kernel",), ("mp_local_kernel",), ("mp_anchor",), ("mp_out_kernel",)]}
 CHUNK = 8  # at least this many forward passes per captured graph replay
 CKPT_K = 8  # levels between checkpoints in the differentiable form's checkpoint mode
 SWEEP_BYTES = 1 << 30  # data one cycle over the input/output sets touches

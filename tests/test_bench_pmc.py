@@ -100,12 +100,13 @@ def test_input_uploads_before_the_calibration_copy_are_skipped(tmp_path, monkeyp
 
 
 def test_a_multipass_step_sums_its_kernels(tmp_path, monkeypatch):
-    """long_chains: the chain kernel and its word-clearing launch are one
-    step (their averages add); multipass kernels absent from the run count
+    """long_chains: the chain kernel and the block path's output pass (a
+    batch with chain and non-chain characters beyond a tile) are one step
+    (their averages add); multipass kernels absent from the run count
     nothing."""
     copy = "__amd_rocclr_copyBuffer"
     chain = "void hs::mp_chain_kernel<false>(hs::ChainLaunch, hs::PoseArgs, hs::OutArgs)"
-    zero = "hs::zero_words_kernel(int*, int)"
+    zero = "void hs::mp_out_kernel(hs::MPLaunch, hs::PoseArgs, hs::OutArgs)"
     fetch = [(1, copy, 128.0 * MIB), (2, zero, 0.0), (3, chain, 100.0 * MIB), (4, zero, 2.0),
              (5, chain, 102.0 * MIB)]
     write = [(1, copy, 256.0 * MIB), (2, zero, 4.0), (3, chain, 300.0 * MIB), (4, zero, 4.0),

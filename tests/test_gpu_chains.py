@@ -8,8 +8,8 @@ Parity against the FP64 oracle at the flat tolerance for chains that end
 inside a segment (odd lengths: a lane holding one joint), at segment and
 superblock boundaries and with one to many superblocks; next to characters
 on the block path and on tiles; with clip sampling, skin and checkpoints;
-repeated launches and graph replays (the publication records are cleared
-every call); the sampler over chain characters; and the plan's
+repeated launches and graph replays (each call tags its publications with
+a new epoch); the sampler over chain characters; and the plan's
 bookkeeping."""
 import numpy as np
 import pytest
@@ -114,7 +114,7 @@ def test_chain_launches_and_graph_replays_repeat():
     Gr, lam, _ = reference(b)
     check_global(first, Gr, lam, "chains first launch")
     out = torch.empty_like(G0)
-    for k in range(4):  # the per-call words are cleared by every call
+    for k in range(4):  # every call publishes under a new epoch
         out.fill_(float("nan"))
         hs.hs_scan_forward(plan, q, t, s, global_out=out)
         torch.cuda.synchronize()
