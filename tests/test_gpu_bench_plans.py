@@ -86,6 +86,37 @@ def test_forward_workload_autotuned(name):
     assert np.array_equal(G[:, 3, :], np.broadcast_to([0.0, 0.0, 0.0, 1.0], (b.num_joints, 4)))
 
 
+@pytest.mark.parametrize("waves", [4, 8])
+def test_heterogeneous_schedules_the_bench_compares(waves):
+    """The launches of the heterogeneous line's schedule comparison: the
+    work queue as a resident loop (four workgroups per CU, grid < tiles)
+    computes what one workgroup per tile computes, bit for bit (the same
+    tiles, the same arithmetic), and both match the oracle on a sample."""
+    b = wl.make("heterogeneous")
+    q, t, s = dev(b.quat), dev(b.trans), dev(b.scale)
+    shape = dict(schedule=hs.HS_SCHED_QUEUE, tile_joints=2048, waves_per_tile=waves)
+    per_tile = hs.Plan(b.offsets, b.parents, **shape)
+    resident = hs.Plan(b.offsets, b.parents, grid_tiles=4, **shape)
+    assert per_tile.info["grid"] == per_tile.info["num_tiles"]
+    assert resident.info["grid"] < resident.info["num_tiles"] == per_tile.info["num_tiles"]
+    G1, _ = hs.hs_scan_forward(per_tile, q, t, s)
+    G2, _ = hs.hs_scan_forward(resident, q, t, s)
+    torch.cuda.synchronize()
+    assert torch.equal(G1, G2)
+    check_forward_sample(G2.cpu().numpy(), b, sample_chars(b, 16, 41), f"heterogeneous resident loop, {waves} waves")
+
+
+def test_heterogeneous_size_classes():
+    """The size-class schedule of the line's comparison (one launch per
+    class, the plan's default shapes) against the oracle on a sample."""
+    b = wl.make("heterogeneous")
+    plan = hs.Plan(b.offsets, b.parents, schedule=hs.HS_SCHED_CLASSES)
+    assert plan.info["schedule"] == hs.HS_SCHED_CLASSES
+    G, _ = hs.hs_scan_forward(plan, dev(b.quat), dev(b.trans), dev(b.scale))
+    torch.cuda.synchronize()
+    check_forward_sample(G.cpu().numpy(), b, sample_chars(b, 16, 42), "heterogeneous size classes")
+
+
 @pytest.mark.parametrize("name", ["fused_sample", "fused_sample_instanced"])
 def test_fused_workload_autotuned(name):
     """Clip sampling, scan and skin in one launch (per-joint and instanced
