@@ -32,6 +32,10 @@
  *     calls neither allocate nor synchronise, run asynchronously on the
  *     given stream, and may be captured into a HIP graph.
  *   - Outputs must not overlap inputs or each other.
+ *   - A plan owns device workspaces (multipass tables, the status word, the
+ *     chain path's publication records and its call counter): calls on one
+ *     plan run in the order of their streams; calls on one plan that may
+ *     run at the same time (unordered streams) race.
  *   - Arrays read or written as 16-byte vectors (quat, global_out, inv_bind,
  *     skin_out, grad_global, grad_quat, ckpt) must be 16-byte aligned; the
  *     others 4-byte aligned.
@@ -223,7 +227,7 @@ typedef struct hs_plan_info {
  * parents[j] is outside [-1, j)), packs whole characters into LDS tiles,
  * prepares the multipass path for characters larger than a tile, uploads
  * the device tables and, if asked, autotunes the launch shape.  opts may be
- * NULL.  Synchronises the device once. */
+ * NULL.  Synchronises the device. */
 hs_status hs_plan_create(hs_context *ctx, const hs_batch *batch, const hs_plan_opts *opts,
                          hs_plan **out);
 
